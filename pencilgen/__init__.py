@@ -1,0 +1,192 @@
+"""Seeded synthetic pencils and start blocks for the oblique-projection FEAST path.
+
+This module builds inputs only: it holds none of the method's arithmetic and is
+shared, as the one common dependency, by the CPU oracle (``oracle/``) and by the
+GPU path's tests and benchmark.
+
+Construction (the test problems are synthetic stand-ins for the Matrix Market
+pencils of Table 1, which are not available here):
+
+* ``A = P D Q`` and ``B = P Q`` with ``P, Q = I + c G``.  This is a Weierstrass
+  form (Theorem 2.1) with ``T = P^{-1}`` and ``S = Q^{-1}``: the eigenvalues of
+  the pencil are exactly the diagonal of ``D`` and the right eigenvector of
+  ``d_i`` is column ``i`` of ``Q^{-1}``.
+* ``G`` has i.i.d. complex Gaussian entries of variance ``g_var`` (default
+  ``1/n``, so ``c G`` is a small perturbation of the identity; ``g_var = 1`` is
+  the literal unit-variance reading, kept for stress runs).
+* Eigenvalue positions are area-uniform in a disk or an annulus around the
+  contour centre.
+* The start block ``V`` is complex Gaussian with ``E|v|^2 = 1``.
+
+Seeds: ``numpy.random.SeedSequence(14041768 + k)`` for workload ``k``; the
+children are spawned in the fixed order ``[G_P, G_Q, D_inside, D_outside,
+D_cluster, V]``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+BASE_SEED = 14041768
+
+
+@dataclasses.dataclass
+class Pencil:
+    """One synthetic pencil (row-major complex128 arrays)."""
+
+    A: np.ndarray          # n x n
+    B: np.ndarray          # n x n
+    V: np.ndarray          # n x m start block
+    d: np.ndarray          # n exact eigenvalues (diagonal of D)
+    P: np.ndarray          # n x n
+    Q: np.ndarray          # n x n
+    center: complex        # contour centre gamma
+    radius: float          # contour radius rho
+    nodes: int             # quadrature nodes N
+    m: int                 # subspace size t
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def inside_mask(self) -> np.ndarray:
+        return np.abs(self.d - self.center) < self.radius
+
+    @property
+    def s(self) -> int:
+        """Exact number of eigenvalues strictly inside the circle."""
+        return int(np.count_nonzero(self.inside_mask))
+
+
+def _cgauss(rng: np.random.Generator, shape, var: float) -> np.ndarray:
+    sd = math.sqrt(var / 2.0)
+    return rng.normal(0.0, sd, shape) + 1j * rng.normal(0.0, sd, shape)
+
+
+def _area_uniform(rng: np.random.Generator, count: int, r1: float, r2: float,
+                  center: complex) -> np.ndarray:
+    """``count`` points area-uniform in the annulus ``r1 <= |z - center| < r2``."""
+    if count == 0:
+        return np.zeros(0, dtype=np.complex128)
+    u = rng.random(count)
+    th = 2.0 * math.pi * rng.random(count)
+    r = np.sqrt(r1 * r1 + u * (r2 * r2 - r1 * r1))
+    return center + r * np.exp(1j * th)
+
+
+def make_pencil(n: int, m: int, inside: int, inside_radius: float,
+                outside_r: tuple, center: complex = 0.0, radius: float = 1.0,
+                nodes: int = 16, c: float = 0.05, cluster: int = 0,
+                cluster_r: tuple = (1.05, 1.2), g_var: Optional[float] = None,
+                seed: int = BASE_SEED, name: str = "") -> Pencil:
+    """Build ``A = P D Q``, ``B = P Q`` and a start block ``V`` (n x m).
+
+    ``inside`` eigenvalues are area-uniform in ``|z - center| < inside_radius``,
+    ``cluster`` in the annulus ``cluster_r`` and the remaining
+    ``n - inside - cluster`` in the annulus ``outside_r`` (radii relative to the
+    centre).
+    """
+    if g_var is None:
+        g_var = 1.0 / n
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(6)
+    rgp, rgq, rdi, rdo, rdc, rv = [np.random.default_rng(k) for k in kids]
+    G_P = _cgauss(rgp, (n, n), g_var)
+    G_Q = _cgauss(rgq, (n, n), g_var)
+    outside = n - inside - cluster
+    if outside < 0:
+        raise ValueError("inside + cluster exceeds n")
+    d = np.concatenate([
+        _area_uniform(rdi, inside, 0.0, inside_radius, center),
+        _area_uniform(rdo, outside, outside_r[0], outside_r[1], center),
+        _area_uniform(rdc, cluster, cluster_r[0], cluster_r[1], center),
+    ])
+    V = _cgauss(rv, (n, m), 1.0)
+    eye = np.eye(n, dtype=np.complex128)
+    P = eye + c * G_P
+    Q = eye + c * G_Q
+    B = P @ Q
+    A = (P * d[None, :]) @ Q
+    return Pencil(A=np.ascontiguousarray(A), B=np.ascontiguousarray(B),
+                  V=np.ascontiguousarray(V), d=d, P=P, Q=Q,
+                  center=complex(center), radius=float(radius), nodes=nodes,
+                  m=m, name=name)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads.  Index k selects seed BASE_SEED + k.
+# ---------------------------------------------------------------------------
+
+def workload(k: int, g_var: Optional[float] = None, n_override: Optional[int] = None) -> Pencil:
+    """Workloads 1, 2, 3 and 5 (single pencils); see ``batch_workload`` for 4.
+
+    ``n_override`` shrinks a workload to a smaller order with the same recipe
+    (eigenvalue fractions kept), for quick tests.
+    """
+    seed = BASE_SEED + k
+    if k == 1:
+        n = n_override or 200
+        s = max(1, round(20 * n / 200))
+        return make_pencil(n, m=max(s + 10, round(30 * n / 200)), inside=s, inside_radius=0.8,
+                           outside_r=(1.5, 5.0), center=0.0, radius=1.0, nodes=16,
+                           c=0.1, g_var=g_var, seed=seed, name="plain-n%d" % n)
+    if k == 2:
+        n = n_override or 4000
+        s = max(1, round(100 * n / 4000))
+        m = max(s + 8, round(160 * n / 4000))
+        return make_pencil(n, m=m, inside=s, inside_radius=0.9, outside_r=(1.3, 10.0),
+                           center=1 + 1j, radius=1.0, nodes=32, c=0.05,
+                           g_var=g_var, seed=seed, name="fp64-n%d" % n)
+    if k == 3:
+        n = n_override or 8000
+        s = max(1, round(120 * n / 8000))
+        m = max(s + 8, round(256 * n / 8000))
+        rest = n - s
+        cluster = int(round(0.05 * rest))
+        return make_pencil(n, m=m, inside=s, inside_radius=1.0, outside_r=(1.2, 20.0),
+                           center=0.0, radius=1.0, nodes=32, c=0.05, cluster=cluster,
+                           cluster_r=(1.05, 1.2), g_var=g_var, seed=seed,
+                           name="mixed-n%d" % n)
+    if k == 5:
+        n = n_override or 2048
+        s = max(1, round(40 * n / 2048))
+        m = max(s + 8, round(64 * n / 2048))
+        return make_pencil(n, m=m, inside=s, inside_radius=0.9, outside_r=(1.3, 10.0),
+                           center=0.0, radius=1.0, nodes=32, c=0.05, g_var=g_var,
+                           seed=seed, name="adjoint-n%d" % n)
+    raise ValueError("workload %r is not a single pencil" % (k,))
+
+
+def batch_sizes(count: int = 64, lo: int = 256, hi: int = 2048, seed: int = BASE_SEED + 4):
+    """Orders n_p ~ U[lo, hi] and centres gamma_p ~ U([-2,2]^2) of the batch workload."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    ns = rng.integers(lo, hi + 1, size=count)
+    centers = rng.uniform(-2.0, 2.0, size=count) + 1j * rng.uniform(-2.0, 2.0, size=count)
+    return [int(x) for x in ns], [complex(x) for x in centers]
+
+
+def batch_workload(count: int = 64, lo: int = 256, hi: int = 2048, nodes: int = 16):
+    """Workload 4: ``count`` independent pencils of uneven order.
+
+    Pencil p has ``floor(n_p/20)`` eigenvalues in ``|z - gamma_p| < 0.9``, the rest
+    in the annulus 1.3..10 about gamma_p, ``m_p = 2 floor(n_p/20)``, radius 1.
+    """
+    ns, centers = batch_sizes(count, lo, hi)
+    out = []
+    for p, (n, g) in enumerate(zip(ns, centers)):
+        s = max(1, n // 20)
+        out.append(make_pencil(n, m=2 * s, inside=s, inside_radius=0.9,
+                               outside_r=(1.3, 10.0), center=g, radius=1.0, nodes=nodes,
+                               c=0.05, seed=BASE_SEED + 4 + 1000 * (p + 1),
+                               name="batch-%d-n%d" % (p, n)))
+    return out
+
+
+def start_block(n: int, m: int, seed: int) -> np.ndarray:
+    """Complex Gaussian n x m block with unit-variance entries."""
+    return _cgauss(np.random.default_rng(seed), (n, m), 1.0)
