@@ -1,0 +1,221 @@
+/*
+ * feast.h -- C ABI of the MI355X (gfx950) oblique-projection FEAST path.
+ *
+ * The method (Yin, Chan, Yeung, arXiv:1404.1768) finds the eigenpairs of a
+ * regular pencil  A x = lambda B x  (A, B complex n x n, non-Hermitian) whose
+ * eigenvalues lie strictly inside a circle |z - gamma| < rho (Section 1).
+ * Every iteration filters a block with a quadrature of the spectral projector
+ * (eq. 8-4), which needs one shifted solve (z_j B - A) Y_j = B U_1 per node
+ * (eq. 4-4), and extracts eigenpairs by oblique projection onto span(U) with
+ * the test space B span(U) (eqs. 6-3-12 .. 7-10, Theorem 3.2); Algorithm 5
+ * (GFEAST) iterates this with its three stopping rules.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex data are interleaved double complex {re, im} (feast_z), the
+ *    memory layout of torch.complex128 / numpy.complex128.  The mixed form
+ *    keeps its factors internally in complex64; no call takes complex64.
+ *  - Matrices are ROW-MAJOR ("C order"): element (i, j) of an r x c matrix
+ *    with leading dimension ld (ld >= c) is at index i*ld + j.
+ *  - Pointers named dX are device pointers (HIP device memory on the current
+ *    device); pointers named hX are host pointers.  The caller owns every
+ *    buffer it passes; the library keeps no pointer after a call returns,
+ *    except that a plan remembers which (dA, dB) its cached factors belong to.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All device work of a plan is enqueued on its stream; entry points that
+ *    return host data synchronise that stream before returning.
+ *  - A plan is not re-entrant: one call at a time per plan.
+ *  - Return value: FEAST_OK (0) on success, a positive status for a result
+ *    that is returned with a warning, a negative code for a failure.  No C++
+ *    exception crosses this interface.  Argument checks happen on the host
+ *    before any device work, so they can be exercised without a GPU.
+ */
+#ifndef FEAST_MI355X_H
+#define FEAST_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } feast_z;
+
+typedef struct feast_plan feast_plan;
+
+enum feast_status {
+  FEAST_OK = 0,
+  FEAST_SINGULAR = 1,          /* an exact zero pivot at some node (node/column in feast_last_error) */
+  FEAST_REFINE_STAGNATED = 2,  /* mixed form: refinement did not reach its target at some node */
+  FEAST_EINVAL = -1,           /* bad size, leading dimension, null pointer, contour or option */
+  FEAST_EDEVICE = -2,          /* HIP runtime error */
+  FEAST_ENOMEM = -3,           /* device or host allocation failed */
+  FEAST_ENUMERIC = -4          /* host reduced eigensolver or QR broke down */
+};
+
+enum feast_rule { FEAST_TRAPEZOID = 0, FEAST_GAUSS_LEGENDRE = 1 };
+enum feast_prec { FEAST_FP64 = 0, FEAST_MIXED = 1 };
+
+/* The circle Gamma = {|z - center| = radius} and its quadrature (eq. 8-4).
+ * FEAST_TRAPEZOID: z_j = center + radius*exp(i*pi*(2j-1)/N), w_j = (z_j-center)/N.
+ * FEAST_GAUSS_LEGENDRE: z_j = center + radius*exp(i*(1+t_j)*pi),
+ *                       w_j = omega_j*(z_j-center)/2 with (t_j, omega_j) the
+ *                       N-point Gauss-Legendre rule on [-1, 1]. */
+typedef struct {
+  feast_z center;
+  double radius;       /* > 0 */
+  int32_t nodes;       /* N >= 1 (N <= 1024) */
+  int32_t rule;        /* enum feast_rule */
+} feast_contour;
+
+/* Options of Algorithm 5 and of the implementation. */
+typedef struct {
+  double eps;          /* line 13 tolerance on e(k) = max r_i (default 1e-10) */
+  double eta;          /* line 10 tolerance separating true from spurious pairs (default 1e-3) */
+  int32_t max_iter;    /* line 15 (default 20) */
+  int32_t prec;        /* enum feast_prec (default FEAST_FP64) */
+  double refine_tol;   /* mixed form: per-node normwise backward-error target of the
+                          final filter (default 4*2^-53) */
+  int32_t max_sweeps;  /* mixed form: refinement sweeps per filter at most (default 6) */
+  int32_t nb;          /* LU panel width, 0 = automatic */
+  int32_t profile;     /* 1: time the LU trailing-update GEMM launches with HIP events on
+                          the plan's stream (reported in feast_info); default 0 */
+} feast_opts;
+
+/* Fill *o with the defaults listed above. */
+void feast_opts_default(feast_opts *o);
+
+/* Quadrature nodes and weights of eq. (8-4) (host only).  hz, hw: N entries each.
+ * Returns FEAST_EINVAL for a null pointer or an invalid contour. */
+int feast_nodes(const feast_contour *c, feast_z *hz, feast_z *hw);
+
+/* Create a plan for order n and subspace size m (1 <= m <= n).  The plan owns
+ * the device workspace and, after the first filter, the LU factors of every
+ * shifted matrix z_j B - A (N n^2 complex entries: complex128 for FEAST_FP64,
+ * complex64 for FEAST_MIXED), reused by every later filter as Section 4.3
+ * allows.  *plan is set to NULL on failure. */
+int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_contour *c,
+                      const feast_opts *o, void *stream);
+
+/* Release the plan and all memory it owns.  NULL is accepted. */
+int feast_plan_destroy(feast_plan *plan);
+
+/* Drop the cached factors (A or B changed in place). */
+int feast_plan_invalidate(feast_plan *plan);
+
+/* The filter of eq. (8-4) applied to a block (Algorithm 5 line 16):
+ *   U = sum_j w_j (z_j B - A)^{-1} B V,   V, U: n x m.
+ * The first call (or the first after feast_plan_invalidate, or with other dA/dB)
+ * factors every z_j B - A with partial pivoting and caches the factors.
+ * FEAST_MIXED factors in complex64 and refines every node solution in FP64
+ * (residual B V - (z_j B - A) Y_j, correction with the complex64 factors,
+ * FP64 update) until the backward-error target or max_sweeps.
+ * dU must not overlap dA, dB or dV.  Returns FEAST_SINGULAR for an exact zero
+ * pivot (the solution then holds non-finite values). */
+int feast_filter(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
+                 int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *dU, int64_t ldu);
+
+/* Oblique projection (Algorithm 5 lines 2, 5 and 17; eqs. 6-3-13, 7-10):
+ *   U = U_1 R_1 (QR),  B U_1 = U_2 R_2 (QR),
+ *   At = U_2^* A U_1,  Bt = U_2^* B U_1   (m x m, written to host memory).
+ * In: dU (n x m).  Out: dU overwritten by the orthonormal U_1; dAU1 = A U_1 and
+ * dBU1 = B U_1 (n x m each, kept for the residuals and the next filter);
+ * hAt, hBt (m x m, row-major, leading dimension m).  Synchronises the stream.
+ * Returns FEAST_ENUMERIC if U is numerically rank deficient beyond what the
+ * shifted Cholesky QR can repair. */
+int feast_project(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
+                  int64_t ldb, feast_z *dU, int64_t ldu, feast_z *dAU1, int64_t ldau,
+                  feast_z *dBU1, int64_t ldbu, feast_z *hAt, feast_z *hBt);
+
+/* Per-run record of Algorithm 5 (optional output of feast_solve). */
+#define FEAST_MAX_HISTORY 64
+typedef struct {
+  int32_t iters;                       /* k at which the run stopped */
+  int32_t filters;                     /* filter applications (the first is Search's) */
+  int32_t count[FEAST_MAX_HISTORY];    /* c(k), k = 1..iters */
+  double err[FEAST_MAX_HISTORY];       /* e(k) (+inf when c(k) = 0) */
+  int32_t sweeps[FEAST_MAX_HISTORY];   /* mixed form: refinement sweeps of each filter */
+  double t_factor_ms, t_filter_ms, t_project_ms, t_host_eig_ms, t_ritz_ms, t_total_ms;
+  /* with opts.profile = 1: the trailing-update GEMMs A22 -= L21 U12 of the last
+     factorisation -- number of launches, summed event time, and algorithmic
+     flops (8 (n-k)^2 kb per matrix and step, complex multiply-add = 8 flops) */
+  int32_t lu_gemm_launches;
+  double lu_gemm_ms;
+  double lu_gemm_flops;
+} feast_info;
+
+/* GFEAST (Algorithm 5, lines 1-18) with the subspace size fixed to m and a
+ * caller-supplied start block V in place of Search (line 1 becomes one filter
+ * application of V followed by QR):
+ *   outputs: *s_found selected eigenpairs; hLambda[0..s_found) their eigenvalues
+ *   (host, capacity m); dX columns 0..s_found-1 their eigenvectors (device,
+ *   n x m, unit 2-norm, largest-modulus entry real positive); hRes[0..s_found)
+ *   their residuals r_i of eq. (5-1) (host, capacity m, may be NULL);
+ *   *err = Err; *flag = 1 (line 13), 0 (line 14, previous iterate returned),
+ *   -1 (line 15); info (may be NULL) the per-iteration record.
+ * Selection (line 10): |lambda - center| < radius and r_i < eta; when nothing
+ * is selected e(k) = +inf and lines 13-14 are skipped.  Synchronises the stream. */
+int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
+                int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *hLambda,
+                feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, double *err,
+                int32_t *flag, feast_info *info);
+
+/* Message describing the last failure of this plan ("" if none). */
+const char *feast_last_error(const feast_plan *plan);
+
+/* ---------------------------------------------------------------------------
+ * Host-side pieces of Algorithm 5 (no device needed)
+ * ------------------------------------------------------------------------- */
+
+/* All eigenpairs of the t x t pencil At y = lambda Bt y (Algorithm 5 line 6;
+ * the paper solves it with an xGGEV-type solver): complex QZ.  Inputs are
+ * row-major with leading dimensions lda, ldb and are not modified.  Outputs:
+ * halpha, hbeta (t each; lambda_i = alpha_i/beta_i, beta_i = 0 for an infinite
+ * eigenvalue) and the right eigenvectors as the COLUMNS of hY (t x t,
+ * row-major, leading dimension ldy, each of unit 2-norm).  Returns
+ * FEAST_ENUMERIC if the QZ iteration does not converge. */
+int feast_reduced_eig(int64_t t, const feast_z *hAt, int64_t lda, const feast_z *hBt,
+                      int64_t ldb, feast_z *halpha, feast_z *hbeta, feast_z *hY, int64_t ldy);
+
+/* Stopping rules of Algorithm 5 (lines 13-15) after iteration k.  Returns 1
+ * (line 13: c(k) = c(k-1) and e(k) < eps), 0 (line 14: c(k) = c(k-1) and
+ * e(k) > e(k-1)), -1 (line 15: k = max_iter) or 2 (continue).  Lines 13-14
+ * are skipped when c_k = 0; line 13 is tested before 14. */
+int feast_stop_rule(int32_t k, int32_t c_k, double e_k, int32_t c_prev, double e_prev,
+                    double eps, int32_t max_iter);
+
+/* ---------------------------------------------------------------------------
+ * Kernel-level entry points (the building blocks of the filter), batched over
+ * `batch` independent problems with element strides between them.
+ * ------------------------------------------------------------------------- */
+
+/* In-place LU with partial pivoting of `batch` n x n row-major matrices:
+ * P_b M_b = L_b U_b (L unit lower).  dPiv[b*n + i] is the 0-based row swapped
+ * with row i at step i (LAPACK order).  dInfo[b] = 0, or 1 + the first column
+ * with an exact zero pivot.  nb = panel width (0 = automatic).  Asynchronous
+ * on `stream`.  The pivot test uses |re| + |im|, ties to the lowest row. */
+int feast_zgetrf_batched(int64_t n, int32_t batch, feast_z *dM, int64_t ldm, int64_t strideM,
+                         int32_t *dPiv, int32_t *dInfo, int32_t nb, void *stream);
+
+/* Solve M_b X_b = R_b (trans = 0) or M_b^* X_b = R_b (trans = 2) in place in
+ * dX (n x nrhs per problem) with the factors of feast_zgetrf_batched. */
+int feast_zgetrs_batched(int64_t n, int64_t nrhs, int32_t batch, const feast_z *dLU,
+                         int64_t ldm, int64_t strideM, const int32_t *dPiv, feast_z *dX,
+                         int64_t ldx, int64_t strideX, int32_t trans, void *stream);
+
+/* C_b = alpha op(A_b) B_b + beta C_b with op(A) = A (transA = 0, A is M x K)
+ * or op(A) = A^* (transA = 2, A stored K x M); B is K x N, C is M x N.  The
+ * FP64 MFMA complex GEMM used by every dense step of the path. */
+int feast_zgemm_batched(int32_t transA, int64_t M, int64_t N, int64_t K, feast_z alpha,
+                        const feast_z *dA, int64_t lda, int64_t strideA, const feast_z *dB,
+                        int64_t ldb, int64_t strideB, feast_z beta, feast_z *dC, int64_t ldc,
+                        int64_t strideC, int32_t batch, void *stream);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int feast_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEAST_MI355X_H */

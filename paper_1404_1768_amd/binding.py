@@ -1,0 +1,391 @@
+"""ctypes binding of ``libfeast_mi355x.so`` (the C ABI declared in ``include/feast.h``).
+
+Argument marshalling only: every step of the method runs in the library.
+PyTorch supplies device memory and the stream.  Tensors must be complex128,
+two-dimensional and row-major with unit column stride (``ld = t.stride(0)``).
+The library must have been built (``python -m paper_1404_1768_amd.build``);
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfeast_mi355x.so")
+
+FEAST_OK = 0
+FEAST_SINGULAR = 1
+FEAST_REFINE_STAGNATED = 2
+FEAST_EINVAL = -1
+FEAST_EDEVICE = -2
+FEAST_ENOMEM = -3
+FEAST_ENUMERIC = -4
+
+TRAPEZOID = 0
+GAUSS_LEGENDRE = 1
+FP64 = 0
+MIXED = 1
+MAX_HISTORY = 64
+
+EXPORTED = [
+    "feast_opts_default", "feast_nodes", "feast_plan_create", "feast_plan_destroy",
+    "feast_plan_invalidate", "feast_filter", "feast_project", "feast_solve", "feast_last_error",
+    "feast_reduced_eig", "feast_stop_rule", "feast_zgetrf_batched", "feast_zgetrs_batched",
+    "feast_zgemm_batched", "feast_version",
+]
+
+
+class FeastZ(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class Contour(C.Structure):
+    _fields_ = [("center", FeastZ), ("radius", C.c_double), ("nodes", C.c_int32),
+                ("rule", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("eta", C.c_double), ("max_iter", C.c_int32),
+                ("prec", C.c_int32), ("refine_tol", C.c_double), ("max_sweeps", C.c_int32),
+                ("nb", C.c_int32), ("profile", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("filters", C.c_int32),
+                ("count", C.c_int32 * MAX_HISTORY), ("err", C.c_double * MAX_HISTORY),
+                ("sweeps", C.c_int32 * MAX_HISTORY),
+                ("t_factor_ms", C.c_double), ("t_filter_ms", C.c_double),
+                ("t_project_ms", C.c_double), ("t_host_eig_ms", C.c_double),
+                ("t_ritz_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("lu_gemm_launches", C.c_int32), ("lu_gemm_ms", C.c_double),
+                ("lu_gemm_flops", C.c_double)]
+
+
+class FeastError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("feast error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            "%s is missing: build it with `python -m paper_1404_1768_amd.build`" % path)
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    i64, i32, dbl = C.c_int64, C.c_int32, C.c_double
+    pz = C.POINTER(FeastZ)
+    lib.feast_opts_default.argtypes = [C.POINTER(Opts)]
+    lib.feast_opts_default.restype = None
+    lib.feast_nodes.argtypes = [C.POINTER(Contour), pz, pz]
+    lib.feast_plan_create.argtypes = [C.POINTER(P), i64, i64, C.POINTER(Contour), C.POINTER(Opts), P]
+    lib.feast_plan_destroy.argtypes = [P]
+    lib.feast_plan_invalidate.argtypes = [P]
+    lib.feast_filter.argtypes = [P, P, i64, P, i64, P, i64, P, i64]
+    lib.feast_project.argtypes = [P, P, i64, P, i64, P, i64, P, i64, P, i64, pz, pz]
+    lib.feast_solve.argtypes = [P, P, i64, P, i64, P, i64, pz, P, i64, C.POINTER(dbl),
+                                C.POINTER(i32), C.POINTER(dbl), C.POINTER(i32), C.POINTER(Info)]
+    lib.feast_last_error.argtypes = [P]
+    lib.feast_last_error.restype = C.c_char_p
+    lib.feast_reduced_eig.argtypes = [i64, pz, i64, pz, i64, pz, pz, pz, i64]
+    lib.feast_stop_rule.argtypes = [i32, i32, dbl, i32, dbl, dbl, i32]
+    lib.feast_zgetrf_batched.argtypes = [i64, i32, P, i64, i64, P, P, i32, P]
+    lib.feast_zgetrs_batched.argtypes = [i64, i64, i32, P, i64, i64, P, P, i64, i64, i32, P]
+    lib.feast_zgemm_batched.argtypes = [i32, i64, i64, i64, FeastZ, P, i64, i64, P, i64, i64,
+                                        FeastZ, P, i64, i64, i32, P]
+    for name in EXPORTED:
+        if name not in ("feast_opts_default", "feast_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------------------
+# helpers
+# ---------------------------------------------------------------------------
+
+def _zptr(a: np.ndarray):
+    assert a.dtype == np.complex128 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(FeastZ))
+
+
+def _dev(t, rows=None, cols=None, name="tensor"):
+    """(pointer, ld) of a device complex128 row-major matrix."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.complex128 or t.dim() != 2 or not t.is_cuda:
+        raise ValueError("%s must be a 2-D complex128 CUDA tensor" % name)
+    if t.stride(1) != 1 or (t.shape[0] > 1 and t.stride(0) < t.shape[1]):
+        raise ValueError("%s must be row-major with unit column stride" % name)
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError("%s has %d rows, expected %d" % (name, t.shape[0], rows))
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError("%s has %d columns, expected %d" % (name, t.shape[1], cols))
+    return C.c_void_p(t.data_ptr()), max(t.stride(0), t.shape[1])
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        if not torch.cuda.is_available():
+            return C.c_void_p(None)
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def contour(center: complex, radius: float, nodes: int, rule: int = TRAPEZOID) -> Contour:
+    c = complex(center)
+    return Contour(FeastZ(c.real, c.imag), float(radius), int(nodes), int(rule))
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    load().feast_opts_default(C.byref(o))
+    return o
+
+
+# ---------------------------------------------------------------------------
+# host-only entry points
+# ---------------------------------------------------------------------------
+
+def feast_nodes(center: complex, radius: float, nodes: int, rule: int = TRAPEZOID):
+    lib = load()
+    z = np.zeros(nodes, dtype=np.complex128)
+    w = np.zeros(nodes, dtype=np.complex128)
+    c = contour(center, radius, nodes, rule)
+    rc = lib.feast_nodes(C.byref(c), _zptr(z), _zptr(w))
+    if rc != FEAST_OK:
+        raise FeastError(rc, "invalid contour")
+    return z, w
+
+
+def feast_reduced_eig(At: np.ndarray, Bt: np.ndarray):
+    lib = load()
+    At = np.ascontiguousarray(At, dtype=np.complex128)
+    Bt = np.ascontiguousarray(Bt, dtype=np.complex128)
+    t = At.shape[0]
+    if At.shape != (t, t) or Bt.shape != (t, t):
+        raise ValueError("square matrices of equal size expected")
+    al = np.zeros(t, dtype=np.complex128)
+    be = np.zeros(t, dtype=np.complex128)
+    Y = np.zeros((t, t), dtype=np.complex128)
+    rc = lib.feast_reduced_eig(t, _zptr(At), t, _zptr(Bt), t, _zptr(al), _zptr(be), _zptr(Y), t)
+    if rc != FEAST_OK:
+        raise FeastError(rc, "reduced eigensolver failed")
+    return al, be, Y
+
+
+def feast_stop_rule(k, c_k, e_k, c_prev, e_prev, eps, max_iter) -> int:
+    return load().feast_stop_rule(k, c_k, float(e_k), c_prev, float(e_prev), float(eps), max_iter)
+
+
+# ---------------------------------------------------------------------------
+# plan
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SolveResult:
+    lam: np.ndarray        # selected eigenvalues
+    X: object              # torch tensor n x s (device)
+    res: np.ndarray        # residuals r_i of eq. (5-1)
+    err: float
+    flag: int
+    iters: int
+    filters: int
+    count: list
+    errs: list
+    sweeps: list
+    times: dict
+    status: int
+    lu_gemm: dict
+
+
+class Plan:
+    """A FEAST plan: contour, options, device workspace and cached LU factors."""
+
+    def __init__(self, n: int, m: int, center: complex, radius: float, nodes: int,
+                 rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
+                 max_iter: int = 20, prec: int = FP64, refine_tol: Optional[float] = None,
+                 max_sweeps: int = 6, nb: int = 0, profile: bool = False, stream=None):
+        self.lib = load()
+        self.n, self.m = int(n), int(m)
+        self.contour = contour(center, radius, nodes, rule)
+        self.opts = default_opts()
+        self.opts.eps, self.opts.eta, self.opts.max_iter = float(eps), float(eta), int(max_iter)
+        self.opts.prec, self.opts.max_sweeps, self.opts.nb = int(prec), int(max_sweeps), int(nb)
+        self.opts.profile = 1 if profile else 0
+        if refine_tol is not None:
+            self.opts.refine_tol = float(refine_tol)
+        self._stream_obj = stream
+        self._h = C.c_void_p()
+        rc = self.lib.feast_plan_create(C.byref(self._h), self.n, self.m, C.byref(self.contour),
+                                        C.byref(self.opts), _stream(stream))
+        if rc != FEAST_OK:
+            raise FeastError(rc, "feast_plan_create failed")
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if self._h:
+            self.lib.feast_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self) -> str:
+        return self.lib.feast_last_error(self._h).decode()
+
+    def _check(self, rc, what, ok=(FEAST_OK,)):
+        if rc not in ok:
+            raise FeastError(rc, "%s: %s" % (what, self.last_error()))
+        return rc
+
+    def invalidate(self):
+        self._check(self.lib.feast_plan_invalidate(self._h), "feast_plan_invalidate")
+
+    # -- the three calls ---------------------------------------------------
+    def filter(self, A, B, V, U=None, allow=(FEAST_OK,)):
+        import torch
+        n, m = self.n, self.m
+        pa, lda = _dev(A, n, n, "A")
+        pb, ldb = _dev(B, n, n, "B")
+        pv, ldv = _dev(V, n, m, "V")
+        if U is None:
+            U = torch.empty((n, m), dtype=torch.complex128, device=V.device)
+        pu, ldu = _dev(U, n, m, "U")
+        rc = self.lib.feast_filter(self._h, pa, lda, pb, ldb, pv, ldv, pu, ldu)
+        self.status = self._check(rc, "feast_filter", ok=(FEAST_OK,) + tuple(allow))
+        return U
+
+    def project(self, A, B, U):
+        import torch
+        n, m = self.n, self.m
+        pa, lda = _dev(A, n, n, "A")
+        pb, ldb = _dev(B, n, n, "B")
+        pu, ldu = _dev(U, n, m, "U")
+        AU1 = torch.empty((n, m), dtype=torch.complex128, device=U.device)
+        BU1 = torch.empty((n, m), dtype=torch.complex128, device=U.device)
+        At = np.zeros((m, m), dtype=np.complex128)
+        Bt = np.zeros((m, m), dtype=np.complex128)
+        rc = self.lib.feast_project(self._h, pa, lda, pb, ldb, pu, ldu,
+                                    C.c_void_p(AU1.data_ptr()), m, C.c_void_p(BU1.data_ptr()), m,
+                                    _zptr(At), _zptr(Bt))
+        self._check(rc, "feast_project")
+        return U, AU1, BU1, At, Bt
+
+    def solve(self, A, B, V, allow=(FEAST_REFINE_STAGNATED,)) -> SolveResult:
+        import torch
+        n, m = self.n, self.m
+        pa, lda = _dev(A, n, n, "A")
+        pb, ldb = _dev(B, n, n, "B")
+        pv, ldv = _dev(V, n, m, "V")
+        X = torch.empty((n, m), dtype=torch.complex128, device=V.device)
+        lam = np.zeros(m, dtype=np.complex128)
+        res = np.zeros(m, dtype=np.float64)
+        s = C.c_int32()
+        err = C.c_double()
+        flag = C.c_int32()
+        info = Info()
+        rc = self.lib.feast_solve(self._h, pa, lda, pb, ldb, pv, ldv, _zptr(lam),
+                                  C.c_void_p(X.data_ptr()), m,
+                                  res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(s),
+                                  C.byref(err), C.byref(flag), C.byref(info))
+        self._check(rc, "feast_solve", ok=(FEAST_OK,) + tuple(allow))
+        k = s.value
+        it = info.iters
+        return SolveResult(
+            lam=lam[:k].copy(), X=X[:, :k], res=res[:k].copy(), err=err.value, flag=flag.value,
+            iters=it, filters=info.filters, count=list(info.count[:it]), errs=list(info.err[:it]),
+            sweeps=list(info.sweeps[:info.filters]),
+            times={"factor": info.t_factor_ms, "filter": info.t_filter_ms,
+                   "project": info.t_project_ms, "host_eig": info.t_host_eig_ms,
+                   "ritz": info.t_ritz_ms, "total": info.t_total_ms},
+            status=rc, lu_gemm={"launches": info.lu_gemm_launches, "ms": info.lu_gemm_ms,
+                                "flops": info.lu_gemm_flops})
+
+
+# Module-level functions with the C names.
+def feast_filter(plan: Plan, A, B, V, U=None):
+    return plan.filter(A, B, V, U)
+
+
+def feast_project(plan: Plan, A, B, U):
+    return plan.project(A, B, U)
+
+
+def feast_solve(plan: Plan, A, B, V):
+    return plan.solve(A, B, V)
+
+
+# ---------------------------------------------------------------------------
+# kernel-level entry points
+# ---------------------------------------------------------------------------
+
+def zgemm_batched(A, B, C_, alpha=1.0, beta=0.0, transA=0, stream=None):
+    """C_b = alpha op(A_b) B_b + beta C_b on 3-D (batch, rows, cols) complex128 tensors."""
+    lib = load()
+    for t, nm in ((A, "A"), (B, "B"), (C_, "C")):
+        if t.dim() != 3 or t.stride(2) != 1 or t.dtype.is_complex is False:
+            raise ValueError("%s must be (batch, rows, cols) row-major" % nm)
+    batch = C_.shape[0]
+    M, N = C_.shape[1], C_.shape[2]
+    K = A.shape[2] if transA == 0 else A.shape[1]
+    a, b = complex(alpha), complex(beta)
+    rc = lib.feast_zgemm_batched(int(transA), M, N, K, FeastZ(a.real, a.imag),
+                                 C.c_void_p(A.data_ptr()), A.stride(1), A.stride(0),
+                                 C.c_void_p(B.data_ptr()), B.stride(1), B.stride(0),
+                                 FeastZ(b.real, b.imag), C.c_void_p(C_.data_ptr()), C_.stride(1),
+                                 C_.stride(0), batch, _stream(stream))
+    if rc != FEAST_OK:
+        raise FeastError(rc, "feast_zgemm_batched")
+    return C_
+
+
+def zgetrf_batched(M, nb: int = 0, stream=None):
+    """In-place LU of a (batch, n, n) complex128 tensor; returns (piv, info) int32 tensors."""
+    import torch
+    lib = load()
+    batch, n = M.shape[0], M.shape[1]
+    piv = torch.empty((batch, n), dtype=torch.int32, device=M.device)
+    info = torch.empty((batch,), dtype=torch.int32, device=M.device)
+    rc = lib.feast_zgetrf_batched(n, batch, C.c_void_p(M.data_ptr()), M.stride(1), M.stride(0),
+                                  C.c_void_p(piv.data_ptr()), C.c_void_p(info.data_ptr()), nb,
+                                  _stream(stream))
+    if rc != FEAST_OK:
+        raise FeastError(rc, "feast_zgetrf_batched")
+    return piv, info
+
+
+def zgetrs_batched(LU, piv, X, trans: int = 0, stream=None):
+    lib = load()
+    batch, n = LU.shape[0], LU.shape[1]
+    nrhs = X.shape[2]
+    rc = lib.feast_zgetrs_batched(n, nrhs, batch, C.c_void_p(LU.data_ptr()), LU.stride(1),
+                                  LU.stride(0), C.c_void_p(piv.data_ptr()),
+                                  C.c_void_p(X.data_ptr()), X.stride(1), X.stride(0), int(trans),
+                                  _stream(stream))
+    if rc != FEAST_OK:
+        raise FeastError(rc, "feast_zgetrs_batched")
+    return X

@@ -1,0 +1,75 @@
+// Shared device-side definitions of the gfx950 FEAST path.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace feast {
+
+// Interleaved complex types: {re, im} as HIP 2-vectors (16 B / 8 B aligned).
+using z64 = double2;
+using c64 = float2;
+
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline z64 zmake(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline z64 zadd(z64 a, z64 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline z64 zsub(z64 a, z64 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline z64 zmul(z64 a, z64 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a - b*c
+__host__ __device__ inline z64 zfms(z64 a, z64 b, z64 c) {
+  return make_double2(a.x - (b.x * c.x - b.y * c.y), a.y - (b.x * c.y + b.y * c.x));
+}
+__host__ __device__ inline z64 zconj(z64 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double zabs1(z64 a) { return fabs(a.x) + fabs(a.y); }
+__host__ __device__ inline z64 zrecip(z64 a) {
+  const double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+
+__host__ __device__ inline c64 cmul(c64 a, c64 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline c64 cfms(c64 a, c64 b, c64 c) {
+  return make_float2(a.x - (b.x * c.x - b.y * c.y), a.y - (b.x * c.y + b.y * c.x));
+}
+__host__ __device__ inline double cabs1(c64 a) { return fabsf(a.x) + fabsf(a.y); }
+__host__ __device__ inline c64 crecip(c64 a) {
+  const float d = a.x * a.x + a.y * a.y;
+  return make_float2(a.x / d, -a.y / d);
+}
+
+// Generic complex helpers for templated kernels (T = z64 or c64).
+template <typename T> struct cplx_traits;
+template <> struct cplx_traits<z64> {
+  using real = double;
+  __device__ static z64 mul(z64 a, z64 b) { return zmul(a, b); }
+  __device__ static z64 fms(z64 a, z64 b, z64 c) { return zfms(a, b, c); }
+  __device__ static z64 recip(z64 a) { return zrecip(a); }
+  __device__ static double abs1(z64 a) { return zabs1(a); }
+  __device__ static z64 make(double r, double i) { return make_double2(r, i); }
+};
+template <> struct cplx_traits<c64> {
+  using real = float;
+  __device__ static c64 mul(c64 a, c64 b) { return cmul(a, b); }
+  __device__ static c64 fms(c64 a, c64 b, c64 c) { return cfms(a, b, c); }
+  __device__ static c64 recip(c64 a) { return crecip(a); }
+  __device__ static double abs1(c64 a) { return cabs1(a); }
+  __device__ static c64 make(double r, double i) {
+    return make_float2(static_cast<float>(r), static_cast<float>(i));
+  }
+};
+
+// Map a linear workgroup id onto a contiguous slice of the work per XCD.
+// Consecutive workgroup ids are dispatched round-robin over the 8 XCDs of an
+// MI355X; giving each XCD a contiguous range of tiles keeps the tiles that
+// share operand panels in the same L2.
+__device__ inline int64_t xcd_remap(int64_t id, int64_t total_padded) {
+  const int64_t per = total_padded / 8;
+  return (id % 8) * per + id / 8;
+}
+
+}  // namespace feast

@@ -1,0 +1,959 @@
+// Plan, drivers and C ABI of the gfx950 oblique-projection FEAST path.
+//
+//   feast_filter  : U = sum_j w_j (z_j B - A)^{-1} B V        (eqs. 8-4, 4-4)
+//   feast_project : U = U_1 R_1, B U_1 = U_2 R_2, At = U_2^* A U_1, Bt = U_2^* B U_1
+//                   (Algorithm 5 lines 2, 5, 17; eqs. 6-3-13, 7-10)
+//   feast_solve   : Algorithm 5 lines 1-18 with the subspace size fixed
+//
+// Device layout.  Every matrix is row-major.  The plan caches, per node j,
+// the LU factors of M_j = z_j B - A (N blocks of n x n, complex128 or
+// complex64), the pivots, the permutation they define, and the inverses of
+// the nb x nb diagonal blocks of L_j and U_j, which turn the blocked
+// triangular solves into MFMA GEMMs.  The N node solutions live side by side
+// in one n x (N m) block (node j in columns [j m, (j+1) m)), so that the FP64
+// refinement residual of all nodes is one GEMM [A; B] * [Y_1 ... Y_N].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/feast.h"
+#include "host_eig.h"
+#include "kernels.h"
+
+using feast::c64;
+using feast::z64;
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+
+inline z64 zc(double r, double i = 0.0) { return make_double2(r, i); }
+
+struct HipError {
+  hipError_t e;
+  const char *what;
+};
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) throw HipError{e_, #x};   \
+  } while (0)
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void alloc(size_t b) {
+    if (bytes >= b && p) return;
+    release();
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      bytes = 0;
+      throw HipError{e, "hipMalloc"};
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+}  // namespace
+
+struct feast_plan {
+  int64_t n = 0, m = 0;
+  int N = 0;
+  feast_contour c{};
+  feast_opts o{};
+  hipStream_t s = nullptr;
+  int nb = 64;
+  int64_t nblk = 0;
+  std::vector<cd> hz, hw;
+  DevBuf dz, dw;
+  // cached factors
+  bool factored = false;
+  const void *fA = nullptr, *fB = nullptr;
+  int64_t flda = 0, fldb = 0;
+  DevBuf F, piv, perm, info, Linv, Uinv;
+  double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
+  // workspaces
+  DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
+  std::string err;
+  int last_sweeps = 0;       // mixed form: sweeps of the last filter
+  double last_be = 0.0;      // mixed form: worst node backward error of the last filter
+  bool stagnated = false;    // mixed form: the last filter missed its target
+  // opts.profile: events around the LU trailing-update GEMMs
+  std::vector<hipEvent_t> ev;
+  int prof_launches = 0;
+  double prof_ms = 0.0, prof_flops = 0.0;
+
+  // n x m work blocks inside W
+  enum { W_ORTH = 0, W_U2 = 1, W_X = 2, W_AX = 3, W_BX = 4, W_XPREV = 5, W_U1 = 6, W_AU1 = 7,
+         W_BU1 = 8, W_UF = 9, W_COUNT = 10 };
+  // m x m blocks inside G
+  enum { G_GRAM = 0, G_AT = 2, G_BT = 3, G_YS = 4, G_COUNT = 5 };
+  z64 *wblk(int i) const { return W.as<z64>() + static_cast<int64_t>(i) * n * m; }
+  z64 *gblk(int i) const { return G.as<z64>() + static_cast<int64_t>(i) * m * m; }
+
+  bool mixed() const { return o.prec == FEAST_MIXED; }
+  int64_t ldY() const { return static_cast<int64_t>(N) * m; }
+  int64_t fstride() const { return n * n; }
+  int64_t istride() const { return nblk * nb * nb; }
+};
+
+namespace {
+
+int fail(feast_plan *p, int code, const std::string &msg) {
+  if (p) p->err = msg;
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking LU of `batch` matrices (row-major, partial pivoting).
+// Panels of width nb are factored recursively (left half, small TRSM, GEMM
+// update of the right half, right half) down to register-resident leaves;
+// then the panel's swaps reach the columns outside it, U12 = L11^{-1} A12 is
+// an in-place MFMA product with the inverted diagonal block, and the trailing
+// update A22 -= L21 U12 is one batched MFMA GEMM over all matrices.
+// ---------------------------------------------------------------------------
+template <typename T>
+void gemm_t(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const T *A,
+            int64_t lda, int64_t sA, const T *B, int64_t ldb, int64_t sB, z64 beta, T *C,
+            int64_t ldc, int64_t sC, int32_t batch, T *work = nullptr, int64_t welems = 0);
+template <>
+void gemm_t<z64>(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
+                 int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,
+                 int64_t ldc, int64_t sC, int32_t batch, z64 *work, int64_t welems) {
+  feast::zgemm(s, ta, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, work, welems);
+}
+template <>
+void gemm_t<c64>(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const c64 *A,
+                 int64_t lda, int64_t sA, const c64 *B, int64_t ldb, int64_t sB, z64 beta, c64 *C,
+                 int64_t ldc, int64_t sC, int32_t batch, c64 *work, int64_t welems) {
+  feast::cgemm(s, ta, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, work, welems);
+}
+
+template <typename T>
+void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+               int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info) {
+  const int ib = feast::leaf_max_width<T>(n - c0);
+  if (w <= ib) {
+    if (!feast::leaf_lu<T>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info))
+      throw HipError{hipErrorInvalidValue, "leaf_lu"};
+    return;
+  }
+  const int w1 = w / 2, w2 = w - w1;
+  panel_rec<T>(s, M, ld, stride, batch, n, c0, w1, pk0, pkb, ipiv, info);
+  feast::trsm_small<T>(s, M, ld, stride, batch, c0, w1, w2);
+  if (c0 + w1 < n)
+    gemm_t<T>(s, 0, n - c0 - w1, w2, w1, zc(-1.0), M + (c0 + w1) * ld + c0, ld, stride,
+              M + c0 * ld + c0 + w1, ld, stride, zc(1.0), M + (c0 + w1) * ld + c0 + w1, ld, stride,
+              batch);
+  panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info);
+}
+
+struct LuProf {
+  std::vector<hipEvent_t> *ev = nullptr;  // 2 per panel step
+  int used = 0;
+  double flops = 0.0;
+};
+
+template <typename T>
+void lu_batched(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n, int nb,
+                int32_t *ipiv, int32_t *info, T *Linv, T *Uinv, int64_t istride,
+                LuProf *prof = nullptr) {
+  feast::fill_i32(s, info, batch, 0);
+  for (int64_t k0 = 0; k0 < n; k0 += nb) {
+    const int kb = static_cast<int>(std::min<int64_t>(nb, n - k0));
+    const int64_t blk = k0 / nb;
+    panel_rec<T>(s, M, ld, stride, batch, n, k0, kb, k0, kb, ipiv, info);
+    feast::laswp_outside<T>(s, M, ld, stride, batch, n, k0, kb, k0, k0 + kb, ipiv);
+    feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, nb, blk, blk + 1, true, Linv, istride);
+    const int64_t rest = n - k0 - kb;
+    if (rest > 0) {
+      // U12 = L11^{-1} A12, in place (one 64-row tile covers the kb <= 64 rows)
+      gemm_t<T>(s, 0, kb, rest, kb, zc(1.0), Linv + blk * nb * nb, nb, istride,
+                M + k0 * ld + k0 + kb, ld, stride, zc(0.0), M + k0 * ld + k0 + kb, ld, stride,
+                batch);
+      // A22 -= L21 U12
+      const bool timed = prof && prof->ev && prof->used + 2 <= static_cast<int>(prof->ev->size());
+      if (timed) HIPCHK(hipEventRecord((*prof->ev)[prof->used], s));
+      gemm_t<T>(s, 0, rest, rest, kb, zc(-1.0), M + (k0 + kb) * ld + k0, ld, stride,
+                M + k0 * ld + k0 + kb, ld, stride, zc(1.0), M + (k0 + kb) * ld + k0 + kb, ld,
+                stride, batch);
+      if (timed) {
+        HIPCHK(hipEventRecord((*prof->ev)[prof->used + 1], s));
+        prof->used += 2;
+        prof->flops += 8.0 * static_cast<double>(rest) * rest * kb * batch;
+      }
+    }
+  }
+  const int64_t nblk = (n + nb - 1) / nb;
+  feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, nb, 0, nblk, false, Uinv, istride);
+}
+
+// Blocked triangular solves with the cached factors, in place on Y
+// (per node: n x m, leading dimension ldy, node stride sY).
+//   trans = 0: Y <- U^{-1} L^{-1} Y   (after the row permutation)
+//   trans = 2: Y <- L^{-*} U^{-*} Y   (before the inverse permutation)
+template <typename T>
+void trsolve(hipStream_t s, const T *F, int64_t ld, int64_t fstride, int32_t batch, int64_t n,
+             int nb, const T *Linv, const T *Uinv, int64_t istride, T *Y, int64_t m, int64_t ldy,
+             int64_t sY, int trans) {
+  const int64_t nblk = (n + nb - 1) / nb;
+  const z64 one = zc(1.0), zero = zc(0.0), mone = zc(-1.0);
+  if (trans == 0) {
+    for (int64_t I = 0; I < nblk; ++I) {
+      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
+      gemm_t<T>(s, 0, rb, m, rb, one, Linv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
+                Y + r0 * ldy, ldy, sY, batch);
+      if (r0 + rb < n)
+        gemm_t<T>(s, 0, n - r0 - rb, m, rb, mone, F + (r0 + rb) * ld + r0, ld, fstride,
+                  Y + r0 * ldy, ldy, sY, one, Y + (r0 + rb) * ldy, ldy, sY, batch);
+    }
+    for (int64_t I = nblk - 1; I >= 0; --I) {
+      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
+      gemm_t<T>(s, 0, rb, m, rb, one, Uinv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
+                Y + r0 * ldy, ldy, sY, batch);
+      if (r0 > 0)
+        gemm_t<T>(s, 0, r0, m, rb, mone, F + r0, ld, fstride, Y + r0 * ldy, ldy, sY, one, Y, ldy,
+                  sY, batch);
+    }
+  } else {
+    // M^* = U^* L^* P: forward with U^* (lower), then backward with L^* (unit upper)
+    for (int64_t I = 0; I < nblk; ++I) {
+      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
+      gemm_t<T>(s, 2, rb, m, rb, one, Uinv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
+                Y + r0 * ldy, ldy, sY, batch);
+      if (r0 + rb < n)
+        gemm_t<T>(s, 2, n - r0 - rb, m, rb, mone, F + r0 * ld + r0 + rb, ld, fstride, Y + r0 * ldy,
+                  ldy, sY, one, Y + (r0 + rb) * ldy, ldy, sY, batch);
+    }
+    for (int64_t I = nblk - 1; I >= 0; --I) {
+      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
+      gemm_t<T>(s, 2, rb, m, rb, one, Linv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
+                Y + r0 * ldy, ldy, sY, batch);
+      if (r0 > 0)
+        gemm_t<T>(s, 2, r0, m, rb, mone, F + r0 * ld, ld, fstride, Y + r0 * ldy, ldy, sY, one, Y,
+                  ldy, sY, batch);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plan helpers
+// ---------------------------------------------------------------------------
+
+void ensure_workspace(feast_plan *p) {
+  const int64_t n = p->n, m = p->m, N = p->N;
+  const size_t zs = sizeof(z64);
+  p->R.alloc(zs * n * m);
+  p->Y.alloc(zs * n * m * N);
+  p->W.alloc(zs * n * m * feast_plan::W_COUNT);
+  p->G.alloc(zs * m * m * feast_plan::G_COUNT);
+  p->splitws.alloc(zs * std::max<int64_t>(m * m * 96, 1 << 16));
+  p->part.alloc(sizeof(double) * std::max<int64_t>(((n + 63) / 64) * 3 * m, 64 * N + 64));
+  p->nrm.alloc(sizeof(double) * (3 * m + 4 * N + 16));
+  p->flag.alloc(sizeof(int32_t) * 16);
+  p->small.alloc(zs * (2 * m + 16));
+  if (p->mixed()) {
+    p->T1.alloc(zs * n * m * N);
+    p->T2.alloc(zs * n * m * N);
+    p->Yc.alloc(sizeof(c64) * n * m * N);
+  }
+}
+
+int64_t splitws_elems(const feast_plan *p) {
+  return static_cast<int64_t>(p->splitws.bytes / sizeof(z64));
+}
+
+// Factor every shifted matrix z_j B - A once and cache the factors (Section 4.3).
+int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
+  const int64_t n = p->n;
+  const int N = p->N;
+  hipStream_t s = p->s;
+  const size_t esz = p->mixed() ? sizeof(c64) : sizeof(z64);
+  p->factored = false;
+  p->F.alloc(esz * N * n * n);
+  p->piv.alloc(sizeof(int32_t) * N * n);
+  p->perm.alloc(sizeof(int32_t) * N * n);
+  p->info.alloc(sizeof(int32_t) * N);
+  p->Linv.alloc(esz * N * p->istride());
+  p->Uinv.alloc(esz * N * p->istride());
+  LuProf prof;
+  if (p->o.profile) {
+    const size_t need = 2 * static_cast<size_t>(p->nblk);
+    while (p->ev.size() < need) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      p->ev.push_back(e);
+    }
+    prof.ev = &p->ev;
+  }
+  if (p->mixed()) {
+    feast::shift_assemble_c(s, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
+    lu_batched<c64>(s, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
+                    p->info.as<int32_t>(), p->Linv.as<c64>(), p->Uinv.as<c64>(), p->istride(),
+                    &prof);
+  } else {
+    feast::shift_assemble_z(s, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<z64>(), n, n * n);
+    lu_batched<z64>(s, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
+                    p->info.as<int32_t>(), p->Linv.as<z64>(), p->Uinv.as<z64>(), p->istride(),
+                    &prof);
+  }
+  feast::perm_from_ipiv(s, p->piv.as<int32_t>(), p->perm.as<int32_t>(), n, N);
+  double *nrm = p->nrm.as<double>();
+  feast::fro2_batched(s, A, lda, 0, n, n, 1, p->part.as<double>(), nrm);
+  feast::fro2_batched(s, B, ldb, 0, n, n, 1, p->part.as<double>(), nrm + 1);
+  std::vector<int32_t> hinfo(N);
+  double h2[2];
+  HIPCHK(hipMemcpyAsync(hinfo.data(), p->info.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(h2, nrm, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  p->normA = std::sqrt(h2[0]);
+  p->normB = std::sqrt(h2[1]);
+  p->prof_launches = prof.used / 2;
+  p->prof_flops = prof.flops;
+  p->prof_ms = 0.0;
+  for (int i = 0; i + 1 < prof.used; i += 2) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
+    p->prof_ms += ms;
+  }
+  p->factored = true;
+  p->fA = A;
+  p->fB = B;
+  p->flda = lda;
+  p->fldb = ldb;
+  for (int j = 0; j < N; ++j)
+    if (hinfo[j] != 0) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf, "exact zero pivot at node %d (z = %.17g%+.17gi), column %d", j,
+                    p->hz[j].real(), p->hz[j].imag(), hinfo[j] - 1);
+      p->err = buf;
+      return FEAST_SINGULAR;
+    }
+  return FEAST_OK;
+}
+
+int ensure_factored(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
+  if (p->factored && p->fA == A && p->fB == B && p->flda == lda && p->fldb == ldb) return FEAST_OK;
+  return factor(p, A, lda, B, ldb);
+}
+
+// FP64 form: Y_j = (z_j B - A)^{-1} R for all nodes (Y: n x N m, node j at columns j m).
+void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr) {
+  const int64_t n = p->n, m = p->m, ldY = p->ldY();
+  z64 *Y = p->Y.as<z64>();
+  feast::gather_rows<z64>(p->s, R, ldr, 0, p->perm.as<int32_t>(), n, m, p->N, Y, ldY, m);
+  trsolve<z64>(p->s, p->F.as<z64>(), n, p->fstride(), p->N, n, p->nb, p->Linv.as<z64>(),
+               p->Uinv.as<z64>(), p->istride(), Y, m, ldY, m, 0);
+}
+
+// Mixed form (spec precision form): complex64 LU solves; FP64 residual
+// r_j = R - (z_j B - A) Y_j of all nodes as the two GEMMs A Y and B Y; the
+// complex64 correction d_j = (LU32_j)^{-1} r_j and the FP64 update Y_j += d_j,
+// repeated until every node's normwise backward error
+//   ||r_j||_F / ((|z_j| ||B||_F + ||A||_F) ||Y_j||_F + ||R||_F)
+// is at most `target` (target <= 0: no refinement).
+void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
+                       const z64 *R, int64_t ldr, double target) {
+  const int64_t n = p->n, m = p->m, ldY = p->ldY();
+  const int N = p->N;
+  hipStream_t s = p->s;
+  z64 *Y = p->Y.as<z64>();
+  c64 *Yc = p->Yc.as<c64>();
+  z64 *T1 = p->T1.as<z64>(), *T2 = p->T2.as<z64>();
+  const c64 *F = p->F.as<c64>();
+  const int32_t *perm = p->perm.as<int32_t>();
+  double *part = p->part.as<double>(), *nrm = p->nrm.as<double>();
+  // complex64 solve of P_j R
+  feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, m);
+  feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0);
+  trsolve<c64>(s, F, n, p->fstride(), N, n, p->nb, p->Linv.as<c64>(), p->Uinv.as<c64>(),
+               p->istride(), Yc, m, ldY, m, 0);
+  feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
+  p->last_sweeps = 0;
+  p->last_be = -1.0;
+  p->stagnated = false;
+  if (!(target > 0.0)) return;
+  feast::fro2_batched(s, R, ldr, 0, n, m, 1, part, nrm + 2 * N);
+  std::vector<double> hn(2 * N + 1);
+  double prev_worst = INFINITY;
+  for (int sweep = 0; sweep <= p->o.max_sweeps; ++sweep) {
+    gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), A, lda, 0, Y, ldY, 0, zc(0.0), T1, ldY, 0, 1);
+    gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), B, ldb, 0, Y, ldY, 0, zc(0.0), T2, ldY, 0, 1);
+    feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, m);
+    feast::fro2_batched(s, T1, ldY, m, n, m, N, part, nrm);
+    feast::fro2_batched(s, Y, ldY, m, n, m, N, part, nrm + N);
+    HIPCHK(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * (2 * N + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double nR = std::sqrt(hn[2 * N]);
+    double worst = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const double mj = std::abs(p->hz[j]) * p->normB + p->normA;
+      const double be = std::sqrt(hn[j]) / (mj * std::sqrt(hn[N + j]) + nR);
+      worst = std::max(worst, be);
+    }
+    p->last_be = worst;
+    if (worst <= target) return;
+    if (sweep == p->o.max_sweeps || !(worst < 0.5 * prev_worst)) {
+      p->stagnated = true;
+      return;
+    }
+    prev_worst = worst;
+    feast::gather_rows<z64>(s, T1, ldY, m, perm, n, m, N, T2, ldY, m);
+    feast::z_to_c(s, T2, ldY, 0, n, ldY, 1, Yc, ldY, 0);
+    trsolve<c64>(s, F, n, p->fstride(), N, n, p->nb, p->Linv.as<c64>(), p->Uinv.as<c64>(),
+                 p->istride(), Yc, m, ldY, m, 0);
+    feast::add_c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
+    p->last_sweeps = sweep + 1;
+  }
+}
+
+// U = sum_j w_j (z_j B - A)^{-1} R  (the filter of eq. 8-4 on the right-hand side R = B U_1).
+int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb, const z64 *R,
+               int64_t ldr, z64 *U, int64_t ldu, double target) {
+  int st = ensure_factored(p, A, lda, B, ldb);
+  if (p->mixed())
+    solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target);
+  else
+    solve_nodes_z(p, R, ldr);
+  feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, p->m, U,
+                      ldu);
+  if (st == FEAST_OK && p->mixed() && p->stagnated) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "refinement stopped at backward error %.3e (target %.3e) after %d sweeps",
+                  p->last_be, target, p->last_sweeps);
+    p->err = buf;
+    st = FEAST_REFINE_STAGNATED;
+  }
+  return st;
+}
+
+// Shifted Cholesky QR3 (three Cholesky QR passes, the first on X^*X + s I with
+// s = 11 (n m + m (m+1)) u ||X||_F^2): an FP64 orthonormalisation that stays
+// stable for condition numbers up to about 1/u, built from the Gram GEMM,
+// a t x t Cholesky, a triangular inverse and one more GEMM per pass.
+void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot) {
+  const int64_t n = p->n, m = p->m;
+  hipStream_t s = p->s;
+  z64 *G = p->gblk(feast_plan::G_GRAM);
+  z64 *Wt = p->wblk(feast_plan::W_ORTH);
+  int32_t *flag = p->flag.as<int32_t>() + flag_slot;
+  const double shift_rel = 11.0 * (static_cast<double>(n) * m + static_cast<double>(m) * (m + 1)) * kU64;
+  for (int pass = 0; pass < 3; ++pass) {
+    gemm_t<z64>(s, 2, m, m, n, zc(1.0), X, ldx, 0, X, ldx, 0, zc(0.0), G, m, 0, 1,
+                p->splitws.as<z64>(), splitws_elems(p));
+    feast::cholesky_upper(s, G, m, pass == 0 ? shift_rel : 0.0, flag + pass);
+    feast::trinv_upper(s, G, m);
+    gemm_t<z64>(s, 0, n, m, m, zc(1.0), X, ldx, 0, G, m, 0, zc(0.0), Wt, m, 0, 1);
+    feast::copy_block_z(s, Wt, m, n, m, X, ldx);
+  }
+}
+
+// Algorithm 5 lines 2/17 and 5: U -> U_1, A U_1, B U_1, U_2, At, Bt (device m x m).
+void project_device(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb, z64 *U,
+                    int64_t ldu, z64 *AU1, int64_t ldau, z64 *BU1, int64_t ldbu) {
+  const int64_t n = p->n, m = p->m;
+  hipStream_t s = p->s;
+  feast::fill_i32(s, p->flag.as<int32_t>(), 6, 0);
+  orth(p, U, ldu, 0);
+  gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, U, ldu, 0, zc(0.0), BU1, ldbu, 0, 1);
+  gemm_t<z64>(s, 0, n, m, n, zc(1.0), A, lda, 0, U, ldu, 0, zc(0.0), AU1, ldau, 0, 1);
+  z64 *U2 = p->wblk(feast_plan::W_U2);
+  feast::copy_block_z(s, BU1, ldbu, n, m, U2, m);
+  orth(p, U2, m, 3);
+  gemm_t<z64>(s, 2, m, m, n, zc(1.0), U2, m, 0, AU1, ldau, 0, zc(0.0), p->gblk(feast_plan::G_AT),
+              m, 0, 1, p->splitws.as<z64>(), splitws_elems(p));
+  gemm_t<z64>(s, 2, m, m, n, zc(1.0), U2, m, 0, BU1, ldbu, 0, zc(0.0), p->gblk(feast_plan::G_BT),
+              m, 0, 1, p->splitws.as<z64>(), splitws_elems(p));
+}
+
+int project_finish(feast_plan *p, feast_z *hAt, feast_z *hBt) {
+  const int64_t m = p->m;
+  hipStream_t s = p->s;
+  int32_t hf[6];
+  HIPCHK(hipMemcpyAsync(hAt, p->gblk(feast_plan::G_AT), sizeof(z64) * m * m, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hBt, p->gblk(feast_plan::G_BT), sizeof(z64) * m * m, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hf, p->flag.p, sizeof(int32_t) * 6, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  for (int i = 0; i < 6; ++i)
+    if (hf[i] != 0) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "Cholesky QR pass %d of %s broke down at column %d", i % 3 + 1,
+                    i < 3 ? "U" : "B U_1", hf[i] - 1);
+      p->err = buf;
+      return FEAST_ENUMERIC;
+    }
+  return FEAST_OK;
+}
+
+bool bad_contour(const feast_contour *c) {
+  return !c || !(c->radius > 0.0) || !std::isfinite(c->radius) || !std::isfinite(c->center.re) ||
+         !std::isfinite(c->center.im) || c->nodes < 1 || c->nodes > 1024 ||
+         (c->rule != FEAST_TRAPEZOID && c->rule != FEAST_GAUSS_LEGENDRE);
+}
+
+template <typename F> int guarded(feast_plan *p, F &&f) {
+  try {
+    return f();
+  } catch (const HipError &e) {
+    if (p) {
+      p->err = std::string(e.what) + ": " + hipGetErrorString(e.e);
+      p->factored = false;
+    }
+    return e.e == hipErrorOutOfMemory ? FEAST_ENOMEM : FEAST_EDEVICE;
+  } catch (const std::bad_alloc &) {
+    if (p) p->err = "host allocation failed";
+    return FEAST_ENOMEM;
+  } catch (...) {
+    if (p) p->err = "unexpected exception";
+    return FEAST_EDEVICE;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int feast_version(void) { return 10000; }
+
+void feast_opts_default(feast_opts *o) {
+  if (!o) return;
+  o->eps = 1e-10;
+  o->eta = 1e-3;
+  o->max_iter = 20;
+  o->prec = FEAST_FP64;
+  o->refine_tol = 4.0 * kU64;
+  o->max_sweeps = 6;
+  o->nb = 0;
+  o->profile = 0;
+}
+
+int feast_nodes(const feast_contour *c, feast_z *hz, feast_z *hw) {
+  if (bad_contour(c) || !hz || !hw) return FEAST_EINVAL;
+  std::vector<cd> z(c->nodes), w(c->nodes);
+  if (feast_host::contour_nodes(cd(c->center.re, c->center.im), c->radius, c->nodes, c->rule,
+                                z.data(), w.data()) != 0)
+    return FEAST_EINVAL;
+  for (int j = 0; j < c->nodes; ++j) {
+    hz[j] = {z[j].real(), z[j].imag()};
+    hw[j] = {w[j].real(), w[j].imag()};
+  }
+  return FEAST_OK;
+}
+
+int feast_stop_rule(int32_t k, int32_t c_k, double e_k, int32_t c_prev, double e_prev, double eps,
+                    int32_t max_iter) {
+  return feast_host::stop_rule(k, c_k, e_k, c_prev, e_prev, eps, max_iter);
+}
+
+int feast_reduced_eig(int64_t t, const feast_z *hAt, int64_t lda, const feast_z *hBt, int64_t ldb,
+                      feast_z *halpha, feast_z *hbeta, feast_z *hY, int64_t ldy) {
+  if (t < 0 || (t > 0 && (!hAt || !hBt || !halpha || !hbeta || !hY)) || lda < t || ldb < t || ldy < t)
+    return FEAST_EINVAL;
+  try {
+    const int nt = static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    const int rc = feast_host::reduced_eig(t, reinterpret_cast<const cd *>(hAt), lda,
+                                           reinterpret_cast<const cd *>(hBt), ldb,
+                                           reinterpret_cast<cd *>(halpha),
+                                           reinterpret_cast<cd *>(hbeta), reinterpret_cast<cd *>(hY),
+                                           ldy, nt);
+    return rc == 0 ? FEAST_OK : FEAST_ENUMERIC;
+  } catch (...) {
+    return FEAST_ENOMEM;
+  }
+}
+
+int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_contour *c,
+                      const feast_opts *o, void *stream) {
+  if (!plan) return FEAST_EINVAL;
+  *plan = nullptr;
+  feast_opts opts;
+  feast_opts_default(&opts);
+  if (o) opts = *o;
+  if (n < 1 || n > 16384 || m < 1 || m > n || bad_contour(c)) return FEAST_EINVAL;
+  if (!(opts.eta > 0.0) || !(opts.eps >= 0.0) || opts.max_iter < 1 ||
+      opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
+      opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) ||
+      (opts.nb != 0 && opts.nb != 16 && opts.nb != 32 && opts.nb != 64))
+    return FEAST_EINVAL;
+  feast_plan *p = nullptr;
+  try {
+    p = new feast_plan();
+  } catch (...) {
+    return FEAST_ENOMEM;
+  }
+  p->n = n;
+  p->m = m;
+  p->N = c->nodes;
+  p->c = *c;
+  p->o = opts;
+  p->s = static_cast<hipStream_t>(stream);
+  p->nb = opts.nb ? opts.nb : 64;
+  p->nblk = (n + p->nb - 1) / p->nb;
+  p->hz.resize(p->N);
+  p->hw.resize(p->N);
+  feast_host::contour_nodes(cd(c->center.re, c->center.im), c->radius, p->N, c->rule, p->hz.data(),
+                            p->hw.data());
+  const int rc = guarded(p, [&]() {
+    p->dz.alloc(sizeof(z64) * p->N);
+    p->dw.alloc(sizeof(z64) * p->N);
+    HIPCHK(hipMemcpy(p->dz.p, p->hz.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->dw.p, p->hw.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
+    ensure_workspace(p);
+    return FEAST_OK;
+  });
+  if (rc != FEAST_OK) {
+    feast_plan_destroy(p);
+    return rc;
+  }
+  *plan = p;
+  return FEAST_OK;
+}
+
+int feast_plan_destroy(feast_plan *p) {
+  if (!p) return FEAST_OK;
+  if (p->s) (void)hipStreamSynchronize(p->s);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  for (DevBuf *b : {&p->dz, &p->dw, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->R,
+                    &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->part, &p->nrm,
+                    &p->flag, &p->small})
+    b->release();
+  delete p;
+  return FEAST_OK;
+}
+
+int feast_plan_invalidate(feast_plan *p) {
+  if (!p) return FEAST_EINVAL;
+  p->factored = false;
+  p->fA = p->fB = nullptr;
+  return FEAST_OK;
+}
+
+const char *feast_last_error(const feast_plan *p) { return p ? p->err.c_str() : "null plan"; }
+
+int feast_filter(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
+                 const feast_z *dV, int64_t ldv, feast_z *dU, int64_t ldu) {
+  if (!p) return FEAST_EINVAL;
+  if (!dA || !dB || !dV || !dU || lda < p->n || ldb < p->n || ldv < p->m || ldu < p->m)
+    return fail(p, FEAST_EINVAL, "feast_filter: null pointer or leading dimension too small");
+  p->err.clear();
+  return guarded(p, [&]() {
+    const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
+    const z64 *V = reinterpret_cast<const z64 *>(dV);
+    // R = B V
+    gemm_t<z64>(p->s, 0, p->n, p->m, p->n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(),
+                p->m, 0, 1);
+    const int st = filter_rhs(p, A, lda, B, ldb, p->R.as<z64>(), p->m, reinterpret_cast<z64 *>(dU),
+                              ldu, p->o.refine_tol);
+    HIPCHK(hipGetLastError());
+    return st;
+  });
+}
+
+int feast_project(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
+                  feast_z *dU, int64_t ldu, feast_z *dAU1, int64_t ldau, feast_z *dBU1,
+                  int64_t ldbu, feast_z *hAt, feast_z *hBt) {
+  if (!p) return FEAST_EINVAL;
+  if (!dA || !dB || !dU || !dAU1 || !dBU1 || !hAt || !hBt || lda < p->n || ldb < p->n ||
+      ldu < p->m || ldau < p->m || ldbu < p->m)
+    return fail(p, FEAST_EINVAL, "feast_project: null pointer or leading dimension too small");
+  p->err.clear();
+  return guarded(p, [&]() {
+    project_device(p, reinterpret_cast<const z64 *>(dA), lda, reinterpret_cast<const z64 *>(dB), ldb,
+                   reinterpret_cast<z64 *>(dU), ldu, reinterpret_cast<z64 *>(dAU1), ldau,
+                   reinterpret_cast<z64 *>(dBU1), ldbu);
+    return project_finish(p, hAt, hBt);
+  });
+}
+
+int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
+                const feast_z *dV, int64_t ldv, feast_z *hLambda, feast_z *dX, int64_t ldx,
+                double *hRes, int32_t *s_found, double *err, int32_t *flag, feast_info *info) {
+  if (!p) return FEAST_EINVAL;
+  if (!dA || !dB || !dV || !hLambda || !dX || !s_found || !err || !flag || lda < p->n ||
+      ldb < p->n || ldv < p->m || ldx < p->m)
+    return fail(p, FEAST_EINVAL, "feast_solve: null pointer or leading dimension too small");
+  p->err.clear();
+  return guarded(p, [&]() -> int {
+    const int64_t n = p->n, m = p->m;
+    hipStream_t s = p->s;
+    const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
+    const z64 *V = reinterpret_cast<const z64 *>(dV);
+    const cd gamma(p->c.center.re, p->c.center.im);
+    const double rho = p->c.radius;
+    feast_info inf{};
+    Timer total;
+    int status = FEAST_OK;
+    // cached factors (first filter)
+    {
+      Timer t;
+      const int st = ensure_factored(p, A, lda, B, ldb);
+      inf.t_factor_ms = t.ms();
+      if (st == FEAST_SINGULAR) return st;
+    }
+    z64 *U1 = p->wblk(feast_plan::W_U1), *AU1 = p->wblk(feast_plan::W_AU1);
+    z64 *BU1 = p->wblk(feast_plan::W_BU1), *UF = p->wblk(feast_plan::W_UF);
+    z64 *X = p->wblk(feast_plan::W_X), *AX = p->wblk(feast_plan::W_AX);
+    z64 *BX = p->wblk(feast_plan::W_BX), *Xprev = p->wblk(feast_plan::W_XPREV);
+    z64 *Ys = p->gblk(feast_plan::G_YS);
+    z64 *dlam = p->small.as<z64>();
+    int32_t *didx = reinterpret_cast<int32_t *>(p->small.as<z64>() + m);
+    double *dnorm = p->nrm.as<double>();
+    const int64_t mm = m * m;
+    std::vector<feast_z> hAt(mm), hBt(mm), hY(mm), halpha(m), hbeta(m);
+    std::vector<double> hn(3 * m);
+    // line 1 (Search with the subspace size fixed): U = Q_N V, then QR inside the projection
+    {
+      Timer t;
+      gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1);
+      const int st = filter_rhs(p, A, lda, B, ldb, p->R.as<z64>(), m, U1, m, 0.0);
+      if (st != FEAST_OK && st != FEAST_REFINE_STAGNATED) return st;
+      HIPCHK(hipStreamSynchronize(s));
+      inf.t_filter_ms += t.ms();
+      inf.sweeps[0] = p->last_sweeps;
+      inf.filters = 1;
+    }
+    // lines 2 and 5 of the first iteration
+    {
+      Timer t;
+      project_device(p, A, lda, B, ldb, U1, m, AU1, m, BU1, m);
+      const int st = project_finish(p, hAt.data(), hBt.data());
+      inf.t_project_ms += t.ms();
+      if (st != FEAST_OK) return st;
+    }
+    // line 3
+    double e_prev = 0.0;
+    int c_prev = 0;
+    std::vector<cd> lam_prev;
+    std::vector<double> r_prev;
+    for (int k = 1; k <= p->o.max_iter; ++k) {
+      // line 6: reduced pencil on the host
+      Timer te;
+      if (feast_reduced_eig(m, hAt.data(), m, hBt.data(), m, halpha.data(), hbeta.data(), hY.data(),
+                            m) != FEAST_OK)
+        return fail(p, FEAST_ENUMERIC, "reduced QZ did not converge");
+      inf.t_host_eig_ms += te.ms();
+      Timer tr;
+      std::vector<cd> lam(m);
+      std::vector<feast_z> hlam(m);
+      for (int64_t i = 0; i < m; ++i) {
+        const cd a(halpha[i].re, halpha[i].im), b(hbeta[i].re, hbeta[i].im);
+        lam[i] = (b != cd(0.0)) ? a / b : cd(INFINITY, 0.0);
+        hlam[i] = std::isfinite(lam[i].real()) ? feast_z{lam[i].real(), lam[i].imag()} : feast_z{0, 0};
+      }
+      // x_i = U_1 y_i together with A x_i = (A U_1) y_i and B x_i = (B U_1) y_i
+      HIPCHK(hipMemcpyAsync(Ys, hY.data(), sizeof(z64) * mm, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(dlam, hlam.data(), sizeof(z64) * m, hipMemcpyHostToDevice, s));
+      gemm_t<z64>(s, 0, n, m, m, zc(1.0), U1, m, 0, Ys, m, 0, zc(0.0), X, m, 0, 1);
+      gemm_t<z64>(s, 0, n, m, m, zc(1.0), AU1, m, 0, Ys, m, 0, zc(0.0), AX, m, 0, 1);
+      gemm_t<z64>(s, 0, n, m, m, zc(1.0), BU1, m, 0, Ys, m, 0, zc(0.0), BX, m, 0, 1);
+      feast::ritz_norms(s, AX, BX, m, n, m, dlam, p->part.as<double>(), dnorm);
+      HIPCHK(hipMemcpyAsync(hn.data(), dnorm, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      // lines 7-12: residuals (eq. 5-1), selection, c(k), e(k)
+      std::vector<int32_t> sel;
+      std::vector<double> rsel;
+      double e_k = 0.0;
+      for (int64_t i = 0; i < m; ++i) {
+        if (!std::isfinite(lam[i].real()) || !std::isfinite(lam[i].imag())) continue;
+        const double den = std::sqrt(hn[3 * i + 1]) + std::sqrt(hn[3 * i + 2]);
+        const double r = den > 0.0 ? std::sqrt(hn[3 * i]) / den : INFINITY;
+        if (std::abs(lam[i] - gamma) < rho && r < p->o.eta) {
+          sel.push_back(static_cast<int32_t>(i));
+          rsel.push_back(r);
+          e_k = std::max(e_k, r);
+        }
+      }
+      const int c_k = static_cast<int>(sel.size());
+      if (c_k == 0) e_k = INFINITY;
+      inf.count[k - 1] = c_k;
+      inf.err[k - 1] = e_k;
+      inf.iters = k;
+      // lines 13-15
+      const int act = feast_host::stop_rule(k, c_k, e_k, c_prev, e_prev, p->o.eps, p->o.max_iter);
+      if (act == 1 || act == -1) {
+        if (c_k > 0) {
+          HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s));
+          feast::gather_normalize_cols(s, X, m, n, didx, c_k, reinterpret_cast<z64 *>(dX), ldx, nullptr);
+        }
+        for (int i = 0; i < c_k; ++i) {
+          hLambda[i] = {lam[sel[i]].real(), lam[sel[i]].imag()};
+          if (hRes) hRes[i] = rsel[i];
+        }
+        *s_found = c_k;
+        *err = e_k;
+        *flag = act;
+        HIPCHK(hipStreamSynchronize(s));
+        inf.t_ritz_ms += tr.ms();
+        break;
+      }
+      if (act == 0) {
+        const int cp = static_cast<int>(lam_prev.size());
+        feast::copy_block_z(s, Xprev, m, n, cp, reinterpret_cast<z64 *>(dX), ldx);
+        for (int i = 0; i < cp; ++i) {
+          hLambda[i] = {lam_prev[i].real(), lam_prev[i].imag()};
+          if (hRes) hRes[i] = r_prev[i];
+        }
+        *s_found = cp;
+        *err = e_prev;
+        *flag = 0;
+        HIPCHK(hipStreamSynchronize(s));
+        inf.t_ritz_ms += tr.ms();
+        break;
+      }
+      // keep iterate k for a possible rebound at k+1
+      lam_prev.clear();
+      r_prev = rsel;
+      for (int i = 0; i < c_k; ++i) lam_prev.push_back(lam[sel[i]]);
+      if (c_k > 0) {
+        HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s));
+        feast::gather_normalize_cols(s, X, m, n, didx, c_k, Xprev, m, nullptr);
+      }
+      e_prev = e_k;
+      c_prev = c_k;
+      inf.t_ritz_ms += tr.ms();
+      // line 16: U = Q_N U_1 (right-hand side B U_1, cached factors)
+      {
+        Timer t;
+        const double target = p->mixed() ? p->o.refine_tol : 0.0;
+        const int st = filter_rhs(p, A, lda, B, ldb, BU1, m, UF, m, target);
+        if (st == FEAST_REFINE_STAGNATED) status = FEAST_REFINE_STAGNATED;
+        else if (st != FEAST_OK) return st;
+        HIPCHK(hipStreamSynchronize(s));
+        inf.t_filter_ms += t.ms();
+        if (inf.filters < FEAST_MAX_HISTORY) inf.sweeps[inf.filters] = p->last_sweeps;
+        inf.filters += 1;
+      }
+      // line 17 and line 5 of the next iteration
+      {
+        Timer t;
+        feast::copy_block_z(s, UF, m, n, m, U1, m);
+        project_device(p, A, lda, B, ldb, U1, m, AU1, m, BU1, m);
+        const int st = project_finish(p, hAt.data(), hBt.data());
+        inf.t_project_ms += t.ms();
+        if (st != FEAST_OK) return st;
+      }
+    }
+    inf.t_total_ms = total.ms();
+    inf.lu_gemm_launches = p->prof_launches;
+    inf.lu_gemm_ms = p->prof_ms;
+    inf.lu_gemm_flops = p->prof_flops;
+    if (info) *info = inf;
+    return status;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Kernel-level entry points
+// ---------------------------------------------------------------------------
+
+int feast_zgemm_batched(int32_t transA, int64_t M, int64_t N, int64_t K, feast_z alpha,
+                        const feast_z *dA, int64_t lda, int64_t strideA, const feast_z *dB,
+                        int64_t ldb, int64_t strideB, feast_z beta, feast_z *dC, int64_t ldc,
+                        int64_t strideC, int32_t batch, void *stream) {
+  if ((transA != 0 && transA != 2) || M < 0 || N < 0 || K < 0 || batch < 0) return FEAST_EINVAL;
+  if (M == 0 || N == 0 || batch == 0) return FEAST_OK;
+  if (!dA || !dB || !dC || ldc < N || ldb < N || lda < (transA == 0 ? K : M)) return FEAST_EINVAL;
+  return guarded(nullptr, [&]() {
+    gemm_t<z64>(static_cast<hipStream_t>(stream), transA, M, N, K, zc(alpha.re, alpha.im),
+                reinterpret_cast<const z64 *>(dA), lda, strideA, reinterpret_cast<const z64 *>(dB),
+                ldb, strideB, zc(beta.re, beta.im), reinterpret_cast<z64 *>(dC), ldc, strideC, batch);
+    HIPCHK(hipGetLastError());
+    return FEAST_OK;
+  });
+}
+
+int feast_zgetrf_batched(int64_t n, int32_t batch, feast_z *dM, int64_t ldm, int64_t strideM,
+                         int32_t *dPiv, int32_t *dInfo, int32_t nb, void *stream) {
+  if (n < 1 || n > 16384 || batch < 1 || !dM || !dPiv || !dInfo || ldm < n ||
+      (nb != 0 && nb != 16 && nb != 32 && nb != 64))
+    return FEAST_EINVAL;
+  const int b = nb ? nb : 64;
+  return guarded(nullptr, [&]() {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nblk = (n + b - 1) / b;
+    DevBuf Li, Ui;
+    Li.alloc(sizeof(z64) * batch * nblk * b * b);
+    Ui.alloc(sizeof(z64) * batch * nblk * b * b);
+    lu_batched<z64>(s, reinterpret_cast<z64 *>(dM), ldm, strideM, batch, n, b, dPiv, dInfo,
+                    Li.as<z64>(), Ui.as<z64>(), nblk * b * b);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    Li.release();
+    Ui.release();
+    return FEAST_OK;
+  });
+}
+
+int feast_zgetrs_batched(int64_t n, int64_t nrhs, int32_t batch, const feast_z *dLU, int64_t ldm,
+                         int64_t strideM, const int32_t *dPiv, feast_z *dX, int64_t ldx,
+                         int64_t strideX, int32_t trans, void *stream) {
+  if (n < 1 || n > 16384 || nrhs < 0 || batch < 1 || !dLU || !dPiv || !dX || ldm < n ||
+      ldx < nrhs || (trans != 0 && trans != 2))
+    return FEAST_EINVAL;
+  if (nrhs == 0) return FEAST_OK;
+  return guarded(nullptr, [&]() {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int b = 64;
+    const int64_t nblk = (n + b - 1) / b;
+    DevBuf Li, Ui, perm, T;
+    Li.alloc(sizeof(z64) * batch * nblk * b * b);
+    Ui.alloc(sizeof(z64) * batch * nblk * b * b);
+    perm.alloc(sizeof(int32_t) * batch * n);
+    T.alloc(sizeof(z64) * batch * n * nrhs);
+    const z64 *F = reinterpret_cast<const z64 *>(dLU);
+    z64 *Xz = reinterpret_cast<z64 *>(dX);
+    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, b, 0, nblk, true, Li.as<z64>(), nblk * b * b);
+    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, b, 0, nblk, false, Ui.as<z64>(), nblk * b * b);
+    feast::perm_from_ipiv(s, dPiv, perm.as<int32_t>(), n, batch);
+    if (trans == 0) {
+      feast::gather_rows<z64>(s, Xz, ldx, strideX, perm.as<int32_t>(), n, nrhs, batch, T.as<z64>(),
+                              nrhs, n * nrhs);
+      trsolve<z64>(s, F, ldm, strideM, batch, n, b, Li.as<z64>(), Ui.as<z64>(), nblk * b * b,
+                   T.as<z64>(), nrhs, nrhs, n * nrhs, 0);
+      for (int32_t i = 0; i < batch; ++i)
+        feast::copy_block_z(s, T.as<z64>() + i * n * nrhs, nrhs, n, nrhs, Xz + i * strideX, ldx);
+    } else {
+      for (int32_t i = 0; i < batch; ++i)
+        feast::copy_block_z(s, Xz + i * strideX, ldx, n, nrhs, T.as<z64>() + i * n * nrhs, nrhs);
+      trsolve<z64>(s, F, ldm, strideM, batch, n, b, Li.as<z64>(), Ui.as<z64>(), nblk * b * b,
+                   T.as<z64>(), nrhs, nrhs, n * nrhs, 2);
+      feast::scatter_rows<z64>(s, T.as<z64>(), nrhs, n * nrhs, perm.as<int32_t>(), n, nrhs, batch,
+                               Xz, ldx, strideX);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return FEAST_OK;
+  });
+}
+
+}  // extern "C"

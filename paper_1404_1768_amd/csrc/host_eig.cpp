@@ -1,0 +1,344 @@
+// Host solver of the reduced t x t pencil  At y = lambda Bt y  (Algorithm 5
+// line 6; Section 3 names LAPACK's xGGES/xGGEV for this step).  It is a
+// from-scratch complex QZ:
+//   1. Bt -> upper triangular by Givens rotations from the left (applied to At);
+//   2. Hessenberg-triangular reduction of (At, Bt) (row rotations from the left,
+//      column rotations from the right, the right ones accumulated in Z);
+//   3. single-shift complex QZ iteration with deflation of negligible
+//      subdiagonal entries of the Hessenberg matrix and of zero diagonal
+//      entries of the triangular one (infinite eigenvalues);
+//   4. right eigenvectors of the triangular pencil (S, P) by back substitution,
+//      mapped back with Z and normalised to unit 2-norm.
+// Left rotations never need to be stored: right eigenvectors only depend on Z.
+//
+// Storage is column-major std::complex<double> inside this file.
+#include "host_eig.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <limits>
+#include <thread>
+#include <vector>
+
+namespace feast_host {
+
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr double kUlp = std::numeric_limits<double>::epsilon();
+constexpr double kSafmin = std::numeric_limits<double>::min();
+
+struct Mat {
+  int64_t n;
+  std::vector<cd> a;
+  explicit Mat(int64_t n_) : n(n_), a(static_cast<size_t>(n_ * n_)) {}
+  cd &operator()(int64_t i, int64_t j) { return a[static_cast<size_t>(j * n + i)]; }
+  cd operator()(int64_t i, int64_t j) const { return a[static_cast<size_t>(j * n + i)]; }
+  cd *col(int64_t j) { return a.data() + j * n; }
+};
+
+// Plane rotation G = [c s; -conj(s) c] with G [f; g] = [r; 0], c real >= 0.
+inline void rot_gen(cd f, cd g, double &c, cd &s, cd &r) {
+  const double ga = std::abs(g);
+  if (ga == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    r = f;
+    return;
+  }
+  const double fa = std::abs(f);
+  if (fa == 0.0) {
+    c = 0.0;
+    s = std::conj(g) / ga;
+    r = ga;
+    return;
+  }
+  const double d = std::hypot(fa, ga);
+  c = fa / d;
+  const cd ph = f / fa;
+  s = ph * std::conj(g) / d;
+  r = ph * d;
+}
+
+// Rows (p, q) <- G [row p; row q] over columns [j0, j1).
+inline void rot_rows(Mat &M, int64_t p, int64_t q, int64_t j0, int64_t j1, double c, cd s) {
+  const cd sc = std::conj(s);
+  for (int64_t j = j0; j < j1; ++j) {
+    cd &x = M(p, j);
+    cd &y = M(q, j);
+    const cd xv = x, yv = y;
+    x = c * xv + s * yv;
+    y = -sc * xv + c * yv;
+  }
+}
+
+// Columns (p, q) <- [col p, col q] W with W = [c conj(s); -s c] over rows [i0, i1).
+// Built from rot_gen(conj(M(i,q)), conj(M(i,p))) it zeroes M(i, p).
+inline void rot_cols(Mat &M, int64_t p, int64_t q, int64_t i0, int64_t i1, double c, cd s) {
+  const cd sc = std::conj(s);
+  cd *cp = M.col(p);
+  cd *cq = M.col(q);
+  for (int64_t i = i0; i < i1; ++i) {
+    const cd xv = cp[i], yv = cq[i];
+    cp[i] = c * xv - s * yv;
+    cq[i] = sc * xv + c * yv;
+  }
+}
+
+// Rotation zeroing M(i, p) against M(i, q) by a right rotation of columns p, q.
+inline void col_rot_for(const Mat &M, int64_t i, int64_t p, int64_t q, double &c, cd &s) {
+  cd r;
+  rot_gen(std::conj(M(i, q)), std::conj(M(i, p)), c, s, r);
+}
+
+double fro(const Mat &M) {
+  double s = 0.0;
+  for (const cd &v : M.a) s += std::norm(v);
+  return std::sqrt(s);
+}
+
+// Eigenvalue of the 2x2 pencil (H, T) at rows/cols (k, k+1) closest to h22/t22.
+cd wilkinson_shift(const Mat &H, const Mat &T, int64_t k) {
+  const cd h11 = H(k, k), h12 = H(k, k + 1), h21 = H(k + 1, k), h22 = H(k + 1, k + 1);
+  const cd t11 = T(k, k), t12 = T(k, k + 1), t22 = T(k + 1, k + 1);
+  // det(Hb - lam Tb) = a lam^2 + b lam + c0 with t21 = 0
+  const cd a = t11 * t22;
+  const cd b = -(h11 * t22 + h22 * t11 - h21 * t12);
+  const cd c0 = h11 * h22 - h12 * h21;
+  const cd target = h22 / t22;
+  if (std::abs(a) == 0.0) return target;
+  const cd disc = std::sqrt(b * b - 4.0 * a * c0);
+  cd q = (std::real(std::conj(b) * disc) >= 0.0) ? -0.5 * (b + disc) : -0.5 * (b - disc);
+  cd r1 = (std::abs(q) > 0.0) ? c0 / q : target;
+  cd r2 = q / a;
+  return (std::abs(r1 - target) <= std::abs(r2 - target)) ? r1 : r2;
+}
+
+}  // namespace
+
+int reduced_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb,
+                cd *alpha, cd *beta, cd *Y, int64_t ldy, int nthreads) {
+  if (t <= 0) return 0;
+  Mat H(t), T(t), Z(t);
+  for (int64_t i = 0; i < t; ++i)
+    for (int64_t j = 0; j < t; ++j) {
+      H(i, j) = At[i * lda + j];
+      T(i, j) = Bt[i * ldb + j];
+      Z(i, j) = (i == j) ? cd(1.0) : cd(0.0);
+    }
+  for (const cd &v : H.a)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return -1;
+  for (const cd &v : T.a)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return -1;
+
+  // 1. T -> upper triangular (left rotations, also applied to H).
+  for (int64_t j = 0; j + 1 < t; ++j) {
+    for (int64_t i = t - 1; i > j; --i) {
+      if (T(i, j) == cd(0.0)) continue;
+      double c;
+      cd s, r;
+      rot_gen(T(i - 1, j), T(i, j), c, s, r);
+      rot_rows(T, i - 1, i, j, t, c, s);
+      T(i, j) = 0.0;
+      rot_rows(H, i - 1, i, 0, t, c, s);
+    }
+  }
+  // 2. Hessenberg-triangular reduction.
+  for (int64_t j = 0; j + 2 < t; ++j) {
+    for (int64_t i = t - 1; i >= j + 2; --i) {
+      if (H(i, j) == cd(0.0)) continue;
+      double c;
+      cd s, r;
+      rot_gen(H(i - 1, j), H(i, j), c, s, r);
+      rot_rows(H, i - 1, i, j, t, c, s);
+      H(i, j) = 0.0;
+      rot_rows(T, i - 1, i, i - 1, t, c, s);
+      // T(i, i-1) is now filled: zero it with a column rotation of (i-1, i).
+      col_rot_for(T, i, i - 1, i, c, s);
+      rot_cols(T, i - 1, i, 0, i + 1, c, s);
+      T(i, i - 1) = 0.0;
+      rot_cols(H, i - 1, i, 0, t, c, s);
+      rot_cols(Z, i - 1, i, 0, t, c, s);
+    }
+  }
+
+  // 3. QZ iteration.
+  const double hnorm = fro(H), tnorm = fro(T);
+  const double atol = std::max(kSafmin, kUlp * hnorm);
+  const double btol = std::max(kSafmin, kUlp * tnorm);
+  int64_t ilast = t - 1;
+  int64_t since = 0;
+  const int64_t maxit = 40 * t + 100;
+  int64_t it = 0;
+  cd eshift = 0.0;
+  while (ilast >= 0) {
+    if (++it > maxit) return -2;
+    // (a) deflation of a negligible subdiagonal at the bottom
+    if (ilast == 0) {
+      ilast = -1;
+      break;
+    }
+    {
+      const double h = std::abs(H(ilast, ilast - 1));
+      if (h <= atol ||
+          h <= kUlp * (std::abs(H(ilast, ilast)) + std::abs(H(ilast - 1, ilast - 1)))) {
+        H(ilast, ilast - 1) = 0.0;
+        --ilast;
+        since = 0;
+        eshift = 0.0;
+        continue;
+      }
+    }
+    // (b) infinite eigenvalue at the bottom: T(ilast, ilast) negligible
+    if (std::abs(T(ilast, ilast)) <= btol) {
+      T(ilast, ilast) = 0.0;
+      double c;
+      cd s;
+      col_rot_for(H, ilast, ilast - 1, ilast, c, s);
+      rot_cols(H, ilast - 1, ilast, 0, ilast + 1, c, s);
+      H(ilast, ilast - 1) = 0.0;
+      rot_cols(T, ilast - 1, ilast, 0, ilast, c, s);
+      rot_cols(Z, ilast - 1, ilast, 0, t, c, s);
+      --ilast;
+      since = 0;
+      eshift = 0.0;
+      continue;
+    }
+    // (c) find the top of the unreduced block
+    int64_t ifirst = 0;
+    for (int64_t j = ilast - 1; j >= 1; --j) {
+      const double h = std::abs(H(j, j - 1));
+      if (h <= atol || h <= kUlp * (std::abs(H(j, j)) + std::abs(H(j - 1, j - 1)))) {
+        H(j, j - 1) = 0.0;
+        ifirst = j;
+        break;
+      }
+    }
+    // (d) zero diagonal of T inside the block: chase it to the bottom
+    int64_t jz = -1;
+    for (int64_t j = ifirst; j < ilast; ++j)
+      if (std::abs(T(j, j)) <= btol) {
+        jz = j;
+        break;
+      }
+    if (jz >= 0) {
+      T(jz, jz) = 0.0;
+      for (int64_t k = jz; k < ilast; ++k) {
+        double c;
+        cd s, r;
+        rot_gen(T(k, k + 1), T(k + 1, k + 1), c, s, r);
+        rot_rows(T, k, k + 1, k + 1, t, c, s);
+        T(k + 1, k + 1) = 0.0;
+        const int64_t h0 = (k > ifirst) ? k - 1 : k;
+        rot_rows(H, k, k + 1, h0, t, c, s);
+        if (k > ifirst) {
+          // fill at H(k+1, k-1): zero it with columns (k-1, k)
+          col_rot_for(H, k + 1, k - 1, k, c, s);
+          rot_cols(H, k - 1, k, 0, k + 2, c, s);
+          H(k + 1, k - 1) = 0.0;
+          rot_cols(T, k - 1, k, 0, k + 1, c, s);
+          rot_cols(Z, k - 1, k, 0, t, c, s);
+        }
+      }
+      continue;  // (b) deflates the bottom next
+    }
+    // (e) one implicit single-shift QZ sweep on [ifirst, ilast]
+    ++since;
+    cd sigma;
+    if (since % 10 == 0) {
+      // exceptional shift
+      eshift += H(ilast, ilast - 1) / T(ilast - 1, ilast - 1);
+      sigma = eshift;
+    } else {
+      sigma = wilkinson_shift(H, T, ilast - 1);
+    }
+    {
+      double c;
+      cd s, r;
+      const cd x = H(ifirst, ifirst) - sigma * T(ifirst, ifirst);
+      const cd y = H(ifirst + 1, ifirst);
+      rot_gen(x, y, c, s, r);
+      rot_rows(H, ifirst, ifirst + 1, ifirst, t, c, s);
+      rot_rows(T, ifirst, ifirst + 1, ifirst, t, c, s);
+    }
+    for (int64_t k = ifirst; k < ilast; ++k) {
+      double c;
+      cd s, r;
+      // restore T: zero T(k+1, k) with columns (k, k+1)
+      col_rot_for(T, k + 1, k, k + 1, c, s);
+      rot_cols(T, k, k + 1, 0, k + 2, c, s);
+      T(k + 1, k) = 0.0;
+      rot_cols(H, k, k + 1, 0, std::min(k + 3, t), c, s);
+      rot_cols(Z, k, k + 1, 0, t, c, s);
+      if (k + 2 <= ilast) {
+        // restore H: zero H(k+2, k) with rows (k+1, k+2)
+        rot_gen(H(k + 1, k), H(k + 2, k), c, s, r);
+        rot_rows(H, k + 1, k + 2, k, t, c, s);
+        H(k + 2, k) = 0.0;
+        rot_rows(T, k + 1, k + 2, k + 1, t, c, s);
+      }
+    }
+  }
+
+  // 4. eigenvalues and right eigenvectors
+  for (int64_t j = 0; j < t; ++j) {
+    alpha[j] = H(j, j);
+    beta[j] = T(j, j);
+  }
+  auto eigvec = [&](int64_t j, std::vector<cd> &v, std::vector<cd> &x) {
+    cd a = H(j, j), b = T(j, j);
+    const double sc = std::max(std::abs(a), std::abs(b));
+    if (sc > 0.0) {
+      a /= sc;
+      b /= sc;
+    } else {
+      b = 1.0;
+    }
+    std::fill(v.begin(), v.end(), cd(0.0));
+    v[j] = 1.0;
+    const double small = std::max(kSafmin, kUlp * (std::abs(b) * hnorm + std::abs(a) * tnorm));
+    for (int64_t k = j - 1; k >= 0; --k) {
+      cd acc = 0.0;
+      for (int64_t l = k + 1; l <= j; ++l) acc += (b * H(k, l) - a * T(k, l)) * v[l];
+      cd d = b * H(k, k) - a * T(k, k);
+      if (std::abs(d) < small) d = small;
+      v[k] = -acc / d;
+      // guard against growth: rescale the partial vector
+      const double m = std::abs(v[k]);
+      if (m > 1e100) {
+        for (int64_t l = k; l <= j; ++l) v[l] /= m;
+      }
+    }
+    std::fill(x.begin(), x.end(), cd(0.0));
+    for (int64_t l = 0; l <= j; ++l) {
+      const cd vl = v[l];
+      if (vl == cd(0.0)) continue;
+      const cd *zc = Z.a.data() + l * t;
+      for (int64_t i = 0; i < t; ++i) x[i] += zc[i] * vl;
+    }
+    double nr = 0.0;
+    for (const cd &e : x) nr += std::norm(e);
+    nr = std::sqrt(nr);
+    if (nr > 0.0)
+      for (cd &e : x) e /= nr;
+    for (int64_t i = 0; i < t; ++i) Y[i * ldy + j] = x[i];
+  };
+  const int nt = std::max(1, std::min<int>(nthreads, static_cast<int>((t + 31) / 32)));
+  if (nt == 1) {
+    std::vector<cd> v(t), x(t);
+    for (int64_t j = 0; j < t; ++j) eigvec(j, v, x);
+  } else {
+    std::vector<std::thread> th;
+    for (int w = 0; w < nt; ++w)
+      th.emplace_back([&, w]() {
+        std::vector<cd> v(t), x(t);
+        for (int64_t j = w; j < t; j += nt) eigvec(j, v, x);
+      });
+    for (auto &x : th) x.join();
+  }
+  return 0;
+}
+
+}  // namespace feast_host

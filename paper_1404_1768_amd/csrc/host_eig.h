@@ -1,0 +1,25 @@
+// Host-side pieces of Algorithm 5: the reduced-pencil eigensolver (line 6),
+// quadrature nodes (eq. 8-4) and the stopping rules (lines 13-15).
+#pragma once
+#include <complex>
+#include <cstdint>
+
+namespace feast_host {
+
+// All eigenpairs of the t x t pencil (At, Bt) (row-major inputs) by complex QZ.
+// alpha/beta: t entries; Y: right eigenvectors as columns (row-major, ldy),
+// unit 2-norm.  Returns 0, -1 (non-finite input) or -2 (no convergence).
+int reduced_eig(int64_t t, const std::complex<double> *At, int64_t lda,
+                const std::complex<double> *Bt, int64_t ldb, std::complex<double> *alpha,
+                std::complex<double> *beta, std::complex<double> *Y, int64_t ldy,
+                int nthreads);
+
+// Nodes z_j and weights w_j of the circle quadrature (rule 0: trapezoid with
+// half-offset angles; rule 1: Gauss-Legendre as in eq. 8-4).
+int contour_nodes(std::complex<double> center, double radius, int N, int rule,
+                  std::complex<double> *z, std::complex<double> *w);
+
+// Decision after iteration k: 1 (line 13), 0 (line 14), -1 (line 15), 2 continue.
+int stop_rule(int k, int c_k, double e_k, int c_prev, double e_prev, double eps, int max_iter);
+
+}  // namespace feast_host

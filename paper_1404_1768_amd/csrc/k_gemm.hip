@@ -1,0 +1,308 @@
+// Batched complex GEMM on the gfx950 matrix cores.
+//
+//   C_b = alpha * op(A_b) * B_b + beta * C_b        (row-major, interleaved complex)
+//
+// FP64 (z64): every complex 16x16x4 tile product is four real
+// v_mfma_f64_16x16x4_f64 products (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br),
+// i.e. 8 real flops per complex multiply-add, the count the roofline uses.
+// FP32 (c64): the same structure on v_mfma_f32_16x16x4_f32.
+//
+// Tiles: BM x BN outputs per 256-thread workgroup (4 waves in a 2x2 grid, each
+// wave owning a (BM/2) x (BN/2) block of 16x16 MFMA tiles), K in steps of 16
+// complex.  Operands are staged through LDS as separate real/imaginary planes
+// stored k-major, so that each MFMA operand fragment is 16 consecutive LDS
+// words per k row; the next K step is prefetched into registers while the
+// current one is multiplied (two LDS buffers, one barrier per step).
+//
+// Lane layouts (measured on gfx950):
+//   A operand (16x4): lane l holds A[l%16][l/16]; B operand (4x16): B[l/16][l%16]
+//   f64 result: lane l, element r holds D[4r + l/16][l%16]
+//   f32 result: lane l, element r holds D[4(l/16) + r][l%16]
+//
+// A launch covers batch x splits x tiles workgroups mapped XCD-contiguously.
+#include "common.h"
+#include "kernels.h"
+
+namespace feast {
+
+namespace {
+
+template <typename T> struct mfma_ops;
+
+template <> struct mfma_ops<z64> {
+  using real = double;
+  using acc_t = dx4;
+  __device__ static acc_t mma(real a, real b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of element r of the 16x16 result held by `lane`
+  __device__ static int out_row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+template <> struct mfma_ops<c64> {
+  using real = float;
+  using acc_t = fx4;
+  __device__ static acc_t mma(real a, real b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
+
+template <typename T, int BM, int BN, int TA>
+__global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
+  using Ops = mfma_ops<T>;
+  using real = typename Ops::real;
+  using acc_t = typename Ops::acc_t;
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int PA = BM + 2, PB = BN + 2;
+  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+  __shared__ real sAr[2][BK][PA], sAi[2][BK][PA], sBr[2][BK][PB], sBi[2][BK][PB];
+
+  const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+  const int64_t tiles = tm * tn;
+  const int64_t total = tiles * d.batch * d.splits;
+  int64_t lin = xcd_remap(blockIdx.x, grid_total);
+  if (lin >= total) return;
+  const int64_t tile = lin % tiles;
+  lin /= tiles;
+  const int64_t bidx = lin % d.batch;
+  const int64_t split = lin / d.batch;
+  const int64_t m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int64_t kbeg = split * d.kchunk;
+  const int64_t kend = (kbeg + d.kchunk < d.K) ? kbeg + d.kchunk : d.K;
+
+  const T *__restrict__ A = d.A + bidx * d.sA;
+  const T *__restrict__ B = d.B + bidx * d.sB;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  T ra[NA], rb[NB];
+
+  auto gload = [&](int64_t k0) {
+    if (TA == 0) {
+      // A is M x K row-major: 16 lanes read one row's 16 consecutive elements
+      const int kk = tid & 15, rr = tid >> 4;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int64_t r = m0 + rr + 16 * i, k = k0 + kk;
+        ra[i] = (r < d.M && k < kend) ? A[r * d.lda + k] : T{};
+      }
+    } else {
+      // A stored K x M row-major; op(A) = A^*
+      const int rr = tid & 63, kk = tid >> 6;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int64_t r = m0 + rr + 64 * (i % (BM / 64)), k = k0 + kk + 4 * (i / (BM / 64));
+        ra[i] = (r < d.M && k < kend) ? A[k * d.lda + r] : T{};
+      }
+    }
+    const int cc = tid & 63, kk = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int64_t c = n0 + cc + 64 * (i % (BN / 64)), k = k0 + kk + 4 * (i / (BN / 64));
+      rb[i] = (c < d.N && k < kend) ? B[k * d.ldb + c] : T{};
+    }
+  };
+  auto sstore = [&](int buf) {
+    if (TA == 0) {
+      const int kk = tid & 15, rr = tid >> 4;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        sAr[buf][kk][rr + 16 * i] = ra[i].x;
+        sAi[buf][kk][rr + 16 * i] = ra[i].y;
+      }
+    } else {
+      const int rr = tid & 63, kk = tid >> 6;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int r = rr + 64 * (i % (BM / 64)), k = kk + 4 * (i / (BM / 64));
+        sAr[buf][k][r] = ra[i].x;
+        sAi[buf][k][r] = -ra[i].y;
+      }
+    }
+    const int cc = tid & 63, kk = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int c = cc + 64 * (i % (BN / 64)), k = kk + 4 * (i / (BN / 64));
+      sBr[buf][k][c] = rb[i].x;
+      sBi[buf][k][c] = rb[i].y;
+    }
+  };
+
+  acc_t cr[FM][FN], ci[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cr[a][b][r] = 0;
+        ci[a][b][r] = 0;
+      }
+
+  const int nk = static_cast<int>((kend - kbeg + BK - 1) / BK);
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+  }
+  const int col16 = lane & 15, krow = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + static_cast<int64_t>(kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      real ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        ar[a] = sAr[buf][kk * 4 + krow][wm * WM + a * 16 + col16];
+        ai[a] = sAi[buf][kk * 4 + krow][wm * WM + a * 16 + col16];
+        nai[a] = -ai[a];
+      }
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        br[b] = sBr[buf][kk * 4 + krow][wn * WN + b * 16 + col16];
+        bi[b] = sBi[buf][kk * 4 + krow][wn * WN + b * 16 + col16];
+      }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          cr[a][b] = Ops::mma(ar[a], br[b], cr[a][b]);
+          ci[a][b] = Ops::mma(ar[a], bi[b], ci[a][b]);
+          cr[a][b] = Ops::mma(nai[a], bi[b], cr[a][b]);
+          ci[a][b] = Ops::mma(ai[a], br[b], ci[a][b]);
+        }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue
+  const real alr = static_cast<real>(d.alpha.x), ali = static_cast<real>(d.alpha.y);
+  const real ber = static_cast<real>(d.beta.x), bei = static_cast<real>(d.beta.y);
+  const bool use_beta = (ber != 0 || bei != 0);
+  T *__restrict__ C = d.C + bidx * d.sC;
+  T *__restrict__ W = (d.splits > 1) ? d.work + (split * d.batch + bidx) * d.M * d.N : nullptr;
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * WM + a * 16 + Ops::out_row(lane, r);
+        const int64_t col = n0 + wn * WN + b * 16 + col16;
+        if (row < d.M && col < d.N) {
+          const real xr = cr[a][b][r], xi = ci[a][b][r];
+          T v;
+          v.x = alr * xr - ali * xi;
+          v.y = alr * xi + ali * xr;
+          if (W) {
+            W[row * d.N + col] = v;
+          } else {
+            if (use_beta) {
+              const T o = C[row * d.ldc + col];
+              v.x += ber * o.x - bei * o.y;
+              v.y += ber * o.y + bei * o.x;
+            }
+            C[row * d.ldc + col] = v;
+          }
+        }
+      }
+}
+
+// Deterministic reduction of split-K partials: C = sum_s W_s + beta C.
+template <typename T>
+__global__ __launch_bounds__(256) void k_splitk_reduce(const GemmArgs<T> d) {
+  const int64_t per = d.M * d.N;
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  if (idx >= per * d.batch) return;
+  const int64_t b = idx / per, e = idx % per;
+  const int64_t row = e / d.N, col = e % d.N;
+  double sr = 0.0, si = 0.0;
+  for (int s = 0; s < d.splits; ++s) {
+    const T v = d.work[(s * d.batch + b) * per + e];
+    sr += v.x;
+    si += v.y;
+  }
+  T *C = d.C + b * d.sC + row * d.ldc + col;
+  if (d.beta.x != 0.0 || d.beta.y != 0.0) {
+    const T o = *C;
+    sr += d.beta.x * o.x - d.beta.y * o.y;
+    si += d.beta.x * o.y + d.beta.y * o.x;
+  }
+  T v;
+  v.x = static_cast<decltype(v.x)>(sr);
+  v.y = static_cast<decltype(v.y)>(si);
+  *C = v;
+}
+
+template <typename T, int BM, int BN>
+void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta) {
+  const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+  const int64_t total = tiles * d.batch * d.splits;
+  const int64_t padded = (total + 7) / 8 * 8;
+  if (ta == 0)
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, 0>), dim3(static_cast<unsigned>(padded)), dim3(256), 0,
+                       s, d, padded);
+  else
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, 2>), dim3(static_cast<unsigned>(padded)), dim3(256), 0,
+                       s, d, padded);
+}
+
+template <typename T>
+void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems) {
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+  if (d.K <= 0) {
+    // C = beta C: a GEMM with an empty K range does exactly that.
+    d.K = 0;
+  }
+  d.splits = 1;
+  d.kchunk = d.K > 0 ? d.K : 1;
+  const int BM = (cfg == GEMM_TALL) ? 128 : 64;
+  const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + 63) / 64);
+  // Split K when the output is too small to fill the chip.
+  if (d.work && d.K >= 512 && tiles * d.batch < 192) {
+    int64_t sp = (256 + tiles * d.batch - 1) / (tiles * d.batch);
+    sp = std::min<int64_t>(sp, d.K / 256);
+    while (sp > 1 && sp * d.batch * d.M * d.N > work_elems) --sp;
+    if (sp > 1) {
+      d.splits = static_cast<int32_t>(sp);
+      d.kchunk = ((d.K + sp - 1) / sp + 15) / 16 * 16;
+      d.splits = static_cast<int32_t>((d.K + d.kchunk - 1) / d.kchunk);
+    }
+  }
+  if (cfg == GEMM_TALL)
+    launch_cfg<T, 128, 64>(s, d, ta);
+  else
+    launch_cfg<T, 64, 64>(s, d, ta);
+  if (d.splits > 1) {
+    const int64_t n = d.M * d.N * d.batch;
+    hipLaunchKernelGGL((k_splitk_reduce<T>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256),
+                       0, s, d);
+  }
+}
+
+}  // namespace
+
+void zgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
+           int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,
+           int64_t ldc, int64_t sC, int32_t batch, z64 *work, int64_t work_elems, int cfg) {
+  GemmArgs<z64> d{M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, batch, 1, K, work};
+  gemm_impl<z64>(s, d, transA, cfg, work_elems);
+}
+
+void cgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha, const c64 *A,
+           int64_t lda, int64_t sA, const c64 *B, int64_t ldb, int64_t sB, z64 beta, c64 *C,
+           int64_t ldc, int64_t sC, int32_t batch, c64 *work, int64_t work_elems, int cfg) {
+  GemmArgs<c64> d{M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, batch, 1, K, work};
+  gemm_impl<c64>(s, d, transA, cfg, work_elems);
+}
+
+}  // namespace feast

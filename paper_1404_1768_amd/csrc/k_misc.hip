@@ -1,0 +1,476 @@
+// Bandwidth- and latency-bound kernels of the path: shifted-matrix assembly,
+// pivot gathers, the weighted node sum, column norms for the Ritz residuals,
+// and the small t x t kernels of the orthonormalisation.
+#include "common.h"
+#include "kernels.h"
+
+namespace feast {
+
+namespace {
+
+// M_j = z_j B - A for all N nodes: A and B are read once, each element is
+// written N times (the write of the N shifted matrices bounds this kernel).
+template <typename T>
+__global__ __launch_bounds__(256) void k_shift(const z64 *__restrict__ A, int64_t lda,
+                                               const z64 *__restrict__ B, int64_t ldb,
+                                               const z64 *__restrict__ z, int32_t N, int64_t n,
+                                               T *__restrict__ M, int64_t ldm, int64_t sM) {
+  const int64_t col = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t row = blockIdx.y;
+  if (col >= n) return;
+  const z64 a = A[row * lda + col], b = B[row * ldb + col];
+  for (int j = 0; j < N; ++j) {
+    const z64 zj = z[j];
+    T v;
+    v.x = static_cast<decltype(v.x)>(zj.x * b.x - zj.y * b.y - a.x);
+    v.y = static_cast<decltype(v.y)>(zj.x * b.y + zj.y * b.x - a.y);
+    M[j * sM + row * ldm + col] = v;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_rows(const T *__restrict__ R, int64_t ldr,
+                                                     int64_t sR, const int32_t *__restrict__ perm,
+                                                     int64_t n, int64_t m, T *__restrict__ Y,
+                                                     int64_t ldy, int64_t sY) {
+  const int64_t row = blockIdx.x;
+  const int b = blockIdx.y;
+  const int64_t src = perm[b * n + row];
+  for (int64_t c = threadIdx.x; c < m; c += 256)
+    Y[b * sY + row * ldy + c] = R[b * sR + src * ldr + c];
+}
+
+__global__ __launch_bounds__(256) void k_shift_residual(const z64 *__restrict__ R, int64_t ldr,
+                                                        z64 *__restrict__ T1,
+                                                        const z64 *__restrict__ T2, int64_t ldt,
+                                                        const z64 *__restrict__ z, int64_t n,
+                                                        int64_t m, int64_t cols) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  if (idx >= n * cols) return;
+  const int64_t row = idx / cols, col = idx % cols;
+  const int64_t j = col / m, c = col % m;
+  const z64 zj = z[j], r = R[row * ldr + c], t2 = T2[row * ldt + col];
+  z64 &t1 = T1[row * ldt + col];
+  t1.x = r.x - (zj.x * t2.x - zj.y * t2.y) + t1.x;
+  t1.y = r.y - (zj.x * t2.y + zj.y * t2.x) + t1.y;
+}
+
+__global__ __launch_bounds__(256) void k_c_to_z(const c64 *__restrict__ X, int64_t ldx, int64_t sX,
+                                                int64_t n, int64_t m, z64 *__restrict__ Y,
+                                                int64_t ldy, int64_t sY) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= n * m) return;
+  const int64_t row = idx / m, col = idx % m;
+  const c64 v = X[b * sX + row * ldx + col];
+  Y[b * sY + row * ldy + col] = make_double2(static_cast<double>(v.x), static_cast<double>(v.y));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_rows(const T *__restrict__ X, int64_t ldx,
+                                                      int64_t sX, const int32_t *__restrict__ perm,
+                                                      int64_t n, int64_t m, T *__restrict__ Y,
+                                                      int64_t ldy, int64_t sY) {
+  const int64_t row = blockIdx.x;
+  const int b = blockIdx.y;
+  const int64_t dst = perm[b * n + row];
+  for (int64_t c = threadIdx.x; c < m; c += 256) Y[b * sY + dst * ldy + c] = X[b * sX + row * ldx + c];
+}
+
+__global__ __launch_bounds__(256) void k_weighted_sum(const z64 *__restrict__ Y, int64_t ldy,
+                                                      int64_t sY, const z64 *__restrict__ w,
+                                                      int32_t N, int64_t n, int64_t m,
+                                                      z64 *__restrict__ U, int64_t ldu) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  if (idx >= n * m) return;
+  const int64_t row = idx / m, col = idx % m;
+  double sr = 0.0, si = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const z64 y = Y[j * sY + row * ldy + col];
+    const z64 wj = w[j];
+    sr += wj.x * y.x - wj.y * y.y;
+    si += wj.x * y.y + wj.y * y.x;
+  }
+  U[row * ldu + col] = make_double2(sr, si);
+}
+
+__global__ __launch_bounds__(256) void k_copy_block(const z64 *__restrict__ X, int64_t ldx,
+                                                    int64_t n, int64_t m, z64 *__restrict__ Y,
+                                                    int64_t ldy) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  if (idx >= n * m) return;
+  const int64_t row = idx / m, col = idx % m;
+  Y[row * ldy + col] = X[row * ldx + col];
+}
+
+__global__ __launch_bounds__(256) void k_z_to_c(const z64 *__restrict__ X, int64_t ldx, int64_t sX,
+                                                int64_t n, int64_t m, c64 *__restrict__ Y,
+                                                int64_t ldy, int64_t sY) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= n * m) return;
+  const int64_t row = idx / m, col = idx % m;
+  const z64 v = X[b * sX + row * ldx + col];
+  Y[b * sY + row * ldy + col] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+}
+
+__global__ __launch_bounds__(256) void k_add_c_to_z(const c64 *__restrict__ X, int64_t ldx,
+                                                    int64_t sX, int64_t n, int64_t m,
+                                                    z64 *__restrict__ Y, int64_t ldy, int64_t sY) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  const int b = blockIdx.y;
+  if (idx >= n * m) return;
+  const int64_t row = idx / m, col = idx % m;
+  const c64 v = X[b * sX + row * ldx + col];
+  z64 &y = Y[b * sY + row * ldy + col];
+  y.x += static_cast<double>(v.x);
+  y.y += static_cast<double>(v.y);
+}
+
+// Partial column sums over a chunk of 64 rows: one thread per column.
+__global__ __launch_bounds__(256) void k_ritz_part(const z64 *__restrict__ AX,
+                                                   const z64 *__restrict__ BX, int64_t ld,
+                                                   int64_t n, int64_t t,
+                                                   const z64 *__restrict__ lam,
+                                                   double *__restrict__ part) {
+  const int64_t chunk = blockIdx.x;
+  const int64_t r0 = chunk * 64;
+  const int64_t r1 = (r0 + 64 < n) ? r0 + 64 : n;
+  for (int64_t c = threadIdx.x; c < t; c += 256) {
+    const z64 l = lam[c];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const z64 ax = AX[r * ld + c], bx = BX[r * ld + c];
+      const double dr = ax.x - (l.x * bx.x - l.y * bx.y);
+      const double di = ax.y - (l.x * bx.y + l.y * bx.x);
+      s0 += dr * dr + di * di;
+      s1 += ax.x * ax.x + ax.y * ax.y;
+      s2 += bx.x * bx.x + bx.y * bx.y;
+    }
+    part[(chunk * t + c) * 3 + 0] = s0;
+    part[(chunk * t + c) * 3 + 1] = s1;
+    part[(chunk * t + c) * 3 + 2] = s2;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const double *__restrict__ part, int64_t chunks,
+                                                   int64_t width, double *__restrict__ out) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= width) return;
+  double s = 0.0;
+  for (int64_t k = 0; k < chunks; ++k) s += part[k * width + i];
+  out[i] = s;
+}
+
+// out[b] = sum_k part[b * len + k], one thread per b (fixed order).
+__global__ __launch_bounds__(256) void k_sum_rows(const double *__restrict__ part, int64_t len,
+                                                  int64_t count, double *__restrict__ out) {
+  const int64_t b = blockIdx.x * 256ll + threadIdx.x;
+  if (b >= count) return;
+  double acc = 0.0;
+  for (int64_t k = 0; k < len; ++k) acc += part[b * len + k];
+  out[b] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_col_part(const z64 *__restrict__ X, int64_t ld, int64_t n,
+                                                  int64_t t, double *__restrict__ part) {
+  const int64_t chunk = blockIdx.x;
+  const int64_t r0 = chunk * 64;
+  const int64_t r1 = (r0 + 64 < n) ? r0 + 64 : n;
+  for (int64_t c = threadIdx.x; c < t; c += 256) {
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const z64 x = X[r * ld + c];
+      s += x.x * x.x + x.y * x.y;
+    }
+    part[chunk * t + c] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fro_part(const z64 *__restrict__ X, int64_t ld, int64_t sX,
+                                                  int64_t n, int64_t m, double *__restrict__ part) {
+  // part[b * gridDim.x + blockIdx.x]
+  __shared__ double red[256];
+  const int b = blockIdx.y;
+  double s = 0.0;
+  const int64_t total = n * m;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += 256ll * gridDim.x) {
+    const int64_t row = i / m, col = i % m;
+    const z64 x = X[b * sX + row * ld + col];
+    s += x.x * x.x + x.y * x.y;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Right-looking Cholesky of a t x t Hermitian matrix in global memory by one
+// workgroup; only the upper triangle is read and R overwrites it.
+__global__ __launch_bounds__(1024) void k_cholesky(z64 *__restrict__ G, int64_t t, double shift,
+                                                   int32_t *__restrict__ flag) {
+  __shared__ double s_d;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_bad = 0;
+    double tr = 0.0;
+    for (int64_t i = 0; i < t; ++i) tr += G[i * t + i].x;
+    s_d = shift * tr;
+  }
+  __syncthreads();
+  const double sh = s_d;
+  for (int64_t i = tid; i < t; i += 1024) G[i * t + i].x += sh;
+  __syncthreads();
+  for (int64_t k = 0; k < t; ++k) {
+    if (tid == 0) {
+      const double d = G[k * t + k].x;
+      if (!(d > 0.0)) {
+        if (s_bad == 0) s_bad = static_cast<int>(k) + 1;
+        s_d = 0.0;
+      } else {
+        s_d = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double dk = s_d;
+    if (dk == 0.0) break;
+    // row k of R
+    for (int64_t j = k + tid; j < t; j += 1024) {
+      z64 v = G[k * t + j];
+      if (j == k) {
+        v = make_double2(dk, 0.0);
+      } else {
+        v.x /= dk;
+        v.y /= dk;
+      }
+      G[k * t + j] = v;
+    }
+    __syncthreads();
+    // trailing update of the upper triangle: G_ij -= conj(R_ki) R_kj, k < i <= j
+    const int64_t m = t - k - 1;
+    for (int64_t e = tid; e < m * m; e += 1024) {
+      const int64_t i = e / m, j = e % m;
+      if (j < i) continue;
+      const int64_t ii = k + 1 + i, jj = k + 1 + j;
+      const z64 rki = G[k * t + ii], rkj = G[k * t + jj];
+      z64 &g = G[ii * t + jj];
+      g.x -= rki.x * rkj.x + rki.y * rkj.y;
+      g.y -= rki.x * rkj.y - rki.y * rkj.x;
+    }
+    __syncthreads();
+  }
+  // zero the strict lower triangle
+  for (int64_t e = tid; e < t * t; e += 1024) {
+    const int64_t i = e / t, j = e % t;
+    if (j < i) G[e] = make_double2(0.0, 0.0);
+  }
+  if (tid == 0) flag[0] = s_bad;
+}
+
+// In-place inverse of a t x t upper-triangular matrix by one workgroup: one
+// thread per column j solves R x = e_j upwards; columns are independent, so the
+// result is written to a scratch half (the strict lower part is used as no
+// storage here: X is accumulated in place column by column from the bottom).
+__global__ __launch_bounds__(1024) void k_trinv_upper(z64 *__restrict__ R, int64_t t,
+                                                      z64 *__restrict__ X) {
+  for (int64_t j = threadIdx.x; j < t; j += 1024) {
+    const z64 djj = R[j * t + j];
+    const double d = djj.x * djj.x + djj.y * djj.y;
+    X[j * t + j] = make_double2(djj.x / d, -djj.y / d);
+    for (int64_t i = j - 1; i >= 0; --i) {
+      double sr = 0.0, si = 0.0;
+      for (int64_t k = i + 1; k <= j; ++k) {
+        const z64 a = R[i * t + k], x = X[k * t + j];
+        sr += a.x * x.x - a.y * x.y;
+        si += a.x * x.y + a.y * x.x;
+      }
+      const z64 dii = R[i * t + i];
+      const double q = dii.x * dii.x + dii.y * dii.y;
+      // x_ij = -s / d_ii
+      X[i * t + j] = make_double2(-(sr * dii.x + si * dii.y) / q, -(si * dii.x - sr * dii.y) / q);
+    }
+    for (int64_t i = j + 1; i < t; ++i) X[i * t + j] = make_double2(0.0, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_copy_t(const z64 *__restrict__ X, z64 *__restrict__ R,
+                                                int64_t count) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < count) R[i] = X[i];
+}
+
+// Column gather + normalisation: block per selected column.
+__global__ __launch_bounds__(256) void k_gather_norm(const z64 *__restrict__ X, int64_t ldx,
+                                                     int64_t n, const int32_t *__restrict__ idx,
+                                                     z64 *__restrict__ Y, int64_t ldy) {
+  __shared__ double s_n[256];
+  __shared__ double s_m[256];
+  __shared__ int64_t s_i[256];
+  const int64_t k = blockIdx.x;
+  const int64_t c = idx[k];
+  double nr = 0.0, mx = -1.0;
+  int64_t mi = 0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) {
+    const z64 v = X[r * ldx + c];
+    const double a2 = v.x * v.x + v.y * v.y;
+    nr += a2;
+    if (a2 > mx) {
+      mx = a2;
+      mi = r;
+    }
+  }
+  s_n[threadIdx.x] = nr;
+  s_m[threadIdx.x] = mx;
+  s_i[threadIdx.x] = mi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      s_n[threadIdx.x] += s_n[threadIdx.x + o];
+      const double om = s_m[threadIdx.x + o];
+      const int64_t oi = s_i[threadIdx.x + o];
+      if (om > s_m[threadIdx.x] || (om == s_m[threadIdx.x] && oi < s_i[threadIdx.x])) {
+        s_m[threadIdx.x] = om;
+        s_i[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const double nrm = sqrt(s_n[0]);
+  const z64 piv = X[s_i[0] * ldx + c];
+  const double pa = sqrt(piv.x * piv.x + piv.y * piv.y);
+  // scale = conj(piv)/(|piv| * nrm)
+  z64 sc = make_double2(1.0 / nrm, 0.0);
+  if (pa > 0.0) sc = make_double2(piv.x / (pa * nrm), -piv.y / (pa * nrm));
+  for (int64_t r = threadIdx.x; r < n; r += 256) {
+    const z64 v = X[r * ldx + c];
+    Y[r * ldy + k] = make_double2(v.x * sc.x - v.y * sc.y, v.x * sc.y + v.y * sc.x);
+  }
+}
+
+}  // namespace
+
+void shift_assemble_z(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
+                      const z64 *z, int32_t N, int64_t n, z64 *M, int64_t ldm, int64_t sM) {
+  hipLaunchKernelGGL((k_shift<z64>), dim3(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n)),
+                     dim3(256), 0, s, A, lda, B, ldb, z, N, n, M, ldm, sM);
+}
+void shift_assemble_c(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
+                      const z64 *z, int32_t N, int64_t n, c64 *M, int64_t ldm, int64_t sM) {
+  hipLaunchKernelGGL((k_shift<c64>), dim3(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(n)),
+                     dim3(256), 0, s, A, lda, B, ldb, z, N, n, M, ldm, sM);
+}
+
+template <typename T>
+void gather_rows(hipStream_t s, const T *R, int64_t ldr, int64_t sR, const int32_t *perm,
+                 int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY) {
+  hipLaunchKernelGGL((k_gather_rows<T>), dim3(static_cast<unsigned>(n), batch), dim3(256), 0, s, R,
+                     ldr, sR, perm, n, m, Y, ldy, sY);
+}
+template void gather_rows<z64>(hipStream_t, const z64 *, int64_t, int64_t, const int32_t *,
+                               int64_t, int64_t, int32_t, z64 *, int64_t, int64_t);
+template void gather_rows<c64>(hipStream_t, const c64 *, int64_t, int64_t, const int32_t *,
+                               int64_t, int64_t, int32_t, c64 *, int64_t, int64_t);
+
+void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64 *T2, int64_t ldt,
+                    const z64 *z, int32_t N, int64_t n, int64_t m) {
+  const int64_t cols = static_cast<int64_t>(N) * m;
+  const int64_t tot = n * cols;
+  hipLaunchKernelGGL(k_shift_residual, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0,
+                     s, R, ldr, T1, T2, ldt, z, n, m, cols);
+}
+
+void c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
+            int32_t batch, z64 *Y, int64_t ldy, int64_t sY) {
+  const int64_t tot = n * m;
+  hipLaunchKernelGGL(k_c_to_z, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256), 0,
+                     s, X, ldx, sX, n, m, Y, ldy, sY);
+}
+
+template <typename T>
+void scatter_rows(hipStream_t s, const T *X, int64_t ldx, int64_t sX, const int32_t *perm,
+                  int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY) {
+  hipLaunchKernelGGL((k_scatter_rows<T>), dim3(static_cast<unsigned>(n), batch), dim3(256), 0, s, X,
+                     ldx, sX, perm, n, m, Y, ldy, sY);
+}
+template void scatter_rows<z64>(hipStream_t, const z64 *, int64_t, int64_t, const int32_t *,
+                                int64_t, int64_t, int32_t, z64 *, int64_t, int64_t);
+
+void weighted_sum(hipStream_t s, const z64 *Y, int64_t ldy, int64_t sY, const z64 *w, int32_t N,
+                  int64_t n, int64_t m, z64 *U, int64_t ldu) {
+  const int64_t tot = n * m;
+  hipLaunchKernelGGL(k_weighted_sum, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s,
+                     Y, ldy, sY, w, N, n, m, U, ldu);
+}
+
+void copy_block_z(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t m, z64 *Y,
+                  int64_t ldy) {
+  const int64_t tot = n * m;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_copy_block, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s,
+                     X, ldx, n, m, Y, ldy);
+}
+
+void z_to_c(hipStream_t s, const z64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
+            int32_t batch, c64 *Y, int64_t ldy, int64_t sY) {
+  const int64_t tot = n * m;
+  hipLaunchKernelGGL(k_z_to_c, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256), 0,
+                     s, X, ldx, sX, n, m, Y, ldy, sY);
+}
+
+void add_c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
+                int32_t batch, z64 *Y, int64_t ldy, int64_t sY) {
+  const int64_t tot = n * m;
+  hipLaunchKernelGGL(k_add_c_to_z, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256),
+                     0, s, X, ldx, sX, n, m, Y, ldy, sY);
+}
+
+void ritz_norms(hipStream_t s, const z64 *AX, const z64 *BX, int64_t ld, int64_t n, int64_t t,
+                const z64 *lam, double *part, double *out) {
+  const int64_t chunks = (n + 63) / 64;
+  hipLaunchKernelGGL(k_ritz_part, dim3(static_cast<unsigned>(chunks)), dim3(256), 0, s, AX, BX, ld,
+                     n, t, lam, part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(static_cast<unsigned>((3 * t + 255) / 256)), dim3(256), 0, s,
+                     part, chunks, 3 * t, out);
+}
+
+void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, double *part,
+                double *out) {
+  const int64_t chunks = (n + 63) / 64;
+  hipLaunchKernelGGL(k_col_part, dim3(static_cast<unsigned>(chunks)), dim3(256), 0, s, X, ld, n, t,
+                     part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(static_cast<unsigned>((t + 255) / 256)), dim3(256), 0, s,
+                     part, chunks, t, out);
+}
+
+void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
+                  int32_t batch, double *part, double *out) {
+  const int blocks = 64;
+  hipLaunchKernelGGL(k_fro_part, dim3(blocks, batch), dim3(256), 0, s, X, ld, sX, n, m, part);
+  hipLaunchKernelGGL(k_sum_rows, dim3(static_cast<unsigned>((batch + 255) / 256)), dim3(256), 0, s,
+                     part, static_cast<int64_t>(blocks), static_cast<int64_t>(batch), out);
+}
+
+void cholesky_upper(hipStream_t s, z64 *G, int64_t t, double shift, int32_t *flag) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, G, t, shift, flag);
+}
+
+void trinv_upper(hipStream_t s, z64 *R, int64_t t) {
+  // needs t*t scratch: use the second half of a 2*t*t buffer provided by the caller
+  hipLaunchKernelGGL(k_trinv_upper, dim3(1), dim3(1024), 0, s, R, t, R + t * t);
+  hipLaunchKernelGGL(k_copy_t, dim3(static_cast<unsigned>((t * t + 255) / 256)), dim3(256), 0, s,
+                     R + t * t, R, t * t);
+}
+
+void gather_normalize_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, const int32_t *idx,
+                           int64_t k, z64 *Y, int64_t ldy, double *part) {
+  (void)part;
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_gather_norm, dim3(static_cast<unsigned>(k)), dim3(256), 0, s, X, ldx, n, idx,
+                     Y, ldy);
+}
+
+}  // namespace feast

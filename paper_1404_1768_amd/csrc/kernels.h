@@ -1,0 +1,142 @@
+// Host-side launchers of the device kernels (all asynchronous on `s`).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "common.h"
+
+namespace feast {
+
+template <typename T> struct GemmArgs {
+  int64_t M, N, K;
+  const T *A;
+  int64_t lda, sA;
+  const T *B;
+  int64_t ldb, sB;
+  T *C;
+  int64_t ldc, sC;
+  z64 alpha, beta;
+  int32_t batch;
+  int32_t splits;
+  int64_t kchunk;
+  T *work;
+};
+
+enum { GEMM_SQUARE = 0, GEMM_TALL = 1 };
+
+// C_b = alpha op(A_b) B_b + beta C_b; transA 0: A is M x K; 2: A stored K x M, op = ^*.
+// `work` (optional, work_elems entries) enables split-K for small outputs.
+// GEMM_TALL uses 128-row tiles (needed for in-place products with M <= 128).
+void zgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
+           int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,
+           int64_t ldc, int64_t sC, int32_t batch, z64 *work = nullptr, int64_t work_elems = 0,
+           int cfg = GEMM_SQUARE);
+void cgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha, const c64 *A,
+           int64_t lda, int64_t sA, const c64 *B, int64_t ldb, int64_t sB, z64 beta, c64 *C,
+           int64_t ldc, int64_t sC, int32_t batch, c64 *work = nullptr, int64_t work_elems = 0,
+           int cfg = GEMM_SQUARE);
+
+// ---- LU building blocks (k_lu.hip); T = z64 or c64 --------------------------
+
+// Factor columns [c0, c0+w) (rows [c0, n)) of each matrix with partial pivoting,
+// swapping rows over the panel columns [pk0, pk0+pkb) as well.  Returns false
+// if w is larger than the register-resident leaf supports for n - c0 rows.
+template <typename T>
+bool leaf_lu(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+             int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info);
+// Largest leaf width for `rows` remaining rows.
+template <typename T> int leaf_max_width(int64_t rows);
+
+// Rows [r0, r0+kb) swapped with ipiv[r0..r0+kb) over columns [0, clo) and [chi, n).
+template <typename T>
+void laswp_outside(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+                   int64_t r0, int kb, int64_t clo, int64_t chi, const int32_t *ipiv);
+
+// X <- L11^{-1} X for the unit-lower L11 = M[c0:c0+w1, c0:c0+w1] and
+// X = M[c0:c0+w1, c0+w1:c0+w1+w2] (w1, w2 <= 64).
+template <typename T>
+void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t c0,
+                int w1, int w2);
+
+// Inverses of the diagonal blocks of the unit-lower L (lower=true) or of the
+// upper U (lower=false) factor: block I covers rows/cols [I*nb, min(n,(I+1)*nb)).
+// out[b][I] is an nb x nb row-major block (ld nb).  Blocks [blk0, blk1).
+template <typename T>
+void diag_block_inverse(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,
+                        int64_t n, int nb, int64_t blk0, int64_t blk1, bool lower, T *out,
+                        int64_t out_stride);
+
+// perm[b][i] = original row at position i of P_b (from LAPACK-order ipiv).
+void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n, int32_t batch);
+
+// info[b] = min(info[b]) helper is inside leaf_lu; zero the array:
+void fill_i32(hipStream_t s, int32_t *p, int64_t count, int32_t v);
+
+// ---- element-wise and reduction kernels (k_misc.hip) ------------------------
+
+// M_j = z_j B - A for every node j (out: N matrices n x n, ld ldm, stride sM).
+void shift_assemble_z(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
+                      const z64 *z, int32_t N, int64_t n, z64 *M, int64_t ldm, int64_t sM);
+void shift_assemble_c(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
+                      const z64 *z, int32_t N, int64_t n, c64 *M, int64_t ldm, int64_t sM);
+
+// Y_b[i, :] = R_b[perm_b[i], :] with R_b = R + b sR (sR = 0: one shared R).
+template <typename T>
+void gather_rows(hipStream_t s, const T *R, int64_t ldr, int64_t sR, const int32_t *perm,
+                 int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY);
+// Y[perm_b[i], :] = X_b[i, :]  (scatter, used by the ^* solve).
+template <typename T>
+void scatter_rows(hipStream_t s, const T *X, int64_t ldx, int64_t sX, const int32_t *perm,
+                  int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY);
+
+// U = sum_j w_j Y_j (fixed summation order; w on the device).
+void weighted_sum(hipStream_t s, const z64 *Y, int64_t ldy, int64_t sY, const z64 *w,
+                  int32_t N, int64_t n, int64_t m, z64 *U, int64_t ldu);
+
+// Copy / convert blocks.
+void copy_block_z(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t m, z64 *Y,
+                  int64_t ldy);
+void z_to_c(hipStream_t s, const z64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
+            int32_t batch, c64 *Y, int64_t ldy, int64_t sY);
+// Y = X (complex64 -> complex128), per batch.
+void c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
+            int32_t batch, z64 *Y, int64_t ldy, int64_t sY);
+// Refinement residual of all nodes in the n x (N m) layout:
+// T1[:, j m + c] <- R[:, c] - z_j T2[:, j m + c] + T1[:, j m + c]   (T1 = A Y, T2 = B Y).
+void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64 *T2,
+                    int64_t ldt, const z64 *z, int32_t N, int64_t n, int64_t m);
+// Y += X (complex64 correction into FP64 solution), per batch.
+void add_c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
+                int32_t batch, z64 *Y, int64_t ldy, int64_t sY);
+
+// Residual norms of Ritz pairs: for every column i of the n x t blocks AX, BX:
+// out[3i+0] = ||AX_i - lam_i BX_i||^2, out[3i+1] = ||AX_i||^2, out[3i+2] = ||BX_i||^2.
+// part: workspace of ceil(n/64) * 3t doubles.
+void ritz_norms(hipStream_t s, const z64 *AX, const z64 *BX, int64_t ld, int64_t n, int64_t t,
+                const z64 *lam, double *part, double *out);
+
+// Per-column squared norms of an n x t block into out[t]; part: ceil(n/64)*t doubles.
+void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, double *part,
+                double *out);
+
+// Frobenius-norm-squared per batch: out[b] = sum |X_b|^2 (n x m blocks);
+// part: workspace of 64 * batch doubles.
+void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
+                  int32_t batch, double *part, double *out);
+
+// Cholesky of the t x t Hermitian G (row-major, upper triangle used) after
+// adding shift_rel * trace(G) to the diagonal: G = R^* R, R upper triangular
+// stored in G (strict lower part zeroed).  flag[0] = 0 ok, or 1 + the failing column.
+void cholesky_upper(hipStream_t s, z64 *G, int64_t t, double shift_rel, int32_t *flag);
+// Inverse of the t x t upper-triangular R in place; R must hold 2 t^2 entries
+// (the second half is scratch).
+void trinv_upper(hipStream_t s, z64 *R, int64_t t);
+
+// Gather columns idx[0..k) of the n x t block X into Y (n x k) and normalise each
+// to unit 2-norm with its largest-modulus entry real positive.
+void gather_normalize_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n,
+                           const int32_t *idx, int64_t k, z64 *Y, int64_t ldy, double *part);
+
+}  // namespace feast

@@ -1,0 +1,157 @@
+"""C-ABI tests that need no GPU: exported symbols, argument validation, and
+the host-side pieces of Algorithm 5 (quadrature nodes, stopping rules and the
+reduced-pencil QZ) against the oracle and brute force."""
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.optimize import linear_sum_assignment
+
+import paper_1404_1768_amd as fm
+from paper_1404_1768_amd import binding as bd
+from oracle import gfeast as o
+from conftest import ROOT, load_example31
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "feast.h")).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char \*)\s*(feast_[a-z0-9_]+)\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _header_functions()
+    assert len(names) >= 14
+    lib = fm.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", fm.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (feast_\w+)", out))
+    for nm in names:
+        assert nm in exported, nm
+        assert hasattr(lib, nm)
+    assert set(bd.EXPORTED) == set(names)
+
+
+def test_version():
+    assert fm.load().feast_version() >= 10000
+
+
+@pytest.mark.parametrize("rule", [fm.TRAPEZOID, fm.GAUSS_LEGENDRE])
+@pytest.mark.parametrize("N", [1, 2, 7, 16, 32, 64])
+def test_nodes_match_oracle(rule, N):
+    z, w = fm.feast_nodes(0.3 - 1.2j, 2.5, N, rule)
+    zo, wo = o.contour_nodes(0.3 - 1.2j, 2.5, N, rule)
+    assert np.max(np.abs(z - zo)) < 1e-13
+    assert np.max(np.abs(w - wo)) < 1e-13
+
+
+@pytest.mark.parametrize("bad", [dict(radius=0.0), dict(radius=-1.0), dict(nodes=0),
+                                 dict(nodes=2000), dict(rule=5), dict(radius=float("nan"))])
+def test_invalid_contour_rejected(bad):
+    kw = dict(center=0.0, radius=1.0, nodes=16, rule=fm.TRAPEZOID)
+    kw.update(bad)
+    with pytest.raises(fm.FeastError) as e:
+        fm.feast_nodes(**kw)
+    assert e.value.code == fm.FEAST_EINVAL
+
+
+@pytest.mark.parametrize("args", [
+    dict(n=0, m=1), dict(n=10, m=0), dict(n=10, m=11), dict(n=20000, m=4),
+    dict(n=10, m=4, eta=0.0), dict(n=10, m=4, max_iter=0), dict(n=10, m=4, max_iter=65),
+    dict(n=10, m=4, prec=7), dict(n=10, m=4, nb=48), dict(n=10, m=4, radius=0.0),
+])
+def test_plan_create_validates_before_device_work(args):
+    kw = dict(center=0.0, radius=1.0, nodes=16)
+    kw.update(args)
+    n, m = kw.pop("n"), kw.pop("m")
+    with pytest.raises(fm.FeastError) as e:
+        fm.Plan(n, m, **kw)
+    assert e.value.code == fm.FEAST_EINVAL
+
+
+def test_null_plan_and_pointer_checks():
+    lib = fm.load()
+    assert lib.feast_filter(None, None, 1, None, 1, None, 1, None, 1) == fm.FEAST_EINVAL
+    assert lib.feast_solve(None, None, 1, None, 1, None, 1, None, None, 1, None, None, None, None,
+                           None) == fm.FEAST_EINVAL
+    assert lib.feast_plan_destroy(None) == fm.FEAST_OK
+    assert lib.feast_zgetrf_batched(0, 1, None, 1, 1, None, None, 0, None) == fm.FEAST_EINVAL
+    assert lib.feast_zgemm_batched(1, 4, 4, 4, bd.FeastZ(1, 0), None, 4, 0, None, 4, 0,
+                                   bd.FeastZ(0, 0), None, 4, 0, 1, None) == fm.FEAST_EINVAL
+    # empty product is a no-op
+    assert lib.feast_zgemm_batched(0, 0, 4, 4, bd.FeastZ(1, 0), None, 4, 0, None, 4, 0,
+                                   bd.FeastZ(0, 0), None, 4, 0, 1, None) == fm.FEAST_OK
+
+
+def test_stop_rule_matches_oracle_on_random_sequences():
+    rng = np.random.default_rng(0)
+    for _ in range(2000):
+        k = int(rng.integers(1, 8))
+        mx = int(rng.integers(1, 8))
+        c_k, c_p = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        e_k = math.inf if c_k == 0 else float(10.0 ** rng.uniform(-14, -2))
+        e_p = float(rng.choice([0.0, math.inf, 10.0 ** rng.uniform(-14, -2), e_k]))
+        eps = float(10.0 ** rng.uniform(-12, -8))
+        assert fm.feast_stop_rule(k, c_k, e_k, c_p, e_p, eps, mx) == \
+            o.stop_rule(k, c_k, e_k, c_p, e_p, eps, mx)
+
+
+def _match(lam, ref):
+    C = np.abs(lam[:, None] - ref[None, :])
+    ri, ci = linear_sum_assignment(C)
+    return C[ri, ci].max()
+
+
+@pytest.mark.parametrize("t", [1, 2, 3, 9, 40, 120])
+def test_reduced_eig_against_brute_force(t):
+    rng = np.random.default_rng(t)
+    A = rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))
+    B = rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))
+    al, be, Y = fm.feast_reduced_eig(A, B)
+    ref = sla.eigvals(A, B)
+    lam = al / be
+    assert _match(lam, ref) < 1e-10 * max(1.0, np.abs(ref).max())
+    for i in range(t):
+        assert abs(np.linalg.norm(Y[:, i]) - 1) < 1e-12
+        r = np.linalg.norm(be[i] * A @ Y[:, i] - al[i] * B @ Y[:, i])
+        assert r <= 1e-13 * (abs(be[i]) * np.linalg.norm(A) + abs(al[i]) * np.linalg.norm(B))
+
+
+def test_reduced_eig_infinite_eigenvalues():
+    # a rank-deficient Bt gives beta = 0 for as many eigenvalues as its rank defect
+    rng = np.random.default_rng(2)
+    t = 14
+    A = rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))
+    B = rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))
+    U, s, Vh = np.linalg.svd(B)
+    s[-3:] = 0
+    B = (U * s) @ Vh
+    al, be, Y = fm.feast_reduced_eig(A, B)
+    inf = np.abs(be) < 1e-12 * np.abs(al)
+    assert np.count_nonzero(inf) == 3
+    ref = sla.eigvals(A, B)
+    assert _match(al[~inf] / be[~inf], ref[np.isfinite(ref)]) < 1e-9
+
+
+def test_reduced_eig_example31_projection():
+    # Section 3: the oblique reduced pencil of Example 3.1 has eigenvalues 0.2, 0.5
+    A, B, eig = load_example31()
+    z, w = o.contour_nodes(0.0, 1.0, 32)
+    V = np.array([[0.3, -1.1], [0.7, 0.2], [-0.4, 0.9], [1.3, 0.5]], dtype=np.complex128)
+    U1, _ = o.orth(o.apply_filter(o.ShiftedSolver(A, B, z), w, V))
+    U2, _ = o.orth(B @ U1)
+    At, Bt = o.project(A, B, U1, U2)
+    al, be, Y = fm.feast_reduced_eig(At, Bt)
+    assert np.allclose(np.sort((al / be).real), [0.2, 0.5], atol=1e-9)
+
+
+def test_reduced_eig_triangular_and_diagonal_inputs():
+    t = 6
+    D = np.diag(np.arange(1, t + 1) * (1 + 0.5j))
+    al, be, Y = fm.feast_reduced_eig(D, np.eye(t))
+    assert np.allclose(np.sort_complex(al / be), np.sort_complex(np.diag(D)))
+    T = np.triu(np.ones((t, t))) + np.diag(np.arange(t))
+    al, be, Y = fm.feast_reduced_eig(T + 0j, np.eye(t) + 0j)
+    assert np.allclose(np.sort((al / be).real), np.sort(np.diag(T)))

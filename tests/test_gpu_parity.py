@@ -1,0 +1,239 @@
+"""GPU parity tests: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: the spec acceptance is eigenvalues within 1e-10 relative of
+the oracle and relative residuals (eq. 5-1) at most 1e-10.  Element-wise
+comparisons of filtered blocks use 1e-11 relative to the block's largest
+entry: both sides solve systems whose condition numbers are below 1e3 here, so
+rounding differences stay near 1e-13.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment
+
+pytestmark = pytest.mark.gpu
+
+import torch  # noqa: E402
+
+import paper_1404_1768_amd as fm  # noqa: E402
+import pencilgen as pg  # noqa: E402
+from oracle import gfeast as o  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def to_dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in arrs]
+
+
+def match(lam, ref):
+    C = np.abs(lam[:, None] - ref[None, :])
+    ri, ci = linear_sum_assignment(C)
+    return ri, ci, C[ri, ci]
+
+
+def host_residuals(A, B, lam, X):
+    AX, BX = A @ X, B @ X
+    return np.array([np.linalg.norm(AX[:, i] - lam[i] * BX[:, i]) /
+                     (np.linalg.norm(AX[:, i]) + np.linalg.norm(BX[:, i])) for i in range(len(lam))])
+
+
+def closed_form_filter(p, N, V):
+    mu = (p.d - p.center) / p.radius
+    f = 1.0 / (1.0 + mu ** N)
+    return np.linalg.solve(p.Q, f[:, None] * (p.Q @ V))
+
+
+# ---------------------------------------------------------------------------
+# feast_filter
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["cfg1", "ragged_gl", "small_n", "m1"])
+def test_filter_matches_oracle(case):
+    if case == "cfg1":
+        p = pg.workload(1)
+        rule = o.TRAPEZOID
+    elif case == "ragged_gl":
+        p = pg.make_pencil(333, m=37, inside=12, inside_radius=0.8, outside_r=(1.3, 6.0),
+                           center=0.5 - 0.25j, radius=1.5, nodes=8, c=0.1, seed=3)
+        rule = o.GAUSS_LEGENDRE
+    elif case == "small_n":
+        p = pg.make_pencil(10, m=4, inside=2, inside_radius=0.5, outside_r=(1.5, 3.0), nodes=5,
+                           c=0.1, seed=4)
+        rule = o.TRAPEZOID
+    else:
+        p = pg.make_pencil(97, m=1, inside=1, inside_radius=0.5, outside_r=(1.5, 3.0), nodes=16,
+                           c=0.1, seed=5)
+        rule = o.TRAPEZOID
+    z, w = o.contour_nodes(p.center, p.radius, p.nodes, rule)
+    ref = o.apply_filter(o.ShiftedSolver(p.A, p.B, z), w, p.V)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, rule=rule) as plan:
+        U = plan.filter(A, B, V).cpu().numpy()
+        # second call reuses the cached factors and must give the same block
+        U2 = plan.filter(A, B, V).cpu().numpy()
+    assert np.max(np.abs(U - ref)) <= 1e-11 * np.abs(ref).max()
+    assert np.array_equal(U, U2)
+    if rule == o.TRAPEZOID:
+        cf = closed_form_filter(p, p.nodes, p.V)
+        assert np.max(np.abs(U - cf)) <= 1e-10 * np.abs(cf).max()
+
+
+def test_filter_mixed_refined_matches_oracle():
+    p = pg.workload(2, n_override=600)
+    z, w = o.contour_nodes(p.center, p.radius, p.nodes)
+    ref = o.apply_filter(o.ShiftedSolver(p.A, p.B, z), w, p.V)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=fm.MIXED) as plan:
+        U = plan.filter(A, B, V).cpu().numpy()
+    assert np.max(np.abs(U - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+def test_filter_singular_node_reported():
+    # an eigenvalue placed exactly on a quadrature node makes z_j B - A singular
+    n = 12
+    z, _ = o.contour_nodes(0.0, 1.0, 8)
+    d = np.concatenate([[z[3]], np.linspace(2.0, 3.0, n - 1)]).astype(np.complex128)
+    A = np.diag(d)
+    B = np.eye(n, dtype=np.complex128)
+    V = pg.start_block(n, 2, seed=1)
+    tA, tB, tV = to_dev(A, B, V)
+    with fm.Plan(n, 2, 0.0, 1.0, 8) as plan:
+        with pytest.raises(fm.FeastError) as e:
+            plan.filter(tA, tB, tV)
+        assert e.value.code == fm.FEAST_SINGULAR
+        assert "node 3" in plan.last_error()
+
+
+# ---------------------------------------------------------------------------
+# feast_project
+# ---------------------------------------------------------------------------
+
+def test_project_matches_oracle():
+    p = pg.workload(1, n_override=300)
+    rng = np.random.default_rng(7)
+    Uin = p.V + 0.1 * (rng.normal(size=p.V.shape) + 1j * rng.normal(size=p.V.shape))
+    A, B, U = to_dev(p.A, p.B, Uin)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes) as plan:
+        U1, AU1, BU1, At, Bt = plan.project(A, B, U)
+    U1, AU1, BU1 = U1.cpu().numpy(), AU1.cpu().numpy(), BU1.cpu().numpy()
+    U1o, _ = o.orth(Uin)
+    U2o, R2o = o.orth(p.B @ U1o)
+    Ato, Bto = o.project(p.A, p.B, U1o, U2o)
+    assert np.linalg.norm(U1.conj().T @ U1 - np.eye(p.m)) < 1e-13
+    assert np.max(np.abs(U1 - U1o)) < 1e-12
+    assert np.max(np.abs(AU1 - p.A @ U1o)) < 1e-11 * np.abs(p.A @ U1o).max()
+    assert np.max(np.abs(BU1 - p.B @ U1o)) < 1e-11 * np.abs(p.B @ U1o).max()
+    assert np.max(np.abs(At - Ato)) < 1e-11 * np.abs(Ato).max()
+    assert np.max(np.abs(Bt - Bto)) < 1e-11 * np.abs(Bto).max()
+    # B~ = R_2 (upper triangular with real positive diagonal)
+    assert np.max(np.abs(np.tril(Bt, -1))) < 1e-12 * np.abs(Bt).max()
+
+
+def test_project_tolerates_ill_conditioned_block():
+    # a filtered block with t > s has singular values down to |f| of the
+    # (t+1)-th eigenvalue; shifted Cholesky QR3 must still orthonormalise it
+    p = pg.workload(1, n_override=400)
+    z, w = o.contour_nodes(p.center, p.radius, p.nodes)
+    Uf = o.apply_filter(o.ShiftedSolver(p.A, p.B, z), w, p.V)
+    sv = np.linalg.svd(Uf, compute_uv=False)
+    assert sv[0] / sv[-1] > 1e3
+    A, B, U = to_dev(p.A, p.B, Uf)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes) as plan:
+        U1, AU1, BU1, At, Bt = plan.project(A, B, U)
+    U1 = U1.cpu().numpy()
+    assert np.linalg.norm(U1.conj().T @ U1 - np.eye(p.m)) < 1e-12
+    # same span as the oracle's Householder basis
+    U1o, _ = o.orth(Uf)
+    sv = np.linalg.svd(U1o.conj().T @ U1, compute_uv=False)
+    assert sv.min() > 1 - 1e-10
+
+
+# ---------------------------------------------------------------------------
+# feast_solve (Algorithm 5)
+# ---------------------------------------------------------------------------
+
+def _compare_solve(p, r, ref, lam_tol=1e-10, res_tol=1e-10, vec_tol=1e-10):
+    assert len(r.lam) == len(ref.lam)
+    ri, ci, d = match(r.lam, ref.lam)
+    scale = np.maximum(np.abs(ref.lam[ci]), 1e-3 * p.radius)
+    assert np.max(d / scale) <= lam_tol, np.max(d / scale)
+    X = r.X.cpu().numpy()
+    hr = host_residuals(p.A, p.B, r.lam, X)
+    assert np.max(hr) <= res_tol, np.max(hr)
+    # the library's residuals use (A U_1) y; the host recomputes A (U_1 y): equal up to rounding
+    assert np.allclose(hr, r.res, rtol=1e-2, atol=1e-13)
+    for i, j in zip(ri, ci):
+        assert abs(np.vdot(ref.X[:, j], X[:, i])) >= 1 - vec_tol
+        assert abs(np.linalg.norm(X[:, i]) - 1) < 1e-12
+
+
+def test_solve_config1_two_filters_matches_oracle():
+    p = pg.workload(1)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, max_iter=2) as plan:
+        r = plan.solve(A, B, V)
+    ref = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, max_iter=2)
+    assert (r.flag, r.iters, r.filters) == (ref.flag, ref.iters, ref.filters) == (-1, 2, 2)
+    assert r.count == [h["c"] for h in ref.history]
+    assert np.allclose(r.errs, [h["e"] for h in ref.history], rtol=1e-3)
+    _compare_solve(p, r, ref, res_tol=1e-6, vec_tol=1e-10)
+
+
+@pytest.mark.parametrize("prec", [fm.FP64, fm.MIXED])
+def test_solve_config1_converged(prec):
+    p = pg.workload(1)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=prec) as plan:
+        r = plan.solve(A, B, V)
+    ref = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes)
+    assert r.flag == 1 and ref.flag == 1
+    assert len(r.lam) == p.s
+    _compare_solve(p, r, ref)
+
+
+@pytest.mark.parametrize("k,n", [(2, 1000), (3, 600), (5, 512)])
+@pytest.mark.parametrize("prec", [fm.FP64, fm.MIXED])
+def test_solve_scaled_workloads(k, n, prec):
+    p = pg.workload(k, n_override=n)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=prec) as plan:
+        r = plan.solve(A, B, V)
+    ref = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes)
+    assert r.flag == 1 and ref.flag == 1
+    assert len(r.lam) == p.s
+    _compare_solve(p, r, ref)
+
+
+def test_solve_example31():
+    from conftest import load_example31
+    A, B, eig = load_example31()
+    V = pg.start_block(4, 3, seed=2)
+    tA, tB, tV = to_dev(A, B, V)
+    with fm.Plan(4, 3, 0.0, 1.0, 16, eps=1e-12) as plan:
+        r = plan.solve(tA, tB, tV)
+    assert r.flag == 1
+    assert np.allclose(np.sort(r.lam.real), [0.2, 0.5], atol=1e-12)
+    X = r.X.cpu().numpy()
+    for lam_ref, x_ref in eig:
+        i = int(np.argmin(np.abs(r.lam - lam_ref)))
+        assert abs(np.vdot(x_ref, X[:, i])) > 1 - 1e-12
+
+
+def test_solve_full_size_fp64_workload():
+    """n=4000, N=32, m=160 (the benchmark workload): eigenvalues against the
+    exact spectrum of the generated pencil, residuals recomputed on the host,
+    and the first filter against the closed form Q^{-1} f(D) Q V."""
+    p = pg.workload(2)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes) as plan:
+        U = plan.filter(A, B, V).cpu().numpy()
+        r = plan.solve(A, B, V)
+    cf = closed_form_filter(p, p.nodes, p.V)
+    assert np.max(np.abs(U - cf)) <= 1e-10 * np.abs(cf).max()
+    assert r.flag == 1 and len(r.lam) == p.s == 100
+    exact = p.d[p.inside_mask]
+    ri, ci, d = match(r.lam, exact)
+    assert np.max(d / np.maximum(np.abs(exact[ci]), 1e-3)) <= 1e-10
+    X = r.X.cpu().numpy()
+    hr = host_residuals(p.A, p.B, r.lam, X)
+    assert hr.max() <= 1e-10
