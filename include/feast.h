@@ -77,7 +77,7 @@ typedef struct {
   double refine_tol;   /* mixed form: per-node normwise backward-error target of the
                           final filter (default 4*2^-53) */
   int32_t max_sweeps;  /* mixed form: refinement sweeps per filter at most (default 6) */
-  int32_t nb;          /* LU panel width, 0 = automatic */
+  int32_t nb;          /* LU panel width: 64 or 128, 0 = automatic (128) */
   int32_t profile;     /* 1: time the LU trailing-update GEMM launches with HIP events on
                           the plan's stream (reported in feast_info); default 0 */
 } feast_opts;
@@ -192,7 +192,7 @@ int feast_stop_rule(int32_t k, int32_t c_k, double e_k, int32_t c_prev, double e
 /* In-place LU with partial pivoting of `batch` n x n row-major matrices:
  * P_b M_b = L_b U_b (L unit lower).  dPiv[b*n + i] is the 0-based row swapped
  * with row i at step i (LAPACK order).  dInfo[b] = 0, or 1 + the first column
- * with an exact zero pivot.  nb = panel width (0 = automatic).  Asynchronous
+ * with an exact zero pivot.  nb = panel width (64 or 128, 0 = automatic).  Synchronous
  * on `stream`.  The pivot test uses |re| + |im|, ties to the lowest row. */
 int feast_zgetrf_batched(int64_t n, int32_t batch, feast_z *dM, int64_t ldm, int64_t strideM,
                          int32_t *dPiv, int32_t *dInfo, int32_t nb, void *stream);

@@ -98,13 +98,15 @@ struct feast_plan {
   DevBuf F, piv, perm, info, Linv, Uinv;
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
-  DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
+  DevBuf R, Y, T1, T2, Yc, W, G, dinv, splitws, part, nrm, flag, small;
   std::string err;
   int last_sweeps = 0;       // mixed form: sweeps of the last filter
   double last_be = 0.0;      // mixed form: worst node backward error of the last filter
   bool stagnated = false;    // mixed form: the last filter missed its target
   // opts.profile: events around the LU trailing-update GEMMs
   std::vector<hipEvent_t> ev;
+  hipStream_t side = nullptr;                 // look-ahead panel stream
+  hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
   int prof_launches = 0;
   double prof_ms = 0.0, prof_flops = 0.0;
 
@@ -112,14 +114,14 @@ struct feast_plan {
   enum { W_ORTH = 0, W_U2 = 1, W_X = 2, W_AX = 3, W_BX = 4, W_XPREV = 5, W_U1 = 6, W_AU1 = 7,
          W_BU1 = 8, W_UF = 9, W_COUNT = 10 };
   // m x m blocks inside G
-  enum { G_GRAM = 0, G_AT = 2, G_BT = 3, G_YS = 4, G_COUNT = 5 };
+  enum { G_GRAM = 0, G_RINV = 1, G_T = 2, G_AT = 3, G_BT = 4, G_YS = 5, G_COUNT = 6 };
   z64 *wblk(int i) const { return W.as<z64>() + static_cast<int64_t>(i) * n * m; }
   z64 *gblk(int i) const { return G.as<z64>() + static_cast<int64_t>(i) * m * m; }
 
   bool mixed() const { return o.prec == FEAST_MIXED; }
   int64_t ldY() const { return static_cast<int64_t>(N) * m; }
   int64_t fstride() const { return n * n; }
-  int64_t istride() const { return nblk * nb * nb; }
+  int64_t istride() const { return nblk * 64 * 64; }  // inverted 64 x 64 diagonal blocks
 };
 
 namespace {
@@ -174,90 +176,136 @@ void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, i
 }
 
 struct LuProf {
-  std::vector<hipEvent_t> *ev = nullptr;  // 2 per panel step
+  std::vector<hipEvent_t> *ev = nullptr;  // pairs around trailing-update launches
   int used = 0;
   double flops = 0.0;
 };
 
+// Diagonal blocks of the triangular factors are inverted in blocks of kIB rows;
+// this is also the leaf size of the recursive triangular solves.
+constexpr int kIB = 64;
+
+// X <- L^{-1} X for the unit-lower L = M[r0:r1, r0:r1] (r0 a multiple of kIB)
+// and X = rows [r0, r1) of the block with columns starting at Xc (leading
+// dimension ldx, batch stride sX): recursive halving, leaves are in-place MFMA
+// products with the inverted kIB x kIB diagonal blocks.
 template <typename T>
-void lu_batched(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n, int nb,
-                int32_t *ipiv, int32_t *info, T *Linv, T *Uinv, int64_t istride,
-                LuProf *prof = nullptr) {
-  feast::fill_i32(s, info, batch, 0);
-  for (int64_t k0 = 0; k0 < n; k0 += nb) {
-    const int kb = static_cast<int>(std::min<int64_t>(nb, n - k0));
-    const int64_t blk = k0 / nb;
-    panel_rec<T>(s, M, ld, stride, batch, n, k0, kb, k0, kb, ipiv, info);
-    feast::laswp_outside<T>(s, M, ld, stride, batch, n, k0, kb, k0, k0 + kb, ipiv);
-    feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, nb, blk, blk + 1, true, Linv, istride);
-    const int64_t rest = n - k0 - kb;
-    if (rest > 0) {
-      // U12 = L11^{-1} A12, in place (one 64-row tile covers the kb <= 64 rows)
-      gemm_t<T>(s, 0, kb, rest, kb, zc(1.0), Linv + blk * nb * nb, nb, istride,
-                M + k0 * ld + k0 + kb, ld, stride, zc(0.0), M + k0 * ld + k0 + kb, ld, stride,
-                batch);
-      // A22 -= L21 U12
-      const bool timed = prof && prof->ev && prof->used + 2 <= static_cast<int>(prof->ev->size());
-      if (timed) HIPCHK(hipEventRecord((*prof->ev)[prof->used], s));
-      gemm_t<T>(s, 0, rest, rest, kb, zc(-1.0), M + (k0 + kb) * ld + k0, ld, stride,
-                M + k0 * ld + k0 + kb, ld, stride, zc(1.0), M + (k0 + kb) * ld + k0 + kb, ld,
-                stride, batch);
-      if (timed) {
-        HIPCHK(hipEventRecord((*prof->ev)[prof->used + 1], s));
-        prof->used += 2;
-        prof->flops += 8.0 * static_cast<double>(rest) * rest * kb * batch;
-      }
-    }
+void trsm_lower_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,
+                    const T *Linv, int64_t istride, int64_t r0, int64_t r1, T *X, int64_t ldx,
+                    int64_t sX, int64_t ncols, int ta) {
+  if (r1 - r0 <= kIB) {
+    gemm_t<T>(s, ta, r1 - r0, ncols, r1 - r0, zc(1.0), Linv + (r0 / kIB) * kIB * kIB, kIB,
+              istride, X + r0 * ldx, ldx, sX, zc(0.0), X + r0 * ldx, ldx, sX, batch);
+    return;
   }
-  const int64_t nblk = (n + nb - 1) / nb;
-  feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, nb, 0, nblk, false, Uinv, istride);
+  const int64_t half = ((r1 - r0 + 2 * kIB - 1) / (2 * kIB)) * kIB;
+  const int64_t mid = r0 + half;
+  trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, r0, mid, X, ldx, sX, ncols, ta);
+  if (ta == 0)  // X[mid:r1] -= L[mid:r1, r0:mid] X[r0:mid]
+    gemm_t<T>(s, 0, r1 - mid, ncols, mid - r0, zc(-1.0), M + mid * ld + r0, ld, stride,
+              X + r0 * ldx, ldx, sX, zc(1.0), X + mid * ldx, ldx, sX, batch);
+  else  // lower factor given as (U^*): rows [mid, r1) of U^* are columns of U rows [r0, mid)
+    gemm_t<T>(s, 2, r1 - mid, ncols, mid - r0, zc(-1.0), M + r0 * ld + mid, ld, stride,
+              X + r0 * ldx, ldx, sX, zc(1.0), X + mid * ldx, ldx, sX, batch);
+  trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, mid, r1, X, ldx, sX, ncols, ta);
 }
 
-// Blocked triangular solves with the cached factors, in place on Y
-// (per node: n x m, leading dimension ldy, node stride sY).
+// X <- U^{-1} X for the upper U = M[r0:r1, r0:r1] (ta = 0), or X <- L^{-*} X
+// with L^* unit upper (ta = 2, Linv holding the inverted blocks of L).
+template <typename T>
+void trsm_upper_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,
+                    const T *Inv, int64_t istride, int64_t r0, int64_t r1, T *X, int64_t ldx,
+                    int64_t sX, int64_t ncols, int ta) {
+  if (r1 - r0 <= kIB) {
+    gemm_t<T>(s, ta, r1 - r0, ncols, r1 - r0, zc(1.0), Inv + (r0 / kIB) * kIB * kIB, kIB,
+              istride, X + r0 * ldx, ldx, sX, zc(0.0), X + r0 * ldx, ldx, sX, batch);
+    return;
+  }
+  const int64_t half = ((r1 - r0 + 2 * kIB - 1) / (2 * kIB)) * kIB;
+  const int64_t mid = r0 + half;
+  trsm_upper_rec<T>(s, M, ld, stride, batch, Inv, istride, mid, r1, X, ldx, sX, ncols, ta);
+  if (ta == 0)  // X[r0:mid] -= U[r0:mid, mid:r1] X[mid:r1]
+    gemm_t<T>(s, 0, mid - r0, ncols, r1 - mid, zc(-1.0), M + r0 * ld + mid, ld, stride,
+              X + mid * ldx, ldx, sX, zc(1.0), X + r0 * ldx, ldx, sX, batch);
+  else  // rows [r0, mid) of L^* are columns of L rows [mid, r1)
+    gemm_t<T>(s, 2, mid - r0, ncols, r1 - mid, zc(-1.0), M + mid * ld + r0, ld, stride,
+              X + mid * ldx, ldx, sX, zc(1.0), X + r0 * ldx, ldx, sX, batch);
+  trsm_upper_rec<T>(s, M, ld, stride, batch, Inv, istride, r0, mid, X, ldx, sX, ncols, ta);
+}
+
+// Streams and events of the look-ahead factorisation.
+struct LuStreams {
+  hipStream_t main = nullptr, side = nullptr;
+  hipEvent_t cols_ready = nullptr, panel_done = nullptr;
+};
+
+template <typename T>
+void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+                int nb, int32_t *ipiv, int32_t *info, T *Linv, T *Uinv, int64_t istride,
+                LuProf *prof = nullptr) {
+  hipStream_t s = st.main;
+  const bool ahead = st.side != nullptr;
+  feast::fill_i32(s, info, batch, 0);
+  auto timed_gemm = [&](int64_t rows, int64_t cols, int64_t kb, const T *Ap, const T *Bp, T *Cp) {
+    const bool timed = prof && prof->ev && prof->used + 2 <= static_cast<int>(prof->ev->size());
+    if (timed) HIPCHK(hipEventRecord((*prof->ev)[prof->used], s));
+    gemm_t<T>(s, 0, rows, cols, kb, zc(-1.0), Ap, ld, stride, Bp, ld, stride, zc(1.0), Cp, ld,
+              stride, batch);
+    if (timed) {
+      HIPCHK(hipEventRecord((*prof->ev)[prof->used + 1], s));
+      prof->used += 2;
+      prof->flops += 8.0 * static_cast<double>(rows) * cols * kb * batch;
+    }
+  };
+  // first panel
+  panel_rec<T>(s, M, ld, stride, batch, n, 0, static_cast<int>(std::min<int64_t>(nb, n)), 0,
+               static_cast<int>(std::min<int64_t>(nb, n)), ipiv, info);
+  for (int64_t k0 = 0; k0 < n; k0 += nb) {
+    const int kb = static_cast<int>(std::min<int64_t>(nb, n - k0));
+    const int64_t k1 = k0 + kb, rest = n - k1;
+    // the panel [k0, k1) is factored (on `s`, or on the side stream joined below)
+    feast::laswp_outside<T>(s, M, ld, stride, batch, n, k0, kb, k0, k1, ipiv);
+    feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, kIB, k0 / kIB,
+                                 (k1 + kIB - 1) / kIB, true, Linv, istride);
+    if (rest <= 0) break;
+    // U12 = L11^{-1} A12
+    trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, k0, k1, M + k1, ld, stride, rest, 0);
+    const int kb1 = static_cast<int>(std::min<int64_t>(nb, rest));
+    if (ahead) {
+      // look-ahead: update the next panel's columns, factor that panel on the
+      // side stream while the rest of the trailing matrix is updated here
+      timed_gemm(rest, kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
+      HIPCHK(hipEventRecord(st.cols_ready, s));
+      HIPCHK(hipStreamWaitEvent(st.side, st.cols_ready, 0));
+      panel_rec<T>(st.side, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
+      HIPCHK(hipEventRecord(st.panel_done, st.side));
+      if (rest > kb1)
+        timed_gemm(rest, rest - kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1 + kb1,
+                   M + k1 * ld + k1 + kb1);
+      HIPCHK(hipStreamWaitEvent(s, st.panel_done, 0));
+    } else {
+      timed_gemm(rest, rest, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
+      panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
+    }
+  }
+  const int64_t nblk = (n + kIB - 1) / kIB;
+  feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, kIB, 0, nblk, false, Uinv, istride);
+}
+
+// Triangular solves with the cached factors, in place on Y (per node: n x m,
+// leading dimension ldy, node stride sY):
 //   trans = 0: Y <- U^{-1} L^{-1} Y   (after the row permutation)
 //   trans = 2: Y <- L^{-*} U^{-*} Y   (before the inverse permutation)
 template <typename T>
 void trsolve(hipStream_t s, const T *F, int64_t ld, int64_t fstride, int32_t batch, int64_t n,
-             int nb, const T *Linv, const T *Uinv, int64_t istride, T *Y, int64_t m, int64_t ldy,
+             const T *Linv, const T *Uinv, int64_t istride, T *Y, int64_t m, int64_t ldy,
              int64_t sY, int trans) {
-  const int64_t nblk = (n + nb - 1) / nb;
-  const z64 one = zc(1.0), zero = zc(0.0), mone = zc(-1.0);
   if (trans == 0) {
-    for (int64_t I = 0; I < nblk; ++I) {
-      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
-      gemm_t<T>(s, 0, rb, m, rb, one, Linv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
-                Y + r0 * ldy, ldy, sY, batch);
-      if (r0 + rb < n)
-        gemm_t<T>(s, 0, n - r0 - rb, m, rb, mone, F + (r0 + rb) * ld + r0, ld, fstride,
-                  Y + r0 * ldy, ldy, sY, one, Y + (r0 + rb) * ldy, ldy, sY, batch);
-    }
-    for (int64_t I = nblk - 1; I >= 0; --I) {
-      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
-      gemm_t<T>(s, 0, rb, m, rb, one, Uinv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
-                Y + r0 * ldy, ldy, sY, batch);
-      if (r0 > 0)
-        gemm_t<T>(s, 0, r0, m, rb, mone, F + r0, ld, fstride, Y + r0 * ldy, ldy, sY, one, Y, ldy,
-                  sY, batch);
-    }
+    trsm_lower_rec<T>(s, F, ld, fstride, batch, Linv, istride, 0, n, Y, ldy, sY, m, 0);
+    trsm_upper_rec<T>(s, F, ld, fstride, batch, Uinv, istride, 0, n, Y, ldy, sY, m, 0);
   } else {
-    // M^* = U^* L^* P: forward with U^* (lower), then backward with L^* (unit upper)
-    for (int64_t I = 0; I < nblk; ++I) {
-      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
-      gemm_t<T>(s, 2, rb, m, rb, one, Uinv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
-                Y + r0 * ldy, ldy, sY, batch);
-      if (r0 + rb < n)
-        gemm_t<T>(s, 2, n - r0 - rb, m, rb, mone, F + r0 * ld + r0 + rb, ld, fstride, Y + r0 * ldy,
-                  ldy, sY, one, Y + (r0 + rb) * ldy, ldy, sY, batch);
-    }
-    for (int64_t I = nblk - 1; I >= 0; --I) {
-      const int64_t r0 = I * nb, rb = std::min<int64_t>(nb, n - r0);
-      gemm_t<T>(s, 2, rb, m, rb, one, Linv + I * nb * nb, nb, istride, Y + r0 * ldy, ldy, sY, zero,
-                Y + r0 * ldy, ldy, sY, batch);
-      if (r0 > 0)
-        gemm_t<T>(s, 2, r0, m, rb, mone, F + r0 * ld, ld, fstride, Y + r0 * ldy, ldy, sY, one, Y,
-                  ldy, sY, batch);
-    }
+    trsm_lower_rec<T>(s, F, ld, fstride, batch, Uinv, istride, 0, n, Y, ldy, sY, m, 2);
+    trsm_upper_rec<T>(s, F, ld, fstride, batch, Linv, istride, 0, n, Y, ldy, sY, m, 2);
   }
 }
 
@@ -272,6 +320,7 @@ void ensure_workspace(feast_plan *p) {
   p->Y.alloc(zs * n * m * N);
   p->W.alloc(zs * n * m * feast_plan::W_COUNT);
   p->G.alloc(zs * m * m * feast_plan::G_COUNT);
+  p->dinv.alloc(zs * ((m + 63) / 64) * 64 * 64);
   p->splitws.alloc(zs * std::max<int64_t>(m * m * 96, 1 << 16));
   p->part.alloc(sizeof(double) * std::max<int64_t>(((n + 63) / 64) * 3 * m, 64 * N + 64));
   p->nrm.alloc(sizeof(double) * (3 * m + 4 * N + 16));
@@ -303,7 +352,7 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
   p->Uinv.alloc(esz * N * p->istride());
   LuProf prof;
   if (p->o.profile) {
-    const size_t need = 2 * static_cast<size_t>(p->nblk);
+    const size_t need = 4 * static_cast<size_t>((n + p->nb - 1) / p->nb);
     while (p->ev.size() < need) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
@@ -313,12 +362,12 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
   }
   if (p->mixed()) {
     feast::shift_assemble_c(s, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
-    lu_batched<c64>(s, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
+    lu_batched<c64>(LuStreams{s, p->side, p->ev_cols, p->ev_panel}, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<c64>(), p->Uinv.as<c64>(), p->istride(),
                     &prof);
   } else {
     feast::shift_assemble_z(s, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<z64>(), n, n * n);
-    lu_batched<z64>(s, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
+    lu_batched<z64>(LuStreams{s, p->side, p->ev_cols, p->ev_panel}, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<z64>(), p->Uinv.as<z64>(), p->istride(),
                     &prof);
   }
@@ -368,18 +417,20 @@ void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr) {
   const int64_t n = p->n, m = p->m, ldY = p->ldY();
   z64 *Y = p->Y.as<z64>();
   feast::gather_rows<z64>(p->s, R, ldr, 0, p->perm.as<int32_t>(), n, m, p->N, Y, ldY, m);
-  trsolve<z64>(p->s, p->F.as<z64>(), n, p->fstride(), p->N, n, p->nb, p->Linv.as<z64>(),
+  trsolve<z64>(p->s, p->F.as<z64>(), n, p->fstride(), p->N, n, p->Linv.as<z64>(),
                p->Uinv.as<z64>(), p->istride(), Y, m, ldY, m, 0);
 }
 
-// Mixed form (spec precision form): complex64 LU solves; FP64 residual
-// r_j = R - (z_j B - A) Y_j of all nodes as the two GEMMs A Y and B Y; the
-// complex64 correction d_j = (LU32_j)^{-1} r_j and the FP64 update Y_j += d_j,
-// repeated until every node's normwise backward error
-//   ||r_j||_F / ((|z_j| ||B||_F + ||A||_F) ||Y_j||_F + ||R||_F)
-// is at most `target` (target <= 0: no refinement).
+// Mixed form: complex64 LU solves; FP64 residual r_j = R - (z_j B - A) Y_j of
+// all nodes as the two GEMMs A Y and B Y; the complex64 correction
+// d_j = (LU32_j)^{-1} r_j and the FP64 update Y_j += d_j.
+//   target > 0 : sweep until every node's normwise backward error
+//                ||r_j||_F / ((|z_j| ||B||_F + ||A||_F) ||Y_j||_F + ||R||_F) <= target
+//                (at most max_sweeps corrections; each test costs one residual);
+//   target <= 0: exactly `sweeps` corrections with no final residual (the caller
+//                judges the accuracy, as Algorithm 5 does through eq. 5-1).
 void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
-                       const z64 *R, int64_t ldr, double target) {
+                       const z64 *R, int64_t ldr, double target, int sweeps) {
   const int64_t n = p->n, m = p->m, ldY = p->ldY();
   const int N = p->N;
   hipStream_t s = p->s;
@@ -392,41 +443,46 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
   // complex64 solve of P_j R
   feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, m);
   feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0);
-  trsolve<c64>(s, F, n, p->fstride(), N, n, p->nb, p->Linv.as<c64>(), p->Uinv.as<c64>(),
+  trsolve<c64>(s, F, n, p->fstride(), N, n, p->Linv.as<c64>(), p->Uinv.as<c64>(),
                p->istride(), Yc, m, ldY, m, 0);
   feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
   p->last_sweeps = 0;
   p->last_be = -1.0;
   p->stagnated = false;
-  if (!(target > 0.0)) return;
-  feast::fro2_batched(s, R, ldr, 0, n, m, 1, part, nrm + 2 * N);
+  const bool verify = target > 0.0;
+  const int max_corr = verify ? p->o.max_sweeps : sweeps;
+  if (!verify && sweeps <= 0) return;
+  if (verify) feast::fro2_batched(s, R, ldr, 0, n, m, 1, part, nrm + 2 * N);
   std::vector<double> hn(2 * N + 1);
   double prev_worst = INFINITY;
-  for (int sweep = 0; sweep <= p->o.max_sweeps; ++sweep) {
+  for (int sweep = 0; sweep <= max_corr; ++sweep) {
+    if (!verify && sweep == max_corr) break;
     gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), A, lda, 0, Y, ldY, 0, zc(0.0), T1, ldY, 0, 1);
     gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), B, ldb, 0, Y, ldY, 0, zc(0.0), T2, ldY, 0, 1);
     feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, m);
-    feast::fro2_batched(s, T1, ldY, m, n, m, N, part, nrm);
-    feast::fro2_batched(s, Y, ldY, m, n, m, N, part, nrm + N);
-    HIPCHK(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * (2 * N + 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double nR = std::sqrt(hn[2 * N]);
-    double worst = 0.0;
-    for (int j = 0; j < N; ++j) {
-      const double mj = std::abs(p->hz[j]) * p->normB + p->normA;
-      const double be = std::sqrt(hn[j]) / (mj * std::sqrt(hn[N + j]) + nR);
-      worst = std::max(worst, be);
+    if (verify) {
+      feast::fro2_batched(s, T1, ldY, m, n, m, N, part, nrm);
+      feast::fro2_batched(s, Y, ldY, m, n, m, N, part, nrm + N);
+      HIPCHK(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * (2 * N + 1), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const double nR = std::sqrt(hn[2 * N]);
+      double worst = 0.0;
+      for (int j = 0; j < N; ++j) {
+        const double mj = std::abs(p->hz[j]) * p->normB + p->normA;
+        const double be = std::sqrt(hn[j]) / (mj * std::sqrt(hn[N + j]) + nR);
+        worst = std::max(worst, be);
+      }
+      p->last_be = worst;
+      if (worst <= target) return;
+      if (sweep == max_corr || !(worst < 0.5 * prev_worst)) {
+        p->stagnated = true;
+        return;
+      }
+      prev_worst = worst;
     }
-    p->last_be = worst;
-    if (worst <= target) return;
-    if (sweep == p->o.max_sweeps || !(worst < 0.5 * prev_worst)) {
-      p->stagnated = true;
-      return;
-    }
-    prev_worst = worst;
     feast::gather_rows<z64>(s, T1, ldY, m, perm, n, m, N, T2, ldY, m);
     feast::z_to_c(s, T2, ldY, 0, n, ldY, 1, Yc, ldY, 0);
-    trsolve<c64>(s, F, n, p->fstride(), N, n, p->nb, p->Linv.as<c64>(), p->Uinv.as<c64>(),
+    trsolve<c64>(s, F, n, p->fstride(), N, n, p->Linv.as<c64>(), p->Uinv.as<c64>(),
                  p->istride(), Yc, m, ldY, m, 0);
     feast::add_c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
     p->last_sweeps = sweep + 1;
@@ -434,11 +490,12 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
 }
 
 // U = sum_j w_j (z_j B - A)^{-1} R  (the filter of eq. 8-4 on the right-hand side R = B U_1).
+// Mixed form: see solve_nodes_mixed for `target` and `sweeps`.
 int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb, const z64 *R,
-               int64_t ldr, z64 *U, int64_t ldu, double target) {
+               int64_t ldr, z64 *U, int64_t ldu, double target, int sweeps) {
   int st = ensure_factored(p, A, lda, B, ldb);
   if (p->mixed())
-    solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target);
+    solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps);
   else
     solve_nodes_z(p, R, ldr);
   feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, p->m, U,
@@ -453,23 +510,71 @@ int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t l
   return st;
 }
 
+// Cholesky G = R^* R of a t x t Hermitian matrix (upper triangle used, R
+// written over it), blocked by 64 columns: LDS Cholesky of the diagonal block,
+// R_J,rest = R_JJ^{-*} G_J,rest and G_rest -= R_J,rest^* R_J,rest as MFMA GEMMs.
+void chol_blocked(feast_plan *p, z64 *G, int64_t t, double shift_rel, int32_t *flag) {
+  hipStream_t s = p->s;
+  z64 *Dinv = p->dinv.as<z64>();
+  if (shift_rel > 0.0) feast::add_diag_shift(s, G, t, shift_rel);
+  for (int64_t J0 = 0; J0 < t; J0 += 64) {
+    const int jb = static_cast<int>(std::min<int64_t>(64, t - J0));
+    z64 *GJ = G + J0 * t + J0;
+    feast::chol_block(s, GJ, t, jb, static_cast<int>(J0), flag);
+    const int64_t rest = t - J0 - jb;
+    if (rest <= 0) break;
+    feast::diag_block_inverse<z64>(s, GJ, t, 0, 1, jb, 64, 0, 1, false, Dinv, 0);
+    gemm_t<z64>(s, 2, jb, rest, jb, zc(1.0), Dinv, 64, 0, GJ + jb, t, 0, zc(0.0), GJ + jb, t, 0, 1);
+    gemm_t<z64>(s, 2, rest, rest, jb, zc(-1.0), GJ + jb, t, 0, GJ + jb, t, 0, zc(1.0),
+                G + (J0 + jb) * t + J0 + jb, t, 0, 1);
+  }
+  feast::zero_lower(s, G, t, false);
+}
+
+// X = R^{-1} for the t x t upper-triangular R (leading dimension t): inverted
+// 64 x 64 diagonal blocks, then X12 = -X11 R12 X22 by recursive halving.
+void inv_upper_rec(hipStream_t s, const z64 *R, int64_t t, z64 *X, z64 *T, int64_t r0, int64_t r1) {
+  if (r1 - r0 <= 64) return;
+  const int64_t mid = r0 + ((r1 - r0 + 127) / 128) * 64;
+  inv_upper_rec(s, R, t, X, T, r0, mid);
+  inv_upper_rec(s, R, t, X, T, mid, r1);
+  gemm_t<z64>(s, 0, mid - r0, r1 - mid, r1 - mid, zc(1.0), R + r0 * t + mid, t, 0, X + mid * t + mid,
+              t, 0, zc(0.0), T, t, 0, 1);
+  gemm_t<z64>(s, 0, mid - r0, r1 - mid, mid - r0, zc(-1.0), X + r0 * t + r0, t, 0, T, t, 0, zc(0.0),
+              X + r0 * t + mid, t, 0, 1);
+}
+
+void inv_upper_blocked(feast_plan *p, const z64 *R, int64_t t, z64 *X, z64 *T) {
+  hipStream_t s = p->s;
+  z64 *Dinv = p->dinv.as<z64>();
+  const int64_t nblk = (t + 63) / 64;
+  feast::zero_lower(s, X, t, true);
+  feast::diag_block_inverse<z64>(s, R, t, 0, 1, t, 64, 0, nblk, false, Dinv, 0);
+  for (int64_t I = 0; I < nblk; ++I) {
+    const int64_t rb = std::min<int64_t>(64, t - I * 64);
+    feast::copy_block_z(s, Dinv + I * 64 * 64, 64, rb, rb, X + I * 64 * t + I * 64, t);
+  }
+  inv_upper_rec(s, R, t, X, T, 0, t);
+}
+
 // Shifted Cholesky QR3 (three Cholesky QR passes, the first on X^*X + s I with
 // s = 11 (n m + m (m+1)) u ||X||_F^2): an FP64 orthonormalisation that stays
 // stable for condition numbers up to about 1/u, built from the Gram GEMM,
-// a t x t Cholesky, a triangular inverse and one more GEMM per pass.
+// a blocked t x t Cholesky, a blocked triangular inverse and one more GEMM per pass.
 void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot) {
   const int64_t n = p->n, m = p->m;
   hipStream_t s = p->s;
   z64 *G = p->gblk(feast_plan::G_GRAM);
+  z64 *Ri = p->gblk(feast_plan::G_RINV), *T = p->gblk(feast_plan::G_T);
   z64 *Wt = p->wblk(feast_plan::W_ORTH);
   int32_t *flag = p->flag.as<int32_t>() + flag_slot;
   const double shift_rel = 11.0 * (static_cast<double>(n) * m + static_cast<double>(m) * (m + 1)) * kU64;
   for (int pass = 0; pass < 3; ++pass) {
     gemm_t<z64>(s, 2, m, m, n, zc(1.0), X, ldx, 0, X, ldx, 0, zc(0.0), G, m, 0, 1,
                 p->splitws.as<z64>(), splitws_elems(p));
-    feast::cholesky_upper(s, G, m, pass == 0 ? shift_rel : 0.0, flag + pass);
-    feast::trinv_upper(s, G, m);
-    gemm_t<z64>(s, 0, n, m, m, zc(1.0), X, ldx, 0, G, m, 0, zc(0.0), Wt, m, 0, 1);
+    chol_blocked(p, G, m, pass == 0 ? shift_rel : 0.0, flag + pass);
+    inv_upper_blocked(p, G, m, Ri, T);
+    gemm_t<z64>(s, 0, n, m, m, zc(1.0), X, ldx, 0, Ri, m, 0, zc(0.0), Wt, m, 0, 1);
     feast::copy_block_z(s, Wt, m, n, m, X, ldx);
   }
 }
@@ -603,7 +708,7 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
   if (!(opts.eta > 0.0) || !(opts.eps >= 0.0) || opts.max_iter < 1 ||
       opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
       opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) ||
-      (opts.nb != 0 && opts.nb != 16 && opts.nb != 32 && opts.nb != 64))
+      (opts.nb != 0 && opts.nb != 64 && opts.nb != 128))
     return FEAST_EINVAL;
   feast_plan *p = nullptr;
   try {
@@ -617,8 +722,8 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
   p->c = *c;
   p->o = opts;
   p->s = static_cast<hipStream_t>(stream);
-  p->nb = opts.nb ? opts.nb : 64;
-  p->nblk = (n + p->nb - 1) / p->nb;
+  p->nb = opts.nb ? opts.nb : 128;
+  p->nblk = (n + 63) / 64;
   p->hz.resize(p->N);
   p->hw.resize(p->N);
   feast_host::contour_nodes(cd(c->center.re, c->center.im), c->radius, p->N, c->rule, p->hz.data(),
@@ -629,6 +734,9 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
     HIPCHK(hipMemcpy(p->dz.p, p->hz.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->dw.p, p->hw.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
     ensure_workspace(p);
+    HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming));
     return FEAST_OK;
   });
   if (rc != FEAST_OK) {
@@ -643,8 +751,14 @@ int feast_plan_destroy(feast_plan *p) {
   if (!p) return FEAST_OK;
   if (p->s) (void)hipStreamSynchronize(p->s);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  if (p->side) {
+    (void)hipStreamSynchronize(p->side);
+    (void)hipStreamDestroy(p->side);
+  }
+  if (p->ev_cols) (void)hipEventDestroy(p->ev_cols);
+  if (p->ev_panel) (void)hipEventDestroy(p->ev_panel);
   for (DevBuf *b : {&p->dz, &p->dw, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->R,
-                    &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->part, &p->nrm,
+                    &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->dinv, &p->splitws, &p->part, &p->nrm,
                     &p->flag, &p->small})
     b->release();
   delete p;
@@ -673,7 +787,7 @@ int feast_filter(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
     gemm_t<z64>(p->s, 0, p->n, p->m, p->n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(),
                 p->m, 0, 1);
     const int st = filter_rhs(p, A, lda, B, ldb, p->R.as<z64>(), p->m, reinterpret_cast<z64 *>(dU),
-                              ldu, p->o.refine_tol);
+                              ldu, p->o.refine_tol, 0);
     HIPCHK(hipGetLastError());
     return st;
   });
@@ -705,7 +819,8 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
   p->err.clear();
   return guarded(p, [&]() -> int {
     const int64_t n = p->n, m = p->m;
-    hipStream_t s = p->s;
+    hipStream_t s = p->s;       // filters and projections
+    hipStream_t s2 = p->side;   // Ritz vectors and residuals (overlap with the next filter)
     const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
     const z64 *V = reinterpret_cast<const z64 *>(dV);
     const cd gamma(p->c.center.re, p->c.center.im);
@@ -713,7 +828,6 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
     feast_info inf{};
     Timer total;
     int status = FEAST_OK;
-    // cached factors (first filter)
     {
       Timer t;
       const int st = ensure_factored(p, A, lda, B, ldb);
@@ -731,16 +845,23 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
     const int64_t mm = m * m;
     std::vector<feast_z> hAt(mm), hBt(mm), hY(mm), halpha(m), hbeta(m);
     std::vector<double> hn(3 * m);
-    // line 1 (Search with the subspace size fixed): U = Q_N V, then QR inside the projection
+    // Mixed form: Search's filter is not refined, later filters get `sweeps`
+    // corrections (one more whenever a refined iteration missed eps).
+    int sweeps = p->mixed() ? 1 : 0;
+    auto run_filter = [&](const z64 *R, z64 *Uout, bool first) -> int {
+      const int st = filter_rhs(p, A, lda, B, ldb, R, m, Uout, m, 0.0, first ? 0 : sweeps);
+      if (inf.filters < FEAST_MAX_HISTORY) inf.sweeps[inf.filters] = p->last_sweeps;
+      inf.filters += 1;
+      return st;
+    };
+    // line 1 (Search with the subspace size fixed): U = Q_N V, QR inside the projection
     {
       Timer t;
       gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1);
-      const int st = filter_rhs(p, A, lda, B, ldb, p->R.as<z64>(), m, U1, m, 0.0);
+      const int st = run_filter(p->R.as<z64>(), U1, true);
       if (st != FEAST_OK && st != FEAST_REFINE_STAGNATED) return st;
       HIPCHK(hipStreamSynchronize(s));
       inf.t_filter_ms += t.ms();
-      inf.sweeps[0] = p->last_sweeps;
-      inf.filters = 1;
     }
     // lines 2 and 5 of the first iteration
     {
@@ -750,12 +871,28 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
       inf.t_project_ms += t.ms();
       if (st != FEAST_OK) return st;
     }
+    HIPCHK(hipEventRecord(p->ev_cols, s));
+    HIPCHK(hipStreamWaitEvent(s2, p->ev_cols, 0));
     // line 3
     double e_prev = 0.0;
     int c_prev = 0;
     std::vector<cd> lam_prev;
     std::vector<double> r_prev;
     for (int k = 1; k <= p->o.max_iter; ++k) {
+      // line 16 ahead of time: the next filter needs only B U_1, so it runs on
+      // the GPU while the host solves the reduced pencil; it is skipped when
+      // this iteration is likely to be the last one
+      // (mixed form: an iteration fed by a refined filter after a settled count)
+      const bool likely_last = (k == p->o.max_iter) || (c_prev > 0 && e_prev < 1e3 * p->o.eps) ||
+                               (p->mixed() && k >= 2 && c_prev > 0 && e_prev < 1e-4);
+      bool speculated = false;
+      Timer tf;
+      if (!likely_last) {
+        const int st = run_filter(BU1, UF, false);
+        if (st == FEAST_REFINE_STAGNATED) status = st;
+        else if (st != FEAST_OK) return st;
+        speculated = true;
+      }
       // line 6: reduced pencil on the host
       Timer te;
       if (feast_reduced_eig(m, hAt.data(), m, hBt.data(), m, halpha.data(), hbeta.data(), hY.data(),
@@ -770,15 +907,15 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
         lam[i] = (b != cd(0.0)) ? a / b : cd(INFINITY, 0.0);
         hlam[i] = std::isfinite(lam[i].real()) ? feast_z{lam[i].real(), lam[i].imag()} : feast_z{0, 0};
       }
-      // x_i = U_1 y_i together with A x_i = (A U_1) y_i and B x_i = (B U_1) y_i
-      HIPCHK(hipMemcpyAsync(Ys, hY.data(), sizeof(z64) * mm, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(dlam, hlam.data(), sizeof(z64) * m, hipMemcpyHostToDevice, s));
-      gemm_t<z64>(s, 0, n, m, m, zc(1.0), U1, m, 0, Ys, m, 0, zc(0.0), X, m, 0, 1);
-      gemm_t<z64>(s, 0, n, m, m, zc(1.0), AU1, m, 0, Ys, m, 0, zc(0.0), AX, m, 0, 1);
-      gemm_t<z64>(s, 0, n, m, m, zc(1.0), BU1, m, 0, Ys, m, 0, zc(0.0), BX, m, 0, 1);
-      feast::ritz_norms(s, AX, BX, m, n, m, dlam, p->part.as<double>(), dnorm);
-      HIPCHK(hipMemcpyAsync(hn.data(), dnorm, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      // x_i = U_1 y_i with A x_i = (A U_1) y_i and B x_i = (B U_1) y_i (side stream)
+      HIPCHK(hipMemcpyAsync(Ys, hY.data(), sizeof(z64) * mm, hipMemcpyHostToDevice, s2));
+      HIPCHK(hipMemcpyAsync(dlam, hlam.data(), sizeof(z64) * m, hipMemcpyHostToDevice, s2));
+      gemm_t<z64>(s2, 0, n, m, m, zc(1.0), U1, m, 0, Ys, m, 0, zc(0.0), X, m, 0, 1);
+      gemm_t<z64>(s2, 0, n, m, m, zc(1.0), AU1, m, 0, Ys, m, 0, zc(0.0), AX, m, 0, 1);
+      gemm_t<z64>(s2, 0, n, m, m, zc(1.0), BU1, m, 0, Ys, m, 0, zc(0.0), BX, m, 0, 1);
+      feast::ritz_norms(s2, AX, BX, m, n, m, dlam, p->part.as<double>(), dnorm);
+      HIPCHK(hipMemcpyAsync(hn.data(), dnorm, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s2));
+      HIPCHK(hipStreamSynchronize(s2));
       // lines 7-12: residuals (eq. 5-1), selection, c(k), e(k)
       std::vector<int32_t> sel;
       std::vector<double> rsel;
@@ -802,8 +939,8 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
       const int act = feast_host::stop_rule(k, c_k, e_k, c_prev, e_prev, p->o.eps, p->o.max_iter);
       if (act == 1 || act == -1) {
         if (c_k > 0) {
-          HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s));
-          feast::gather_normalize_cols(s, X, m, n, didx, c_k, reinterpret_cast<z64 *>(dX), ldx, nullptr);
+          HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s2));
+          feast::gather_normalize_cols(s2, X, m, n, didx, c_k, reinterpret_cast<z64 *>(dX), ldx, nullptr);
         }
         for (int i = 0; i < c_k; ++i) {
           hLambda[i] = {lam[sel[i]].real(), lam[sel[i]].imag()};
@@ -812,13 +949,13 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
         *s_found = c_k;
         *err = e_k;
         *flag = act;
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipStreamSynchronize(s2));
         inf.t_ritz_ms += tr.ms();
         break;
       }
       if (act == 0) {
         const int cp = static_cast<int>(lam_prev.size());
-        feast::copy_block_z(s, Xprev, m, n, cp, reinterpret_cast<z64 *>(dX), ldx);
+        feast::copy_block_z(s2, Xprev, m, n, cp, reinterpret_cast<z64 *>(dX), ldx);
         for (int i = 0; i < cp; ++i) {
           hLambda[i] = {lam_prev[i].real(), lam_prev[i].imag()};
           if (hRes) hRes[i] = r_prev[i];
@@ -826,7 +963,7 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
         *s_found = cp;
         *err = e_prev;
         *flag = 0;
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipStreamSynchronize(s2));
         inf.t_ritz_ms += tr.ms();
         break;
       }
@@ -835,34 +972,38 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
       r_prev = rsel;
       for (int i = 0; i < c_k; ++i) lam_prev.push_back(lam[sel[i]]);
       if (c_k > 0) {
-        HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s));
-        feast::gather_normalize_cols(s, X, m, n, didx, c_k, Xprev, m, nullptr);
+        HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s2));
+        feast::gather_normalize_cols(s2, X, m, n, didx, c_k, Xprev, m, nullptr);
       }
+      // a refined iteration whose count is settled but missed eps: refine harder
+      if (p->mixed() && k >= 2 && c_k == c_prev && e_k >= p->o.eps && sweeps < p->o.max_sweeps)
+        ++sweeps;
       e_prev = e_k;
       c_prev = c_k;
+      HIPCHK(hipEventRecord(p->ev_panel, s2));
       inf.t_ritz_ms += tr.ms();
-      // line 16: U = Q_N U_1 (right-hand side B U_1, cached factors)
-      {
-        Timer t;
-        const double target = p->mixed() ? p->o.refine_tol : 0.0;
-        const int st = filter_rhs(p, A, lda, B, ldb, BU1, m, UF, m, target);
-        if (st == FEAST_REFINE_STAGNATED) status = FEAST_REFINE_STAGNATED;
+      // line 16 (unless it already ran)
+      if (!speculated) {
+        const int st = run_filter(BU1, UF, false);
+        if (st == FEAST_REFINE_STAGNATED) status = st;
         else if (st != FEAST_OK) return st;
-        HIPCHK(hipStreamSynchronize(s));
-        inf.t_filter_ms += t.ms();
-        if (inf.filters < FEAST_MAX_HISTORY) inf.sweeps[inf.filters] = p->last_sweeps;
-        inf.filters += 1;
       }
-      // line 17 and line 5 of the next iteration
+      HIPCHK(hipStreamSynchronize(s));
+      inf.t_filter_ms += tf.ms() - te.ms();
+      // line 17 and line 5 of the next iteration (after the side stream is done with U_1)
       {
         Timer t;
+        HIPCHK(hipStreamWaitEvent(s, p->ev_panel, 0));
         feast::copy_block_z(s, UF, m, n, m, U1, m);
         project_device(p, A, lda, B, ldb, U1, m, AU1, m, BU1, m);
         const int st = project_finish(p, hAt.data(), hBt.data());
         inf.t_project_ms += t.ms();
         if (st != FEAST_OK) return st;
+        HIPCHK(hipEventRecord(p->ev_cols, s));
+        HIPCHK(hipStreamWaitEvent(s2, p->ev_cols, 0));
       }
     }
+    HIPCHK(hipStreamSynchronize(s));
     inf.t_total_ms = total.ms();
     inf.lu_gemm_launches = p->prof_launches;
     inf.lu_gemm_ms = p->prof_ms;
@@ -895,17 +1036,18 @@ int feast_zgemm_batched(int32_t transA, int64_t M, int64_t N, int64_t K, feast_z
 int feast_zgetrf_batched(int64_t n, int32_t batch, feast_z *dM, int64_t ldm, int64_t strideM,
                          int32_t *dPiv, int32_t *dInfo, int32_t nb, void *stream) {
   if (n < 1 || n > 16384 || batch < 1 || !dM || !dPiv || !dInfo || ldm < n ||
-      (nb != 0 && nb != 16 && nb != 32 && nb != 64))
+      (nb != 0 && nb != 64 && nb != 128))
     return FEAST_EINVAL;
-  const int b = nb ? nb : 64;
+  const int b = nb ? nb : 128;
   return guarded(nullptr, [&]() {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t nblk = (n + b - 1) / b;
+    const int64_t nblk = (n + 63) / 64;
     DevBuf Li, Ui;
-    Li.alloc(sizeof(z64) * batch * nblk * b * b);
-    Ui.alloc(sizeof(z64) * batch * nblk * b * b);
-    lu_batched<z64>(s, reinterpret_cast<z64 *>(dM), ldm, strideM, batch, n, b, dPiv, dInfo,
-                    Li.as<z64>(), Ui.as<z64>(), nblk * b * b);
+    Li.alloc(sizeof(z64) * batch * nblk * 64 * 64);
+    Ui.alloc(sizeof(z64) * batch * nblk * 64 * 64);
+    lu_batched<z64>(LuStreams{s, nullptr, nullptr, nullptr}, reinterpret_cast<z64 *>(dM), ldm,
+                    strideM, batch, n, b, dPiv, dInfo, Li.as<z64>(), Ui.as<z64>(),
+                    nblk * 64 * 64);
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipGetLastError());
     Li.release();
@@ -923,30 +1065,29 @@ int feast_zgetrs_batched(int64_t n, int64_t nrhs, int32_t batch, const feast_z *
   if (nrhs == 0) return FEAST_OK;
   return guarded(nullptr, [&]() {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int b = 64;
-    const int64_t nblk = (n + b - 1) / b;
+    const int64_t nblk = (n + 63) / 64, ist = nblk * 64 * 64;
     DevBuf Li, Ui, perm, T;
-    Li.alloc(sizeof(z64) * batch * nblk * b * b);
-    Ui.alloc(sizeof(z64) * batch * nblk * b * b);
+    Li.alloc(sizeof(z64) * batch * ist);
+    Ui.alloc(sizeof(z64) * batch * ist);
     perm.alloc(sizeof(int32_t) * batch * n);
     T.alloc(sizeof(z64) * batch * n * nrhs);
     const z64 *F = reinterpret_cast<const z64 *>(dLU);
     z64 *Xz = reinterpret_cast<z64 *>(dX);
-    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, b, 0, nblk, true, Li.as<z64>(), nblk * b * b);
-    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, b, 0, nblk, false, Ui.as<z64>(), nblk * b * b);
+    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, 64, 0, nblk, true, Li.as<z64>(), ist);
+    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, 64, 0, nblk, false, Ui.as<z64>(), ist);
     feast::perm_from_ipiv(s, dPiv, perm.as<int32_t>(), n, batch);
     if (trans == 0) {
       feast::gather_rows<z64>(s, Xz, ldx, strideX, perm.as<int32_t>(), n, nrhs, batch, T.as<z64>(),
                               nrhs, n * nrhs);
-      trsolve<z64>(s, F, ldm, strideM, batch, n, b, Li.as<z64>(), Ui.as<z64>(), nblk * b * b,
-                   T.as<z64>(), nrhs, nrhs, n * nrhs, 0);
+      trsolve<z64>(s, F, ldm, strideM, batch, n, Li.as<z64>(), Ui.as<z64>(), ist, T.as<z64>(),
+                   nrhs, nrhs, n * nrhs, 0);
       for (int32_t i = 0; i < batch; ++i)
         feast::copy_block_z(s, T.as<z64>() + i * n * nrhs, nrhs, n, nrhs, Xz + i * strideX, ldx);
     } else {
       for (int32_t i = 0; i < batch; ++i)
         feast::copy_block_z(s, Xz + i * strideX, ldx, n, nrhs, T.as<z64>() + i * n * nrhs, nrhs);
-      trsolve<z64>(s, F, ldm, strideM, batch, n, b, Li.as<z64>(), Ui.as<z64>(), nblk * b * b,
-                   T.as<z64>(), nrhs, nrhs, n * nrhs, 2);
+      trsolve<z64>(s, F, ldm, strideM, batch, n, Li.as<z64>(), Ui.as<z64>(), ist, T.as<z64>(),
+                   nrhs, nrhs, n * nrhs, 2);
       feast::scatter_rows<z64>(s, T.as<z64>(), nrhs, n * nrhs, perm.as<int32_t>(), n, nrhs, batch,
                                Xz, ldx, strideX);
     }

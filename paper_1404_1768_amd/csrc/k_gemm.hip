@@ -50,7 +50,11 @@ template <> struct mfma_ops<c64> {
 
 template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
 
-template <typename T, int BM, int BN, int TA>
+// SUB = true computes C -= op(A) B exactly: the accumulators start from C (loaded
+// before the K loop, so its latency overlaps the first operand loads) and the
+// MFMAs use -A; the epilogue is then a plain store.  SUB = false is the general
+// C = alpha op(A) B + beta C with the C read in the epilogue.
+template <typename T, int BM, int BN, int TA, bool SUB>
 __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
   using Ops = mfma_ops<T>;
   using real = typename Ops::real;
@@ -75,8 +79,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
   const int64_t kbeg = split * d.kchunk;
   const int64_t kend = (kbeg + d.kchunk < d.K) ? kbeg + d.kchunk : d.K;
 
-  const T *__restrict__ A = d.A + bidx * d.sA;
-  const T *__restrict__ B = d.B + bidx * d.sB;
+  const T *A = d.A + bidx * d.sA;
+  const T *B = d.B + bidx * d.sB;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -136,6 +140,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
   };
 
   acc_t cr[FM][FN], ci[FM][FN];
+  T *C = d.C + bidx * d.sC;
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -144,6 +149,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
       for (int r = 0; r < 4; ++r) {
         cr[a][b][r] = 0;
         ci[a][b][r] = 0;
+        if (SUB) {
+          const int64_t row = m0 + wm * WM + a * 16 + Ops::out_row(lane, r);
+          const int64_t col = n0 + wn * WN + b * 16 + (lane & 15);
+          if (row < d.M && col < d.N) {
+            const T o = C[row * d.ldc + col];
+            cr[a][b][r] = o.x;
+            ci[a][b][r] = o.y;
+          }
+        }
       }
 
   const int nk = static_cast<int>((kend - kbeg + BK - 1) / BK);
@@ -163,6 +177,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
       for (int a = 0; a < FM; ++a) {
         ar[a] = sAr[buf][kk * 4 + krow][wm * WM + a * 16 + col16];
         ai[a] = sAi[buf][kk * 4 + krow][wm * WM + a * 16 + col16];
+        if (SUB) {  // accumulate (-A) B:  Cr += (-Ar) Br - (-Ai) Bi, Ci += (-Ar) Bi + (-Ai) Br
+          ar[a] = -ar[a];
+          ai[a] = -ai[a];
+        }
         nai[a] = -ai[a];
       }
 #pragma unroll
@@ -188,8 +206,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
   const real alr = static_cast<real>(d.alpha.x), ali = static_cast<real>(d.alpha.y);
   const real ber = static_cast<real>(d.beta.x), bei = static_cast<real>(d.beta.y);
   const bool use_beta = (ber != 0 || bei != 0);
-  T *__restrict__ C = d.C + bidx * d.sC;
-  T *__restrict__ W = (d.splits > 1) ? d.work + (split * d.batch + bidx) * d.M * d.N : nullptr;
+  T *W = (d.splits > 1) ? d.work + (split * d.batch + bidx) * d.M * d.N : nullptr;
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -201,6 +218,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
         if (row < d.M && col < d.N) {
           const real xr = cr[a][b][r], xi = ci[a][b][r];
           T v;
+          if (SUB) {
+            v.x = xr;
+            v.y = xi;
+            C[row * d.ldc + col] = v;
+            continue;
+          }
           v.x = alr * xr - ali * xi;
           v.y = alr * xi + ali * xr;
           if (W) {
@@ -248,12 +271,21 @@ void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta) {
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
   const int64_t total = tiles * d.batch * d.splits;
   const int64_t padded = (total + 7) / 8 * 8;
-  if (ta == 0)
-    hipLaunchKernelGGL((k_gemm<T, BM, BN, 0>), dim3(static_cast<unsigned>(padded)), dim3(256), 0,
-                       s, d, padded);
-  else
-    hipLaunchKernelGGL((k_gemm<T, BM, BN, 2>), dim3(static_cast<unsigned>(padded)), dim3(256), 0,
-                       s, d, padded);
+  const dim3 grid(static_cast<unsigned>(padded));
+  // C -= op(A) B is recognised from alpha = -1, beta = 1 without split-K
+  const bool sub = d.splits == 1 && d.alpha.x == -1.0 && d.alpha.y == 0.0 && d.beta.x == 1.0 &&
+                   d.beta.y == 0.0;
+  if (ta == 0) {
+    if (sub)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true>), grid, dim3(256), 0, s, d, padded);
+    else
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, false>), grid, dim3(256), 0, s, d, padded);
+  } else {
+    if (sub)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 2, true>), grid, dim3(256), 0, s, d, padded);
+    else
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 2, false>), grid, dim3(256), 0, s, d, padded);
+  }
 }
 
 template <typename T>

@@ -297,6 +297,75 @@ __global__ __launch_bounds__(1024) void k_trinv_upper(z64 *__restrict__ R, int64
   }
 }
 
+// A += shift_rel * trace(A) on the diagonal (t x t, one workgroup).
+__global__ __launch_bounds__(256) void k_add_shift(z64 *__restrict__ G, int64_t t, double shift_rel) {
+  __shared__ double red[256];
+  double tr = 0.0;
+  for (int64_t i = threadIdx.x; i < t; i += 256) tr += G[i * t + i].x;
+  red[threadIdx.x] = tr;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double sh = shift_rel * red[0];
+  for (int64_t i = threadIdx.x; i < t; i += 256) G[i * t + i].x += sh;
+}
+
+// Cholesky of one jb x jb (jb <= 64) Hermitian diagonal block held in LDS:
+// upper triangle in, R (upper) out, strict lower part of the block zeroed.
+__global__ __launch_bounds__(256) void k_chol_block(z64 *__restrict__ G, int64_t ld, int jb,
+                                                    int col0, int32_t *__restrict__ flag) {
+  __shared__ z64 S[64][65];
+  __shared__ double s_d;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int i = e / jb, j = e % jb;
+    S[i][j] = G[i * ld + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < jb; ++k) {
+    if (tid == 0) {
+      const double d = S[k][k].x;
+      if (!(d > 0.0)) {
+        if (flag[0] == 0) flag[0] = col0 + k + 1;
+        s_d = 1.0;  // keep going with a unit pivot; the caller reports the failure
+      } else {
+        s_d = sqrt(d);
+      }
+      S[k][k] = make_double2(s_d, 0.0);
+    }
+    __syncthreads();
+    const double d = s_d;
+    for (int j = k + 1 + tid; j < jb; j += 256) {
+      S[k][j].x /= d;
+      S[k][j].y /= d;
+    }
+    __syncthreads();
+    const int m = jb - k - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j < i) continue;
+      const z64 a = S[k][i], b = S[k][j];
+      S[i][j].x -= a.x * b.x + a.y * b.y;
+      S[i][j].y -= a.x * b.y - a.y * b.x;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int i = e / jb, j = e % jb;
+    G[i * ld + j] = (j >= i) ? S[i][j] : make_double2(0.0, 0.0);
+  }
+}
+
+// Strict lower triangle of a t x t matrix set to zero; optionally the whole matrix.
+__global__ __launch_bounds__(256) void k_zero_lower(z64 *__restrict__ X, int64_t t, int all) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= t * t) return;
+  const int64_t i = e / t, j = e % t;
+  if (all || j < i) X[e] = make_double2(0.0, 0.0);
+}
+
 __global__ __launch_bounds__(256) void k_copy_t(const z64 *__restrict__ X, z64 *__restrict__ R,
                                                 int64_t count) {
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
@@ -448,7 +517,7 @@ void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, d
 
 void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
                   int32_t batch, double *part, double *out) {
-  const int blocks = 64;
+  const int blocks = (batch == 1 && n * m > (1 << 22)) ? 1024 : 64;
   hipLaunchKernelGGL(k_fro_part, dim3(blocks, batch), dim3(256), 0, s, X, ld, sX, n, m, part);
   hipLaunchKernelGGL(k_sum_rows, dim3(static_cast<unsigned>((batch + 255) / 256)), dim3(256), 0, s,
                      part, static_cast<int64_t>(blocks), static_cast<int64_t>(batch), out);
@@ -456,6 +525,19 @@ void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n
 
 void cholesky_upper(hipStream_t s, z64 *G, int64_t t, double shift, int32_t *flag) {
   hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, G, t, shift, flag);
+}
+
+void add_diag_shift(hipStream_t s, z64 *G, int64_t t, double shift_rel) {
+  hipLaunchKernelGGL(k_add_shift, dim3(1), dim3(256), 0, s, G, t, shift_rel);
+}
+
+void chol_block(hipStream_t s, z64 *G, int64_t ld, int jb, int col0, int32_t *flag) {
+  hipLaunchKernelGGL(k_chol_block, dim3(1), dim3(256), 0, s, G, ld, jb, col0, flag);
+}
+
+void zero_lower(hipStream_t s, z64 *X, int64_t t, bool all) {
+  hipLaunchKernelGGL(k_zero_lower, dim3(static_cast<unsigned>((t * t + 255) / 256)), dim3(256), 0,
+                     s, X, t, all ? 1 : 0);
 }
 
 void trinv_upper(hipStream_t s, z64 *R, int64_t t) {

@@ -122,7 +122,7 @@ void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, d
                 double *out);
 
 // Frobenius-norm-squared per batch: out[b] = sum |X_b|^2 (n x m blocks);
-// part: workspace of 64 * batch doubles.
+// part: workspace of max(64 * batch, 1024) doubles.
 void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
                   int32_t batch, double *part, double *out);
 
@@ -133,6 +133,13 @@ void cholesky_upper(hipStream_t s, z64 *G, int64_t t, double shift_rel, int32_t 
 // Inverse of the t x t upper-triangular R in place; R must hold 2 t^2 entries
 // (the second half is scratch).
 void trinv_upper(hipStream_t s, z64 *R, int64_t t);
+// Blocked pieces: diagonal += shift_rel * trace; Cholesky of one jb x jb (<= 64)
+// diagonal block inside a matrix of leading dimension ld (flag[0] = 1 + the first
+// non-positive pivot column, numbered from col0); zero the strict lower triangle
+// (or everything) of a t x t matrix.
+void add_diag_shift(hipStream_t s, z64 *G, int64_t t, double shift_rel);
+void chol_block(hipStream_t s, z64 *G, int64_t ld, int jb, int col0, int32_t *flag);
+void zero_lower(hipStream_t s, z64 *X, int64_t t, bool all);
 
 // Gather columns idx[0..k) of the n x t block X into Y (n x k) and normalise each
 // to unit 2-norm with its largest-modulus entry real positive.

@@ -60,7 +60,7 @@ def test_invalid_contour_rejected(bad):
 @pytest.mark.parametrize("args", [
     dict(n=0, m=1), dict(n=10, m=0), dict(n=10, m=11), dict(n=20000, m=4),
     dict(n=10, m=4, eta=0.0), dict(n=10, m=4, max_iter=0), dict(n=10, m=4, max_iter=65),
-    dict(n=10, m=4, prec=7), dict(n=10, m=4, nb=48), dict(n=10, m=4, radius=0.0),
+    dict(n=10, m=4, prec=7), dict(n=10, m=4, nb=32), dict(n=10, m=4, radius=0.0),
 ])
 def test_plan_create_validates_before_device_work(args):
     kw = dict(center=0.0, radius=1.0, nodes=16)
