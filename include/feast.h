@@ -80,6 +80,9 @@ typedef struct {
   int32_t nb;          /* LU panel width: 64 or 128, 0 = automatic (128) */
   int32_t profile;     /* 1: time the LU trailing-update GEMM launches with HIP events on
                           the plan's stream (reported in feast_info); default 0 */
+  int32_t side_cus;    /* compute units reserved for the look-ahead panel factorisation
+                          (CU-masked stream; the trailing updates get the others);
+                          0 = no reservation (default 32) */
 } feast_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -159,6 +162,33 @@ int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z 
                 int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *hLambda,
                 feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, double *err,
                 int32_t *flag, feast_info *info);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint form (derivatives of the eigenvalues found by feast_solve)
+ * ------------------------------------------------------------------------- */
+
+/* Left eigenvectors y_i (y_i^* A = lambda_i y_i^* B) of the s right eigenvectors
+ * X (device, n x s) found inside the contour, from the adjoint of the filter of
+ * eq. (8-4) on the plan's cached factors:
+ *   W <- sum_j conj(w_j) (z_j B - A)^{-*} W,  W_0 = B X,   `sweeps` times
+ * (each sweep damps the components outside the contour by the filter values
+ * there), then Y = W (W^* B X)^{-*}, so that Y^* B X = I (y_i^* B x_i = 1).
+ * The (z_j B - A)^* solves reuse the forward factors: U^* first, then L^*, then
+ * the transposed row permutation.  FP64 plans only.  dY: n x s (device).
+ * Synchronises the stream. */
+int feast_left_eigvecs(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
+                       int64_t ldb, const feast_z *dX, int64_t ldx, int64_t s, int32_t sweeps,
+                       feast_z *dY, int64_t ldy);
+
+/* Gradients of a real loss L of the eigenvalues lambda_i (first-order
+ * perturbation: d lambda_i = y_i^* (dA - lambda_i dB) x_i with y_i^* B x_i = 1).
+ * hG[i] = dL/d conj(lambda_i) in PyTorch's convention (for L = sum |lambda_i|^2,
+ * hG[i] = 2 lambda_i).  Outputs (device, n x n, overwritten):
+ *   dGA = sum_i hG[i] y_i x_i^*,   dGB = -sum_i hG[i] conj(lambda_i) y_i x_i^*.
+ * Synchronises the stream. */
+int feast_eig_grad(feast_plan *plan, const feast_z *dX, int64_t ldx, const feast_z *dY,
+                   int64_t ldy, int64_t s, const feast_z *hLam, const feast_z *hG, feast_z *dGA,
+                   int64_t ldga, feast_z *dGB, int64_t ldgb);
 
 /* Message describing the last failure of this plan ("" if none). */
 const char *feast_last_error(const feast_plan *plan);

@@ -36,7 +36,7 @@ EXPORTED = [
     "feast_opts_default", "feast_nodes", "feast_plan_create", "feast_plan_destroy",
     "feast_plan_invalidate", "feast_filter", "feast_project", "feast_solve", "feast_last_error",
     "feast_reduced_eig", "feast_stop_rule", "feast_zgetrf_batched", "feast_zgetrs_batched",
-    "feast_zgemm_batched", "feast_version",
+    "feast_zgemm_batched", "feast_version", "feast_left_eigvecs", "feast_eig_grad",
 ]
 
 
@@ -52,7 +52,7 @@ class Contour(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("eta", C.c_double), ("max_iter", C.c_int32),
                 ("prec", C.c_int32), ("refine_tol", C.c_double), ("max_sweeps", C.c_int32),
-                ("nb", C.c_int32), ("profile", C.c_int32)]
+                ("nb", C.c_int32), ("profile", C.c_int32), ("side_cus", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -105,6 +105,8 @@ def load(path: str = LIB_PATH):
     lib.feast_zgetrs_batched.argtypes = [i64, i64, i32, P, i64, i64, P, P, i64, i64, i32, P]
     lib.feast_zgemm_batched.argtypes = [i32, i64, i64, i64, FeastZ, P, i64, i64, P, i64, i64,
                                         FeastZ, P, i64, i64, i32, P]
+    lib.feast_left_eigvecs.argtypes = [P, P, i64, P, i64, P, i64, i64, i32, P, i64]
+    lib.feast_eig_grad.argtypes = [P, P, i64, P, i64, i64, pz, pz, P, i64, P, i64]
     for name in EXPORTED:
         if name not in ("feast_opts_default", "feast_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -219,7 +221,8 @@ class Plan:
     def __init__(self, n: int, m: int, center: complex, radius: float, nodes: int,
                  rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
                  max_iter: int = 20, prec: int = FP64, refine_tol: Optional[float] = None,
-                 max_sweeps: int = 6, nb: int = 0, profile: bool = False, stream=None):
+                 max_sweeps: int = 6, nb: int = 0, profile: bool = False,
+                 side_cus: Optional[int] = None, stream=None):
         self.lib = load()
         self.n, self.m = int(n), int(m)
         self.contour = contour(center, radius, nodes, rule)
@@ -227,6 +230,8 @@ class Plan:
         self.opts.eps, self.opts.eta, self.opts.max_iter = float(eps), float(eta), int(max_iter)
         self.opts.prec, self.opts.max_sweeps, self.opts.nb = int(prec), int(max_sweeps), int(nb)
         self.opts.profile = 1 if profile else 0
+        if side_cus is not None:
+            self.opts.side_cus = int(side_cus)
         if refine_tol is not None:
             self.opts.refine_tol = float(refine_tol)
         self._stream_obj = stream
@@ -324,6 +329,81 @@ class Plan:
                    "ritz": info.t_ritz_ms, "total": info.t_total_ms},
             status=rc, lu_gemm={"launches": info.lu_gemm_launches, "ms": info.lu_gemm_ms,
                                 "flops": info.lu_gemm_flops})
+
+
+    # -- adjoint form ------------------------------------------------------
+    def left_eigvecs(self, A, B, X, sweeps: int = 3):
+        """Left eigenvectors Y (n x s) with Y^* B X = I from the adjoint filter."""
+        import torch
+        n = self.n
+        pa, lda = _dev(A, n, n, "A")
+        pb, ldb = _dev(B, n, n, "B")
+        X = X.contiguous()
+        s = X.shape[1]
+        px, ldx = _dev(X, n, s, "X")
+        Y = torch.empty((n, s), dtype=torch.complex128, device=X.device)
+        rc = self.lib.feast_left_eigvecs(self._h, pa, lda, pb, ldb, px, ldx, s, int(sweeps),
+                                         C.c_void_p(Y.data_ptr()), s)
+        self._check(rc, "feast_left_eigvecs")
+        return Y
+
+    def eig_grad(self, X, Y, lam, g):
+        """(dL/dA, dL/dB) for dL/d conj(lambda_i) = g_i (PyTorch convention)."""
+        import torch
+        n = self.n
+        X = X.contiguous()
+        Y = Y.contiguous()
+        s = X.shape[1]
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128).reshape(s))
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.complex128).reshape(s))
+        GA = torch.empty((n, n), dtype=torch.complex128, device=X.device)
+        GB = torch.empty((n, n), dtype=torch.complex128, device=X.device)
+        rc = self.lib.feast_eig_grad(self._h, C.c_void_p(X.data_ptr()), s, C.c_void_p(Y.data_ptr()),
+                                     s, s, _zptr(lam), _zptr(g), C.c_void_p(GA.data_ptr()), n,
+                                     C.c_void_p(GB.data_ptr()), n)
+        self._check(rc, "feast_eig_grad")
+        return GA, GB
+
+
+def _feast_eig_function():
+    import torch
+
+    class FeastEig(torch.autograd.Function):
+        """Eigenvalues inside the contour as a differentiable function of (A, B).
+
+        Forward: Algorithm 5 (``feast_solve``).  Backward: left eigenvectors from
+        the adjoint filter on the forward LU factors (``feast_left_eigvecs``) and
+        the rank-s gradient assembly (``feast_eig_grad``)."""
+
+        @staticmethod
+        def forward(ctx, A, B, V, plan, sweeps):
+            r = plan.solve(A, B, V)
+            ctx.plan, ctx.sweeps = plan, sweeps
+            ctx.X = r.X.contiguous().clone()
+            ctx.lam = r.lam.copy()
+            ctx.save_for_backward(A, B)
+            ctx.result = r
+            return torch.from_numpy(r.lam.copy()).to(A.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            A, B = ctx.saved_tensors
+            Y = ctx.plan.left_eigvecs(A, B, ctx.X, ctx.sweeps)
+            GA, GB = ctx.plan.eig_grad(ctx.X, Y, ctx.lam, g.detach().cpu().numpy())
+            return GA, GB, None, None, None
+
+    return FeastEig
+
+
+_FEAST_EIG = None
+
+
+def feast_eig(A, B, V, plan: "Plan", sweeps: int = 3):
+    """Differentiable eigenvalues of (A, B) inside the plan's contour."""
+    global _FEAST_EIG
+    if _FEAST_EIG is None:
+        _FEAST_EIG = _feast_eig_function()
+    return _FEAST_EIG.apply(A, B, V, plan, sweeps)
 
 
 # Module-level functions with the C names.

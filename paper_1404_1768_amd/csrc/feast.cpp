@@ -90,7 +90,7 @@ struct feast_plan {
   int nb = 64;
   int64_t nblk = 0;
   std::vector<cd> hz, hw;
-  DevBuf dz, dw;
+  DevBuf dz, dw, dwc;  // nodes, weights, conjugated weights
   // cached factors
   bool factored = false;
   const void *fA = nullptr, *fB = nullptr;
@@ -99,13 +99,16 @@ struct feast_plan {
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
   DevBuf R, Y, T1, T2, Yc, W, G, dinv, splitws, part, nrm, flag, small;
+  DevBuf adj, adj_piv, adj_info, adj_inv;  // adjoint solves (allocated on first use)
   std::string err;
   int last_sweeps = 0;       // mixed form: sweeps of the last filter
   double last_be = 0.0;      // mixed form: worst node backward error of the last filter
   bool stagnated = false;    // mixed form: the last filter missed its target
   // opts.profile: events around the LU trailing-update GEMMs
   std::vector<hipEvent_t> ev;
-  hipStream_t side = nullptr;                 // look-ahead panel stream
+  hipStream_t side = nullptr;                 // look-ahead panel stream (CU-masked if asked)
+  hipStream_t lu_main = nullptr;              // trailing updates when the side stream is masked
+  hipStream_t aux = nullptr;                  // Ritz vectors/residuals overlapping a filter
   hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
   int prof_launches = 0;
   double prof_ms = 0.0, prof_flops = 0.0;
@@ -360,16 +363,28 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     }
     prof.ev = &p->ev;
   }
+  // the factorisation runs on lu_main (the CUs not reserved for panels) when
+  // the side stream is CU-masked, ordered after the caller's stream
+  hipStream_t sl = p->lu_main ? p->lu_main : s;
+  if (sl != s) {
+    HIPCHK(hipEventRecord(p->ev_cols, s));
+    HIPCHK(hipStreamWaitEvent(sl, p->ev_cols, 0));
+  }
+  const LuStreams lst{sl, p->side, p->ev_cols, p->ev_panel};
   if (p->mixed()) {
-    feast::shift_assemble_c(s, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
-    lu_batched<c64>(LuStreams{s, p->side, p->ev_cols, p->ev_panel}, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
+    feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
+    lu_batched<c64>(lst, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<c64>(), p->Uinv.as<c64>(), p->istride(),
                     &prof);
   } else {
-    feast::shift_assemble_z(s, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<z64>(), n, n * n);
-    lu_batched<z64>(LuStreams{s, p->side, p->ev_cols, p->ev_panel}, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
+    feast::shift_assemble_z(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<z64>(), n, n * n);
+    lu_batched<z64>(lst, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<z64>(), p->Uinv.as<z64>(), p->istride(),
                     &prof);
+  }
+  if (sl != s) {
+    HIPCHK(hipEventRecord(p->ev_panel, sl));
+    HIPCHK(hipStreamWaitEvent(s, p->ev_panel, 0));
   }
   feast::perm_from_ipiv(s, p->piv.as<int32_t>(), p->perm.as<int32_t>(), n, N);
   double *nrm = p->nrm.as<double>();
@@ -660,6 +675,7 @@ void feast_opts_default(feast_opts *o) {
   o->max_sweeps = 6;
   o->nb = 0;
   o->profile = 0;
+  o->side_cus = 32;
 }
 
 int feast_nodes(const feast_contour *c, feast_z *hz, feast_z *hw) {
@@ -707,7 +723,7 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
   if (n < 1 || n > 16384 || m < 1 || m > n || bad_contour(c)) return FEAST_EINVAL;
   if (!(opts.eta > 0.0) || !(opts.eps >= 0.0) || opts.max_iter < 1 ||
       opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
-      opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) ||
+      opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) || opts.side_cus < 0 ||
       (opts.nb != 0 && opts.nb != 64 && opts.nb != 128))
     return FEAST_EINVAL;
   feast_plan *p = nullptr;
@@ -731,10 +747,35 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
   const int rc = guarded(p, [&]() {
     p->dz.alloc(sizeof(z64) * p->N);
     p->dw.alloc(sizeof(z64) * p->N);
+    p->dwc.alloc(sizeof(z64) * p->N);
+    std::vector<cd> wc(p->N);
+    for (int j = 0; j < p->N; ++j) wc[j] = std::conj(p->hw[j]);
     HIPCHK(hipMemcpy(p->dz.p, p->hz.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->dw.p, p->hw.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(p->dwc.p, wc.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
     ensure_workspace(p);
-    HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (opts.side_cus > 0 && opts.side_cus < ncu) {
+      // reserve side_cus compute units, spread evenly, for the panel stream
+      const int words = (ncu + 31) / 32, stride = ncu / opts.side_cus;
+      std::vector<uint32_t> side_mask(words, 0u), main_mask(words, 0u);
+      int taken = 0;
+      for (int i = 0; i < ncu; ++i) {
+        if (i % stride == 0 && taken < opts.side_cus) {
+          side_mask[i / 32] |= 1u << (i % 32);
+          ++taken;
+        } else {
+          main_mask[i / 32] |= 1u << (i % 32);
+        }
+      }
+      HIPCHK(hipExtStreamCreateWithCUMask(&p->side, words, side_mask.data()));
+      HIPCHK(hipExtStreamCreateWithCUMask(&p->lu_main, words, main_mask.data()));
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    }
     HIPCHK(hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming));
     return FEAST_OK;
@@ -751,13 +792,14 @@ int feast_plan_destroy(feast_plan *p) {
   if (!p) return FEAST_OK;
   if (p->s) (void)hipStreamSynchronize(p->s);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-  if (p->side) {
-    (void)hipStreamSynchronize(p->side);
-    (void)hipStreamDestroy(p->side);
-  }
+  for (hipStream_t st : {p->side, p->lu_main, p->aux})
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
   if (p->ev_cols) (void)hipEventDestroy(p->ev_cols);
   if (p->ev_panel) (void)hipEventDestroy(p->ev_panel);
-  for (DevBuf *b : {&p->dz, &p->dw, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->R,
+  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->R,
                     &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->dinv, &p->splitws, &p->part, &p->nrm,
                     &p->flag, &p->small})
     b->release();
@@ -820,7 +862,7 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
   return guarded(p, [&]() -> int {
     const int64_t n = p->n, m = p->m;
     hipStream_t s = p->s;       // filters and projections
-    hipStream_t s2 = p->side;   // Ritz vectors and residuals (overlap with the next filter)
+    hipStream_t s2 = p->aux;    // Ritz vectors and residuals (overlap with the next filter)
     const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
     const z64 *V = reinterpret_cast<const z64 *>(dV);
     const cd gamma(p->c.center.re, p->c.center.im);
@@ -1010,6 +1052,118 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
     inf.lu_gemm_flops = p->prof_flops;
     if (info) *info = inf;
     return status;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint form: left eigenvectors on the cached factors and eigenvalue gradients
+// ---------------------------------------------------------------------------
+
+int feast_left_eigvecs(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
+                       int64_t ldb, const feast_z *dX, int64_t ldx, int64_t scnt, int32_t sweeps,
+                       feast_z *dY, int64_t ldy) {
+  if (!p) return FEAST_EINVAL;
+  if (!dA || !dB || !dX || !dY || scnt < 1 || scnt > p->m || sweeps < 1 || sweeps > 16 ||
+      lda < p->n || ldb < p->n || ldx < scnt || ldy < scnt)
+    return fail(p, FEAST_EINVAL, "feast_left_eigvecs: bad argument");
+  if (p->mixed())
+    return fail(p, FEAST_EINVAL, "feast_left_eigvecs needs an FP64 plan");
+  p->err.clear();
+  return guarded(p, [&]() -> int {
+    const int64_t n = p->n, sc = scnt;
+    const int N = p->N;
+    hipStream_t s = p->s;
+    const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
+    const z64 *X = reinterpret_cast<const z64 *>(dX);
+    const int st = ensure_factored(p, A, lda, B, ldb);
+    if (st != FEAST_OK) return st;
+    const int64_t ldw = static_cast<int64_t>(N) * sc;
+    p->adj.alloc(sizeof(z64) * n * ldw);
+    z64 *Y = p->Y.as<z64>(), *Adj = p->adj.as<z64>();
+    z64 *G = p->wblk(feast_plan::W_X), *W = p->wblk(feast_plan::W_AX), *BX = p->wblk(feast_plan::W_BX);
+    // start block B X: its filtered image spans the left eigenvectors (rows of T in
+    // the Weierstrass form) of the eigenvalues inside the contour
+    gemm_t<z64>(s, 0, n, sc, n, zc(1.0), B, ldb, 0, X, ldx, 0, zc(0.0), BX, sc, 0, 1);
+    feast::copy_block_z(s, BX, sc, n, sc, G, sc);
+    for (int k = 0; k < sweeps; ++k) {
+      // W = sum_j conj(w_j) (z_j B - A)^{-*} G with the cached factors:
+      // (z_j B - A)^* = U^* L^* P, so solve with U^*, then L^*, then undo P
+      feast::bcast_cols(s, G, sc, n, sc, N, Y, ldw);
+      trsolve<z64>(s, p->F.as<z64>(), n, p->fstride(), N, n, p->Linv.as<z64>(), p->Uinv.as<z64>(),
+                   p->istride(), Y, sc, ldw, sc, 2);
+      feast::scatter_rows<z64>(s, Y, ldw, sc, p->perm.as<int32_t>(), n, sc, N, Adj, ldw, sc);
+      feast::weighted_sum(s, Adj, ldw, sc, p->dwc.as<z64>(), N, n, sc, W, sc);
+      if (k + 1 < sweeps) feast::copy_block_z(s, W, sc, n, sc, G, sc);
+    }
+    // Y = W (W^* B X)^{-*}, so that Y^* B X = I
+    z64 *S = p->gblk(feast_plan::G_AT), *T = p->gblk(feast_plan::G_BT), *Z = p->gblk(feast_plan::G_YS);
+    gemm_t<z64>(s, 2, sc, sc, n, zc(1.0), W, sc, 0, BX, sc, 0, zc(0.0), S, sc, 0, 1,
+                p->splitws.as<z64>(), splitws_elems(p));
+    feast::conj_transpose(s, S, sc, sc, sc, T, sc);
+    const int64_t nb64 = (sc + 63) / 64;
+    p->adj_piv.alloc(sizeof(int32_t) * sc * 2);
+    p->adj_info.alloc(sizeof(int32_t) * 4);
+    p->adj_inv.alloc(sizeof(z64) * 2 * nb64 * 64 * 64);
+    int32_t *piv = p->adj_piv.as<int32_t>(), *perm = piv + sc;
+    z64 *Li = p->adj_inv.as<z64>(), *Ui = Li + nb64 * 64 * 64;
+    lu_batched<z64>(LuStreams{s, nullptr, nullptr, nullptr}, T, sc, 0, 1, sc, 128, piv,
+                    p->adj_info.as<int32_t>(), Li, Ui, nb64 * 64 * 64);
+    feast::perm_from_ipiv(s, piv, perm, sc, 1);
+    feast::identity(s, S, sc);
+    feast::gather_rows<z64>(s, S, sc, 0, perm, sc, sc, 1, Z, sc, 0);
+    trsolve<z64>(s, T, sc, 0, 1, sc, Li, Ui, nb64 * 64 * 64, Z, sc, sc, 0, 0);
+    gemm_t<z64>(s, 0, n, sc, sc, zc(1.0), W, sc, 0, Z, sc, 0, zc(0.0), reinterpret_cast<z64 *>(dY),
+                ldy, 0, 1);
+    int32_t hinfo = 0;
+    HIPCHK(hipMemcpyAsync(&hinfo, p->adj_info.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    if (hinfo != 0) return fail(p, FEAST_ENUMERIC, "W^* B X is singular: left basis lost rank");
+    return FEAST_OK;
+  });
+}
+
+int feast_eig_grad(feast_plan *p, const feast_z *dX, int64_t ldx, const feast_z *dY, int64_t ldy,
+                   int64_t scnt, const feast_z *hLam, const feast_z *hG, feast_z *dGA, int64_t ldga,
+                   feast_z *dGB, int64_t ldgb) {
+  if (!p) return FEAST_EINVAL;
+  if (!dX || !dY || !hLam || !hG || !dGA || !dGB || scnt < 0 || scnt > p->m || ldx < scnt ||
+      ldy < scnt || ldga < p->n || ldgb < p->n)
+    return fail(p, FEAST_EINVAL, "feast_eig_grad: bad argument");
+  p->err.clear();
+  return guarded(p, [&]() -> int {
+    const int64_t n = p->n, sc = scnt;
+    hipStream_t s = p->s;
+    if (sc == 0) {
+      gemm_t<z64>(s, 0, n, n, 0, zc(0.0), nullptr, 1, 0, nullptr, n, 0, zc(0.0),
+                  reinterpret_cast<z64 *>(dGA), ldga, 0, 1);
+      gemm_t<z64>(s, 0, n, n, 0, zc(0.0), nullptr, 1, 0, nullptr, n, 0, zc(0.0),
+                  reinterpret_cast<z64 *>(dGB), ldgb, 0, 1);
+      HIPCHK(hipStreamSynchronize(s));
+      return FEAST_OK;
+    }
+    std::vector<z64> d(2 * sc);
+    for (int64_t i = 0; i < sc; ++i) {
+      const cd g(hG[i].re, hG[i].im), l(hLam[i].re, hLam[i].im);
+      const cd gb = -g * std::conj(l);
+      d[i] = zc(g.real(), g.imag());
+      d[sc + i] = zc(gb.real(), gb.imag());
+    }
+    z64 *dd = p->small.as<z64>();
+    z64 *XH = p->wblk(feast_plan::W_X), *Yg = p->wblk(feast_plan::W_AX), *Yb = p->wblk(feast_plan::W_BX);
+    HIPCHK(hipMemcpyAsync(dd, d.data(), sizeof(z64) * 2 * sc, hipMemcpyHostToDevice, s));
+    feast::conj_transpose(s, reinterpret_cast<const z64 *>(dX), ldx, n, sc, XH, n);
+    feast::copy_block_z(s, reinterpret_cast<const z64 *>(dY), ldy, n, sc, Yg, sc);
+    feast::copy_block_z(s, reinterpret_cast<const z64 *>(dY), ldy, n, sc, Yb, sc);
+    feast::scale_cols(s, Yg, sc, n, sc, dd);
+    feast::scale_cols(s, Yb, sc, n, sc, dd + sc);
+    gemm_t<z64>(s, 0, n, n, sc, zc(1.0), Yg, sc, 0, XH, n, 0, zc(0.0), reinterpret_cast<z64 *>(dGA),
+                ldga, 0, 1);
+    gemm_t<z64>(s, 0, n, n, sc, zc(1.0), Yb, sc, 0, XH, n, 0, zc(0.0), reinterpret_cast<z64 *>(dGB),
+                ldgb, 0, 1);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return FEAST_OK;
   });
 }
 

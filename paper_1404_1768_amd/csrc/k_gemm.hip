@@ -54,12 +54,12 @@ template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
 // before the K loop, so its latency overlaps the first operand loads) and the
 // MFMAs use -A; the epilogue is then a plain store.  SUB = false is the general
 // C = alpha op(A) B + beta C with the C read in the epilogue.
-template <typename T, int BM, int BN, int TA, bool SUB>
+template <typename T, int BM, int BN, int TA, bool SUB, int BK>
 __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
   using Ops = mfma_ops<T>;
   using real = typename Ops::real;
   using acc_t = typename Ops::acc_t;
-  constexpr int BK = 16;
+  static_assert(BK == 8 || BK == 16, "BK");
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int PA = BM + 2, PB = BN + 2;
@@ -90,11 +90,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
 
   auto gload = [&](int64_t k0) {
     if (TA == 0) {
-      // A is M x K row-major: 16 lanes read one row's 16 consecutive elements
-      const int kk = tid & 15, rr = tid >> 4;
+      // A is M x K row-major: BK lanes read one row's BK consecutive elements
+      const int kk = tid % BK, rr = tid / BK;
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
-        const int64_t r = m0 + rr + 16 * i, k = k0 + kk;
+        const int64_t r = m0 + rr + (256 / BK) * i, k = k0 + kk;
         ra[i] = (r < d.M && k < kend) ? A[r * d.lda + k] : T{};
       }
     } else {
@@ -115,11 +115,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
   };
   auto sstore = [&](int buf) {
     if (TA == 0) {
-      const int kk = tid & 15, rr = tid >> 4;
+      const int kk = tid % BK, rr = tid / BK;
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
-        sAr[buf][kk][rr + 16 * i] = ra[i].x;
-        sAi[buf][kk][rr + 16 * i] = ra[i].y;
+        sAr[buf][kk][rr + (256 / BK) * i] = ra[i].x;
+        sAi[buf][kk][rr + (256 / BK) * i] = ra[i].y;
       }
     } else {
       const int rr = tid & 63, kk = tid >> 6;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
     if (kt + 1 < nk) gload(kbeg + static_cast<int64_t>(kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      real ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
+      real ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a) {
         ar[a] = sAr[buf][kk * 4 + krow][wm * WM + a * 16 + col16];
@@ -181,20 +181,26 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
           ar[a] = -ar[a];
           ai[a] = -ai[a];
         }
-        nai[a] = -ai[a];
       }
 #pragma unroll
       for (int b = 0; b < FN; ++b) {
         br[b] = sBr[buf][kk * 4 + krow][wn * WN + b * 16 + col16];
         bi[b] = sBi[buf][kk * 4 + krow][wn * WN + b * 16 + col16];
       }
+      // two sweeps over all tiles: an accumulator is reused only after every
+      // other accumulator of the wave has been issued once
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
           cr[a][b] = Ops::mma(ar[a], br[b], cr[a][b]);
           ci[a][b] = Ops::mma(ar[a], bi[b], ci[a][b]);
-          cr[a][b] = Ops::mma(nai[a], bi[b], cr[a][b]);
+        }
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          cr[a][b] = Ops::mma(-ai[a], bi[b], cr[a][b]);
           ci[a][b] = Ops::mma(ai[a], br[b], ci[a][b]);
         }
     }
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmArgs<T> d) {
   *C = v;
 }
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, int BK = 16>
 void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta) {
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
   const int64_t total = tiles * d.batch * d.splits;
@@ -277,19 +283,20 @@ void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta) {
                    d.beta.y == 0.0;
   if (ta == 0) {
     if (sub)
-      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true>), grid, dim3(256), 0, s, d, padded);
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, BK>), grid, dim3(256), 0, s, d, padded);
     else
-      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, false>), grid, dim3(256), 0, s, d, padded);
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, false, BK>), grid, dim3(256), 0, s, d, padded);
   } else {
     if (sub)
-      hipLaunchKernelGGL((k_gemm<T, BM, BN, 2, true>), grid, dim3(256), 0, s, d, padded);
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 2, true, BK>), grid, dim3(256), 0, s, d, padded);
     else
-      hipLaunchKernelGGL((k_gemm<T, BM, BN, 2, false>), grid, dim3(256), 0, s, d, padded);
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 2, false, BK>), grid, dim3(256), 0, s, d, padded);
   }
 }
 
 template <typename T>
 void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems) {
+  // (cfg may be upgraded to GEMM_BIG below)
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   if (d.K <= 0) {
     // C = beta C: a GEMM with an empty K range does exactly that.
@@ -297,7 +304,9 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
   }
   d.splits = 1;
   d.kchunk = d.K > 0 ? d.K : 1;
-  const int BM = (cfg == GEMM_TALL) ? 128 : 64;
+  // (a 128 x 128 complex64 tile measured slower than 64 x 64 in the LU update,
+  // and the FP64 one needs more than the 512 registers of a lane: not used)
+  const int BM = (cfg == GEMM_TALL || cfg == GEMM_BIG) ? 128 : 64;
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + 63) / 64);
   // Split K when the output is too small to fill the chip.
   if (d.work && d.K >= 512 && tiles * d.batch < 192) {

@@ -24,10 +24,12 @@ template <typename T> __device__ inline T czero() {
 // One workgroup of 1024 threads per matrix holds the leaf columns [c0, c0+w)
 // of rows [c0, n) in registers (thread t owns rows c0 + t + 1024 q) and
 // factors them column by column: |re|+|im| argmax over the column (wave64
-// shuffles, then across the 16 waves through LDS; ties go to the lowest row),
-// exchange of the pivot row with the diagonal row, scaling, and the rank-1
-// update of the remaining leaf columns.  The leaf's row swaps are also applied
-// to the other columns of the enclosing panel [pk0, pk0+pkb).
+// shuffles, then every thread reduces the 16 wave results from LDS; ties go to
+// the lowest row), exchange of the pivot row with the diagonal row, scaling and
+// the rank-1 update of the remaining leaf columns -- two barriers per column.
+// The leaf's row swaps are then applied to the other columns of the enclosing
+// panel [pk0, pk0+pkb) as one gather: the composed permutation of the at most
+// 2w rows involved is read in full before any of it is written.
 template <typename T, int RPT, int IB>
 __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld, int64_t stride,
                                                int64_t n, int64_t c0, int w, int64_t pk0,
@@ -38,14 +40,14 @@ __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld,
   T *M = Mall + b * stride;
   int32_t *ipiv = ipiv_all + b * n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double s_val[16];
-  __shared__ int s_idx[16];
-  __shared__ int s_piv;
-  __shared__ int s_info;
+  __shared__ double s_val[2][16];
+  __shared__ int s_idx[2][16];
   __shared__ int s_pivs[IB];
   __shared__ T s_prow[IB];
   __shared__ T s_crow[IB];
-  if (tid == 0) s_info = 0;
+  __shared__ int s_key[2 * IB], s_src[2 * IB];
+  __shared__ int s_nkey;
+  int info_local = 0;
 
   T a[RPT][IB];
 #pragma unroll
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld,
   for (int c = 0; c < IB; ++c) {
     if (c >= w) break;
     const int64_t rc = c0 + c;
-    // local argmax of |re| + |im| over owned rows >= rc
+    const int par = c & 1;
     double best = -1.0;
     int bidx = INT_MAX;
 #pragma unroll
@@ -83,29 +85,31 @@ __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld,
       }
     }
     if (lane == 0) {
-      s_val[wave] = best;
-      s_idx[wave] = bidx;
+      s_val[par][wave] = best;
+      s_idx[par][wave] = bidx;
     }
     __syncthreads();
-    if (tid == 0) {
-      double bv = s_val[0];
-      int bi = s_idx[0];
-      for (int k = 1; k < 16; ++k)
-        if (s_val[k] > bv || (s_val[k] == bv && s_idx[k] < bi)) {
-          bv = s_val[k];
-          bi = s_idx[k];
-        }
-      if (bi == INT_MAX) {  // no comparable entry (NaN column): keep the diagonal row
-        bi = static_cast<int>(rc);
-        bv = 0.0;
+    double bv = s_val[par][0];
+    int bi = s_idx[par][0];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+      const double v = s_val[par][k];
+      const int i = s_idx[par][k];
+      if (v > bv || (v == bv && i < bi)) {
+        bv = v;
+        bi = i;
       }
-      s_piv = bi;
+    }
+    if (bi == INT_MAX) {  // no comparable entry (NaN column): keep the diagonal row
+      bi = static_cast<int>(rc);
+      bv = 0.0;
+    }
+    if (bv == 0.0 && info_local == 0) info_local = static_cast<int>(rc) + 1;
+    const int64_t p = bi;
+    if (tid == 0) {
       s_pivs[c] = bi;
       ipiv[rc] = bi;
-      if (bv == 0.0 && s_info == 0) s_info = static_cast<int>(rc) + 1;
     }
-    __syncthreads();
-    const int64_t p = s_piv;
     const int64_t prel = p - c0;
     const int ptid = static_cast<int>(prel & 1023), pq = static_cast<int>(prel >> 10);
     if (tid == ptid) {
@@ -144,7 +148,6 @@ __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld,
         for (int k = c + 1; k < IB; ++k) a[q][k] = Tr::fms(a[q][k], l, s_prow[k]);
       }
     }
-    __syncthreads();
   }
 
 #pragma unroll
@@ -155,21 +158,55 @@ __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld,
       for (int c = 0; c < IB; ++c)
         if (c < w) M[r * ld + c0 + c] = a[q][c];
   }
-  // apply the leaf's swaps to the other panel columns
-  if (tid < pkb) {
-    const int64_t col = pk0 + tid;
-    if (col < c0 || col >= c0 + w) {
-      for (int c = 0; c < w; ++c) {
-        const int64_t rc = c0 + c, p = s_pivs[c];
-        if (p != rc) {
-          const T x = M[rc * ld + col];
-          M[rc * ld + col] = M[p * ld + col];
-          M[p * ld + col] = x;
-        }
+  // composed permutation of the rows touched by the leaf's swaps
+  if (tid == 0) {
+    int nk = 0;
+    for (int c = 0; c < w; ++c) {
+      const int r1 = static_cast<int>(c0) + c, r2 = s_pivs[c];
+      int i1 = -1, i2 = -1;
+      for (int k = 0; k < nk; ++k) {
+        if (s_key[k] == r1) i1 = k;
+        if (s_key[k] == r2) i2 = k;
+      }
+      if (i1 < 0) {
+        s_key[nk] = r1;
+        s_src[nk] = r1;
+        i1 = nk++;
+      }
+      if (i2 < 0) {
+        s_key[nk] = r2;
+        s_src[nk] = r2;
+        i2 = nk++;
+      }
+      const int t = s_src[i1];
+      s_src[i1] = s_src[i2];
+      s_src[i2] = t;
+    }
+    s_nkey = nk;
+  }
+  __syncthreads();
+  const int nk = s_nkey;
+  const int ncol = pkb;  // panel columns; the leaf's own columns are skipped
+  T v[2];
+  int64_t dst[2], col[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + 1024 * h;
+    dst[h] = -1;
+    if (e < ncol * nk) {
+      const int k = e / ncol;
+      col[h] = pk0 + e % ncol;
+      if ((col[h] < c0 || col[h] >= c0 + w) && s_key[k] != s_src[k]) {
+        v[h] = M[static_cast<int64_t>(s_src[k]) * ld + col[h]];
+        dst[h] = s_key[k];
       }
     }
   }
-  if (tid == 0 && s_info != 0 && info_all[b] == 0) info_all[b] = s_info;
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (dst[h] >= 0) M[dst[h] * ld + col[h]] = v[h];
+  if (tid == 0 && info_local != 0 && info_all[b] == 0) info_all[b] = info_local;
 }
 
 template <typename T>

@@ -420,7 +420,70 @@ __global__ __launch_bounds__(256) void k_gather_norm(const z64 *__restrict__ X, 
   }
 }
 
+// Y[:, j*s + c] = X[:, c] for every node j (broadcast of one block to N slots).
+__global__ __launch_bounds__(256) void k_bcast_cols(const z64 *__restrict__ X, int64_t ldx,
+                                                    int64_t n, int64_t s, int32_t N,
+                                                    z64 *__restrict__ Y, int64_t ldy) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  if (idx >= n * s * N) return;
+  const int64_t row = idx / (s * N), col = idx % (s * N);
+  Y[row * ldy + col] = X[row * ldx + col % s];
+}
+
+// Y (cols x rows) = X^* for the rows x cols block X.
+__global__ __launch_bounds__(256) void k_conj_transpose(const z64 *__restrict__ X, int64_t ldx,
+                                                        int64_t rows, int64_t cols,
+                                                        z64 *__restrict__ Y, int64_t ldy) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx / cols, j = idx % cols;
+  const z64 v = X[i * ldx + j];
+  Y[j * ldy + i] = make_double2(v.x, -v.y);
+}
+
+// X[:, c] *= d[c]
+__global__ __launch_bounds__(256) void k_scale_cols(z64 *__restrict__ X, int64_t ldx, int64_t n,
+                                                    int64_t s, const z64 *__restrict__ d) {
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  if (idx >= n * s) return;
+  const int64_t i = idx / s, c = idx % s;
+  const z64 v = X[i * ldx + c], f = d[c];
+  X[i * ldx + c] = make_double2(v.x * f.x - v.y * f.y, v.x * f.y + v.y * f.x);
+}
+
+// Identity of order t (row-major, ld t).
+__global__ __launch_bounds__(256) void k_identity(z64 *__restrict__ X, int64_t t) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= t * t) return;
+  X[e] = make_double2((e / t == e % t) ? 1.0 : 0.0, 0.0);
+}
+
 }  // namespace
+
+void bcast_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t c, int32_t N, z64 *Y,
+                int64_t ldy) {
+  const int64_t tot = n * c * N;
+  hipLaunchKernelGGL(k_bcast_cols, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s,
+                     X, ldx, n, c, N, Y, ldy);
+}
+
+void conj_transpose(hipStream_t s, const z64 *X, int64_t ldx, int64_t rows, int64_t cols, z64 *Y,
+                    int64_t ldy) {
+  const int64_t tot = rows * cols;
+  hipLaunchKernelGGL(k_conj_transpose, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0,
+                     s, X, ldx, rows, cols, Y, ldy);
+}
+
+void scale_cols(hipStream_t s, z64 *X, int64_t ldx, int64_t n, int64_t c, const z64 *d) {
+  const int64_t tot = n * c;
+  hipLaunchKernelGGL(k_scale_cols, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s,
+                     X, ldx, n, c, d);
+}
+
+void identity(hipStream_t s, z64 *X, int64_t t) {
+  hipLaunchKernelGGL(k_identity, dim3(static_cast<unsigned>((t * t + 255) / 256)), dim3(256), 0, s,
+                     X, t);
+}
 
 void shift_assemble_z(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
                       const z64 *z, int32_t N, int64_t n, z64 *M, int64_t ldm, int64_t sM) {

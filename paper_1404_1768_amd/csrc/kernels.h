@@ -24,7 +24,7 @@ template <typename T> struct GemmArgs {
   T *work;
 };
 
-enum { GEMM_SQUARE = 0, GEMM_TALL = 1 };
+enum { GEMM_SQUARE = 0, GEMM_TALL = 1, GEMM_BIG = 2 };
 
 // C_b = alpha op(A_b) B_b + beta C_b; transA 0: A is M x K; 2: A stored K x M, op = ^*.
 // `work` (optional, work_elems entries) enables split-K for small outputs.
@@ -145,5 +145,14 @@ void zero_lower(hipStream_t s, z64 *X, int64_t t, bool all);
 // to unit 2-norm with its largest-modulus entry real positive.
 void gather_normalize_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n,
                            const int32_t *idx, int64_t k, z64 *Y, int64_t ldy, double *part);
+
+// Adjoint helpers: broadcast an n x c block to the N node slots of an n x (N c)
+// block; Y = X^* (rows x cols -> cols x rows); X[:, c] *= d[c]; t x t identity.
+void bcast_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t c, int32_t N, z64 *Y,
+                int64_t ldy);
+void conj_transpose(hipStream_t s, const z64 *X, int64_t ldx, int64_t rows, int64_t cols, z64 *Y,
+                    int64_t ldy);
+void scale_cols(hipStream_t s, z64 *X, int64_t ldx, int64_t n, int64_t c, const z64 *d);
+void identity(hipStream_t s, z64 *X, int64_t t);
 
 }  // namespace feast
