@@ -80,9 +80,6 @@ typedef struct {
   int32_t nb;          /* LU panel width: 64 or 128, 0 = automatic (128) */
   int32_t profile;     /* 1: time the LU trailing-update GEMM launches with HIP events on
                           the plan's stream (reported in feast_info); default 0 */
-  int32_t side_cus;    /* compute units reserved for the look-ahead panel factorisation
-                          (CU-masked stream; the trailing updates get the others);
-                          0 = no reservation (default 32) */
 } feast_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -170,9 +167,12 @@ int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z 
 /* Left eigenvectors y_i (y_i^* A = lambda_i y_i^* B) of the s right eigenvectors
  * X (device, n x s) found inside the contour, from the adjoint of the filter of
  * eq. (8-4) on the plan's cached factors:
- *   W <- sum_j conj(w_j) (z_j B - A)^{-*} W,  W_0 = B X,   `sweeps` times
- * (each sweep damps the components outside the contour by the filter values
- * there), then Y = W (W^* B X)^{-*}, so that Y^* B X = I (y_i^* B x_i = 1).
+ *   W <- sum_j conj(w_j) (z_j B - A)^{-*} B^* W,  W_0 = X,   `sweeps` times.
+ * That operator maps every left eigenvector y_k to conj(f(lambda_k)) y_k, so
+ * each sweep damps the components outside the contour by the filter values
+ * there (without the B^* the sweeps stall at about max|f| outside times the
+ * departure of B from the identity).  Then Y = W (W^* B X)^{-*}, so that
+ * Y^* B X = I (y_i^* B x_i = 1).
  * The (z_j B - A)^* solves reuse the forward factors: U^* first, then L^*, then
  * the transposed row permutation.  FP64 plans only.  dY: n x s (device).
  * Synchronises the stream. */

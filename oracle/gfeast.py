@@ -116,11 +116,28 @@ def apply_filter(solver: ShiftedSolver, w: np.ndarray, U1: np.ndarray,
 
 def apply_filter_adjoint(solver: ShiftedSolver, w: np.ndarray, W: np.ndarray) -> np.ndarray:
     """``sum_j conj(w_j) (z_j B - A)^{-H} W`` -- the conjugate transpose of the
-    resolvent sum without the trailing ``B``; it maps onto the left eigenspace."""
+    resolvent sum of eq. (8-4) without its trailing ``B``.  For a left
+    eigenvector ``y_k`` (``y_k^H A = lam_k y_k^H B``) one has
+    ``(z_j B - A)^H y_k = conj(z_j - lam_k) B^H y_k``, so this maps ``B^H y_k``
+    to ``conj(f(lam_k)) y_k``."""
     out = np.zeros_like(W)
     for j in range(len(w)):
         out += np.conj(w[j]) * solver.solve(j, W, trans=2)
     return out
+
+
+def left_eigenvectors(solver: ShiftedSolver, w: np.ndarray, B: np.ndarray, X: np.ndarray,
+                      sweeps: int) -> np.ndarray:
+    """Left eigenvectors belonging to the right eigenvectors ``X`` found inside
+    the contour: subspace iteration with the adjoint filter operator
+    ``W -> sum_j conj(w_j) (z_j B - A)^{-H} B^H W`` from ``W = X`` (it scales
+    each left eigenvector ``y_k`` by ``conj(f(lam_k))``, so the components
+    outside the contour shrink by the filter values there), then the
+    normalisation ``Y = W (W^H B X)^{-H}`` that makes ``Y^H B X = I``."""
+    W = X
+    for _ in range(sweeps):
+        W = apply_filter_adjoint(solver, w, B.conj().T @ W)
+    return W @ np.linalg.inv(W.conj().T @ B @ X).conj().T
 
 
 # ---------------------------------------------------------------------------

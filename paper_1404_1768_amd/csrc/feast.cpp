@@ -106,8 +106,7 @@ struct feast_plan {
   bool stagnated = false;    // mixed form: the last filter missed its target
   // opts.profile: events around the LU trailing-update GEMMs
   std::vector<hipEvent_t> ev;
-  hipStream_t side = nullptr;                 // look-ahead panel stream (CU-masked if asked)
-  hipStream_t lu_main = nullptr;              // trailing updates when the side stream is masked
+  hipStream_t side = nullptr;                 // look-ahead panel stream
   hipStream_t aux = nullptr;                  // Ritz vectors/residuals overlapping a filter
   hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
   int prof_launches = 0;
@@ -170,6 +169,11 @@ void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, i
   }
   const int w1 = w / 2, w2 = w - w1;
   panel_rec<T>(s, M, ld, stride, batch, n, c0, w1, pk0, pkb, ipiv, info);
+  if (w2 <= feast::panel_update_max_width()) {
+    feast::panel_update<T>(s, M, ld, stride, batch, n, c0, w1, w2);
+    panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info);
+    return;
+  }
   feast::trsm_small<T>(s, M, ld, stride, batch, c0, w1, w2);
   if (c0 + w1 < n)
     gemm_t<T>(s, 0, n - c0 - w1, w2, w1, zc(-1.0), M + (c0 + w1) * ld + c0, ld, stride,
@@ -363,13 +367,7 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     }
     prof.ev = &p->ev;
   }
-  // the factorisation runs on lu_main (the CUs not reserved for panels) when
-  // the side stream is CU-masked, ordered after the caller's stream
-  hipStream_t sl = p->lu_main ? p->lu_main : s;
-  if (sl != s) {
-    HIPCHK(hipEventRecord(p->ev_cols, s));
-    HIPCHK(hipStreamWaitEvent(sl, p->ev_cols, 0));
-  }
+  hipStream_t sl = s;
   const LuStreams lst{sl, p->side, p->ev_cols, p->ev_panel};
   if (p->mixed()) {
     feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
@@ -381,10 +379,6 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     lu_batched<z64>(lst, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<z64>(), p->Uinv.as<z64>(), p->istride(),
                     &prof);
-  }
-  if (sl != s) {
-    HIPCHK(hipEventRecord(p->ev_panel, sl));
-    HIPCHK(hipStreamWaitEvent(s, p->ev_panel, 0));
   }
   feast::perm_from_ipiv(s, p->piv.as<int32_t>(), p->perm.as<int32_t>(), n, N);
   double *nrm = p->nrm.as<double>();
@@ -675,7 +669,6 @@ void feast_opts_default(feast_opts *o) {
   o->max_sweeps = 6;
   o->nb = 0;
   o->profile = 0;
-  o->side_cus = 32;
 }
 
 int feast_nodes(const feast_contour *c, feast_z *hz, feast_z *hw) {
@@ -723,7 +716,7 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
   if (n < 1 || n > 16384 || m < 1 || m > n || bad_contour(c)) return FEAST_EINVAL;
   if (!(opts.eta > 0.0) || !(opts.eps >= 0.0) || opts.max_iter < 1 ||
       opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
-      opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) || opts.side_cus < 0 ||
+      opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) ||
       (opts.nb != 0 && opts.nb != 64 && opts.nb != 128))
     return FEAST_EINVAL;
   feast_plan *p = nullptr;
@@ -755,27 +748,7 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
     HIPCHK(hipMemcpy(p->dwc.p, wc.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
     ensure_workspace(p);
     HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
-    int dev = 0, ncu = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (opts.side_cus > 0 && opts.side_cus < ncu) {
-      // reserve side_cus compute units, spread evenly, for the panel stream
-      const int words = (ncu + 31) / 32, stride = ncu / opts.side_cus;
-      std::vector<uint32_t> side_mask(words, 0u), main_mask(words, 0u);
-      int taken = 0;
-      for (int i = 0; i < ncu; ++i) {
-        if (i % stride == 0 && taken < opts.side_cus) {
-          side_mask[i / 32] |= 1u << (i % 32);
-          ++taken;
-        } else {
-          main_mask[i / 32] |= 1u << (i % 32);
-        }
-      }
-      HIPCHK(hipExtStreamCreateWithCUMask(&p->side, words, side_mask.data()));
-      HIPCHK(hipExtStreamCreateWithCUMask(&p->lu_main, words, main_mask.data()));
-    } else {
-      HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-    }
+    HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming));
     return FEAST_OK;
@@ -792,7 +765,7 @@ int feast_plan_destroy(feast_plan *p) {
   if (!p) return FEAST_OK;
   if (p->s) (void)hipStreamSynchronize(p->s);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-  for (hipStream_t st : {p->side, p->lu_main, p->aux})
+  for (hipStream_t st : {p->side, p->aux})
     if (st) {
       (void)hipStreamSynchronize(st);
       (void)hipStreamDestroy(st);
@@ -1081,11 +1054,11 @@ int feast_left_eigvecs(feast_plan *p, const feast_z *dA, int64_t lda, const feas
     p->adj.alloc(sizeof(z64) * n * ldw);
     z64 *Y = p->Y.as<z64>(), *Adj = p->adj.as<z64>();
     z64 *G = p->wblk(feast_plan::W_X), *W = p->wblk(feast_plan::W_AX), *BX = p->wblk(feast_plan::W_BX);
-    // start block B X: its filtered image spans the left eigenvectors (rows of T in
-    // the Weierstrass form) of the eigenvalues inside the contour
     gemm_t<z64>(s, 0, n, sc, n, zc(1.0), B, ldb, 0, X, ldx, 0, zc(0.0), BX, sc, 0, 1);
-    feast::copy_block_z(s, BX, sc, n, sc, G, sc);
     for (int k = 0; k < sweeps; ++k) {
+      // G = B^* W (W_0 = X): the adjoint filter acts on B^* y_k as conj(f(lambda_k)) y_k
+      gemm_t<z64>(s, 2, n, sc, n, zc(1.0), B, ldb, 0, k == 0 ? X : W, k == 0 ? ldx : sc, 0,
+                  zc(0.0), G, sc, 0, 1);
       // W = sum_j conj(w_j) (z_j B - A)^{-*} G with the cached factors:
       // (z_j B - A)^* = U^* L^* P, so solve with U^*, then L^*, then undo P
       feast::bcast_cols(s, G, sc, n, sc, N, Y, ldw);
@@ -1093,7 +1066,6 @@ int feast_left_eigvecs(feast_plan *p, const feast_z *dA, int64_t lda, const feas
                    p->istride(), Y, sc, ldw, sc, 2);
       feast::scatter_rows<z64>(s, Y, ldw, sc, p->perm.as<int32_t>(), n, sc, N, Adj, ldw, sc);
       feast::weighted_sum(s, Adj, ldw, sc, p->dwc.as<z64>(), N, n, sc, W, sc);
-      if (k + 1 < sweeps) feast::copy_block_z(s, W, sc, n, sc, G, sc);
     }
     // Y = W (W^* B X)^{-*}, so that Y^* B X = I
     z64 *S = p->gblk(feast_plan::G_AT), *T = p->gblk(feast_plan::G_BT), *Z = p->gblk(feast_plan::G_YS);

@@ -256,6 +256,104 @@ __global__ __launch_bounds__(64) void k_trsm_small(T *__restrict__ Mall, int64_t
   }
 }
 
+// One recursion step of the panel factorisation in a single launch, for
+// w1, w2 <= 32:
+//   X = L11^{-1} X      for X = M[c0:c0+w1, c0+w1:c0+w1+w2], L11 unit lower (w1 x w1),
+//   C -= L21 X          for C = M[c0+w1:n, c0+w1:c0+w1+w2], L21 = M[c0+w1:n, c0:c0+w1].
+// write_x = false: every workgroup solves the small triangular system in LDS
+// (eight lanes per column share each inner product) and updates 64 rows of C
+// from an LDS copy of its L21 rows, 8 outputs per thread; X in the matrix is
+// left as it was, because workgroups that start later still read it.
+// write_x = true (one workgroup per matrix, launched afterwards): solve again
+// and store X.  The update is a rank-w1 product with w1 <= 32: it is bound by
+// the traffic of C, so it runs on the VALU.
+constexpr int kPU = 32;
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int64_t ld,
+                                                      int64_t stride, int64_t n, int64_t c0, int w1,
+                                                      int w2, bool write_x) {
+  using Tr = cplx_traits<T>;
+  __shared__ T sL[64][kPU + 1];
+  __shared__ T sX[kPU][kPU + 1];
+  T *M = Mall + blockIdx.y * stride;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < w1 * w1; e += 256) {
+    const int i = e / w1, k = e % w1;
+    sL[i][k] = M[(c0 + i) * ld + c0 + k];
+  }
+  for (int e = tid; e < w1 * w2; e += 256) {
+    const int i = e / w2, j = e % w2;
+    sX[i][j] = M[(c0 + i) * ld + c0 + w1 + j];
+  }
+  __syncthreads();
+  {
+    // forward substitution: column j = tid / 8, lanes q = tid % 8 split the sum
+    const int j = tid >> 3, q = tid & 7;
+    for (int i = 1; i < w1; ++i) {
+      T part = Tr::make(0.0, 0.0);
+      if (j < w2)
+        for (int k = q; k < i; k += 8) part = Tr::fms(part, sL[i][k], sX[k][j]);
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        part.x += __shfl_xor(part.x, off);
+        part.y += __shfl_xor(part.y, off);
+      }
+      if (q == 0 && j < w2) {
+        T x = sX[i][j];
+        x.x += part.x;
+        x.y += part.y;
+        sX[i][j] = x;
+      }
+      // the eight lanes of a column are in one wavefront: order its LDS accesses
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+  }
+  __syncthreads();
+  if (write_x) {
+    for (int e = tid; e < w1 * w2; e += 256) {
+      const int i = e / w2, j = e % w2;
+      if (i > 0) M[(c0 + i) * ld + c0 + w1 + j] = sX[i][j];
+    }
+    return;
+  }
+  const int64_t r0 = c0 + w1 + static_cast<int64_t>(blockIdx.x) * 64;
+  const int rows = static_cast<int>((n - r0 < 64) ? n - r0 : 64);
+  if (rows <= 0) return;
+  // L21 rows of this chunk into LDS (sL is free after the solve)
+  for (int e = tid; e < rows * w1; e += 256) {
+    const int i = e / w1, k = e % w1;
+    sL[i][k] = M[(r0 + i) * ld + c0 + k];
+  }
+  __syncthreads();
+  const int ti = tid >> 4, tj = tid & 15;
+  T acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      acc[a][b] = (i < rows && j < w2) ? M[(r0 + i) * ld + c0 + w1 + j] : Tr::make(0.0, 0.0);
+    }
+  for (int k = 0; k < w1; ++k) {
+    T l[4], x[2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) l[a] = sL[ti + 16 * a][k];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) x[b] = sX[k][tj + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = Tr::fms(acc[a][b], l[a], x[b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (i < rows && j < w2) M[(r0 + i) * ld + c0 + w1 + j] = acc[a][b];
+    }
+}
+
 // Inverse of one diagonal block (lower unit or upper non-unit), one thread per column.
 template <typename T>
 __global__ __launch_bounds__(64) void k_diag_inv(const T *__restrict__ Mall, int64_t ld,
@@ -405,6 +503,24 @@ void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, 
 }
 template void trsm_small<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int, int);
 template void trsm_small<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int, int);
+
+template <typename T>
+void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+                  int64_t c0, int w1, int w2) {
+  if (w1 <= 0 || w2 <= 0 || w1 > kPU || w2 > kPU) return;
+  const int64_t rows = n - c0 - w1;
+  const unsigned chunks = static_cast<unsigned>(rows > 0 ? (rows + 63) / 64 : 1);
+  if (rows > 0)
+    hipLaunchKernelGGL((k_panel_update<T>), dim3(chunks, batch), dim3(256), 0, s, M, ld, stride, n,
+                       c0, w1, w2, false);
+  hipLaunchKernelGGL((k_panel_update<T>), dim3(1, batch), dim3(256), 0, s, M, ld, stride, n, c0, w1,
+                     w2, true);
+}
+template void panel_update<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
+                                int, int);
+template void panel_update<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
+                                int, int);
+int panel_update_max_width() { return kPU; }
 
 template <typename T>
 void diag_block_inverse(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,

@@ -60,6 +60,14 @@ template <typename T>
 void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t c0,
                 int w1, int w2);
 
+// Both halves of one panel recursion step in one launch (w1, w2 <=
+// panel_update_max_width()): X = L11^{-1} X as in trsm_small, then
+// M[c0+w1:n, c0+w1:c0+w1+w2] -= M[c0+w1:n, c0:c0+w1] X.
+template <typename T>
+void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+                  int64_t c0, int w1, int w2);
+int panel_update_max_width();
+
 // Inverses of the diagonal blocks of the unit-lower L (lower=true) or of the
 // upper U (lower=false) factor: block I covers rows/cols [I*nb, min(n,(I+1)*nb)).
 // out[b][I] is an nb x nb row-major block (ld nb).  Blocks [blk0, blk1).

@@ -54,6 +54,11 @@ def test_left_eigvecs_properties():
         Y = plan.left_eigvecs(A, B, r.X, 3).cpu().numpy()
     X = r.X.cpu().numpy()
     assert len(r.lam) == p.s
+    # closed form: x = Q^{-1} e_k alpha  =>  y = P^{-*} e_k / conj(alpha)
+    QX, Pi_h = p.Q @ X, np.linalg.inv(p.P).conj().T
+    Yc = np.stack([Pi_h[:, np.argmax(np.abs(QX[:, i]))] / np.conj(QX[np.argmax(np.abs(QX[:, i])), i])
+                   for i in range(p.s)], axis=1)
+    assert np.linalg.norm(Y - Yc) / np.linalg.norm(Yc) < 1e-11
     # biorthonormal: Y^* B X = I and Y^* A X = diag(lambda)
     assert np.max(np.abs(Y.conj().T @ p.B @ X - np.eye(p.s))) < 1e-10
     assert np.max(np.abs(Y.conj().T @ p.A @ X - np.diag(r.lam))) < 1e-10

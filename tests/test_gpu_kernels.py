@@ -76,6 +76,24 @@ def test_zgetrf_reconstructs_and_pivots_partially(n, nb):
         assert np.abs(L).max() <= np.sqrt(2.0) * (1 + 1e-12)
 
 
+def test_zgetrf_many_workgroups_per_panel_step():
+    # batch 32 at n = 2000: each panel step launches ~1000 workgroups, more than
+    # are resident at once, so workgroups of one launch start at different times
+    # (a kernel that rewrites its own input in place would show here)
+    rng = np.random.default_rng(7)
+    n, batch = 2000, 32
+    M = crand(rng, batch, n, n)
+    tM = torch.from_numpy(M).to(DEV)
+    piv, info = fm.zgetrf_batched(tM)
+    assert np.all(info.cpu().numpy() == 0)
+    F, piv = tM.cpu().numpy(), piv.cpu().numpy()
+    for b in (0, batch - 1):
+        L = np.tril(F[b], -1) + np.eye(n)
+        U = np.triu(F[b])
+        err = np.linalg.norm(_apply_pivots(M[b], piv[b]) - L @ U) / np.linalg.norm(M[b])
+        assert err < 1e-14 * n, err
+
+
 def test_zgetrf_reports_exact_zero_pivot():
     n = 40
     rng = np.random.default_rng(5)

@@ -334,9 +334,53 @@ def test_gradient_closed_form_and_finite_differences():
         assert abs(fd - an) < 1e-6 * max(1.0, abs(an))
 
 
+def _closed_form_left(p, X):
+    """Left eigenvectors of ``A = P D Q``, ``B = P Q`` matching the columns of
+    ``X``: ``x = Q^{-1} e_k alpha`` gives ``y = P^{-*} e_k / conj(alpha)`` with
+    ``y^* B x = 1``; ``k`` is the index whose coordinate dominates ``Q x``."""
+    QX = p.Q @ X
+    Pi_h = np.linalg.inv(p.P).conj().T
+    Y = np.zeros_like(X)
+    for i in range(X.shape[1]):
+        k = int(np.argmax(np.abs(QX[:, i])))
+        Y[:, i] = Pi_h[:, k] / np.conj(QX[k, i])
+    return Y
+
+
+@pytest.mark.parametrize("n", [64, 300])
+def test_left_eigenvectors_match_closed_form(n):
+    # The adjoint filter operator sum_j conj(w_j)(z_j B - A)^{-*} B^* scales each
+    # left eigenvector P^{-*} e_k by conj(f(d_k)); three sweeps from the converged
+    # right eigenvectors reach the closed form to rounding.
+    p = pg.workload(5, n_override=n)
+    z, w = o.contour_nodes(p.center, p.radius, p.nodes)
+    res = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, eps=1e-13, max_iter=20)
+    assert len(res.lam) == p.s
+    Y = o.left_eigenvectors(o.ShiftedSolver(p.A, p.B, z), w, p.B, res.X, 3)
+    Yc = _closed_form_left(p, res.X)
+    assert np.linalg.norm(Y - Yc) / np.linalg.norm(Yc) < 1e-12
+    assert np.abs(Y.conj().T @ p.B @ res.X - np.eye(p.s)).max() < 1e-12
+
+
 # ---------------------------------------------------------------------------
 # Planted mistakes: the pins above must catch them
 # ---------------------------------------------------------------------------
+
+def test_planted_adjoint_without_B_star_stalls():
+    # Sweeping the adjoint resolvent sum without B^* between the sweeps stalls at
+    # about max|f| outside times the departure of B from I; the closed-form pin
+    # rejects it.
+    p = pg.workload(5, n_override=300)
+    z, w = o.contour_nodes(p.center, p.radius, p.nodes)
+    res = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, eps=1e-13, max_iter=20)
+    S = o.ShiftedSolver(p.A, p.B, z)
+    W = p.B @ res.X
+    for _ in range(4):
+        W = o.apply_filter_adjoint(S, w, W)
+    Y = W @ np.linalg.inv(W.conj().T @ p.B @ res.X).conj().T
+    Yc = _closed_form_left(p, res.X)
+    assert np.linalg.norm(Y - Yc) / np.linalg.norm(Yc) > 1e-10
+
 
 def test_planted_weight_sign_error_is_caught():
     p = pg.workload(1, n_override=80)
