@@ -194,6 +194,64 @@ int feast_eig_grad(feast_plan *plan, const feast_z *dX, int64_t ldx, const feast
 const char *feast_last_error(const feast_plan *plan);
 
 /* ---------------------------------------------------------------------------
+ * Batched form: many independent pencils of uneven order in lockstep
+ * ------------------------------------------------------------------------- */
+
+/* A batch of `count` independent pencils (A_p, B_p), p = 0..count-1, of orders
+ * n[p] with subspace sizes m[p] and contours c[p] (every contour with the same
+ * number of nodes N).  All count*N shifted matrices z_pj B_p - A_p are
+ * factored together: each pencil is padded with an identity block to a
+ * multiple of 64, the pencils are ordered by size so that the ones still
+ * active at a panel step are a prefix, and every panel step, triangular solve
+ * and trailing update is one grouped launch over all active pencils (the LU
+ * factors are cached as in feast_filter, Section 4.3).  The device work of a
+ * factorisation and of a filter is captured once in a HIP graph and replayed.
+ * All pointer arguments of the batch calls below are HOST arrays of `count`
+ * entries (device pointers or host buffers as stated), in the caller's order.
+ * Options as for a plan (nb is ignored: the grouped LU uses 64-wide panels).
+ * Limits: 1 <= count <= 4096, 1 <= m[p] <= n[p] <= 16384. */
+typedef struct feast_batch feast_batch;
+
+typedef struct {
+  int32_t iters;        /* largest iteration count over the pencils */
+  int32_t filters;      /* grouped filters applied */
+  int32_t graph_launches; /* HIP graph replays (factorisations + filters) */
+  double t_factor_ms, t_filter_ms, t_project_ms, t_host_eig_ms, t_total_ms;
+} feast_batch_info;
+
+int feast_batch_create(feast_batch **batch, int32_t count, const int64_t *n, const int64_t *m,
+                       const feast_contour *c, const feast_opts *o, void *stream);
+int feast_batch_destroy(feast_batch *batch);
+/* Drop the cached factors (A_p or B_p changed in place). */
+int feast_batch_invalidate(feast_batch *batch);
+const char *feast_batch_last_error(const feast_batch *batch);
+
+/* U_p = sum_j w_pj (z_pj B_p - A_p)^{-1} B_p V_p for every pencil (eqs. 8-4,
+ * 4-4).  dA, dB: n x n, dV, dU: n x m (device, row-major, leading dimensions
+ * in lda, ldb, ldv, ldu).  Mixed plans apply `sweeps` FP64 refinement
+ * corrections per node (0 = the complex64 solve alone).  FEAST_SINGULAR when
+ * an exact zero pivot occurs (pencil and node in feast_batch_last_error). */
+int feast_batch_filter(feast_batch *batch, const feast_z *const *dA, const int64_t *lda,
+                       const feast_z *const *dB, const int64_t *ldb, const feast_z *const *dV,
+                       const int64_t *ldv, feast_z *const *dU, const int64_t *ldu,
+                       int32_t sweeps);
+
+/* Algorithm 5 for every pencil, as feast_solve, with the filters of all
+ * pencils still iterating run as one grouped filter (pencils that have
+ * stopped keep their result).  Per pencil p: hLambda[p] (host, >= m[p]
+ * entries), dX[p] (device n x m, leading dimension ldx[p]), hRes[p] (host,
+ * >= m[p], may be NULL as a whole array), s_found[p], err[p], flag[p],
+ * iters[p] (host arrays of count entries).  Mixed plans refine as
+ * feast_solve does (no refinement on the first filter, one correction per
+ * node afterwards, one more whenever a refined iteration misses eps).
+ * info may be NULL. */
+int feast_batch_solve(feast_batch *batch, const feast_z *const *dA, const int64_t *lda,
+                      const feast_z *const *dB, const int64_t *ldb, const feast_z *const *dV,
+                      const int64_t *ldv, feast_z *const *hLambda, feast_z *const *dX,
+                      const int64_t *ldx, double *const *hRes, int32_t *s_found, double *err,
+                      int32_t *flag, int32_t *iters, feast_batch_info *info);
+
+/* ---------------------------------------------------------------------------
  * Host-side pieces of Algorithm 5 (no device needed)
  * ------------------------------------------------------------------------- */
 

@@ -9,4 +9,5 @@ from .binding import (FEAST_OK, FEAST_SINGULAR, FEAST_REFINE_STAGNATED, FEAST_EI
                       FEAST_EDEVICE, FEAST_ENOMEM, FEAST_ENUMERIC, TRAPEZOID, GAUSS_LEGENDRE,
                       FP64, MIXED, FeastError, Plan, SolveResult, feast_filter, feast_project,
                       feast_solve, feast_nodes, feast_reduced_eig, feast_stop_rule, load,
-                      zgemm_batched, zgetrf_batched, zgetrs_batched, LIB_PATH, feast_eig)
+                      zgemm_batched, zgetrf_batched, zgetrs_batched, LIB_PATH, feast_eig,
+                      Batch, BatchResult)

@@ -37,6 +37,8 @@ EXPORTED = [
     "feast_plan_invalidate", "feast_filter", "feast_project", "feast_solve", "feast_last_error",
     "feast_reduced_eig", "feast_stop_rule", "feast_zgetrf_batched", "feast_zgetrs_batched",
     "feast_zgemm_batched", "feast_version", "feast_left_eigvecs", "feast_eig_grad",
+    "feast_batch_create", "feast_batch_destroy", "feast_batch_invalidate",
+    "feast_batch_last_error", "feast_batch_filter", "feast_batch_solve",
 ]
 
 
@@ -64,6 +66,13 @@ class Info(C.Structure):
                 ("t_ritz_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("lu_gemm_launches", C.c_int32), ("lu_gemm_ms", C.c_double),
                 ("lu_gemm_flops", C.c_double)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("filters", C.c_int32), ("graph_launches", C.c_int32),
+                ("t_factor_ms", C.c_double), ("t_filter_ms", C.c_double),
+                ("t_project_ms", C.c_double), ("t_host_eig_ms", C.c_double),
+                ("t_total_ms", C.c_double)]
 
 
 class FeastError(RuntimeError):
@@ -107,8 +116,19 @@ def load(path: str = LIB_PATH):
                                         FeastZ, P, i64, i64, i32, P]
     lib.feast_left_eigvecs.argtypes = [P, P, i64, P, i64, P, i64, i64, i32, P, i64]
     lib.feast_eig_grad.argtypes = [P, P, i64, P, i64, i64, pz, pz, P, i64, P, i64]
+    pi64, pp = C.POINTER(i64), C.POINTER(P)
+    lib.feast_batch_create.argtypes = [C.POINTER(P), i32, pi64, pi64, C.POINTER(Contour),
+                                       C.POINTER(Opts), P]
+    lib.feast_batch_destroy.argtypes = [P]
+    lib.feast_batch_invalidate.argtypes = [P]
+    lib.feast_batch_last_error.argtypes = [P]
+    lib.feast_batch_last_error.restype = C.c_char_p
+    lib.feast_batch_filter.argtypes = [P, pp, pi64, pp, pi64, pp, pi64, pp, pi64, i32]
+    lib.feast_batch_solve.argtypes = [P, pp, pi64, pp, pi64, pp, pi64, pp, pp, pi64, pp,
+                                      C.POINTER(i32), C.POINTER(dbl), C.POINTER(i32),
+                                      C.POINTER(i32), C.POINTER(BatchInfo)]
     for name in EXPORTED:
-        if name not in ("feast_opts_default", "feast_last_error"):
+        if name not in ("feast_opts_default", "feast_last_error", "feast_batch_last_error"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -466,3 +486,127 @@ def zgetrs_batched(LU, piv, X, trans: int = 0, stream=None):
     if rc != FEAST_OK:
         raise FeastError(rc, "feast_zgetrs_batched")
     return X
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class BatchResult:
+    lam: list              # per pencil: selected eigenvalues (numpy)
+    X: list                # per pencil: torch tensor n x s (device)
+    res: list              # per pencil: residuals r_i of eq. (5-1)
+    err: np.ndarray
+    flag: np.ndarray
+    iters: np.ndarray
+    info: dict
+
+
+class Batch:
+    """Many independent pencils of uneven order, factored and filtered in
+    lockstep (grouped launches replayed from HIP graphs)."""
+
+    def __init__(self, ns, ms, centers, radii, nodes: int, rule: int = TRAPEZOID,
+                 eps: float = 1e-10, eta: float = 1e-3, max_iter: int = 20, prec: int = FP64,
+                 max_sweeps: int = 6, stream=None):
+        self.lib = load()
+        self.ns = [int(x) for x in ns]
+        self.ms = [int(x) for x in ms]
+        P = len(self.ns)
+        if len(self.ms) != P or len(centers) != P or len(radii) != P:
+            raise ValueError("one n, m, center and radius per pencil")
+        self.P = P
+        self._c = (Contour * P)(*[contour(c, r, nodes, rule) for c, r in zip(centers, radii)])
+        self.opts = default_opts()
+        self.opts.eps, self.opts.eta, self.opts.max_iter = float(eps), float(eta), int(max_iter)
+        self.opts.prec, self.opts.max_sweeps = int(prec), int(max_sweeps)
+        self._stream_obj = stream
+        self._h = C.c_void_p()
+        n_arr = (C.c_int64 * P)(*self.ns)
+        m_arr = (C.c_int64 * P)(*self.ms)
+        rc = self.lib.feast_batch_create(C.byref(self._h), P, n_arr, m_arr, self._c,
+                                         C.byref(self.opts), _stream(stream))
+        if rc != FEAST_OK:
+            raise FeastError(rc, "feast_batch_create failed")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.feast_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self) -> str:
+        return self.lib.feast_batch_last_error(self._h).decode()
+
+    def invalidate(self):
+        self.lib.feast_batch_invalidate(self._h)
+
+    def _mats(self, ts, rows, cols, name):
+        ptrs = (C.c_void_p * self.P)()
+        lds = (C.c_int64 * self.P)()
+        if len(ts) != self.P:
+            raise ValueError("%s: one tensor per pencil" % name)
+        for i, t in enumerate(ts):
+            p, ld = _dev(t, rows[i], cols[i], "%s[%d]" % (name, i))
+            ptrs[i], lds[i] = p, ld
+        return ptrs, lds
+
+    def filter(self, As, Bs, Vs, sweeps: int = 0):
+        """U_p = sum_j w_pj (z_pj B_p - A_p)^{-1} B_p V_p for every pencil."""
+        import torch
+        a, la = self._mats(As, self.ns, self.ns, "A")
+        b, lb = self._mats(Bs, self.ns, self.ns, "B")
+        v, lv = self._mats(Vs, self.ns, self.ms, "V")
+        Us = [torch.empty((n, m), dtype=torch.complex128, device=Vs[0].device)
+              for n, m in zip(self.ns, self.ms)]
+        u, lu = self._mats(Us, self.ns, self.ms, "U")
+        rc = self.lib.feast_batch_filter(self._h, a, la, b, lb, v, lv, u, lu, int(sweeps))
+        if rc != FEAST_OK:
+            raise FeastError(rc, self.last_error())
+        return Us
+
+    def solve(self, As, Bs, Vs) -> BatchResult:
+        import torch
+        P = self.P
+        a, la = self._mats(As, self.ns, self.ns, "A")
+        b, lb = self._mats(Bs, self.ns, self.ns, "B")
+        v, lv = self._mats(Vs, self.ns, self.ms, "V")
+        Xs = [torch.zeros((n, m), dtype=torch.complex128, device=Vs[0].device)
+              for n, m in zip(self.ns, self.ms)]
+        x, lx = self._mats(Xs, self.ns, self.ms, "X")
+        lam = [np.zeros(m, dtype=np.complex128) for m in self.ms]
+        res = [np.zeros(m, dtype=np.float64) for m in self.ms]
+        hl = (C.c_void_p * P)(*[C.c_void_p(l.ctypes.data) for l in lam])
+        hr = (C.c_void_p * P)(*[C.c_void_p(r.ctypes.data) for r in res])
+        s_found = (C.c_int32 * P)()
+        err = (C.c_double * P)()
+        flag = (C.c_int32 * P)()
+        iters = (C.c_int32 * P)()
+        info = BatchInfo()
+        rc = self.lib.feast_batch_solve(self._h, a, la, b, lb, v, lv, hl, x, lx, hr, s_found, err,
+                                        flag, iters, C.byref(info))
+        if rc != FEAST_OK:
+            raise FeastError(rc, self.last_error())
+        torch.cuda.current_stream().synchronize()
+        k = list(s_found)
+        return BatchResult(
+            lam=[lam[i][:k[i]].copy() for i in range(P)],
+            X=[Xs[i][:, :k[i]] for i in range(P)],
+            res=[res[i][:k[i]].copy() for i in range(P)],
+            err=np.array(list(err)), flag=np.array(list(flag)), iters=np.array(list(iters)),
+            info={"iters": info.iters, "filters": info.filters,
+                  "graph_launches": info.graph_launches, "factor": info.t_factor_ms,
+                  "filter": info.t_filter_ms, "project": info.t_project_ms,
+                  "host_eig": info.t_host_eig_ms, "total": info.t_total_ms})

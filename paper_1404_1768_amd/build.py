@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libfeast_mi355x.so")
 ARCH = "gfx950"
 
 DEVICE_SOURCES = ["k_gemm.hip", "k_lu.hip", "k_misc.hip"]
-HOST_HIP_SOURCES = ["feast.cpp"]           # host code that calls the HIP runtime
+HOST_HIP_SOURCES = ["feast.cpp", "batch.cpp"]           # host code that calls the HIP runtime
 HOST_SOURCES = ["host_eig.cpp", "host_util.cpp"]   # plain C++
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-fcx-limited-range"]

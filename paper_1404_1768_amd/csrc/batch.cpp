@@ -1,0 +1,912 @@
+// Batched form: the filter and Algorithm 5 over many independent pencils of
+// uneven order, with all shifted systems of all pencils factored and solved
+// in lockstep.
+//
+// Layout.  Pencil p (internal order: decreasing padded order) of order n_p is
+// padded to np_p = 64 ceil(n_p / 64) with an identity block: its N shifted
+// matrices are np_p x np_p row-major blocks, the real part z B - A in the
+// leading n_p x n_p corner, ones on the rest of the diagonal and zeros
+// elsewhere.  Partial pivoting never moves a padding row into the leading
+// block (those rows are zero in its columns), the padding stays the identity
+// under the factorisation, and solutions keep zeros in the padding rows, so a
+// padded pencil factors and solves exactly like the original.  With every
+// order a multiple of the 64-wide panel, the pencils still active at panel
+// step k0 are the prefix np_p > k0, and each step is one grouped launch per
+// kernel over that prefix (GrpMat descriptors for the panel kernels, tables
+// of GEMM problems for the MFMA products).  Matrix b = p N + j of the flat
+// per-matrix arrays (pivots, permutations, info, inverted diagonal blocks) is
+// node j of pencil p.
+//
+// Node solutions of pencil p: an np_p x (N m_p) block, node j in columns
+// [j m_p, (j+1) m_p), as in the single-pencil plan.  The small per-pencil
+// steps (orthonormalisation, projection, reduced eigenproblem, residuals) run
+// on a member plan per pencil that owns only n x m and m x m workspaces.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "host_eig.h"
+#include "plan.h"
+
+using namespace feast_drv;
+using feast::GemmArgs;
+using feast::GrpMat;
+
+namespace {
+
+constexpr int64_t kPanel = 64;
+
+// Device tables of the grouped GEMM launches.  The launch schedule of a batch
+// depends only on the orders: it is run once in record mode (tables are
+// collected on the host and nothing is launched), the tables are uploaded,
+// and every later run takes them from device memory in the same order.
+struct Tables {
+  bool record = true;
+  std::vector<char> host;
+  std::vector<size_t> off, cnt;
+  size_t cur = 0;
+  DevBuf dev;
+  void begin() { cur = 0; }
+  template <class E> const E *put(const std::vector<E> &v) {
+    if (record) {
+      const size_t o = (host.size() + 255) / 256 * 256;
+      host.resize(o + sizeof(E) * v.size());
+      std::memcpy(host.data() + o, v.data(), sizeof(E) * v.size());
+      off.push_back(o);
+      cnt.push_back(v.size());
+      return nullptr;
+    }
+    if (cur >= off.size() || cnt[cur] != v.size())
+      throw HipError{hipErrorInvalidValue, "grouped launch schedule changed"};
+    return reinterpret_cast<const E *>(static_cast<const char *>(dev.p) + off[cur++]);
+  }
+  void upload() {
+    dev.alloc(std::max<size_t>(host.size(), 256));
+    if (!host.empty()) HIPCHK(hipMemcpy(dev.p, host.data(), host.size(), hipMemcpyHostToDevice));
+    record = false;
+  }
+};
+
+// A captured HIP graph, re-captured when its key (the caller's pointers and
+// leading dimensions, the sweep count) changes.
+struct Graph {
+  hipGraphExec_t exec = nullptr;
+  std::vector<int64_t> key;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    key.clear();
+  }
+};
+
+}  // namespace
+
+struct feast_batch {
+  int P = 0, N = 0;
+  feast_opts o{};
+  hipStream_t s = nullptr;   // caller's stream
+  hipStream_t gs = nullptr;  // the batch's own stream (graphs are captured and replayed here)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<int> order;     // internal index -> caller index
+  std::vector<int> where;     // caller index -> internal index
+  std::vector<int64_t> n, m, np;
+  std::vector<feast_plan *> sub;  // member plans (internal order)
+  int64_t nmax = 0, nblk = 0;
+  // grouped factors
+  DevBuf F, piv, perm, info, Linv, Uinv, grp;
+  std::vector<int64_t> foff;  // element offset of pencil p's first matrix in F
+  // node solutions (np_p x N m_p each) and the mixed-form buffers
+  DevBuf Y, Yc, T1, T2;
+  std::vector<int64_t> yoff, toff;
+  Tables lu_tab, sv_tab;
+  Graph g_factor, g_filter;
+  bool factored = false;
+  std::vector<int64_t> fkey;
+  std::string err;
+  int launches = 0;
+
+  bool mixed() const { return o.prec == FEAST_MIXED; }
+  int64_t istride() const { return nblk * 64 * 64; }
+  int64_t ldY(int p) const { return static_cast<int64_t>(N) * m[p]; }
+  int active(int64_t k) const {  // pencils with np > k (a prefix)
+    int a = 0;
+    while (a < P && np[a] > k) ++a;
+    return a;
+  }
+};
+
+namespace {
+
+int bfail(feast_batch *b, int code, const std::string &msg) {
+  if (b) b->err = msg;
+  return code;
+}
+
+template <typename F> int bguarded(feast_batch *b, F &&f) {
+  try {
+    return f();
+  } catch (const HipError &e) {
+    if (b) {
+      b->err = std::string(e.what) + ": " + hipGetErrorString(e.e);
+      b->factored = false;
+    }
+    return e.e == hipErrorOutOfMemory ? FEAST_ENOMEM : FEAST_EDEVICE;
+  } catch (const std::bad_alloc &) {
+    if (b) b->err = "host allocation failed";
+    return FEAST_ENOMEM;
+  } catch (...) {
+    if (b) b->err = "unexpected exception";
+    return FEAST_EDEVICE;
+  }
+}
+
+// A member plan: nodes, weights and the n x m / m x m workspaces of one pencil,
+// running on the batch stream; it never factors.
+feast_plan *member_plan(int64_t n, int64_t m, const feast_contour &c, const feast_opts &o,
+                        hipStream_t s) {
+  feast_plan *p = new feast_plan();
+  p->n = n;
+  p->m = m;
+  p->N = c.nodes;
+  p->c = c;
+  p->o = o;
+  p->s = s;
+  p->nblk = (n + 63) / 64;
+  p->hz.resize(p->N);
+  p->hw.resize(p->N);
+  feast_host::contour_nodes(cd(c.center.re, c.center.im), c.radius, p->N, c.rule, p->hz.data(),
+                            p->hw.data());
+  p->dz.alloc(sizeof(z64) * p->N);
+  p->dw.alloc(sizeof(z64) * p->N);
+  HIPCHK(hipMemcpy(p->dz.p, p->hz.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->dw.p, p->hw.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
+  ensure_workspace(p, false);
+  return p;
+}
+
+// Grouped product over a list of problems (skipped when empty).
+template <typename T>
+void ggemm(feast_batch *b, Tables &tab, int ta, bool sub, std::vector<GemmArgs<T>> &e) {
+  if (e.empty()) return;
+  const int64_t tiles = feast::gemm_group_tiles<T>(e.data(), static_cast<int>(e.size()));
+  const GemmArgs<T> *d = tab.put(e);
+  if (!tab.record) feast::gemm_group<T>(b->gs, ta, sub, d, static_cast<int>(e.size()), tiles);
+}
+
+template <typename T>
+GemmArgs<T> gargs(int64_t M, int64_t Nc, int64_t K, const T *A, int64_t lda, int64_t sA,
+                  const T *B, int64_t ldb, int64_t sB, T *C, int64_t ldc, int64_t sC, double alpha,
+                  double beta, int32_t batch) {
+  return GemmArgs<T>{M, Nc, K, A, lda, sA, B, ldb, sB, C, ldc, sC, make_double2(alpha, 0.0),
+                     make_double2(beta, 0.0), batch, 1, K, nullptr, 0};
+}
+
+// Panel [c0, c0 + w) of the active matrices: halves down to register leaves,
+// each split joined by the fused triangular solve + rank update.
+template <typename T>
+void panel_grp(feast_batch *b, T *F, int nmat, int64_t c0, int w, int64_t pk0, int pkb) {
+  const GrpMat *g = b->grp.as<GrpMat>();
+  int32_t *piv = b->piv.as<int32_t>(), *info = b->info.as<int32_t>();
+  const int ib = feast::leaf_max_width<T>(b->nmax - c0);
+  if (w <= ib) {
+    if (!feast::leaf_lu<T>(b->gs, F, 0, 0, nmat, b->nmax, c0, w, pk0, pkb, piv, info, g, b->N))
+      throw HipError{hipErrorInvalidValue, "leaf_lu"};
+    return;
+  }
+  const int w1 = w / 2, w2 = w - w1;
+  panel_grp<T>(b, F, nmat, c0, w1, pk0, pkb);
+  feast::panel_update<T>(b->gs, F, 0, 0, nmat, b->nmax, c0, w1, w2, g, b->N);
+  panel_grp<T>(b, F, nmat, c0 + w1, w2, pk0, pkb);
+}
+
+// Blocked right-looking LU of every shifted matrix of every pencil in lockstep
+// (64-wide panels).  record: only collect the GEMM tables.
+template <typename T>
+void lu_grouped(feast_batch *b, bool record) {
+  Tables &tab = b->lu_tab;
+  tab.begin();
+  T *F = b->F.as<T>();
+  T *Linv = b->Linv.as<T>(), *Uinv = b->Uinv.as<T>();
+  const int N = b->N;
+  const int64_t is = b->istride();
+  const GrpMat *g = b->grp.as<GrpMat>();
+  int32_t *piv = b->piv.as<int32_t>();
+  if (!record) feast::fill_i32(b->gs, b->info.as<int32_t>(), static_cast<int64_t>(b->P) * N, 0);
+  for (int64_t k0 = 0; k0 < b->nmax; k0 += kPanel) {
+    const int64_t k1 = k0 + kPanel;
+    const int act = b->active(k0), nmat = act * N;
+    if (!record) {
+      panel_grp<T>(b, F, nmat, k0, static_cast<int>(kPanel), k0, static_cast<int>(kPanel));
+      feast::laswp_outside<T>(b->gs, F, 0, 0, nmat, b->nmax, k0, static_cast<int>(kPanel), k0, k1,
+                              piv, g, N);
+      feast::diag_block_inverse<T>(b->gs, F, 0, 0, nmat, b->nmax, 64, k0 / 64, k0 / 64 + 1, true,
+                                   Linv, is, g, N);
+    }
+    const int act2 = b->active(k1);
+    std::vector<GemmArgs<T>> u12, upd;
+    for (int p = 0; p < act2; ++p) {
+      const int64_t ld = b->np[p], st = ld * ld, rest = ld - k1;
+      T *M = F + b->foff[p];
+      // U12 = L11^{-1} A12 in place (one 64-row tile row), then A22 -= L21 U12
+      u12.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + (k0 / 64) * 4096, 64, is,
+                             M + k0 * ld + k1, ld, st, M + k0 * ld + k1, ld, st, 1.0, 0.0, N));
+      upd.push_back(gargs<T>(rest, rest, kPanel, M + k1 * ld + k0, ld, st, M + k0 * ld + k1, ld, st,
+                             M + k1 * ld + k1, ld, st, -1.0, 1.0, N));
+    }
+    ggemm<T>(b, tab, 0, false, u12);
+    ggemm<T>(b, tab, 0, true, upd);
+  }
+  if (!record) {
+    const int nmat = b->P * N;
+    feast::diag_block_inverse<T>(b->gs, F, 0, 0, nmat, b->nmax, 64, 0, b->nblk, false, Uinv, is, g,
+                                 N);
+    feast::perm_from_ipiv(b->gs, piv, b->perm.as<int32_t>(), b->nmax, nmat, g, N);
+  }
+}
+
+// Y_p <- L^{-1} Y_p (rows [r0, r1) of every pencil's node blocks), recursive
+// halving at multiples of 64; leaves are in-place products with the inverted
+// diagonal blocks.
+template <typename T>
+void trsm_lower_grp(feast_batch *b, Tables &tab, T *Y, int64_t r0, int64_t r1) {
+  const T *F = b->F.as<T>();
+  const T *Linv = b->Linv.as<T>();
+  const int N = b->N;
+  const int64_t is = b->istride();
+  if (r1 - r0 <= 64) {
+    std::vector<GemmArgs<T>> e;
+    for (int p = 0; p < b->active(r0); ++p) {
+      const int64_t ldy = b->ldY(p);
+      T *X = Y + b->yoff[p] + r0 * ldy;
+      e.push_back(gargs<T>(r1 - r0, b->m[p], r1 - r0, Linv + p * N * is + (r0 / 64) * 4096, 64, is,
+                           X, ldy, b->m[p], X, ldy, b->m[p], 1.0, 0.0, N));
+    }
+    ggemm<T>(b, tab, 0, false, e);
+    return;
+  }
+  const int64_t mid = r0 + ((r1 - r0 + 127) / 128) * 64;
+  trsm_lower_grp<T>(b, tab, Y, r0, mid);
+  std::vector<GemmArgs<T>> e;
+  for (int p = 0; p < b->active(mid); ++p) {
+    const int64_t ld = b->np[p], ldy = b->ldY(p), rows = std::min(r1, ld) - mid;
+    const T *M = F + b->foff[p];
+    T *Yp = Y + b->yoff[p];
+    e.push_back(gargs<T>(rows, b->m[p], mid - r0, M + mid * ld + r0, ld, ld * ld, Yp + r0 * ldy, ldy,
+                         b->m[p], Yp + mid * ldy, ldy, b->m[p], -1.0, 1.0, N));
+  }
+  ggemm<T>(b, tab, 0, true, e);
+  trsm_lower_grp<T>(b, tab, Y, mid, r1);
+}
+
+// Y_p <- U^{-1} Y_p, rows [r0, r1).
+template <typename T>
+void trsm_upper_grp(feast_batch *b, Tables &tab, T *Y, int64_t r0, int64_t r1) {
+  const T *F = b->F.as<T>();
+  const T *Uinv = b->Uinv.as<T>();
+  const int N = b->N;
+  const int64_t is = b->istride();
+  if (r1 - r0 <= 64) {
+    std::vector<GemmArgs<T>> e;
+    for (int p = 0; p < b->active(r0); ++p) {
+      const int64_t ldy = b->ldY(p);
+      T *X = Y + b->yoff[p] + r0 * ldy;
+      e.push_back(gargs<T>(r1 - r0, b->m[p], r1 - r0, Uinv + p * N * is + (r0 / 64) * 4096, 64, is,
+                           X, ldy, b->m[p], X, ldy, b->m[p], 1.0, 0.0, N));
+    }
+    ggemm<T>(b, tab, 0, false, e);
+    return;
+  }
+  const int64_t mid = r0 + ((r1 - r0 + 127) / 128) * 64;
+  trsm_upper_grp<T>(b, tab, Y, mid, r1);
+  std::vector<GemmArgs<T>> e;
+  for (int p = 0; p < b->active(mid); ++p) {  // X[r0:mid] -= U[r0:mid, mid:r1] X[mid:r1]
+    const int64_t ld = b->np[p], ldy = b->ldY(p), K = std::min(r1, ld) - mid;
+    const T *M = F + b->foff[p];
+    T *Yp = Y + b->yoff[p];
+    e.push_back(gargs<T>(mid - r0, b->m[p], K, M + r0 * ld + mid, ld, ld * ld, Yp + mid * ldy, ldy,
+                         b->m[p], Yp + r0 * ldy, ldy, b->m[p], -1.0, 1.0, N));
+  }
+  ggemm<T>(b, tab, 0, true, e);
+  trsm_upper_grp<T>(b, tab, Y, r0, mid);
+}
+
+// Y <- U^{-1} L^{-1} Y for every node of every pencil (rows already permuted).
+template <typename T>
+void trsolve_grouped(feast_batch *b, T *Y) {
+  b->sv_tab.begin();
+  trsm_lower_grp<T>(b, b->sv_tab, Y, 0, b->nmax);
+  trsm_upper_grp<T>(b, b->sv_tab, Y, 0, b->nmax);
+}
+
+// Key of a graph: the caller's pointers and leading dimensions plus a tag.
+std::vector<int64_t> make_key(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
+                              const feast_z *const *dB, const int64_t *ldb, int64_t tag) {
+  std::vector<int64_t> k;
+  k.reserve(4 * b->P + 1);
+  for (int i = 0; i < b->P; ++i) {
+    k.push_back(reinterpret_cast<int64_t>(dA[i]));
+    k.push_back(lda[i]);
+    k.push_back(reinterpret_cast<int64_t>(dB[i]));
+    k.push_back(ldb[i]);
+  }
+  k.push_back(tag);
+  return k;
+}
+
+template <class Body> void run_graph(feast_batch *b, Graph &g, const std::vector<int64_t> &key, Body &&body) {
+  if (!g.exec || g.key != key) {
+    g.reset();
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
+    try {
+      body();
+    } catch (...) {
+      (void)hipStreamEndCapture(b->gs, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(b->gs, &graph));
+    const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+    g.key = key;
+  }
+  HIPCHK(hipGraphLaunch(g.exec, b->gs));
+  ++b->launches;
+}
+
+// Factor every shifted matrix of every pencil (graph), then check the pivots.
+int factor_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
+               const feast_z *const *dB, const int64_t *ldb) {
+  const std::vector<int64_t> key = make_key(b, dA, lda, dB, ldb, 0);
+  if (b->factored && key == b->fkey) return FEAST_OK;
+  b->factored = false;
+  run_graph(b, b->g_factor, key, [&]() {
+    for (int p = 0; p < b->P; ++p) {
+      const int c = b->order[p];
+      const z64 *A = reinterpret_cast<const z64 *>(dA[c]), *B = reinterpret_cast<const z64 *>(dB[c]);
+      const int64_t ld = b->np[p];
+      if (b->mixed())
+        feast::shift_assemble_c(b->gs, A, lda[c], B, ldb[c], b->sub[p]->dz.as<z64>(), b->N, b->n[p],
+                                b->F.as<c64>() + b->foff[p], ld, ld * ld);
+      else
+        feast::shift_assemble_z(b->gs, A, lda[c], B, ldb[c], b->sub[p]->dz.as<z64>(), b->N, b->n[p],
+                                b->F.as<z64>() + b->foff[p], ld, ld * ld);
+    }
+    if (b->mixed())
+      lu_grouped<c64>(b, false);
+    else
+      lu_grouped<z64>(b, false);
+  });
+  std::vector<int32_t> hinfo(static_cast<size_t>(b->P) * b->N);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), b->info.p, sizeof(int32_t) * hinfo.size(),
+                        hipMemcpyDeviceToHost, b->gs));
+  HIPCHK(hipStreamSynchronize(b->gs));
+  for (int p = 0; p < b->P; ++p)
+    for (int j = 0; j < b->N; ++j) {
+      const int32_t v = hinfo[static_cast<size_t>(p) * b->N + j];
+      if (v != 0) {
+        char buf[200];
+        const cd z = b->sub[p]->hz[j];
+        std::snprintf(buf, sizeof buf, "exact zero pivot in pencil %d at node %d (z = %.17g%+.17gi), column %d",
+                      b->order[p], j, z.real(), z.imag(), v - 1);
+        b->err = buf;
+        return FEAST_SINGULAR;
+      }
+    }
+  b->factored = true;
+  b->fkey = key;
+  return FEAST_OK;
+}
+
+// U_p = sum_j w_pj (z_pj B_p - A_p)^{-1} R_p for every pencil, with R_p in the
+// member plan's R block and U_p written to its W_UF block (graph).
+void filter_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
+                const feast_z *const *dB, const int64_t *ldb, int sweeps) {
+  const int N = b->N;
+  const int64_t nmax = b->nmax;
+  const std::vector<int64_t> key = make_key(b, dA, lda, dB, ldb, b->mixed() ? 1 + sweeps : 0);
+  run_graph(b, b->g_filter, key, [&]() {
+    hipStream_t s = b->gs;
+    const int32_t *perm = b->perm.as<int32_t>();
+    if (!b->mixed()) {
+      z64 *Y = b->Y.as<z64>();
+      for (int p = 0; p < b->P; ++p)
+        feast::gather_rows<z64>(s, b->sub[p]->R.as<z64>(), b->m[p], 0, perm + p * N * nmax, b->n[p],
+                                b->m[p], N, Y + b->yoff[p], b->ldY(p), b->m[p], nmax);
+      trsolve_grouped<z64>(b, Y);
+    } else {
+      z64 *Y = b->Y.as<z64>(), *T1 = b->T1.as<z64>(), *T2 = b->T2.as<z64>();
+      c64 *Yc = b->Yc.as<c64>();
+      for (int p = 0; p < b->P; ++p) {
+        const int64_t ldy = b->ldY(p);
+        feast::gather_rows<z64>(s, b->sub[p]->R.as<z64>(), b->m[p], 0, perm + p * N * nmax,
+                                b->n[p], b->m[p], N, T1 + b->toff[p], ldy, b->m[p], nmax);
+        feast::z_to_c(s, T1 + b->toff[p], ldy, 0, b->n[p], ldy, 1, Yc + b->yoff[p], ldy, 0);
+      }
+      trsolve_grouped<c64>(b, Yc);
+      for (int p = 0; p < b->P; ++p)
+        feast::c_to_z(s, Yc + b->yoff[p], b->ldY(p), 0, b->n[p], b->ldY(p), 1, Y + b->yoff[p],
+                      b->ldY(p), 0);
+      for (int sw = 0; sw < sweeps; ++sw) {
+        // FP64 residual r_j = R - z_j (B Y_j) + A Y_j of all nodes of a pencil
+        // as two products, then the complex64 correction
+        for (int p = 0; p < b->P; ++p) {
+          const int c = b->order[p];
+          const int64_t n = b->n[p], ldy = b->ldY(p);
+          const z64 *A = reinterpret_cast<const z64 *>(dA[c]);
+          const z64 *B = reinterpret_cast<const z64 *>(dB[c]);
+          z64 *t1 = T1 + b->toff[p], *t2 = T2 + b->toff[p], *y = Y + b->yoff[p];
+          gemm_t<z64>(s, 0, n, ldy, n, make_double2(1.0, 0.0), A, lda[c], 0, y, ldy, 0,
+                      make_double2(0.0, 0.0), t1, ldy, 0, 1);
+          gemm_t<z64>(s, 0, n, ldy, n, make_double2(1.0, 0.0), B, ldb[c], 0, y, ldy, 0,
+                      make_double2(0.0, 0.0), t2, ldy, 0, 1);
+          feast::shift_residual(s, b->sub[p]->R.as<z64>(), b->m[p], t1, t2, ldy,
+                                b->sub[p]->dz.as<z64>(), N, n, b->m[p]);
+          feast::gather_rows<z64>(s, t1, ldy, b->m[p], perm + p * N * nmax, n, b->m[p], N, t2, ldy,
+                                  b->m[p], nmax);
+          feast::z_to_c(s, t2, ldy, 0, n, ldy, 1, Yc + b->yoff[p], ldy, 0);
+        }
+        trsolve_grouped<c64>(b, Yc);
+        for (int p = 0; p < b->P; ++p)
+          feast::add_c_to_z(s, Yc + b->yoff[p], b->ldY(p), 0, b->n[p], b->ldY(p), 1,
+                            Y + b->yoff[p], b->ldY(p), 0);
+      }
+    }
+    const z64 *Y = b->Y.as<z64>();
+    for (int p = 0; p < b->P; ++p)
+      feast::weighted_sum(s, Y + b->yoff[p], b->ldY(p), b->m[p], b->sub[p]->dw.as<z64>(), N,
+                          b->n[p], b->m[p], b->sub[p]->wblk(feast_plan::W_UF), b->m[p]);
+  });
+}
+
+// The caller's stream -> batch stream -> caller's stream ordering.
+void enter(feast_batch *b) {
+  HIPCHK(hipEventRecord(b->ev_in, b->s));
+  HIPCHK(hipStreamWaitEvent(b->gs, b->ev_in, 0));
+}
+void leave(feast_batch *b) {
+  HIPCHK(hipEventRecord(b->ev_out, b->gs));
+  HIPCHK(hipStreamWaitEvent(b->s, b->ev_out, 0));
+}
+
+// Runs f(i) for i in [0, count) on up to `threads` host threads.
+template <class F> void parallel_for(int count, int threads, F &&f) {
+  threads = std::max(1, std::min(threads, count));
+  if (threads == 1) {
+    for (int i = 0; i < count; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t)
+    pool.emplace_back([&]() {
+      for (int i = next++; i < count; i = next++) f(i);
+    });
+  for (auto &th : pool) th.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const int64_t *m,
+                       const feast_contour *c, const feast_opts *o, void *stream) {
+  if (!out) return FEAST_EINVAL;
+  *out = nullptr;
+  if (count < 1 || count > 4096 || !n || !m || !c) return FEAST_EINVAL;
+  feast_opts opts;
+  feast_opts_default(&opts);
+  if (o) opts = *o;
+  if (!(opts.eta > 0.0) || !(opts.eps >= 0.0) || opts.max_iter < 1 ||
+      opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
+      opts.max_sweeps < 0)
+    return FEAST_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > 16384 || m[i] < 1 || m[i] > n[i] || bad_contour(&c[i]) ||
+        c[i].nodes != c[0].nodes)
+      return FEAST_EINVAL;
+  }
+  feast_batch *b = nullptr;
+  try {
+    b = new feast_batch();
+  } catch (...) {
+    return FEAST_ENOMEM;
+  }
+  b->P = count;
+  b->N = c[0].nodes;
+  b->o = opts;
+  b->s = static_cast<hipStream_t>(stream);
+  const int rc = bguarded(b, [&]() {
+    const int P = count, N = b->N;
+    b->order.resize(P);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    auto padded = [&](int i) { return (n[i] + kPanel - 1) / kPanel * kPanel; };
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return padded(x) > padded(y); });
+    b->where.resize(P);
+    for (int p = 0; p < P; ++p) b->where[b->order[p]] = p;
+    HIPCHK(hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    int64_t fo = 0, yo = 0, to = 0;
+    for (int p = 0; p < P; ++p) {
+      const int i = b->order[p];
+      b->n.push_back(n[i]);
+      b->m.push_back(m[i]);
+      b->np.push_back(padded(i));
+      b->foff.push_back(fo);
+      b->yoff.push_back(yo);
+      b->toff.push_back(to);
+      fo += static_cast<int64_t>(N) * b->np[p] * b->np[p];
+      yo += b->np[p] * N * m[i];
+      to += n[i] * N * m[i];
+      b->sub.push_back(member_plan(n[i], m[i], c[i], opts, b->gs));
+    }
+    b->nmax = b->np[0];
+    b->nblk = b->nmax / 64;
+    const int64_t nmat = static_cast<int64_t>(P) * N;
+    const size_t esz = b->mixed() ? sizeof(c64) : sizeof(z64);
+    b->F.alloc(esz * fo);
+    b->piv.alloc(sizeof(int32_t) * nmat * b->nmax);
+    b->perm.alloc(sizeof(int32_t) * nmat * b->nmax);
+    b->info.alloc(sizeof(int32_t) * nmat);
+    b->Linv.alloc(esz * nmat * b->istride());
+    b->Uinv.alloc(esz * nmat * b->istride());
+    // zero padding rows of the node solutions and the identity padding of the
+    // shifted matrices (never touched again: the factorisation keeps it), all
+    // ordered on the batch stream
+    b->Y.alloc(sizeof(z64) * yo);
+    HIPCHK(hipMemsetAsync(b->Y.p, 0, sizeof(z64) * yo, b->gs));
+    if (b->mixed()) {
+      b->Yc.alloc(sizeof(c64) * yo);
+      HIPCHK(hipMemsetAsync(b->Yc.p, 0, sizeof(c64) * yo, b->gs));
+      b->T1.alloc(sizeof(z64) * to);
+      b->T2.alloc(sizeof(z64) * to);
+    }
+    HIPCHK(hipMemsetAsync(b->F.p, 0, esz * fo, b->gs));
+    std::vector<GrpMat> g(P);
+    for (int p = 0; p < P; ++p) {
+      const int64_t ld = b->np[p];
+      void *base = static_cast<char *>(b->F.p) + esz * b->foff[p];
+      g[p] = GrpMat{base, ld, ld * ld, ld};
+      if (b->mixed())
+        feast::pad_diag<c64>(b->gs, static_cast<c64 *>(base), ld, ld * ld, N, b->n[p], ld);
+      else
+        feast::pad_diag<z64>(b->gs, static_cast<z64 *>(base), ld, ld * ld, N, b->n[p], ld);
+    }
+    b->grp.alloc(sizeof(GrpMat) * P);
+    HIPCHK(hipMemcpy(b->grp.p, g.data(), sizeof(GrpMat) * P, hipMemcpyHostToDevice));
+    // record the grouped GEMM tables of the factorisation and of a solve
+    if (b->mixed()) {
+      lu_grouped<c64>(b, true);
+      trsolve_grouped<c64>(b, b->Yc.as<c64>());
+    } else {
+      lu_grouped<z64>(b, true);
+      trsolve_grouped<z64>(b, b->Y.as<z64>());
+    }
+    b->lu_tab.upload();
+    b->sv_tab.upload();
+    HIPCHK(hipStreamSynchronize(b->gs));
+    return FEAST_OK;
+  });
+  if (rc != FEAST_OK) {
+    feast_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return FEAST_OK;
+}
+
+int feast_batch_destroy(feast_batch *b) {
+  if (!b) return FEAST_OK;
+  if (b->gs) (void)hipStreamSynchronize(b->gs);
+  b->g_factor.reset();
+  b->g_filter.reset();
+  for (feast_plan *p : b->sub) feast_plan_destroy(p);
+  for (DevBuf *d : {&b->F, &b->piv, &b->perm, &b->info, &b->Linv, &b->Uinv, &b->grp, &b->Y, &b->Yc,
+                    &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev})
+    d->release();
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->gs) (void)hipStreamDestroy(b->gs);
+  delete b;
+  return FEAST_OK;
+}
+
+int feast_batch_invalidate(feast_batch *b) {
+  if (!b) return FEAST_EINVAL;
+  b->factored = false;
+  b->fkey.clear();
+  return FEAST_OK;
+}
+
+const char *feast_batch_last_error(const feast_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int feast_batch_filter(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
+                       const feast_z *const *dB, const int64_t *ldb, const feast_z *const *dV,
+                       const int64_t *ldv, feast_z *const *dU, const int64_t *ldu, int32_t sweeps) {
+  if (!b) return FEAST_EINVAL;
+  if (!dA || !lda || !dB || !ldb || !dV || !ldv || !dU || !ldu || sweeps < 0 || sweeps > 16 ||
+      (sweeps > 0 && !b->mixed()))
+    return bfail(b, FEAST_EINVAL, "feast_batch_filter: bad argument");
+  for (int i = 0; i < b->P; ++i) {
+    const int p = b->where[i];
+    if (!dA[i] || !dB[i] || !dV[i] || !dU[i] || lda[i] < b->n[p] || ldb[i] < b->n[p] ||
+        ldv[i] < b->m[p] || ldu[i] < b->m[p])
+      return bfail(b, FEAST_EINVAL, "feast_batch_filter: null pointer or leading dimension too small");
+  }
+  b->err.clear();
+  return bguarded(b, [&]() -> int {
+    enter(b);
+    const int st = factor_all(b, dA, lda, dB, ldb);
+    if (st != FEAST_OK) return st;
+    for (int p = 0; p < b->P; ++p) {
+      const int c = b->order[p];
+      gemm_t<z64>(b->gs, 0, b->n[p], b->m[p], b->n[p], make_double2(1.0, 0.0),
+                  reinterpret_cast<const z64 *>(dB[c]), ldb[c], 0,
+                  reinterpret_cast<const z64 *>(dV[c]), ldv[c], 0, make_double2(0.0, 0.0),
+                  b->sub[p]->R.as<z64>(), b->m[p], 0, 1);
+    }
+    filter_all(b, dA, lda, dB, ldb, sweeps);
+    for (int p = 0; p < b->P; ++p) {
+      const int c = b->order[p];
+      feast::copy_block_z(b->gs, b->sub[p]->wblk(feast_plan::W_UF), b->m[p], b->n[p], b->m[p],
+                          reinterpret_cast<z64 *>(dU[c]), ldu[c]);
+    }
+    leave(b);
+    HIPCHK(hipGetLastError());
+    return FEAST_OK;
+  });
+}
+
+int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
+                      const feast_z *const *dB, const int64_t *ldb, const feast_z *const *dV,
+                      const int64_t *ldv, feast_z *const *hLambda, feast_z *const *dX,
+                      const int64_t *ldx, double *const *hRes, int32_t *s_found, double *err,
+                      int32_t *flag, int32_t *iters, feast_batch_info *info) {
+  if (!b) return FEAST_EINVAL;
+  if (!dA || !lda || !dB || !ldb || !dV || !ldv || !hLambda || !dX || !ldx || !s_found || !err ||
+      !flag || !iters)
+    return bfail(b, FEAST_EINVAL, "feast_batch_solve: null argument array");
+  for (int i = 0; i < b->P; ++i) {
+    const int p = b->where[i];
+    if (!dA[i] || !dB[i] || !dV[i] || !dX[i] || !hLambda[i] || lda[i] < b->n[p] ||
+        ldb[i] < b->n[p] || ldv[i] < b->m[p] || ldx[i] < b->m[p])
+      return bfail(b, FEAST_EINVAL, "feast_batch_solve: null pointer or leading dimension too small");
+  }
+  b->err.clear();
+  return bguarded(b, [&]() -> int {
+    const int P = b->P;
+    hipStream_t s = b->gs;
+    feast_batch_info inf{};
+    Timer total;
+    enter(b);
+    {
+      Timer t;
+      const int st = factor_all(b, dA, lda, dB, ldb);
+      inf.t_factor_ms = t.ms();
+      if (st != FEAST_OK) return st;
+    }
+    auto Ap = [&](int p) { return reinterpret_cast<const z64 *>(dA[b->order[p]]); };
+    auto Bp = [&](int p) { return reinterpret_cast<const z64 *>(dB[b->order[p]]); };
+    // per-pencil state of Algorithm 5
+    struct St {
+      bool done = false;
+      int c_prev = 0;
+      double e_prev = 0.0;
+      std::vector<cd> lam_prev;
+      std::vector<double> r_prev;
+      std::vector<feast_z> At, Bt, Yh, alpha, beta, lam;
+      std::vector<double> hn;
+    };
+    std::vector<St> st(P);
+    for (int p = 0; p < P; ++p) {
+      const int64_t m = b->m[p];
+      st[p].At.resize(m * m);
+      st[p].Bt.resize(m * m);
+      st[p].Yh.resize(m * m);
+      st[p].alpha.resize(m);
+      st[p].beta.resize(m);
+      st[p].lam.resize(m);
+      st[p].hn.resize(3 * m);
+    }
+    int sweeps = 0;  // mixed form: corrections per node (none on the first filter)
+    auto grouped_filter = [&]() {
+      Timer t;
+      filter_all(b, dA, lda, dB, ldb, b->mixed() ? sweeps : 0);
+      HIPCHK(hipStreamSynchronize(s));
+      inf.t_filter_ms += t.ms();
+      inf.filters += 1;
+    };
+    auto project_active = [&]() -> int {
+      Timer t;
+      for (int p = 0; p < P; ++p) {
+        if (st[p].done) continue;
+        feast_plan *q = b->sub[p];
+        const int64_t m = b->m[p];
+        feast::copy_block_z(s, q->wblk(feast_plan::W_UF), m, b->n[p], m, q->wblk(feast_plan::W_U1), m);
+        project_device(q, Ap(p), lda[b->order[p]], Bp(p), ldb[b->order[p]],
+                       q->wblk(feast_plan::W_U1), m, q->wblk(feast_plan::W_AU1), m,
+                       q->wblk(feast_plan::W_BU1), m);
+      }
+      for (int p = 0; p < P; ++p) {
+        if (st[p].done) continue;
+        const int r = project_finish(b->sub[p], st[p].At.data(), st[p].Bt.data());
+        if (r != FEAST_OK) {
+          b->err = "pencil " + std::to_string(b->order[p]) + ": " + b->sub[p]->err;
+          return r;
+        }
+      }
+      inf.t_project_ms += t.ms();
+      return FEAST_OK;
+    };
+    // line 1 (Search with the subspace size fixed): U = Q_N V
+    for (int p = 0; p < P; ++p) {
+      const int c = b->order[p];
+      gemm_t<z64>(s, 0, b->n[p], b->m[p], b->n[p], make_double2(1.0, 0.0), Bp(p), ldb[c], 0,
+                  reinterpret_cast<const z64 *>(dV[c]), ldv[c], 0, make_double2(0.0, 0.0),
+                  b->sub[p]->R.as<z64>(), b->m[p], 0, 1);
+    }
+    grouped_filter();
+    {
+      const int r = project_active();
+      if (r != FEAST_OK) return r;
+    }
+    const int nthreads =
+        static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    for (int k = 1; k <= b->o.max_iter; ++k) {
+      // line 6 for every active pencil, in parallel on the host
+      Timer te;
+      std::vector<int> act;
+      for (int p = 0; p < P; ++p)
+        if (!st[p].done) act.push_back(p);
+      std::vector<int> qz(P, 0);
+      parallel_for(static_cast<int>(act.size()), nthreads, [&](int i) {
+        const int p = act[i];
+        const int64_t m = b->m[p];
+        qz[p] = feast_host::reduced_eig(m, reinterpret_cast<const cd *>(st[p].At.data()), m,
+                                        reinterpret_cast<const cd *>(st[p].Bt.data()), m,
+                                        reinterpret_cast<cd *>(st[p].alpha.data()),
+                                        reinterpret_cast<cd *>(st[p].beta.data()),
+                                        reinterpret_cast<cd *>(st[p].Yh.data()), m, 1);
+      });
+      inf.t_host_eig_ms += te.ms();
+      for (int p : act)
+        if (qz[p] != 0) return bfail(b, FEAST_ENUMERIC, "reduced QZ did not converge in pencil " +
+                                                          std::to_string(b->order[p]));
+      // lines 7-9: Ritz vectors and the norms of eq. 5-1 on the device
+      std::vector<std::vector<cd>> lam(P);
+      for (int p : act) {
+        feast_plan *q = b->sub[p];
+        const int64_t n = b->n[p], m = b->m[p];
+        lam[p].resize(m);
+        for (int64_t i = 0; i < m; ++i) {
+          const cd a(st[p].alpha[i].re, st[p].alpha[i].im), be(st[p].beta[i].re, st[p].beta[i].im);
+          lam[p][i] = (be != cd(0.0)) ? a / be : cd(INFINITY, 0.0);
+          st[p].lam[i] = std::isfinite(lam[p][i].real()) ? feast_z{lam[p][i].real(), lam[p][i].imag()}
+                                                         : feast_z{0, 0};
+        }
+        z64 *Ys = q->gblk(feast_plan::G_YS), *dlam = q->small.as<z64>();
+        HIPCHK(hipMemcpyAsync(Ys, st[p].Yh.data(), sizeof(z64) * m * m, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dlam, st[p].lam.data(), sizeof(z64) * m, hipMemcpyHostToDevice, s));
+        const z64 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
+        gemm_t<z64>(s, 0, n, m, m, one, q->wblk(feast_plan::W_U1), m, 0, Ys, m, 0, zero,
+                    q->wblk(feast_plan::W_X), m, 0, 1);
+        gemm_t<z64>(s, 0, n, m, m, one, q->wblk(feast_plan::W_AU1), m, 0, Ys, m, 0, zero,
+                    q->wblk(feast_plan::W_AX), m, 0, 1);
+        gemm_t<z64>(s, 0, n, m, m, one, q->wblk(feast_plan::W_BU1), m, 0, Ys, m, 0, zero,
+                    q->wblk(feast_plan::W_BX), m, 0, 1);
+        feast::ritz_norms(s, q->wblk(feast_plan::W_AX), q->wblk(feast_plan::W_BX), m, n, m, dlam,
+                          q->part.as<double>(), q->nrm.as<double>());
+        HIPCHK(hipMemcpyAsync(st[p].hn.data(), q->nrm.p, sizeof(double) * 3 * m,
+                              hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(hipStreamSynchronize(s));
+      // lines 10-15 per pencil
+      bool refine_more = false;
+      for (int p : act) {
+        feast_plan *q = b->sub[p];
+        const int c = b->order[p];
+        const int64_t n = b->n[p], m = b->m[p];
+        const cd gamma(q->c.center.re, q->c.center.im);
+        std::vector<int32_t> sel;
+        std::vector<double> rsel;
+        double e_k = 0.0;
+        for (int64_t i = 0; i < m; ++i) {
+          if (!std::isfinite(lam[p][i].real()) || !std::isfinite(lam[p][i].imag())) continue;
+          const double den = std::sqrt(st[p].hn[3 * i + 1]) + std::sqrt(st[p].hn[3 * i + 2]);
+          const double r = den > 0.0 ? std::sqrt(st[p].hn[3 * i]) / den : INFINITY;
+          if (std::abs(lam[p][i] - gamma) < q->c.radius && r < b->o.eta) {
+            sel.push_back(static_cast<int32_t>(i));
+            rsel.push_back(r);
+            e_k = std::max(e_k, r);
+          }
+        }
+        const int c_k = static_cast<int>(sel.size());
+        if (c_k == 0) e_k = INFINITY;
+        const int a = feast_host::stop_rule(k, c_k, e_k, st[p].c_prev, st[p].e_prev, b->o.eps,
+                                            b->o.max_iter);
+        int32_t *didx = reinterpret_cast<int32_t *>(q->small.as<z64>() + m);
+        if (a == 1 || a == -1) {
+          if (c_k > 0) {
+            HIPCHK(hipMemcpy(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice));
+            feast::gather_normalize_cols(s, q->wblk(feast_plan::W_X), m, n, didx, c_k,
+                                         reinterpret_cast<z64 *>(dX[c]), ldx[c], nullptr);
+            HIPCHK(hipStreamSynchronize(s));
+          }
+          for (int i = 0; i < c_k; ++i) {
+            hLambda[c][i] = {lam[p][sel[i]].real(), lam[p][sel[i]].imag()};
+            if (hRes && hRes[c]) hRes[c][i] = rsel[i];
+          }
+          s_found[c] = c_k;
+          err[c] = e_k;
+          flag[c] = a;
+          iters[c] = k;
+          st[p].done = true;
+          continue;
+        }
+        if (a == 0) {
+          const int cp = static_cast<int>(st[p].lam_prev.size());
+          feast::copy_block_z(s, q->wblk(feast_plan::W_XPREV), m, n, cp,
+                              reinterpret_cast<z64 *>(dX[c]), ldx[c]);
+          for (int i = 0; i < cp; ++i) {
+            hLambda[c][i] = {st[p].lam_prev[i].real(), st[p].lam_prev[i].imag()};
+            if (hRes && hRes[c]) hRes[c][i] = st[p].r_prev[i];
+          }
+          s_found[c] = cp;
+          err[c] = st[p].e_prev;
+          flag[c] = 0;
+          iters[c] = k;
+          st[p].done = true;
+          continue;
+        }
+        // keep iterate k for a possible rebound at k+1
+        st[p].lam_prev.clear();
+        st[p].r_prev = rsel;
+        for (int i = 0; i < c_k; ++i) st[p].lam_prev.push_back(lam[p][sel[i]]);
+        if (c_k > 0) {
+          HIPCHK(hipMemcpy(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice));
+          feast::gather_normalize_cols(s, q->wblk(feast_plan::W_X), m, n, didx, c_k,
+                                       q->wblk(feast_plan::W_XPREV), m, nullptr);
+        }
+        if (b->mixed() && k >= 2 && c_k == st[p].c_prev && e_k >= b->o.eps) refine_more = true;
+        st[p].e_prev = e_k;
+        st[p].c_prev = c_k;
+      }
+      inf.iters = k;
+      bool any = false;
+      for (int p = 0; p < P; ++p) any = any || !st[p].done;
+      if (!any) break;
+      // line 16 for the pencils still iterating (one grouped filter), line 17
+      if (b->mixed()) {
+        if (sweeps == 0) sweeps = 1;
+        else if (refine_more && sweeps < b->o.max_sweeps) ++sweeps;
+      }
+      for (int p = 0; p < P; ++p)
+        if (!st[p].done)
+          feast::copy_block_z(s, b->sub[p]->wblk(feast_plan::W_BU1), b->m[p], b->n[p], b->m[p],
+                              b->sub[p]->R.as<z64>(), b->m[p]);
+      grouped_filter();
+      const int r = project_active();
+      if (r != FEAST_OK) return r;
+    }
+    leave(b);
+    HIPCHK(hipStreamSynchronize(s));
+    inf.t_total_ms = total.ms();
+    inf.graph_launches = b->launches;
+    if (info) *info = inf;
+    return FEAST_OK;
+  });
+}
+
+}  // extern "C"

@@ -63,6 +63,32 @@ template <> struct cplx_traits<c64> {
   }
 };
 
+// Matrices of a grouped launch.  Matrix b belongs to entry b / nodes (one
+// pencil) and is its node b % nodes: order n, leading dimension ld, at
+// base + (b % nodes) * stride.  Per-matrix side arrays (pivots, info,
+// inverted blocks) stay flat over b with the stride of the largest order.
+struct GrpMat {
+  void *base;
+  int64_t ld, stride, n;
+};
+
+template <typename T> struct MatRef {
+  T *M;
+  int64_t ld, n;
+};
+
+// Matrix b of a uniform batch (g == nullptr: base + b * stride, order n) or of
+// a grouped one.
+template <typename T>
+__device__ inline MatRef<T> mat_of(const GrpMat *g, int nodes, T *base, int64_t ld, int64_t stride,
+                                   int64_t n, int b) {
+  if (g) {
+    const GrpMat e = g[b / nodes];
+    return {static_cast<T *>(e.base) + (b % nodes) * e.stride, e.ld, e.n};
+  }
+  return {base + b * stride, ld, n};
+}
+
 // Map a linear workgroup id onto a contiguous slice of the work per XCD.
 // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs of an
 // MI355X; giving each XCD a contiguous range of tiles keeps the tiles that

@@ -24,114 +24,12 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/feast.h"
 #include "host_eig.h"
-#include "kernels.h"
+#include "plan.h"
 
-using feast::c64;
-using feast::z64;
-using cd = std::complex<double>;
+using namespace feast_drv;
 
 namespace {
-
-constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
-
-inline z64 zc(double r, double i = 0.0) { return make_double2(r, i); }
-
-struct HipError {
-  hipError_t e;
-  const char *what;
-};
-
-#define HIPCHK(x)                                   \
-  do {                                              \
-    hipError_t e_ = (x);                            \
-    if (e_ != hipSuccess) throw HipError{e_, #x};   \
-  } while (0)
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  void alloc(size_t b) {
-    if (bytes >= b && p) return;
-    release();
-    if (b == 0) return;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      p = nullptr;
-      bytes = 0;
-      throw HipError{e, "hipMalloc"};
-    }
-    bytes = b;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  template <typename T> T *as() const { return static_cast<T *>(p); }
-};
-
-struct Timer {
-  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-  double ms() const {
-    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  }
-};
-
-}  // namespace
-
-struct feast_plan {
-  int64_t n = 0, m = 0;
-  int N = 0;
-  feast_contour c{};
-  feast_opts o{};
-  hipStream_t s = nullptr;
-  int nb = 64;
-  int64_t nblk = 0;
-  std::vector<cd> hz, hw;
-  DevBuf dz, dw, dwc;  // nodes, weights, conjugated weights
-  // cached factors
-  bool factored = false;
-  const void *fA = nullptr, *fB = nullptr;
-  int64_t flda = 0, fldb = 0;
-  DevBuf F, piv, perm, info, Linv, Uinv;
-  double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
-  // workspaces
-  DevBuf R, Y, T1, T2, Yc, W, G, dinv, splitws, part, nrm, flag, small;
-  DevBuf adj, adj_piv, adj_info, adj_inv;  // adjoint solves (allocated on first use)
-  std::string err;
-  int last_sweeps = 0;       // mixed form: sweeps of the last filter
-  double last_be = 0.0;      // mixed form: worst node backward error of the last filter
-  bool stagnated = false;    // mixed form: the last filter missed its target
-  // opts.profile: events around the LU trailing-update GEMMs
-  std::vector<hipEvent_t> ev;
-  hipStream_t side = nullptr;                 // look-ahead panel stream
-  hipStream_t aux = nullptr;                  // Ritz vectors/residuals overlapping a filter
-  hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
-  int prof_launches = 0;
-  double prof_ms = 0.0, prof_flops = 0.0;
-
-  // n x m work blocks inside W
-  enum { W_ORTH = 0, W_U2 = 1, W_X = 2, W_AX = 3, W_BX = 4, W_XPREV = 5, W_U1 = 6, W_AU1 = 7,
-         W_BU1 = 8, W_UF = 9, W_COUNT = 10 };
-  // m x m blocks inside G
-  enum { G_GRAM = 0, G_RINV = 1, G_T = 2, G_AT = 3, G_BT = 4, G_YS = 5, G_COUNT = 6 };
-  z64 *wblk(int i) const { return W.as<z64>() + static_cast<int64_t>(i) * n * m; }
-  z64 *gblk(int i) const { return G.as<z64>() + static_cast<int64_t>(i) * m * m; }
-
-  bool mixed() const { return o.prec == FEAST_MIXED; }
-  int64_t ldY() const { return static_cast<int64_t>(N) * m; }
-  int64_t fstride() const { return n * n; }
-  int64_t istride() const { return nblk * 64 * 64; }  // inverted 64 x 64 diagonal blocks
-};
-
-namespace {
-
-int fail(feast_plan *p, int code, const std::string &msg) {
-  if (p) p->err = msg;
-  return code;
-}
 
 // ---------------------------------------------------------------------------
 // Blocked right-looking LU of `batch` matrices (row-major, partial pivoting).
@@ -141,23 +39,6 @@ int fail(feast_plan *p, int code, const std::string &msg) {
 // an in-place MFMA product with the inverted diagonal block, and the trailing
 // update A22 -= L21 U12 is one batched MFMA GEMM over all matrices.
 // ---------------------------------------------------------------------------
-template <typename T>
-void gemm_t(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const T *A,
-            int64_t lda, int64_t sA, const T *B, int64_t ldb, int64_t sB, z64 beta, T *C,
-            int64_t ldc, int64_t sC, int32_t batch, T *work = nullptr, int64_t welems = 0);
-template <>
-void gemm_t<z64>(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
-                 int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,
-                 int64_t ldc, int64_t sC, int32_t batch, z64 *work, int64_t welems) {
-  feast::zgemm(s, ta, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, work, welems);
-}
-template <>
-void gemm_t<c64>(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const c64 *A,
-                 int64_t lda, int64_t sA, const c64 *B, int64_t ldb, int64_t sB, z64 beta, c64 *C,
-                 int64_t ldc, int64_t sC, int32_t batch, c64 *work, int64_t welems) {
-  feast::cgemm(s, ta, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, work, welems);
-}
-
 template <typename T>
 void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
                int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info) {
@@ -257,7 +138,7 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
     const bool timed = prof && prof->ev && prof->used + 2 <= static_cast<int>(prof->ev->size());
     if (timed) HIPCHK(hipEventRecord((*prof->ev)[prof->used], s));
     gemm_t<T>(s, 0, rows, cols, kb, zc(-1.0), Ap, ld, stride, Bp, ld, stride, zc(1.0), Cp, ld,
-              stride, batch);
+              stride, batch, nullptr, 0, feast::GEMM_UPDATE);
     if (timed) {
       HIPCHK(hipEventRecord((*prof->ev)[prof->used + 1], s));
       prof->used += 2;
@@ -320,31 +201,6 @@ void trsolve(hipStream_t s, const T *F, int64_t ld, int64_t fstride, int32_t bat
 // Plan helpers
 // ---------------------------------------------------------------------------
 
-void ensure_workspace(feast_plan *p) {
-  const int64_t n = p->n, m = p->m, N = p->N;
-  const size_t zs = sizeof(z64);
-  p->R.alloc(zs * n * m);
-  p->Y.alloc(zs * n * m * N);
-  p->W.alloc(zs * n * m * feast_plan::W_COUNT);
-  p->G.alloc(zs * m * m * feast_plan::G_COUNT);
-  p->dinv.alloc(zs * ((m + 63) / 64) * 64 * 64);
-  p->splitws.alloc(zs * std::max<int64_t>(m * m * 96, 1 << 16));
-  p->part.alloc(sizeof(double) * std::max<int64_t>(((n + 63) / 64) * 3 * m, 64 * N + 64));
-  p->nrm.alloc(sizeof(double) * (3 * m + 4 * N + 16));
-  p->flag.alloc(sizeof(int32_t) * 16);
-  p->small.alloc(zs * (2 * m + 16));
-  if (p->mixed()) {
-    p->T1.alloc(zs * n * m * N);
-    p->T2.alloc(zs * n * m * N);
-    p->Yc.alloc(sizeof(c64) * n * m * N);
-  }
-}
-
-int64_t splitws_elems(const feast_plan *p) {
-  return static_cast<int64_t>(p->splitws.bytes / sizeof(z64));
-}
-
-// Factor every shifted matrix z_j B - A once and cache the factors (Section 4.3).
 int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
   const int64_t n = p->n;
   const int N = p->N;
@@ -570,6 +426,56 @@ void inv_upper_blocked(feast_plan *p, const z64 *R, int64_t t, z64 *X, z64 *T) {
 // s = 11 (n m + m (m+1)) u ||X||_F^2): an FP64 orthonormalisation that stays
 // stable for condition numbers up to about 1/u, built from the Gram GEMM,
 // a blocked t x t Cholesky, a blocked triangular inverse and one more GEMM per pass.
+}  // namespace
+
+// Helpers shared with the batched driver (declared in plan.h).
+namespace feast_drv {
+
+int fail(feast_plan *p, int code, const std::string &msg) {
+  if (p) p->err = msg;
+  return code;
+}
+
+template <>
+void gemm_t<z64>(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
+                 int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,
+                 int64_t ldc, int64_t sC, int32_t batch, z64 *work, int64_t welems, int cfg) {
+  feast::zgemm(s, ta, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, work, welems,
+               cfg);
+}
+template <>
+void gemm_t<c64>(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const c64 *A,
+                 int64_t lda, int64_t sA, const c64 *B, int64_t ldb, int64_t sB, z64 beta, c64 *C,
+                 int64_t ldc, int64_t sC, int32_t batch, c64 *work, int64_t welems, int cfg) {
+  feast::cgemm(s, ta, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, work, welems,
+               cfg);
+}
+
+void ensure_workspace(feast_plan *p, bool with_nodes) {
+  const int64_t n = p->n, m = p->m, N = p->N;
+  const size_t zs = sizeof(z64);
+  p->R.alloc(zs * n * m);
+  if (with_nodes) p->Y.alloc(zs * n * m * N);
+  p->W.alloc(zs * n * m * feast_plan::W_COUNT);
+  p->G.alloc(zs * m * m * feast_plan::G_COUNT);
+  p->dinv.alloc(zs * ((m + 63) / 64) * 64 * 64);
+  p->splitws.alloc(zs * std::max<int64_t>(m * m * 96, 1 << 16));
+  p->part.alloc(sizeof(double) * std::max<int64_t>(((n + 63) / 64) * 3 * m, 64 * N + 64));
+  p->nrm.alloc(sizeof(double) * (3 * m + 4 * N + 16));
+  p->flag.alloc(sizeof(int32_t) * 16);
+  p->small.alloc(zs * (2 * m + 16));
+  if (p->mixed() && with_nodes) {
+    p->T1.alloc(zs * n * m * N);
+    p->T2.alloc(zs * n * m * N);
+    p->Yc.alloc(sizeof(c64) * n * m * N);
+  }
+}
+
+int64_t splitws_elems(const feast_plan *p) {
+  return static_cast<int64_t>(p->splitws.bytes / sizeof(z64));
+}
+
+// Factor every shifted matrix z_j B - A once and cache the factors (Section 4.3).
 void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot) {
   const int64_t n = p->n, m = p->m;
   hipStream_t s = p->s;
@@ -632,25 +538,7 @@ bool bad_contour(const feast_contour *c) {
          (c->rule != FEAST_TRAPEZOID && c->rule != FEAST_GAUSS_LEGENDRE);
 }
 
-template <typename F> int guarded(feast_plan *p, F &&f) {
-  try {
-    return f();
-  } catch (const HipError &e) {
-    if (p) {
-      p->err = std::string(e.what) + ": " + hipGetErrorString(e.e);
-      p->factored = false;
-    }
-    return e.e == hipErrorOutOfMemory ? FEAST_ENOMEM : FEAST_EDEVICE;
-  } catch (const std::bad_alloc &) {
-    if (p) p->err = "host allocation failed";
-    return FEAST_ENOMEM;
-  } catch (...) {
-    if (p) p->err = "unexpected exception";
-    return FEAST_EDEVICE;
-  }
-}
-
-}  // namespace
+}  // namespace feast_drv
 
 // ===========================================================================
 // C ABI

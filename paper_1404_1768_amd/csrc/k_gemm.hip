@@ -54,8 +54,9 @@ template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
 // before the K loop, so its latency overlaps the first operand loads) and the
 // MFMAs use -A; the epilogue is then a plain store.  SUB = false is the general
 // C = alpha op(A) B + beta C with the C read in the epilogue.
+// One output tile: `lin` indexes the tiles x batch x splits of problem d.
 template <typename T, int BM, int BN, int TA, bool SUB, int BK>
-__global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   using Ops = mfma_ops<T>;
   using real = typename Ops::real;
   using acc_t = typename Ops::acc_t;
@@ -69,7 +70,6 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
   const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
   const int64_t tiles = tm * tn;
   const int64_t total = tiles * d.batch * d.splits;
-  int64_t lin = xcd_remap(blockIdx.x, grid_total);
   if (lin >= total) return;
   const int64_t tile = lin % tiles;
   lin /= tiles;
@@ -246,6 +246,30 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_
       }
 }
 
+// UPD only renames the instance used for the LU trailing update (same code), so
+// that kernel traces time that update on its own.
+template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool UPD = false>
+__global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
+  gemm_tile<T, BM, BN, TA, SUB, BK>(d, xcd_remap(blockIdx.x, grid_total));
+}
+
+// A group of independent problems in one launch: tab[e].tile0 is the first
+// linear tile of problem e (increasing); a workgroup finds its problem by
+// bisection over the table.
+template <typename T, int BM, int BN, int TA, bool SUB, int BK>
+__global__ __launch_bounds__(256) void k_gemm_grp(const GemmArgs<T> *__restrict__ tab, int count,
+                                                  int64_t grid_total) {
+  const int64_t lin = xcd_remap(blockIdx.x, grid_total);
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].tile0 <= lin) lo = mid;
+    else hi = mid - 1;
+  }
+  const GemmArgs<T> d = tab[lo];
+  gemm_tile<T, BM, BN, TA, SUB, BK>(d, lin - d.tile0);
+}
+
 // Deterministic reduction of split-K partials: C = sum_s W_s + beta C.
 template <typename T>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmArgs<T> d) {
@@ -273,7 +297,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmArgs<T> d) {
 }
 
 template <typename T, int BM, int BN, int BK = 16>
-void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta) {
+void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta, bool update = false) {
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
   const int64_t total = tiles * d.batch * d.splits;
   const int64_t padded = (total + 7) / 8 * 8;
@@ -282,7 +306,9 @@ void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta) {
   const bool sub = d.splits == 1 && d.alpha.x == -1.0 && d.alpha.y == 0.0 && d.beta.x == 1.0 &&
                    d.beta.y == 0.0;
   if (ta == 0) {
-    if (sub)
+    if (sub && update)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, BK, true>), grid, dim3(256), 0, s, d, padded);
+    else if (sub)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, BK>), grid, dim3(256), 0, s, d, padded);
     else
       hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, false, BK>), grid, dim3(256), 0, s, d, padded);
@@ -296,7 +322,6 @@ void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta) {
 
 template <typename T>
 void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems) {
-  // (cfg may be upgraded to GEMM_BIG below)
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   if (d.K <= 0) {
     // C = beta C: a GEMM with an empty K range does exactly that.
@@ -306,7 +331,7 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
   d.kchunk = d.K > 0 ? d.K : 1;
   // (a 128 x 128 complex64 tile measured slower than 64 x 64 in the LU update,
   // and the FP64 one needs more than the 512 registers of a lane: not used)
-  const int BM = (cfg == GEMM_TALL || cfg == GEMM_BIG) ? 128 : 64;
+  const int BM = (cfg == GEMM_TALL) ? 128 : 64;
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + 63) / 64);
   // Split K when the output is too small to fill the chip.
   if (d.work && d.K >= 512 && tiles * d.batch < 192) {
@@ -322,7 +347,7 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
   if (cfg == GEMM_TALL)
     launch_cfg<T, 128, 64>(s, d, ta);
   else
-    launch_cfg<T, 64, 64>(s, d, ta);
+    launch_cfg<T, 64, 64>(s, d, ta, cfg == GEMM_UPDATE);
   if (d.splits > 1) {
     const int64_t n = d.M * d.N * d.batch;
     hipLaunchKernelGGL((k_splitk_reduce<T>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256),
@@ -332,17 +357,52 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
 
 }  // namespace
 
+template <typename T>
+int64_t gemm_group_tiles(GemmArgs<T> *tab, int count) {
+  int64_t t = 0;
+  for (int e = 0; e < count; ++e) {
+    tab[e].splits = 1;
+    tab[e].kchunk = tab[e].K > 0 ? tab[e].K : 1;
+    tab[e].tile0 = t;
+    t += ((tab[e].M + 63) / 64) * ((tab[e].N + 63) / 64) * tab[e].batch;
+  }
+  return t;
+}
+template int64_t gemm_group_tiles<z64>(GemmArgs<z64> *, int);
+template int64_t gemm_group_tiles<c64>(GemmArgs<c64> *, int);
+
+template <typename T>
+void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int count,
+                int64_t total_tiles) {
+  if (count <= 0 || total_tiles <= 0) return;
+  const int64_t padded = (total_tiles + 7) / 8 * 8;
+  const dim3 grid(static_cast<unsigned>(padded));
+  if (ta == 0) {
+    if (sub)
+      hipLaunchKernelGGL((k_gemm_grp<T, 64, 64, 0, true, 16>), grid, dim3(256), 0, s, dtab, count,
+                         padded);
+    else
+      hipLaunchKernelGGL((k_gemm_grp<T, 64, 64, 0, false, 16>), grid, dim3(256), 0, s, dtab, count,
+                         padded);
+  } else {
+    hipLaunchKernelGGL((k_gemm_grp<T, 64, 64, 2, false, 16>), grid, dim3(256), 0, s, dtab, count,
+                       padded);
+  }
+}
+template void gemm_group<z64>(hipStream_t, int, bool, const GemmArgs<z64> *, int, int64_t);
+template void gemm_group<c64>(hipStream_t, int, bool, const GemmArgs<c64> *, int, int64_t);
+
 void zgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
            int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,
            int64_t ldc, int64_t sC, int32_t batch, z64 *work, int64_t work_elems, int cfg) {
-  GemmArgs<z64> d{M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, batch, 1, K, work};
+  GemmArgs<z64> d{M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, batch, 1, K, work, 0};
   gemm_impl<z64>(s, d, transA, cfg, work_elems);
 }
 
 void cgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha, const c64 *A,
            int64_t lda, int64_t sA, const c64 *B, int64_t ldb, int64_t sB, z64 beta, c64 *C,
            int64_t ldc, int64_t sC, int32_t batch, c64 *work, int64_t work_elems, int cfg) {
-  GemmArgs<c64> d{M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, batch, 1, K, work};
+  GemmArgs<c64> d{M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta, batch, 1, K, work, 0};
   gemm_impl<c64>(s, d, transA, cfg, work_elems);
 }
 

@@ -31,14 +31,18 @@ template <typename T> __device__ inline T czero() {
 // panel [pk0, pk0+pkb) as one gather: the composed permutation of the at most
 // 2w rows involved is read in full before any of it is written.
 template <typename T, int RPT, int IB>
-__global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld, int64_t stride,
-                                               int64_t n, int64_t c0, int w, int64_t pk0,
+__global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld_in, int64_t stride,
+                                               int64_t n_in, int64_t c0, int w, int64_t pk0,
                                                int pkb, int32_t *__restrict__ ipiv_all,
-                                               int32_t *__restrict__ info_all) {
+                                               int32_t *__restrict__ info_all,
+                                               const GrpMat *__restrict__ grp, int nodes) {
   using Tr = cplx_traits<T>;
   const int b = blockIdx.x;
-  T *M = Mall + b * stride;
-  int32_t *ipiv = ipiv_all + b * n;
+  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, b);
+  T *M = mr.M;
+  const int64_t ld = mr.ld, n = mr.n;
+  if (c0 + w > n) return;  // (grouped: this matrix is already factored)
+  int32_t *ipiv = ipiv_all + b * n_in;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double s_val[2][16];
   __shared__ int s_idx[2][16];
@@ -210,13 +214,17 @@ __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_laswp_outside(T *__restrict__ Mall, int64_t ld,
-                                                       int64_t stride, int64_t n, int64_t r0,
+__global__ __launch_bounds__(256) void k_laswp_outside(T *__restrict__ Mall, int64_t ld_in,
+                                                       int64_t stride, int64_t n_in, int64_t r0,
                                                        int kb, int64_t clo, int64_t chi,
-                                                       const int32_t *__restrict__ ipiv_all) {
+                                                       const int32_t *__restrict__ ipiv_all,
+                                                       const GrpMat *__restrict__ grp, int nodes) {
   const int b = blockIdx.y;
-  T *M = Mall + b * stride;
-  const int32_t *ipiv = ipiv_all + b * n;
+  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, b);
+  T *M = mr.M;
+  const int64_t ld = mr.ld, n = mr.n;
+  if (r0 + kb > n) return;
+  const int32_t *ipiv = ipiv_all + b * n_in;
   const int64_t t = blockIdx.x * 256ll + threadIdx.x;
   const int64_t ncols = clo + (n - chi);
   if (t >= ncols) return;
@@ -269,13 +277,17 @@ __global__ __launch_bounds__(64) void k_trsm_small(T *__restrict__ Mall, int64_t
 // the traffic of C, so it runs on the VALU.
 constexpr int kPU = 32;
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int64_t ld,
-                                                      int64_t stride, int64_t n, int64_t c0, int w1,
-                                                      int w2, bool write_x) {
+__global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int64_t ld_in,
+                                                      int64_t stride, int64_t n_in, int64_t c0,
+                                                      int w1, int w2, bool write_x,
+                                                      const GrpMat *__restrict__ grp, int nodes) {
   using Tr = cplx_traits<T>;
   __shared__ T sL[64][kPU + 1];
   __shared__ T sX[kPU][kPU + 1];
-  T *M = Mall + blockIdx.y * stride;
+  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, blockIdx.y);
+  T *M = mr.M;
+  const int64_t ld = mr.ld, n = mr.n;
+  if (c0 + w1 + w2 > n) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < w1 * w1; e += 256) {
     const int i = e / w1, k = e % w1;
@@ -356,16 +368,19 @@ __global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int6
 
 // Inverse of one diagonal block (lower unit or upper non-unit), one thread per column.
 template <typename T>
-__global__ __launch_bounds__(64) void k_diag_inv(const T *__restrict__ Mall, int64_t ld,
-                                                 int64_t stride, int64_t n, int nb, int64_t blk0,
+__global__ __launch_bounds__(64) void k_diag_inv(const T *__restrict__ Mall, int64_t ld_in,
+                                                 int64_t stride, int64_t n_in, int nb, int64_t blk0,
                                                  bool lower, T *__restrict__ out,
-                                                 int64_t out_stride) {
+                                                 int64_t out_stride,
+                                                 const GrpMat *__restrict__ grp, int nodes) {
   using Tr = cplx_traits<T>;
   __shared__ T sD[64][65];
   __shared__ T sX[64][65];
   const int64_t I = blk0 + blockIdx.x;
   const int b = blockIdx.y;
-  const T *M = Mall + b * stride;
+  const MatRef<const T> mr = mat_of<const T>(grp, nodes, Mall, ld_in, stride, n_in, b);
+  const T *M = mr.M;
+  const int64_t ld = mr.ld, n = mr.n;
   const int64_t r0 = I * nb;
   const int rb = static_cast<int>((n - r0 < nb) ? n - r0 : nb);
   const int tid = threadIdx.x;
@@ -398,12 +413,16 @@ __global__ __launch_bounds__(64) void k_diag_inv(const T *__restrict__ Mall, int
     if (tid < nb) o[i * nb + tid] = (i < rb && tid < rb) ? sX[i][tid] : czero<T>();
 }
 
+// n: order (pivot vectors of the batch are n_stride apart; grouped batches read
+// each matrix's order from grp)
 __global__ __launch_bounds__(256) void k_perm(const int32_t *__restrict__ ipiv_all,
-                                              int32_t *__restrict__ perm_all, int64_t n) {
+                                              int32_t *__restrict__ perm_all, int64_t n_stride,
+                                              const GrpMat *__restrict__ grp, int nodes) {
   extern __shared__ int32_t sp[];
   const int b = blockIdx.x;
-  const int32_t *ipiv = ipiv_all + b * n;
-  int32_t *perm = perm_all + b * n;
+  const int64_t n = grp ? grp[b / nodes].n : n_stride;
+  const int32_t *ipiv = ipiv_all + b * n_stride;
+  int32_t *perm = perm_all + b * n_stride;
   for (int64_t i = threadIdx.x; i < n; i += 256) sp[i] = static_cast<int32_t>(i);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -425,9 +444,10 @@ __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
 
 template <typename T, int RPT, int IB>
 void launch_leaf(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                 int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info) {
+                 int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
+                 const GrpMat *grp, int nodes) {
   hipLaunchKernelGGL((k_leaf<T, RPT, IB>), dim3(batch), dim3(1024), 0, s, M, ld, stride, n, c0, w,
-                     pk0, pkb, ipiv, info);
+                     pk0, pkb, ipiv, info, grp, nodes);
 }
 
 }  // namespace
@@ -448,52 +468,55 @@ template <> int leaf_max_width<c64>(int64_t rows) {
 
 template <>
 bool leaf_lu<z64>(hipStream_t s, z64 *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info) {
+                  int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
+                  const GrpMat *grp, int nodes) {
   const int64_t rows = n - c0;
   if (w < 1 || w > leaf_max_width<z64>(rows) || pkb > 1024) return false;
   if (rows <= 1024)
-    launch_leaf<z64, 1, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<z64, 1, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 2048)
-    launch_leaf<z64, 2, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<z64, 2, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 4096)
-    launch_leaf<z64, 4, 4>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<z64, 4, 4>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 8192)
-    launch_leaf<z64, 8, 2>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<z64, 8, 2>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else
-    launch_leaf<z64, 16, 1>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<z64, 16, 1>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   return true;
 }
 
 template <>
 bool leaf_lu<c64>(hipStream_t s, c64 *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info) {
+                  int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
+                  const GrpMat *grp, int nodes) {
   const int64_t rows = n - c0;
   if (w < 1 || w > leaf_max_width<c64>(rows) || pkb > 1024) return false;
   if (rows <= 1024)
-    launch_leaf<c64, 1, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<c64, 1, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 2048)
-    launch_leaf<c64, 2, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<c64, 2, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 4096)
-    launch_leaf<c64, 4, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<c64, 4, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 8192)
-    launch_leaf<c64, 8, 4>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<c64, 8, 4>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else
-    launch_leaf<c64, 16, 2>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info);
+    launch_leaf<c64, 16, 2>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   return true;
 }
 
 template <typename T>
 void laswp_outside(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                   int64_t r0, int kb, int64_t clo, int64_t chi, const int32_t *ipiv) {
+                   int64_t r0, int kb, int64_t clo, int64_t chi, const int32_t *ipiv,
+                   const GrpMat *grp, int nodes) {
   const int64_t ncols = clo + (n - chi);
   if (ncols <= 0 || kb <= 0) return;
   hipLaunchKernelGGL((k_laswp_outside<T>), dim3(static_cast<unsigned>((ncols + 255) / 256), batch),
-                     dim3(256), 0, s, M, ld, stride, n, r0, kb, clo, chi, ipiv);
+                     dim3(256), 0, s, M, ld, stride, n, r0, kb, clo, chi, ipiv, grp, nodes);
 }
 template void laswp_outside<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                 int, int64_t, int64_t, const int32_t *);
+                                 int, int64_t, int64_t, const int32_t *, const GrpMat *, int);
 template void laswp_outside<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                 int, int64_t, int64_t, const int32_t *);
+                                 int, int64_t, int64_t, const int32_t *, const GrpMat *, int);
 
 template <typename T>
 void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t c0,
@@ -506,38 +529,41 @@ template void trsm_small<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int
 
 template <typename T>
 void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w1, int w2) {
+                  int64_t c0, int w1, int w2, const GrpMat *grp, int nodes) {
   if (w1 <= 0 || w2 <= 0 || w1 > kPU || w2 > kPU) return;
   const int64_t rows = n - c0 - w1;
   const unsigned chunks = static_cast<unsigned>(rows > 0 ? (rows + 63) / 64 : 1);
   if (rows > 0)
     hipLaunchKernelGGL((k_panel_update<T>), dim3(chunks, batch), dim3(256), 0, s, M, ld, stride, n,
-                       c0, w1, w2, false);
+                       c0, w1, w2, false, grp, nodes);
   hipLaunchKernelGGL((k_panel_update<T>), dim3(1, batch), dim3(256), 0, s, M, ld, stride, n, c0, w1,
-                     w2, true);
+                     w2, true, grp, nodes);
 }
 template void panel_update<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                int, int);
+                                int, int, const GrpMat *, int);
 template void panel_update<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                int, int);
+                                int, int, const GrpMat *, int);
 int panel_update_max_width() { return kPU; }
 
 template <typename T>
 void diag_block_inverse(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,
                         int64_t n, int nb, int64_t blk0, int64_t blk1, bool lower, T *out,
-                        int64_t out_stride) {
+                        int64_t out_stride, const GrpMat *grp, int nodes) {
   if (blk1 <= blk0) return;
   hipLaunchKernelGGL((k_diag_inv<T>), dim3(static_cast<unsigned>(blk1 - blk0), batch), dim3(64),
-                     0, s, M, ld, stride, n, nb, blk0, lower, out, out_stride);
+                     0, s, M, ld, stride, n, nb, blk0, lower, out, out_stride, grp, nodes);
 }
 template void diag_block_inverse<z64>(hipStream_t, const z64 *, int64_t, int64_t, int32_t,
-                                      int64_t, int, int64_t, int64_t, bool, z64 *, int64_t);
+                                      int64_t, int, int64_t, int64_t, bool, z64 *, int64_t,
+                                      const GrpMat *, int);
 template void diag_block_inverse<c64>(hipStream_t, const c64 *, int64_t, int64_t, int32_t,
-                                      int64_t, int, int64_t, int64_t, bool, c64 *, int64_t);
+                                      int64_t, int, int64_t, int64_t, bool, c64 *, int64_t,
+                                      const GrpMat *, int);
 
-void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n, int32_t batch) {
+void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n, int32_t batch,
+                    const GrpMat *grp, int nodes) {
   hipLaunchKernelGGL(k_perm, dim3(batch), dim3(256), static_cast<unsigned>(n * sizeof(int32_t)), s,
-                     ipiv, perm, n);
+                     ipiv, perm, n, grp, nodes);
 }
 
 void fill_i32(hipStream_t s, int32_t *p, int64_t count, int32_t v) {

@@ -31,11 +31,11 @@ __global__ __launch_bounds__(256) void k_shift(const z64 *__restrict__ A, int64_
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_rows(const T *__restrict__ R, int64_t ldr,
                                                      int64_t sR, const int32_t *__restrict__ perm,
-                                                     int64_t n, int64_t m, T *__restrict__ Y,
-                                                     int64_t ldy, int64_t sY) {
+                                                     int64_t pstride, int64_t m,
+                                                     T *__restrict__ Y, int64_t ldy, int64_t sY) {
   const int64_t row = blockIdx.x;
   const int b = blockIdx.y;
-  const int64_t src = perm[b * n + row];
+  const int64_t src = perm[b * pstride + row];
   for (int64_t c = threadIdx.x; c < m; c += 256)
     Y[b * sY + row * ldy + c] = R[b * sR + src * ldr + c];
 }
@@ -498,14 +498,39 @@ void shift_assemble_c(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, in
 
 template <typename T>
 void gather_rows(hipStream_t s, const T *R, int64_t ldr, int64_t sR, const int32_t *perm,
-                 int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY) {
+                 int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY,
+                 int64_t pstride) {
+  if (n <= 0 || batch <= 0) return;
   hipLaunchKernelGGL((k_gather_rows<T>), dim3(static_cast<unsigned>(n), batch), dim3(256), 0, s, R,
-                     ldr, sR, perm, n, m, Y, ldy, sY);
+                     ldr, sR, perm, pstride > 0 ? pstride : n, m, Y, ldy, sY);
 }
 template void gather_rows<z64>(hipStream_t, const z64 *, int64_t, int64_t, const int32_t *,
-                               int64_t, int64_t, int32_t, z64 *, int64_t, int64_t);
+                               int64_t, int64_t, int32_t, z64 *, int64_t, int64_t, int64_t);
 template void gather_rows<c64>(hipStream_t, const c64 *, int64_t, int64_t, const int32_t *,
-                               int64_t, int64_t, int32_t, c64 *, int64_t, int64_t);
+                               int64_t, int64_t, int32_t, c64 *, int64_t, int64_t, int64_t);
+
+// Ones on the diagonal of rows [n0, n) of `batch` matrices (the identity block
+// that pads a pencil's shifted matrices to a multiple of the panel width).
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_diag(T *__restrict__ M, int64_t ld, int64_t stride,
+                                                  int64_t n0, int64_t n) {
+  const int64_t i = n0 + blockIdx.x * 256ll + threadIdx.x;
+  if (i >= n) return;
+  T one;
+  one.x = 1;
+  one.y = 0;
+  M[blockIdx.y * stride + i * ld + i] = one;
+}
+
+template <typename T>
+void pad_diag(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n0,
+              int64_t n) {
+  if (n <= n0 || batch <= 0) return;
+  hipLaunchKernelGGL((k_pad_diag<T>), dim3(static_cast<unsigned>((n - n0 + 255) / 256), batch),
+                     dim3(256), 0, s, M, ld, stride, n0, n);
+}
+template void pad_diag<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int64_t);
+template void pad_diag<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int64_t);
 
 void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64 *T2, int64_t ldt,
                     const z64 *z, int32_t N, int64_t n, int64_t m) {

@@ -22,9 +22,12 @@ template <typename T> struct GemmArgs {
   int32_t splits;
   int64_t kchunk;
   T *work;
+  int64_t tile0;  // grouped launches: first linear tile of this problem
 };
 
-enum { GEMM_SQUARE = 0, GEMM_TALL = 1, GEMM_BIG = 2 };
+// GEMM_UPDATE: the 64 x 64 configuration under a kernel name of its own (the
+// LU trailing update).
+enum { GEMM_SQUARE = 0, GEMM_TALL = 1, GEMM_UPDATE = 3 };
 
 // C_b = alpha op(A_b) B_b + beta C_b; transA 0: A is M x K; 2: A stored K x M, op = ^*.
 // `work` (optional, work_elems entries) enables split-K for small outputs.
@@ -38,21 +41,39 @@ void cgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha
            int64_t ldc, int64_t sC, int32_t batch, c64 *work = nullptr, int64_t work_elems = 0,
            int cfg = GEMM_SQUARE);
 
+// Grouped product: `count` independent problems (each a uniform batch, 64 x 64
+// tiles, no split-K) in one launch.  gemm_group_tiles fills tile0 (and splits,
+// kchunk) of a host table and returns the total tile count; the launch reads
+// the table from device memory.  sub: every problem is C -= A B (alpha = -1,
+// beta = 1); ta: 0 or 2 (2 only with sub = false).
+template <typename T> int64_t gemm_group_tiles(GemmArgs<T> *tab, int count);
+template <typename T>
+void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int count,
+                int64_t total_tiles);
+
 // ---- LU building blocks (k_lu.hip); T = z64 or c64 --------------------------
+//
+// Every launcher below runs over a uniform batch (M + b * stride, order n) or,
+// with grp != nullptr, over a grouped one (GrpMat, common.h): n is then the
+// largest order (the stride of the flat pivot/info arrays) and each matrix
+// reads its own order; matrices too small for the requested columns skip the
+// launch.
 
 // Factor columns [c0, c0+w) (rows [c0, n)) of each matrix with partial pivoting,
 // swapping rows over the panel columns [pk0, pk0+pkb) as well.  Returns false
 // if w is larger than the register-resident leaf supports for n - c0 rows.
 template <typename T>
 bool leaf_lu(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-             int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info);
+             int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
+             const GrpMat *grp = nullptr, int nodes = 1);
 // Largest leaf width for `rows` remaining rows.
 template <typename T> int leaf_max_width(int64_t rows);
 
 // Rows [r0, r0+kb) swapped with ipiv[r0..r0+kb) over columns [0, clo) and [chi, n).
 template <typename T>
 void laswp_outside(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                   int64_t r0, int kb, int64_t clo, int64_t chi, const int32_t *ipiv);
+                   int64_t r0, int kb, int64_t clo, int64_t chi, const int32_t *ipiv,
+                   const GrpMat *grp = nullptr, int nodes = 1);
 
 // X <- L11^{-1} X for the unit-lower L11 = M[c0:c0+w1, c0:c0+w1] and
 // X = M[c0:c0+w1, c0+w1:c0+w1+w2] (w1, w2 <= 64).
@@ -65,7 +86,7 @@ void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, 
 // M[c0+w1:n, c0+w1:c0+w1+w2] -= M[c0+w1:n, c0:c0+w1] X.
 template <typename T>
 void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w1, int w2);
+                  int64_t c0, int w1, int w2, const GrpMat *grp = nullptr, int nodes = 1);
 int panel_update_max_width();
 
 // Inverses of the diagonal blocks of the unit-lower L (lower=true) or of the
@@ -74,10 +95,11 @@ int panel_update_max_width();
 template <typename T>
 void diag_block_inverse(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,
                         int64_t n, int nb, int64_t blk0, int64_t blk1, bool lower, T *out,
-                        int64_t out_stride);
+                        int64_t out_stride, const GrpMat *grp = nullptr, int nodes = 1);
 
 // perm[b][i] = original row at position i of P_b (from LAPACK-order ipiv).
-void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n, int32_t batch);
+void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n, int32_t batch,
+                    const GrpMat *grp = nullptr, int nodes = 1);
 
 // info[b] = min(info[b]) helper is inside leaf_lu; zero the array:
 void fill_i32(hipStream_t s, int32_t *p, int64_t count, int32_t v);
@@ -90,10 +112,16 @@ void shift_assemble_z(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, in
 void shift_assemble_c(hipStream_t s, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
                       const z64 *z, int32_t N, int64_t n, c64 *M, int64_t ldm, int64_t sM);
 
-// Y_b[i, :] = R_b[perm_b[i], :] with R_b = R + b sR (sR = 0: one shared R).
+// Y_b[i, :] = R_b[perm_b[i], :] for rows i < n, with R_b = R + b sR (sR = 0:
+// one shared R) and perm_b = perm + b pstride (pstride 0: n).
 template <typename T>
 void gather_rows(hipStream_t s, const T *R, int64_t ldr, int64_t sR, const int32_t *perm,
-                 int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY);
+                 int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY,
+                 int64_t pstride = 0);
+// Ones on the diagonal of rows [n0, n) of `batch` matrices.
+template <typename T>
+void pad_diag(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n0,
+              int64_t n);
 // Y[perm_b[i], :] = X_b[i, :]  (scatter, used by the ^* solve).
 template <typename T>
 void scatter_rows(hipStream_t s, const T *X, int64_t ldx, int64_t sX, const int32_t *perm,

@@ -85,6 +85,47 @@ def test_null_plan_and_pointer_checks():
                                    bd.FeastZ(0, 0), None, 4, 0, 1, None) == fm.FEAST_OK
 
 
+@pytest.mark.parametrize("case", ["count0", "m_gt_n", "n_big", "nodes_differ", "bad_radius",
+                                  "prec", "max_iter"])
+def test_batch_create_validates_before_device_work(case):
+    ns, ms = [100, 60], [10, 6]
+    centers, radii, nodes = [0.0, 1.0], [1.0, 1.0], 16
+    kw = {}
+    if case == "count0":
+        ns, ms, centers, radii = [], [], [], []
+    elif case == "m_gt_n":
+        ms = [10, 61]
+    elif case == "n_big":
+        ns = [100, 20000]
+    elif case == "bad_radius":
+        radii = [1.0, 0.0]
+    elif case == "prec":
+        kw["prec"] = 3
+    elif case == "max_iter":
+        kw["max_iter"] = 0
+    if case == "nodes_differ":
+        lib = fm.load()
+        c = (bd.Contour * 2)(bd.contour(0.0, 1.0, 16), bd.contour(1.0, 1.0, 8))
+        h = bd.C.c_void_p()
+        rc = lib.feast_batch_create(bd.C.byref(h), 2, (bd.C.c_int64 * 2)(*ns),
+                                    (bd.C.c_int64 * 2)(*ms), c, None, None)
+        assert rc == fm.FEAST_EINVAL and not h.value
+        return
+    with pytest.raises(fm.FeastError) as e:
+        fm.Batch(ns, ms, centers, radii, nodes, **kw)
+    assert e.value.code == fm.FEAST_EINVAL
+
+
+def test_null_batch_checks():
+    lib = fm.load()
+    assert lib.feast_batch_destroy(None) == fm.FEAST_OK
+    assert lib.feast_batch_invalidate(None) == fm.FEAST_EINVAL
+    assert lib.feast_batch_filter(None, None, None, None, None, None, None, None, None, 0) == fm.FEAST_EINVAL
+    assert lib.feast_batch_solve(None, None, None, None, None, None, None, None, None, None, None,
+                                 None, None, None, None, None) == fm.FEAST_EINVAL
+    assert lib.feast_batch_last_error(None) == b"null batch"
+
+
 def test_stop_rule_matches_oracle_on_random_sequences():
     rng = np.random.default_rng(0)
     for _ in range(2000):
