@@ -74,6 +74,23 @@ struct Tables {
     if (!host.empty()) HIPCHK(hipMemcpy(dev.p, host.data(), host.size(), hipMemcpyHostToDevice));
     record = false;
   }
+  // Per-call tables: back to record mode (the device buffer is kept), and an
+  // upload ordered on `s` (the host copy stays alive until the next reset,
+  // which follows a synchronisation of `s`).
+  void reset() {
+    record = true;
+    host.clear();
+    off.clear();
+    cnt.clear();
+    cur = 0;
+  }
+  void upload_async(hipStream_t s) {
+    dev.alloc(std::max<size_t>(host.size(), 256));
+    if (!host.empty())
+      HIPCHK(hipMemcpyAsync(dev.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    record = false;
+    cur = 0;
+  }
 };
 
 // A captured HIP graph, re-captured when its key (the caller's pointers and
@@ -107,7 +124,9 @@ struct feast_batch {
   // node solutions (np_p x N m_p each) and the mixed-form buffers
   DevBuf Y, Yc, T1, T2;
   std::vector<int64_t> yoff, toff;
-  Tables lu_tab, sv_tab;
+  Tables lu_tab, sv_tab, pj_tab;
+  DevBuf dinv, flags;  // grouped orthonormalisation: inverted 64 x 64 blocks, breakdown flags
+  int64_t mmax = 0;
   Graph g_factor, g_filter;
   bool factored = false;
   std::vector<int64_t> fkey;
@@ -117,6 +136,7 @@ struct feast_batch {
   bool mixed() const { return o.prec == FEAST_MIXED; }
   int64_t istride() const { return nblk * 64 * 64; }
   int64_t ldY(int p) const { return static_cast<int64_t>(N) * m[p]; }
+  int64_t mblk() const { return (mmax + 63) / 64; }
   int active(int64_t k) const {  // pencils with np > k (a prefix)
     int a = 0;
     while (a < P && np[a] > k) ++a;
@@ -469,6 +489,219 @@ void filter_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
   });
 }
 
+// ---------------------------------------------------------------------------
+// Grouped orthonormalisation and projection over the pencils in a list `act`
+// (Algorithm 5 lines 2/17 and 5): every step is one launch over all of them.
+// The GEMM problem lists and descriptors depend on the list, so each round is
+// scheduled twice, recording and then launching (tables uploaded in between).
+// ---------------------------------------------------------------------------
+
+std::vector<GrpMat> gmats(feast_batch *b, const std::vector<int> &act, z64 *(*blk)(feast_plan *, int),
+                          int which, bool square) {
+  std::vector<GrpMat> g;
+  for (int p : act) {
+    const int64_t m = b->m[p];
+    g.push_back(GrpMat{blk(b->sub[p], which), m, 0, square ? m : b->n[p]});
+  }
+  return g;
+}
+z64 *gblk_of(feast_plan *q, int i) { return q->gblk(i); }
+z64 *wblk_of(feast_plan *q, int i) { return q->wblk(i); }
+
+// X_p <- orth(X_p) (n_p x m_p, leading dimension m_p) by shifted Cholesky QR3,
+// as the single-pencil plan does it; flags of list entry i at flags[8 i + slot + pass].
+void orth_grouped(feast_batch *b, Tables &t, const std::vector<int> &act, int xblk, int slot) {
+  const bool rec = t.record;
+  hipStream_t s = b->gs;
+  const int cnt = static_cast<int>(act.size());
+  const z64 one = make_double2(1.0, 0.0);
+  const GrpMat *gG = t.put(gmats(b, act, gblk_of, feast_plan::G_GRAM, true));
+  const GrpMat *gR = t.put(gmats(b, act, gblk_of, feast_plan::G_RINV, true));
+  std::vector<GrpMat> wsrc, xdst;
+  std::vector<double> shifts;
+  for (int p : act) {
+    const int64_t n = b->n[p], m = b->m[p];
+    wsrc.push_back(GrpMat{b->sub[p]->wblk(feast_plan::W_ORTH), m, 0, n});
+    xdst.push_back(GrpMat{b->sub[p]->wblk(xblk), m, m, n});
+    shifts.push_back(11.0 * (static_cast<double>(n) * m + static_cast<double>(m) * (m + 1)) * kU64);
+  }
+  const GrpMat *gW = t.put(wsrc), *gX = t.put(xdst);
+  const double *dshift = t.put(shifts);
+  z64 *Dinv = b->dinv.as<z64>();
+  const int64_t dstride = b->mblk() * 4096;
+  int64_t nm_max = 0;
+  for (int p : act) nm_max = std::max(nm_max, b->n[p] * b->m[p]);
+  for (int pass = 0; pass < 3; ++pass) {
+    // Gram matrix G = X^* X
+    std::vector<GemmArgs<z64>> e;
+    for (int p : act) {
+      const int64_t n = b->n[p], m = b->m[p];
+      z64 *X = b->sub[p]->wblk(xblk);
+      e.push_back(gargs<z64>(m, m, n, X, m, 0, X, m, 0, b->sub[p]->gblk(feast_plan::G_GRAM), m, 0,
+                             1.0, 0.0, 1));
+    }
+    ggemm<z64>(b, t, 2, false, e);
+    if (pass == 0 && !rec) feast::add_shift_grp(s, gG, cnt, dshift);
+    // blocked Cholesky G = R^* R (upper R over G)
+    for (int64_t J0 = 0; J0 < b->mmax; J0 += 64) {
+      if (!rec) {
+        feast::chol_block_grp(s, gG, cnt, J0, b->flags.as<int32_t>() + slot + pass, 8);
+        feast::diag_block_inverse<z64>(s, nullptr, 0, 0, cnt, b->mmax, 64, J0 / 64, J0 / 64 + 1,
+                                       false, Dinv, dstride, gG, 1);
+      }
+      std::vector<GemmArgs<z64>> e1, e2;
+      for (int i = 0; i < cnt; ++i) {
+        const int p = act[i];
+        const int64_t m = b->m[p];
+        if (J0 >= m) continue;
+        const int64_t jb = std::min<int64_t>(64, m - J0), rest = m - J0 - jb;
+        if (rest <= 0) continue;
+        z64 *G = b->sub[p]->gblk(feast_plan::G_GRAM);
+        z64 *GJ = G + J0 * m + J0;
+        e1.push_back(gargs<z64>(jb, rest, jb, Dinv + i * dstride + (J0 / 64) * 4096, 64, 0, GJ + jb,
+                                m, 0, GJ + jb, m, 0, 1.0, 0.0, 1));
+        e2.push_back(gargs<z64>(rest, rest, jb, GJ + jb, m, 0, GJ + jb, m, 0,
+                                G + (J0 + jb) * m + J0 + jb, m, 0, -1.0, 1.0, 1));
+      }
+      ggemm<z64>(b, t, 2, false, e1);
+      ggemm<z64>(b, t, 2, false, e2);
+    }
+    // Ri = R^{-1}: inverted diagonal blocks, then X12 = -X11 R12 X22 by halving
+    if (!rec) {
+      feast::zero_lower_grp(s, gG, cnt, b->mmax, false);
+      feast::zero_lower_grp(s, gR, cnt, b->mmax, true);
+      feast::diag_block_inverse<z64>(s, nullptr, 0, 0, cnt, b->mmax, 64, 0, b->mblk(), false, Dinv,
+                                     dstride, gG, 1);
+      feast::put_diag_grp(s, gR, cnt, b->mblk(), Dinv, dstride);
+    }
+    struct Rec {
+      static void run(feast_batch *b, Tables &t, const std::vector<int> &act, int64_t r0,
+                      int64_t r1) {
+        if (r1 - r0 <= 64) return;
+        const int64_t mid = r0 + ((r1 - r0 + 127) / 128) * 64;
+        run(b, t, act, r0, mid);
+        run(b, t, act, mid, r1);
+        std::vector<GemmArgs<z64>> e1, e2;
+        for (int p : act) {
+          const int64_t m = b->m[p];
+          if (m <= mid) continue;
+          const int64_t c1 = std::min(r1, m);
+          z64 *R = b->sub[p]->gblk(feast_plan::G_GRAM), *X = b->sub[p]->gblk(feast_plan::G_RINV);
+          z64 *T = b->sub[p]->gblk(feast_plan::G_T);
+          e1.push_back(gargs<z64>(mid - r0, c1 - mid, c1 - mid, R + r0 * m + mid, m, 0,
+                                  X + mid * m + mid, m, 0, T, m, 0, 1.0, 0.0, 1));
+          e2.push_back(gargs<z64>(mid - r0, c1 - mid, mid - r0, X + r0 * m + r0, m, 0, T, m, 0,
+                                  X + r0 * m + mid, m, 0, -1.0, 0.0, 1));
+        }
+        ggemm<z64>(b, t, 0, false, e1);
+        ggemm<z64>(b, t, 0, false, e2);
+      }
+    };
+    Rec::run(b, t, act, 0, b->mmax);
+    // X <- X Ri
+    std::vector<GemmArgs<z64>> ex;
+    for (int p : act) {
+      const int64_t n = b->n[p], m = b->m[p];
+      ex.push_back(gargs<z64>(n, m, m, b->sub[p]->wblk(xblk), m, 0,
+                              b->sub[p]->gblk(feast_plan::G_RINV), m, 0,
+                              b->sub[p]->wblk(feast_plan::W_ORTH), m, 0, 1.0, 0.0, 1));
+    }
+    ggemm<z64>(b, t, 0, false, ex);
+    if (!rec) feast::copy_grp(s, gW, gX, cnt, nm_max);
+  }
+}
+
+// One scheduling pass of the grouped projection of the pencils in `act`:
+// U_1 = orth(UF), B U_1, A U_1, U_2 = orth(B U_1), At = U_2^* A U_1, Bt = U_2^* B U_1.
+void project_schedule(feast_batch *b, Tables &t, const std::vector<int> &act,
+                      const feast_z *const *dA, const int64_t *lda, const feast_z *const *dB,
+                      const int64_t *ldb) {
+  const bool rec = t.record;
+  hipStream_t s = b->gs;
+  const int cnt = static_cast<int>(act.size());
+  std::vector<GrpMat> uf, u1, bu, u2;
+  int64_t nm_max = 0;
+  for (int p : act) {
+    const int64_t n = b->n[p], m = b->m[p];
+    feast_plan *q = b->sub[p];
+    uf.push_back(GrpMat{q->wblk(feast_plan::W_UF), m, 0, n});
+    u1.push_back(GrpMat{q->wblk(feast_plan::W_U1), m, m, n});
+    bu.push_back(GrpMat{q->wblk(feast_plan::W_BU1), m, 0, n});
+    u2.push_back(GrpMat{q->wblk(feast_plan::W_U2), m, m, n});
+    nm_max = std::max(nm_max, n * m);
+  }
+  const GrpMat *guf = t.put(uf), *gu1 = t.put(u1), *gbu = t.put(bu), *gu2 = t.put(u2);
+  if (!rec) {
+    feast::fill_i32(s, b->flags.as<int32_t>(), 8 * static_cast<int64_t>(cnt), 0);
+    feast::copy_grp(s, guf, gu1, cnt, nm_max);
+  }
+  orth_grouped(b, t, act, feast_plan::W_U1, 0);
+  std::vector<GemmArgs<z64>> eb, ea;
+  for (int p : act) {
+    const int c = b->order[p];
+    const int64_t n = b->n[p], m = b->m[p];
+    feast_plan *q = b->sub[p];
+    eb.push_back(gargs<z64>(n, m, n, reinterpret_cast<const z64 *>(dB[c]), ldb[c], 0,
+                            q->wblk(feast_plan::W_U1), m, 0, q->wblk(feast_plan::W_BU1), m, 0, 1.0,
+                            0.0, 1));
+    ea.push_back(gargs<z64>(n, m, n, reinterpret_cast<const z64 *>(dA[c]), lda[c], 0,
+                            q->wblk(feast_plan::W_U1), m, 0, q->wblk(feast_plan::W_AU1), m, 0, 1.0,
+                            0.0, 1));
+  }
+  ggemm<z64>(b, t, 0, false, eb);
+  ggemm<z64>(b, t, 0, false, ea);
+  if (!rec) feast::copy_grp(s, gbu, gu2, cnt, nm_max);
+  orth_grouped(b, t, act, feast_plan::W_U2, 3);
+  std::vector<GemmArgs<z64>> pa, pb;
+  for (int p : act) {
+    const int64_t n = b->n[p], m = b->m[p];
+    feast_plan *q = b->sub[p];
+    z64 *U2 = q->wblk(feast_plan::W_U2);
+    pa.push_back(gargs<z64>(m, m, n, U2, m, 0, q->wblk(feast_plan::W_AU1), m, 0,
+                            q->gblk(feast_plan::G_AT), m, 0, 1.0, 0.0, 1));
+    pb.push_back(gargs<z64>(m, m, n, U2, m, 0, q->wblk(feast_plan::W_BU1), m, 0,
+                            q->gblk(feast_plan::G_BT), m, 0, 1.0, 0.0, 1));
+  }
+  ggemm<z64>(b, t, 2, false, pa);
+  ggemm<z64>(b, t, 2, false, pb);
+}
+
+// The grouped projection of `act` with At, Bt copied to the host (synchronises);
+// a Cholesky QR breakdown is reported as for a single plan.
+int project_grouped(feast_batch *b, const std::vector<int> &act, const feast_z *const *dA,
+                    const int64_t *lda, const feast_z *const *dB, const int64_t *ldb,
+                    std::vector<std::vector<feast_z>> &At, std::vector<std::vector<feast_z>> &Bt) {
+  if (act.empty()) return FEAST_OK;
+  Tables &t = b->pj_tab;
+  t.reset();
+  project_schedule(b, t, act, dA, lda, dB, ldb);
+  t.upload_async(b->gs);
+  project_schedule(b, t, act, dA, lda, dB, ldb);
+  hipStream_t s = b->gs;
+  const int cnt = static_cast<int>(act.size());
+  std::vector<int32_t> hf(8 * cnt);
+  for (int p : act) {
+    const int64_t m = b->m[p];
+    HIPCHK(hipMemcpyAsync(At[p].data(), b->sub[p]->gblk(feast_plan::G_AT), sizeof(z64) * m * m,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(Bt[p].data(), b->sub[p]->gblk(feast_plan::G_BT), sizeof(z64) * m * m,
+                          hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipMemcpyAsync(hf.data(), b->flags.p, sizeof(int32_t) * 8 * cnt, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  for (int i = 0; i < cnt; ++i)
+    for (int k = 0; k < 6; ++k)
+      if (hf[8 * i + k] != 0) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf, "pencil %d: Cholesky QR pass %d of %s broke down at column %d",
+                      b->order[act[i]], k % 3 + 1, k < 3 ? "U" : "B U_1", hf[8 * i + k] - 1);
+        b->err = buf;
+        return FEAST_ENUMERIC;
+      }
+  return FEAST_OK;
+}
+
 // The caller's stream -> batch stream -> caller's stream ordering.
 void enter(feast_batch *b) {
   HIPCHK(hipEventRecord(b->ev_in, b->s));
@@ -554,6 +787,9 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
     }
     b->nmax = b->np[0];
     b->nblk = b->nmax / 64;
+    b->mmax = *std::max_element(b->m.begin(), b->m.end());
+    b->dinv.alloc(sizeof(z64) * P * b->mblk() * 4096);
+    b->flags.alloc(sizeof(int32_t) * 8 * P);
     const int64_t nmat = static_cast<int64_t>(P) * N;
     const size_t esz = b->mixed() ? sizeof(c64) : sizeof(z64);
     b->F.alloc(esz * fo);
@@ -614,7 +850,8 @@ int feast_batch_destroy(feast_batch *b) {
   b->g_filter.reset();
   for (feast_plan *p : b->sub) feast_plan_destroy(p);
   for (DevBuf *d : {&b->F, &b->piv, &b->perm, &b->info, &b->Linv, &b->Uinv, &b->grp, &b->Y, &b->Yc,
-                    &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev})
+                    &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev, &b->pj_tab.dev, &b->dinv,
+                    &b->flags})
     d->release();
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -706,14 +943,12 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       double e_prev = 0.0;
       std::vector<cd> lam_prev;
       std::vector<double> r_prev;
-      std::vector<feast_z> At, Bt, Yh, alpha, beta, lam;
+      std::vector<feast_z> Yh, alpha, beta, lam;
       std::vector<double> hn;
     };
     std::vector<St> st(P);
     for (int p = 0; p < P; ++p) {
       const int64_t m = b->m[p];
-      st[p].At.resize(m * m);
-      st[p].Bt.resize(m * m);
       st[p].Yh.resize(m * m);
       st[p].alpha.resize(m);
       st[p].beta.resize(m);
@@ -728,27 +963,19 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       inf.t_filter_ms += t.ms();
       inf.filters += 1;
     };
+    std::vector<std::vector<feast_z>> hAt(P), hBt(P);
+    for (int p = 0; p < P; ++p) {
+      hAt[p].resize(b->m[p] * b->m[p]);
+      hBt[p].resize(b->m[p] * b->m[p]);
+    }
     auto project_active = [&]() -> int {
       Timer t;
-      for (int p = 0; p < P; ++p) {
-        if (st[p].done) continue;
-        feast_plan *q = b->sub[p];
-        const int64_t m = b->m[p];
-        feast::copy_block_z(s, q->wblk(feast_plan::W_UF), m, b->n[p], m, q->wblk(feast_plan::W_U1), m);
-        project_device(q, Ap(p), lda[b->order[p]], Bp(p), ldb[b->order[p]],
-                       q->wblk(feast_plan::W_U1), m, q->wblk(feast_plan::W_AU1), m,
-                       q->wblk(feast_plan::W_BU1), m);
-      }
-      for (int p = 0; p < P; ++p) {
-        if (st[p].done) continue;
-        const int r = project_finish(b->sub[p], st[p].At.data(), st[p].Bt.data());
-        if (r != FEAST_OK) {
-          b->err = "pencil " + std::to_string(b->order[p]) + ": " + b->sub[p]->err;
-          return r;
-        }
-      }
+      std::vector<int> act;
+      for (int p = 0; p < P; ++p)
+        if (!st[p].done) act.push_back(p);
+      const int r = project_grouped(b, act, dA, lda, dB, ldb, hAt, hBt);
       inf.t_project_ms += t.ms();
-      return FEAST_OK;
+      return r;
     };
     // line 1 (Search with the subspace size fixed): U = Q_N V
     for (int p = 0; p < P; ++p) {
@@ -774,8 +1001,8 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       parallel_for(static_cast<int>(act.size()), nthreads, [&](int i) {
         const int p = act[i];
         const int64_t m = b->m[p];
-        qz[p] = feast_host::reduced_eig(m, reinterpret_cast<const cd *>(st[p].At.data()), m,
-                                        reinterpret_cast<const cd *>(st[p].Bt.data()), m,
+        qz[p] = feast_host::reduced_eig(m, reinterpret_cast<const cd *>(hAt[p].data()), m,
+                                        reinterpret_cast<const cd *>(hBt[p].data()), m,
                                         reinterpret_cast<cd *>(st[p].alpha.data()),
                                         reinterpret_cast<cd *>(st[p].beta.data()),
                                         reinterpret_cast<cd *>(st[p].Yh.data()), m, 1);

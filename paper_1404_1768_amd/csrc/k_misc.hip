@@ -458,6 +458,122 @@ __global__ __launch_bounds__(256) void k_identity(z64 *__restrict__ X, int64_t t
   X[e] = make_double2((e / t == e % t) ? 1.0 : 0.0, 0.0);
 }
 
+
+// ---- grouped forms over the pencils of a batch (GrpMat descriptors, one
+// matrix per entry: base, leading dimension ld, order n; entries are
+// matrices of the pencils in a list) ----
+
+// G_b += shift_rel[b] * trace(G_b) * I (t = n_b).
+__global__ __launch_bounds__(256) void k_add_shift_grp(const GrpMat *__restrict__ g,
+                                                       const double *__restrict__ shift_rel) {
+  __shared__ double red[256];
+  const GrpMat e = g[blockIdx.x];
+  z64 *G = static_cast<z64 *>(e.base);
+  const int64_t t = e.n, ld = e.ld;
+  double tr = 0.0;
+  for (int64_t i = threadIdx.x; i < t; i += 256) tr += G[i * ld + i].x;
+  red[threadIdx.x] = tr;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double sh = shift_rel[blockIdx.x] * red[0];
+  for (int64_t i = threadIdx.x; i < t; i += 256) G[i * ld + i].x += sh;
+}
+
+// Cholesky of the diagonal block [J0, J0 + jb) of G_b (jb = min(64, n_b - J0)),
+// as k_chol_block; flags at flag[b * flag_stride].
+__global__ __launch_bounds__(256) void k_chol_block_grp(const GrpMat *__restrict__ g, int64_t J0,
+                                                        int32_t *__restrict__ flag,
+                                                        int flag_stride) {
+  __shared__ z64 S[64][65];
+  __shared__ double s_d;
+  const GrpMat e = g[blockIdx.x];
+  if (J0 >= e.n) return;
+  const int jb = static_cast<int>(e.n - J0 < 64 ? e.n - J0 : 64);
+  const int64_t ld = e.ld;
+  z64 *G = static_cast<z64 *>(e.base) + J0 * ld + J0;
+  int32_t *fl = flag + blockIdx.x * flag_stride;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < jb * jb; q += 256) {
+    const int i = q / jb, j = q % jb;
+    S[i][j] = G[i * ld + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < jb; ++k) {
+    if (tid == 0) {
+      const double d = S[k][k].x;
+      if (!(d > 0.0)) {
+        if (fl[0] == 0) fl[0] = static_cast<int>(J0) + k + 1;
+        s_d = 1.0;
+      } else {
+        s_d = sqrt(d);
+      }
+      S[k][k] = make_double2(s_d, 0.0);
+    }
+    __syncthreads();
+    const double d = s_d;
+    for (int j = k + 1 + tid; j < jb; j += 256) {
+      S[k][j].x /= d;
+      S[k][j].y /= d;
+    }
+    __syncthreads();
+    const int m = jb - k - 1;
+    for (int q = tid; q < m * m; q += 256) {
+      const int i = k + 1 + q / m, j = k + 1 + q % m;
+      if (j < i) continue;
+      const z64 a = S[k][i], bb = S[k][j];
+      S[i][j].x -= a.x * bb.x + a.y * bb.y;
+      S[i][j].y -= a.x * bb.y - a.y * bb.x;
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < jb * jb; q += 256) {
+    const int i = q / jb, j = q % jb;
+    G[i * ld + j] = (j >= i) ? S[i][j] : make_double2(0.0, 0.0);
+  }
+}
+
+// Zero the strict lower triangle (all = 0) or everything (all = 1) of the
+// n_b x n_b matrix b.
+__global__ __launch_bounds__(256) void k_zero_lower_grp(const GrpMat *__restrict__ g, int all) {
+  const GrpMat e = g[blockIdx.y];
+  const int64_t q = blockIdx.x * 256ll + threadIdx.x;
+  if (q >= e.n * e.n) return;
+  const int64_t i = q / e.n, j = q % e.n;
+  if (all || j < i) static_cast<z64 *>(e.base)[i * e.ld + j] = make_double2(0.0, 0.0);
+}
+
+// Y_b = X_b for rows x cols blocks: src[b] (ld, n = rows), dst[b] (ld), cols[b]
+// columns taken from dst[b].stride (unused as a stride here).
+__global__ __launch_bounds__(256) void k_copy_grp(const GrpMat *__restrict__ src,
+                                                  const GrpMat *__restrict__ dst) {
+  const GrpMat a = src[blockIdx.y], c = dst[blockIdx.y];
+  const int64_t rows = a.n, cols = c.stride;
+  const int64_t q = blockIdx.x * 256ll + threadIdx.x;
+  if (q >= rows * cols) return;
+  const int64_t i = q / cols, j = q % cols;
+  static_cast<z64 *>(c.base)[i * c.ld + j] = static_cast<const z64 *>(a.base)[i * a.ld + j];
+}
+
+// Diagonal blocks of the inverted factor into X_b: block I of Dinv (64 x 64,
+// matrix b at Dinv + b * dstride) to X_b[I*64 : , I*64 : ] (rb = min(64, n_b - I*64)).
+__global__ __launch_bounds__(256) void k_put_diag_grp(const GrpMat *__restrict__ g,
+                                                      const z64 *__restrict__ Dinv,
+                                                      int64_t dstride) {
+  const GrpMat e = g[blockIdx.y];
+  const int64_t I = blockIdx.x;
+  const int64_t r0 = I * 64;
+  if (r0 >= e.n) return;
+  const int rb = static_cast<int>(e.n - r0 < 64 ? e.n - r0 : 64);
+  const z64 *D = Dinv + blockIdx.y * dstride + I * 4096;
+  z64 *X = static_cast<z64 *>(e.base) + r0 * e.ld + r0;
+  for (int q = threadIdx.x; q < rb * rb; q += 256) {
+    const int i = q / rb, j = q % rb;
+    X[i * e.ld + j] = D[i * 64 + j];
+  }
+}
 }  // namespace
 
 void bcast_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t c, int32_t N, z64 *Y,
@@ -641,6 +757,40 @@ void gather_normalize_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, 
   if (k <= 0) return;
   hipLaunchKernelGGL(k_gather_norm, dim3(static_cast<unsigned>(k)), dim3(256), 0, s, X, ldx, n, idx,
                      Y, ldy);
+}
+
+}  // namespace feast
+
+namespace feast {
+
+void add_shift_grp(hipStream_t s, const GrpMat *g, int count, const double *shift_rel) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_add_shift_grp, dim3(count), dim3(256), 0, s, g, shift_rel);
+}
+
+void chol_block_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32_t *flag,
+                    int flag_stride) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_chol_block_grp, dim3(count), dim3(256), 0, s, g, J0, flag, flag_stride);
+}
+
+void zero_lower_grp(hipStream_t s, const GrpMat *g, int count, int64_t tmax, bool all) {
+  if (count <= 0 || tmax <= 0) return;
+  hipLaunchKernelGGL(k_zero_lower_grp, dim3(static_cast<unsigned>((tmax * tmax + 255) / 256), count),
+                     dim3(256), 0, s, g, all ? 1 : 0);
+}
+
+void copy_grp(hipStream_t s, const GrpMat *src, const GrpMat *dst, int count, int64_t max_elems) {
+  if (count <= 0 || max_elems <= 0) return;
+  hipLaunchKernelGGL(k_copy_grp, dim3(static_cast<unsigned>((max_elems + 255) / 256), count),
+                     dim3(256), 0, s, src, dst);
+}
+
+void put_diag_grp(hipStream_t s, const GrpMat *g, int count, int64_t nblk_max, const z64 *Dinv,
+                  int64_t dstride) {
+  if (count <= 0 || nblk_max <= 0) return;
+  hipLaunchKernelGGL(k_put_diag_grp, dim3(static_cast<unsigned>(nblk_max), count), dim3(256), 0, s,
+                     g, Dinv, dstride);
 }
 
 }  // namespace feast

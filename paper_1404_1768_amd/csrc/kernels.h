@@ -104,6 +104,24 @@ void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n
 // info[b] = min(info[b]) helper is inside leaf_lu; zero the array:
 void fill_i32(hipStream_t s, int32_t *p, int64_t count, int32_t v);
 
+// ---- grouped small-matrix kernels of the batched orthonormalisation ----------
+// (k_misc.hip).  Entry b of each GrpMat array is one pencil's matrix: base,
+// leading dimension ld, order n; `count` entries, one workgroup row each.
+
+// G_b += shift_rel[b] * trace(G_b) * I (shift_rel: device array).
+void add_shift_grp(hipStream_t s, const GrpMat *g, int count, const double *shift_rel);
+// Cholesky of the diagonal block [J0, J0 + 64) of every G_b with n_b > J0
+// (upper factor in place; flag[b * flag_stride] = 1 + first failing column).
+void chol_block_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32_t *flag,
+                    int flag_stride);
+// Zero the strict lower triangle (or all) of every n_b x n_b matrix (tmax = max n_b).
+void zero_lower_grp(hipStream_t s, const GrpMat *g, int count, int64_t tmax, bool all);
+// dst_b = src_b for src_b.n rows and dst_b.stride columns (max_elems = max rows*cols).
+void copy_grp(hipStream_t s, const GrpMat *src, const GrpMat *dst, int count, int64_t max_elems);
+// Diagonal blocks I of Dinv + b * dstride (64 x 64 each) into X_b.
+void put_diag_grp(hipStream_t s, const GrpMat *g, int count, int64_t nblk_max, const z64 *Dinv,
+                  int64_t dstride);
+
 // ---- element-wise and reduction kernels (k_misc.hip) ------------------------
 
 // M_j = z_j B - A for every node j (out: N matrices n x n, ld ldm, stride sM).
