@@ -80,6 +80,11 @@ typedef struct {
   int32_t nb;          /* LU panel width: 64 or 128, 0 = automatic (128) */
   int32_t profile;     /* 1: time the LU trailing-update GEMM launches with HIP events on
                           the plan's stream (reported in feast_info); default 0 */
+  int32_t lookahead;   /* 1: factor the next panel on a second stream while the trailing
+                          matrix is updated; 0: panels and updates in sequence (default 0: the panel
+                          kernels need whole compute units, which the update holds,
+                          so the overlap measured slower) */
+  int32_t update_tile; /* LU trailing-update tile: 0 = 64 x 64, 1 = 128 x 64 (default 0) */
 } feast_opts;
 
 /* Fill *o with the defaults listed above. */

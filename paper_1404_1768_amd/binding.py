@@ -54,7 +54,8 @@ class Contour(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("eta", C.c_double), ("max_iter", C.c_int32),
                 ("prec", C.c_int32), ("refine_tol", C.c_double), ("max_sweeps", C.c_int32),
-                ("nb", C.c_int32), ("profile", C.c_int32)]
+                ("nb", C.c_int32), ("profile", C.c_int32), ("lookahead", C.c_int32),
+                ("update_tile", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -241,7 +242,9 @@ class Plan:
     def __init__(self, n: int, m: int, center: complex, radius: float, nodes: int,
                  rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
                  max_iter: int = 20, prec: int = FP64, refine_tol: Optional[float] = None,
-                 max_sweeps: int = 6, nb: int = 0, profile: bool = False, stream=None):
+                 max_sweeps: int = 6, nb: int = 0, profile: bool = False,
+                 lookahead: Optional[bool] = None, update_tile: Optional[int] = None,
+                 stream=None):
         self.lib = load()
         self.n, self.m = int(n), int(m)
         self.contour = contour(center, radius, nodes, rule)
@@ -249,6 +252,10 @@ class Plan:
         self.opts.eps, self.opts.eta, self.opts.max_iter = float(eps), float(eta), int(max_iter)
         self.opts.prec, self.opts.max_sweeps, self.opts.nb = int(prec), int(max_sweeps), int(nb)
         self.opts.profile = 1 if profile else 0
+        if lookahead is not None:
+            self.opts.lookahead = 1 if lookahead else 0
+        if update_tile is not None:
+            self.opts.update_tile = int(update_tile)
         if refine_tol is not None:
             self.opts.refine_tol = float(refine_tol)
         self._stream_obj = stream

@@ -125,6 +125,7 @@ void trsm_upper_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32
 struct LuStreams {
   hipStream_t main = nullptr, side = nullptr;
   hipEvent_t cols_ready = nullptr, panel_done = nullptr;
+  int update_cfg = feast::GEMM_UPDATE;  // tile of the trailing update
 };
 
 template <typename T>
@@ -138,7 +139,7 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
     const bool timed = prof && prof->ev && prof->used + 2 <= static_cast<int>(prof->ev->size());
     if (timed) HIPCHK(hipEventRecord((*prof->ev)[prof->used], s));
     gemm_t<T>(s, 0, rows, cols, kb, zc(-1.0), Ap, ld, stride, Bp, ld, stride, zc(1.0), Cp, ld,
-              stride, batch, nullptr, 0, feast::GEMM_UPDATE);
+              stride, batch, nullptr, 0, st.update_cfg);
     if (timed) {
       HIPCHK(hipEventRecord((*prof->ev)[prof->used + 1], s));
       prof->used += 2;
@@ -224,7 +225,8 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     prof.ev = &p->ev;
   }
   hipStream_t sl = s;
-  const LuStreams lst{sl, p->side, p->ev_cols, p->ev_panel};
+  const LuStreams lst{sl, p->o.lookahead ? p->side : nullptr, p->ev_cols, p->ev_panel,
+                      p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE};
   if (p->mixed()) {
     feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
     lu_batched<c64>(lst, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
@@ -557,6 +559,8 @@ void feast_opts_default(feast_opts *o) {
   o->max_sweeps = 6;
   o->nb = 0;
   o->profile = 0;
+  o->lookahead = 0;
+  o->update_tile = 0;
 }
 
 int feast_nodes(const feast_contour *c, feast_z *hz, feast_z *hw) {
@@ -605,7 +609,8 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
   if (!(opts.eta > 0.0) || !(opts.eps >= 0.0) || opts.max_iter < 1 ||
       opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
       opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) ||
-      (opts.nb != 0 && opts.nb != 64 && opts.nb != 128))
+      (opts.nb != 0 && opts.nb != 64 && opts.nb != 128) || opts.lookahead < 0 ||
+      opts.lookahead > 1 || opts.update_tile < 0 || opts.update_tile > 1)
     return FEAST_EINVAL;
   feast_plan *p = nullptr;
   try {

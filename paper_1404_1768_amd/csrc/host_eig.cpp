@@ -1,6 +1,8 @@
 // Host solver of the reduced t x t pencil  At y = lambda Bt y  (Algorithm 5
-// line 6; Section 3 names LAPACK's xGGES/xGGEV for this step).  It is a
-// from-scratch complex QZ:
+// line 6; Section 3 names LAPACK's xGGES/xGGEV for this step).  When Bt is
+// upper triangular and well conditioned -- the method's B~ equals R_2 of the
+// QR of B U_1 -- the standard problem Bt^{-1} At is solved (std_eig below).
+// Otherwise it is a from-scratch complex QZ:
 //   1. Bt -> upper triangular by Givens rotations from the left (applied to At);
 //   2. Hessenberg-triangular reduction of (At, Bt) (row rotations from the left,
 //      column rotations from the right, the right ones accumulated in Z);
@@ -118,8 +120,11 @@ cd wilkinson_shift(const Mat &H, const Mat &T, int64_t k) {
 
 }  // namespace
 
-int reduced_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb,
-                cd *alpha, cd *beta, cd *Y, int64_t ldy, int nthreads) {
+namespace {
+
+// General pencil: complex QZ (steps 1-4 of the file comment).
+int qz_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *alpha, cd *beta,
+           cd *Y, int64_t ldy, int nthreads) {
   if (t <= 0) return 0;
   Mat H(t), T(t), Z(t);
   for (int64_t i = 0; i < t; ++i)
@@ -339,6 +344,249 @@ int reduced_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb,
     for (auto &x : th) x.join();
   }
   return 0;
+}
+
+// Pencil with an upper-triangular, well-conditioned Bt (the projected B of the
+// method equals R_2 of the QR of B U_1): the standard problem C = Bt^{-1} At.
+//   1. C by back substitution, reduced to Hessenberg form H0 by Hermitian
+//      Householder reflectors P_k = I - f_k u_k u_k^* (kept, not accumulated);
+//   2. eigenvalues by single-shift complex QR on the active window only (no
+//      Schur form, no Schur vectors);
+//   3. each eigenvector by two steps of inverse iteration with H0 - lambda I
+//      (LU of a Hessenberg matrix with partial pivoting, O(t^2)), mapped back
+//      through the reflectors.  Quality is judged downstream anyway: every
+//      Ritz pair's residual (eq. 5-1) is computed with the original A and B.
+int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *alpha, cd *beta,
+            cd *Y, int64_t ldy, int nthreads) {
+  Mat H(t);
+  {
+    std::vector<cd> x(t);
+    for (int64_t j = 0; j < t; ++j) {
+      for (int64_t i = 0; i < t; ++i) x[i] = At[i * lda + j];
+      for (int64_t i = t - 1; i >= 0; --i) {
+        cd acc = x[i];
+        const cd *ri = Bt + i * ldb;
+        for (int64_t k = i + 1; k < t; ++k) acc -= ri[k] * x[k];
+        x[i] = acc / ri[i];
+      }
+      for (int64_t i = 0; i < t; ++i) H(i, j) = x[i];
+    }
+  }
+  for (const cd &v : H.a)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return -1;
+  // 1. Hessenberg form; reflector k acts on rows/columns k+1..t-1
+  std::vector<std::vector<cd>> refl(t);
+  std::vector<double> rf(t, 0.0);
+  {
+    std::vector<cd> w(t);
+    for (int64_t k = 0; k + 2 < t; ++k) {
+      const int64_t L = t - k - 1;
+      // (the part below the subdiagonal is summed on its own: a tiny tail under
+      // a large subdiagonal entry vanishes in |x|^2 - |x_0|^2)
+      double tail = 0.0;
+      for (int64_t i = 1; i < L; ++i) tail += std::norm(H(k + 1 + i, k));
+      if (tail == 0.0) continue;
+      const double xn = std::sqrt(std::norm(H(k + 1, k)) + tail);
+      const cd x0 = H(k + 1, k);
+      const double a0 = std::abs(x0);
+      const cd ph = (a0 > 0.0) ? x0 / a0 : cd(1.0);
+      std::vector<cd> &u = refl[k];
+      u.resize(L);
+      for (int64_t i = 0; i < L; ++i) u[i] = H(k + 1 + i, k);
+      u[0] += ph * xn;
+      double un2 = 0.0;
+      for (int64_t i = 0; i < L; ++i) un2 += std::norm(u[i]);
+      const double f = 2.0 / un2;
+      rf[k] = f;
+      for (int64_t j = k + 1; j < t; ++j) {
+        cd d = 0.0;
+        cd *hc = H.col(j) + k + 1;
+        for (int64_t i = 0; i < L; ++i) d += std::conj(u[i]) * hc[i];
+        d *= f;
+        for (int64_t i = 0; i < L; ++i) hc[i] -= d * u[i];
+      }
+      H(k + 1, k) = -ph * xn;
+      for (int64_t i = 1; i < L; ++i) H(k + 1 + i, k) = 0.0;
+      std::fill(w.begin(), w.end(), cd(0.0));
+      for (int64_t m = 0; m < L; ++m) {
+        const cd um = u[m];
+        const cd *hc = H.col(k + 1 + m);
+        for (int64_t i = 0; i < t; ++i) w[i] += hc[i] * um;
+      }
+      for (int64_t m = 0; m < L; ++m) {
+        const cd cu = f * std::conj(u[m]);
+        cd *hc = H.col(k + 1 + m);
+        for (int64_t i = 0; i < t; ++i) hc[i] -= w[i] * cu;
+      }
+    }
+  }
+  const Mat H0 = H;
+  const double hnorm = fro(H0);
+  const double atol = std::max(kSafmin, kUlp * hnorm);
+  // 2. eigenvalues: single-shift QR on the unreduced window [l, h]
+  int64_t ilast = t - 1, since = 0, it = 0;
+  const int64_t maxit = 40 * t + 100;
+  cd eshift = 0.0;
+  auto negligible = [&](int64_t j) {
+    const double hv = std::abs(H(j, j - 1));
+    return hv <= atol || hv <= kUlp * (std::abs(H(j, j)) + std::abs(H(j - 1, j - 1)));
+  };
+  while (ilast > 0) {
+    if (++it > maxit) return -2;
+    if (negligible(ilast)) {
+      H(ilast, ilast - 1) = 0.0;
+      --ilast;
+      since = 0;
+      eshift = 0.0;
+      continue;
+    }
+    int64_t l = 0;
+    for (int64_t j = ilast - 1; j >= 1; --j)
+      if (negligible(j)) {
+        H(j, j - 1) = 0.0;
+        l = j;
+        break;
+      }
+    const int64_t h = ilast;
+    ++since;
+    cd sigma;
+    if (since % 10 == 0) {
+      eshift += H(h, h - 1);
+      sigma = H(h, h) + eshift;
+    } else {
+      const cd a = H(h - 1, h - 1), b = H(h - 1, h), c = H(h, h - 1), d = H(h, h);
+      const cd tr = 0.5 * (a - d);
+      const cd disc = std::sqrt(tr * tr + b * c);
+      const cd r1 = d - (b * c) / (tr + disc), r2 = d - (b * c) / (tr - disc);
+      cd best = d;
+      const bool f1 = std::isfinite(r1.real()) && std::isfinite(r1.imag());
+      const bool f2 = std::isfinite(r2.real()) && std::isfinite(r2.imag());
+      if (f1 && f2) best = (std::abs(r1 - d) <= std::abs(r2 - d)) ? r1 : r2;
+      else if (f1) best = r1;
+      else if (f2) best = r2;
+      sigma = best;
+    }
+    double c;
+    cd sv, r;
+    rot_gen(H(l, l) - sigma, H(l + 1, l), c, sv, r);
+    for (int64_t k = l; k < h; ++k) {
+      if (k > l) {
+        rot_gen(H(k, k - 1), H(k + 1, k - 1), c, sv, r);
+        H(k, k - 1) = r;
+        H(k + 1, k - 1) = 0.0;
+      }
+      // rows (k, k+1), columns k..h
+      const cd mc = -std::conj(sv);
+      for (int64_t j = k; j <= h; ++j) {
+        const cd xv = H(k, j), yv = H(k + 1, j);
+        H(k, j) = c * xv + sv * yv;
+        H(k + 1, j) = mc * xv + c * yv;
+      }
+      // columns (k, k+1), rows l..min(k+2, h)
+      const cd sc = std::conj(sv);
+      cd *cp = H.col(k), *cq = H.col(k + 1);
+      const int64_t i1 = std::min(k + 2, h);
+      for (int64_t i = l; i <= i1; ++i) {
+        const cd xv = cp[i], yv = cq[i];
+        cp[i] = c * xv + sc * yv;
+        cq[i] = -sv * xv + c * yv;
+      }
+    }
+  }
+  for (int64_t j = 0; j < t; ++j) {
+    alpha[j] = H(j, j);
+    beta[j] = 1.0;
+  }
+  // 3. eigenvectors by inverse iteration on H0, then x = P_0 ... P_{t-3} v
+  auto eigvec = [&](int64_t j, std::vector<cd> &lu, std::vector<cd> &v, std::vector<int8_t> &sw) {
+    const cd lam = alpha[j];
+    // LU of H0 - lam I (upper Hessenberg, column-major copy in lu): eliminate
+    // the subdiagonal with row interchanges between k and k+1
+    for (int64_t q = 0; q < t * t; ++q) lu[q] = H0.a[q];
+    for (int64_t k = 0; k < t; ++k) lu[k * t + k] -= lam;
+    const double tiny = std::max(kSafmin, kUlp * hnorm);
+    for (int64_t k = 0; k + 1 < t; ++k) {
+      cd &dk = lu[k * t + k];
+      cd &sk = lu[k * t + k + 1];
+      sw[k] = std::abs(sk) > std::abs(dk) ? 1 : 0;
+      if (sw[k])
+        for (int64_t jj = k; jj < t; ++jj) std::swap(lu[jj * t + k], lu[jj * t + k + 1]);
+      cd piv = lu[k * t + k];
+      if (std::abs(piv) < tiny) piv = lu[k * t + k] = tiny;
+      const cd mlt = lu[k * t + k + 1] / piv;
+      lu[k * t + k + 1] = mlt;
+      for (int64_t jj = k + 1; jj < t; ++jj) lu[jj * t + k + 1] -= mlt * lu[jj * t + k];
+    }
+    if (std::abs(lu[(t - 1) * t + t - 1]) < tiny) lu[(t - 1) * t + t - 1] = tiny;
+    std::fill(v.begin(), v.end(), cd(1.0));
+    for (int pass = 0; pass < 2; ++pass) {
+      // forward (unit lower, with the interchanges), then backward (upper)
+      for (int64_t k = 0; k + 1 < t; ++k) {
+        if (sw[k]) std::swap(v[k], v[k + 1]);
+        v[k + 1] -= lu[k * t + k + 1] * v[k];
+      }
+      for (int64_t k = t - 1; k >= 0; --k) {
+        cd acc = v[k];
+        for (int64_t jj = k + 1; jj < t; ++jj) acc -= lu[jj * t + k] * v[jj];
+        v[k] = acc / lu[k * t + k];
+      }
+      double nr = 0.0;
+      for (const cd &e : v) nr = std::max(nr, std::abs(e));
+      if (nr > 0.0)
+        for (cd &e : v) e /= nr;
+    }
+    for (int64_t k = t - 3; k >= 0; --k) {
+      if (refl[k].empty()) continue;
+      const std::vector<cd> &u = refl[k];
+      const int64_t L = t - k - 1;
+      cd d = 0.0;
+      for (int64_t i = 0; i < L; ++i) d += std::conj(u[i]) * v[k + 1 + i];
+      d *= rf[k];
+      for (int64_t i = 0; i < L; ++i) v[k + 1 + i] -= d * u[i];
+    }
+    double nr = 0.0;
+    for (const cd &e : v) nr += std::norm(e);
+    nr = std::sqrt(nr);
+    for (int64_t i = 0; i < t; ++i) Y[i * ldy + j] = nr > 0.0 ? v[i] / nr : v[i];
+  };
+  const int nt = std::max(1, std::min<int>(nthreads, static_cast<int>((t + 15) / 16)));
+  std::vector<std::thread> th;
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w]() {
+      std::vector<cd> lu(t * t), v(t);
+      std::vector<int8_t> sw(t);
+      for (int64_t j = w; j < t; j += nt) eigvec(j, lu, v, sw);
+    });
+  for (auto &x : th) x.join();
+  return 0;
+}
+
+}  // namespace
+
+int reduced_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *alpha,
+                cd *beta, cd *Y, int64_t ldy, int nthreads) {
+  if (t <= 0) return 0;
+  // Bt upper triangular to rounding and well conditioned on its diagonal:
+  // the standard problem Bt^{-1} At is as accurate as the pencil and cheaper.
+  double bn2 = 0.0, low2 = 0.0, dmin = INFINITY, dmax = 0.0;
+  bool finite = true;
+  for (int64_t i = 0; i < t; ++i)
+    for (int64_t j = 0; j < t; ++j) {
+      const cd v = Bt[i * ldb + j];
+      if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) finite = false;
+      bn2 += std::norm(v);
+      if (j < i) low2 += std::norm(v);
+      if (j == i) {
+        dmin = std::min(dmin, std::abs(v));
+        dmax = std::max(dmax, std::abs(v));
+      }
+    }
+  // (the strictly lower part of a computed U_2^* B U_1 is rounding: inner
+  // products of length n, far below 1e-12 of the whole; the diagonal ratio is
+  // a lower bound on the condition number of the triangle)
+  if (finite && dmax > 0.0 && dmin >= 1e-4 * dmax && low2 <= 1e-24 * bn2)
+    return std_eig(t, At, lda, Bt, ldb, alpha, beta, Y, ldy, nthreads);
+  return qz_eig(t, At, lda, Bt, ldb, alpha, beta, Y, ldy, nthreads);
 }
 
 }  // namespace feast_host

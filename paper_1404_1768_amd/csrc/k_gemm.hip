@@ -331,7 +331,7 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
   d.kchunk = d.K > 0 ? d.K : 1;
   // (a 128 x 128 complex64 tile measured slower than 64 x 64 in the LU update,
   // and the FP64 one needs more than the 512 registers of a lane: not used)
-  const int BM = (cfg == GEMM_TALL) ? 128 : 64;
+  const int BM = (cfg == GEMM_TALL || cfg == GEMM_UPDATE_TALL) ? 128 : 64;
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + 63) / 64);
   // Split K when the output is too small to fill the chip.
   if (d.work && d.K >= 512 && tiles * d.batch < 192) {
@@ -344,8 +344,8 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
       d.splits = static_cast<int32_t>((d.K + d.kchunk - 1) / d.kchunk);
     }
   }
-  if (cfg == GEMM_TALL)
-    launch_cfg<T, 128, 64>(s, d, ta);
+  if (cfg == GEMM_TALL || cfg == GEMM_UPDATE_TALL)
+    launch_cfg<T, 128, 64>(s, d, ta, cfg == GEMM_UPDATE_TALL);
   else
     launch_cfg<T, 64, 64>(s, d, ta, cfg == GEMM_UPDATE);
   if (d.splits > 1) {

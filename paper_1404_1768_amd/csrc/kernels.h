@@ -25,9 +25,9 @@ template <typename T> struct GemmArgs {
   int64_t tile0;  // grouped launches: first linear tile of this problem
 };
 
-// GEMM_UPDATE: the 64 x 64 configuration under a kernel name of its own (the
-// LU trailing update).
-enum { GEMM_SQUARE = 0, GEMM_TALL = 1, GEMM_UPDATE = 3 };
+// GEMM_UPDATE / GEMM_UPDATE_TALL: the 64 x 64 / 128 x 64 configurations under
+// kernel names of their own (the LU trailing update).
+enum { GEMM_SQUARE = 0, GEMM_TALL = 1, GEMM_UPDATE = 3, GEMM_UPDATE_TALL = 4 };
 
 // C_b = alpha op(A_b) B_b + beta C_b; transA 0: A is M x K; 2: A stored K x M, op = ^*.
 // `work` (optional, work_elems entries) enables split-K for small outputs.

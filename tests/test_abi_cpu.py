@@ -160,6 +160,60 @@ def test_reduced_eig_against_brute_force(t):
         assert r <= 1e-13 * (abs(be[i]) * np.linalg.norm(A) + abs(al[i]) * np.linalg.norm(B))
 
 
+@pytest.mark.parametrize("t", [1, 2, 3, 17, 64, 160])
+def test_reduced_eig_triangular_B_standard_form(t):
+    # The method's projected B is upper triangular (R_2 of the QR of B U_1):
+    # the solver then works on B^{-1} A; eigenvalues against brute force and
+    # every eigenvector's residual with the original pair.
+    rng = np.random.default_rng(100 + t)
+    A = (rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))) / np.sqrt(t)
+    B = np.triu(0.05 * (rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))))
+    B[np.diag_indices(t)] = 1.0 + 0.2 * rng.normal(size=t)
+    al, be, Y = fm.feast_reduced_eig(A, B)
+    assert np.all(be == 1.0)
+    ref = sla.eigvals(A, B)
+    assert _match(al, ref) < 1e-11 * max(1.0, np.abs(ref).max())
+    nA, nB = np.linalg.norm(A), np.linalg.norm(B)
+    for i in range(t):
+        assert abs(np.linalg.norm(Y[:, i]) - 1) < 1e-12
+        r = np.linalg.norm(A @ Y[:, i] - al[i] * B @ Y[:, i])
+        assert r <= 1e-12 * (nA + abs(al[i]) * nB), (i, r)
+
+
+def test_reduced_eig_triangular_B_clusters_and_ritz_like_spectrum():
+    # A projected pencil as the method produces it: 40 eigenvalues of a known
+    # block in a disk (two pairs 1e-9 apart), 20 spurious ones elsewhere, a
+    # rounding-level lower triangle in B (the GEMM-computed U_2^* B U_1).
+    rng = np.random.default_rng(7)
+    t = 60
+    d = 0.8 * np.sqrt(rng.uniform(size=t)) * np.exp(2j * np.pi * rng.uniform(size=t))
+    d[40:] = 3.0 * d[40:] + 2.0
+    d[1] = d[0] + 1e-9
+    d[3] = d[2] + 1e-9j
+    S = np.eye(t) + 0.1 * (rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))) / np.sqrt(t)
+    R = np.triu(np.eye(t) + 0.05 * (rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))))
+    A = R @ S @ np.diag(d) @ np.linalg.inv(S)
+    B = R + 1e-17 * np.tril(rng.normal(size=(t, t)), -1)
+    al, be, Y = fm.feast_reduced_eig(A, B)
+    lam = al / be
+    assert _match(lam, d) < 1e-9
+    nA, nB = np.linalg.norm(A), np.linalg.norm(B)
+    for i in range(t):
+        r = np.linalg.norm(A @ Y[:, i] - lam[i] * B @ Y[:, i])
+        assert r <= 1e-12 * (nA + abs(lam[i]) * nB), (i, r)
+
+
+def test_reduced_eig_tiny_couplings_keep_full_accuracy():
+    # A nearly decoupled block: entries 1e-11 below a 4.5e-2 subdiagonal must
+    # still be reduced (their sum of squares is below the rounding of the
+    # column's), or the Hessenberg form is lost at the 1e-11 level.
+    M = np.array([[0.49, 0.045, 1e-11], [0.045, 0.2, 2e-9], [1e-11, 2e-9, 2.0]], complex)
+    al, be, Y = fm.feast_reduced_eig(M, np.eye(3, dtype=complex))
+    assert _match(al / be, np.linalg.eigvals(M)) < 1e-15
+    for i in range(3):
+        assert np.linalg.norm(M @ Y[:, i] - al[i] / be[i] * Y[:, i]) < 1e-15
+
+
 def test_reduced_eig_infinite_eigenvalues():
     # a rank-deficient Bt gives beta = 0 for as many eigenvalues as its rank defect
     rng = np.random.default_rng(2)

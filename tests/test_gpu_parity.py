@@ -204,6 +204,22 @@ def test_solve_scaled_workloads(k, n, prec):
     _compare_solve(p, r, ref)
 
 
+@pytest.mark.parametrize("prec", [fm.FP64, fm.MIXED])
+@pytest.mark.parametrize("update_tile", [0, 1])
+def test_solve_lookahead_and_tall_update(prec, update_tile):
+    # the look-ahead factorisation (next panel on a second stream) and the
+    # 128-row trailing-update tile against the oracle
+    p = pg.workload(2, n_override=1000)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=prec, lookahead=True,
+                 update_tile=update_tile) as plan:
+        r = plan.solve(A, B, V)
+    ref = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes)
+    assert r.flag == 1 and ref.flag == 1
+    assert len(r.lam) == p.s
+    _compare_solve(p, r, ref)
+
+
 def test_solve_example31():
     from conftest import load_example31
     A, B, eig = load_example31()
