@@ -33,6 +33,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (complex64 LU)
+
+# HBM bytes per launch of the LU trailing update, from two rocprofv3 PMC passes
+# (FETCH_SIZE, then WRITE_SIZE) of this script with --forms mixed,fp64 --steps 1
+# --warmup 0 --no-batched --no-cpu-baseline --copy-calibration, each scaled by
+# what the counter reads for the 1 GiB copy of --copy-calibration (fetch x2.000,
+# write x1.000); the summary and the commands are in profiles/.  The figures
+# hold for the kernel source they were taken on (its sha256), else `traffic`
+# is reported as null.
+TRAFFIC = {"source": "paper_1404_1768_amd/csrc/k_gemm.hip",
+           "sha256": "2242b21c1013095ac5cf2650eb7ed996f36fec568a32fe92473eecc8151fb829",
+           "mixed": {"fetch": 1756391315, "write": 1310961151},
+           "fp64": {"fetch": 4489191433, "write": 2621922301}}
+
+
+def kernel_traffic(form):
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC["source"])
+    try:
+        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    t = TRAFFIC.get(form)
+    if t is None or sha != TRAFFIC["sha256"]:
+        return None
+    return t["fetch"] + t["write"]
 DTYPE = {"fp64": "complex128", "mixed": "complex64+complex128"}
 
 
@@ -66,6 +91,7 @@ def time_form(form, p, A, B, V, steps, warmup):
              {k: round(v, 1) for k, v in last.times.items()}))
         return {"ms": ms, "ok": ok, "iters": last.iters, "filters": last.filters,
                 "err": last.err, "count": len(last.lam), "sweeps": last.sweeps,
+                "errs": [float("%.3g" % e) for e in last.errs],
                 "phases_ms": {k: round(v, 3) for k, v in last.times.items()},
                 "lu_gemm": last.lu_gemm}
     finally:
@@ -159,6 +185,11 @@ def main():
     ap.add_argument("--cpu-nodes", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain device copy of 1 GiB (3 launches): the reference "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters of a PMC run")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the n=8000, m=256 mixed-precision workload (key 'large')")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the path shards over quadrature nodes across GPUs "
@@ -174,6 +205,14 @@ def main():
     log("[bench] generated workload n=%d m=%d N=%d s=%d in %.1f s" %
         (p.n, p.m, p.nodes, p.s, time.perf_counter() - t0))
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.complex64, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 3 x (1 GiB read + 1 GiB written)")
+        del src, dst
     A = torch.from_numpy(p.A).to(dev)
     B = torch.from_numpy(p.B).to(dev)
     V = torch.from_numpy(p.V).to(dev)
@@ -189,7 +228,7 @@ def main():
     achieved = (lg["flops"] / (lg["ms"] * 1e-3) / 1e12) if lg["ms"] > 0 else 0.0
     roof = {"bound": "mfma", "kernel": "LU trailing-update GEMM (%s)" % DTYPE[best],
             "achieved": round(achieved, 2), "peak": PEAK[best], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[best], 4), "traffic": None,
+            "frac": round(achieved / PEAK[best], 4), "traffic": kernel_traffic(best),
             "launches": lg["launches"],
             "avg_launch_us": round(lg["ms"] * 1e3 / max(1, lg["launches"]), 2),
             "flops_per_launch": round(lg["flops"] / max(1, lg["launches"]))}
@@ -201,6 +240,14 @@ def main():
         bV = [torch.from_numpy(q.V).to(dev) for q in ps]
         batched = time_batch(ps, bA, bB, bV, min(args.steps, 3), max(args.warmup, 1))
         del bA, bB, bV
+    large = None
+    if args.large:
+        pl = pg.workload(3)
+        lA, lB, lV = (torch.from_numpy(x).to(dev) for x in (pl.A, pl.B, pl.V))
+        r = time_form("mixed", pl, lA, lB, lV, min(args.steps, 2), 1)
+        large = {"workload": "pencil n=8000 N=32 m=256 s=120 (394 eigenvalues in 1.05..1.2)",
+                 "mixed": r}
+        del lA, lB, lV
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, b["iters"], b["filters"], args.cpu_nodes)
@@ -213,6 +260,7 @@ def main():
         "config": {"workload": "pencil n=4000 N=32 m=160 s=100 (trapezoid, circle 1+1i r=1)",
                    "form": best, "n": p.n, "nodes": p.nodes, "m": p.m, "eps": 1e-10},
         "forms": forms, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
 

@@ -955,7 +955,8 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       st[p].lam.resize(m);
       st[p].hn.resize(3 * m);
     }
-    int sweeps = 0;  // mixed form: corrections per node (none on the first filter)
+    int sweeps = 0;       // mixed form: corrections per node of the next filter
+    int base_sweeps = 0;  // (none on Search's filter)
     auto grouped_filter = [&]() {
       Timer t;
       filter_all(b, dA, lda, dB, ldb, b->mixed() ? sweeps : 0);
@@ -1106,7 +1107,9 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
           feast::gather_normalize_cols(s, q->wblk(feast_plan::W_X), m, n, didx, c_k,
                                        q->wblk(feast_plan::W_XPREV), m, nullptr);
         }
-        if (b->mixed() && k >= 2 && c_k == st[p].c_prev && e_k >= b->o.eps) refine_more = true;
+        if (b->mixed() && k >= 2 && c_k == st[p].c_prev && e_k >= b->o.eps &&
+            e_k > 0.5 * st[p].e_prev)
+          refine_more = true;
         st[p].e_prev = e_k;
         st[p].c_prev = c_k;
       }
@@ -1115,10 +1118,19 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       for (int p = 0; p < P; ++p) any = any || !st[p].done;
       if (!any) break;
       // line 16 for the pencils still iterating (one grouped filter), line 17
+      // mixed form: as feast_solve, one grouped sweep count for all pencils --
+      // refined once any pencil still iterating has e(k) <= 1e-4 (or on the
+      // first filter after Search), one more on a stall
+      int sweeps_now = 0;
       if (b->mixed()) {
-        if (sweeps == 0) sweeps = 1;
-        else if (refine_more && sweeps < b->o.max_sweeps) ++sweeps;
+        if (base_sweeps == 0) base_sweeps = 1;
+        else if (refine_more && base_sweeps < b->o.max_sweeps) ++base_sweeps;
+        bool close = (k == 1);
+        for (int p = 0; p < P; ++p)
+          if (!st[p].done && std::isfinite(st[p].e_prev) && st[p].e_prev <= 1e-4) close = true;
+        sweeps_now = close ? base_sweeps : 0;
       }
+      sweeps = sweeps_now;
       for (int p = 0; p < P; ++p)
         if (!st[p].done)
           feast::copy_block_z(s, b->sub[p]->wblk(feast_plan::W_BU1), b->m[p], b->n[p], b->m[p],

@@ -753,11 +753,21 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
     const int64_t mm = m * m;
     std::vector<feast_z> hAt(mm), hBt(mm), hY(mm), halpha(m), hbeta(m);
     std::vector<double> hn(3 * m);
-    // Mixed form: Search's filter is not refined, later filters get `sweeps`
-    // corrections (one more whenever a refined iteration missed eps).
+    // Mixed form: Search's filter is not refined; a later filter gets `sweeps`
+    // corrections (one more whenever a refined iteration missed eps without
+    // halving e(k)) unless the last known e(k) is infinite or above
+    // kRefineFrom, where the complex64 solves are already more accurate than
+    // the subspace (the first filter after Search, with no e(k) yet, is refined).
+    constexpr double kRefineFrom = 1e-4;
     int sweeps = p->mixed() ? 1 : 0;
+    auto sweeps_for = [&](double e_last, bool known) {
+      if (!p->mixed()) return 0;
+      if (known && !(e_last <= kRefineFrom)) return 0;
+      return sweeps;
+    };
+    int sweeps_now = sweeps;
     auto run_filter = [&](const z64 *R, z64 *Uout, bool first) -> int {
-      const int st = filter_rhs(p, A, lda, B, ldb, R, m, Uout, m, 0.0, first ? 0 : sweeps);
+      const int st = filter_rhs(p, A, lda, B, ldb, R, m, Uout, m, 0.0, first ? 0 : sweeps_now);
       if (inf.filters < FEAST_MAX_HISTORY) inf.sweeps[inf.filters] = p->last_sweeps;
       inf.filters += 1;
       return st;
@@ -782,25 +792,31 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
     HIPCHK(hipEventRecord(p->ev_cols, s));
     HIPCHK(hipStreamWaitEvent(s2, p->ev_cols, 0));
     // line 3
-    double e_prev = 0.0;
+    double e_prev = 0.0, e_prev2 = 0.0;
     int c_prev = 0;
     std::vector<cd> lam_prev;
     std::vector<double> r_prev;
     for (int k = 1; k <= p->o.max_iter; ++k) {
       // line 16 ahead of time: the next filter needs only B U_1, so it runs on
       // the GPU while the host solves the reduced pencil; it is skipped when
-      // this iteration is likely to be the last one
-      // (mixed form: an iteration fed by a refined filter after a settled count)
-      const bool likely_last = (k == p->o.max_iter) || (c_prev > 0 && e_prev < 1e3 * p->o.eps) ||
-                               (p->mixed() && k >= 2 && c_prev > 0 && e_prev < 1e-4);
+      // this iteration is likely to be the last one: e(k) predicted from the
+      // observed reduction factor e(k-1)/e(k-2) (before two values exist, a
+      // fast one), below eps.  A wrong guess only costs the overlap.
+      const double q = (k >= 3 && e_prev2 > 0.0 && std::isfinite(e_prev2) && std::isfinite(e_prev))
+                           ? std::min(1.0, e_prev / e_prev2)
+                           : 1e-8;
+      const bool likely_last =
+          (k == p->o.max_iter) || (c_prev > 0 && std::isfinite(e_prev) && e_prev * q < p->o.eps);
       bool speculated = false;
       Timer tf;
       if (!likely_last) {
+        sweeps_now = sweeps_for(e_prev, k >= 2);
         const int st = run_filter(BU1, UF, false);
         if (st == FEAST_REFINE_STAGNATED) status = st;
         else if (st != FEAST_OK) return st;
         speculated = true;
       }
+      const double launch_ms = tf.ms();
       // line 6: reduced pencil on the host
       Timer te;
       if (feast_reduced_eig(m, hAt.data(), m, hBt.data(), m, halpha.data(), hbeta.data(), hY.data(),
@@ -883,21 +899,28 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
         HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s2));
         feast::gather_normalize_cols(s2, X, m, n, didx, c_k, Xprev, m, nullptr);
       }
-      // a refined iteration whose count is settled but missed eps: refine harder
-      if (p->mixed() && k >= 2 && c_k == c_prev && e_k >= p->o.eps && sweeps < p->o.max_sweeps)
+      // a refined iteration whose count is settled, that missed eps and whose
+      // error stopped falling geometrically: the solves, not the subspace,
+      // limit the accuracy, so refine harder
+      if (p->mixed() && k >= 2 && c_k == c_prev && e_k >= p->o.eps && e_k > 0.5 * e_prev &&
+          sweeps < p->o.max_sweeps)
         ++sweeps;
+      e_prev2 = e_prev;
       e_prev = e_k;
       c_prev = c_k;
       HIPCHK(hipEventRecord(p->ev_panel, s2));
       inf.t_ritz_ms += tr.ms();
       // line 16 (unless it already ran)
+      // filter time: its launch plus whatever of it the host work did not hide
+      Timer tw;
       if (!speculated) {
+        sweeps_now = sweeps_for(e_k, true);
         const int st = run_filter(BU1, UF, false);
         if (st == FEAST_REFINE_STAGNATED) status = st;
         else if (st != FEAST_OK) return st;
       }
       HIPCHK(hipStreamSynchronize(s));
-      inf.t_filter_ms += tf.ms() - te.ms();
+      inf.t_filter_ms += launch_ms + tw.ms();
       // line 17 and line 5 of the next iteration (after the side stream is done with U_1)
       {
         Timer t;

@@ -63,7 +63,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   static_assert(BK == 8 || BK == 16, "BK");
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int PA = BM + 2, PB = BN + 2;
+  // LDS row pitch (32 banks of 4 bytes).  FP64 planes: a read of 16
+  // consecutive doubles covers the 32 banks; an odd pitch keeps the 16 rows of
+  // an A store apart.  complex64 planes: pitch BM + 2 (reads of rows k and k+1
+  // then share banks 2-way; an XOR swizzle removing that measured no faster
+  // and costs registers).
+  constexpr bool F32 = sizeof(real) == 4;
+  constexpr int PA = F32 ? BM + 2 : BM + 1, PB = F32 ? BN + 2 : BN + 1;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   __shared__ real sAr[2][BK][PA], sAi[2][BK][PA], sBr[2][BK][PB], sBi[2][BK][PB];
 
@@ -75,7 +81,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   lin /= tiles;
   const int64_t bidx = lin % d.batch;
   const int64_t split = lin / d.batch;
-  const int64_t m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  // tiles in groups of up to 8 tile rows, column by column inside a group:
+  // consecutive workgroups share the A row panels of the group (kept in L2)
+  // and read each B column panel once per group instead of once per tile row
+  constexpr int64_t G = 8;
+  const int64_t grp = tile / (G * tn);
+  const int64_t gr0 = grp * G;
+  const int64_t grows = (tm - gr0 < G) ? tm - gr0 : G;
+  const int64_t gt = tile - grp * G * tn;
+  const int64_t m0 = (gr0 + gt % grows) * BM, n0 = (gt / grows) * BN;
   const int64_t kbeg = split * d.kchunk;
   const int64_t kend = (kbeg + d.kchunk < d.K) ? kbeg + d.kchunk : d.K;
 
@@ -175,8 +189,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
       real ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a) {
-        ar[a] = sAr[buf][kk * 4 + krow][wm * WM + a * 16 + col16];
-        ai[a] = sAi[buf][kk * 4 + krow][wm * WM + a * 16 + col16];
+        const int kr = kk * 4 + krow;
+        ar[a] = sAr[buf][kr][wm * WM + a * 16 + col16];
+        ai[a] = sAi[buf][kr][wm * WM + a * 16 + col16];
         if (SUB) {  // accumulate (-A) B:  Cr += (-Ar) Br - (-Ai) Bi, Ci += (-Ar) Bi + (-Ai) Br
           ar[a] = -ar[a];
           ai[a] = -ai[a];
@@ -184,8 +199,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
       }
 #pragma unroll
       for (int b = 0; b < FN; ++b) {
-        br[b] = sBr[buf][kk * 4 + krow][wn * WN + b * 16 + col16];
-        bi[b] = sBi[buf][kk * 4 + krow][wn * WN + b * 16 + col16];
+        const int kr = kk * 4 + krow;
+        br[b] = sBr[buf][kr][wn * WN + b * 16 + col16];
+        bi[b] = sBi[buf][kr][wn * WN + b * 16 + col16];
       }
       // two sweeps over all tiles: an accumulator is reused only after every
       // other accumulator of the wave has been issued once

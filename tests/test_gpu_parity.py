@@ -253,3 +253,25 @@ def test_solve_full_size_fp64_workload():
     X = r.X.cpu().numpy()
     hr = host_residuals(p.A, p.B, r.lam, X)
     assert hr.max() <= 1e-10
+
+
+def test_solve_full_size_mixed_large_workload():
+    """n=8000, N=32, m=256 with 394 eigenvalues clustered just outside the
+    contour, complex64 LU with FP64 refinement: count, eigenvalues against the
+    planted spectrum (1e-10 relative), and host residuals of a sample of the
+    returned eigenpairs with the original A, B (the oracle's 32 dense LUs of
+    order 8000 are out of reach of a test)."""
+    p = pg.workload(3)
+    A, B, V = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=fm.MIXED, eps=1e-10) as plan:
+        r = plan.solve(A, B, V)
+    assert r.flag == 1, (r.flag, r.err, r.count[:r.iters])
+    assert len(r.lam) == p.s == 120
+    assert r.err <= 1e-10
+    d_in = p.d[p.inside_mask]
+    ri, ci, dist = match(r.lam, d_in)
+    assert np.all(dist <= 1e-10 * np.maximum(np.abs(d_in[ci]), 1e-3 * p.radius))
+    X = r.X.cpu().numpy()
+    sample = np.arange(0, len(r.lam), 12)
+    res = host_residuals(p.A, p.B, r.lam[sample], X[:, sample])
+    assert np.all(res <= 1e-10), res.max()
