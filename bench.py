@@ -42,9 +42,9 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # hold for the kernel source they were taken on (its sha256), else `traffic`
 # is reported as null.
 TRAFFIC = {"source": "paper_1404_1768_amd/csrc/k_gemm.hip",
-           "sha256": "2242b21c1013095ac5cf2650eb7ed996f36fec568a32fe92473eecc8151fb829",
-           "mixed": {"fetch": 1756391315, "write": 1310961151},
-           "fp64": {"fetch": 4489191433, "write": 2621922301}}
+           "sha256": "abc95c0fc2766a0eaa0ed27174c1ce9d111b9113d38a142ab2920625f57135f0",
+           "mixed": {"fetch": 1756998155, "write": 1310955785},
+           "fp64": {"fetch": 4260283815, "write": 2621911570}}
 
 
 def kernel_traffic(form):

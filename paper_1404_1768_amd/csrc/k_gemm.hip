@@ -55,7 +55,7 @@ template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
 // MFMAs use -A; the epilogue is then a plain store.  SUB = false is the general
 // C = alpha op(A) B + beta C with the C read in the epilogue.
 // One output tile: `lin` indexes the tiles x batch x splits of problem d.
-template <typename T, int BM, int BN, int TA, bool SUB, int BK>
+template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool M3>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   using Ops = mfma_ops<T>;
   using real = typename Ops::real;
@@ -72,6 +72,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   constexpr int PA = F32 ? BM + 2 : BM + 1, PB = F32 ? BN + 2 : BN + 1;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   __shared__ real sAr[2][BK][PA], sAi[2][BK][PA], sBr[2][BK][PB], sBi[2][BK][PB];
+  // M3: the three-multiplication complex product
+  //   T1 = (Ar + Ai) Br,  P = -Ai (Br + Bi),  Q = Ar (Bi - Br),
+  //   Re(AB) = T1 + P,    Im(AB) = T1 + Q
+  // (3 real MFMAs per complex step instead of 4; its normwise rounding bound is
+  // about twice the usual one).
+  // The operand sums are formed once, when a tile is staged in LDS: plane
+  // sAs = Ar + Ai, sBs = Br + Bi, and sBi holds Bi - Br.
+  __shared__ real sAs[2][M3 ? BK : 1][M3 ? PA : 1], sBs[2][M3 ? BK : 1][M3 ? PB : 1];
 
   const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
   const int64_t tiles = tm * tn;
@@ -134,6 +142,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
       for (int i = 0; i < NA; ++i) {
         sAr[buf][kk][rr + (256 / BK) * i] = ra[i].x;
         sAi[buf][kk][rr + (256 / BK) * i] = ra[i].y;
+        if constexpr (M3) sAs[buf][kk][rr + (256 / BK) * i] = ra[i].x + ra[i].y;
       }
     } else {
       const int rr = tid & 63, kk = tid >> 6;
@@ -142,6 +151,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
         const int r = rr + 64 * (i % (BM / 64)), k = kk + 4 * (i / (BM / 64));
         sAr[buf][k][r] = ra[i].x;
         sAi[buf][k][r] = -ra[i].y;
+        if constexpr (M3) sAs[buf][k][r] = ra[i].x - ra[i].y;
       }
     }
     const int cc = tid & 63, kk = tid >> 6;
@@ -149,11 +159,25 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
     for (int i = 0; i < NB; ++i) {
       const int c = cc + 64 * (i % (BN / 64)), k = kk + 4 * (i / (BN / 64));
       sBr[buf][k][c] = rb[i].x;
-      sBi[buf][k][c] = rb[i].y;
+      if constexpr (M3) {
+        sBi[buf][k][c] = rb[i].y - rb[i].x;
+        sBs[buf][k][c] = rb[i].x + rb[i].y;
+      } else {
+        sBi[buf][k][c] = rb[i].y;
+      }
     }
   };
 
   acc_t cr[FM][FN], ci[FM][FN];
+  acc_t t1[M3 ? FM : 1][M3 ? FN : 1];
+  if constexpr (M3) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t1[a][b][r] = 0;
+  }
   T *C = d.C + bidx * d.sC;
 #pragma unroll
   for (int a = 0; a < FM; ++a)
@@ -186,44 +210,85 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
     if (kt + 1 < nk) gload(kbeg + static_cast<int64_t>(kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      real ar[FM], ai[FM], br[FN], bi[FN];
+      const int kr = kk * 4 + krow;
+      if constexpr (M3) {
+        // cr accumulates P, ci accumulates Q, t1 accumulates T1 (A negated for C -= A B)
+        real as[FM], ai[FM], ar[FM], br[FN], bs[FN], bd[FN];
 #pragma unroll
-      for (int a = 0; a < FM; ++a) {
-        const int kr = kk * 4 + krow;
-        ar[a] = sAr[buf][kr][wm * WM + a * 16 + col16];
-        ai[a] = sAi[buf][kr][wm * WM + a * 16 + col16];
-        if (SUB) {  // accumulate (-A) B:  Cr += (-Ar) Br - (-Ai) Bi, Ci += (-Ar) Bi + (-Ai) Br
-          ar[a] = -ar[a];
-          ai[a] = -ai[a];
+        for (int a = 0; a < FM; ++a) {
+          const int c = wm * WM + a * 16 + col16;
+          as[a] = SUB ? -sAs[buf][kr][c] : sAs[buf][kr][c];
+          ai[a] = SUB ? sAi[buf][kr][c] : -sAi[buf][kr][c];  // -Ai for P
+          ar[a] = SUB ? -sAr[buf][kr][c] : sAr[buf][kr][c];
         }
-      }
-#pragma unroll
-      for (int b = 0; b < FN; ++b) {
-        const int kr = kk * 4 + krow;
-        br[b] = sBr[buf][kr][wn * WN + b * 16 + col16];
-        bi[b] = sBi[buf][kr][wn * WN + b * 16 + col16];
-      }
-      // two sweeps over all tiles: an accumulator is reused only after every
-      // other accumulator of the wave has been issued once
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
-          cr[a][b] = Ops::mma(ar[a], br[b], cr[a][b]);
-          ci[a][b] = Ops::mma(ar[a], bi[b], ci[a][b]);
+          const int c = wn * WN + b * 16 + col16;
+          br[b] = sBr[buf][kr][c];
+          bs[b] = sBs[buf][kr][c];
+          bd[b] = sBi[buf][kr][c];
         }
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) t1[a][b] = Ops::mma(as[a], br[b], t1[a][b]);
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) cr[a][b] = Ops::mma(ai[a], bs[b], cr[a][b]);
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) ci[a][b] = Ops::mma(ar[a], bd[b], ci[a][b]);
+      } else {
+        real ar[FM], ai[FM], br[FN], bi[FN];
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+          ar[a] = sAr[buf][kr][wm * WM + a * 16 + col16];
+          ai[a] = sAi[buf][kr][wm * WM + a * 16 + col16];
+          if (SUB) {  // accumulate (-A) B:  Cr += (-Ar) Br - (-Ai) Bi, Ci += (-Ar) Bi + (-Ai) Br
+            ar[a] = -ar[a];
+            ai[a] = -ai[a];
+          }
+        }
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
-          cr[a][b] = Ops::mma(-ai[a], bi[b], cr[a][b]);
-          ci[a][b] = Ops::mma(ai[a], br[b], ci[a][b]);
+          br[b] = sBr[buf][kr][wn * WN + b * 16 + col16];
+          bi[b] = sBi[buf][kr][wn * WN + b * 16 + col16];
         }
+        // two sweeps over all tiles: an accumulator is reused only after every
+        // other accumulator of the wave has been issued once
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            cr[a][b] = Ops::mma(ar[a], br[b], cr[a][b]);
+            ci[a][b] = Ops::mma(ar[a], bi[b], ci[a][b]);
+          }
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            cr[a][b] = Ops::mma(-ai[a], bi[b], cr[a][b]);
+            ci[a][b] = Ops::mma(ai[a], br[b], ci[a][b]);
+          }
+      }
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
 
+  if constexpr (M3) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cr[a][b][r] += t1[a][b][r];
+          ci[a][b][r] += t1[a][b][r];
+        }
+  }
   // epilogue
   const real alr = static_cast<real>(d.alpha.x), ali = static_cast<real>(d.alpha.y);
   const real ber = static_cast<real>(d.beta.x), bei = static_cast<real>(d.beta.y);
@@ -264,9 +329,18 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
 
 // UPD only renames the instance used for the LU trailing update (same code), so
 // that kernel traces time that update on its own.
+// Complex products take three real MFMAs per step (M3) in the single-problem
+// complex64 kernels and in the FP64 trailing update (where the extra LDS plane
+// and accumulators still allow two workgroups per compute unit at BK = 8).
+// Other FP64 products, and the grouped kernels of every type, keep four: the
+// grouped complex64 LU of the batched form loses enough backward accuracy with
+// three that a pencil near the tolerance needs one more refinement iteration,
+// which costs far more than the multiplications saved.
+template <typename T> constexpr bool kM3 = sizeof(T) == 8;
+
 template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool UPD = false>
 __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
-  gemm_tile<T, BM, BN, TA, SUB, BK>(d, xcd_remap(blockIdx.x, grid_total));
+  gemm_tile<T, BM, BN, TA, SUB, BK, kM3<T> || UPD>(d, xcd_remap(blockIdx.x, grid_total));
 }
 
 // A group of independent problems in one launch: tab[e].tile0 is the first
@@ -283,7 +357,7 @@ __global__ __launch_bounds__(256) void k_gemm_grp(const GemmArgs<T> *__restrict_
     else hi = mid - 1;
   }
   const GemmArgs<T> d = tab[lo];
-  gemm_tile<T, BM, BN, TA, SUB, BK>(d, lin - d.tile0);
+  gemm_tile<T, BM, BN, TA, SUB, BK, false>(d, lin - d.tile0);
 }
 
 // Deterministic reduction of split-K partials: C = sum_s W_s + beta C.
@@ -322,8 +396,9 @@ void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta, bool update = false
   const bool sub = d.splits == 1 && d.alpha.x == -1.0 && d.alpha.y == 0.0 && d.beta.x == 1.0 &&
                    d.beta.y == 0.0;
   if (ta == 0) {
-    if (sub && update)
-      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, BK, true>), grid, dim3(256), 0, s, d, padded);
+    if (sub && update)  // (FP64 update: BK = 8 keeps two workgroups per compute unit)
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, (sizeof(T) == 16 ? 8 : BK), true>), grid,
+                         dim3(256), 0, s, d, padded);
     else if (sub)
       hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, BK>), grid, dim3(256), 0, s, d, padded);
     else
