@@ -21,22 +21,109 @@ template <typename T> __device__ inline T czero() {
   return z;
 }
 
-// One workgroup of 1024 threads per matrix holds the leaf columns [c0, c0+w)
-// of rows [c0, n) in registers (thread t owns rows c0 + t + 1024 q) and
-// factors them column by column: |re|+|im| argmax over the column (wave64
-// shuffles, then every thread reduces the 16 wave results from LDS; ties go to
-// the lowest row), exchange of the pivot row with the diagonal row, scaling and
-// the rank-1 update of the remaining leaf columns -- two barriers per column.
-// The leaf's row swaps are then applied to the other columns of the enclosing
-// panel [pk0, pk0+pkb) as one gather: the composed permutation of the at most
-// 2w rows involved is read in full before any of it is written.
-template <typename T, int RPT, int IB>
-__global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld_in, int64_t stride,
-                                               int64_t n_in, int64_t c0, int w, int64_t pk0,
-                                               int pkb, int32_t *__restrict__ ipiv_all,
-                                               int32_t *__restrict__ info_all,
-                                               const GrpMat *__restrict__ grp, int nodes) {
+// 32-bit lane exchange through DPP (VALU, no LDS round trip); lanes that the
+// pattern gives no source read 0, the identity of the unsigned maxima below.
+template <int CTRL> __device__ inline uint32_t dpp32(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(0, static_cast<int>(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ inline uint64_t dpp64(uint64_t v) {
+  return (static_cast<uint64_t>(dpp32<CTRL>(static_cast<uint32_t>(v >> 32))) << 32) |
+         dpp32<CTRL>(static_cast<uint32_t>(v));
+}
+// Maximum of an unsigned key over the 64 lanes of a wavefront, returned
+// uniformly: swaps inside quads, rotations inside rows of 16, then the
+// broadcasts of lane 15 and lane 31 that leave the full maximum in lane 63.
+__device__ inline uint64_t wave_max_u64(uint64_t k) {
+  uint64_t o;
+  o = dpp64<0xb1>(k);  // quad_perm [1,0,3,2]
+  k = o > k ? o : k;
+  o = dpp64<0x4e>(k);  // quad_perm [2,3,0,1]
+  k = o > k ? o : k;
+  o = dpp64<0x124>(k);  // row_ror:4
+  k = o > k ? o : k;
+  o = dpp64<0x128>(k);  // row_ror:8
+  k = o > k ? o : k;
+  o = dpp64<0x142>(k);  // row_bcast:15
+  k = o > k ? o : k;
+  o = dpp64<0x143>(k);  // row_bcast:31
+  k = o > k ? o : k;
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(k), 63);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(k >> 32), 63);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Maximum over each row of 16 lanes, left in every lane of the row.
+__device__ inline uint64_t row16_max_u64(uint64_t k) {
+  uint64_t o;
+  o = dpp64<0xb1>(k);
+  k = o > k ? o : k;
+  o = dpp64<0x4e>(k);
+  k = o > k ? o : k;
+  o = dpp64<0x124>(k);
+  k = o > k ? o : k;
+  o = dpp64<0x128>(k);
+  k = o > k ? o : k;
+  return k;
+}
+__device__ inline uint64_t uniform_u64(uint64_t k) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(k));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(k >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Pivot keys: |re| + |im| of a candidate as an unsigned integer that orders
+// like the value (IEEE bits of a non-negative number, plus one so that 0 marks
+// "no candidate"; NaN is no candidate).  complex64 packs the row index into
+// the low half (complemented, so the lowest row wins a tie) and needs one
+// reduction; complex128 breaks ties in a second reduction over the row index.
+template <typename T> struct PivKey;
+template <> struct PivKey<c64> {
+  static constexpr bool kPacked = true;
+  __device__ static uint64_t key(c64 a, int row) {
+    const float v = fabsf(a.x) + fabsf(a.y);
+    if (!(v >= 0.0f)) return 0;
+    return (static_cast<uint64_t>(__float_as_uint(v)) << 32) | (0xFFFFFFFFu - static_cast<uint32_t>(row));
+  }
+};
+template <> struct PivKey<z64> {
+  static constexpr bool kPacked = false;
+  __device__ static uint64_t key(z64 a, int) {
+    const double v = fabs(a.x) + fabs(a.y);
+    if (!(v >= 0.0)) return 0;
+    return static_cast<uint64_t>(__double_as_longlong(v)) + 1;
+  }
+};
+
+// Rows of the leaf staged through LDS in blocks of at most NT rows, so that
+// global loads and stores walk along rows (IB consecutive lanes per row)
+// instead of one row per lane.
+template <typename T, int NT, int IB> struct LeafStage {
+  static constexpr int kRows = (NT * (IB + 1) * static_cast<int>(sizeof(T)) <= 81920) ? NT : NT / 2;
+};
+
+// One workgroup of NT threads per matrix holds the leaf columns [c0, c0+w)
+// of rows [c0, n) in registers (thread t owns rows c0 + t + NT q) and factors
+// them column by column with partial pivoting (largest |re|+|im|, lowest row
+// on ties; Section 4.3 reuses these factors for every filter).
+// Per column: each wavefront reduces its pivot key with DPP, the winning lane
+// posts its key and whole row to LDS, the owner of the diagonal row posts
+// that row, and after one barrier every thread picks the winner among the
+// posts, exchanges the two rows and applies the rank-1 update.  Posts are
+// double-buffered by column parity, so one barrier per column suffices.
+// The per-column selection work is repeated by every wavefront, so fewer,
+// fuller wavefronts (NT < 1024, more rows per thread) shorten a column.
+template <typename T, int NT, int RPT, int IB>
+__global__ __launch_bounds__(NT) void k_leaf(T *__restrict__ Mall, int64_t ld_in, int64_t stride,
+                                             int64_t n_in, int64_t c0, int w, int64_t pk0,
+                                             int pkb, int32_t *__restrict__ ipiv_all,
+                                             int32_t *__restrict__ info_all,
+                                             const GrpMat *__restrict__ grp, int nodes) {
   using Tr = cplx_traits<T>;
+  using PK = PivKey<T>;
+  constexpr int SR = LeafStage<T, NT, IB>::kRows;
+  constexpr int NW = NT / 64;
+  static_assert(NW <= 16, "at most 16 wavefronts");
   const int b = blockIdx.x;
   const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, b);
   T *M = mr.M;
@@ -44,171 +131,217 @@ __global__ __launch_bounds__(1024) void k_leaf(T *__restrict__ Mall, int64_t ld_
   if (c0 + w > n) return;  // (grouped: this matrix is already factored)
   int32_t *ipiv = ipiv_all + b * n_in;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double s_val[2][16];
-  __shared__ int s_idx[2][16];
+  __shared__ T stg[SR][IB + 1];
+  __shared__ uint64_t s_key[2][16];
+  __shared__ uint32_t s_row[2][16];
+  __shared__ T s_post[2][16][IB];
+  __shared__ T s_crow[2][IB];
   __shared__ int s_pivs[IB];
-  __shared__ T s_prow[IB];
-  __shared__ T s_crow[IB];
-  __shared__ int s_key[2 * IB], s_src[2 * IB];
-  __shared__ int s_nkey;
   int info_local = 0;
+  // rows of this thread relative to c0: tid + NT q (32-bit: rows < 2^31)
+  const int nrel = static_cast<int>(n - c0);
 
   T a[RPT][IB];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int64_t r = c0 + tid + 1024 * q;
+  for (int q = 0; q < RPT; ++q)
 #pragma unroll
-    for (int c = 0; c < IB; ++c) a[q][c] = (r < n && c < w) ? M[r * ld + c0 + c] : czero<T>();
-  }
+    for (int h = 0; h < NT / SR; ++h) {
+      const int64_t base = c0 + NT * q + SR * h;
+      const T *Mb = M + base * ld + c0;
+      const int lim = static_cast<int>(n - base < SR ? n - base : SR);  // rows of this block
+      if (lim <= 0) {  // the block lies below the matrix (uniform): nothing to read
+        if (tid >= SR * h && tid < SR * (h + 1))
+#pragma unroll
+          for (int c = 0; c < IB; ++c) a[q][c] = czero<T>();
+        continue;
+      }
+      // addresses clamped into the block's rows (lim >= 1), so all loads issue
+      // before the first wait
+      T t[SR * IB / NT];
+#pragma unroll
+      for (int k = 0; k < SR * IB / NT; ++k) {
+        const int e = tid + NT * k, i = e / IB, c = e % IB;
+        t[k] = Mb[(i < lim ? i : 0) * static_cast<int>(ld) + (c < w ? c : 0)];
+      }
+#pragma unroll
+      for (int k = 0; k < SR * IB / NT; ++k) {
+        const int e = tid + NT * k, i = e / IB, c = e % IB;
+        stg[i][c] = (i < lim && c < w) ? t[k] : czero<T>();
+      }
+      __syncthreads();
+      if (tid >= SR * h && tid < SR * (h + 1))
+#pragma unroll
+        for (int c = 0; c < IB; ++c) a[q][c] = stg[tid - SR * h][c];
+      __syncthreads();
+    }
 
 #pragma unroll
   for (int c = 0; c < IB; ++c) {
     if (c >= w) break;
     const int64_t rc = c0 + c;
     const int par = c & 1;
-    double best = -1.0;
-    int bidx = INT_MAX;
+    // this thread's best candidate (relative rows c .. nrel-1)
+    uint64_t best = 0;
+    int bq = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int64_t r = c0 + tid + 1024 * q;
-      if (r >= rc && r < n) {
-        const double v = Tr::abs1(a[q][c]);
-        if (v > best) {
-          best = v;
-          bidx = static_cast<int>(r);
-        }
+      const int r = tid + NT * q;
+      const uint64_t k = (r >= c && r < nrel) ? PK::key(a[q][c], static_cast<int>(c0) + r) : 0;
+      if (k > best) {  // strict: the lowest row of this thread wins a tie
+        best = k;
+        bq = q;
       }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bidx, off, 64);
-      if (ov > best || (ov == best && oi < bidx)) {
-        best = ov;
-        bidx = oi;
-      }
+    const int myrow = static_cast<int>(c0) + tid + NT * bq;
+    const uint64_t wbest = wave_max_u64(best);
+    bool mine = best == wbest && wbest != 0;
+    if constexpr (!PK::kPacked) {
+      // ties in value: the lowest row among the lanes holding the maximum
+      const uint64_t ik = mine ? 0xFFFFFFFFull - static_cast<uint32_t>(myrow) : 0;
+      const uint64_t wi = wave_max_u64(ik);
+      mine = mine && ik == wi;
     }
-    if (lane == 0) {
-      s_val[par][wave] = best;
-      s_idx[par][wave] = bidx;
-    }
-    __syncthreads();
-    double bv = s_val[par][0];
-    int bi = s_idx[par][0];
-#pragma unroll
-    for (int k = 1; k < 16; ++k) {
-      const double v = s_val[par][k];
-      const int i = s_idx[par][k];
-      if (v > bv || (v == bv && i < bi)) {
-        bv = v;
-        bi = i;
-      }
-    }
-    if (bi == INT_MAX) {  // no comparable entry (NaN column): keep the diagonal row
-      bi = static_cast<int>(rc);
-      bv = 0.0;
-    }
-    if (bv == 0.0 && info_local == 0) info_local = static_cast<int>(rc) + 1;
-    const int64_t p = bi;
-    if (tid == 0) {
-      s_pivs[c] = bi;
-      ipiv[rc] = bi;
-    }
-    const int64_t prel = p - c0;
-    const int ptid = static_cast<int>(prel & 1023), pq = static_cast<int>(prel >> 10);
-    if (tid == ptid) {
+    if (mine) {
+      s_key[par][wave] = wbest;
+      s_row[par][wave] = static_cast<uint32_t>(myrow);
 #pragma unroll
       for (int q = 0; q < RPT; ++q)
-        if (q == pq)
+        if (q == bq)
 #pragma unroll
-          for (int k = 0; k < IB; ++k) s_prow[k] = a[q][k];
+          for (int k = 0; k < IB; ++k) s_post[par][wave][k] = a[q][k];
     }
-    if (tid == c) {
+    if (wbest == 0 && lane == 0) s_key[par][wave] = 0;  // no candidate in this wavefront
+    if (tid == c)
 #pragma unroll
-      for (int k = 0; k < IB; ++k) s_crow[k] = a[0][k];
-    }
+      for (int k = 0; k < IB; ++k) s_crow[par][k] = a[0][k];
     __syncthreads();
-    if (tid == c) {
-#pragma unroll
-      for (int k = 0; k < IB; ++k) a[0][k] = s_prow[k];
+    // the winner among the posts: lane v of every row of 16 reads post v
+    const int pv = lane & 15;
+    const uint64_t pk = pv < NW ? s_key[par][pv] : 0;
+    const uint32_t prw = pv < NW ? s_row[par][pv] : 0xFFFFFFFFu;
+    const uint64_t gk = uniform_u64(row16_max_u64(pk));
+    uint32_t grow = 0xFFFFFFFFu - static_cast<uint32_t>(gk);
+    if constexpr (!PK::kPacked) {  // ties in value: the lowest row
+      const uint64_t rk = (pk == gk && gk != 0) ? 0xFFFFFFFFull - prw : 0;
+      grow = 0xFFFFFFFFu - static_cast<uint32_t>(uniform_u64(row16_max_u64(rk)));
     }
-    if (tid == ptid && p != rc) {
+    const uint64_t hit = __builtin_amdgcn_ballot_w64(gk != 0 && pk == gk && prw == grow);
+    const int gw = hit ? static_cast<int>(__builtin_ctzll(hit) & 15) : -1;
+    int64_t p = rc;
+    T prow[IB];
+    if (gw >= 0) {
+      p = grow;
 #pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q == pq)
+      for (int k = 0; k < IB; ++k) prow[k] = s_post[par][gw][k];
+    } else {  // no comparable entry (NaN column): keep the diagonal row
 #pragma unroll
-          for (int k = 0; k < IB; ++k) a[q][k] = s_crow[k];
+      for (int k = 0; k < IB; ++k) prow[k] = s_crow[par][k];
     }
-    const T piv = s_prow[c];
+    const T piv = prow[c];
     const bool zero = (piv.x == 0 && piv.y == 0);
+    if ((zero || gw < 0) && info_local == 0) info_local = static_cast<int>(rc) + 1;
+    if (tid == 0) s_pivs[c] = static_cast<int>(p);
+    if (p != rc) {
+      const int prel = static_cast<int>(p - c0);
+      const int ptid = prel % NT, pq = prel / NT;
+      if (tid == c)
+#pragma unroll
+        for (int k = 0; k < IB; ++k) a[0][k] = prow[k];
+      if (tid == ptid)
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+          if (q == pq)
+#pragma unroll
+            for (int k = 0; k < IB; ++k) a[q][k] = s_crow[par][k];
+    }
     const T inv = zero ? czero<T>() : Tr::recip(piv);
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const int64_t r = c0 + tid + 1024 * q;
-      if (r > rc && r < n) {
+      const int r = tid + NT * q;
+      if (r > c && r < nrel) {
         const T l = Tr::mul(a[q][c], inv);
         a[q][c] = l;
 #pragma unroll
-        for (int k = c + 1; k < IB; ++k) a[q][k] = Tr::fms(a[q][k], l, s_prow[k]);
+        for (int k = c + 1; k < IB; ++k) a[q][k] = Tr::fms(a[q][k], l, prow[k]);
       }
     }
   }
 
+  // leaf columns back through LDS (row-contiguous stores), then the pivots
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int64_t r = c0 + tid + 1024 * q;
-    if (r < n)
+  for (int q = 0; q < RPT; ++q)
 #pragma unroll
-      for (int c = 0; c < IB; ++c)
-        if (c < w) M[r * ld + c0 + c] = a[q][c];
-  }
-  // composed permutation of the rows touched by the leaf's swaps
-  if (tid == 0) {
-    int nk = 0;
-    for (int c = 0; c < w; ++c) {
-      const int r1 = static_cast<int>(c0) + c, r2 = s_pivs[c];
-      int i1 = -1, i2 = -1;
-      for (int k = 0; k < nk; ++k) {
-        if (s_key[k] == r1) i1 = k;
-        if (s_key[k] == r2) i2 = k;
+    for (int h = 0; h < NT / SR; ++h) {
+      const int64_t base = c0 + NT * q + SR * h;
+      __syncthreads();
+      if (tid >= SR * h && tid < SR * (h + 1))
+#pragma unroll
+        for (int c = 0; c < IB; ++c) stg[tid - SR * h][c] = a[q][c];
+      __syncthreads();
+      T *Mb = M + base * ld + c0;
+      const int lim = static_cast<int>(n - base < SR ? n - base : SR);
+#pragma unroll
+      for (int k = 0; k < SR * IB / NT; ++k) {
+        const int e = tid + NT * k, i = e / IB, c = e % IB;
+        if (i < lim && c < w) Mb[i * static_cast<int>(ld) + c] = stg[i][c];
       }
-      if (i1 < 0) {
-        s_key[nk] = r1;
-        s_src[nk] = r1;
-        i1 = nk++;
-      }
-      if (i2 < 0) {
-        s_key[nk] = r2;
-        s_src[nk] = r2;
-        i2 = nk++;
-      }
-      const int t = s_src[i1];
-      s_src[i1] = s_src[i2];
-      s_src[i2] = t;
     }
-    s_nkey = nk;
-  }
-  __syncthreads();
-  const int nk = s_nkey;
+  if (tid < w) ipiv[c0 + tid] = s_pivs[tid];
+  // The leaf's swaps (c0 + c <-> s_pivs[c], in order) applied to the other
+  // columns of the panel as one gather.  Destinations: the w leaf rows and
+  // each distinct pivot row below them; each thread finds the source of its
+  // destination by walking the swaps backwards, and all sources are read
+  // before any destination is written.
+  int pv_[IB];
+#pragma unroll
+  for (int c = 0; c < IB; ++c) pv_[c] = c < w ? s_pivs[c] : -1;
   const int ncol = pkb;  // panel columns; the leaf's own columns are skipped
-  T v[2];
-  int64_t dst[2], col[2];
+  constexpr int H = 2048 / NT;  // 2 w pkb <= 2048 elements
+  T v[H];
+  int64_t dst[H], col[H];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int e = tid + 1024 * h;
+  for (int h = 0; h < H; ++h) {
+    const int e = tid + NT * h;
+    v[h] = czero<T>();
+    col[h] = 0;
     dst[h] = -1;
-    if (e < ncol * nk) {
-      const int k = e / ncol;
-      col[h] = pk0 + e % ncol;
-      if ((col[h] < c0 || col[h] >= c0 + w) && s_key[k] != s_src[k]) {
-        v[h] = M[static_cast<int64_t>(s_src[k]) * ld + col[h]];
-        dst[h] = s_key[k];
+    const int k = e / ncol;
+    if (k < 2 * w) {
+      int key = -1;
+      if (k < w) {
+        key = static_cast<int>(c0) + k;
+      } else {
+        const int j = k - w;
+        int pj = -1;
+#pragma unroll
+        for (int c = 0; c < IB; ++c)
+          if (c == j) pj = pv_[c];
+        bool first = pj >= c0 + w;
+#pragma unroll
+        for (int c = 0; c < IB; ++c)
+          if (c < j && pv_[c] == pj) first = false;
+        if (first) key = pj;
+      }
+      if (key >= 0) {
+        int src = key;
+#pragma unroll
+        for (int c = IB - 1; c >= 0; --c)
+          if (c < w) {
+            const int top = static_cast<int>(c0) + c;
+            if (src == top) src = pv_[c];
+            else if (src == pv_[c]) src = top;
+          }
+        col[h] = pk0 + e % ncol;
+        if ((col[h] < c0 || col[h] >= c0 + w) && src != key) {
+          v[h] = M[static_cast<int64_t>(src) * ld + col[h]];
+          dst[h] = key;
+        }
       }
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < H; ++h)
     if (dst[h] >= 0) M[dst[h] * ld + col[h]] = v[h];
   if (tid == 0 && info_local != 0 && info_all[b] == 0) info_all[b] = info_local;
 }
@@ -442,11 +575,11 @@ __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t v) {
   if (i < count) p[i] = v;
 }
 
-template <typename T, int RPT, int IB>
+template <typename T, int RPT, int IB, int NT = 1024>
 void launch_leaf(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
                  int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
                  const GrpMat *grp, int nodes) {
-  hipLaunchKernelGGL((k_leaf<T, RPT, IB>), dim3(batch), dim3(1024), 0, s, M, ld, stride, n, c0, w,
+  hipLaunchKernelGGL((k_leaf<T, NT, RPT, IB>), dim3(batch), dim3(NT), 0, s, M, ld, stride, n, c0, w,
                      pk0, pkb, ipiv, info, grp, nodes);
 }
 
@@ -471,11 +604,12 @@ bool leaf_lu<z64>(hipStream_t s, z64 *M, int64_t ld, int64_t stride, int32_t bat
                   int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
                   const GrpMat *grp, int nodes) {
   const int64_t rows = n - c0;
-  if (w < 1 || w > leaf_max_width<z64>(rows) || pkb > 1024) return false;
+  if (w < 1 || w > leaf_max_width<z64>(rows) || 2 * w * pkb > 2048) return false;
+  // (complex128 leaves of up to 2048 rows run a little faster with 512 threads)
   if (rows <= 1024)
-    launch_leaf<z64, 1, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
+    launch_leaf<z64, 2, 8, 512>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 2048)
-    launch_leaf<z64, 2, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
+    launch_leaf<z64, 4, 8, 512>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 4096)
     launch_leaf<z64, 4, 4>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 8192)
@@ -490,7 +624,7 @@ bool leaf_lu<c64>(hipStream_t s, c64 *M, int64_t ld, int64_t stride, int32_t bat
                   int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
                   const GrpMat *grp, int nodes) {
   const int64_t rows = n - c0;
-  if (w < 1 || w > leaf_max_width<c64>(rows) || pkb > 1024) return false;
+  if (w < 1 || w > leaf_max_width<c64>(rows) || 2 * w * pkb > 2048) return false;
   if (rows <= 1024)
     launch_leaf<c64, 1, 8>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info, grp, nodes);
   else if (rows <= 2048)

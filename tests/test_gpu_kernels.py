@@ -94,6 +94,25 @@ def test_zgetrf_many_workgroups_per_panel_step():
         assert err < 1e-14 * n, err
 
 
+@pytest.mark.parametrize("n,nb", [(600, 64), (2100, 0)])
+def test_zgetrf_leaf_row_blocks_past_the_last_row(n, nb):
+    # the panel leaves stage their rows through LDS in fixed blocks; at these
+    # orders whole blocks lie below the last row of a matrix and must be
+    # skipped (the last matrix of the batch ends its allocation)
+    rng = np.random.default_rng(n + 11)
+    batch = 2
+    M = crand(rng, batch, n, n)
+    tM = torch.from_numpy(M).to(DEV)
+    piv, info = fm.zgetrf_batched(tM, nb=nb)
+    assert np.all(info.cpu().numpy() == 0)
+    F, piv = tM.cpu().numpy(), piv.cpu().numpy()
+    for b in range(batch):
+        L = np.tril(F[b], -1) + np.eye(n)
+        U = np.triu(F[b])
+        err = np.linalg.norm(_apply_pivots(M[b], piv[b]) - L @ U) / np.linalg.norm(M[b])
+        assert err < 1e-14 * n, err
+
+
 def test_zgetrf_reports_exact_zero_pivot():
     n = 40
     rng = np.random.default_rng(5)
