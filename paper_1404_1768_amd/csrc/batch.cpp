@@ -458,20 +458,26 @@ void filter_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
         feast::c_to_z(s, Yc + b->yoff[p], b->ldY(p), 0, b->n[p], b->ldY(p), 1, Y + b->yoff[p],
                       b->ldY(p), 0);
       for (int sw = 0; sw < sweeps; ++sw) {
-        // FP64 residual r_j = R - z_j (B Y_j) + A Y_j of all nodes of a pencil
-        // as two products, then the complex64 correction
+        // FP64 residual r_j = R - (z_j B - A) Y_j of all nodes of a pencil in
+        // one launch, then the complex64 correction
         for (int p = 0; p < b->P; ++p) {
           const int c = b->order[p];
           const int64_t n = b->n[p], ldy = b->ldY(p);
           const z64 *A = reinterpret_cast<const z64 *>(dA[c]);
           const z64 *B = reinterpret_cast<const z64 *>(dB[c]);
           z64 *t1 = T1 + b->toff[p], *t2 = T2 + b->toff[p], *y = Y + b->yoff[p];
-          gemm_t<z64>(s, 0, n, ldy, n, make_double2(1.0, 0.0), A, lda[c], 0, y, ldy, 0,
-                      make_double2(0.0, 0.0), t1, ldy, 0, 1);
-          gemm_t<z64>(s, 0, n, ldy, n, make_double2(1.0, 0.0), B, ldb[c], 0, y, ldy, 0,
-                      make_double2(0.0, 0.0), t2, ldy, 0, 1);
-          feast::shift_residual(s, b->sub[p]->R.as<z64>(), b->m[p], t1, t2, ldy,
-                                b->sub[p]->dz.as<z64>(), N, n, b->m[p]);
+          if (lda[c] == ldb[c]) {
+            feast::zgemm_shift_residual(s, n, b->m[p], n, A, B, lda[c], b->sub[p]->dz.as<z64>(), y,
+                                        ldy, b->m[p], b->sub[p]->R.as<z64>(), b->m[p], 0, t1, ldy,
+                                        b->m[p], N);
+          } else {
+            gemm_t<z64>(s, 0, n, ldy, n, make_double2(1.0, 0.0), A, lda[c], 0, y, ldy, 0,
+                        make_double2(0.0, 0.0), t1, ldy, 0, 1);
+            gemm_t<z64>(s, 0, n, ldy, n, make_double2(1.0, 0.0), B, ldb[c], 0, y, ldy, 0,
+                        make_double2(0.0, 0.0), t2, ldy, 0, 1);
+            feast::shift_residual(s, b->sub[p]->R.as<z64>(), b->m[p], t1, t2, ldy,
+                                  b->sub[p]->dz.as<z64>(), N, n, b->m[p]);
+          }
           feast::gather_rows<z64>(s, t1, ldy, b->m[p], perm + p * N * nmax, n, b->m[p], N, t2, ldy,
                                   b->m[p], nmax);
           feast::z_to_c(s, t2, ldy, 0, n, ldy, 1, Yc + b->yoff[p], ldy, 0);

@@ -289,7 +289,7 @@ void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr) {
 }
 
 // Mixed form: complex64 LU solves; FP64 residual r_j = R - (z_j B - A) Y_j of
-// all nodes as the two GEMMs A Y and B Y; the complex64 correction
+// all nodes (one launch, z_j B - A formed per staged tile); the complex64 correction
 // d_j = (LU32_j)^{-1} r_j and the FP64 update Y_j += d_j.
 //   target > 0 : sweep until every node's normwise backward error
 //                ||r_j||_F / ((|z_j| ||B||_F + ||A||_F) ||Y_j||_F + ||R||_F) <= target
@@ -324,9 +324,14 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
   double prev_worst = INFINITY;
   for (int sweep = 0; sweep <= max_corr; ++sweep) {
     if (!verify && sweep == max_corr) break;
-    gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), A, lda, 0, Y, ldY, 0, zc(0.0), T1, ldY, 0, 1);
-    gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), B, ldb, 0, Y, ldY, 0, zc(0.0), T2, ldY, 0, 1);
-    feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, m);
+    if (lda == ldb) {  // r_j = R - (z_j B - A) Y_j, shifted matrices formed tile by tile
+      feast::zgemm_shift_residual(s, n, m, n, A, B, lda, p->dz.as<z64>(), Y, ldY, m, R, ldr, 0, T1,
+                                  ldY, m, N);
+    } else {
+      gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), A, lda, 0, Y, ldY, 0, zc(0.0), T1, ldY, 0, 1);
+      gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), B, ldb, 0, Y, ldY, 0, zc(0.0), T2, ldY, 0, 1);
+      feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, m);
+    }
     if (verify) {
       feast::fro2_batched(s, T1, ldY, m, n, m, N, part, nrm);
       feast::fro2_batched(s, Y, ldY, m, n, m, N, part, nrm + N);

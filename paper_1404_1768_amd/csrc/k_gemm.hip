@@ -55,8 +55,13 @@ template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
 // MFMAs use -A; the epilogue is then a plain store.  SUB = false is the general
 // C = alpha op(A) B + beta C with the C read in the epilogue.
 // One output tile: `lin` indexes the tiles x batch x splits of problem d.
-template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool M3>
+//
+// SHF (with SUB, TA = 0): the A operand is shift[b] A2 - A, formed from the two
+// staged tiles in registers before they are written to LDS, and the
+// accumulators start from C0 rather than C (C = C0 - (shift A2 - A) B).
+template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool M3, bool SHF = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
+  static_assert(!SHF || (SUB && TA == 0), "shifted operand: C0 - (s A2 - A) B only");
   using Ops = mfma_ops<T>;
   using real = typename Ops::real;
   using acc_t = typename Ops::acc_t;
@@ -103,12 +108,22 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
 
   const T *A = d.A + bidx * d.sA;
   const T *B = d.B + bidx * d.sB;
+  const T *A2 = SHF ? d.A2 + bidx * d.sA : nullptr;
+  real zr = 0, zi = 0;
+  if constexpr (SHF) {
+    zr = static_cast<real>(d.shift[bidx].x);
+    zi = static_cast<real>(d.shift[bidx].y);
+  }
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  // a wavefront whose whole output block lies outside C (ragged last tile)
+  // stages operands and meets the barriers but issues no MFMAs
+  const bool live = (m0 + wm * WM < d.M) && (n0 + wn * WN < d.N);
 
   T ra[NA], rb[NB];
+  T ra2[SHF ? NA : 1];
 
   auto gload = [&](int64_t k0) {
     if (TA == 0) {
@@ -118,6 +133,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
       for (int i = 0; i < NA; ++i) {
         const int64_t r = m0 + rr + (256 / BK) * i, k = k0 + kk;
         ra[i] = (r < d.M && k < kend) ? A[r * d.lda + k] : T{};
+        if constexpr (SHF) ra2[i] = (r < d.M && k < kend) ? A2[r * d.lda + k] : T{};
       }
     } else {
       // A stored K x M row-major; op(A) = A^*
@@ -138,6 +154,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   auto sstore = [&](int buf) {
     if (TA == 0) {
       const int kk = tid % BK, rr = tid / BK;
+      if constexpr (SHF) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          const real ex = zr * ra2[i].x - zi * ra2[i].y - ra[i].x;
+          const real ey = zr * ra2[i].y + zi * ra2[i].x - ra[i].y;
+          ra[i].x = ex;
+          ra[i].y = ey;
+        }
+      }
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
         sAr[buf][kk][rr + (256 / BK) * i] = ra[i].x;
@@ -191,7 +216,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
           const int64_t row = m0 + wm * WM + a * 16 + Ops::out_row(lane, r);
           const int64_t col = n0 + wn * WN + b * 16 + (lane & 15);
           if (row < d.M && col < d.N) {
-            const T o = C[row * d.ldc + col];
+            const T o = SHF ? d.C0[bidx * d.sC0 + row * d.ldc0 + col] : C[row * d.ldc + col];
             cr[a][b][r] = o.x;
             ci[a][b][r] = o.y;
           }
@@ -208,6 +233,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload(kbeg + static_cast<int64_t>(kt + 1) * BK);
+    if (live)
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + krow;
@@ -341,6 +367,13 @@ template <typename T> constexpr bool kM3 = sizeof(T) == 8;
 template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool UPD = false>
 __global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
   gemm_tile<T, BM, BN, TA, SUB, BK, kM3<T> || UPD>(d, xcd_remap(blockIdx.x, grid_total));
+}
+
+// C_b = C0_b - (shift[b] A2 - A) B_b (FP64: three-product form at BK = 8, as the
+// trailing update).
+template <typename T, int BK>
+__global__ __launch_bounds__(256) void k_gemm_shift(const GemmArgs<T> d, int64_t grid_total) {
+  gemm_tile<T, 64, 64, 0, true, BK, true, true>(d, xcd_remap(blockIdx.x, grid_total));
 }
 
 // A group of independent problems in one launch: tab[e].tile0 is the first
@@ -482,6 +515,19 @@ void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int co
 }
 template void gemm_group<z64>(hipStream_t, int, bool, const GemmArgs<z64> *, int, int64_t);
 template void gemm_group<c64>(hipStream_t, int, bool, const GemmArgs<c64> *, int, int64_t);
+
+void zgemm_shift_residual(hipStream_t s, int64_t M, int64_t N, int64_t K, const z64 *A,
+                          const z64 *A2, int64_t lda, const z64 *shift, const z64 *Y, int64_t ldy,
+                          int64_t sY, const z64 *R, int64_t ldr, int64_t sR, z64 *C, int64_t ldc,
+                          int64_t sC, int32_t batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  GemmArgs<z64> d{M, N, K, A, lda, 0, Y, ldy, sY, C, ldc, sC, make_double2(-1.0, 0.0),
+                  make_double2(1.0, 0.0), batch, 1, K > 0 ? K : 1, nullptr, 0, A2, shift, R, ldr, sR};
+  const int64_t total = ((M + 63) / 64) * ((N + 63) / 64) * batch;
+  const int64_t padded = (total + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_gemm_shift<z64, 8>), dim3(static_cast<unsigned>(padded)), dim3(256), 0, s, d,
+                     padded);
+}
 
 void zgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
            int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,

@@ -23,7 +23,24 @@ template <typename T> struct GemmArgs {
   int64_t kchunk;
   T *work;
   int64_t tile0;  // grouped launches: first linear tile of this problem
+  // shifted-operand products only (left null otherwise): op(A_b) is
+  // shift[b] A2 - A, and the accumulators start from C0 (+ b sC0) instead of C
+  const T *A2;
+  const z64 *shift;
+  const T *C0;
+  int64_t ldc0, sC0;
 };
+
+// Residuals of shifted systems in one launch: for b < batch,
+//   C_b = R_b - (shift[b] A2 - A) Y_b
+// with A, A2 (M x K, leading dimension lda, shared by all b), Y_b = Y + b sY
+// (K x N, ldy), R_b = R + b sR (M x N, ldr) and C_b = C + b sC (ldc); shift
+// is a device array of `batch` complex values.  The shifted matrix is formed
+// tile by tile while it is staged, so the product costs one GEMM per b.
+void zgemm_shift_residual(hipStream_t s, int64_t M, int64_t N, int64_t K, const z64 *A,
+                          const z64 *A2, int64_t lda, const z64 *shift, const z64 *Y, int64_t ldy,
+                          int64_t sY, const z64 *R, int64_t ldr, int64_t sR, z64 *C, int64_t ldc,
+                          int64_t sC, int32_t batch);
 
 // GEMM_UPDATE / GEMM_UPDATE_TALL: the 64 x 64 / 128 x 64 configurations under
 // kernel names of their own (the LU trailing update).
