@@ -17,6 +17,8 @@
 #include "host_eig.h"
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <limits>
@@ -358,10 +360,13 @@ int qz_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *
 //      Ritz pair's residual (eq. 5-1) is computed with the original A and B.
 int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *alpha, cd *beta,
             cd *Y, int64_t ldy, int nthreads) {
+  // threads: about one per 16 columns (at t = 160: up to 10)
+  const int nt = std::max(1, std::min<int>(nthreads, static_cast<int>((t + 15) / 16)));
   Mat H(t);
-  {
+  // C = Bt^{-1} At by back substitution, columns split over the threads
+  auto csolve = [&](int w) {
     std::vector<cd> x(t);
-    for (int64_t j = 0; j < t; ++j) {
+    for (int64_t j = w; j < t; j += nt) {
       for (int64_t i = 0; i < t; ++i) x[i] = At[i * lda + j];
       for (int64_t i = t - 1; i >= 0; --i) {
         cd acc = x[i];
@@ -371,10 +376,19 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
       }
       for (int64_t i = 0; i < t; ++i) H(i, j) = x[i];
     }
+  };
+  if (nt > 1) {
+    std::vector<std::thread> th;
+    for (int w = 1; w < nt; ++w) th.emplace_back(csolve, w);
+    csolve(0);
+    for (auto &x : th) x.join();
+  } else {
+    csolve(0);
   }
   for (const cd &v : H.a)
     if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return -1;
-  // 1. Hessenberg form; reflector k acts on rows/columns k+1..t-1
+  // 1. Hessenberg form; reflector k acts on rows/columns k+1..t-1 (one
+  // thread: at these orders a step is too short to share)
   std::vector<std::vector<cd>> refl(t);
   std::vector<double> rf(t, 0.0);
   {
@@ -423,6 +437,80 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
   const Mat H0 = H;
   const double hnorm = fro(H0);
   const double atol = std::max(kSafmin, kUlp * hnorm);
+  // 3. eigenvectors by inverse iteration on H0, then x = P_0 ... P_{t-3} v;
+  // the other threads take eigenvalues as the QR iteration deflates them
+  // (from the last index down), the QR thread joins when it is done
+  std::atomic<int64_t> ready{t};  // alpha[j] is final for j >= ready
+  std::atomic<bool> failed{false};
+  auto eigvec = [&](int64_t j, std::vector<cd> &lu, std::vector<cd> &v, std::vector<int8_t> &sw) {
+    const cd lam = alpha[j];
+    // LU of H0 - lam I (upper Hessenberg, column-major copy in lu): eliminate
+    // the subdiagonal with row interchanges between k and k+1
+    for (int64_t q = 0; q < t * t; ++q) lu[q] = H0.a[q];
+    for (int64_t k = 0; k < t; ++k) lu[k * t + k] -= lam;
+    const double tiny = std::max(kSafmin, kUlp * hnorm);
+    for (int64_t k = 0; k + 1 < t; ++k) {
+      cd &dk = lu[k * t + k];
+      cd &sk = lu[k * t + k + 1];
+      sw[k] = std::abs(sk) > std::abs(dk) ? 1 : 0;
+      if (sw[k])
+        for (int64_t jj = k; jj < t; ++jj) std::swap(lu[jj * t + k], lu[jj * t + k + 1]);
+      cd piv = lu[k * t + k];
+      if (std::abs(piv) < tiny) piv = lu[k * t + k] = tiny;
+      const cd mlt = lu[k * t + k + 1] / piv;
+      lu[k * t + k + 1] = mlt;
+      for (int64_t jj = k + 1; jj < t; ++jj) lu[jj * t + k + 1] -= mlt * lu[jj * t + k];
+    }
+    if (std::abs(lu[(t - 1) * t + t - 1]) < tiny) lu[(t - 1) * t + t - 1] = tiny;
+    std::fill(v.begin(), v.end(), cd(1.0));
+    for (int pass = 0; pass < 2; ++pass) {
+      // forward (unit lower, with the interchanges), then backward (upper)
+      for (int64_t k = 0; k + 1 < t; ++k) {
+        if (sw[k]) std::swap(v[k], v[k + 1]);
+        v[k + 1] -= lu[k * t + k + 1] * v[k];
+      }
+      for (int64_t k = t - 1; k >= 0; --k) {
+        cd acc = v[k];
+        for (int64_t jj = k + 1; jj < t; ++jj) acc -= lu[jj * t + k] * v[jj];
+        v[k] = acc / lu[k * t + k];
+      }
+      double nr = 0.0;
+      for (const cd &e : v) nr = std::max(nr, std::abs(e));
+      if (nr > 0.0)
+        for (cd &e : v) e /= nr;
+    }
+    for (int64_t k = t - 3; k >= 0; --k) {
+      if (refl[k].empty()) continue;
+      const std::vector<cd> &u = refl[k];
+      const int64_t L = t - k - 1;
+      cd d = 0.0;
+      for (int64_t i = 0; i < L; ++i) d += std::conj(u[i]) * v[k + 1 + i];
+      d *= rf[k];
+      for (int64_t i = 0; i < L; ++i) v[k + 1 + i] -= d * u[i];
+    }
+    double nr = 0.0;
+    for (const cd &e : v) nr += std::norm(e);
+    nr = std::sqrt(nr);
+    for (int64_t i = 0; i < t; ++i) Y[i * ldy + j] = nr > 0.0 ? v[i] / nr : v[i];
+  };
+  std::atomic<int64_t> next{t - 1};
+  auto worker = [&]() {
+    std::vector<cd> lu(t * t), v(t);
+    std::vector<int8_t> sw(t);
+    for (;;) {
+      const int64_t j = next.fetch_sub(1, std::memory_order_relaxed);
+      if (j < 0) return;
+      // (deflations come every few tens of microseconds: poll with short
+      // sleeps rather than spin, so that the QR thread keeps its core)
+      while (ready.load(std::memory_order_acquire) > j) {
+        if (failed.load(std::memory_order_relaxed)) return;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      }
+      eigvec(j, lu, v, sw);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 1; w < nt; ++w) th.emplace_back(worker);
   // 2. eigenvalues: single-shift QR on the unreduced window [l, h]
   int64_t ilast = t - 1, since = 0, it = 0;
   const int64_t maxit = 40 * t + 100;
@@ -431,10 +519,19 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
     const double hv = std::abs(H(j, j - 1));
     return hv <= atol || hv <= kUlp * (std::abs(H(j, j)) + std::abs(H(j - 1, j - 1)));
   };
+  int rc = 0;
   while (ilast > 0) {
-    if (++it > maxit) return -2;
+    if (++it > maxit) {
+      rc = -2;
+      failed.store(true, std::memory_order_relaxed);
+      break;
+    }
     if (negligible(ilast)) {
       H(ilast, ilast - 1) = 0.0;
+      // eigenvalue ilast is final: its eigenvector may start
+      alpha[ilast] = H(ilast, ilast);
+      beta[ilast] = 1.0;
+      ready.store(ilast, std::memory_order_release);
       --ilast;
       since = 0;
       eshift = 0.0;
@@ -493,72 +590,14 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
       }
     }
   }
-  for (int64_t j = 0; j < t; ++j) {
-    alpha[j] = H(j, j);
-    beta[j] = 1.0;
+  if (rc == 0 && t > 0) {
+    alpha[0] = H(0, 0);
+    beta[0] = 1.0;
+    ready.store(0, std::memory_order_release);
   }
-  // 3. eigenvectors by inverse iteration on H0, then x = P_0 ... P_{t-3} v
-  auto eigvec = [&](int64_t j, std::vector<cd> &lu, std::vector<cd> &v, std::vector<int8_t> &sw) {
-    const cd lam = alpha[j];
-    // LU of H0 - lam I (upper Hessenberg, column-major copy in lu): eliminate
-    // the subdiagonal with row interchanges between k and k+1
-    for (int64_t q = 0; q < t * t; ++q) lu[q] = H0.a[q];
-    for (int64_t k = 0; k < t; ++k) lu[k * t + k] -= lam;
-    const double tiny = std::max(kSafmin, kUlp * hnorm);
-    for (int64_t k = 0; k + 1 < t; ++k) {
-      cd &dk = lu[k * t + k];
-      cd &sk = lu[k * t + k + 1];
-      sw[k] = std::abs(sk) > std::abs(dk) ? 1 : 0;
-      if (sw[k])
-        for (int64_t jj = k; jj < t; ++jj) std::swap(lu[jj * t + k], lu[jj * t + k + 1]);
-      cd piv = lu[k * t + k];
-      if (std::abs(piv) < tiny) piv = lu[k * t + k] = tiny;
-      const cd mlt = lu[k * t + k + 1] / piv;
-      lu[k * t + k + 1] = mlt;
-      for (int64_t jj = k + 1; jj < t; ++jj) lu[jj * t + k + 1] -= mlt * lu[jj * t + k];
-    }
-    if (std::abs(lu[(t - 1) * t + t - 1]) < tiny) lu[(t - 1) * t + t - 1] = tiny;
-    std::fill(v.begin(), v.end(), cd(1.0));
-    for (int pass = 0; pass < 2; ++pass) {
-      // forward (unit lower, with the interchanges), then backward (upper)
-      for (int64_t k = 0; k + 1 < t; ++k) {
-        if (sw[k]) std::swap(v[k], v[k + 1]);
-        v[k + 1] -= lu[k * t + k + 1] * v[k];
-      }
-      for (int64_t k = t - 1; k >= 0; --k) {
-        cd acc = v[k];
-        for (int64_t jj = k + 1; jj < t; ++jj) acc -= lu[jj * t + k] * v[jj];
-        v[k] = acc / lu[k * t + k];
-      }
-      double nr = 0.0;
-      for (const cd &e : v) nr = std::max(nr, std::abs(e));
-      if (nr > 0.0)
-        for (cd &e : v) e /= nr;
-    }
-    for (int64_t k = t - 3; k >= 0; --k) {
-      if (refl[k].empty()) continue;
-      const std::vector<cd> &u = refl[k];
-      const int64_t L = t - k - 1;
-      cd d = 0.0;
-      for (int64_t i = 0; i < L; ++i) d += std::conj(u[i]) * v[k + 1 + i];
-      d *= rf[k];
-      for (int64_t i = 0; i < L; ++i) v[k + 1 + i] -= d * u[i];
-    }
-    double nr = 0.0;
-    for (const cd &e : v) nr += std::norm(e);
-    nr = std::sqrt(nr);
-    for (int64_t i = 0; i < t; ++i) Y[i * ldy + j] = nr > 0.0 ? v[i] / nr : v[i];
-  };
-  const int nt = std::max(1, std::min<int>(nthreads, static_cast<int>((t + 15) / 16)));
-  std::vector<std::thread> th;
-  for (int w = 0; w < nt; ++w)
-    th.emplace_back([&, w]() {
-      std::vector<cd> lu(t * t), v(t);
-      std::vector<int8_t> sw(t);
-      for (int64_t j = w; j < t; j += nt) eigvec(j, lu, v, sw);
-    });
+  if (rc == 0) worker();
   for (auto &x : th) x.join();
-  return 0;
+  return rc;
 }
 
 }  // namespace
