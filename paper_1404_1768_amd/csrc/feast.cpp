@@ -77,25 +77,28 @@ constexpr int kIB = 64;
 // and X = rows [r0, r1) of the block with columns starting at Xc (leading
 // dimension ldx, batch stride sX): recursive halving, leaves are in-place MFMA
 // products with the inverted kIB x kIB diagonal blocks.
+//   lb: rows of the inverted diagonal blocks (64, or 128 with leaf products on
+//   128-row tiles, which keep the in-place product within one workgroup).
 template <typename T>
 void trsm_lower_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,
                     const T *Linv, int64_t istride, int64_t r0, int64_t r1, T *X, int64_t ldx,
-                    int64_t sX, int64_t ncols, int ta) {
-  if (r1 - r0 <= kIB) {
-    gemm_t<T>(s, ta, r1 - r0, ncols, r1 - r0, zc(1.0), Linv + (r0 / kIB) * kIB * kIB, kIB,
-              istride, X + r0 * ldx, ldx, sX, zc(0.0), X + r0 * ldx, ldx, sX, batch);
+                    int64_t sX, int64_t ncols, int ta, int lb = kIB) {
+  if (r1 - r0 <= lb) {
+    gemm_t<T>(s, ta, r1 - r0, ncols, r1 - r0, zc(1.0), Linv + (r0 / lb) * lb * lb, lb, istride,
+              X + r0 * ldx, ldx, sX, zc(0.0), X + r0 * ldx, ldx, sX, batch, nullptr, 0,
+              lb > 64 ? feast::GEMM_TALL : feast::GEMM_SQUARE);
     return;
   }
-  const int64_t half = ((r1 - r0 + 2 * kIB - 1) / (2 * kIB)) * kIB;
+  const int64_t half = ((r1 - r0 + 2 * lb - 1) / (2 * lb)) * lb;
   const int64_t mid = r0 + half;
-  trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, r0, mid, X, ldx, sX, ncols, ta);
+  trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, r0, mid, X, ldx, sX, ncols, ta, lb);
   if (ta == 0)  // X[mid:r1] -= L[mid:r1, r0:mid] X[r0:mid]
     gemm_t<T>(s, 0, r1 - mid, ncols, mid - r0, zc(-1.0), M + mid * ld + r0, ld, stride,
               X + r0 * ldx, ldx, sX, zc(1.0), X + mid * ldx, ldx, sX, batch);
   else  // lower factor given as (U^*): rows [mid, r1) of U^* are columns of U rows [r0, mid)
     gemm_t<T>(s, 2, r1 - mid, ncols, mid - r0, zc(-1.0), M + r0 * ld + mid, ld, stride,
               X + r0 * ldx, ldx, sX, zc(1.0), X + mid * ldx, ldx, sX, batch);
-  trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, mid, r1, X, ldx, sX, ncols, ta);
+  trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, mid, r1, X, ldx, sX, ncols, ta, lb);
 }
 
 // X <- U^{-1} X for the upper U = M[r0:r1, r0:r1] (ta = 0), or X <- L^{-*} X
@@ -103,22 +106,23 @@ void trsm_lower_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32
 template <typename T>
 void trsm_upper_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch,
                     const T *Inv, int64_t istride, int64_t r0, int64_t r1, T *X, int64_t ldx,
-                    int64_t sX, int64_t ncols, int ta) {
-  if (r1 - r0 <= kIB) {
-    gemm_t<T>(s, ta, r1 - r0, ncols, r1 - r0, zc(1.0), Inv + (r0 / kIB) * kIB * kIB, kIB,
-              istride, X + r0 * ldx, ldx, sX, zc(0.0), X + r0 * ldx, ldx, sX, batch);
+                    int64_t sX, int64_t ncols, int ta, int lb = kIB) {
+  if (r1 - r0 <= lb) {
+    gemm_t<T>(s, ta, r1 - r0, ncols, r1 - r0, zc(1.0), Inv + (r0 / lb) * lb * lb, lb, istride,
+              X + r0 * ldx, ldx, sX, zc(0.0), X + r0 * ldx, ldx, sX, batch, nullptr, 0,
+              lb > 64 ? feast::GEMM_TALL : feast::GEMM_SQUARE);
     return;
   }
-  const int64_t half = ((r1 - r0 + 2 * kIB - 1) / (2 * kIB)) * kIB;
+  const int64_t half = ((r1 - r0 + 2 * lb - 1) / (2 * lb)) * lb;
   const int64_t mid = r0 + half;
-  trsm_upper_rec<T>(s, M, ld, stride, batch, Inv, istride, mid, r1, X, ldx, sX, ncols, ta);
+  trsm_upper_rec<T>(s, M, ld, stride, batch, Inv, istride, mid, r1, X, ldx, sX, ncols, ta, lb);
   if (ta == 0)  // X[r0:mid] -= U[r0:mid, mid:r1] X[mid:r1]
     gemm_t<T>(s, 0, mid - r0, ncols, r1 - mid, zc(-1.0), M + r0 * ld + mid, ld, stride,
               X + mid * ldx, ldx, sX, zc(1.0), X + r0 * ldx, ldx, sX, batch);
   else  // rows [r0, mid) of L^* are columns of L rows [mid, r1)
     gemm_t<T>(s, 2, mid - r0, ncols, r1 - mid, zc(-1.0), M + mid * ld + r0, ld, stride,
               X + mid * ldx, ldx, sX, zc(1.0), X + r0 * ldx, ldx, sX, batch);
-  trsm_upper_rec<T>(s, M, ld, stride, batch, Inv, istride, r0, mid, X, ldx, sX, ncols, ta);
+  trsm_upper_rec<T>(s, M, ld, stride, batch, Inv, istride, r0, mid, X, ldx, sX, ncols, ta, lb);
 }
 
 // Streams and events of the look-ahead factorisation.
@@ -188,14 +192,22 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
 template <typename T>
 void trsolve(hipStream_t s, const T *F, int64_t ld, int64_t fstride, int32_t batch, int64_t n,
              const T *Linv, const T *Uinv, int64_t istride, T *Y, int64_t m, int64_t ldy,
-             int64_t sY, int trans) {
+             int64_t sY, int trans, int lb = kIB) {
   if (trans == 0) {
-    trsm_lower_rec<T>(s, F, ld, fstride, batch, Linv, istride, 0, n, Y, ldy, sY, m, 0);
-    trsm_upper_rec<T>(s, F, ld, fstride, batch, Uinv, istride, 0, n, Y, ldy, sY, m, 0);
+    trsm_lower_rec<T>(s, F, ld, fstride, batch, Linv, istride, 0, n, Y, ldy, sY, m, 0, lb);
+    trsm_upper_rec<T>(s, F, ld, fstride, batch, Uinv, istride, 0, n, Y, ldy, sY, m, 0, lb);
   } else {
-    trsm_lower_rec<T>(s, F, ld, fstride, batch, Uinv, istride, 0, n, Y, ldy, sY, m, 2);
-    trsm_upper_rec<T>(s, F, ld, fstride, batch, Linv, istride, 0, n, Y, ldy, sY, m, 2);
+    trsm_lower_rec<T>(s, F, ld, fstride, batch, Uinv, istride, 0, n, Y, ldy, sY, m, 2, lb);
+    trsm_upper_rec<T>(s, F, ld, fstride, batch, Linv, istride, 0, n, Y, ldy, sY, m, 2, lb);
   }
+}
+
+// The plan's solves: leaves on its inverted 128 x 128 diagonal blocks.
+template <typename T>
+void plan_trsolve(feast_plan *p, hipStream_t s, T *Y, int64_t m, int64_t ldy, int64_t sY,
+                  int trans) {
+  trsolve<T>(s, p->F.as<T>(), p->n, p->fstride(), p->N, p->n, p->Linv2.as<T>(), p->Uinv2.as<T>(),
+             p->istride2(), Y, m, ldy, sY, trans, 128);
 }
 
 // ---------------------------------------------------------------------------
@@ -214,6 +226,8 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
   p->info.alloc(sizeof(int32_t) * N);
   p->Linv.alloc(esz * N * p->istride());
   p->Uinv.alloc(esz * N * p->istride());
+  p->Linv2.alloc(esz * N * p->istride2());
+  p->Uinv2.alloc(esz * N * p->istride2());
   LuProf prof;
   if (p->o.profile) {
     const size_t need = 4 * static_cast<size_t>((n + p->nb - 1) / p->nb);
@@ -232,11 +246,19 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     lu_batched<c64>(lst, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<c64>(), p->Uinv.as<c64>(), p->istride(),
                     &prof);
+    for (const bool lower : {true, false})
+      feast::inverse_pairs<c64>(sl, p->F.as<c64>(), n, n * n, N, n,
+                                (lower ? p->Linv : p->Uinv).as<c64>(), p->istride(),
+                                (lower ? p->Linv2 : p->Uinv2).as<c64>(), p->istride2(), lower);
   } else {
     feast::shift_assemble_z(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<z64>(), n, n * n);
     lu_batched<z64>(lst, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<z64>(), p->Uinv.as<z64>(), p->istride(),
                     &prof);
+    for (const bool lower : {true, false})
+      feast::inverse_pairs<z64>(sl, p->F.as<z64>(), n, n * n, N, n,
+                                (lower ? p->Linv : p->Uinv).as<z64>(), p->istride(),
+                                (lower ? p->Linv2 : p->Uinv2).as<z64>(), p->istride2(), lower);
   }
   feast::perm_from_ipiv(s, p->piv.as<int32_t>(), p->perm.as<int32_t>(), n, N);
   double *nrm = p->nrm.as<double>();
@@ -284,8 +306,7 @@ void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr) {
   const int64_t n = p->n, m = p->m, ldY = p->ldY();
   z64 *Y = p->Y.as<z64>();
   feast::gather_rows<z64>(p->s, R, ldr, 0, p->perm.as<int32_t>(), n, m, p->N, Y, ldY, m);
-  trsolve<z64>(p->s, p->F.as<z64>(), n, p->fstride(), p->N, n, p->Linv.as<z64>(),
-               p->Uinv.as<z64>(), p->istride(), Y, m, ldY, m, 0);
+  plan_trsolve<z64>(p, p->s, Y, m, ldY, m, 0);
 }
 
 // Mixed form: complex64 LU solves; FP64 residual r_j = R - (z_j B - A) Y_j of
@@ -310,8 +331,7 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
   // complex64 solve of P_j R
   feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, m);
   feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0);
-  trsolve<c64>(s, F, n, p->fstride(), N, n, p->Linv.as<c64>(), p->Uinv.as<c64>(),
-               p->istride(), Yc, m, ldY, m, 0);
+  plan_trsolve<c64>(p, s, Yc, m, ldY, m, 0);
   feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
   p->last_sweeps = 0;
   p->last_be = -1.0;
@@ -354,8 +374,7 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
     }
     feast::gather_rows<z64>(s, T1, ldY, m, perm, n, m, N, T2, ldY, m);
     feast::z_to_c(s, T2, ldY, 0, n, ldY, 1, Yc, ldY, 0);
-    trsolve<c64>(s, F, n, p->fstride(), N, n, p->Linv.as<c64>(), p->Uinv.as<c64>(),
-                 p->istride(), Yc, m, ldY, m, 0);
+    plan_trsolve<c64>(p, s, Yc, m, ldY, m, 0);
     feast::add_c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
     p->last_sweeps = sweep + 1;
   }
@@ -670,7 +689,7 @@ int feast_plan_destroy(feast_plan *p) {
     }
   if (p->ev_cols) (void)hipEventDestroy(p->ev_cols);
   if (p->ev_panel) (void)hipEventDestroy(p->ev_panel);
-  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->R,
+  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->R,
                     &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->dinv, &p->splitws, &p->part, &p->nrm,
                     &p->flag, &p->small})
     b->release();
@@ -983,8 +1002,7 @@ int feast_left_eigvecs(feast_plan *p, const feast_z *dA, int64_t lda, const feas
       // W = sum_j conj(w_j) (z_j B - A)^{-*} G with the cached factors:
       // (z_j B - A)^* = U^* L^* P, so solve with U^*, then L^*, then undo P
       feast::bcast_cols(s, G, sc, n, sc, N, Y, ldw);
-      trsolve<z64>(s, p->F.as<z64>(), n, p->fstride(), N, n, p->Linv.as<z64>(), p->Uinv.as<z64>(),
-                   p->istride(), Y, sc, ldw, sc, 2);
+      plan_trsolve<z64>(p, s, Y, sc, ldw, sc, 2);
       feast::scatter_rows<z64>(s, Y, ldw, sc, p->perm.as<int32_t>(), n, sc, N, Adj, ldw, sc);
       feast::weighted_sum(s, Adj, ldw, sc, p->dwc.as<z64>(), N, n, sc, W, sc);
     }

@@ -546,6 +546,87 @@ __global__ __launch_bounds__(64) void k_diag_inv(const T *__restrict__ Mall, int
     if (tid < nb) o[i * nb + tid] = (i < rb && tid < rb) ? sX[i][tid] : czero<T>();
 }
 
+// Inverse of a 128-row diagonal block of a triangular factor from the inverses
+// I1, I2 of its two 64-row halves (zero padded past the order) and the
+// off-diagonal 64 x 64 block C of the factor:
+//   lower (unit):  [L11 0; C L22]^{-1} = [I1 0; -I2 C I1  I2]
+//   upper:         [U11 C; 0 U22]^{-1} = [I1  -I1 C I2; 0 I2]
+// One workgroup per (block, matrix); the two 64 x 64 x 64 products run from
+// LDS, 16 outputs per thread.
+template <typename T>
+__global__ __launch_bounds__(256) void k_inv_pair(const T *__restrict__ F, int64_t ld,
+                                                  int64_t fstride, int64_t n,
+                                                  const T *__restrict__ inv64, int64_t istride,
+                                                  T *__restrict__ inv128, int64_t istride2,
+                                                  bool lower) {
+  using Tr = cplx_traits<T>;
+  __shared__ T sA[64][65];
+  __shared__ T sB[64][65];
+  const int64_t B = blockIdx.x, b = blockIdx.y;
+  const int64_t r0 = 128 * B;
+  const int h2 = static_cast<int>((n - r0 - 64 < 64) ? n - r0 - 64 : 64);  // rows of the second half
+  const T *M = F + b * fstride;
+  const T *I1 = inv64 + b * istride + (2 * B) * 4096;
+  const T *I2 = I1 + 4096;
+  T *out = inv128 + b * istride2 + B * 16384;
+  const int tid = threadIdx.x;
+  // the two diagonal halves (the second one absent when h2 <= 0)
+  for (int e = tid; e < 128 * 128; e += 256) {
+    const int i = e >> 7, j = e & 127;
+    T v = czero<T>();
+    if (i < 64 && j < 64) v = I1[i * 64 + j];
+    else if (i >= 64 && j >= 64 && h2 > 0) v = I2[(i - 64) * 64 + (j - 64)];
+    out[e] = v;
+  }
+  if (h2 <= 0) return;
+  // first product: lower T = C I1 (C = rows [r0+64, r0+64+h2) x cols [r0, r0+64)),
+  //                upper T = I1 C (C = rows [r0, r0+64) x cols [r0+64, r0+64+h2))
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (lower) {
+      sA[i][j] = (i < h2) ? M[(r0 + 64 + i) * ld + r0 + j] : czero<T>();
+      sB[i][j] = I1[i * 64 + j];
+    } else {
+      sA[i][j] = I1[i * 64 + j];
+      sB[i][j] = (j < h2) ? M[(r0 + i) * ld + r0 + 64 + j] : czero<T>();
+    }
+  }
+  __syncthreads();
+  T acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, i = e >> 6, j = e & 63;
+    T x = czero<T>();
+    for (int l = 0; l < 64; ++l) x = Tr::fms(x, sA[i][l], sB[l][j]);  // accumulates -(A B)
+    acc[q] = x;
+  }
+  __syncthreads();
+  // second product with the negated first one: lower X = I2 (-C I1), upper X = (-I1 C) I2
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, i = e >> 6, j = e & 63;
+    if (lower) {
+      sB[i][j] = acc[q];
+      sA[i][j] = I2[i * 64 + j];
+    } else {
+      sA[i][j] = acc[q];
+      sB[i][j] = I2[i * 64 + j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, i = e >> 6, j = e & 63;
+    T x = czero<T>();
+    for (int l = 0; l < 64; ++l) x = Tr::fms(x, sA[i][l], sB[l][j]);
+    // x = -(sA sB): negate back to the product of the (already negated) factors
+    x.x = -x.x;
+    x.y = -x.y;
+    if (lower) out[(64 + i) * 128 + j] = x;
+    else out[i * 128 + 64 + j] = x;
+  }
+}
+
 // n: order (pivot vectors of the batch are n_stride apart; grouped batches read
 // each matrix's order from grp)
 __global__ __launch_bounds__(256) void k_perm(const int32_t *__restrict__ ipiv_all,
@@ -693,6 +774,19 @@ template void diag_block_inverse<z64>(hipStream_t, const z64 *, int64_t, int64_t
 template void diag_block_inverse<c64>(hipStream_t, const c64 *, int64_t, int64_t, int32_t,
                                       int64_t, int, int64_t, int64_t, bool, c64 *, int64_t,
                                       const GrpMat *, int);
+
+template <typename T>
+void inverse_pairs(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+                   const T *inv64, int64_t istride, T *inv128, int64_t istride2, bool lower) {
+  const int64_t nb2 = (n + 127) / 128;
+  if (nb2 <= 0 || batch <= 0) return;
+  hipLaunchKernelGGL((k_inv_pair<T>), dim3(static_cast<unsigned>(nb2), batch), dim3(256), 0, s, M,
+                     ld, stride, n, inv64, istride, inv128, istride2, lower);
+}
+template void inverse_pairs<z64>(hipStream_t, const z64 *, int64_t, int64_t, int32_t, int64_t,
+                                 const z64 *, int64_t, z64 *, int64_t, bool);
+template void inverse_pairs<c64>(hipStream_t, const c64 *, int64_t, int64_t, int32_t, int64_t,
+                                 const c64 *, int64_t, c64 *, int64_t, bool);
 
 void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n, int32_t batch,
                     const GrpMat *grp, int nodes) {

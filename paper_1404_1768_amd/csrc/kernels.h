@@ -114,6 +114,13 @@ void diag_block_inverse(hipStream_t s, const T *M, int64_t ld, int64_t stride, i
                         int64_t n, int nb, int64_t blk0, int64_t blk1, bool lower, T *out,
                         int64_t out_stride, const GrpMat *grp = nullptr, int nodes = 1);
 
+// Inverted 128-row diagonal blocks (row-major 128 x 128, istride2 apart per
+// matrix) built from the inverted 64-row blocks of diag_block_inverse (nb = 64,
+// istride apart) and the factor's off-diagonal 64 x 64 blocks.
+template <typename T>
+void inverse_pairs(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
+                   const T *inv64, int64_t istride, T *inv128, int64_t istride2, bool lower);
+
 // perm[b][i] = original row at position i of P_b (from LAPACK-order ipiv).
 void perm_from_ipiv(hipStream_t s, const int32_t *ipiv, int32_t *perm, int64_t n, int32_t batch,
                     const GrpMat *grp = nullptr, int nodes = 1);

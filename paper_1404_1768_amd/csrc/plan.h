@@ -86,6 +86,7 @@ struct feast_plan {
   const void *fA = nullptr, *fB = nullptr;
   int64_t flda = 0, fldb = 0;
   DevBuf F, piv, perm, info, Linv, Uinv;
+  DevBuf Linv2, Uinv2;  // inverted 128 x 128 diagonal blocks (the solves' leaves)
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
   DevBuf R, Y, T1, T2, Yc, W, G, dinv, splitws, part, nrm, flag, small;
@@ -114,6 +115,7 @@ struct feast_plan {
   int64_t ldY() const { return static_cast<int64_t>(N) * m; }
   int64_t fstride() const { return n * n; }
   int64_t istride() const { return nblk * 64 * 64; }  // inverted 64 x 64 diagonal blocks
+  int64_t istride2() const { return ((n + 127) / 128) * 128 * 128; }  // 128 x 128 ones
 };
 
 

@@ -129,6 +129,25 @@ def test_project_matches_oracle():
     assert np.max(np.abs(np.tril(Bt, -1))) < 1e-12 * np.abs(Bt).max()
 
 
+@pytest.mark.parametrize("m", [100, 230])
+def test_project_several_cholesky_blocks(m):
+    # subspace sizes that span several 32-column blocks of the small Cholesky
+    # (the last one ragged): orthonormal U_1 and A~, B~ as the oracle's
+    p = pg.make_pencil(600, m=m, inside=m // 2, inside_radius=0.9, outside_r=(1.3, 10.0),
+                       center=0.0, radius=1.0, nodes=16, c=0.05, seed=91 + m, name="proj-m%d" % m)
+    A, B, U = to_dev(p.A, p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes) as plan:
+        U1, AU1, BU1, At, Bt = plan.project(A, B, U)
+    U1 = U1.cpu().numpy()
+    U1o, _ = o.orth(p.V)
+    U2o, _ = o.orth(p.B @ U1o)
+    Ato, Bto = o.project(p.A, p.B, U1o, U2o)
+    assert np.linalg.norm(U1.conj().T @ U1 - np.eye(p.m)) < 1e-13
+    assert np.max(np.abs(U1 - U1o)) < 1e-11
+    assert np.max(np.abs(At - Ato)) < 1e-10 * np.abs(Ato).max()
+    assert np.max(np.abs(Bt - Bto)) < 1e-10 * np.abs(Bto).max()
+
+
 def test_project_tolerates_ill_conditioned_block():
     # a filtered block with t > s has singular values down to |f| of the
     # (t+1)-th eigenvalue; shifted Cholesky QR3 must still orthonormalise it
