@@ -42,9 +42,9 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # hold for the kernel source they were taken on (its sha256), else `traffic`
 # is reported as null.
 TRAFFIC = {"source": "paper_1404_1768_amd/csrc/k_gemm.hip",
-           "sha256": "abc95c0fc2766a0eaa0ed27174c1ce9d111b9113d38a142ab2920625f57135f0",
-           "mixed": {"fetch": 1756998155, "write": 1310955785},
-           "fp64": {"fetch": 4260283815, "write": 2621911570}}
+           "sha256": "ed670fc6b72e5e6e8bb23e1fc6b720a648f9f67db2d0722a6b6dd80d9f1bd940",
+           "mixed": {"fetch": 1754467822, "write": 1310958338},
+           "fp64": {"fetch": 4147150802, "write": 2621916675}}
 
 
 def kernel_traffic(form):
