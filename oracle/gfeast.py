@@ -19,10 +19,15 @@ notes of the repository):
   circle integral of eq. (8-4); Gauss-Legendre with ``theta_j = (1 + t_j) pi``
   and ``w_j = omega_j (z_j - gamma)/2`` is eq. (8-4) itself.
 * Sign: shifted systems are ``(z_j B - A) Y_j = B U_1`` as in eq. (4-4).
-* Search (Algorithm 4, GFEAST line 1) with a fixed subspace size ``t = m`` and
-  a caller-supplied start block ``V``: ``U_1`` is the orthonormal factor of the
-  filtered block ``Q_N V`` (the remark after Algorithm 4: its ``U_1`` is a
-  projection onto the eigenspace, i.e. the first filter application).
+* GFEAST line 1 with a fixed subspace size ``t = m`` and a caller-supplied
+  start block ``V``: ``U_1`` is the orthonormal factor of the filtered block
+  ``Q_N V`` (the remark after Algorithm 4: its ``U_1`` is a projection onto the
+  eigenspace, i.e. the first filter application).  ``search`` is Algorithm 4
+  itself; its random columns come from a caller-supplied pool, its trace
+  estimate uses the real part of ``trace(Y_0^* U)`` (the expectation is real),
+  and the numerical rank of the column-pivoted ``R`` counts the diagonal
+  entries with ``|R_ii| >= tau |R_11|`` (the paper names rank-revealing QR but
+  no threshold).
 * Line 17 takes the QR of ``B U_1`` with the new ``U_1`` (same span as ``B U``).
 * Empty selection: ``e(k) = +inf`` and the rules of lines 13-14 are skipped.
 * ``lambda`` inside means ``|lambda - gamma| < rho`` (strict); infinite
@@ -266,8 +271,19 @@ def gfeast(A: np.ndarray, B: np.ndarray, V: np.ndarray, center: complex, radius:
         solver = ShiftedSolver(A, B, z)
     # line 1 (Search with fixed t): U = Q_N V, U_1 = orth(U)
     U = apply_filter(solver, w, V)
-    filters = 1
     U1, _ = orth(U)
+    return gfeast_from(A, B, U1, center, radius, N, rule, eps, eta, max_iter, solver, filters=1)
+
+
+def gfeast_from(A: np.ndarray, B: np.ndarray, U1: np.ndarray, center: complex, radius: float,
+                N: int, rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
+                max_iter: int = 20, solver: Optional[ShiftedSolver] = None,
+                filters: int = 0) -> Result:
+    """Algorithm 5 lines 2-18 from an orthonormal ``U_1`` that is already a
+    filtered basis (Search's output, or line 1's)."""
+    z, w = contour_nodes(center, radius, N, rule)
+    if solver is None:
+        solver = ShiftedSolver(A, B, z)
     # line 2: B U_1 = U_2 R_2
     BU1 = B @ U1
     U2, _ = orth(BU1)
@@ -307,6 +323,95 @@ def gfeast(A: np.ndarray, B: np.ndarray, V: np.ndarray, center: complex, radius:
         BU1 = B @ U1
         U2, _ = orth(BU1)
     raise AssertionError("unreachable: line 15 stops at max_iter")
+
+
+# ---------------------------------------------------------------------------
+# Search (Algorithm 4, Section 4.1): an upper bound t of s and U_1
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SearchResult:
+    U1: np.ndarray      # orthonormal basis of the filtered block (n x t)
+    t: int              # numerical rank at the last round (upper bound of s)
+    s0: int             # trace estimate of s (line 2)
+    rounds: int         # rank tests performed (line 9)
+    used: int           # pool columns consumed
+    filters: int        # filter applications
+
+
+def numerical_rank(R: np.ndarray, tau: float) -> int:
+    """Number of diagonal entries of a column-pivoted triangular factor with
+    ``|R_ii| >= tau |R_11|`` (pivoting makes them non-increasing)."""
+    d = np.abs(np.diag(R))
+    if d.size == 0 or not d[0] > 0:
+        return 0
+    return int(np.count_nonzero(d >= tau * d[0]))
+
+
+def trace_estimate(Y0: np.ndarray, U: np.ndarray) -> int:
+    """``s_0 = ceil(trace(Y_0^* U) / p)`` (Algorithm 4 line 2, eq. (trace)):
+    for ``U = Q Y_0`` with Gaussian ``Y_0`` the expectation of the trace is
+    ``p trace(Q) = p s``."""
+    p = Y0.shape[1]
+    return int(math.ceil(float(np.real(np.trace(Y0.conj().T @ U))) / p))
+
+
+def search(solver: ShiftedSolver, w: np.ndarray, Y_pool: np.ndarray, p: int,
+           alpha: float = 1.5, tau: float = 1e-3, t_max: Optional[int] = None) -> SearchResult:
+    """Algorithm 4: filter ``p`` Gaussian columns, estimate ``s_0`` from the
+    trace, widen the block to ``s_dagger`` columns, and repeat the
+    rank-revealing QR (column-pivoted Householder QR) until the block is
+    numerically rank deficient; then ``t`` is its rank and ``U_1`` the first
+    ``t`` columns of ``Q``.  Columns are taken from ``Y_pool`` in order.
+    ``t_max`` (default ``n``) caps ``s_dagger``; a block that is still of full
+    rank at the cap raises ``ValueError``."""
+    n = Y_pool.shape[0]
+    cap = n if t_max is None else min(t_max, n)
+    if not 1 <= p <= cap:
+        raise ValueError("p out of range")
+    # line 1
+    Y0 = Y_pool[:, :p]
+    used = p
+    U = apply_filter(solver, w, Y0)
+    filters = 1
+    # line 2
+    s0 = trace_estimate(Y0, U)
+    sd = min(max(p, s0), cap)
+    rounds = 0
+    while True:
+        # lines 3-8
+        if sd > p:
+            if used + (sd - p) > Y_pool.shape[1]:
+                raise ValueError("random column pool exhausted")
+            Yt = Y_pool[:, used:used + sd - p]
+            used += sd - p
+            U = np.hstack([U, apply_filter(solver, w, Yt)])
+            filters += 1
+        else:
+            sd = p
+        # lines 9-10
+        Q, R, _ = sla.qr(U, mode="economic", pivoting=True)
+        rounds += 1
+        t = numerical_rank(R, tau)
+        if t < sd:
+            return SearchResult(Q[:, :t], t, s0, rounds, used, filters)
+        nxt = min(int(math.ceil(alpha * t)), cap)
+        if nxt <= t:
+            raise ValueError("block of full rank at the column cap")
+        p, U, sd = t, Q[:, :t], nxt
+
+
+def gfeast_search(A: np.ndarray, B: np.ndarray, Y_pool: np.ndarray, center: complex,
+                  radius: float, N: int, p: int, alpha: float = 1.5, tau: float = 1e-3,
+                  rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
+                  max_iter: int = 20, t_max: Optional[int] = None):
+    """Algorithm 5 with line 1 = Algorithm 4: returns (Result, SearchResult)."""
+    z, w = contour_nodes(center, radius, N, rule)
+    solver = ShiftedSolver(A, B, z)
+    sr = search(solver, w, Y_pool, p, alpha, tau, t_max)
+    res = gfeast_from(A, B, sr.U1, center, radius, N, rule, eps, eta, max_iter, solver,
+                      filters=sr.filters)
+    return res, sr
 
 
 # ---------------------------------------------------------------------------
