@@ -170,6 +170,58 @@ int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z 
                 int32_t *flag, feast_info *info);
 
 /* ---------------------------------------------------------------------------
+ * Search (Algorithm 4, Section 4.1): an upper bound t of the number s of
+ * eigenvalues inside the contour, without knowing s
+ * ------------------------------------------------------------------------- */
+
+typedef struct feast_search_info {
+  int64_t t;        /* numerical rank of the last block: the upper bound of s */
+  int64_t s0;       /* trace estimate ceil(Re trace(Y_0^* U) / p) (line 2) */
+  int64_t used;     /* columns of the random pool consumed */
+  int32_t rounds;   /* rank tests performed (line 9) */
+  int32_t filters;  /* filter applications */
+  double ms;        /* wall time of the call */
+} feast_search_info;
+
+/* Algorithm 4 on the plan's cached factors (factored first if needed):
+ *   line 1: U = Q_N Y_0 for the first p columns Y_0 of the pool dY;
+ *   line 2: s_0 = ceil(Re trace(Y_0^* U) / p), s_dagger = min(max(p, s_0), m);
+ *   lines 3-8: U gets s_dagger - p more filtered columns from the pool, in order;
+ *   line 9: rank-revealing step; line 10: t = numerical rank; if t < s_dagger
+ *   stop, else U = U_1, p = t, s_dagger = min(ceil(alpha t), m) and repeat.
+ * dY: device, n x ycols (leading dimension ldy >= ycols), entries N(0,1) drawn
+ * by the caller (the paper's Y is real: pass zero imaginary parts); columns are
+ * consumed left to right.  The numerical rank counts |R_jj| >= tau |R_00| of
+ * the column-pivoted triangular factor (the paper names rank-revealing QR but
+ * no threshold; tau = 1e-3 separates the filter's inside values near 1 from
+ * outside values 1/(1 + mu^N)).  The rank-revealing step is the diagonally
+ * pivoted Cholesky of the Gram matrix U^* U, which has the pivots and |R_jj|
+ * of the column-pivoted QR of U; decisions at tau >> sqrt(eps) are unaffected
+ * by squaring the condition number.
+ * Output: dU1 (device, n x t, leading dimension ldu >= m) an orthonormal basis
+ * of the t leading pivot columns (the first t columns of the QR's Q), and
+ * *info.  The plan's m caps s_dagger: FEAST_EINVAL (with a message) when the
+ * block is still of full rank at m columns, or when the pool runs out.
+ * Mixed plans do not refine Search's filters.  Synchronises the stream. */
+int feast_search(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
+                 int64_t ldb, const feast_z *dY, int64_t ldy, int64_t ycols, int32_t p,
+                 double alpha, double tau, feast_z *dU1, int64_t ldu, feast_search_info *info);
+
+/* Change the plan's subspace size to m (1 <= m <= n), keeping the cached
+ * factors (they do not depend on m); workspaces grow as needed.  Used to run
+ * Algorithm 5 with Search's t. */
+int feast_plan_set_m(feast_plan *plan, int64_t m);
+
+/* Algorithm 5 lines 2-18 from Search's basis: dU1 (device, n x m, leading
+ * dimension ldu >= m, orthonormal, already filtered) is U_1 of line 2; the
+ * outputs are those of feast_solve (info->filters counts this call's filters
+ * only). */
+int feast_solve_from(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
+                     int64_t ldb, const feast_z *dU1, int64_t ldu, feast_z *hLambda,
+                     feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, double *err,
+                     int32_t *flag, feast_info *info);
+
+/* ---------------------------------------------------------------------------
  * Adjoint form (derivatives of the eigenvalues found by feast_solve)
  * ------------------------------------------------------------------------- */
 

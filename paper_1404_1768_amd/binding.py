@@ -39,6 +39,7 @@ EXPORTED = [
     "feast_zgemm_batched", "feast_version", "feast_left_eigvecs", "feast_eig_grad",
     "feast_batch_create", "feast_batch_destroy", "feast_batch_invalidate",
     "feast_batch_last_error", "feast_batch_filter", "feast_batch_solve",
+    "feast_search", "feast_plan_set_m", "feast_solve_from",
 ]
 
 
@@ -67,6 +68,11 @@ class Info(C.Structure):
                 ("t_ritz_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("lu_gemm_launches", C.c_int32), ("lu_gemm_ms", C.c_double),
                 ("lu_gemm_flops", C.c_double)]
+
+
+class SearchInfo(C.Structure):
+    _fields_ = [("t", C.c_int64), ("s0", C.c_int64), ("used", C.c_int64),
+                ("rounds", C.c_int32), ("filters", C.c_int32), ("ms", C.c_double)]
 
 
 class BatchInfo(C.Structure):
@@ -107,6 +113,10 @@ def load(path: str = LIB_PATH):
     lib.feast_project.argtypes = [P, P, i64, P, i64, P, i64, P, i64, P, i64, pz, pz]
     lib.feast_solve.argtypes = [P, P, i64, P, i64, P, i64, pz, P, i64, C.POINTER(dbl),
                                 C.POINTER(i32), C.POINTER(dbl), C.POINTER(i32), C.POINTER(Info)]
+    lib.feast_solve_from.argtypes = list(lib.feast_solve.argtypes)
+    lib.feast_search.argtypes = [P, P, i64, P, i64, P, i64, i64, i32, dbl, dbl, P, i64,
+                                 C.POINTER(SearchInfo)]
+    lib.feast_plan_set_m.argtypes = [P, i64]
     lib.feast_last_error.argtypes = [P]
     lib.feast_last_error.restype = C.c_char_p
     lib.feast_reduced_eig.argtypes = [i64, pz, i64, pz, i64, pz, pz, pz, i64]
@@ -325,6 +335,13 @@ class Plan:
         return U, AU1, BU1, At, Bt
 
     def solve(self, A, B, V, allow=(FEAST_REFINE_STAGNATED,)) -> SolveResult:
+        return self._solve(self.lib.feast_solve, "feast_solve", A, B, V, allow)
+
+    def solve_from(self, A, B, U1, allow=(FEAST_REFINE_STAGNATED,)) -> SolveResult:
+        """Algorithm 5 lines 2-18 from Search's orthonormal basis U1 (n x m)."""
+        return self._solve(self.lib.feast_solve_from, "feast_solve_from", A, B, U1, allow)
+
+    def _solve(self, fn, what, A, B, V, allow) -> SolveResult:
         import torch
         n, m = self.n, self.m
         pa, lda = _dev(A, n, n, "A")
@@ -337,11 +354,10 @@ class Plan:
         err = C.c_double()
         flag = C.c_int32()
         info = Info()
-        rc = self.lib.feast_solve(self._h, pa, lda, pb, ldb, pv, ldv, _zptr(lam),
-                                  C.c_void_p(X.data_ptr()), m,
-                                  res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(s),
-                                  C.byref(err), C.byref(flag), C.byref(info))
-        self._check(rc, "feast_solve", ok=(FEAST_OK,) + tuple(allow))
+        rc = fn(self._h, pa, lda, pb, ldb, pv, ldv, _zptr(lam), C.c_void_p(X.data_ptr()), m,
+                res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(s), C.byref(err),
+                C.byref(flag), C.byref(info))
+        self._check(rc, what, ok=(FEAST_OK,) + tuple(allow))
         k = s.value
         it = info.iters
         return SolveResult(
@@ -354,6 +370,31 @@ class Plan:
             status=rc, lu_gemm={"launches": info.lu_gemm_launches, "ms": info.lu_gemm_ms,
                                 "flops": info.lu_gemm_flops})
 
+    # -- Search (Algorithm 4) ----------------------------------------------
+    def search(self, A, B, Ypool, p: int, alpha: float = 1.5, tau: float = 1e-3):
+        """Algorithm 4 with the random columns of Ypool (n x q, N(0,1) entries,
+        complex dtype): returns (U1 of shape n x t, info dict with t, s0, used,
+        rounds, filters, ms)."""
+        import torch
+        n, m = self.n, self.m
+        pa, lda = _dev(A, n, n, "A")
+        pb, ldb = _dev(B, n, n, "B")
+        q = int(Ypool.shape[1])
+        py, ldy = _dev(Ypool, n, q, "Ypool")
+        U1 = torch.empty((n, m), dtype=torch.complex128, device=Ypool.device)
+        info = SearchInfo()
+        rc = self.lib.feast_search(self._h, pa, lda, pb, ldb, py, ldy, q, int(p), float(alpha),
+                                   float(tau), C.c_void_p(U1.data_ptr()), m, C.byref(info))
+        self._check(rc, "feast_search")
+        t = int(info.t)
+        return U1[:, :t], {"t": t, "s0": int(info.s0), "used": int(info.used),
+                           "rounds": int(info.rounds), "filters": int(info.filters),
+                           "ms": float(info.ms)}
+
+    def set_m(self, m: int):
+        """New subspace size, keeping the cached factors."""
+        self._check(self.lib.feast_plan_set_m(self._h, int(m)), "feast_plan_set_m")
+        self.m = int(m)
 
     # -- adjoint form ------------------------------------------------------
     def left_eigvecs(self, A, B, X, sweeps: int = 3):

@@ -302,11 +302,13 @@ int ensure_factored(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int6
 }
 
 // FP64 form: Y_j = (z_j B - A)^{-1} R for all nodes (Y: n x N m, node j at columns j m).
-void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr) {
+// (cols: right-hand sides actually used, at most m; node j's block keeps its
+// place at column j m of Y)
+void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr, int64_t cols) {
   const int64_t n = p->n, m = p->m, ldY = p->ldY();
   z64 *Y = p->Y.as<z64>();
-  feast::gather_rows<z64>(p->s, R, ldr, 0, p->perm.as<int32_t>(), n, m, p->N, Y, ldY, m);
-  plan_trsolve<z64>(p, p->s, Y, m, ldY, m, 0);
+  feast::gather_rows<z64>(p->s, R, ldr, 0, p->perm.as<int32_t>(), n, cols, p->N, Y, ldY, m);
+  plan_trsolve<z64>(p, p->s, Y, cols, ldY, m, 0);
 }
 
 // Mixed form: complex64 LU solves; FP64 residual r_j = R - (z_j B - A) Y_j of
@@ -318,8 +320,8 @@ void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr) {
 //   target <= 0: exactly `sweeps` corrections with no final residual (the caller
 //                judges the accuracy, as Algorithm 5 does through eq. 5-1).
 void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
-                       const z64 *R, int64_t ldr, double target, int sweeps) {
-  const int64_t n = p->n, m = p->m, ldY = p->ldY();
+                       const z64 *R, int64_t ldr, double target, int sweeps, int64_t cols) {
+  const int64_t n = p->n, m = cols, ldY = p->ldY(), sY = p->m;
   const int N = p->N;
   hipStream_t s = p->s;
   z64 *Y = p->Y.as<z64>();
@@ -329,9 +331,9 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
   const int32_t *perm = p->perm.as<int32_t>();
   double *part = p->part.as<double>(), *nrm = p->nrm.as<double>();
   // complex64 solve of P_j R
-  feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, m);
+  feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, sY);
   feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0);
-  plan_trsolve<c64>(p, s, Yc, m, ldY, m, 0);
+  plan_trsolve<c64>(p, s, Yc, m, ldY, sY, 0);
   feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
   p->last_sweeps = 0;
   p->last_be = -1.0;
@@ -345,16 +347,16 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
   for (int sweep = 0; sweep <= max_corr; ++sweep) {
     if (!verify && sweep == max_corr) break;
     if (lda == ldb) {  // r_j = R - (z_j B - A) Y_j, shifted matrices formed tile by tile
-      feast::zgemm_shift_residual(s, n, m, n, A, B, lda, p->dz.as<z64>(), Y, ldY, m, R, ldr, 0, T1,
-                                  ldY, m, N);
+      feast::zgemm_shift_residual(s, n, m, n, A, B, lda, p->dz.as<z64>(), Y, ldY, sY, R, ldr, 0, T1,
+                                  ldY, sY, N);
     } else {
       gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), A, lda, 0, Y, ldY, 0, zc(0.0), T1, ldY, 0, 1);
       gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), B, ldb, 0, Y, ldY, 0, zc(0.0), T2, ldY, 0, 1);
-      feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, m);
+      feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, sY);
     }
     if (verify) {
-      feast::fro2_batched(s, T1, ldY, m, n, m, N, part, nrm);
-      feast::fro2_batched(s, Y, ldY, m, n, m, N, part, nrm + N);
+      feast::fro2_batched(s, T1, ldY, sY, n, m, N, part, nrm);
+      feast::fro2_batched(s, Y, ldY, sY, n, m, N, part, nrm + N);
       HIPCHK(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * (2 * N + 1), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       const double nR = std::sqrt(hn[2 * N]);
@@ -372,9 +374,11 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
       }
       prev_worst = worst;
     }
-    feast::gather_rows<z64>(s, T1, ldY, m, perm, n, m, N, T2, ldY, m);
+    // (with cols < m the unused node columns of T1 hold stale values: they are
+    // carried along by the conversions but never read by the products)
+    feast::gather_rows<z64>(s, T1, ldY, sY, perm, n, m, N, T2, ldY, sY);
     feast::z_to_c(s, T2, ldY, 0, n, ldY, 1, Yc, ldY, 0);
-    plan_trsolve<c64>(p, s, Yc, m, ldY, m, 0);
+    plan_trsolve<c64>(p, s, Yc, m, ldY, sY, 0);
     feast::add_c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
     p->last_sweeps = sweep + 1;
   }
@@ -383,13 +387,14 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
 // U = sum_j w_j (z_j B - A)^{-1} R  (the filter of eq. 8-4 on the right-hand side R = B U_1).
 // Mixed form: see solve_nodes_mixed for `target` and `sweeps`.
 int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb, const z64 *R,
-               int64_t ldr, z64 *U, int64_t ldu, double target, int sweeps) {
+               int64_t ldr, z64 *U, int64_t ldu, double target, int sweeps, int64_t cols = -1) {
+  if (cols < 0) cols = p->m;
   int st = ensure_factored(p, A, lda, B, ldb);
   if (p->mixed())
-    solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps);
+    solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps, cols);
   else
-    solve_nodes_z(p, R, ldr);
-  feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, p->m, U,
+    solve_nodes_z(p, R, ldr, cols);
+  feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, cols, U,
                       ldu);
   if (st == FEAST_OK && p->mixed() && p->stagnated) {
     char buf[160];
@@ -501,9 +506,9 @@ int64_t splitws_elems(const feast_plan *p) {
   return static_cast<int64_t>(p->splitws.bytes / sizeof(z64));
 }
 
-// Factor every shifted matrix z_j B - A once and cache the factors (Section 4.3).
-void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot) {
-  const int64_t n = p->n, m = p->m;
+// (cols: columns of X to orthonormalise, at most the plan's m; default m)
+void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot, int64_t cols) {
+  const int64_t n = p->n, m = cols < 0 ? p->m : cols;
   hipStream_t s = p->s;
   z64 *G = p->gblk(feast_plan::G_GRAM);
   z64 *Ri = p->gblk(feast_plan::G_RINV), *T = p->gblk(feast_plan::G_T);
@@ -741,9 +746,12 @@ int feast_project(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *
   });
 }
 
-int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
-                const feast_z *dV, int64_t ldv, feast_z *hLambda, feast_z *dX, int64_t ldx,
-                double *hRes, int32_t *s_found, double *err, int32_t *flag, feast_info *info) {
+// Algorithm 5; from_basis: dV is an orthonormal U_1 that is already filtered
+// (Search's output), so line 1 is skipped.
+static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
+                      int64_t ldb, const feast_z *dV, int64_t ldv, bool from_basis,
+                      feast_z *hLambda, feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found,
+                      double *err, int32_t *flag, feast_info *info) {
   if (!p) return FEAST_EINVAL;
   if (!dA || !dB || !dV || !hLambda || !dX || !s_found || !err || !flag || lda < p->n ||
       ldb < p->n || ldv < p->m || ldx < p->m)
@@ -796,8 +804,11 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
       inf.filters += 1;
       return st;
     };
-    // line 1 (Search with the subspace size fixed): U = Q_N V, QR inside the projection
-    {
+    if (from_basis) {
+      // line 1 was Search (feast_search): its basis is U_1
+      feast::copy_block_z(s, V, ldv, n, m, U1, m);
+    } else {
+      // line 1 (Search with the subspace size fixed): U = Q_N V, QR inside the projection
       Timer t;
       gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1);
       const int st = run_filter(p->R.as<z64>(), U1, true);
@@ -965,6 +976,146 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
     inf.lu_gemm_flops = p->prof_flops;
     if (info) *info = inf;
     return status;
+  });
+}
+
+int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
+                const feast_z *dV, int64_t ldv, feast_z *hLambda, feast_z *dX, int64_t ldx,
+                double *hRes, int32_t *s_found, double *err, int32_t *flag, feast_info *info) {
+  return solve_impl(p, dA, lda, dB, ldb, dV, ldv, false, hLambda, dX, ldx, hRes, s_found, err,
+                    flag, info);
+}
+
+int feast_solve_from(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
+                     int64_t ldb, const feast_z *dU1, int64_t ldu, feast_z *hLambda, feast_z *dX,
+                     int64_t ldx, double *hRes, int32_t *s_found, double *err, int32_t *flag,
+                     feast_info *info) {
+  return solve_impl(p, dA, lda, dB, ldb, dU1, ldu, true, hLambda, dX, ldx, hRes, s_found, err,
+                    flag, info);
+}
+
+int feast_plan_set_m(feast_plan *p, int64_t m) {
+  if (!p) return FEAST_EINVAL;
+  if (m < 1 || m > p->n) return fail(p, FEAST_EINVAL, "feast_plan_set_m: m must be in [1, n]");
+  p->err.clear();
+  return guarded(p, [&]() -> int {
+    p->m = m;
+    ensure_workspace(p);
+    return FEAST_OK;
+  });
+}
+
+// Algorithm 4 (Search).  The filtered blocks, the trace and the Gram matrices
+// are GPU products; the rank-revealing step is the pivoted Cholesky of the
+// s_dagger x s_dagger Gram matrix on the host (the pivots and |R_ii| of the
+// column-pivoted QR of the block); the basis U_1 of the t leading pivot
+// columns is orthonormalised on the GPU (shifted Cholesky QR3).
+int feast_search(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
+                 const feast_z *dY, int64_t ldy, int64_t ycols, int32_t p0, double alpha,
+                 double tau, feast_z *dU1, int64_t ldu, feast_search_info *info) {
+  if (!p) return FEAST_EINVAL;
+  if (!dA || !dB || !dY || !dU1 || !info || lda < p->n || ldb < p->n || ycols < 1 ||
+      ldy < ycols || ldu < p->m)
+    return fail(p, FEAST_EINVAL, "feast_search: null pointer or leading dimension too small");
+  if (p0 < 1 || p0 > p->m || p0 > ycols || !(alpha > 1.0) || !(tau > 0.0 && tau < 1.0))
+    return fail(p, FEAST_EINVAL, "feast_search: need 1 <= p <= min(m, pool columns), alpha > 1, 0 < tau < 1");
+  p->err.clear();
+  return guarded(p, [&]() -> int {
+    Timer total;
+    const int64_t n = p->n, m = p->m, cap = std::min(n, m);
+    hipStream_t s = p->s;
+    const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
+    const z64 *Y = reinterpret_cast<const z64 *>(dY);
+    int st = ensure_factored(p, A, lda, B, ldb);
+    if (st == FEAST_SINGULAR) return st;
+    z64 *U = p->wblk(feast_plan::W_X);    // block under test, n x s_dagger (leading dim m)
+    z64 *Wg = p->wblk(feast_plan::W_AX);  // leading pivot columns, then U_1
+    z64 *R = p->R.as<z64>();              // right-hand sides B Y (leading dim m)
+    z64 *G = p->gblk(feast_plan::G_GRAM);
+    int32_t *didx = reinterpret_cast<int32_t *>(p->small.as<z64>());
+    feast_search_info out{};
+    // (Search's filters are not refined in the mixed form: its rank test needs
+    // single-precision accuracy only)
+    auto filt = [&](int64_t col0, int64_t c, z64 *dst) -> int {
+      gemm_t<z64>(s, 0, n, c, n, zc(1.0), B, ldb, 0, Y + col0, ldy, 0, zc(0.0), R, m, 0, 1);
+      const int r = filter_rhs(p, A, lda, B, ldb, R, m, dst, m, 0.0, 0, c);
+      out.filters += 1;
+      return r;
+    };
+    auto gram = [&](const z64 *X, int64_t k, int64_t ldx2, const z64 *Z, int64_t ldz,
+                    std::vector<feast_z> &h) {
+      gemm_t<z64>(s, 2, k, k, n, zc(1.0), X, ldx2, 0, Z, ldz, 0, zc(0.0), G, k, 0, 1,
+                  p->splitws.as<z64>(), splitws_elems(p));
+      h.resize(static_cast<size_t>(k * k));
+      HIPCHK(hipMemcpyAsync(h.data(), G, sizeof(z64) * k * k, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    };
+    // line 1
+    int64_t pc = p0, used = p0;
+    st = filt(0, pc, U);
+    if (st != FEAST_OK) return st;
+    // line 2: s_0 = ceil(Re trace(Y_0^* U) / p)
+    std::vector<feast_z> hg;
+    gram(Y, pc, ldy, U, m, hg);
+    double tr = 0.0;
+    for (int64_t i = 0; i < pc; ++i) tr += hg[i * pc + i].re;
+    out.s0 = static_cast<int64_t>(std::ceil(tr / static_cast<double>(pc)));
+    int64_t sd = std::min(std::max<int64_t>(pc, out.s0), cap);
+    std::vector<int32_t> piv;
+    std::vector<double> rd;
+    for (;;) {
+      // lines 3-8: widen the block with s_dagger - p newly filtered columns
+      if (sd > pc) {
+        const int64_t c = sd - pc;
+        if (used + c > ycols)
+          return fail(p, FEAST_EINVAL, "feast_search: random column pool exhausted");
+        st = filt(used, c, U + pc);
+        if (st != FEAST_OK) return st;
+        used += c;
+      } else {
+        sd = pc;
+      }
+      // line 9: rank-revealing step
+      gram(U, sd, m, U, m, hg);
+      piv.assign(static_cast<size_t>(sd), 0);
+      rd.assign(static_cast<size_t>(sd), 0.0);
+      const int64_t t = feast_host::pivoted_cholesky_rank(
+          sd, reinterpret_cast<const cd *>(hg.data()), sd, tau, piv.data(), rd.data());
+      out.rounds += 1;
+      if (t < 1) return fail(p, FEAST_ENUMERIC, "feast_search: the filtered block is zero");
+      HIPCHK(hipMemcpyAsync(didx, piv.data(), sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+      feast::gather_normalize_cols(s, U, m, n, didx, t, Wg, m, p->part.as<double>());
+      feast::fill_i32(s, p->flag.as<int32_t>(), 3, 0);
+      orth(p, Wg, m, 0, t);
+      int32_t hf[3];
+      HIPCHK(hipMemcpyAsync(hf, p->flag.p, sizeof hf, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (hf[0] || hf[1] || hf[2])
+        return fail(p, FEAST_ENUMERIC, "feast_search: Cholesky QR of the pivot columns broke down");
+      // line 10
+      if (t < sd) {
+        feast::copy_block_z(s, Wg, m, n, t, reinterpret_cast<z64 *>(dU1), ldu);
+        out.t = t;
+        break;
+      }
+      const int64_t nxt = std::min<int64_t>(static_cast<int64_t>(std::ceil(alpha * t)), cap);
+      if (nxt <= t) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "feast_search: the block is still of full rank at %lld columns (the plan's "
+                      "subspace size m); use a larger m",
+                      static_cast<long long>(t));
+        return fail(p, FEAST_EINVAL, buf);
+      }
+      feast::copy_block_z(s, Wg, m, n, t, U, m);
+      pc = t;
+      sd = nxt;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    out.used = used;
+    out.ms = total.ms();
+    *info = out;
+    return FEAST_OK;
   });
 }
 

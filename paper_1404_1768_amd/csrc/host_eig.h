@@ -19,6 +19,16 @@ int reduced_eig(int64_t t, const std::complex<double> *At, int64_t lda,
 int contour_nodes(std::complex<double> center, double radius, int N, int rule,
                   std::complex<double> *z, std::complex<double> *w);
 
+// Rank-revealing step of Search (Algorithm 4 line 9) on the Gram matrix
+// G = U^* U (k x k Hermitian positive semi-definite, row-major, leading
+// dimension ldg): Cholesky with diagonal pivoting, Pi^T G Pi = R^* R, which in
+// exact arithmetic has the pivots and |R_ii| of the column-pivoted QR of U.
+// piv[0..k) receives the column order; rdiag[j] = R_jj for the columns
+// factored (zero past the first non-positive remaining diagonal).  Returns the
+// numerical rank #{j : R_jj >= tau R_00}.
+int64_t pivoted_cholesky_rank(int64_t k, const std::complex<double> *G, int64_t ldg, double tau,
+                              int32_t *piv, double *rdiag);
+
 // Decision after iteration k: 1 (line 13), 0 (line 14), -1 (line 15), 2 continue.
 int stop_rule(int k, int c_k, double e_k, int c_prev, double e_prev, double eps, int max_iter);
 

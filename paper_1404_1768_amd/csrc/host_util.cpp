@@ -1,6 +1,7 @@
 // Quadrature nodes of eq. (8-4) and the stopping rules of Algorithm 5.
 #include <cmath>
 #include <complex>
+#include <vector>
 
 #include "host_eig.h"
 
@@ -88,6 +89,47 @@ int stop_rule(int k, int c_k, double e_k, int c_prev, double e_prev, double eps,
   }
   if (k == max_iter) return -1;
   return 2;
+}
+
+int64_t pivoted_cholesky_rank(int64_t k, const std::complex<double> *G, int64_t ldg, double tau,
+                              int32_t *piv, double *rdiag) {
+  using cd = std::complex<double>;
+  // R (row-major k x k) holds the rows of R in pivoted column order as they
+  // are produced; d[i] is the remaining diagonal of column piv[i]
+  std::vector<cd> R(static_cast<size_t>(k * k), cd(0.0));
+  std::vector<double> d(static_cast<size_t>(k));
+  for (int64_t i = 0; i < k; ++i) {
+    piv[i] = static_cast<int32_t>(i);
+    d[i] = G[i * ldg + i].real();
+    rdiag[i] = 0.0;
+  }
+  int64_t done = 0;
+  for (int64_t j = 0; j < k; ++j) {
+    int64_t q = j;
+    for (int64_t i = j + 1; i < k; ++i)
+      if (d[i] > d[q]) q = i;
+    if (!(d[q] > 0.0)) break;
+    if (q != j) {
+      std::swap(piv[j], piv[q]);
+      std::swap(d[j], d[q]);
+      for (int64_t l = 0; l < j; ++l) std::swap(R[l * k + j], R[l * k + q]);
+    }
+    const double rjj = std::sqrt(d[j]);
+    rdiag[j] = rjj;
+    R[j * k + j] = rjj;
+    for (int64_t i = j + 1; i < k; ++i) {
+      cd v = G[static_cast<int64_t>(piv[j]) * ldg + piv[i]];
+      for (int64_t l = 0; l < j; ++l) v -= std::conj(R[l * k + j]) * R[l * k + i];
+      v /= rjj;
+      R[j * k + i] = v;
+      d[i] -= std::norm(v);
+    }
+    done = j + 1;
+  }
+  int64_t rank = 0;
+  for (int64_t j = 0; j < done; ++j)
+    if (rdiag[j] >= tau * rdiag[0]) ++rank;
+  return rank;
 }
 
 }  // namespace feast_host
