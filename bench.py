@@ -98,6 +98,46 @@ def time_form(form, p, A, B, V, steps, warmup):
         plan.close()
 
 
+def time_search(p, A, B, steps, warmup):
+    """Algorithm 4 then Algorithm 5 from its basis (mixed form) on the same
+    pencil, without the caller's m: p = 50 Gaussian start columns, alpha = 1.5,
+    tau = 1e-3, subspace capacity 240.  One step = factorisation + Search +
+    Algorithm 5 lines 2-18 (Search's filters are the first application)."""
+    import numpy as np
+    import torch
+    import paper_1404_1768_amd as fm
+    pool = torch.from_numpy(np.random.default_rng(7).normal(size=(p.n, 400)).astype(
+        np.complex128)).to(A.device)
+    plan = fm.Plan(p.n, 240, p.center, p.radius, p.nodes, prec=fm.MIXED, eps=1e-10)
+    try:
+        def one():
+            plan.set_m(240)
+            plan.invalidate()
+            U1, info = plan.search(A, B, pool, 50, alpha=1.5, tau=1e-3)
+            plan.set_m(info["t"])
+            r = plan.solve_from(A, B, U1)
+            return info, r
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [one() for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        info, r = runs[-1]
+        ok = all(i["t"] >= p.s and x.flag == 1 and len(x.lam) == p.s and x.err <= 1e-10
+                 for i, x in runs)
+        out = {"workload": "pencil n=4000 N=32 s=100, Search p=50 alpha=1.5 tau=1e-3, mixed",
+               "ms": ms, "ok": ok, "search_ms": round(info["ms"], 3), "t": info["t"],
+               "s0": info["s0"], "rounds": info["rounds"], "search_filters": info["filters"],
+               "pool_columns": info["used"], "iters": r.iters, "err": r.err,
+               "count": len(r.lam)}
+        log("[bench] search+solve: %.1f ms/step ok=%s %s" % (ms, ok, out))
+        return out
+    finally:
+        plan.close()
+
+
 def time_batch(ps, As, Bs, Vs, steps, warmup):
     """Workload of 64 pencils: one step = a complete batched solve of every
     pencil (factorisations of all 1024 shifted matrices included)."""
@@ -185,6 +225,8 @@ def main():
     ap.add_argument("--cpu-nodes", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-search", action="store_true",
+                    help="skip the Search (Algorithm 4) + Algorithm 5 leg (key 'search')")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 1 GiB (3 launches): the reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a PMC run")
@@ -240,6 +282,9 @@ def main():
         bV = [torch.from_numpy(q.V).to(dev) for q in ps]
         batched = time_batch(ps, bA, bB, bV, min(args.steps, 3), max(args.warmup, 1))
         del bA, bB, bV
+    search = None
+    if not args.no_search:
+        search = time_search(p, A, B, min(args.steps, 3), 1)
     large = None
     if args.large:
         pl = pg.workload(3)
@@ -260,7 +305,7 @@ def main():
         "config": {"workload": "pencil n=4000 N=32 m=160 s=100 (trapezoid, circle 1+1i r=1)",
                    "form": best, "n": p.n, "nodes": p.nodes, "m": p.m, "eps": 1e-10},
         "forms": forms, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
-        "large": large,
+        "search": search, "large": large,
     }
     print(json.dumps(out), flush=True)
 

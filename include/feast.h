@@ -170,6 +170,25 @@ int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z 
                 int32_t *flag, feast_info *info);
 
 /* ---------------------------------------------------------------------------
+ * Irregular contours (Section 4.3): eigenpairs inside a closed curve Gamma are
+ * found by solving inside a circle that encloses Gamma and keeping those
+ * inside Gamma.  Gamma is a closed polygon given by its vertices (host
+ * array, either orientation, no repeated closing vertex).  Host only.
+ * ------------------------------------------------------------------------- */
+
+/* The smallest circle enclosing the nv >= 1 vertices (it encloses the
+ * polygon), radius enlarged by the factor (1 + margin), margin >= 0: a margin
+ * keeps eigenvalues near the vertices away from the circle, where the filter
+ * value falls to 1/2.  FEAST_EINVAL for bad arguments or non-finite vertices. */
+int feast_enclosing_circle(int32_t nv, const feast_z *vertices, double margin, feast_z *center,
+                           double *radius);
+
+/* inside[i] = 1 if lambda[i] lies inside the polygon (even-odd rule; a point on
+ * an edge may be reported either way), else 0, for i < k.  nv >= 3. */
+int feast_region_select(int32_t nv, const feast_z *vertices, int64_t k, const feast_z *lambda,
+                        int32_t *inside);
+
+/* ---------------------------------------------------------------------------
  * Search (Algorithm 4, Section 4.1): an upper bound t of the number s of
  * eigenvalues inside the contour, without knowing s
  * ------------------------------------------------------------------------- */

@@ -326,6 +326,61 @@ def gfeast_from(A: np.ndarray, B: np.ndarray, U1: np.ndarray, center: complex, r
 
 
 # ---------------------------------------------------------------------------
+# Irregular contours (Section 4.3): an enclosing circle, then the region test
+# ---------------------------------------------------------------------------
+
+def enclosing_circle(vertices: np.ndarray, margin: float = 0.0):
+    """Smallest circle containing all vertices, by brute force over the circles
+    spanned by two points (as a diameter) or three (circumcircle); the radius
+    is then enlarged by ``1 + margin``.  (A disc containing the vertices
+    contains the polygon: it is convex.)  Small polygons only."""
+    v = np.asarray(vertices, dtype=np.complex128).ravel()
+    if v.size == 1:
+        return complex(v[0]), 0.0
+    cands = []
+    for i in range(v.size):
+        for j in range(i + 1, v.size):
+            cands.append(((v[i] + v[j]) / 2, abs(v[i] - v[j]) / 2))
+            for k in range(j + 1, v.size):
+                a, b, c = v[i], v[j], v[k]
+                # circumcentre: the point equidistant from a, b, c (2x2 linear system)
+                M = np.array([[2 * (b - a).real, 2 * (b - a).imag],
+                              [2 * (c - a).real, 2 * (c - a).imag]])
+                if abs(np.linalg.det(M)) < 1e-300:
+                    continue
+                rhs = np.array([abs(b) ** 2 - abs(a) ** 2, abs(c) ** 2 - abs(a) ** 2])
+                x, y = np.linalg.solve(M, rhs)
+                cands.append((complex(x, y), abs(complex(x, y) - a)))
+    best = None
+    for c, r in cands:
+        if np.all(np.abs(v - c) <= r * (1 + 1e-10) + 1e-14) and (best is None or r < best[1]):
+            best = (c, r)
+    return complex(best[0]), float(best[1]) * (1.0 + margin)
+
+
+def inside_region(points: np.ndarray, vertices: np.ndarray) -> np.ndarray:
+    """Winding number of the closed polygon about each point (non-zero =
+    inside), summed from the turning angles of its edges."""
+    v = np.asarray(vertices, dtype=np.complex128).ravel()
+    z = np.asarray(points, dtype=np.complex128).ravel()
+    a = v[None, :] - z[:, None]
+    b = np.roll(v, -1)[None, :] - z[:, None]
+    wind = np.sum(np.angle(b / a), axis=1) / (2 * np.pi)
+    return np.abs(wind) > 0.5
+
+
+def gfeast_region(A: np.ndarray, B: np.ndarray, V: np.ndarray, vertices: np.ndarray, N: int,
+                  margin: float = 0.1, **kw):
+    """Section 4.3 for an irregular curve: Algorithm 5 on an enclosing circle,
+    then the eigenpairs inside the curve.  Returns (Result restricted, circle)."""
+    center, radius = enclosing_circle(vertices, margin)
+    res = gfeast(A, B, V, center, radius, N, **kw)
+    keep = inside_region(res.lam, vertices)
+    return dataclasses.replace(res, lam=res.lam[keep], X=res.X[:, keep], r=res.r[keep]), \
+        (center, radius)
+
+
+# ---------------------------------------------------------------------------
 # Search (Algorithm 4, Section 4.1): an upper bound t of s and U_1
 # ---------------------------------------------------------------------------
 

@@ -10,4 +10,4 @@ from .binding import (FEAST_OK, FEAST_SINGULAR, FEAST_REFINE_STAGNATED, FEAST_EI
                       FP64, MIXED, FeastError, Plan, SolveResult, feast_filter, feast_project,
                       feast_solve, feast_nodes, feast_reduced_eig, feast_stop_rule, load,
                       zgemm_batched, zgetrf_batched, zgetrs_batched, LIB_PATH, feast_eig,
-                      Batch, BatchResult)
+                      Batch, BatchResult, enclosing_circle, region_inside, solve_region)

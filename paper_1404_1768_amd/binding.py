@@ -39,7 +39,8 @@ EXPORTED = [
     "feast_zgemm_batched", "feast_version", "feast_left_eigvecs", "feast_eig_grad",
     "feast_batch_create", "feast_batch_destroy", "feast_batch_invalidate",
     "feast_batch_last_error", "feast_batch_filter", "feast_batch_solve",
-    "feast_search", "feast_plan_set_m", "feast_solve_from",
+    "feast_search", "feast_plan_set_m", "feast_solve_from", "feast_enclosing_circle",
+    "feast_region_select",
 ]
 
 
@@ -117,6 +118,8 @@ def load(path: str = LIB_PATH):
     lib.feast_search.argtypes = [P, P, i64, P, i64, P, i64, i64, i32, dbl, dbl, P, i64,
                                  C.POINTER(SearchInfo)]
     lib.feast_plan_set_m.argtypes = [P, i64]
+    lib.feast_enclosing_circle.argtypes = [i32, pz, dbl, pz, C.POINTER(dbl)]
+    lib.feast_region_select.argtypes = [i32, pz, i64, pz, C.POINTER(i32)]
     lib.feast_last_error.argtypes = [P]
     lib.feast_last_error.restype = C.c_char_p
     lib.feast_reduced_eig.argtypes = [i64, pz, i64, pz, i64, pz, pz, pz, i64]
@@ -223,6 +226,44 @@ def feast_reduced_eig(At: np.ndarray, Bt: np.ndarray):
 
 def feast_stop_rule(k, c_k, e_k, c_prev, e_prev, eps, max_iter) -> int:
     return load().feast_stop_rule(k, c_k, float(e_k), c_prev, float(e_prev), float(eps), max_iter)
+
+
+def enclosing_circle(vertices, margin: float = 0.1):
+    """(center, radius) of the smallest circle enclosing the polygon's
+    vertices, radius enlarged by (1 + margin)."""
+    v = np.ascontiguousarray(vertices, dtype=np.complex128).ravel()
+    c = FeastZ()
+    r = C.c_double()
+    rc = load().feast_enclosing_circle(v.size, _zptr(v), float(margin), C.byref(c), C.byref(r))
+    if rc != FEAST_OK:
+        raise FeastError(rc, "feast_enclosing_circle: bad vertices or margin")
+    return complex(c.re, c.im), r.value
+
+
+def region_inside(vertices, lam) -> np.ndarray:
+    """Boolean mask of the points lam inside the polygon (even-odd rule)."""
+    v = np.ascontiguousarray(vertices, dtype=np.complex128).ravel()
+    z = np.ascontiguousarray(lam, dtype=np.complex128).ravel()
+    out = np.zeros(z.size, dtype=np.int32)
+    rc = load().feast_region_select(v.size, _zptr(v), z.size, _zptr(z),
+                                    out.ctypes.data_as(C.POINTER(C.c_int32)))
+    if rc != FEAST_OK:
+        raise FeastError(rc, "feast_region_select: bad arguments")
+    return out.astype(bool)
+
+
+def solve_region(A, B, V, vertices, nodes: int = 32, margin: float = 0.1, **plan_kw):
+    """Eigenpairs inside an irregular closed curve (a polygon): Algorithm 5 on
+    the enclosing circle, then the pairs inside the polygon (Section 4.3).
+    Returns (SolveResult restricted to the region, (center, radius))."""
+    center, radius = enclosing_circle(vertices, margin)
+    n, m = int(A.shape[0]), int(V.shape[1])
+    with Plan(n, m, center, radius, nodes, **plan_kw) as plan:
+        r = plan.solve(A, B, V)
+    keep = region_inside(vertices, r.lam)
+    idx = np.flatnonzero(keep)
+    r = dataclasses.replace(r, lam=r.lam[idx], X=r.X[:, idx], res=r.res[idx])
+    return r, (center, radius)
 
 
 # ---------------------------------------------------------------------------

@@ -979,6 +979,28 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
   });
 }
 
+int feast_enclosing_circle(int32_t nv, const feast_z *vertices, double margin, feast_z *center,
+                           double *radius) {
+  if (nv < 1 || !vertices || !center || !radius || !(margin >= 0.0)) return FEAST_EINVAL;
+  for (int32_t i = 0; i < nv; ++i)
+    if (!std::isfinite(vertices[i].re) || !std::isfinite(vertices[i].im)) return FEAST_EINVAL;
+  cd c;
+  double r;
+  feast_host::enclosing_circle(nv, reinterpret_cast<const cd *>(vertices), &c, &r);
+  *center = {c.real(), c.imag()};
+  *radius = r * (1.0 + margin);
+  return FEAST_OK;
+}
+
+int feast_region_select(int32_t nv, const feast_z *vertices, int64_t k, const feast_z *lambda,
+                        int32_t *inside) {
+  if (nv < 3 || !vertices || k < 0 || (k > 0 && (!lambda || !inside))) return FEAST_EINVAL;
+  const cd *v = reinterpret_cast<const cd *>(vertices);
+  for (int64_t i = 0; i < k; ++i)
+    inside[i] = feast_host::inside_polygon(cd(lambda[i].re, lambda[i].im), nv, v) ? 1 : 0;
+  return FEAST_OK;
+}
+
 int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
                 const feast_z *dV, int64_t ldv, feast_z *hLambda, feast_z *dX, int64_t ldx,
                 double *hRes, int32_t *s_found, double *err, int32_t *flag, feast_info *info) {

@@ -29,6 +29,14 @@ int contour_nodes(std::complex<double> center, double radius, int N, int rule,
 int64_t pivoted_cholesky_rank(int64_t k, const std::complex<double> *G, int64_t ldg, double tau,
                               int32_t *piv, double *rdiag);
 
+// Irregular contours (Section 4.3): the smallest circle enclosing the vertices
+// of a closed polygon (Welzl's incremental construction; it encloses the
+// polygon, since a disc contains the convex hull of its points), and the
+// even-odd inside test of a point against the polygon.
+void enclosing_circle(int64_t nv, const std::complex<double> *v, std::complex<double> *center,
+                      double *radius);
+bool inside_polygon(std::complex<double> z, int64_t nv, const std::complex<double> *v);
+
 // Decision after iteration k: 1 (line 13), 0 (line 14), -1 (line 15), 2 continue.
 int stop_rule(int k, int c_k, double e_k, int c_prev, double e_prev, double eps, int max_iter);
 

@@ -132,4 +132,66 @@ int64_t pivoted_cholesky_rank(int64_t k, const std::complex<double> *G, int64_t 
   return rank;
 }
 
+namespace {
+
+using cd = std::complex<double>;
+
+struct Disc {
+  cd c;
+  double r;
+  bool holds(cd z) const { return std::abs(z - c) <= r * (1.0 + 1e-12) + 1e-300; }
+};
+
+Disc disc2(cd a, cd b) { return Disc{0.5 * (a + b), 0.5 * std::abs(a - b)}; }
+
+// Circle through a, b, c; collinear points fall back to the widest pair.
+Disc disc3(cd a, cd b, cd c) {
+  const cd b1 = b - a, c1 = c - a;
+  const double d = 2.0 * (b1.real() * c1.imag() - b1.imag() * c1.real());
+  if (d == 0.0) {
+    Disc best = disc2(a, b);
+    for (const Disc &o : {disc2(a, c), disc2(b, c)})
+      if (o.r > best.r) best = o;
+    return best;
+  }
+  const double nb = std::norm(b1), nc = std::norm(c1);
+  const cd u((c1.imag() * nb - b1.imag() * nc) / d, (b1.real() * nc - c1.real() * nb) / d);
+  return Disc{a + u, std::abs(u)};
+}
+
+}  // namespace
+
+void enclosing_circle(int64_t nv, const cd *v, cd *center, double *radius) {
+  if (nv <= 0) {
+    *center = 0.0;
+    *radius = 0.0;
+    return;
+  }
+  Disc D{v[0], 0.0};
+  for (int64_t i = 1; i < nv; ++i) {
+    if (D.holds(v[i])) continue;
+    D = Disc{v[i], 0.0};
+    for (int64_t j = 0; j < i; ++j) {
+      if (D.holds(v[j])) continue;
+      D = disc2(v[i], v[j]);
+      for (int64_t k = 0; k < j; ++k)
+        if (!D.holds(v[k])) D = disc3(v[i], v[j], v[k]);
+    }
+  }
+  *center = D.c;
+  *radius = D.r;
+}
+
+bool inside_polygon(cd z, int64_t nv, const cd *v) {
+  bool in = false;
+  for (int64_t i = 0, j = nv - 1; i < nv; j = i++) {
+    const double yi = v[i].imag(), yj = v[j].imag();
+    if ((yi > z.imag()) != (yj > z.imag())) {
+      const double x = v[i].real() + (z.imag() - yi) * (v[j].real() - v[i].real()) / (yj - yi);
+      if (z.real() < x) in = !in;
+    }
+  }
+  return in;
+}
+
 }  // namespace feast_host

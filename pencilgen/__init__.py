@@ -190,3 +190,49 @@ def batch_workload(count: int = 64, lo: int = 256, hi: int = 2048, nodes: int = 
 def start_block(n: int, m: int, seed: int) -> np.ndarray:
     """Complex Gaussian n x m block with unit-variance entries."""
     return _cgauss(np.random.default_rng(seed), (n, m), 1.0)
+
+
+def pencil_from_eigenvalues(d: np.ndarray, m: int, center: complex, radius: float, nodes: int,
+                            c: float = 0.05, seed: int = BASE_SEED, name: str = "") -> Pencil:
+    """``A = P D Q``, ``B = P Q`` with the given eigenvalues ``d`` (same P, Q and V
+    recipe as ``make_pencil``; children ``[G_P, G_Q, V]`` of the seed)."""
+    d = np.asarray(d, dtype=np.complex128)
+    n = d.size
+    rgp, rgq, rv = (np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(3))
+    eye = np.eye(n, dtype=np.complex128)
+    P = eye + c * _cgauss(rgp, (n, n), 1.0 / n)
+    Q = eye + c * _cgauss(rgq, (n, n), 1.0 / n)
+    B = P @ Q
+    A = (P * d[None, :]) @ Q
+    V = _cgauss(rv, (n, m), 1.0)
+    return Pencil(A=np.ascontiguousarray(A), B=np.ascontiguousarray(B), V=np.ascontiguousarray(V),
+                  d=d, P=P, Q=Q, center=complex(center), radius=float(radius), nodes=nodes, m=m,
+                  name=name)
+
+
+# L-shaped region: the unit square [-1, 1]^2 without its upper-right quarter
+L_REGION = np.array([-1 - 1j, 1 - 1j, 1 + 0j, 0 + 0j, 0 + 1j, -1 + 1j], dtype=np.complex128)
+
+
+def region_workload(n: int = 600, inside: int = 30, notch: int = 8, nodes: int = 32,
+                    seed: int = BASE_SEED + 6):
+    """An irregular region (the L-shaped polygon ``L_REGION``): ``inside``
+    eigenvalues uniform in the L, ``notch`` in the cut-out quarter
+    ``(0.15, 0.85)^2`` (inside the enclosing circle, outside the region) and the
+    rest area-uniform in ``2.5 <= |z| < 8``.  Returns the pencil (its circle
+    fields are placeholders: the driver derives the circle from the region)
+    and the mask of the eigenvalues inside the region."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
+    pts = []
+    while len(pts) < inside:
+        x, y = rng.uniform(-0.95, 0.95, size=2)
+        if x <= -0.05 or y <= -0.05:               # the L, clear of its inner edges
+            pts.append(x + 1j * y)
+    notch_pts = rng.uniform(0.15, 0.85, size=notch) + 1j * rng.uniform(0.15, 0.85, size=notch)
+    out = _area_uniform(rng, n - inside - notch, 2.5, 8.0, 0.0)
+    d = np.concatenate([np.array(pts), notch_pts, out])
+    p = pencil_from_eigenvalues(d, m=2 * (inside + notch), center=0.0, radius=1.0, nodes=nodes,
+                                seed=seed + 1, name="region-L-n%d" % n)
+    mask = np.zeros(n, dtype=bool)
+    mask[:inside] = True
+    return p, mask
