@@ -326,6 +326,51 @@ def gfeast_from(A: np.ndarray, B: np.ndarray, U1: np.ndarray, center: complex, r
 
 
 # ---------------------------------------------------------------------------
+# Block_CIRR (Algorithm 1, Section 2): the comparison method on the same solves
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class CirrResult:
+    lam: np.ndarray     # selected eigenvalues (inside the circle, r < eta)
+    X: np.ndarray       # their eigenvectors (unit columns)
+    r: np.ndarray       # their residuals (eq. 5-1)
+    t: int              # columns of the moment block, h g
+    sv: np.ndarray      # singular values of the moment block (step 2)
+
+
+def cirr_moments(solver: ShiftedSolver, z: np.ndarray, w: np.ndarray, Y: np.ndarray,
+                 g: int, center: complex, radius: float) -> np.ndarray:
+    """Step 1: ``[R_0, ..., R_{g-1}]`` with ``R_i`` the quadrature of
+    ``F_i Y`` (eq. 2-2-21), in the shifted and scaled powers
+    ``((z - gamma)/rho)^i`` (same span as ``z^i`` for ``i < g``)."""
+    mu = (z - center) / radius
+    Ys = [solver.solve(j, Y) for j in range(len(w))]
+    return np.hstack([sum(w[j] * mu[j] ** i * Ys[j] for j in range(len(w))) for i in range(g)])
+
+
+def block_cirr(A: np.ndarray, B: np.ndarray, Y: np.ndarray, g: int, center: complex,
+               radius: float, N: int, rule: int = TRAPEZOID, eta: float = 1e-3,
+               solver: Optional[ShiftedSolver] = None) -> CirrResult:
+    """Algorithm 1: moments, SVD (step 2, all ``h g`` left singular vectors),
+    Rayleigh-Ritz with the left space equal to the right one (steps 3-4), Ritz
+    vectors and the selection of step 5 (inside the circle with ``r_i < eta``,
+    as GFEAST's line 10)."""
+    z, w = contour_nodes(center, radius, N, rule)
+    if solver is None:
+        solver = ShiftedSolver(A, B, z)
+    M = cirr_moments(solver, z, w, Y, g, center, radius)
+    U, S, _ = np.linalg.svd(M, full_matrices=False)
+    Ab = U.conj().T @ (A @ U)
+    Bb = U.conj().T @ (B @ U)
+    alpha, beta, Yv = reduced_eig(Ab, Bb)
+    lam = eigenvalues_from(alpha, beta)
+    X = normalize_columns(U @ Yv)
+    r = residuals(A, B, lam, X)
+    sel = inside(lam, center, radius) & (r < eta)
+    return CirrResult(lam[sel], X[:, sel], r[sel], M.shape[1], S)
+
+
+# ---------------------------------------------------------------------------
 # Irregular contours (Section 4.3): an enclosing circle, then the region test
 # ---------------------------------------------------------------------------
 
