@@ -138,6 +138,37 @@ def time_search(p, A, B, steps, warmup):
         plan.close()
 
 
+def time_cirr(p, A, B, V, steps, warmup):
+    """Block_CIRR (Algorithm 1), the paper's comparison method, on the same
+    pencil and factors machinery (mixed form): h = 32 columns of the start
+    block, g = 5 moments (t = 160).  One step = factorisation + one pass."""
+    import numpy as np
+    import torch
+    import paper_1404_1768_amd as fm
+    Y = V[:, :32].contiguous()
+    plan = fm.Plan(p.n, 160, p.center, p.radius, p.nodes, prec=fm.MIXED)
+    try:
+        for _ in range(warmup):
+            plan.invalidate()
+            plan.cirr(A, B, Y, 5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.invalidate()
+            lam, X, res, info = plan.cirr(A, B, Y, 5)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        d_in = p.d[p.inside_mask]
+        err = float(np.max(np.min(np.abs(lam[:, None] - d_in[None, :]), axis=1))) if len(lam) else None
+        out = {"workload": "pencil n=4000 N=32 s=100, Block_CIRR h=32 g=5 (t=160), mixed",
+               "ms": ms, "count": len(lam), "max_residual": float(res.max()) if len(res) else None,
+               "max_eig_error": err, "ok": len(lam) == p.s}
+        log("[bench] block_cirr: %.1f ms/step %s" % (ms, out))
+        return out
+    finally:
+        plan.close()
+
+
 def time_batch(ps, As, Bs, Vs, steps, warmup):
     """Workload of 64 pencils: one step = a complete batched solve of every
     pencil (factorisations of all 1024 shifted matrices included)."""
@@ -225,6 +256,8 @@ def main():
     ap.add_argument("--cpu-nodes", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cirr", action="store_true",
+                    help="skip the Block_CIRR (Algorithm 1) comparison leg (key 'cirr')")
     ap.add_argument("--no-search", action="store_true",
                     help="skip the Search (Algorithm 4) + Algorithm 5 leg (key 'search')")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -285,6 +318,9 @@ def main():
     search = None
     if not args.no_search:
         search = time_search(p, A, B, min(args.steps, 3), 1)
+    cirr = None
+    if not args.no_cirr:
+        cirr = time_cirr(p, A, B, V, min(args.steps, 3), 1)
     large = None
     if args.large:
         pl = pg.workload(3)
@@ -305,7 +341,7 @@ def main():
         "config": {"workload": "pencil n=4000 N=32 m=160 s=100 (trapezoid, circle 1+1i r=1)",
                    "form": best, "n": p.n, "nodes": p.nodes, "m": p.m, "eps": 1e-10},
         "forms": forms, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
-        "search": search, "large": large,
+        "search": search, "cirr": cirr, "large": large,
     }
     print(json.dumps(out), flush=True)
 

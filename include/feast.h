@@ -170,6 +170,38 @@ int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z 
                 int32_t *flag, feast_info *info);
 
 /* ---------------------------------------------------------------------------
+ * Block_CIRR (Algorithm 1, Section 2): the paper's comparison method, on the
+ * plan's cached factors
+ * ------------------------------------------------------------------------- */
+
+typedef struct feast_cirr_info {
+  int64_t t;    /* columns of the moment block, h g */
+  double ms;    /* wall time of the call */
+} feast_cirr_info;
+
+/* Algorithm 1 with the plan's contour and quadrature:
+ *   step 1: R_i = sum_j w_j mu_j^i (z_j B - A)^{-1} Y, i = 0..g-1, with the
+ *           shifted, scaled powers mu_j = (z_j - center)/radius (the same span
+ *           as z_j^i for i < g, better scaled) -- the quadrature of F_i Y of
+ *           eq. (2-2-21);
+ *   step 2: an orthonormal basis U of span[R_0 .. R_{g-1}] (shifted Cholesky
+ *           QR3; Rayleigh-Ritz depends on the span only, so this gives the
+ *           eigenvalues of the SVD's left factor);
+ *   steps 3-4: eigenpairs of (U^* A U, U^* B U) on the host (QZ);
+ *   step 5: x_i = U y_i; selected: |lambda - center| < radius and r_i < eta
+ *           (eq. 5-1), as Algorithm 5 line 10.
+ * dY: device, n x h (leading dimension ldy >= h), the random block; h g <= m.
+ * Outputs as feast_solve: hLambda/hRes (host, capacity m), dX (device n x m,
+ * leading dimension ldx >= m), *s_found.  Mixed plans refine the node
+ * solutions once in FP64.  There is no outer iteration: accuracy follows
+ * the quadrature (outside eigenvalues leak in at 1/(1 + mu^N)).  Synchronises
+ * the stream. */
+int feast_cirr(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
+               int64_t ldb, const feast_z *dY, int64_t ldy, int32_t h, int32_t g,
+               feast_z *hLambda, feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found,
+               feast_cirr_info *info);
+
+/* ---------------------------------------------------------------------------
  * Irregular contours (Section 4.3): eigenpairs inside a closed curve Gamma are
  * found by solving inside a circle that encloses Gamma and keeping those
  * inside Gamma.  Gamma is a closed polygon given by its vertices (host

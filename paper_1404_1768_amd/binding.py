@@ -40,7 +40,7 @@ EXPORTED = [
     "feast_batch_create", "feast_batch_destroy", "feast_batch_invalidate",
     "feast_batch_last_error", "feast_batch_filter", "feast_batch_solve",
     "feast_search", "feast_plan_set_m", "feast_solve_from", "feast_enclosing_circle",
-    "feast_region_select",
+    "feast_region_select", "feast_cirr",
 ]
 
 
@@ -74,6 +74,10 @@ class Info(C.Structure):
 class SearchInfo(C.Structure):
     _fields_ = [("t", C.c_int64), ("s0", C.c_int64), ("used", C.c_int64),
                 ("rounds", C.c_int32), ("filters", C.c_int32), ("ms", C.c_double)]
+
+
+class CirrInfo(C.Structure):
+    _fields_ = [("t", C.c_int64), ("ms", C.c_double)]
 
 
 class BatchInfo(C.Structure):
@@ -118,6 +122,8 @@ def load(path: str = LIB_PATH):
     lib.feast_search.argtypes = [P, P, i64, P, i64, P, i64, i64, i32, dbl, dbl, P, i64,
                                  C.POINTER(SearchInfo)]
     lib.feast_plan_set_m.argtypes = [P, i64]
+    lib.feast_cirr.argtypes = [P, P, i64, P, i64, P, i64, i32, i32, pz, P, i64, C.POINTER(dbl),
+                               C.POINTER(i32), C.POINTER(CirrInfo)]
     lib.feast_enclosing_circle.argtypes = [i32, pz, dbl, pz, C.POINTER(dbl)]
     lib.feast_region_select.argtypes = [i32, pz, i64, pz, C.POINTER(i32)]
     lib.feast_last_error.argtypes = [P]
@@ -431,6 +437,29 @@ class Plan:
         return U1[:, :t], {"t": t, "s0": int(info.s0), "used": int(info.used),
                            "rounds": int(info.rounds), "filters": int(info.filters),
                            "ms": float(info.ms)}
+
+    # -- Block_CIRR (Algorithm 1) -------------------------------------------
+    def cirr(self, A, B, Y, g: int):
+        """Algorithm 1 with the random block Y (n x h) and g moments (h g <= m):
+        returns (lam, X (n x s), res, info dict with t and ms)."""
+        import torch
+        n, m = self.n, self.m
+        pa, lda = _dev(A, n, n, "A")
+        pb, ldb = _dev(B, n, n, "B")
+        h = int(Y.shape[1])
+        py, ldy = _dev(Y, n, h, "Y")
+        X = torch.empty((n, m), dtype=torch.complex128, device=Y.device)
+        lam = np.zeros(m, dtype=np.complex128)
+        res = np.zeros(m, dtype=np.float64)
+        s = C.c_int32()
+        info = CirrInfo()
+        rc = self.lib.feast_cirr(self._h, pa, lda, pb, ldb, py, ldy, h, int(g), _zptr(lam),
+                                 C.c_void_p(X.data_ptr()), m,
+                                 res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(s),
+                                 C.byref(info))
+        self._check(rc, "feast_cirr")
+        k = s.value
+        return lam[:k].copy(), X[:, :k], res[:k].copy(), {"t": int(info.t), "ms": float(info.ms)}
 
     def set_m(self, m: int):
         """New subspace size, keeping the cached factors."""

@@ -352,7 +352,7 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
     } else {
       gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), A, lda, 0, Y, ldY, 0, zc(0.0), T1, ldY, 0, 1);
       gemm_t<z64>(s, 0, n, ldY, n, zc(1.0), B, ldb, 0, Y, ldY, 0, zc(0.0), T2, ldY, 0, 1);
-      feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, sY);
+      feast::shift_residual(s, R, ldr, T1, T2, ldY, p->dz.as<z64>(), N, n, sY, m);
     }
     if (verify) {
       feast::fro2_batched(s, T1, ldY, sY, n, m, N, part, nrm);
@@ -694,7 +694,7 @@ int feast_plan_destroy(feast_plan *p) {
     }
   if (p->ev_cols) (void)hipEventDestroy(p->ev_cols);
   if (p->ev_panel) (void)hipEventDestroy(p->ev_panel);
-  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->R,
+  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->cirr_w, &p->R,
                     &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->dinv, &p->splitws, &p->part, &p->nrm,
                     &p->flag, &p->small})
     b->release();
@@ -976,6 +976,124 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     inf.lu_gemm_flops = p->prof_flops;
     if (info) *info = inf;
     return status;
+  });
+}
+
+// Block_CIRR (Algorithm 1) on the plan's cached factors.  Step 1's node
+// solutions are the filter's solves with right-hand side Y itself (mixed plans
+// apply one FP64 refinement sweep: there is no outer iteration to absorb
+// complex64 solve errors); the moments are weighted node sums; step 2's
+// orthonormal basis of the moment block comes from shifted Cholesky QR3 (the
+// Rayleigh-Ritz pencil depends on the span only, so it has the eigenvalues the
+// SVD's left factor gives); steps 3-5 reuse the projection, host eigensolver
+// and Ritz-residual pieces of Algorithm 5.
+int feast_cirr(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
+               const feast_z *dY, int64_t ldy, int32_t h, int32_t g, feast_z *hLambda,
+               feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, feast_cirr_info *info) {
+  if (!p) return FEAST_EINVAL;
+  if (!dA || !dB || !dY || !hLambda || !dX || !s_found || lda < p->n || ldb < p->n || h < 1 ||
+      g < 1 || ldy < h || ldx < p->m || static_cast<int64_t>(h) * g > p->m)
+    return fail(p, FEAST_EINVAL,
+                "feast_cirr: null pointer, leading dimension too small, or h g > m");
+  p->err.clear();
+  return guarded(p, [&]() -> int {
+    Timer total;
+    const int64_t n = p->n, m = p->m, t = static_cast<int64_t>(h) * g;
+    const int N = p->N;
+    hipStream_t s = p->s;
+    const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
+    const z64 *Y = reinterpret_cast<const z64 *>(dY);
+    int st = ensure_factored(p, A, lda, B, ldb);
+    if (st == FEAST_SINGULAR) return st;
+    z64 *U = p->wblk(feast_plan::W_X), *AU = p->wblk(feast_plan::W_AU1);
+    z64 *BU = p->wblk(feast_plan::W_BU1), *X = p->wblk(feast_plan::W_UF);
+    z64 *AX = p->wblk(feast_plan::W_AX), *BX = p->wblk(feast_plan::W_BX);
+    z64 *Ab = p->gblk(feast_plan::G_AT), *Bb = p->gblk(feast_plan::G_BT);
+    z64 *Ys = p->gblk(feast_plan::G_YS);
+    z64 *dlam = p->small.as<z64>();
+    int32_t *didx = reinterpret_cast<int32_t *>(p->small.as<z64>() + m);
+    // step 1: Y_j = (z_j B - A)^{-1} Y, then R_i = sum_j w_j mu_j^i Y_j, mu_j = (z_j - gamma)/rho
+    if (p->mixed())
+      solve_nodes_mixed(p, A, lda, B, ldb, Y, ldy, 0.0, 1, h);
+    else
+      solve_nodes_z(p, Y, ldy, h);
+    const cd gamma(p->c.center.re, p->c.center.im);
+    std::vector<cd> wi(static_cast<size_t>(g) * N);
+    for (int j = 0; j < N; ++j) {
+      const cd mu = (p->hz[j] - gamma) / p->c.radius;
+      cd pw(1.0);
+      for (int i = 0; i < g; ++i, pw *= mu) wi[static_cast<size_t>(i) * N + j] = p->hw[j] * pw;
+    }
+    p->cirr_w.alloc(sizeof(z64) * wi.size());
+    HIPCHK(hipMemcpyAsync(p->cirr_w.p, wi.data(), sizeof(z64) * wi.size(), hipMemcpyHostToDevice, s));
+    for (int i = 0; i < g; ++i)
+      feast::weighted_sum(s, p->Y.as<z64>(), p->ldY(), m, p->cirr_w.as<z64>() + i * N, N, n, h,
+                          U + static_cast<int64_t>(i) * h, m);
+    // step 2: orthonormal basis of the moment block (in place)
+    feast::fill_i32(s, p->flag.as<int32_t>(), 3, 0);
+    orth(p, U, m, 0, t);
+    // step 3: A~ = U^* A U, B~ = U^* B U
+    gemm_t<z64>(s, 0, n, t, n, zc(1.0), A, lda, 0, U, m, 0, zc(0.0), AU, m, 0, 1);
+    gemm_t<z64>(s, 0, n, t, n, zc(1.0), B, ldb, 0, U, m, 0, zc(0.0), BU, m, 0, 1);
+    gemm_t<z64>(s, 2, t, t, n, zc(1.0), U, m, 0, AU, m, 0, zc(0.0), Ab, t, 0, 1,
+                p->splitws.as<z64>(), splitws_elems(p));
+    gemm_t<z64>(s, 2, t, t, n, zc(1.0), U, m, 0, BU, m, 0, zc(0.0), Bb, t, 0, 1,
+                p->splitws.as<z64>(), splitws_elems(p));
+    const int64_t tt = t * t;
+    std::vector<feast_z> hA(tt), hB(tt), hYv(tt), hal(t), hbe(t);
+    int32_t hf[3];
+    HIPCHK(hipMemcpyAsync(hA.data(), Ab, sizeof(z64) * tt, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hB.data(), Bb, sizeof(z64) * tt, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hf, p->flag.p, sizeof hf, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hf[0] || hf[1] || hf[2])
+      return fail(p, FEAST_ENUMERIC, "feast_cirr: Cholesky QR of the moment block broke down");
+    // step 4
+    if (feast_reduced_eig(t, hA.data(), t, hB.data(), t, hal.data(), hbe.data(), hYv.data(), t) !=
+        FEAST_OK)
+      return fail(p, FEAST_ENUMERIC, "feast_cirr: reduced eigensolver did not converge");
+    std::vector<cd> lam(t);
+    std::vector<feast_z> hlam(t);
+    for (int64_t i = 0; i < t; ++i) {
+      const cd a(hal[i].re, hal[i].im), b(hbe[i].re, hbe[i].im);
+      lam[i] = (b != cd(0.0)) ? a / b : cd(INFINITY, 0.0);
+      hlam[i] = std::isfinite(lam[i].real()) ? feast_z{lam[i].real(), lam[i].imag()} : feast_z{0, 0};
+    }
+    // step 5: x_i = U y_i, residuals (eq. 5-1) from (A U) y_i and (B U) y_i, selection
+    HIPCHK(hipMemcpyAsync(Ys, hYv.data(), sizeof(z64) * tt, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dlam, hlam.data(), sizeof(z64) * t, hipMemcpyHostToDevice, s));
+    gemm_t<z64>(s, 0, n, t, t, zc(1.0), U, m, 0, Ys, t, 0, zc(0.0), X, m, 0, 1);
+    gemm_t<z64>(s, 0, n, t, t, zc(1.0), AU, m, 0, Ys, t, 0, zc(0.0), AX, m, 0, 1);
+    gemm_t<z64>(s, 0, n, t, t, zc(1.0), BU, m, 0, Ys, t, 0, zc(0.0), BX, m, 0, 1);
+    double *dnorm = p->nrm.as<double>();
+    std::vector<double> hn(3 * t);
+    feast::ritz_norms(s, AX, BX, m, n, t, dlam, p->part.as<double>(), dnorm);
+    HIPCHK(hipMemcpyAsync(hn.data(), dnorm, sizeof(double) * 3 * t, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double rho = p->c.radius;
+    std::vector<int32_t> sel;
+    for (int64_t i = 0; i < t; ++i) {
+      if (!std::isfinite(lam[i].real()) || !std::isfinite(lam[i].imag())) continue;
+      const double den = std::sqrt(hn[3 * i + 1]) + std::sqrt(hn[3 * i + 2]);
+      const double r = den > 0.0 ? std::sqrt(hn[3 * i]) / den : INFINITY;
+      if (std::abs(lam[i] - gamma) < rho && r < p->o.eta) {
+        hLambda[sel.size()] = hlam[i];
+        if (hRes) hRes[sel.size()] = r;
+        sel.push_back(static_cast<int32_t>(i));
+      }
+    }
+    const int32_t c = static_cast<int32_t>(sel.size());
+    if (c > 0) {
+      HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c, hipMemcpyHostToDevice, s));
+      feast::gather_normalize_cols(s, X, m, n, didx, c, reinterpret_cast<z64 *>(dX), ldx, nullptr);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    *s_found = c;
+    if (info) {
+      info->t = t;
+      info->ms = total.ms();
+    }
+    return FEAST_OK;
   });
 }
 

@@ -40,15 +40,18 @@ __global__ __launch_bounds__(256) void k_gather_rows(const T *__restrict__ R, in
     Y[b * sY + row * ldy + c] = R[b * sR + src * ldr + c];
 }
 
+// T1 = R - z_j T2 + T1 on the used columns c < used of every node block j
+// (node blocks m columns apart; R is shared, n x used).
 __global__ __launch_bounds__(256) void k_shift_residual(const z64 *__restrict__ R, int64_t ldr,
                                                         z64 *__restrict__ T1,
                                                         const z64 *__restrict__ T2, int64_t ldt,
                                                         const z64 *__restrict__ z, int64_t n,
-                                                        int64_t m, int64_t cols) {
+                                                        int64_t m, int64_t used, int32_t N) {
   const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t cols = static_cast<int64_t>(N) * used;
   if (idx >= n * cols) return;
-  const int64_t row = idx / cols, col = idx % cols;
-  const int64_t j = col / m, c = col % m;
+  const int64_t row = idx / cols, k = idx % cols;
+  const int64_t j = k / used, c = k % used, col = j * m + c;
   const z64 zj = z[j], r = R[row * ldr + c], t2 = T2[row * ldt + col];
   z64 &t1 = T1[row * ldt + col];
   t1.x = r.x - (zj.x * t2.x - zj.y * t2.y) + t1.x;
@@ -649,11 +652,12 @@ template void pad_diag<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64
 template void pad_diag<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int64_t);
 
 void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64 *T2, int64_t ldt,
-                    const z64 *z, int32_t N, int64_t n, int64_t m) {
-  const int64_t cols = static_cast<int64_t>(N) * m;
-  const int64_t tot = n * cols;
+                    const z64 *z, int32_t N, int64_t n, int64_t m, int64_t used) {
+  if (used < 0) used = m;
+  const int64_t tot = n * static_cast<int64_t>(N) * used;
+  if (tot <= 0) return;
   hipLaunchKernelGGL(k_shift_residual, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0,
-                     s, R, ldr, T1, T2, ldt, z, n, m, cols);
+                     s, R, ldr, T1, T2, ldt, z, n, m, used, N);
 }
 
 void c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,

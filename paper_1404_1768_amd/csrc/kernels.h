@@ -182,9 +182,11 @@ void z_to_c(hipStream_t s, const z64 *X, int64_t ldx, int64_t sX, int64_t n, int
 void c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
             int32_t batch, z64 *Y, int64_t ldy, int64_t sY);
 // Refinement residual of all nodes in the n x (N m) layout:
-// T1[:, j m + c] <- R[:, c] - z_j T2[:, j m + c] + T1[:, j m + c]   (T1 = A Y, T2 = B Y).
+// T1[:, j m + c] <- R[:, c] - z_j T2[:, j m + c] + T1[:, j m + c]   (T1 = A Y, T2 = B Y)
+// for the used columns c < used (default m) of every node block.
 void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64 *T2,
-                    int64_t ldt, const z64 *z, int32_t N, int64_t n, int64_t m);
+                    int64_t ldt, const z64 *z, int32_t N, int64_t n, int64_t m,
+                    int64_t used = -1);
 // Y += X (complex64 correction into FP64 solution), per batch.
 void add_c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
                 int32_t batch, z64 *Y, int64_t ldy, int64_t sY);

@@ -91,6 +91,7 @@ struct feast_plan {
   // workspaces
   DevBuf R, Y, T1, T2, Yc, W, G, dinv, splitws, part, nrm, flag, small;
   DevBuf adj, adj_piv, adj_info, adj_inv;  // adjoint solves (allocated on first use)
+  DevBuf cirr_w;                           // Block_CIRR moment weights (g x N)
   std::string err;
   int last_sweeps = 0;       // mixed form: sweeps of the last filter
   double last_be = 0.0;      // mixed form: worst node backward error of the last filter

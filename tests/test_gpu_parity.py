@@ -88,6 +88,21 @@ def test_filter_mixed_refined_matches_oracle():
     assert np.max(np.abs(U - ref)) <= 1e-10 * np.abs(ref).max()
 
 
+def test_filter_mixed_refined_with_unequal_leading_dimensions():
+    # A stored with a wider leading dimension than B: the refinement residual
+    # takes the two-product path instead of the shifted-operand GEMM
+    p = pg.workload(1, n_override=300)
+    Apad = np.zeros((p.n, p.n + 24), dtype=np.complex128)
+    Apad[:, :p.n] = p.A
+    tA = torch.from_numpy(Apad).to(DEV)[:, :p.n]
+    tB, tV = to_dev(p.B, p.V)
+    with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=fm.MIXED, max_sweeps=4) as plan:
+        U = plan.filter(tA, tB, tV).cpu().numpy()
+    z, w = o.contour_nodes(p.center, p.radius, p.nodes)
+    ref = o.apply_filter(o.ShiftedSolver(p.A, p.B, z), w, p.V)
+    assert np.max(np.abs(U - ref)) <= 1e-10 * np.abs(ref).max()
+
+
 def test_filter_singular_node_reported():
     # an eigenvalue placed exactly on a quadrature node makes z_j B - A singular
     n = 12
