@@ -18,8 +18,13 @@ bounded sample of the same workload on this host, and (key "batched") the
 batched form on its own workload: 64 independent pencils of order n in
 [256, 2048] (seeded), floor(n/20) eigenvalues inside each pencil's unit
 circle, N = 16 nodes, m = 2 floor(n/20), solved together in both forms.
+Further keys time the other rows on their own workloads: "search" (Algorithm 4
+then Algorithm 5 on the metric's pencil), "cirr" (Block_CIRR, Algorithm 1, on
+the same pencil) and "standin" (dense stand-ins of the two largest problems of
+Table 1 with the Gauss-Legendre rule).
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--forms fp64,mixed] [--no-batched]
+                    [--no-search] [--no-cirr] [--no-standin] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -169,6 +174,51 @@ def time_cirr(p, A, B, V, steps, warmup):
         plan.close()
 
 
+def time_standin(ks, steps, warmup):
+    """Sparse-shaped stand-ins of Table 1 held dense (same orders, numbers of
+    non-zeros and structure, random values): Algorithm 5 with the
+    Gauss-Legendre rule, 16 nodes and m = 40, on the stored circle around about
+    20 reference eigenvalues.  One step = one complete solve, factorisations
+    included; the count is checked against the stored reference count."""
+    import numpy as np
+    import torch
+    import pencilgen as pg
+    import paper_1404_1768_amd as fm
+    with open(os.path.join(ROOT, "tests", "golden", "standin_contours.json")) as f:
+        golden = json.load(f)
+    out = {}
+    for k in ks:
+        g = golden[str(k)]
+        name, A, B, V = pg.sparse_standin(k)
+        dA, dB, dV = (torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0") for x in (A, B, V))
+        del A, B
+        c = complex(*g["center"])
+        row = {"n": g["n"], "s_ref": g["s"]}
+        for form, prec in (("fp64", fm.FP64), ("mixed", fm.MIXED)):
+            plan = fm.Plan(g["n"], 40, c, g["radius"], 16, rule=fm.GAUSS_LEGENDRE, eps=1e-10,
+                           prec=prec)
+            try:
+                for _ in range(warmup):
+                    plan.invalidate()
+                    plan.solve(dA, dB, dV)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    plan.invalidate()
+                    r = plan.solve(dA, dB, dV)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / steps
+            finally:
+                plan.close()
+            row[form] = {"ms": ms, "iters": r.iters, "count": len(r.lam), "err": r.err,
+                         "ok": r.flag == 1 and r.err <= 1e-10 and len(r.lam) == g["s"]}
+        log("[bench] stand-in %s: %s" % (name, row))
+        out[name] = row
+        del dA, dB, dV
+    return {"workload": "Table 1 stand-ins (dense), Gauss-Legendre N=16, m=40, eps=1e-10",
+            "problems": out}
+
+
 def time_batch(ps, As, Bs, Vs, steps, warmup):
     """Workload of 64 pencils: one step = a complete batched solve of every
     pencil (factorisations of all 1024 shifted matrices included)."""
@@ -260,6 +310,8 @@ def main():
                     help="skip the Block_CIRR (Algorithm 1) comparison leg (key 'cirr')")
     ap.add_argument("--no-search", action="store_true",
                     help="skip the Search (Algorithm 4) + Algorithm 5 leg (key 'search')")
+    ap.add_argument("--no-standin", action="store_true",
+                    help="skip the Table 1 stand-in leg (key 'standin')")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 1 GiB (3 launches): the reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a PMC run")
@@ -321,6 +373,9 @@ def main():
     cirr = None
     if not args.no_cirr:
         cirr = time_cirr(p, A, B, V, min(args.steps, 3), 1)
+    standin = None
+    if not args.no_standin:
+        standin = time_standin((6, 7), min(args.steps, 2), 1)
     large = None
     if args.large:
         pl = pg.workload(3)
@@ -341,7 +396,7 @@ def main():
         "config": {"workload": "pencil n=4000 N=32 m=160 s=100 (trapezoid, circle 1+1i r=1)",
                    "form": best, "n": p.n, "nodes": p.nodes, "m": p.m, "eps": 1e-10},
         "forms": forms, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
-        "search": search, "cirr": cirr, "large": large,
+        "search": search, "cirr": cirr, "standin": standin, "large": large,
     }
     print(json.dumps(out), flush=True)
 

@@ -407,28 +407,10 @@ int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t l
 }
 
 // Cholesky G = R^* R of a t x t Hermitian matrix (upper triangle used, R
-// written over it), blocked by 64 columns: LDS Cholesky of the diagonal block,
-// R_J,rest = R_JJ^{-*} G_J,rest and G_rest -= R_J,rest^* R_J,rest as MFMA GEMMs.
-void chol_blocked(feast_plan *p, z64 *G, int64_t t, double shift_rel, int32_t *flag) {
-  hipStream_t s = p->s;
-  z64 *Dinv = p->dinv.as<z64>();
-  if (shift_rel > 0.0) feast::add_diag_shift(s, G, t, shift_rel);
-  for (int64_t J0 = 0; J0 < t; J0 += 64) {
-    const int jb = static_cast<int>(std::min<int64_t>(64, t - J0));
-    z64 *GJ = G + J0 * t + J0;
-    feast::chol_block(s, GJ, t, jb, static_cast<int>(J0), flag);
-    const int64_t rest = t - J0 - jb;
-    if (rest <= 0) break;
-    feast::diag_block_inverse<z64>(s, GJ, t, 0, 1, jb, 64, 0, 1, false, Dinv, 0);
-    gemm_t<z64>(s, 2, jb, rest, jb, zc(1.0), Dinv, 64, 0, GJ + jb, t, 0, zc(0.0), GJ + jb, t, 0, 1);
-    gemm_t<z64>(s, 2, rest, rest, jb, zc(-1.0), GJ + jb, t, 0, GJ + jb, t, 0, zc(1.0),
-                G + (J0 + jb) * t + J0 + jb, t, 0, 1);
-  }
-  feast::zero_lower(s, G, t, false);
-}
-
-// X = R^{-1} for the t x t upper-triangular R (leading dimension t): inverted
-// 64 x 64 diagonal blocks, then X12 = -X11 R12 X22 by recursive halving.
+// written over it) and X = R^{-1}, blocked by 64 columns: one kernel factors a
+// diagonal block and inverts it (the inverse goes to X's diagonal block), then
+// R_J,rest = R_JJ^{-*} G_J,rest and G_rest -= R_J,rest^* R_J,rest as MFMA GEMMs;
+// X's off-diagonal blocks follow by X12 = -X11 R12 X22, halving recursively.
 void inv_upper_rec(hipStream_t s, const z64 *R, int64_t t, z64 *X, z64 *T, int64_t r0, int64_t r1) {
   if (r1 - r0 <= 64) return;
   const int64_t mid = r0 + ((r1 - r0 + 127) / 128) * 64;
@@ -440,17 +422,25 @@ void inv_upper_rec(hipStream_t s, const z64 *R, int64_t t, z64 *X, z64 *T, int64
               X + r0 * t + mid, t, 0, 1);
 }
 
-void inv_upper_blocked(feast_plan *p, const z64 *R, int64_t t, z64 *X, z64 *T) {
+void chol_inv_blocked(feast_plan *p, z64 *G, int64_t t, double shift_rel, int32_t *flag, z64 *X,
+                      z64 *T) {
   hipStream_t s = p->s;
-  z64 *Dinv = p->dinv.as<z64>();
-  const int64_t nblk = (t + 63) / 64;
-  feast::zero_lower(s, X, t, true);
-  feast::diag_block_inverse<z64>(s, R, t, 0, 1, t, 64, 0, nblk, false, Dinv, 0);
-  for (int64_t I = 0; I < nblk; ++I) {
-    const int64_t rb = std::min<int64_t>(64, t - I * 64);
-    feast::copy_block_z(s, Dinv + I * 64 * 64, 64, rb, rb, X + I * 64 * t + I * 64, t);
+  if (shift_rel > 0.0) feast::add_diag_shift(s, G, t, shift_rel);
+  for (int64_t J0 = 0; J0 < t; J0 += 64) {
+    const int jb = static_cast<int>(std::min<int64_t>(64, t - J0));
+    z64 *GJ = G + J0 * t + J0, *XJ = X + J0 * t + J0;
+    feast::chol_inv_block(s, GJ, t, jb, static_cast<int>(J0), flag, XJ, t);
+    const int64_t rest = t - J0 - jb;
+    if (rest <= 0) break;
+    gemm_t<z64>(s, 2, jb, rest, jb, zc(1.0), XJ, t, 0, GJ + jb, t, 0, zc(0.0), GJ + jb, t, 0, 1);
+    gemm_t<z64>(s, 2, rest, rest, jb, zc(-1.0), GJ + jb, t, 0, GJ + jb, t, 0, zc(1.0),
+                G + (J0 + jb) * t + J0 + jb, t, 0, 1);
   }
-  inv_upper_rec(s, R, t, X, T, 0, t);
+  if (t > 64) {
+    feast::zero_lower(s, G, t, false);
+    feast::zero_lower(s, X, t, false);
+    inv_upper_rec(s, G, t, X, T, 0, t);
+  }
 }
 
 // Shifted Cholesky QR3 (three Cholesky QR passes, the first on X^*X + s I with
@@ -489,7 +479,6 @@ void ensure_workspace(feast_plan *p, bool with_nodes) {
   if (with_nodes) p->Y.alloc(zs * n * m * N);
   p->W.alloc(zs * n * m * feast_plan::W_COUNT);
   p->G.alloc(zs * m * m * feast_plan::G_COUNT);
-  p->dinv.alloc(zs * ((m + 63) / 64) * 64 * 64);
   p->splitws.alloc(zs * std::max<int64_t>(m * m * 96, 1 << 16));
   p->part.alloc(sizeof(double) * std::max<int64_t>(((n + 63) / 64) * 3 * m, 64 * N + 64));
   p->nrm.alloc(sizeof(double) * (3 * m + 4 * N + 16));
@@ -518,8 +507,7 @@ void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot, int64_t cols) {
   for (int pass = 0; pass < 3; ++pass) {
     gemm_t<z64>(s, 2, m, m, n, zc(1.0), X, ldx, 0, X, ldx, 0, zc(0.0), G, m, 0, 1,
                 p->splitws.as<z64>(), splitws_elems(p));
-    chol_blocked(p, G, m, pass == 0 ? shift_rel : 0.0, flag + pass);
-    inv_upper_blocked(p, G, m, Ri, T);
+    chol_inv_blocked(p, G, m, pass == 0 ? shift_rel : 0.0, flag + pass, Ri, T);
     gemm_t<z64>(s, 0, n, m, m, zc(1.0), X, ldx, 0, Ri, m, 0, zc(0.0), Wt, m, 0, 1);
     feast::copy_block_z(s, Wt, m, n, m, X, ldx);
   }
@@ -532,11 +520,18 @@ void project_device(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int6
   hipStream_t s = p->s;
   feast::fill_i32(s, p->flag.as<int32_t>(), 6, 0);
   orth(p, U, ldu, 0);
+  // A U_1 runs on the side stream beside B U_1 and the orthonormalisation of
+  // B U_1: one n x m product alone fills only (n/64)(m/64) workgroups, and the
+  // Cholesky QR chain leaves most compute units idle
+  HIPCHK(hipEventRecord(p->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+  gemm_t<z64>(p->side, 0, n, m, n, zc(1.0), A, lda, 0, U, ldu, 0, zc(0.0), AU1, ldau, 0, 1);
+  HIPCHK(hipEventRecord(p->ev_join, p->side));
   gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, U, ldu, 0, zc(0.0), BU1, ldbu, 0, 1);
-  gemm_t<z64>(s, 0, n, m, n, zc(1.0), A, lda, 0, U, ldu, 0, zc(0.0), AU1, ldau, 0, 1);
   z64 *U2 = p->wblk(feast_plan::W_U2);
   feast::copy_block_z(s, BU1, ldbu, n, m, U2, m);
   orth(p, U2, m, 3);
+  HIPCHK(hipStreamWaitEvent(s, p->ev_join, 0));
   gemm_t<z64>(s, 2, m, m, n, zc(1.0), U2, m, 0, AU1, ldau, 0, zc(0.0), p->gblk(feast_plan::G_AT),
               m, 0, 1, p->splitws.as<z64>(), splitws_elems(p));
   gemm_t<z64>(s, 2, m, m, n, zc(1.0), U2, m, 0, BU1, ldbu, 0, zc(0.0), p->gblk(feast_plan::G_BT),
@@ -673,6 +668,8 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
     HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
     return FEAST_OK;
   });
   if (rc != FEAST_OK) {
@@ -694,8 +691,10 @@ int feast_plan_destroy(feast_plan *p) {
     }
   if (p->ev_cols) (void)hipEventDestroy(p->ev_cols);
   if (p->ev_panel) (void)hipEventDestroy(p->ev_panel);
+  for (hipEvent_t e : {p->ev_fork, p->ev_join})
+    if (e) (void)hipEventDestroy(e);
   for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->cirr_w, &p->R,
-                    &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->dinv, &p->splitws, &p->part, &p->nrm,
+                    &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->part, &p->nrm,
                     &p->flag, &p->small})
     b->release();
   delete p;

@@ -211,95 +211,6 @@ __global__ __launch_bounds__(256) void k_fro_part(const z64 *__restrict__ X, int
   if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = red[0];
 }
 
-// Right-looking Cholesky of a t x t Hermitian matrix in global memory by one
-// workgroup; only the upper triangle is read and R overwrites it.
-__global__ __launch_bounds__(1024) void k_cholesky(z64 *__restrict__ G, int64_t t, double shift,
-                                                   int32_t *__restrict__ flag) {
-  __shared__ double s_d;
-  __shared__ int s_bad;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    s_bad = 0;
-    double tr = 0.0;
-    for (int64_t i = 0; i < t; ++i) tr += G[i * t + i].x;
-    s_d = shift * tr;
-  }
-  __syncthreads();
-  const double sh = s_d;
-  for (int64_t i = tid; i < t; i += 1024) G[i * t + i].x += sh;
-  __syncthreads();
-  for (int64_t k = 0; k < t; ++k) {
-    if (tid == 0) {
-      const double d = G[k * t + k].x;
-      if (!(d > 0.0)) {
-        if (s_bad == 0) s_bad = static_cast<int>(k) + 1;
-        s_d = 0.0;
-      } else {
-        s_d = sqrt(d);
-      }
-    }
-    __syncthreads();
-    const double dk = s_d;
-    if (dk == 0.0) break;
-    // row k of R
-    for (int64_t j = k + tid; j < t; j += 1024) {
-      z64 v = G[k * t + j];
-      if (j == k) {
-        v = make_double2(dk, 0.0);
-      } else {
-        v.x /= dk;
-        v.y /= dk;
-      }
-      G[k * t + j] = v;
-    }
-    __syncthreads();
-    // trailing update of the upper triangle: G_ij -= conj(R_ki) R_kj, k < i <= j
-    const int64_t m = t - k - 1;
-    for (int64_t e = tid; e < m * m; e += 1024) {
-      const int64_t i = e / m, j = e % m;
-      if (j < i) continue;
-      const int64_t ii = k + 1 + i, jj = k + 1 + j;
-      const z64 rki = G[k * t + ii], rkj = G[k * t + jj];
-      z64 &g = G[ii * t + jj];
-      g.x -= rki.x * rkj.x + rki.y * rkj.y;
-      g.y -= rki.x * rkj.y - rki.y * rkj.x;
-    }
-    __syncthreads();
-  }
-  // zero the strict lower triangle
-  for (int64_t e = tid; e < t * t; e += 1024) {
-    const int64_t i = e / t, j = e % t;
-    if (j < i) G[e] = make_double2(0.0, 0.0);
-  }
-  if (tid == 0) flag[0] = s_bad;
-}
-
-// In-place inverse of a t x t upper-triangular matrix by one workgroup: one
-// thread per column j solves R x = e_j upwards; columns are independent, so the
-// result is written to a scratch half (the strict lower part is used as no
-// storage here: X is accumulated in place column by column from the bottom).
-__global__ __launch_bounds__(1024) void k_trinv_upper(z64 *__restrict__ R, int64_t t,
-                                                      z64 *__restrict__ X) {
-  for (int64_t j = threadIdx.x; j < t; j += 1024) {
-    const z64 djj = R[j * t + j];
-    const double d = djj.x * djj.x + djj.y * djj.y;
-    X[j * t + j] = make_double2(djj.x / d, -djj.y / d);
-    for (int64_t i = j - 1; i >= 0; --i) {
-      double sr = 0.0, si = 0.0;
-      for (int64_t k = i + 1; k <= j; ++k) {
-        const z64 a = R[i * t + k], x = X[k * t + j];
-        sr += a.x * x.x - a.y * x.y;
-        si += a.x * x.y + a.y * x.x;
-      }
-      const z64 dii = R[i * t + i];
-      const double q = dii.x * dii.x + dii.y * dii.y;
-      // x_ij = -s / d_ii
-      X[i * t + j] = make_double2(-(sr * dii.x + si * dii.y) / q, -(si * dii.x - sr * dii.y) / q);
-    }
-    for (int64_t i = j + 1; i < t; ++i) X[i * t + j] = make_double2(0.0, 0.0);
-  }
-}
-
 // A += shift_rel * trace(A) on the diagonal (t x t, one workgroup).
 __global__ __launch_bounds__(256) void k_add_shift(z64 *__restrict__ G, int64_t t, double shift_rel) {
   __shared__ double red[256];
@@ -315,50 +226,142 @@ __global__ __launch_bounds__(256) void k_add_shift(z64 *__restrict__ G, int64_t 
   for (int64_t i = threadIdx.x; i < t; i += 256) G[i * t + i].x += sh;
 }
 
-// Cholesky of one jb x jb (jb <= 64) Hermitian diagonal block held in LDS:
-// upper triangle in, R (upper) out, strict lower part of the block zeroed.
-__global__ __launch_bounds__(256) void k_chol_block(z64 *__restrict__ G, int64_t ld, int jb,
-                                                    int col0, int32_t *__restrict__ flag) {
-  __shared__ z64 S[64][65];
-  __shared__ double s_d;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int i = e / jb, j = e % jb;
-    S[i][j] = G[i * ld + j];
-  }
+// Cholesky of one jb x jb (jb <= 64) Hermitian diagonal block and the inverse
+// of its factor, by one workgroup of 256 threads.  The upper triangle of the
+// block is read; R (upper) is written over it with the strict lower part
+// zeroed, and R^{-1} (jb x jb, upper) to Rinv (leading dimension ldi).
+// Thread (ti, tj) holds the 16 entries (ti + 16a, tj + 16b), a, b < 4, in
+// registers.  Cholesky step k subtracts conj(G_ki) G_kj / G_kk from every
+// entry with k < i <= j (G_k. is the pivot row, read-only during the step);
+// the inverse runs the same way from the bottom, X_i. = B_i. / R_ii and
+// B_r. -= R_ri X_i. for r < i with B = I at the start.  Each step passes
+// one row through LDS (double-buffered), so it needs one barrier.
+// flag[0] = 1 + col0 + k for the first non-positive pivot k (a unit pivot is
+// used in its place so the kernel finishes).
+__global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t ld, int jb,
+                                                  int col0, int32_t *__restrict__ flag,
+                                                  z64 *__restrict__ Rinv, int64_t ldi) {
+  __shared__ z64 row[2][64];
+  __shared__ z64 Rs[64][65];
+  __shared__ double dg[64];
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  z64 v[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      v[a][b] = (i <= j && j < jb) ? G[i * ld + j] : make_double2(0.0, 0.0);
+    }
+  if (ti == 0)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) row[0][tj + 16 * b] = v[0][b];
   __syncthreads();
   for (int k = 0; k < jb; ++k) {
-    if (tid == 0) {
-      const double d = S[k][k].x;
-      if (!(d > 0.0)) {
-        if (flag[0] == 0) flag[0] = col0 + k + 1;
-        s_d = 1.0;  // keep going with a unit pivot; the caller reports the failure
-      } else {
-        s_d = sqrt(d);
+    const z64 *rk = row[k & 1];
+    double d = rk[k].x;
+    if (!(d > 0.0)) {
+      if (tid == 0 && flag[0] == 0) flag[0] = col0 + k + 1;
+      d = 1.0;
+    }
+    if (tid == 0) dg[k] = d;
+    const double rd = 1.0 / d;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = ti + 16 * a;
+      if (i <= k || i >= jb) continue;
+      const z64 q = rk[i];
+      const double qr = q.x * rd, qi = -q.y * rd;  // conj(G_ki) / G_kk
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = tj + 16 * b;
+        if (j < i || j >= jb) continue;
+        const z64 w = rk[j];
+        v[a][b].x -= qr * w.x - qi * w.y;
+        v[a][b].y -= qr * w.y + qi * w.x;
       }
-      S[k][k] = make_double2(s_d, 0.0);
     }
-    __syncthreads();
-    const double d = s_d;
-    for (int j = k + 1 + tid; j < jb; j += 256) {
-      S[k][j].x /= d;
-      S[k][j].y /= d;
-    }
-    __syncthreads();
-    const int m = jb - k - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j < i) continue;
-      const z64 a = S[k][i], b = S[k][j];
-      S[i][j].x -= a.x * b.x + a.y * b.y;
-      S[i][j].y -= a.x * b.y - a.y * b.x;
+    const int nk = k + 1;
+    if (nk < jb && ti == (nk & 15)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == (nk >> 4))
+#pragma unroll
+          for (int b = 0; b < 4; ++b) row[nk & 1][tj + 16 * b] = v[a][b];
     }
     __syncthreads();
   }
-  for (int e = tid; e < jb * jb; e += 256) {
-    const int i = e / jb, j = e % jb;
-    G[i * ld + j] = (j >= i) ? S[i][j] : make_double2(0.0, 0.0);
+  // R_ij = G_ij / sqrt(d_i) for i <= j (row i stops changing after step i - 1)
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = ti + 16 * a;
+    const double sq = (i < jb) ? sqrt(dg[i]) : 1.0, sc = 1.0 / sq;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = tj + 16 * b;
+      z64 r = (i <= j && j < jb) ? make_double2(v[a][b].x * sc, v[a][b].y * sc)
+                                 : make_double2(0.0, 0.0);
+      if (i == j && i < jb) r = make_double2(sq, 0.0);
+      Rs[i][j] = r;
+      if (i < jb && j < jb) G[i * ld + j] = r;
+      v[a][b] = make_double2(i == j && i < jb ? 1.0 : 0.0, 0.0);
+    }
   }
+  __syncthreads();
+  // X = R^{-1}: the owners of row jb - 1 start the chain
+  if (ti == ((jb - 1) & 15)) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (a == ((jb - 1) >> 4)) {
+        const double rii = 1.0 / Rs[jb - 1][jb - 1].x;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          v[a][b].x *= rii;
+          v[a][b].y *= rii;
+          row[(jb - 1) & 1][tj + 16 * b] = v[a][b];
+        }
+      }
+  }
+  __syncthreads();
+  for (int i = jb - 1; i > 0; --i) {
+    const z64 *xi = row[i & 1];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = ti + 16 * a;
+      if (r >= i) continue;
+      const z64 q = Rs[r][i];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = tj + 16 * b;
+        if (j < i || j >= jb) continue;
+        const z64 w = xi[j];
+        v[a][b].x -= q.x * w.x - q.y * w.y;
+        v[a][b].y -= q.x * w.y + q.y * w.x;
+      }
+    }
+    const int ni = i - 1;
+    if (ti == (ni & 15)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == (ni >> 4)) {
+          const double rii = 1.0 / Rs[ni][ni].x;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            v[a][b].x *= rii;
+            v[a][b].y *= rii;
+            row[ni & 1][tj + 16 * b] = v[a][b];
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (i < jb && j < jb) Rinv[i * ldi + j] = (i <= j) ? v[a][b] : make_double2(0.0, 0.0);
+    }
 }
 
 // Strict lower triangle of a t x t matrix set to zero; optionally the whole matrix.
@@ -367,12 +370,6 @@ __global__ __launch_bounds__(256) void k_zero_lower(z64 *__restrict__ X, int64_t
   if (e >= t * t) return;
   const int64_t i = e / t, j = e % t;
   if (all || j < i) X[e] = make_double2(0.0, 0.0);
-}
-
-__global__ __launch_bounds__(256) void k_copy_t(const z64 *__restrict__ X, z64 *__restrict__ R,
-                                                int64_t count) {
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
-  if (i < count) R[i] = X[i];
 }
 
 // Column gather + normalisation: block per selected column.
@@ -731,28 +728,18 @@ void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n
                      part, static_cast<int64_t>(blocks), static_cast<int64_t>(batch), out);
 }
 
-void cholesky_upper(hipStream_t s, z64 *G, int64_t t, double shift, int32_t *flag) {
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, G, t, shift, flag);
-}
-
 void add_diag_shift(hipStream_t s, z64 *G, int64_t t, double shift_rel) {
   hipLaunchKernelGGL(k_add_shift, dim3(1), dim3(256), 0, s, G, t, shift_rel);
 }
 
-void chol_block(hipStream_t s, z64 *G, int64_t ld, int jb, int col0, int32_t *flag) {
-  hipLaunchKernelGGL(k_chol_block, dim3(1), dim3(256), 0, s, G, ld, jb, col0, flag);
+void chol_inv_block(hipStream_t s, z64 *G, int64_t ld, int jb, int col0, int32_t *flag, z64 *Rinv,
+                    int64_t ldi) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, G, ld, jb, col0, flag, Rinv, ldi);
 }
 
 void zero_lower(hipStream_t s, z64 *X, int64_t t, bool all) {
   hipLaunchKernelGGL(k_zero_lower, dim3(static_cast<unsigned>((t * t + 255) / 256)), dim3(256), 0,
                      s, X, t, all ? 1 : 0);
-}
-
-void trinv_upper(hipStream_t s, z64 *R, int64_t t) {
-  // needs t*t scratch: use the second half of a 2*t*t buffer provided by the caller
-  hipLaunchKernelGGL(k_trinv_upper, dim3(1), dim3(1024), 0, s, R, t, R + t * t);
-  hipLaunchKernelGGL(k_copy_t, dim3(static_cast<unsigned>((t * t + 255) / 256)), dim3(256), 0, s,
-                     R + t * t, R, t * t);
 }
 
 void gather_normalize_cols(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, const int32_t *idx,

@@ -206,19 +206,14 @@ void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, d
 void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
                   int32_t batch, double *part, double *out);
 
-// Cholesky of the t x t Hermitian G (row-major, upper triangle used) after
-// adding shift_rel * trace(G) to the diagonal: G = R^* R, R upper triangular
-// stored in G (strict lower part zeroed).  flag[0] = 0 ok, or 1 + the failing column.
-void cholesky_upper(hipStream_t s, z64 *G, int64_t t, double shift_rel, int32_t *flag);
-// Inverse of the t x t upper-triangular R in place; R must hold 2 t^2 entries
-// (the second half is scratch).
-void trinv_upper(hipStream_t s, z64 *R, int64_t t);
 // Blocked pieces: diagonal += shift_rel * trace; Cholesky of one jb x jb (<= 64)
-// diagonal block inside a matrix of leading dimension ld (flag[0] = 1 + the first
-// non-positive pivot column, numbered from col0); zero the strict lower triangle
-// (or everything) of a t x t matrix.
+// diagonal block inside a matrix of leading dimension ld, R written over it
+// (strict lower part zeroed) and R^{-1} (jb x jb) to Rinv with leading
+// dimension ldi (flag[0] = 1 + the first non-positive pivot column, numbered
+// from col0); zero the strict lower triangle (or everything) of a t x t matrix.
 void add_diag_shift(hipStream_t s, z64 *G, int64_t t, double shift_rel);
-void chol_block(hipStream_t s, z64 *G, int64_t ld, int jb, int col0, int32_t *flag);
+void chol_inv_block(hipStream_t s, z64 *G, int64_t ld, int jb, int col0, int32_t *flag, z64 *Rinv,
+                    int64_t ldi);
 void zero_lower(hipStream_t s, z64 *X, int64_t t, bool all);
 
 // Gather columns idx[0..k) of the n x t block X into Y (n x k) and normalise each

@@ -89,7 +89,7 @@ struct feast_plan {
   DevBuf Linv2, Uinv2;  // inverted 128 x 128 diagonal blocks (the solves' leaves)
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
-  DevBuf R, Y, T1, T2, Yc, W, G, dinv, splitws, part, nrm, flag, small;
+  DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
   DevBuf adj, adj_piv, adj_info, adj_inv;  // adjoint solves (allocated on first use)
   DevBuf cirr_w;                           // Block_CIRR moment weights (g x N)
   std::string err;
@@ -101,6 +101,7 @@ struct feast_plan {
   hipStream_t side = nullptr;                 // look-ahead panel stream
   hipStream_t aux = nullptr;                  // Ritz vectors/residuals overlapping a filter
   hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // A U_1 on the side stream in the projection
   int prof_launches = 0;
   double prof_ms = 0.0, prof_flops = 0.0;
 
