@@ -371,6 +371,36 @@ def block_cirr(A: np.ndarray, B: np.ndarray, Y: np.ndarray, g: int, center: comp
 
 
 # ---------------------------------------------------------------------------
+# Reference spectrum and contours for the sparse-shaped stand-ins (Table 1)
+# ---------------------------------------------------------------------------
+
+def dense_eigenvalues(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """All finite eigenvalues of the pencil by the dense QZ (LAPACK ``xGGEV``),
+    the reference the paper's experiments take (Section 5).  A pencil with real
+    entries is passed to the real QZ (``dggev``), whose eigenvalues are the same
+    and which runs several times faster."""
+    if not np.iscomplexobj(A) or (np.all(A.imag == 0) and np.all(B.imag == 0)):
+        A, B = np.real(A), np.real(B)
+    lam = sla.eigvals(A, B)
+    return lam[np.isfinite(lam)]
+
+
+def standin_contour(lam: np.ndarray, target: int = 20, probes: int = 40):
+    """A circle around about ``target`` reference eigenvalues with the widest
+    relative gap: centres at the ``probes`` eigenvalues closest to the median
+    real part, counts ``target - 8 .. target + 8``, radius midway between the
+    s-th and (s+1)-th distances.  Returns (center, radius, s, gap)."""
+    best = None
+    for c in lam[np.argsort(np.abs(lam - np.median(lam.real)))[:probes]]:
+        d = np.sort(np.abs(lam - c))
+        for s in range(max(8, target - 8), min(target + 9, d.size)):
+            gap = d[s] / d[s - 1]
+            if best is None or gap > best[3]:
+                best = (complex(c), float(0.5 * (d[s - 1] + d[s])), s, float(gap))
+    return best
+
+
+# ---------------------------------------------------------------------------
 # Irregular contours (Section 4.3): an enclosing circle, then the region test
 # ---------------------------------------------------------------------------
 

@@ -236,3 +236,64 @@ def region_workload(n: int = 600, inside: int = 30, notch: int = 8, nodes: int =
     mask = np.zeros(n, dtype=bool)
     mask[:inside] = True
     return p, mask
+
+
+# Table 1 of the paper: (name, n, nnz(A), nnz(B), property of A, property of B).
+# The Matrix Market files are not available; these are the shapes the
+# stand-ins below reproduce.
+TABLE1 = [
+    ("BFW398", 398, 3678, 2910, "unsym", "symind"),
+    ("BFW782", 782, 7514, 5982, "unsym", "symind"),
+    ("PLAT/PLSK1919", 1919, 17159, 4831, "symind", "skew"),
+    ("BCSSTK/M13", 2003, 42943, 11973, "spd", "spsd"),
+    ("BCSSTK/M27", 1224, 28675, 28675, "spd", "symind"),
+    ("MHD3200", 3200, 68026, 18316, "unsym", "symind"),
+    ("MHD4800", 4800, 102252, 27520, "unsym", "symind"),
+]
+
+
+def _sparse_real(rng, n: int, nnz: int, kind: str) -> np.ndarray:
+    """A dense array holding a real sparse matrix with about ``nnz`` non-zeros
+    of the given structure: unsym, symind (symmetric indefinite), skew,
+    spd (symmetric, diagonally dominant, positive diagonal), spsd (as spd with
+    a tenth of the rows and columns zero, hence singular)."""
+    M = np.zeros((n, n))
+    if kind == "unsym":
+        k = max(nnz - n, 0)
+        i, j = rng.integers(0, n, k), rng.integers(0, n, k)
+        M[i, j] = rng.normal(size=k)
+        M[np.arange(n), np.arange(n)] += rng.normal(size=n) + 2.0 * rng.choice([-1, 1], n)
+        return M
+    off = nnz - (0 if kind == "skew" else n)
+    if kind == "spsd":  # the zeroed tenth of the rows and columns removes about 19%
+        off = int(off / 0.81)
+    half = max(off // 2, 0)
+    i, j = rng.integers(0, n, half), rng.integers(0, n, half)
+    keep = i != j
+    i, j = np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
+    U = np.zeros((n, n))
+    U[i, j] = rng.normal(size=i.size)  # strict upper triangle
+    if kind == "skew":
+        return U - U.T
+    M = U + U.T
+    if kind == "symind":
+        M[np.arange(n), np.arange(n)] = rng.normal(size=n) * 2.0
+    else:  # spd / spsd: diagonally dominant
+        M[np.arange(n), np.arange(n)] = np.abs(M).sum(axis=1) + 1.0
+        if kind == "spsd":
+            z = rng.choice(n, n // 10, replace=False)
+            M[z, :] = 0.0
+            M[:, z] = 0.0
+    return M
+
+
+def sparse_standin(k: int, m: int = 40, seed: int = BASE_SEED + 100):
+    """Stand-in for problem k (1..7) of Table 1: real A, B of its order, number
+    of non-zeros and structure (random values and pattern), returned dense as
+    complex128, with a complex Gaussian start block V (n x m)."""
+    name, n, nnz_a, nnz_b, ka, kb = TABLE1[k - 1]
+    ra, rb, rv = (np.random.default_rng(s) for s in np.random.SeedSequence(seed + k).spawn(3))
+    A = _sparse_real(ra, n, nnz_a, ka).astype(np.complex128)
+    B = _sparse_real(rb, n, nnz_b, kb).astype(np.complex128)
+    V = _cgauss(rv, (n, m), 1.0)
+    return name, A, B, V
