@@ -372,29 +372,62 @@ __global__ __launch_bounds__(256) void k_laswp_outside(T *__restrict__ Mall, int
   }
 }
 
-// X = L11^{-1} X with L11 unit lower (w1 x w1), X (w1 x w2), both inside the
-// matrix; one workgroup per matrix, one thread per column of X.
+// X = L11^{-1} X with L11 unit lower (w1 x w1), X (w1 x w2), w1, w2 <= 64, both
+// inside the matrix; one workgroup of 256 threads per matrix, X in registers
+// (the layout of k_diag_inv), forward substitution with one barrier per row.
 template <typename T>
-__global__ __launch_bounds__(64) void k_trsm_small(T *__restrict__ Mall, int64_t ld,
-                                                   int64_t stride, int64_t c0, int w1, int w2) {
+__global__ __launch_bounds__(256) void k_trsm_small(T *__restrict__ Mall, int64_t ld,
+                                                    int64_t stride, int64_t c0, int w1, int w2) {
   using Tr = cplx_traits<T>;
   __shared__ T sL[64][65];
-  __shared__ T sX[64][65];
+  __shared__ T rowb[2][64];
   T *M = Mall + blockIdx.x * stride;
-  const int tid = threadIdx.x;
-  for (int i = 0; i < w1; ++i) {
-    if (tid < w1) sL[i][tid] = M[(c0 + i) * ld + c0 + tid];
-    if (tid < w2) sX[i][tid] = M[(c0 + i) * ld + c0 + w1 + tid];
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    sL[i][j] = (i < w1 && j < w1) ? M[(c0 + i) * ld + c0 + j] : czero<T>();
   }
-  __syncthreads();
-  if (tid < w2) {
-    for (int i = 1; i < w1; ++i) {
-      T x = sX[i][tid];
-      for (int k = 0; k < i; ++k) x = Tr::fms(x, sL[i][k], sX[k][tid]);
-      sX[i][tid] = x;
+  T x[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = ti + 16 * a, j = tj + 16 * c;
+      x[a][c] = (i < w1 && j < w2) ? M[(c0 + i) * ld + c0 + w1 + j] : czero<T>();
     }
-    for (int i = 1; i < w1; ++i) M[(c0 + i) * ld + c0 + w1 + tid] = sX[i][tid];
+  for (int i = 0; i + 1 < w1; ++i) {
+    if (ti == (i & 15)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == (i >> 4))
+#pragma unroll
+          for (int c = 0; c < 4; ++c) rowb[i & 1][tj + 16 * c] = x[a][c];
+    }
+    __syncthreads();
+    T la[4], xb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) la[a] = sL[ti + 16 * a][i];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][tj + 16 * c];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (16 * a + 4 * wv + 3 <= i) continue;
+      const bool on = ti + 16 * a > i;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const T y = Tr::fms(x[a][c], la[a], xb[c]);
+        x[a][c] = on ? y : x[a][c];
+      }
+    }
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = ti + 16 * a, j = tj + 16 * c;
+      if (i >= 1 && i < w1 && j < w2) M[(c0 + i) * ld + c0 + w1 + j] = x[a][c];
+    }
 }
 
 // One recursion step of the panel factorisation in a single launch, for
@@ -499,16 +532,29 @@ __global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int6
     }
 }
 
-// Inverse of one diagonal block (lower unit or upper non-unit), one thread per column.
+// Register layout shared by the 64 x 64 triangular kernels below: 256 threads,
+// thread (ti, tj) = (tid / 16, tid % 16) holds the 16 entries (ti + 16a,
+// tj + 16c), a, c < 4, and wave wv = tid / 64 holds rows ti in [4 wv, 4 wv + 4)
+// of every 16-row block.  A substitution step publishes one finished row
+// through a double-buffered LDS row, so it needs one barrier, and skips the
+// 16 x 16 blocks whose entries it cannot change (a wave-uniform test).
+
+// Inverse of one nb x nb diagonal block (nb = 64; lower unit or upper
+// non-unit) of each matrix, X = D^{-1} with X = I to start:
+//   lower: forward, row i of X is final at step i; rows r > i take
+//          X_r. -= D_ri X_i.;
+//   upper: backward, X_i. = X_i. / D_ii at step i; rows r < i take
+//          X_r. -= D_ri X_i..
+// Written zero padded to 64 x 64 at out + b out_stride + I 64^2.
 template <typename T>
-__global__ __launch_bounds__(64) void k_diag_inv(const T *__restrict__ Mall, int64_t ld_in,
-                                                 int64_t stride, int64_t n_in, int nb, int64_t blk0,
-                                                 bool lower, T *__restrict__ out,
-                                                 int64_t out_stride,
-                                                 const GrpMat *__restrict__ grp, int nodes) {
+__global__ __launch_bounds__(256) void k_diag_inv(const T *__restrict__ Mall, int64_t ld_in,
+                                                  int64_t stride, int64_t n_in, int nb, int64_t blk0,
+                                                  bool lower, T *__restrict__ out,
+                                                  int64_t out_stride,
+                                                  const GrpMat *__restrict__ grp, int nodes) {
   using Tr = cplx_traits<T>;
   __shared__ T sD[64][65];
-  __shared__ T sX[64][65];
+  __shared__ T rowb[2][64];
   const int64_t I = blk0 + blockIdx.x;
   const int b = blockIdx.y;
   const MatRef<const T> mr = mat_of<const T>(grp, nodes, Mall, ld_in, stride, n_in, b);
@@ -516,34 +562,87 @@ __global__ __launch_bounds__(64) void k_diag_inv(const T *__restrict__ Mall, int
   const int64_t ld = mr.ld, n = mr.n;
   const int64_t r0 = I * nb;
   const int rb = static_cast<int>((n - r0 < nb) ? n - r0 : nb);
-  const int tid = threadIdx.x;
-  for (int i = 0; i < rb; ++i)
-    if (tid < rb) sD[i][tid] = M[(r0 + i) * ld + r0 + tid];
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    sD[i][j] = (i < rb && j < rb) ? M[(r0 + i) * ld + r0 + j] : czero<T>();
+  }
+  T x[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      x[a][c] = (ti + 16 * a == tj + 16 * c && ti + 16 * a < rb) ? Tr::make(1.0, 0.0) : czero<T>();
   __syncthreads();
-  const int j = tid;
-  if (j < rb) {
-    if (lower) {
-      for (int i = 0; i < j; ++i) sX[i][j] = czero<T>();
-      sX[j][j] = Tr::make(1.0, 0.0);
-      for (int i = j + 1; i < rb; ++i) {
-        T x = czero<T>();
-        for (int k = j; k < i; ++k) x = Tr::fms(x, sD[i][k], sX[k][j]);
-        sX[i][j] = x;
+  if (lower) {
+    for (int i = 0; i + 1 < rb; ++i) {
+      if (ti == (i & 15)) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          if (a == (i >> 4))
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rowb[i & 1][tj + 16 * c] = x[a][c];
       }
-    } else {
-      for (int i = j + 1; i < rb; ++i) sX[i][j] = czero<T>();
-      sX[j][j] = Tr::recip(sD[j][j]);
-      for (int i = j - 1; i >= 0; --i) {
-        T x = czero<T>();
-        for (int k = i + 1; k <= j; ++k) x = Tr::fms(x, sD[i][k], sX[k][j]);
-        sX[i][j] = Tr::mul(x, Tr::recip(sD[i][i]));
+      __syncthreads();
+      T la[4], xb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) la[a] = sD[ti + 16 * a][i];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][tj + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (16 * a + 4 * wv + 3 <= i) continue;
+        const bool on = ti + 16 * a > i;
+#pragma unroll
+        for (int c = 0; c <= a; ++c) {  // X_rj = 0 for j > r
+          if (16 * c > i) continue;
+          const bool up = on && tj + 16 * c <= i;
+          const T y = Tr::fms(x[a][c], la[a], xb[c]);
+          x[a][c] = up ? y : x[a][c];
+        }
+      }
+    }
+  } else {
+    for (int i = rb - 1; i >= 0; --i) {
+      if (ti == (i & 15)) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          if (a == (i >> 4)) {
+            const T di = Tr::recip(sD[i][i]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              x[a][c] = Tr::mul(x[a][c], di);
+              rowb[i & 1][tj + 16 * c] = x[a][c];
+            }
+          }
+      }
+      __syncthreads();
+      if (i == 0) break;
+      T ua[4], xb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) ua[a] = sD[ti + 16 * a][i];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][tj + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (16 * a + 4 * wv >= i) continue;
+        const bool on = ti + 16 * a < i;
+#pragma unroll
+        for (int c = a; c < 4; ++c) {  // X_rj = 0 for j < r
+          if (16 * c + 15 < i) continue;
+          const bool up = on && tj + 16 * c >= i;
+          const T y = Tr::fms(x[a][c], ua[a], xb[c]);
+          x[a][c] = up ? y : x[a][c];
+        }
       }
     }
   }
-  __syncthreads();
   T *o = out + b * out_stride + I * static_cast<int64_t>(nb) * nb;
-  for (int i = 0; i < nb; ++i)
-    if (tid < nb) o[i * nb + tid] = (i < rb && tid < rb) ? sX[i][tid] : czero<T>();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[(ti + 16 * a) * nb + tj + 16 * c] = x[a][c];
 }
 
 // Inverse of a 128-row diagonal block of a triangular factor from the inverses
@@ -737,7 +836,7 @@ template <typename T>
 void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t c0,
                 int w1, int w2) {
   if (w1 <= 1 || w2 <= 0) return;
-  hipLaunchKernelGGL((k_trsm_small<T>), dim3(batch), dim3(64), 0, s, M, ld, stride, c0, w1, w2);
+  hipLaunchKernelGGL((k_trsm_small<T>), dim3(batch), dim3(256), 0, s, M, ld, stride, c0, w1, w2);
 }
 template void trsm_small<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int, int);
 template void trsm_small<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int, int);
@@ -765,7 +864,7 @@ void diag_block_inverse(hipStream_t s, const T *M, int64_t ld, int64_t stride, i
                         int64_t n, int nb, int64_t blk0, int64_t blk1, bool lower, T *out,
                         int64_t out_stride, const GrpMat *grp, int nodes) {
   if (blk1 <= blk0) return;
-  hipLaunchKernelGGL((k_diag_inv<T>), dim3(static_cast<unsigned>(blk1 - blk0), batch), dim3(64),
+  hipLaunchKernelGGL((k_diag_inv<T>), dim3(static_cast<unsigned>(blk1 - blk0), batch), dim3(256),
                      0, s, M, ld, stride, n, nb, blk0, lower, out, out_stride, grp, nodes);
 }
 template void diag_block_inverse<z64>(hipStream_t, const z64 *, int64_t, int64_t, int32_t,

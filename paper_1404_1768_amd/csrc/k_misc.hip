@@ -245,6 +245,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
   __shared__ z64 Rs[64][65];
   __shared__ double dg[64];
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave: rows ti in [4 wv, 4 wv + 4)
   z64 v[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -265,20 +266,27 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
       d = 1.0;
     }
     if (tid == 0) dg[k] = d;
+    // all LDS reads of the step first, then branch-free updates (masked rows
+    // and columns take a zero update), so the reads overlap
+    z64 ri[4], rj[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ri[a] = rk[ti + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rj[b] = rk[tj + 16 * b];
     const double rd = 1.0 / d;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
+      if (16 * a + 4 * wv + 3 <= k) continue;  // the wave's rows of this block are done
       const int i = ti + 16 * a;
-      if (i <= k || i >= jb) continue;
-      const z64 q = rk[i];
-      const double qr = q.x * rd, qi = -q.y * rd;  // conj(G_ki) / G_kk
+      const bool on = i > k && i < jb;
+      const double qr = on ? ri[a].x * rd : 0.0, qi = on ? -ri[a].y * rd : 0.0;  // conj(G_ki)/G_kk
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = a; b < 4; ++b) {  // columns j >= i only
         const int j = tj + 16 * b;
-        if (j < i || j >= jb) continue;
-        const z64 w = rk[j];
-        v[a][b].x -= qr * w.x - qi * w.y;
-        v[a][b].y -= qr * w.y + qi * w.x;
+        const bool up = j >= i && j < jb;
+        const double dx = qr * rj[b].x - qi * rj[b].y, dy = qr * rj[b].y + qi * rj[b].x;
+        v[a][b].x -= up ? dx : 0.0;
+        v[a][b].y -= up ? dy : 0.0;
       }
     }
     const int nk = k + 1;
@@ -325,18 +333,25 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
   __syncthreads();
   for (int i = jb - 1; i > 0; --i) {
     const z64 *xi = row[i & 1];
+    z64 qa[4], xb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) qa[a] = Rs[ti + 16 * a][i];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xb[b] = xi[tj + 16 * b];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
+      if (16 * a + 4 * wv >= i) continue;  // none of the wave's rows of this block is above i
       const int r = ti + 16 * a;
-      if (r >= i) continue;
-      const z64 q = Rs[r][i];
+      const bool on = r < i;
+      const double qr = on ? qa[a].x : 0.0, qi = on ? qa[a].y : 0.0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = a; b < 4; ++b) {  // X_rj = 0 for j < r
+        if (16 * b + 15 < i) continue;
         const int j = tj + 16 * b;
-        if (j < i || j >= jb) continue;
-        const z64 w = xi[j];
-        v[a][b].x -= q.x * w.x - q.y * w.y;
-        v[a][b].y -= q.x * w.y + q.y * w.x;
+        const bool up = j >= i && j < jb;
+        const double dx = qr * xb[b].x - qi * xb[b].y, dy = qr * xb[b].y + qi * xb[b].x;
+        v[a][b].x -= up ? dx : 0.0;
+        v[a][b].y -= up ? dy : 0.0;
       }
     }
     const int ni = i - 1;
