@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void k_trsm_small(T *__restrict__ Mall, int64_
                                                     int64_t stride, int64_t c0, int w1, int w2) {
   using Tr = cplx_traits<T>;
   __shared__ T sL[64][65];
-  __shared__ T rowb[2][64];
+  __shared__ T rowb[2][4][64];
   T *M = Mall + blockIdx.x * stride;
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -397,28 +397,23 @@ __global__ __launch_bounds__(256) void k_trsm_small(T *__restrict__ Mall, int64_
       x[a][c] = (i < w1 && j < w2) ? M[(c0 + i) * ld + c0 + w1 + j] : czero<T>();
     }
   for (int i = 0; i + 1 < w1; ++i) {
-    if (ti == (i & 15)) {
+    if (ti == (i & 15))  // the owners of row i publish it (all four row blocks)
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        if (a == (i >> 4))
 #pragma unroll
-          for (int c = 0; c < 4; ++c) rowb[i & 1][tj + 16 * c] = x[a][c];
-    }
+        for (int c = 0; c < 4; ++c) rowb[i & 1][a][tj + 16 * c] = x[a][c];
     __syncthreads();
     T la[4], xb[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) la[a] = sL[ti + 16 * a][i];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][tj + 16 * c];
+    for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][i >> 4][tj + 16 * c];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       if (16 * a + 4 * wv + 3 <= i) continue;
-      const bool on = ti + 16 * a > i;
+      const T l = (ti + 16 * a > i) ? la[a] : czero<T>();  // rows r > i only
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const T y = Tr::fms(x[a][c], la[a], xb[c]);
-        x[a][c] = on ? y : x[a][c];
-      }
+      for (int c = 0; c < 4; ++c) x[a][c] = Tr::fms(x[a][c], l, xb[c]);
     }
   }
 #pragma unroll
@@ -536,8 +531,10 @@ __global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int6
 // thread (ti, tj) = (tid / 16, tid % 16) holds the 16 entries (ti + 16a,
 // tj + 16c), a, c < 4, and wave wv = tid / 64 holds rows ti in [4 wv, 4 wv + 4)
 // of every 16-row block.  A substitution step publishes one finished row
-// through a double-buffered LDS row, so it needs one barrier, and skips the
-// 16 x 16 blocks whose entries it cannot change (a wave-uniform test).
+// through double-buffered LDS rows, so it needs one barrier, and skips the
+// 16 x 16 blocks whose entries it cannot change (a wave-uniform test).  The
+// owners of row i write all four of their rows and readers take block i / 16:
+// choosing the register block by i would put the array in scratch memory.
 
 // Inverse of one nb x nb diagonal block (nb = 64; lower unit or upper
 // non-unit) of each matrix, X = D^{-1} with X = I to start:
@@ -554,7 +551,7 @@ __global__ __launch_bounds__(256) void k_diag_inv(const T *__restrict__ Mall, in
                                                   const GrpMat *__restrict__ grp, int nodes) {
   using Tr = cplx_traits<T>;
   __shared__ T sD[64][65];
-  __shared__ T rowb[2][64];
+  __shared__ T rowb[2][4][64];
   const int64_t I = blk0 + blockIdx.x;
   const int b = blockIdx.y;
   const MatRef<const T> mr = mat_of<const T>(grp, nodes, Mall, ld_in, stride, n_in, b);
@@ -577,45 +574,47 @@ __global__ __launch_bounds__(256) void k_diag_inv(const T *__restrict__ Mall, in
   __syncthreads();
   if (lower) {
     for (int i = 0; i + 1 < rb; ++i) {
-      if (ti == (i & 15)) {
+      if (ti == (i & 15))  // the owners of row i publish it (all four row blocks)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-          if (a == (i >> 4))
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rowb[i & 1][tj + 16 * c] = x[a][c];
-      }
+          for (int c = 0; c < 4; ++c) rowb[i & 1][a][tj + 16 * c] = x[a][c];
       __syncthreads();
       T la[4], xb[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) la[a] = sD[ti + 16 * a][i];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][tj + 16 * c];
+      for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][i >> 4][tj + 16 * c];
+      // masked operands (rows r > i, columns j <= i) instead of masked results:
+      // a select on the register array would move it to scratch memory
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xb[c] = (tj + 16 * c <= i) ? xb[c] : czero<T>();
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (16 * a + 4 * wv + 3 <= i) continue;
-        const bool on = ti + 16 * a > i;
+        const T l = (ti + 16 * a > i) ? la[a] : czero<T>();
 #pragma unroll
         for (int c = 0; c <= a; ++c) {  // X_rj = 0 for j > r
           if (16 * c > i) continue;
-          const bool up = on && tj + 16 * c <= i;
-          const T y = Tr::fms(x[a][c], la[a], xb[c]);
-          x[a][c] = up ? y : x[a][c];
+          x[a][c] = Tr::fms(x[a][c], l, xb[c]);
         }
       }
     }
   } else {
     for (int i = rb - 1; i >= 0; --i) {
-      if (ti == (i & 15)) {
+      {  // the owners of row i scale and publish it (selects keep x in registers)
+        const T di = Tr::recip(sD[i][i]);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-          if (a == (i >> 4)) {
-            const T di = Tr::recip(sD[i][i]);
+        for (int a = 0; a < 4; ++a) {
+          const T f = (ti + 16 * a == i) ? di : Tr::make(1.0, 0.0);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              x[a][c] = Tr::mul(x[a][c], di);
-              rowb[i & 1][tj + 16 * c] = x[a][c];
-            }
-          }
+          for (int c = 0; c < 4; ++c) x[a][c] = Tr::mul(x[a][c], f);
+        }
+        if (ti == (i & 15))
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rowb[i & 1][a][tj + 16 * c] = x[a][c];
       }
       __syncthreads();
       if (i == 0) break;
@@ -623,17 +622,17 @@ __global__ __launch_bounds__(256) void k_diag_inv(const T *__restrict__ Mall, in
 #pragma unroll
       for (int a = 0; a < 4; ++a) ua[a] = sD[ti + 16 * a][i];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][tj + 16 * c];
+      for (int c = 0; c < 4; ++c) xb[c] = rowb[i & 1][i >> 4][tj + 16 * c];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xb[c] = (tj + 16 * c >= i) ? xb[c] : czero<T>();
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (16 * a + 4 * wv >= i) continue;
-        const bool on = ti + 16 * a < i;
+        const T u = (ti + 16 * a < i) ? ua[a] : czero<T>();  // rows r < i only
 #pragma unroll
         for (int c = a; c < 4; ++c) {  // X_rj = 0 for j < r
           if (16 * c + 15 < i) continue;
-          const bool up = on && tj + 16 * c >= i;
-          const T y = Tr::fms(x[a][c], ua[a], xb[c]);
-          x[a][c] = up ? y : x[a][c];
+          x[a][c] = Tr::fms(x[a][c], u, xb[c]);
         }
       }
     }

@@ -226,6 +226,29 @@ __global__ __launch_bounds__(256) void k_add_shift(z64 *__restrict__ G, int64_t 
   for (int64_t i = threadIdx.x; i < t; i += 256) G[i * t + i].x += sh;
 }
 
+// Row i of the 16-entry-per-thread register block (layout of k_chol_inv)
+// divided by the real diagonal Rs[i][i]; its owners then publish all four of
+// their row blocks to row[i & 1] (readers take block i / 16: choosing the
+// register block by i would put the array in scratch memory).
+__device__ inline void scale_publish(z64 (&v)[4][4], const z64 (*Rs)[65], z64 (*row)[4][64],
+                                     int i, int ti, int tj) {
+  const double rii = 1.0 / Rs[i][i].x;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const double f = (ti + 16 * a == i) ? rii : 1.0;  // a factor, not a select on v
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      v[a][b].x *= f;
+      v[a][b].y *= f;
+    }
+  }
+  if (ti == (i & 15))
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) row[i & 1][a][tj + 16 * b] = v[a][b];
+}
+
 // Cholesky of one jb x jb (jb <= 64) Hermitian diagonal block and the inverse
 // of its factor, by one workgroup of 256 threads.  The upper triangle of the
 // block is read; R (upper) is written over it with the strict lower part
@@ -241,7 +264,7 @@ __global__ __launch_bounds__(256) void k_add_shift(z64 *__restrict__ G, int64_t 
 __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t ld, int jb,
                                                   int col0, int32_t *__restrict__ flag,
                                                   z64 *__restrict__ Rinv, int64_t ldi) {
-  __shared__ z64 row[2][64];
+  __shared__ z64 row[2][4][64];
   __shared__ z64 Rs[64][65];
   __shared__ double dg[64];
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
@@ -256,10 +279,12 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
     }
   if (ti == 0)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) row[0][tj + 16 * b] = v[0][b];
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) row[0][a][tj + 16 * b] = v[a][b];
   __syncthreads();
   for (int k = 0; k < jb; ++k) {
-    const z64 *rk = row[k & 1];
+    const z64 *rk = row[k & 1][k >> 4];
     double d = rk[k].x;
     if (!(d > 0.0)) {
       if (tid == 0 && flag[0] == 0) flag[0] = col0 + k + 1;
@@ -290,13 +315,11 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
       }
     }
     const int nk = k + 1;
-    if (nk < jb && ti == (nk & 15)) {
+    if (nk < jb && ti == (nk & 15))  // the owners of row k + 1 publish it
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        if (a == (nk >> 4))
 #pragma unroll
-          for (int b = 0; b < 4; ++b) row[nk & 1][tj + 16 * b] = v[a][b];
-    }
+        for (int b = 0; b < 4; ++b) row[nk & 1][a][tj + 16 * b] = v[a][b];
     __syncthreads();
   }
   // R_ij = G_ij / sqrt(d_i) for i <= j (row i stops changing after step i - 1)
@@ -317,22 +340,10 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
   }
   __syncthreads();
   // X = R^{-1}: the owners of row jb - 1 start the chain
-  if (ti == ((jb - 1) & 15)) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-      if (a == ((jb - 1) >> 4)) {
-        const double rii = 1.0 / Rs[jb - 1][jb - 1].x;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          v[a][b].x *= rii;
-          v[a][b].y *= rii;
-          row[(jb - 1) & 1][tj + 16 * b] = v[a][b];
-        }
-      }
-  }
+  scale_publish(v, Rs, row, jb - 1, ti, tj);
   __syncthreads();
   for (int i = jb - 1; i > 0; --i) {
-    const z64 *xi = row[i & 1];
+    const z64 *xi = row[i & 1][i >> 4];
     z64 qa[4], xb[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) qa[a] = Rs[ti + 16 * a][i];
@@ -354,20 +365,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
         v[a][b].y -= up ? dy : 0.0;
       }
     }
-    const int ni = i - 1;
-    if (ti == (ni & 15)) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if (a == (ni >> 4)) {
-          const double rii = 1.0 / Rs[ni][ni].x;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            v[a][b].x *= rii;
-            v[a][b].y *= rii;
-            row[ni & 1][tj + 16 * b] = v[a][b];
-          }
-        }
-    }
+    scale_publish(v, Rs, row, i - 1, ti, tj);  // row i - 1 of X is final
     __syncthreads();
   }
 #pragma unroll
