@@ -319,8 +319,11 @@ void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr, int64_t cols) {
 //                (at most max_sweeps corrections; each test costs one residual);
 //   target <= 0: exactly `sweeps` corrections with no final residual (the caller
 //                judges the accuracy, as Algorithm 5 does through eq. 5-1).
+//   resume     : Y already holds this right-hand side's node solutions (a
+//                filter that ran with fewer corrections): refine them further.
 void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb,
-                       const z64 *R, int64_t ldr, double target, int sweeps, int64_t cols) {
+                       const z64 *R, int64_t ldr, double target, int sweeps, int64_t cols,
+                       bool resume = false) {
   const int64_t n = p->n, m = cols, ldY = p->ldY(), sY = p->m;
   const int N = p->N;
   hipStream_t s = p->s;
@@ -330,11 +333,12 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
   const c64 *F = p->F.as<c64>();
   const int32_t *perm = p->perm.as<int32_t>();
   double *part = p->part.as<double>(), *nrm = p->nrm.as<double>();
-  // complex64 solve of P_j R
-  feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, sY);
-  feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0);
-  plan_trsolve<c64>(p, s, Yc, m, ldY, sY, 0);
-  feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
+  if (!resume) {  // complex64 solve of P_j R
+    feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, sY);
+    feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0);
+    plan_trsolve<c64>(p, s, Yc, m, ldY, sY, 0);
+    feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
+  }
   p->last_sweeps = 0;
   p->last_be = -1.0;
   p->stagnated = false;
@@ -387,11 +391,12 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
 // U = sum_j w_j (z_j B - A)^{-1} R  (the filter of eq. 8-4 on the right-hand side R = B U_1).
 // Mixed form: see solve_nodes_mixed for `target` and `sweeps`.
 int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb, const z64 *R,
-               int64_t ldr, z64 *U, int64_t ldu, double target, int sweeps, int64_t cols = -1) {
+               int64_t ldr, z64 *U, int64_t ldu, double target, int sweeps, int64_t cols = -1,
+               bool resume = false) {
   if (cols < 0) cols = p->m;
   int st = ensure_factored(p, A, lda, B, ldb);
   if (p->mixed())
-    solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps, cols);
+    solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps, cols, resume);
   else
     solve_nodes_z(p, R, ldr, cols);
   feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, cols, U,
@@ -785,20 +790,26 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     std::vector<feast_z> hAt(mm), hBt(mm), hY(mm), halpha(m), hbeta(m);
     std::vector<double> hn(3 * m);
     // Mixed form: Search's filter is not refined; a later filter gets `sweeps`
-    // corrections (one more whenever a refined iteration missed eps without
-    // halving e(k)) unless the last known e(k) is infinite or above
+    // corrections unless the last known e(k) is infinite or above
     // kRefineFrom, where the complex64 solves are already more accurate than
-    // the subspace (the first filter after Search, with no e(k) yet, is refined).
+    // the subspace (the first filter after Search, with no e(k) yet, is
+    // refined).  Once a refined iteration with a settled count misses eps
+    // without halving e(k), the solves limit the accuracy (their forward error
+    // is the backward error times cond(z_j B - A)): every later filter then
+    // refines each node until its backward error reaches refine_tol.
     constexpr double kRefineFrom = 1e-4;
-    int sweeps = p->mixed() ? 1 : 0;
+    const int sweeps = p->mixed() ? 1 : 0;
     auto sweeps_for = [&](double e_last, bool known) {
       if (!p->mixed()) return 0;
       if (known && !(e_last <= kRefineFrom)) return 0;
       return sweeps;
     };
     int sweeps_now = sweeps;
-    auto run_filter = [&](const z64 *R, z64 *Uout, bool first) -> int {
-      const int st = filter_rhs(p, A, lda, B, ldb, R, m, Uout, m, 0.0, first ? 0 : sweeps_now);
+    bool verify = false;
+    auto run_filter = [&](const z64 *R, z64 *Uout, bool first, bool resume = false) -> int {
+      const double target = (!first && verify) ? p->o.refine_tol : 0.0;
+      const int st = filter_rhs(p, A, lda, B, ldb, R, m, Uout, m, target, first ? 0 : sweeps_now,
+                                -1, resume);
       if (inf.filters < FEAST_MAX_HISTORY) inf.sweeps[inf.filters] = p->last_sweeps;
       inf.filters += 1;
       return st;
@@ -935,10 +946,11 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       }
       // a refined iteration whose count is settled, that missed eps and whose
       // error stopped falling geometrically: the solves, not the subspace,
-      // limit the accuracy, so refine harder
-      if (p->mixed() && k >= 2 && c_k == c_prev && e_k >= p->o.eps && e_k > 0.5 * e_prev &&
-          sweeps < p->o.max_sweeps)
-        ++sweeps;
+      // limit the accuracy, so refine to full accuracy from now on
+      bool verify_now = false;
+      if (p->mixed() && !verify && k >= 2 && c_k == c_prev && e_k >= p->o.eps &&
+          e_k > 0.5 * e_prev)
+        verify = verify_now = true;
       e_prev2 = e_prev;
       e_prev = e_k;
       c_prev = c_k;
@@ -947,9 +959,11 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       // line 16 (unless it already ran)
       // filter time: its launch plus whatever of it the host work did not hide
       Timer tw;
-      if (!speculated) {
+      if (!speculated || verify_now) {
+        // (a filter launched ahead with unverified corrections is refined
+        // further from its node solutions once verification is switched on)
         sweeps_now = sweeps_for(e_k, true);
-        const int st = run_filter(BU1, UF, false);
+        const int st = run_filter(BU1, UF, false, speculated);
         if (st == FEAST_REFINE_STAGNATED) status = st;
         else if (st != FEAST_OK) return st;
       }
