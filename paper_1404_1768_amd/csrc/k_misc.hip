@@ -226,65 +226,48 @@ __global__ __launch_bounds__(256) void k_add_shift(z64 *__restrict__ G, int64_t 
   for (int64_t i = threadIdx.x; i < t; i += 256) G[i * t + i].x += sh;
 }
 
-// Row i of the 16-entry-per-thread register block (layout of k_chol_inv)
-// divided by the real diagonal Rs[i][i]; its owners then publish all four of
-// their row blocks to row[i & 1] (readers take block i / 16: choosing the
-// register block by i would put the array in scratch memory).
-__device__ inline void scale_publish(z64 (&v)[4][4], const z64 (*Rs)[65], z64 (*row)[4][64],
-                                     int i, int ti, int tj) {
-  const double rii = 1.0 / Rs[i][i].x;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const double f = (ti + 16 * a == i) ? rii : 1.0;  // a factor, not a select on v
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      v[a][b].x *= f;
-      v[a][b].y *= f;
-    }
-  }
-  if (ti == (i & 15))
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) row[i & 1][a][tj + 16 * b] = v[a][b];
-}
-
 // Cholesky of one jb x jb (jb <= 64) Hermitian diagonal block and the inverse
-// of its factor, by one workgroup of 256 threads.  The upper triangle of the
-// block is read; R (upper) is written over it with the strict lower part
-// zeroed, and R^{-1} (jb x jb, upper) to Rinv (leading dimension ldi).
-// Thread (ti, tj) holds the 16 entries (ti + 16a, tj + 16b), a, b < 4, in
-// registers.  Cholesky step k subtracts conj(G_ki) G_kj / G_kk from every
-// entry with k < i <= j (G_k. is the pivot row, read-only during the step);
-// the inverse runs the same way from the bottom, X_i. = B_i. / R_ii and
-// B_r. -= R_ri X_i. for r < i with B = I at the start.  Each step passes
-// one row through LDS (double-buffered), so it needs one barrier.
+// of its factor, by one workgroup of S*S threads (S = 32: 1024 threads).  The
+// upper triangle of the block is read; R (upper) is written over it with the
+// strict lower part zeroed, and R^{-1} (jb x jb, upper) to Rinv (leading
+// dimension ldi).  Thread (ti, tj) holds the E*E entries (ti + S a, tj + S b),
+// a, b < E = 64/S, in registers; wave wv holds the rows ti in
+// [RW wv, RW (wv + 1)), RW = 64/S.  Cholesky step k subtracts
+// conj(G_ki) G_kj / G_kk from every entry with k < i <= j (row k is read-only
+// during the step); the inverse runs the same way from the bottom,
+// X_i. = B_i. / R_ii and B_r. -= R_ri X_i. for r < i with B = I to start.
+// Each step passes one finished row through LDS (double-buffered; its owners
+// write all E of their row blocks and readers take block i / S, because
+// choosing a register block by i would move the array to scratch memory), so
+// it needs one barrier, and skips the blocks whose entries it cannot change.
 // flag[0] = 1 + col0 + k for the first non-positive pivot k (a unit pivot is
 // used in its place so the kernel finishes).
-__global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t ld, int jb,
-                                                  int col0, int32_t *__restrict__ flag,
-                                                  z64 *__restrict__ Rinv, int64_t ldi) {
-  __shared__ z64 row[2][4][64];
+template <int S>
+__global__ __launch_bounds__(S * S) void k_chol_inv(z64 *__restrict__ G, int64_t ld, int jb,
+                                                    int col0, int32_t *__restrict__ flag,
+                                                    z64 *__restrict__ Rinv, int64_t ldi) {
+  constexpr int E = 64 / S, RW = 64 / S;
+  __shared__ z64 row[2][E][64];
   __shared__ z64 Rs[64][65];
   __shared__ double dg[64];
-  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave: rows ti in [4 wv, 4 wv + 4)
-  z64 v[4][4];
+  const int tid = threadIdx.x, ti = tid / S, tj = tid % S;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  z64 v[E][E];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < E; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ti + 16 * a, j = tj + 16 * b;
+    for (int b = 0; b < E; ++b) {
+      const int i = ti + S * a, j = tj + S * b;
       v[a][b] = (i <= j && j < jb) ? G[i * ld + j] : make_double2(0.0, 0.0);
     }
   if (ti == 0)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < E; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) row[0][a][tj + 16 * b] = v[a][b];
+      for (int b = 0; b < E; ++b) row[0][a][tj + S * b] = v[a][b];
   __syncthreads();
   for (int k = 0; k < jb; ++k) {
-    const z64 *rk = row[k & 1][k >> 4];
+    const z64 *rk = row[k & 1][k / S];
     double d = rk[k].x;
     if (!(d > 0.0)) {
       if (tid == 0 && flag[0] == 0) flag[0] = col0 + k + 1;
@@ -293,21 +276,21 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
     if (tid == 0) dg[k] = d;
     // all LDS reads of the step first, then branch-free updates (masked rows
     // and columns take a zero update), so the reads overlap
-    z64 ri[4], rj[4];
+    z64 ri[E], rj[E];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) ri[a] = rk[ti + 16 * a];
+    for (int a = 0; a < E; ++a) ri[a] = rk[ti + S * a];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rj[b] = rk[tj + 16 * b];
+    for (int b = 0; b < E; ++b) rj[b] = rk[tj + S * b];
     const double rd = 1.0 / d;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (16 * a + 4 * wv + 3 <= k) continue;  // the wave's rows of this block are done
-      const int i = ti + 16 * a;
+    for (int a = 0; a < E; ++a) {
+      if (S * a + RW * wv + RW - 1 <= k) continue;  // the wave's rows of this block are done
+      const int i = ti + S * a;
       const bool on = i > k && i < jb;
       const double qr = on ? ri[a].x * rd : 0.0, qi = on ? -ri[a].y * rd : 0.0;  // conj(G_ki)/G_kk
 #pragma unroll
-      for (int b = a; b < 4; ++b) {  // columns j >= i only
-        const int j = tj + 16 * b;
+      for (int b = a; b < E; ++b) {  // columns j >= i only
+        const int j = tj + S * b;
         const bool up = j >= i && j < jb;
         const double dx = qr * rj[b].x - qi * rj[b].y, dy = qr * rj[b].y + qi * rj[b].x;
         v[a][b].x -= up ? dx : 0.0;
@@ -315,21 +298,21 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
       }
     }
     const int nk = k + 1;
-    if (nk < jb && ti == (nk & 15))  // the owners of row k + 1 publish it
+    if (nk < jb && ti == nk % S)  // the owners of row k + 1 publish it
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < E; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) row[nk & 1][a][tj + 16 * b] = v[a][b];
+        for (int b = 0; b < E; ++b) row[nk & 1][a][tj + S * b] = v[a][b];
     __syncthreads();
   }
   // R_ij = G_ij / sqrt(d_i) for i <= j (row i stops changing after step i - 1)
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = ti + 16 * a;
+  for (int a = 0; a < E; ++a) {
+    const int i = ti + S * a;
     const double sq = (i < jb) ? sqrt(dg[i]) : 1.0, sc = 1.0 / sq;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = tj + 16 * b;
+    for (int b = 0; b < E; ++b) {
+      const int j = tj + S * b;
       z64 r = (i <= j && j < jb) ? make_double2(v[a][b].x * sc, v[a][b].y * sc)
                                  : make_double2(0.0, 0.0);
       if (i == j && i < jb) r = make_double2(sq, 0.0);
@@ -339,40 +322,54 @@ __global__ __launch_bounds__(256) void k_chol_inv(z64 *__restrict__ G, int64_t l
     }
   }
   __syncthreads();
-  // X = R^{-1}: the owners of row jb - 1 start the chain
-  scale_publish(v, Rs, row, jb - 1, ti, tj);
-  __syncthreads();
-  for (int i = jb - 1; i > 0; --i) {
-    const z64 *xi = row[i & 1][i >> 4];
-    z64 qa[4], xb[4];
+  // X = R^{-1}, from the bottom: at step i the owners scale row i by 1/R_ii
+  // (a factor per row block, not a select on v) and publish it
+  for (int i = jb - 1; i >= 0; --i) {
+    const double rii = 1.0 / Rs[i][i].x;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) qa[a] = Rs[ti + 16 * a][i];
+    for (int a = 0; a < E; ++a) {
+      const double f = (ti + S * a == i) ? rii : 1.0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) xb[b] = xi[tj + 16 * b];
+      for (int b = 0; b < E; ++b) {
+        v[a][b].x *= f;
+        v[a][b].y *= f;
+      }
+    }
+    if (i == 0) break;
+    if (ti == i % S)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (16 * a + 4 * wv >= i) continue;  // none of the wave's rows of this block is above i
-      const int r = ti + 16 * a;
+      for (int a = 0; a < E; ++a)
+#pragma unroll
+        for (int b = 0; b < E; ++b) row[i & 1][a][tj + S * b] = v[a][b];
+    __syncthreads();
+    const z64 *xi = row[i & 1][i / S];
+    z64 qa[E], xb[E];
+#pragma unroll
+    for (int a = 0; a < E; ++a) qa[a] = Rs[ti + S * a][i];
+#pragma unroll
+    for (int b = 0; b < E; ++b) xb[b] = xi[tj + S * b];
+#pragma unroll
+    for (int a = 0; a < E; ++a) {
+      if (S * a + RW * wv >= i) continue;  // none of the wave's rows of this block is above i
+      const int r = ti + S * a;
       const bool on = r < i;
       const double qr = on ? qa[a].x : 0.0, qi = on ? qa[a].y : 0.0;
 #pragma unroll
-      for (int b = a; b < 4; ++b) {  // X_rj = 0 for j < r
-        if (16 * b + 15 < i) continue;
-        const int j = tj + 16 * b;
+      for (int b = a; b < E; ++b) {  // X_rj = 0 for j < r
+        if (S * b + S - 1 < i) continue;
+        const int j = tj + S * b;
         const bool up = j >= i && j < jb;
         const double dx = qr * xb[b].x - qi * xb[b].y, dy = qr * xb[b].y + qi * xb[b].x;
         v[a][b].x -= up ? dx : 0.0;
         v[a][b].y -= up ? dy : 0.0;
       }
     }
-    scale_publish(v, Rs, row, i - 1, ti, tj);  // row i - 1 of X is final
-    __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < E; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ti + 16 * a, j = tj + 16 * b;
+    for (int b = 0; b < E; ++b) {
+      const int i = ti + S * a, j = tj + S * b;
       if (i < jb && j < jb) Rinv[i * ldi + j] = (i <= j) ? v[a][b] : make_double2(0.0, 0.0);
     }
 }
@@ -747,7 +744,7 @@ void add_diag_shift(hipStream_t s, z64 *G, int64_t t, double shift_rel) {
 
 void chol_inv_block(hipStream_t s, z64 *G, int64_t ld, int jb, int col0, int32_t *flag, z64 *Rinv,
                     int64_t ldi) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, s, G, ld, jb, col0, flag, Rinv, ldi);
+  hipLaunchKernelGGL((k_chol_inv<32>), dim3(1), dim3(1024), 0, s, G, ld, jb, col0, flag, Rinv, ldi);
 }
 
 void zero_lower(hipStream_t s, z64 *X, int64_t t, bool all) {
