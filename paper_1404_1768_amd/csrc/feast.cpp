@@ -41,7 +41,8 @@ namespace {
 // ---------------------------------------------------------------------------
 template <typename T>
 void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-               int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info) {
+               int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
+               int32_t *cnt = nullptr) {
   const int ib = feast::leaf_max_width<T>(n - c0);
   if (w <= ib) {
     if (!feast::leaf_lu<T>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info))
@@ -49,10 +50,10 @@ void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, i
     return;
   }
   const int w1 = w / 2, w2 = w - w1;
-  panel_rec<T>(s, M, ld, stride, batch, n, c0, w1, pk0, pkb, ipiv, info);
+  panel_rec<T>(s, M, ld, stride, batch, n, c0, w1, pk0, pkb, ipiv, info, cnt);
   if (w2 <= feast::panel_update_max_width()) {
-    feast::panel_update<T>(s, M, ld, stride, batch, n, c0, w1, w2);
-    panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info);
+    feast::panel_update<T>(s, M, ld, stride, batch, n, c0, w1, w2, nullptr, 1, cnt);
+    panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info, cnt);
     return;
   }
   feast::trsm_small<T>(s, M, ld, stride, batch, c0, w1, w2);
@@ -60,7 +61,7 @@ void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, i
     gemm_t<T>(s, 0, n - c0 - w1, w2, w1, zc(-1.0), M + (c0 + w1) * ld + c0, ld, stride,
               M + c0 * ld + c0 + w1, ld, stride, zc(1.0), M + (c0 + w1) * ld + c0 + w1, ld, stride,
               batch);
-  panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info);
+  panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info, cnt);
 }
 
 struct LuProf {
@@ -130,6 +131,7 @@ struct LuStreams {
   hipStream_t main = nullptr, side = nullptr;
   hipEvent_t cols_ready = nullptr, panel_done = nullptr;
   int update_cfg = feast::GEMM_UPDATE;  // tile of the trailing update
+  int32_t *cnt = nullptr;  // per-matrix counters of the one-launch panel updates (or null)
 };
 
 template <typename T>
@@ -151,8 +153,9 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
     }
   };
   // first panel
+  if (st.cnt) feast::fill_i32(s, st.cnt, batch, 0);
   panel_rec<T>(s, M, ld, stride, batch, n, 0, static_cast<int>(std::min<int64_t>(nb, n)), 0,
-               static_cast<int>(std::min<int64_t>(nb, n)), ipiv, info);
+               static_cast<int>(std::min<int64_t>(nb, n)), ipiv, info, st.cnt);
   for (int64_t k0 = 0; k0 < n; k0 += nb) {
     const int kb = static_cast<int>(std::min<int64_t>(nb, n - k0));
     const int64_t k1 = k0 + kb, rest = n - k1;
@@ -170,7 +173,7 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
       timed_gemm(rest, kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
       HIPCHK(hipEventRecord(st.cols_ready, s));
       HIPCHK(hipStreamWaitEvent(st.side, st.cols_ready, 0));
-      panel_rec<T>(st.side, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
+      panel_rec<T>(st.side, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info, st.cnt);
       HIPCHK(hipEventRecord(st.panel_done, st.side));
       if (rest > kb1)
         timed_gemm(rest, rest - kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1 + kb1,
@@ -178,7 +181,7 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
       HIPCHK(hipStreamWaitEvent(s, st.panel_done, 0));
     } else {
       timed_gemm(rest, rest, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
-      panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
+      panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info, st.cnt);
     }
   }
   const int64_t nblk = (n + kIB - 1) / kIB;
@@ -239,8 +242,10 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     prof.ev = &p->ev;
   }
   hipStream_t sl = s;
+  p->pucnt.alloc(sizeof(int32_t) * N);
   const LuStreams lst{sl, p->o.lookahead ? p->side : nullptr, p->ev_cols, p->ev_panel,
-                      p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE};
+                      p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE,
+                      p->pucnt.as<int32_t>()};
   if (p->mixed()) {
     feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
     lu_batched<c64>(lst, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
@@ -698,7 +703,7 @@ int feast_plan_destroy(feast_plan *p) {
   if (p->ev_panel) (void)hipEventDestroy(p->ev_panel);
   for (hipEvent_t e : {p->ev_fork, p->ev_join})
     if (e) (void)hipEventDestroy(e);
-  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->cirr_w, &p->R,
+  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->pucnt, &p->cirr_w, &p->R,
                     &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->part, &p->nrm,
                     &p->flag, &p->small})
     b->release();

@@ -434,21 +434,18 @@ __global__ __launch_bounds__(256) void k_trsm_small(T *__restrict__ Mall, int64_
 // from an LDS copy of its L21 rows, 8 outputs per thread; X in the matrix is
 // left as it was, because workgroups that start later still read it.
 // write_x = true (one workgroup per matrix, launched afterwards): solve again
-// and store X.  The update is a rank-w1 product with w1 <= 32: it is bound by
-// the traffic of C, so it runs on the VALU.
+// and store X.  With per-matrix counters cnt (zero on entry, zero again on
+// exit) the single launch stores X itself: every workgroup counts itself out
+// after its update, and the last one of a matrix (all the others have read X
+// by then) writes its solved copy.  The update is a rank-w1 product with
+// w1 <= 32: it is bound by the traffic of C, so it runs on the VALU.
 constexpr int kPU = 32;
+// The body of k_panel_update for one workgroup: the small triangular solve
+// into sX, then (write_x = false) the update of this workgroup's 64 rows of C.
 template <typename T>
-__global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int64_t ld_in,
-                                                      int64_t stride, int64_t n_in, int64_t c0,
-                                                      int w1, int w2, bool write_x,
-                                                      const GrpMat *__restrict__ grp, int nodes) {
+__device__ void panel_update_body(T *__restrict__ M, int64_t ld, int64_t n, int64_t c0, int w1,
+                                  int w2, bool write_x, T (*sL)[kPU + 1], T (*sX)[kPU + 1]) {
   using Tr = cplx_traits<T>;
-  __shared__ T sL[64][kPU + 1];
-  __shared__ T sX[kPU][kPU + 1];
-  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, blockIdx.y);
-  T *M = mr.M;
-  const int64_t ld = mr.ld, n = mr.n;
-  if (c0 + w1 + w2 > n) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < w1 * w1; e += 256) {
     const int i = e / w1, k = e % w1;
@@ -491,7 +488,7 @@ __global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int6
   }
   const int64_t r0 = c0 + w1 + static_cast<int64_t>(blockIdx.x) * 64;
   const int rows = static_cast<int>((n - r0 < 64) ? n - r0 : 64);
-  if (rows <= 0) return;
+  if (rows <= 0) return;  // (uniform over the workgroup)
   // L21 rows of this chunk into LDS (sL is free after the solve)
   for (int e = tid; e < rows * w1; e += 256) {
     const int i = e / w1, k = e % w1;
@@ -526,6 +523,41 @@ __global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int6
       if (i < rows && j < w2) M[(r0 + i) * ld + c0 + w1 + j] = acc[a][b];
     }
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int64_t ld_in,
+                                                      int64_t stride, int64_t n_in, int64_t c0,
+                                                      int w1, int w2, bool write_x,
+                                                      const GrpMat *__restrict__ grp, int nodes,
+                                                      int32_t *__restrict__ cnt) {
+  __shared__ T sL[64][kPU + 1];
+  __shared__ T sX[kPU][kPU + 1];
+  __shared__ int s_last;
+  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, blockIdx.y);
+  T *M = mr.M;
+  const int64_t ld = mr.ld, n = mr.n;
+  // (with counters every workgroup reaches the count below: no early return)
+  if (c0 + w1 + w2 > n && !cnt) return;
+  const bool valid = c0 + w1 + w2 <= n;
+  const int tid = threadIdx.x;
+  if (valid) panel_update_body<T>(M, ld, n, c0, w1, w2, write_x, sL, sX);
+  if (cnt) {
+    // (no fence: this workgroup's loads of X completed before the count, their
+    // values having been used; a device-scope release fence here would write
+    // back the whole L2 of the XCD on every workgroup)
+    if (tid == 0) s_last = atomicAdd(&cnt[blockIdx.y], 1) == static_cast<int>(gridDim.x) - 1;
+    __syncthreads();
+    if (s_last) {
+      if (valid)
+        for (int e = tid; e < w1 * w2; e += 256) {
+          const int i = e / w2, j = e % w2;
+          if (i > 0) M[(c0 + i) * ld + c0 + w1 + j] = sX[i][j];
+        }
+      if (tid == 0) atomicExch(&cnt[blockIdx.y], 0);
+    }
+  }
+}
+
 
 // Register layout shared by the 64 x 64 triangular kernels below: 256 threads,
 // thread (ti, tj) = (tid / 16, tid % 16) holds the 16 entries (ti + 16a,
@@ -842,20 +874,25 @@ template void trsm_small<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int
 
 template <typename T>
 void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w1, int w2, const GrpMat *grp, int nodes) {
+                  int64_t c0, int w1, int w2, const GrpMat *grp, int nodes, int32_t *cnt) {
   if (w1 <= 0 || w2 <= 0 || w1 > kPU || w2 > kPU) return;
   const int64_t rows = n - c0 - w1;
   const unsigned chunks = static_cast<unsigned>(rows > 0 ? (rows + 63) / 64 : 1);
+  if (cnt) {  // one launch; the last workgroup of each matrix stores X
+    hipLaunchKernelGGL((k_panel_update<T>), dim3(chunks, batch), dim3(256), 0, s, M, ld, stride, n,
+                       c0, w1, w2, false, grp, nodes, cnt);
+    return;
+  }
   if (rows > 0)
     hipLaunchKernelGGL((k_panel_update<T>), dim3(chunks, batch), dim3(256), 0, s, M, ld, stride, n,
-                       c0, w1, w2, false, grp, nodes);
+                       c0, w1, w2, false, grp, nodes, nullptr);
   hipLaunchKernelGGL((k_panel_update<T>), dim3(1, batch), dim3(256), 0, s, M, ld, stride, n, c0, w1,
-                     w2, true, grp, nodes);
+                     w2, true, grp, nodes, nullptr);
 }
 template void panel_update<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                int, int, const GrpMat *, int);
+                                int, int, const GrpMat *, int, int32_t *);
 template void panel_update<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                int, int, const GrpMat *, int);
+                                int, int, const GrpMat *, int, int32_t *);
 int panel_update_max_width() { return kPU; }
 
 template <typename T>

@@ -101,9 +101,12 @@ void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, 
 // Both halves of one panel recursion step in one launch (w1, w2 <=
 // panel_update_max_width()): X = L11^{-1} X as in trsm_small, then
 // M[c0+w1:n, c0+w1:c0+w1+w2] -= M[c0+w1:n, c0:c0+w1] X.
+//   cnt: optional per-matrix counters (batch of them, zero on entry and left
+//   zero) that let a single launch store the solved X block.
 template <typename T>
 void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w1, int w2, const GrpMat *grp = nullptr, int nodes = 1);
+                  int64_t c0, int w1, int w2, const GrpMat *grp = nullptr, int nodes = 1,
+                  int32_t *cnt = nullptr);
 int panel_update_max_width();
 
 // Inverses of the diagonal blocks of the unit-lower L (lower=true) or of the

@@ -86,7 +86,8 @@ struct feast_plan {
   const void *fA = nullptr, *fB = nullptr;
   int64_t flda = 0, fldb = 0;
   DevBuf F, piv, perm, info, Linv, Uinv;
-  DevBuf Linv2, Uinv2;  // inverted 128 x 128 diagonal blocks (the solves' leaves)
+  DevBuf Linv2, Uinv2;
+  DevBuf pucnt;  // per-node counters of the one-launch panel updates  // inverted 128 x 128 diagonal blocks (the solves' leaves)
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
   DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
