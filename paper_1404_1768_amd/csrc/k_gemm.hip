@@ -233,40 +233,62 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload(kbeg + static_cast<int64_t>(kt + 1) * BK);
-    if (live)
+    if constexpr (M3) {
+      if (live) {
+        // cr accumulates P, ci accumulates Q, t1 accumulates T1 (A negated for
+        // C -= A B).  The operands of k-step kk + 1 are read from LDS while the
+        // MFMAs of step kk issue (two MFMAs per LDS read), so the read latency
+        // hides behind the matrix cores instead of stalling them.
+        real as[2][FM], ai[2][FM], ar[2][FM], br[2][FN], bs[2][FN], bd[2][FN];
+        auto ops = [&](int kk, int o) {
+          const int kr = kk * 4 + krow;
+#pragma unroll
+          for (int a = 0; a < FM; ++a) {
+            const int c = wm * WM + a * 16 + col16;
+            as[o][a] = SUB ? -sAs[buf][kr][c] : sAs[buf][kr][c];
+            ai[o][a] = SUB ? sAi[buf][kr][c] : -sAi[buf][kr][c];  // -Ai for P
+            ar[o][a] = SUB ? -sAr[buf][kr][c] : sAr[buf][kr][c];
+          }
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            const int c = wn * WN + b * 16 + col16;
+            br[o][b] = sBr[buf][kr][c];
+            bs[o][b] = sBs[buf][kr][c];
+            bd[o][b] = sBi[buf][kr][c];
+          }
+        };
+        ops(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+          const int o = kk & 1;
+          if (kk + 1 < BK / 4) ops(kk + 1, o ^ 1);
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) t1[a][b] = Ops::mma(as[o][a], br[o][b], t1[a][b]);
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) cr[a][b] = Ops::mma(ai[o][a], bs[o][b], cr[a][b]);
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) ci[a][b] = Ops::mma(ar[o][a], bd[o][b], ci[a][b]);
+          if (kk + 1 < BK / 4) {
+            // interleave: 3 FM FN MFMAs with the next step's 3 (FM + FN) LDS reads
+#pragma unroll
+            for (int g = 0; g < 3 * (FM + FN); ++g) {
+              __builtin_amdgcn_sched_group_barrier(0x008, (3 * FM * FN) / (3 * (FM + FN)), 0);
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+          }
+        }
+      }
+    } else if (live)
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + krow;
-      if constexpr (M3) {
-        // cr accumulates P, ci accumulates Q, t1 accumulates T1 (A negated for C -= A B)
-        real as[FM], ai[FM], ar[FM], br[FN], bs[FN], bd[FN];
-#pragma unroll
-        for (int a = 0; a < FM; ++a) {
-          const int c = wm * WM + a * 16 + col16;
-          as[a] = SUB ? -sAs[buf][kr][c] : sAs[buf][kr][c];
-          ai[a] = SUB ? sAi[buf][kr][c] : -sAi[buf][kr][c];  // -Ai for P
-          ar[a] = SUB ? -sAr[buf][kr][c] : sAr[buf][kr][c];
-        }
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          const int c = wn * WN + b * 16 + col16;
-          br[b] = sBr[buf][kr][c];
-          bs[b] = sBs[buf][kr][c];
-          bd[b] = sBi[buf][kr][c];
-        }
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-#pragma unroll
-          for (int b = 0; b < FN; ++b) t1[a][b] = Ops::mma(as[a], br[b], t1[a][b]);
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-#pragma unroll
-          for (int b = 0; b < FN; ++b) cr[a][b] = Ops::mma(ai[a], bs[b], cr[a][b]);
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-#pragma unroll
-          for (int b = 0; b < FN; ++b) ci[a][b] = Ops::mma(ar[a], bd[b], ci[a][b]);
-      } else {
+      {
         real ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a) {
@@ -364,15 +386,24 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
 // which costs far more than the multiplications saved.
 template <typename T> constexpr bool kM3 = sizeof(T) == 8;
 
+// Waves per SIMD the register allocation must leave room for (512 registers a
+// lane are shared by the waves of a SIMD): the complex64 64 x 64 tile fits
+// three workgroups per compute unit in LDS, and at 168 registers three also
+// fit the register file; the complex128 64 x 64 tiles fit two at 256 (left to
+// themselves they take over 300, one wave per SIMD).  Neither spills.
+template <typename T, int BM> constexpr int kWaves = BM != 64 ? 1 : (sizeof(T) == 8 ? 3 : 2);
+
 template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool UPD = false>
-__global__ __launch_bounds__(256) void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<T, BM>)))
+void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
   gemm_tile<T, BM, BN, TA, SUB, BK, kM3<T> || UPD>(d, xcd_remap(blockIdx.x, grid_total));
 }
 
 // C_b = C0_b - (shift[b] A2 - A) B_b (FP64: three-product form at BK = 8, as the
 // trailing update).
 template <typename T, int BK>
-__global__ __launch_bounds__(256) void k_gemm_shift(const GemmArgs<T> d, int64_t grid_total) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<T, 64>)))
+void k_gemm_shift(const GemmArgs<T> d, int64_t grid_total) {
   gemm_tile<T, 64, 64, 0, true, BK, true, true>(d, xcd_remap(blockIdx.x, grid_total));
 }
 
