@@ -59,7 +59,8 @@ template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
 // SHF (with SUB, TA = 0): the A operand is shift[b] A2 - A, formed from the two
 // staged tiles in registers before they are written to LDS, and the
 // accumulators start from C0 rather than C (C = C0 - (shift A2 - A) B).
-template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool M3, bool SHF = false>
+template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool M3, bool SHF = false,
+          bool PIPE = true>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
   static_assert(!SHF || (SUB && TA == 0), "shifted operand: C0 - (s A2 - A) B only");
   using Ops = mfma_ops<T>;
@@ -284,17 +285,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
           }
         }
       }
-    } else if (live)
+    } else if (live && !PIPE) {
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int kr = kk * 4 + krow;
-      {
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + krow;
         real ar[FM], ai[FM], br[FN], bi[FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a) {
           ar[a] = sAr[buf][kr][wm * WM + a * 16 + col16];
           ai[a] = sAi[buf][kr][wm * WM + a * 16 + col16];
-          if (SUB) {  // accumulate (-A) B:  Cr += (-Ar) Br - (-Ai) Bi, Ci += (-Ar) Bi + (-Ai) Br
+          if (SUB) {  // accumulate (-A) B
             ar[a] = -ar[a];
             ai[a] = -ai[a];
           }
@@ -304,8 +304,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
           br[b] = sBr[buf][kr][wn * WN + b * 16 + col16];
           bi[b] = sBi[buf][kr][wn * WN + b * 16 + col16];
         }
-        // two sweeps over all tiles: an accumulator is reused only after every
-        // other accumulator of the wave has been issued once
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -320,6 +318,57 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
             cr[a][b] = Ops::mma(-ai[a], bi[b], cr[a][b]);
             ci[a][b] = Ops::mma(ai[a], br[b], ci[a][b]);
           }
+      }
+    } else if (live) {
+      // four real products per complex step, the next step's operands read
+      // while the current MFMAs issue (as above)
+      real ar[2][FM], ai[2][FM], br[2][FN], bi[2][FN];
+      auto ops = [&](int kk, int o) {
+        const int kr = kk * 4 + krow;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+          ar[o][a] = sAr[buf][kr][wm * WM + a * 16 + col16];
+          ai[o][a] = sAi[buf][kr][wm * WM + a * 16 + col16];
+          if (SUB) {  // accumulate (-A) B:  Cr += (-Ar) Br - (-Ai) Bi, Ci += (-Ar) Bi + (-Ai) Br
+            ar[o][a] = -ar[o][a];
+            ai[o][a] = -ai[o][a];
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+          br[o][b] = sBr[buf][kr][wn * WN + b * 16 + col16];
+          bi[o][b] = sBi[buf][kr][wn * WN + b * 16 + col16];
+        }
+      };
+      ops(0, 0);
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int o = kk & 1;
+        if (kk + 1 < BK / 4) ops(kk + 1, o ^ 1);
+        // two sweeps over all tiles: an accumulator is reused only after every
+        // other accumulator of the wave has been issued once
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            cr[a][b] = Ops::mma(ar[o][a], br[o][b], cr[a][b]);
+            ci[a][b] = Ops::mma(ar[o][a], bi[o][b], ci[a][b]);
+          }
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            cr[a][b] = Ops::mma(-ai[o][a], bi[o][b], cr[a][b]);
+            ci[a][b] = Ops::mma(ai[o][a], br[o][b], ci[a][b]);
+          }
+        if (kk + 1 < BK / 4) {
+          // interleave: 4 FM FN MFMAs with the next step's 2 (FM + FN) LDS reads
+#pragma unroll
+          for (int g = 0; g < 2 * (FM + FN); ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, (4 * FM * FN) / (2 * (FM + FN)), 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          }
+        }
       }
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
@@ -410,9 +459,12 @@ void k_gemm_shift(const GemmArgs<T> d, int64_t grid_total) {
 // A group of independent problems in one launch: tab[e].tile0 is the first
 // linear tile of problem e (increasing); a workgroup finds its problem by
 // bisection over the table.
+// (the grouped tiles keep the unpipelined four-product loop: the complex64 one
+// then fits four workgroups per compute unit, 128 registers a lane; the
+// complex128 one takes the two-wave budget of the single-problem tile)
 template <typename T, int BM, int BN, int TA, bool SUB, int BK>
-__global__ __launch_bounds__(256) void k_gemm_grp(const GemmArgs<T> *__restrict__ tab, int count,
-                                                  int64_t grid_total) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 16 ? 2 : 1)))
+void k_gemm_grp(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid_total) {
   const int64_t lin = xcd_remap(blockIdx.x, grid_total);
   int lo = 0, hi = count - 1;
   while (lo < hi) {
@@ -421,7 +473,7 @@ __global__ __launch_bounds__(256) void k_gemm_grp(const GemmArgs<T> *__restrict_
     else hi = mid - 1;
   }
   const GemmArgs<T> d = tab[lo];
-  gemm_tile<T, BM, BN, TA, SUB, BK, false>(d, lin - d.tile0);
+  gemm_tile<T, BM, BN, TA, SUB, BK, false, false, false>(d, lin - d.tile0);
 }
 
 // Deterministic reduction of split-K partials: C = sum_s W_s + beta C.
