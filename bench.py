@@ -41,15 +41,16 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 
 # HBM bytes per launch of the LU trailing update, from two rocprofv3 PMC passes
 # (FETCH_SIZE, then WRITE_SIZE) of this script with --forms mixed,fp64 --steps 1
-# --warmup 0 --no-batched --no-cpu-baseline --copy-calibration, each scaled by
+# --warmup 0 --no-batched --no-cpu-baseline --no-search --no-cirr --no-standin
+# --copy-calibration, each scaled by
 # what the counter reads for the 1 GiB copy of --copy-calibration (fetch x2.000,
 # write x1.000); the summary and the commands are in profiles/.  The figures
 # hold for the kernel source they were taken on (its sha256), else `traffic`
 # is reported as null.
 TRAFFIC = {"source": "paper_1404_1768_amd/csrc/k_gemm.hip",
-           "sha256": "ed670fc6b72e5e6e8bb23e1fc6b720a648f9f67db2d0722a6b6dd80d9f1bd940",
-           "mixed": {"fetch": 1754467822, "write": 1310958338},
-           "fp64": {"fetch": 4147150802, "write": 2621916675}}
+           "sha256": "3ccc6cfe65879770eaf952da486caca5978fdb1bcdb3b6253301a6ec70c721b1",
+           "mixed": {"fetch": 1751955932, "write": 1310956619},
+           "fp64": {"fetch": 4114521508, "write": 2621913237}}
 
 
 def kernel_traffic(form):
