@@ -438,9 +438,11 @@ template <typename T> constexpr bool kM3 = sizeof(T) == 8;
 // Waves per SIMD the register allocation must leave room for (512 registers a
 // lane are shared by the waves of a SIMD): the complex64 64 x 64 tile fits
 // three workgroups per compute unit in LDS, and at 168 registers three also
-// fit the register file; the complex128 64 x 64 tiles fit two at 256 (left to
-// themselves they take over 300, one wave per SIMD).  Neither spills.
-template <typename T, int BM> constexpr int kWaves = BM != 64 ? 1 : (sizeof(T) == 8 ? 3 : 2);
+// fit the register file; the complex128 64 x 64 tiles and the complex64
+// 128 x 64 tiles fit two at 256 (left to themselves they take over 300, one
+// wave per SIMD).  None of them spills; the complex128 128 x 64 tile would.
+template <typename T, int BM>
+constexpr int kWaves = BM != 64 ? (sizeof(T) == 8 ? 2 : 1) : (sizeof(T) == 8 ? 3 : 2);
 
 template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool UPD = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<T, BM>)))
