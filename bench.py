@@ -48,9 +48,9 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # hold for the kernel source they were taken on (its sha256), else `traffic`
 # is reported as null.
 TRAFFIC = {"source": "paper_1404_1768_amd/csrc/k_gemm.hip",
-           "sha256": "3ccc6cfe65879770eaf952da486caca5978fdb1bcdb3b6253301a6ec70c721b1",
-           "mixed": {"fetch": 1751955932, "write": 1310956619},
-           "fp64": {"fetch": 4114521508, "write": 2621913237}}
+           "sha256": "d32b85b0c37481135e912906349db0df3012ca0755d95bf66dc6b234401a8d7d",
+           "mixed": {"fetch": 1752434579, "write": 1310960786},
+           "fp64": {"fetch": 4134227397, "write": 2621921572}}
 
 
 def kernel_traffic(form):

@@ -35,12 +35,17 @@ constexpr double kUlp = std::numeric_limits<double>::epsilon();
 constexpr double kSafmin = std::numeric_limits<double>::min();
 
 struct Mat {
-  int64_t n;
+  int64_t n, ld;
   std::vector<cd> a;
-  explicit Mat(int64_t n_) : n(n_), a(static_cast<size_t>(n_ * n_)) {}
-  cd &operator()(int64_t i, int64_t j) { return a[static_cast<size_t>(j * n + i)]; }
-  cd operator()(int64_t i, int64_t j) const { return a[static_cast<size_t>(j * n + i)]; }
-  cd *col(int64_t j) { return a.data() + j * n; }
+  // columns 64-byte aligned and an odd number of cache lines apart, so that a
+  // walk along a row (the QR sweeps' row rotations) spreads over all cache
+  // sets: with ld = n = 256 every column of a row falls in the same set
+  explicit Mat(int64_t n_)
+      : n(n_), ld(4 * (2 * ((n_ + 7) / 8) + 1)), a(static_cast<size_t>(ld * n_)) {}
+  cd &operator()(int64_t i, int64_t j) { return a[static_cast<size_t>(j * ld + i)]; }
+  cd operator()(int64_t i, int64_t j) const { return a[static_cast<size_t>(j * ld + i)]; }
+  cd *col(int64_t j) { return a.data() + j * ld; }
+  const cd *col(int64_t j) const { return a.data() + j * ld; }
 };
 
 // Plane rotation G = [c s; -conj(s) c] with G [f; g] = [r; 0], c real >= 0.
@@ -322,7 +327,7 @@ int qz_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *
     for (int64_t l = 0; l <= j; ++l) {
       const cd vl = v[l];
       if (vl == cd(0.0)) continue;
-      const cd *zc = Z.a.data() + l * t;
+      const cd *zc = Z.col(l);
       for (int64_t i = 0; i < t; ++i) x[i] += zc[i] * vl;
     }
     double nr = 0.0;
@@ -446,7 +451,7 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
     const cd lam = alpha[j];
     // LU of H0 - lam I (upper Hessenberg, column-major copy in lu): eliminate
     // the subdiagonal with row interchanges between k and k+1
-    for (int64_t q = 0; q < t * t; ++q) lu[q] = H0.a[q];
+    for (int64_t j = 0; j < t; ++j) std::copy(H0.col(j), H0.col(j) + t, lu.data() + j * t);
     for (int64_t k = 0; k < t; ++k) lu[k * t + k] -= lam;
     const double tiny = std::max(kSafmin, kUlp * hnorm);
     for (int64_t k = 0; k + 1 < t; ++k) {
