@@ -17,6 +17,7 @@
 #include "host_eig.h"
 
 #include <algorithm>
+#include <immintrin.h>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -353,6 +354,46 @@ int qz_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *
   return 0;
 }
 
+// The QR sweep's two rotations with AVX2 (two complex numbers a register).
+// Rows (k, k+1) over n columns: p points at entry (k, j0); the pair (k, j),
+// (k+1, j) is adjacent in column-major storage and columns are ld apart:
+//   x' = c x + s y,  y' = m x + c y.
+inline void rot_rows_pair(cd *p, int64_t ld, int64_t n, double c, cd s, cd m) {
+  const __m256d vc = _mm256_set1_pd(c);
+  const __m256d zr = _mm256_setr_pd(s.real(), s.real(), m.real(), m.real());
+  const __m256d zi = _mm256_setr_pd(s.imag(), s.imag(), m.imag(), m.imag());
+  double *d = reinterpret_cast<double *>(p);
+  for (int64_t j = 0; j < n; ++j) {
+    const __m256d v = _mm256_loadu_pd(d + 2 * ld * j);      // [x, y]
+    const __m256d w = _mm256_permute2f128_pd(v, v, 0x01);   // [y, x]
+    const __m256d ws = _mm256_permute_pd(w, 0x5);           // re and im swapped
+    const __m256d zw = _mm256_fmaddsub_pd(w, zr, _mm256_mul_pd(ws, zi));  // [s y, m x]
+    _mm256_storeu_pd(d + 2 * ld * j, _mm256_fmadd_pd(vc, v, zw));
+  }
+}
+
+// Columns x, y over n rows, two rows per step:  x' = c x + a y,  y' = b x + c y.
+inline void rot_cols_pair(cd *x, cd *y, int64_t n, double c, cd a, cd b) {
+  const __m256d vc = _mm256_set1_pd(c);
+  const __m256d ar = _mm256_set1_pd(a.real()), ai = _mm256_set1_pd(a.imag());
+  const __m256d br = _mm256_set1_pd(b.real()), bi = _mm256_set1_pd(b.imag());
+  double *px = reinterpret_cast<double *>(x), *py = reinterpret_cast<double *>(y);
+  int64_t i = 0;
+  for (; i + 2 <= n; i += 2) {
+    const __m256d vx = _mm256_loadu_pd(px + 2 * i), vy = _mm256_loadu_pd(py + 2 * i);
+    const __m256d sx = _mm256_permute_pd(vx, 0x5), sy = _mm256_permute_pd(vy, 0x5);
+    const __m256d ay = _mm256_fmaddsub_pd(vy, ar, _mm256_mul_pd(sy, ai));
+    const __m256d bx = _mm256_fmaddsub_pd(vx, br, _mm256_mul_pd(sx, bi));
+    _mm256_storeu_pd(px + 2 * i, _mm256_fmadd_pd(vc, vx, ay));
+    _mm256_storeu_pd(py + 2 * i, _mm256_fmadd_pd(vc, vy, bx));
+  }
+  for (; i < n; ++i) {
+    const cd xv = x[i], yv = y[i];
+    x[i] = c * xv + a * yv;
+    y[i] = b * xv + c * yv;
+  }
+}
+
 // Pencil with an upper-triangular, well-conditioned Bt (the projected B of the
 // method equals R_2 of the QR of B U_1): the standard problem C = Bt^{-1} At.
 //   1. C by back substitution, reduced to Hessenberg form H0 by Hermitian
@@ -578,21 +619,10 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
         H(k + 1, k - 1) = 0.0;
       }
       // rows (k, k+1), columns k..h
-      const cd mc = -std::conj(sv);
-      for (int64_t j = k; j <= h; ++j) {
-        const cd xv = H(k, j), yv = H(k + 1, j);
-        H(k, j) = c * xv + sv * yv;
-        H(k + 1, j) = mc * xv + c * yv;
-      }
+      rot_rows_pair(H.col(k) + k, H.ld, h - k + 1, c, sv, -std::conj(sv));
       // columns (k, k+1), rows l..min(k+2, h)
-      const cd sc = std::conj(sv);
-      cd *cp = H.col(k), *cq = H.col(k + 1);
       const int64_t i1 = std::min(k + 2, h);
-      for (int64_t i = l; i <= i1; ++i) {
-        const cd xv = cp[i], yv = cq[i];
-        cp[i] = c * xv + sc * yv;
-        cq[i] = -sv * xv + c * yv;
-      }
+      rot_cols_pair(H.col(k) + l, H.col(k + 1) + l, i1 - l + 1, c, std::conj(sv), -sv);
     }
   }
   if (rc == 0 && t > 0) {
