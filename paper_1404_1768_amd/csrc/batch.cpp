@@ -112,7 +112,8 @@ struct feast_batch {
   feast_opts o{};
   hipStream_t s = nullptr;   // caller's stream
   hipStream_t gs = nullptr;  // the batch's own stream (graphs are captured and replayed here)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t as = nullptr;  // Ritz vectors and residuals while a filter runs on gs
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_proj = nullptr;
   std::vector<int> order;     // internal index -> caller index
   std::vector<int> where;     // caller index -> internal index
   std::vector<int64_t> n, m, np;
@@ -775,8 +776,10 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
     b->where.resize(P);
     for (int p = 0; p < P; ++p) b->where[b->order[p]] = p;
     HIPCHK(hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&b->as, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_proj, hipEventDisableTiming));
     int64_t fo = 0, yo = 0, to = 0;
     for (int p = 0; p < P; ++p) {
       const int i = b->order[p];
@@ -852,6 +855,7 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
 int feast_batch_destroy(feast_batch *b) {
   if (!b) return FEAST_OK;
   if (b->gs) (void)hipStreamSynchronize(b->gs);
+  if (b->as) (void)hipStreamSynchronize(b->as);
   b->g_factor.reset();
   b->g_filter.reset();
   for (feast_plan *p : b->sub) feast_plan_destroy(p);
@@ -861,7 +865,9 @@ int feast_batch_destroy(feast_batch *b) {
     d->release();
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->ev_proj) (void)hipEventDestroy(b->ev_proj);
   if (b->gs) (void)hipStreamDestroy(b->gs);
+  if (b->as) (void)hipStreamDestroy(b->as);
   delete b;
   return FEAST_OK;
 }
@@ -999,6 +1005,29 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
     const int nthreads =
         static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
     for (int k = 1; k <= b->o.max_iter; ++k) {
+      // line 16 of the first iteration ahead of time: the next filter needs
+      // only B U_1, so it runs on gs while the host solves the reduced pencils
+      // and the Ritz vectors and residuals go to the second stream (a pencil
+      // that stops at k = 1 has its filter computed for nothing; the grouped
+      // filter covers every pencil anyway).  Later iterations, usually the
+      // last, run in order.
+      const bool spec = (k == 1);
+      hipStream_t rs = s;
+      if (spec) {
+        Timer tf;
+        HIPCHK(hipEventRecord(b->ev_proj, s));
+        HIPCHK(hipStreamWaitEvent(b->as, b->ev_proj, 0));
+        rs = b->as;
+        for (int p = 0; p < P; ++p)
+          if (!st[p].done)
+            feast::copy_block_z(s, b->sub[p]->wblk(feast_plan::W_BU1), b->m[p], b->n[p], b->m[p],
+                                b->sub[p]->R.as<z64>(), b->m[p]);
+        if (b->mixed()) base_sweeps = 1;  // (the first refined filter: one correction)
+        sweeps = b->mixed() ? base_sweeps : 0;
+        filter_all(b, dA, lda, dB, ldb, sweeps);
+        inf.filters += 1;
+        inf.t_filter_ms += tf.ms();
+      }
       // line 6 for every active pencil, in parallel on the host
       Timer te;
       std::vector<int> act;
@@ -1031,21 +1060,21 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
                                                          : feast_z{0, 0};
         }
         z64 *Ys = q->gblk(feast_plan::G_YS), *dlam = q->small.as<z64>();
-        HIPCHK(hipMemcpyAsync(Ys, st[p].Yh.data(), sizeof(z64) * m * m, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(dlam, st[p].lam.data(), sizeof(z64) * m, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(Ys, st[p].Yh.data(), sizeof(z64) * m * m, hipMemcpyHostToDevice, rs));
+        HIPCHK(hipMemcpyAsync(dlam, st[p].lam.data(), sizeof(z64) * m, hipMemcpyHostToDevice, rs));
         const z64 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
-        gemm_t<z64>(s, 0, n, m, m, one, q->wblk(feast_plan::W_U1), m, 0, Ys, m, 0, zero,
+        gemm_t<z64>(rs, 0, n, m, m, one, q->wblk(feast_plan::W_U1), m, 0, Ys, m, 0, zero,
                     q->wblk(feast_plan::W_X), m, 0, 1);
-        gemm_t<z64>(s, 0, n, m, m, one, q->wblk(feast_plan::W_AU1), m, 0, Ys, m, 0, zero,
+        gemm_t<z64>(rs, 0, n, m, m, one, q->wblk(feast_plan::W_AU1), m, 0, Ys, m, 0, zero,
                     q->wblk(feast_plan::W_AX), m, 0, 1);
-        gemm_t<z64>(s, 0, n, m, m, one, q->wblk(feast_plan::W_BU1), m, 0, Ys, m, 0, zero,
+        gemm_t<z64>(rs, 0, n, m, m, one, q->wblk(feast_plan::W_BU1), m, 0, Ys, m, 0, zero,
                     q->wblk(feast_plan::W_BX), m, 0, 1);
-        feast::ritz_norms(s, q->wblk(feast_plan::W_AX), q->wblk(feast_plan::W_BX), m, n, m, dlam,
+        feast::ritz_norms(rs, q->wblk(feast_plan::W_AX), q->wblk(feast_plan::W_BX), m, n, m, dlam,
                           q->part.as<double>(), q->nrm.as<double>());
         HIPCHK(hipMemcpyAsync(st[p].hn.data(), q->nrm.p, sizeof(double) * 3 * m,
-                              hipMemcpyDeviceToHost, s));
+                              hipMemcpyDeviceToHost, rs));
       }
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipStreamSynchronize(rs));
       // lines 10-15 per pencil
       bool refine_more = false;
       for (int p : act) {
@@ -1074,9 +1103,9 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
         if (a == 1 || a == -1) {
           if (c_k > 0) {
             HIPCHK(hipMemcpy(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice));
-            feast::gather_normalize_cols(s, q->wblk(feast_plan::W_X), m, n, didx, c_k,
+            feast::gather_normalize_cols(rs, q->wblk(feast_plan::W_X), m, n, didx, c_k,
                                          reinterpret_cast<z64 *>(dX[c]), ldx[c], nullptr);
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipStreamSynchronize(rs));
           }
           for (int i = 0; i < c_k; ++i) {
             hLambda[c][i] = {lam[p][sel[i]].real(), lam[p][sel[i]].imag()};
@@ -1091,7 +1120,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
         }
         if (a == 0) {
           const int cp = static_cast<int>(st[p].lam_prev.size());
-          feast::copy_block_z(s, q->wblk(feast_plan::W_XPREV), m, n, cp,
+          feast::copy_block_z(rs, q->wblk(feast_plan::W_XPREV), m, n, cp,
                               reinterpret_cast<z64 *>(dX[c]), ldx[c]);
           for (int i = 0; i < cp; ++i) {
             hLambda[c][i] = {st[p].lam_prev[i].real(), st[p].lam_prev[i].imag()};
@@ -1110,7 +1139,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
         for (int i = 0; i < c_k; ++i) st[p].lam_prev.push_back(lam[p][sel[i]]);
         if (c_k > 0) {
           HIPCHK(hipMemcpy(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice));
-          feast::gather_normalize_cols(s, q->wblk(feast_plan::W_X), m, n, didx, c_k,
+          feast::gather_normalize_cols(rs, q->wblk(feast_plan::W_X), m, n, didx, c_k,
                                        q->wblk(feast_plan::W_XPREV), m, nullptr);
         }
         if (b->mixed() && k >= 2 && c_k == st[p].c_prev && e_k >= b->o.eps &&
@@ -1119,6 +1148,9 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
         st[p].e_prev = e_k;
         st[p].c_prev = c_k;
       }
+      // (the second stream's gathers and copies of this iteration are done
+      // before the results are returned or the next projection overwrites U_1)
+      if (rs != s) HIPCHK(hipStreamSynchronize(rs));
       inf.iters = k;
       bool any = false;
       for (int p = 0; p < P; ++p) any = any || !st[p].done;
@@ -1127,21 +1159,27 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       // mixed form: as feast_solve, one grouped sweep count for all pencils --
       // refined once any pencil still iterating has e(k) <= 1e-4 (or on the
       // first filter after Search), one more on a stall
-      int sweeps_now = 0;
-      if (b->mixed()) {
-        if (base_sweeps == 0) base_sweeps = 1;
-        else if (refine_more && base_sweeps < b->o.max_sweeps) ++base_sweeps;
-        bool close = (k == 1);
+      if (spec) {
+        Timer tw;
+        HIPCHK(hipStreamSynchronize(s));  // the filter launched ahead
+        inf.t_filter_ms += tw.ms();
+      } else {
+        int sweeps_now = 0;
+        if (b->mixed()) {
+          if (base_sweeps == 0) base_sweeps = 1;
+          else if (refine_more && base_sweeps < b->o.max_sweeps) ++base_sweeps;
+          bool close = false;
+          for (int p = 0; p < P; ++p)
+            if (!st[p].done && std::isfinite(st[p].e_prev) && st[p].e_prev <= 1e-4) close = true;
+          sweeps_now = close ? base_sweeps : 0;
+        }
+        sweeps = sweeps_now;
         for (int p = 0; p < P; ++p)
-          if (!st[p].done && std::isfinite(st[p].e_prev) && st[p].e_prev <= 1e-4) close = true;
-        sweeps_now = close ? base_sweeps : 0;
+          if (!st[p].done)
+            feast::copy_block_z(s, b->sub[p]->wblk(feast_plan::W_BU1), b->m[p], b->n[p], b->m[p],
+                                b->sub[p]->R.as<z64>(), b->m[p]);
+        grouped_filter();
       }
-      sweeps = sweeps_now;
-      for (int p = 0; p < P; ++p)
-        if (!st[p].done)
-          feast::copy_block_z(s, b->sub[p]->wblk(feast_plan::W_BU1), b->m[p], b->n[p], b->m[p],
-                              b->sub[p]->R.as<z64>(), b->m[p]);
-      grouped_filter();
       const int r = project_active();
       if (r != FEAST_OK) return r;
     }
