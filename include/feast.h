@@ -161,9 +161,11 @@ typedef struct {
  * Selection (line 10): |lambda - center| < radius and r_i < eta; when nothing
  * is selected e(k) = +inf and lines 13-14 are skipped.  Mixed plans apply
  * fixed FP64 refinement sweeps per filter (the accuracy is judged by e(k)):
- * none on the first filter, one on later filters, one more whenever an
- * iteration with a settled count misses eps without at least halving e(k)
- * (at most max_sweeps).  Synchronises the stream. */
+ * none on the first filter, one on later filters; once an iteration with a
+ * settled count misses eps without at least halving e(k), every later filter
+ * refines each node until its normwise backward error reaches refine_tol (at
+ * most max_sweeps; a filter already launched is refined further from its
+ * node solutions).  Synchronises the stream. */
 int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
                 int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *hLambda,
                 feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, double *err,
@@ -353,10 +355,12 @@ int feast_batch_filter(feast_batch *batch, const feast_z *const *dA, const int64
  * stopped keep their result).  Per pencil p: hLambda[p] (host, >= m[p]
  * entries), dX[p] (device n x m, leading dimension ldx[p]), hRes[p] (host,
  * >= m[p], may be NULL as a whole array), s_found[p], err[p], flag[p],
- * iters[p] (host arrays of count entries).  Mixed plans refine as
- * feast_solve does (no refinement on the first filter, one correction per
- * node afterwards, one more whenever a refined iteration misses eps without
- * at least halving e(k)).
+ * iters[p] (host arrays of count entries).  Mixed plans refine with one
+ * grouped sweep count: none on the first filter, one correction per node
+ * afterwards, one more whenever a refined iteration of some pencil misses eps
+ * without at least halving e(k) (at most max_sweeps).  The second filter is
+ * launched before the first iteration's host eigensolves (a pencil that stops
+ * there has had it computed for nothing).
  * info may be NULL. */
 int feast_batch_solve(feast_batch *batch, const feast_z *const *dA, const int64_t *lda,
                       const feast_z *const *dB, const int64_t *ldb, const feast_z *const *dV,
