@@ -144,3 +144,25 @@ def test_batch_full_workload_counts_and_spectrum():
             p = ps[i]
             ref = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, eps=1e-10, max_iter=20)
             check_eigenvalues(r.lam[i], ref.lam, p.radius)
+
+
+@pytest.mark.parametrize("prec", [fm.FP64, fm.MIXED])
+def test_batch_single_iteration_stops_every_pencil_at_line_15(prec):
+    """max_iter = 1: every pencil stops at k = 1 by line 15 (flag -1) while the
+    second filter, launched ahead of the host eigensolves, is still in flight;
+    the first iteration's Ritz pairs match the oracle's."""
+    ps = small_batch()[:4]
+    As, Bs, Vs = [to_dev(p.A) for p in ps], [to_dev(p.B) for p in ps], [to_dev(p.V) for p in ps]
+    with make_batch(ps, prec, max_iter=1) as b:
+        r = b.solve(As, Bs, Vs)
+        r2 = b.solve(As, Bs, Vs)  # the batch is reusable after the filter left in flight
+    for i, p in enumerate(ps):
+        assert r.flag[i] == -1 and r2.flag[i] == -1
+        ref = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, max_iter=1)
+        assert ref.flag == -1
+        assert len(r.lam[i]) == len(ref.lam) == len(r2.lam[i])
+        tol = 1e-9 if prec == fm.FP64 else 1e-4  # (one unrefined complex64 filter)
+        C = np.abs(r.lam[i][:, None] - ref.lam[None, :])
+        ri, ci = linear_sum_assignment(C)
+        assert np.max(C[ri, ci]) <= tol * max(1.0, abs(p.center) + p.radius)
+        assert np.allclose(np.sort_complex(r.lam[i]), np.sort_complex(r2.lam[i]), rtol=0, atol=1e-12)
