@@ -20,11 +20,12 @@ batched form on its own workload: 64 independent pencils of order n in
 circle, N = 16 nodes, m = 2 floor(n/20), solved together in both forms.
 Further keys time the other rows on their own workloads: "search" (Algorithm 4
 then Algorithm 5 on the metric's pencil), "cirr" (Block_CIRR, Algorithm 1, on
-the same pencil) and "standin" (dense stand-ins of the two largest problems of
+the same pencil), "adjoint" (forward solve and gradient of sum |lambda|^2 on the
+n = 2048 pencil) and "standin" (dense stand-ins of the two largest problems of
 Table 1 with the Gauss-Legendre rule).
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--forms fp64,mixed] [--no-batched]
-                    [--no-search] [--no-cirr] [--no-standin] [--no-cpu-baseline]
+                    [--no-search] [--no-cirr] [--no-adjoint] [--no-standin] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -220,6 +221,52 @@ def time_standin(ks, steps, warmup):
             "problems": out}
 
 
+def time_adjoint(steps, warmup):
+    """The adjoint form on its workload: n = 2048, 40 eigenvalues in the unit
+    circle, N = 32, m = 64, FP64.  One step = the forward solve (factorisation
+    included) and the backward pass of L = sum |lambda_i|^2 through
+    feast_eig (left eigenvectors by 3 adjoint sweeps on the forward factors,
+    then the rank-s gradient assembly of dL/dA and dL/dB)."""
+    import numpy as np
+    import torch
+    import pencilgen as pg
+    import paper_1404_1768_amd as fm
+    p = pg.workload(5)
+    A, B, V = (torch.from_numpy(x).to("cuda:0") for x in (p.A, p.B, p.V))
+    A.requires_grad_(True)
+    B.requires_grad_(True)
+    plan = fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=fm.FP64)
+    try:
+        def step():
+            plan.invalidate()
+            A.grad = None
+            B.grad = None
+            t0 = time.perf_counter()
+            lam = fm.feast_eig(A, B, V, plan)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            (lam.abs() ** 2).sum().backward()
+            torch.cuda.synchronize()
+            return lam, (t1 - t0) * 1e3, (time.perf_counter() - t1) * 1e3
+        for _ in range(warmup):
+            step()
+        fw, bw = [], []
+        for _ in range(steps):
+            lam, f, b = step()
+            fw.append(f)
+            bw.append(b)
+        ok = (len(lam) == p.s and bool(torch.isfinite(A.grad).all()) and
+              bool(torch.isfinite(B.grad).all()))
+        out = {"workload": "pencil n=2048 N=32 m=64 s=40 (circle 0, r=1), FP64, "
+                           "L = sum |lambda_i|^2, 3 adjoint sweeps",
+               "ms": (sum(fw) + sum(bw)) / steps, "forward_ms": sum(fw) / steps,
+               "backward_ms": sum(bw) / steps, "count": len(lam), "ok": ok}
+        log("[bench] adjoint: %s" % out)
+        return out
+    finally:
+        plan.close()
+
+
 def time_batch(ps, As, Bs, Vs, steps, warmup):
     """Workload of 64 pencils: one step = a complete batched solve of every
     pencil (factorisations of all 1024 shifted matrices included)."""
@@ -313,6 +360,8 @@ def main():
                     help="skip the Search (Algorithm 4) + Algorithm 5 leg (key 'search')")
     ap.add_argument("--no-standin", action="store_true",
                     help="skip the Table 1 stand-in leg (key 'standin')")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint (gradient) leg (key 'adjoint')")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 1 GiB (3 launches): the reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a PMC run")
@@ -374,6 +423,9 @@ def main():
     cirr = None
     if not args.no_cirr:
         cirr = time_cirr(p, A, B, V, min(args.steps, 3), 1)
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = time_adjoint(min(args.steps, 3), 1)
     standin = None
     if not args.no_standin:
         standin = time_standin((6, 7), min(args.steps, 2), 1)
@@ -397,7 +449,8 @@ def main():
         "config": {"workload": "pencil n=4000 N=32 m=160 s=100 (trapezoid, circle 1+1i r=1)",
                    "form": best, "n": p.n, "nodes": p.nodes, "m": p.m, "eps": 1e-10},
         "forms": forms, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
-        "search": search, "cirr": cirr, "standin": standin, "large": large,
+        "search": search, "cirr": cirr, "adjoint": adjoint, "standin": standin,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
 
