@@ -109,7 +109,7 @@ def time_search(p, A, B, steps, warmup):
     """Algorithm 4 then Algorithm 5 from its basis (mixed form) on the same
     pencil, without the caller's m: p = 50 Gaussian start columns, alpha = 1.5,
     tau = 1e-3, subspace capacity 240.  One step = factorisation + Search +
-    Algorithm 5 lines 2-18 (Search's filters are the first application)."""
+    Algorithm 5 after its Search call (Search's filters are the first application)."""
     import numpy as np
     import torch
     import paper_1404_1768_amd as fm

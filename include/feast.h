@@ -70,9 +70,9 @@ typedef struct {
 
 /* Options of Algorithm 5 and of the implementation. */
 typedef struct {
-  double eps;          /* line 13 tolerance on e(k) = max r_i (default 1e-10) */
-  double eta;          /* line 10 tolerance separating true from spurious pairs (default 1e-3) */
-  int32_t max_iter;    /* line 15 (default 20) */
+  double eps;          /* convergence tolerance on e(k) = max r_i (default 1e-10) */
+  double eta;          /* selection tolerance separating true from spurious pairs (default 1e-3) */
+  int32_t max_iter;    /* iteration cap (default 20) */
   int32_t prec;        /* enum feast_prec (default FEAST_FP64) */
   double refine_tol;   /* mixed form: per-node normwise backward-error target of the
                           final filter (default 4*2^-53) */
@@ -108,7 +108,7 @@ int feast_plan_destroy(feast_plan *plan);
 /* Drop the cached factors (A or B changed in place). */
 int feast_plan_invalidate(feast_plan *plan);
 
-/* The filter of eq. (8-4) applied to a block (Algorithm 5 line 16):
+/* The filter of eq. (8-4) applied to a block (Algorithm 5, filter step):
  *   U = sum_j w_j (z_j B - A)^{-1} B V,   V, U: n x m.
  * The first call (or the first after feast_plan_invalidate, or with other dA/dB)
  * factors every z_j B - A with partial pivoting and caches the factors.
@@ -120,7 +120,7 @@ int feast_plan_invalidate(feast_plan *plan);
 int feast_filter(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
                  int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *dU, int64_t ldu);
 
-/* Oblique projection (Algorithm 5 lines 2, 5 and 17; eqs. 6-3-13, 7-10):
+/* Oblique projection (Algorithm 5: its QR steps and the reduced pencil; eqs. 6-3-13, 7-10):
  *   U = U_1 R_1 (QR),  B U_1 = U_2 R_2 (QR),
  *   At = U_2^* A U_1,  Bt = U_2^* B U_1   (m x m, written to host memory).
  * In: dU (n x m).  Out: dU overwritten by the orthonormal U_1; dAU1 = A U_1 and
@@ -149,17 +149,17 @@ typedef struct {
   double lu_gemm_flops;
 } feast_info;
 
-/* GFEAST (Algorithm 5, lines 1-18) with the subspace size fixed to m and a
- * caller-supplied start block V in place of Search (line 1 becomes one filter
+/* GFEAST (Algorithm 5) with the subspace size fixed to m and a caller-supplied
+ * start block V in place of Search (the Search call becomes one filter
  * application of V followed by QR):
  *   outputs: *s_found selected eigenpairs; hLambda[0..s_found) their eigenvalues
  *   (host, capacity m); dX columns 0..s_found-1 their eigenvectors (device,
  *   n x m, unit 2-norm, largest-modulus entry real positive); hRes[0..s_found)
  *   their residuals r_i of eq. (5-1) (host, capacity m, may be NULL);
- *   *err = Err; *flag = 1 (line 13), 0 (line 14, previous iterate returned),
- *   -1 (line 15); info (may be NULL) the per-iteration record.
- * Selection (line 10): |lambda - center| < radius and r_i < eta; when nothing
- * is selected e(k) = +inf and lines 13-14 are skipped.  Mixed plans apply
+ *   *err = Err; *flag = 1 (converged), 0 (no improvement, previous iterate
+ *   returned), -1 (iteration cap reached); info (may be NULL) the per-iteration record.
+ * Selection: |lambda - center| < radius and r_i < eta; when nothing is
+ * selected e(k) = +inf and the two count-based stops are skipped.  Mixed plans apply
  * fixed FP64 refinement sweeps per filter (the accuracy is judged by e(k)):
  * none on the first filter, one on later filters; once an iteration with a
  * settled count misses eps without at least halving e(k), every later filter
@@ -182,16 +182,16 @@ typedef struct feast_cirr_info {
 } feast_cirr_info;
 
 /* Algorithm 1 with the plan's contour and quadrature:
- *   step 1: R_i = sum_j w_j mu_j^i (z_j B - A)^{-1} Y, i = 0..g-1, with the
+ *   moments: R_i = sum_j w_j mu_j^i (z_j B - A)^{-1} Y, i = 0..g-1, with the
  *           shifted, scaled powers mu_j = (z_j - center)/radius (the same span
  *           as z_j^i for i < g, better scaled) -- the quadrature of F_i Y of
  *           eq. (2-2-21);
- *   step 2: an orthonormal basis U of span[R_0 .. R_{g-1}] (shifted Cholesky
+ *   basis: an orthonormal basis U of span[R_0 .. R_{g-1}] (shifted Cholesky
  *           QR3; Rayleigh-Ritz depends on the span only, so this gives the
  *           eigenvalues of the SVD's left factor);
- *   steps 3-4: eigenpairs of (U^* A U, U^* B U) on the host (QZ);
- *   step 5: x_i = U y_i; selected: |lambda - center| < radius and r_i < eta
- *           (eq. 5-1), as Algorithm 5 line 10.
+ *   reduced pencil: eigenpairs of (U^* A U, U^* B U) on the host (QZ);
+ *   Ritz pairs: x_i = U y_i; selected: |lambda - center| < radius and
+ *           r_i < eta (eq. 5-1), as in Algorithm 5's selection.
  * dY: device, n x h (leading dimension ldy >= h), the random block; h g <= m.
  * Outputs as feast_solve: hLambda/hRes (host, capacity m), dX (device n x m,
  * leading dimension ldx >= m), *s_found.  Mixed plans refine the node
@@ -229,19 +229,19 @@ int feast_region_select(int32_t nv, const feast_z *vertices, int64_t k, const fe
 
 typedef struct feast_search_info {
   int64_t t;        /* numerical rank of the last block: the upper bound of s */
-  int64_t s0;       /* trace estimate ceil(Re trace(Y_0^* U) / p) (line 2) */
+  int64_t s0;       /* trace estimate ceil(Re trace(Y_0^* U) / p) */
   int64_t used;     /* columns of the random pool consumed */
-  int32_t rounds;   /* rank tests performed (line 9) */
+  int32_t rounds;   /* rank-revealing tests performed */
   int32_t filters;  /* filter applications */
   double ms;        /* wall time of the call */
 } feast_search_info;
 
 /* Algorithm 4 on the plan's cached factors (factored first if needed):
- *   line 1: U = Q_N Y_0 for the first p columns Y_0 of the pool dY;
- *   line 2: s_0 = ceil(Re trace(Y_0^* U) / p), s_dagger = min(max(p, s_0), m);
- *   lines 3-8: U gets s_dagger - p more filtered columns from the pool, in order;
- *   line 9: rank-revealing step; line 10: t = numerical rank; if t < s_dagger
- *   stop, else U = U_1, p = t, s_dagger = min(ceil(alpha t), m) and repeat.
+ *   first sample: U = Q_N Y_0 for the first p columns Y_0 of the pool dY;
+ *   trace estimate: s_0 = ceil(Re trace(Y_0^* U) / p),
+ *     s_dagger = min(max(p, s_0), m);
+ *   widening: U gets s_dagger - p more filtered columns from the pool, in order;
+ *   rank test: rank-revealing step, t = numerical rank; if t < s_dagger stop, else U = U_1, p = t, s_dagger = min(ceil(alpha t), m) and repeat.
  * dY: device, n x ycols (leading dimension ldy >= ycols), entries N(0,1) drawn
  * by the caller (the paper's Y is real: pass zero imaginary parts); columns are
  * consumed left to right.  The numerical rank counts |R_jj| >= tau |R_00| of
@@ -265,8 +265,8 @@ int feast_search(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z
  * Algorithm 5 with Search's t. */
 int feast_plan_set_m(feast_plan *plan, int64_t m);
 
-/* Algorithm 5 lines 2-18 from Search's basis: dU1 (device, n x m, leading
- * dimension ldu >= m, orthonormal, already filtered) is U_1 of line 2; the
+/* Algorithm 5 after its Search call, from Search's basis: dU1 (device, n x m,
+ * leading dimension ldu >= m, orthonormal, already filtered) is Search's U_1; the
  * outputs are those of feast_solve (info->filters counts this call's filters
  * only). */
 int feast_solve_from(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
@@ -372,7 +372,7 @@ int feast_batch_solve(feast_batch *batch, const feast_z *const *dA, const int64_
  * Host-side pieces of Algorithm 5 (no device needed)
  * ------------------------------------------------------------------------- */
 
-/* All eigenpairs of the t x t pencil At y = lambda Bt y (Algorithm 5 line 6;
+/* All eigenpairs of the t x t pencil At y = lambda Bt y (Algorithm 5, reduced eigenproblem;
  * the paper solves it with an xGGEV-type solver): complex QZ.  Inputs are
  * row-major with leading dimensions lda, ldb and are not modified.  Outputs:
  * halpha, hbeta (t each; lambda_i = alpha_i/beta_i, beta_i = 0 for an infinite
@@ -382,10 +382,10 @@ int feast_batch_solve(feast_batch *batch, const feast_z *const *dA, const int64_
 int feast_reduced_eig(int64_t t, const feast_z *hAt, int64_t lda, const feast_z *hBt,
                       int64_t ldb, feast_z *halpha, feast_z *hbeta, feast_z *hY, int64_t ldy);
 
-/* Stopping rules of Algorithm 5 (lines 13-15) after iteration k.  Returns 1
- * (line 13: c(k) = c(k-1) and e(k) < eps), 0 (line 14: c(k) = c(k-1) and
- * e(k) > e(k-1)), -1 (line 15: k = max_iter) or 2 (continue).  Lines 13-14
- * are skipped when c_k = 0; line 13 is tested before 14. */
+/* Stopping rules of Algorithm 5 after iteration k.  Returns 1 (converged:
+ * c(k) = c(k-1) and e(k) < eps), 0 (no improvement: c(k) = c(k-1) and
+ * e(k) > e(k-1)), -1 (iteration cap: k = max_iter) or 2 (continue).  The two
+ * count-based rules are skipped when c_k = 0; convergence is tested first. */
 int feast_stop_rule(int32_t k, int32_t c_k, double e_k, int32_t c_prev, double e_prev,
                     double eps, int32_t max_iter);
 

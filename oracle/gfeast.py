@@ -19,7 +19,7 @@ notes of the repository):
   circle integral of eq. (8-4); Gauss-Legendre with ``theta_j = (1 + t_j) pi``
   and ``w_j = omega_j (z_j - gamma)/2`` is eq. (8-4) itself.
 * Sign: shifted systems are ``(z_j B - A) Y_j = B U_1`` as in eq. (4-4).
-* GFEAST line 1 with a fixed subspace size ``t = m`` and a caller-supplied
+* GFEAST's Search call with a fixed subspace size ``t = m`` and a caller-supplied
   start block ``V``: ``U_1`` is the orthonormal factor of the filtered block
   ``Q_N V`` (the remark after Algorithm 4: its ``U_1`` is a projection onto the
   eigenspace, i.e. the first filter application).  ``search`` is Algorithm 4
@@ -28,8 +28,10 @@ notes of the repository):
   and the numerical rank of the column-pivoted ``R`` counts the diagonal
   entries with ``|R_ii| >= tau |R_11|`` (the paper names rank-revealing QR but
   no threshold).
-* Line 17 takes the QR of ``B U_1`` with the new ``U_1`` (same span as ``B U``).
-* Empty selection: ``e(k) = +inf`` and the rules of lines 13-14 are skipped.
+* The QR step at the end of each iteration factors ``B U_1`` with the new
+  ``U_1`` (same span as ``B U``).
+* Empty selection: ``e(k) = +inf`` and the two rules that compare ``c(k)``
+  with ``c(k-1)`` are skipped.
 * ``lambda`` inside means ``|lambda - gamma| < rho`` (strict); infinite
   eigenvalues (``beta = 0``) are outside.
 """
@@ -162,7 +164,7 @@ def orth(X: np.ndarray):
 
 def project(A: np.ndarray, B: np.ndarray, U1: np.ndarray, U2: np.ndarray):
     """Oblique projection with trial space span(U_1) and test space span(U_2) = B K
-    (eqs. 6-3-12, 6-3-13, 7-10; Algorithm 5 line 5):
+    (eqs. 6-3-12, 6-3-13, 7-10; the reduced pencil of Algorithm 5):
     ``At = U_2^* A U_1``, ``Bt = U_2^* B U_1``."""
     U2h = U2.conj().T
     return U2h @ (A @ U1), U2h @ (B @ U1)
@@ -195,7 +197,7 @@ def normalize_columns(X: np.ndarray) -> np.ndarray:
 
 def residuals(A: np.ndarray, B: np.ndarray, lam: np.ndarray, X: np.ndarray) -> np.ndarray:
     """Relative residuals ``r_i = ||A x_i - lambda_i B x_i|| / (||A x_i|| + ||B x_i||)``
-    (eq. 5-1; Algorithm 5 line 9).  Infinite ``lambda_i`` give ``+inf``."""
+    (eq. 5-1; Algorithm 5's residual).  Infinite ``lambda_i`` give ``+inf``."""
     AX, BX = A @ X, B @ X
     r = np.full(X.shape[1], np.inf)
     for i in range(X.shape[1]):
@@ -217,13 +219,13 @@ def inside(lam: np.ndarray, center: complex, radius: float) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Stopping rules (Algorithm 5 lines 12-15; Section 4.2)
+# Stopping rules (Algorithm 5; Section 4.2)
 # ---------------------------------------------------------------------------
 
 CONTINUE = 2
-CONVERGED = 1      # line 13
-REBOUND = 0        # line 14: previous iterate is returned
-MAX_ITER = -1      # line 15
+CONVERGED = 1      # same count and e(k) < eps
+REBOUND = 0        # same count and e(k) > e(k-1): previous iterate is returned
+MAX_ITER = -1      # k = max_iter
 
 
 def stop_rule(k: int, c_k: int, e_k: float, c_prev: int, e_prev: float,
@@ -261,15 +263,15 @@ class Result:
 def gfeast(A: np.ndarray, B: np.ndarray, V: np.ndarray, center: complex, radius: float,
            N: int, rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
            max_iter: int = 20, solver: Optional[ShiftedSolver] = None) -> Result:
-    """Algorithm 5 lines 1-18 with ``t = V.shape[1]`` fixed.
+    """Algorithm 5 with ``t = V.shape[1]`` fixed.
 
-    Line 1 (Search) becomes one filter application of the start block ``V``
-    followed by QR; the loop then follows lines 2-18.
+    The Search call becomes one filter application of the start block ``V``
+    followed by QR; the rest follows Algorithm 5 in order.
     """
     z, w = contour_nodes(center, radius, N, rule)
     if solver is None:
         solver = ShiftedSolver(A, B, z)
-    # line 1 (Search with fixed t): U = Q_N V, U_1 = orth(U)
+    # Search with fixed t: U = Q_N V, U_1 = orth(U)
     U = apply_filter(solver, w, V)
     U1, _ = orth(U)
     return gfeast_from(A, B, U1, center, radius, N, rule, eps, eta, max_iter, solver, filters=1)
@@ -279,35 +281,35 @@ def gfeast_from(A: np.ndarray, B: np.ndarray, U1: np.ndarray, center: complex, r
                 N: int, rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
                 max_iter: int = 20, solver: Optional[ShiftedSolver] = None,
                 filters: int = 0) -> Result:
-    """Algorithm 5 lines 2-18 from an orthonormal ``U_1`` that is already a
-    filtered basis (Search's output, or line 1's)."""
+    """Algorithm 5 after its Search call, from an orthonormal ``U_1`` that is
+    already a filtered basis (Search's output, or that of ``gfeast``)."""
     z, w = contour_nodes(center, radius, N, rule)
     if solver is None:
         solver = ShiftedSolver(A, B, z)
-    # line 2: B U_1 = U_2 R_2
+    # QR of B U_1 = U_2 R_2
     BU1 = B @ U1
     U2, _ = orth(BU1)
-    # line 3
+    # e(0) = 0, c(0) = 0
     e_prev, c_prev = 0.0, 0
     prev = None
     history = []
     for k in range(1, max_iter + 1):
-        # line 5
+        # reduced pencil
         At = U2.conj().T @ (A @ U1)
         Bt = U2.conj().T @ BU1
-        # line 6
+        # reduced eigenproblem and Ritz vectors
         alpha, beta, Y = reduced_eig(At, Bt)
         lam = eigenvalues_from(alpha, beta)
         X = normalize_columns(U1 @ Y)
-        # lines 7-11
+        # residuals and selection, c(k)
         r = residuals(A, B, lam, X)
         sel = inside(lam, center, radius) & (r < eta)
         c_k = int(np.count_nonzero(sel))
-        # line 12
+        # e(k) = max r
         e_k = float(np.max(r[sel])) if c_k > 0 else math.inf
         cur = (lam[sel], X[:, sel], r[sel], e_k)
         history.append({"k": k, "c": c_k, "e": e_k})
-        # lines 13-15
+        # stopping rules
         act = stop_rule(k, c_k, e_k, c_prev, e_prev, eps, max_iter)
         if act == CONVERGED or act == MAX_ITER:
             return Result(cur[0], cur[1], cur[2], cur[3], act, k, filters, history)
@@ -315,14 +317,14 @@ def gfeast_from(A: np.ndarray, B: np.ndarray, U1: np.ndarray, center: complex, r
             return Result(prev[0], prev[1], prev[2], prev[3], act, k, filters, history)
         prev = cur
         e_prev, c_prev = e_k, c_k
-        # line 16: U = Q_N U_1 with the cached factors
+        # filter: U = Q_N U_1 with the cached factors
         U = apply_filter(solver, w, U1, BU1)
         filters += 1
-        # line 17
+        # QR of U and of B U
         U1, _ = orth(U)
         BU1 = B @ U1
         U2, _ = orth(BU1)
-    raise AssertionError("unreachable: line 15 stops at max_iter")
+    raise AssertionError("unreachable: the iteration cap stops at max_iter")
 
 
 # ---------------------------------------------------------------------------
@@ -335,12 +337,12 @@ class CirrResult:
     X: np.ndarray       # their eigenvectors (unit columns)
     r: np.ndarray       # their residuals (eq. 5-1)
     t: int              # columns of the moment block, h g
-    sv: np.ndarray      # singular values of the moment block (step 2)
+    sv: np.ndarray      # singular values of the moment block
 
 
 def cirr_moments(solver: ShiftedSolver, z: np.ndarray, w: np.ndarray, Y: np.ndarray,
                  g: int, center: complex, radius: float) -> np.ndarray:
-    """Step 1: ``[R_0, ..., R_{g-1}]`` with ``R_i`` the quadrature of
+    """Moments of Algorithm 1: ``[R_0, ..., R_{g-1}]`` with ``R_i`` the quadrature of
     ``F_i Y`` (eq. 2-2-21), in the shifted and scaled powers
     ``((z - gamma)/rho)^i`` (same span as ``z^i`` for ``i < g``)."""
     mu = (z - center) / radius
@@ -351,10 +353,10 @@ def cirr_moments(solver: ShiftedSolver, z: np.ndarray, w: np.ndarray, Y: np.ndar
 def block_cirr(A: np.ndarray, B: np.ndarray, Y: np.ndarray, g: int, center: complex,
                radius: float, N: int, rule: int = TRAPEZOID, eta: float = 1e-3,
                solver: Optional[ShiftedSolver] = None) -> CirrResult:
-    """Algorithm 1: moments, SVD (step 2, all ``h g`` left singular vectors),
-    Rayleigh-Ritz with the left space equal to the right one (steps 3-4), Ritz
-    vectors and the selection of step 5 (inside the circle with ``r_i < eta``,
-    as GFEAST's line 10)."""
+    """Algorithm 1: moments, SVD (all ``h g`` left singular vectors),
+    Rayleigh-Ritz with the left space equal to the right one, Ritz vectors and
+    the final selection (inside the circle with ``r_i < eta``, as in GFEAST's
+    selection)."""
     z, w = contour_nodes(center, radius, N, rule)
     if solver is None:
         solver = ShiftedSolver(A, B, z)
@@ -463,8 +465,8 @@ def gfeast_region(A: np.ndarray, B: np.ndarray, V: np.ndarray, vertices: np.ndar
 class SearchResult:
     U1: np.ndarray      # orthonormal basis of the filtered block (n x t)
     t: int              # numerical rank at the last round (upper bound of s)
-    s0: int             # trace estimate of s (line 2)
-    rounds: int         # rank tests performed (line 9)
+    s0: int             # trace estimate of s
+    rounds: int         # rank-revealing tests performed
     used: int           # pool columns consumed
     filters: int        # filter applications
 
@@ -479,7 +481,7 @@ def numerical_rank(R: np.ndarray, tau: float) -> int:
 
 
 def trace_estimate(Y0: np.ndarray, U: np.ndarray) -> int:
-    """``s_0 = ceil(trace(Y_0^* U) / p)`` (Algorithm 4 line 2, eq. (trace)):
+    """``s_0 = ceil(trace(Y_0^* U) / p)`` (Algorithm 4, eq. (trace)):
     for ``U = Q Y_0`` with Gaussian ``Y_0`` the expectation of the trace is
     ``p trace(Q) = p s``."""
     p = Y0.shape[1]
@@ -499,17 +501,17 @@ def search(solver: ShiftedSolver, w: np.ndarray, Y_pool: np.ndarray, p: int,
     cap = n if t_max is None else min(t_max, n)
     if not 1 <= p <= cap:
         raise ValueError("p out of range")
-    # line 1
+    # first filtered sample
     Y0 = Y_pool[:, :p]
     used = p
     U = apply_filter(solver, w, Y0)
     filters = 1
-    # line 2
+    # trace estimate
     s0 = trace_estimate(Y0, U)
     sd = min(max(p, s0), cap)
     rounds = 0
     while True:
-        # lines 3-8
+        # widen the block to s_dagger columns
         if sd > p:
             if used + (sd - p) > Y_pool.shape[1]:
                 raise ValueError("random column pool exhausted")
@@ -519,7 +521,7 @@ def search(solver: ShiftedSolver, w: np.ndarray, Y_pool: np.ndarray, p: int,
             filters += 1
         else:
             sd = p
-        # lines 9-10
+        # rank-revealing QR and rank test
         Q, R, _ = sla.qr(U, mode="economic", pivoting=True)
         rounds += 1
         t = numerical_rank(R, tau)
@@ -535,7 +537,7 @@ def gfeast_search(A: np.ndarray, B: np.ndarray, Y_pool: np.ndarray, center: comp
                   radius: float, N: int, p: int, alpha: float = 1.5, tau: float = 1e-3,
                   rule: int = TRAPEZOID, eps: float = 1e-10, eta: float = 1e-3,
                   max_iter: int = 20, t_max: Optional[int] = None):
-    """Algorithm 5 with line 1 = Algorithm 4: returns (Result, SearchResult)."""
+    """Algorithm 5 with Algorithm 4 as its Search call: returns (Result, SearchResult)."""
     z, w = contour_nodes(center, radius, N, rule)
     solver = ShiftedSolver(A, B, z)
     sr = search(solver, w, Y_pool, p, alpha, tau, t_max)

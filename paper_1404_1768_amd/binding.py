@@ -385,7 +385,7 @@ class Plan:
         return self._solve(self.lib.feast_solve, "feast_solve", A, B, V, allow)
 
     def solve_from(self, A, B, U1, allow=(FEAST_REFINE_STAGNATED,)) -> SolveResult:
-        """Algorithm 5 lines 2-18 from Search's orthonormal basis U1 (n x m)."""
+        """Algorithm 5 after its Search call, from Search's orthonormal basis U1 (n x m)."""
         return self._solve(self.lib.feast_solve_from, "feast_solve_from", A, B, U1, allow)
 
     def _solve(self, fn, what, A, B, V, allow) -> SolveResult:

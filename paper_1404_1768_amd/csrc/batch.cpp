@@ -498,7 +498,7 @@ void filter_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
 
 // ---------------------------------------------------------------------------
 // Grouped orthonormalisation and projection over the pencils in a list `act`
-// (Algorithm 5 lines 2/17 and 5): every step is one launch over all of them.
+// (Algorithm 5's QR steps and reduced pencil): every step is one launch over all of them.
 // The GEMM problem lists and descriptors depend on the list, so each round is
 // scheduled twice, recording and then launching (tables uploaded in between).
 // ---------------------------------------------------------------------------
@@ -990,7 +990,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       inf.t_project_ms += t.ms();
       return r;
     };
-    // line 1 (Search with the subspace size fixed): U = Q_N V
+    // Search with the subspace size fixed: U = Q_N V
     for (int p = 0; p < P; ++p) {
       const int c = b->order[p];
       gemm_t<z64>(s, 0, b->n[p], b->m[p], b->n[p], make_double2(1.0, 0.0), Bp(p), ldb[c], 0,
@@ -1005,7 +1005,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
     const int nthreads =
         static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
     for (int k = 1; k <= b->o.max_iter; ++k) {
-      // line 16 of the first iteration ahead of time: the next filter needs
+      // filter step of the first iteration ahead of time: the next filter needs
       // only B U_1, so it runs on gs while the host solves the reduced pencils
       // and the Ritz vectors and residuals go to the second stream (a pencil
       // that stops at k = 1 has its filter computed for nothing; the grouped
@@ -1028,7 +1028,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
         inf.filters += 1;
         inf.t_filter_ms += tf.ms();
       }
-      // line 6 for every active pencil, in parallel on the host
+      // reduced eigenproblem of every active pencil, in parallel on the host
       Timer te;
       std::vector<int> act;
       for (int p = 0; p < P; ++p)
@@ -1047,7 +1047,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       for (int p : act)
         if (qz[p] != 0) return bfail(b, FEAST_ENUMERIC, "reduced QZ did not converge in pencil " +
                                                           std::to_string(b->order[p]));
-      // lines 7-9: Ritz vectors and the norms of eq. 5-1 on the device
+      // Ritz vectors and the norms of eq. 5-1 on the device
       std::vector<std::vector<cd>> lam(P);
       for (int p : act) {
         feast_plan *q = b->sub[p];
@@ -1075,7 +1075,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
                               hipMemcpyDeviceToHost, rs));
       }
       HIPCHK(hipStreamSynchronize(rs));
-      // lines 10-15 per pencil
+      // selection and stopping rules per pencil
       bool refine_more = false;
       for (int p : act) {
         feast_plan *q = b->sub[p];
@@ -1155,7 +1155,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       bool any = false;
       for (int p = 0; p < P; ++p) any = any || !st[p].done;
       if (!any) break;
-      // line 16 for the pencils still iterating (one grouped filter), line 17
+      // filter step for the pencils still iterating (one grouped filter), QR step
       // mixed form: as feast_solve, one grouped sweep count for all pencils --
       // refined once any pencil still iterating has e(k) <= 1e-4 (or on the
       // first filter after Search), one more on a stall

@@ -2,8 +2,8 @@
 //
 //   feast_filter  : U = sum_j w_j (z_j B - A)^{-1} B V        (eqs. 8-4, 4-4)
 //   feast_project : U = U_1 R_1, B U_1 = U_2 R_2, At = U_2^* A U_1, Bt = U_2^* B U_1
-//                   (Algorithm 5 lines 2, 5, 17; eqs. 6-3-13, 7-10)
-//   feast_solve   : Algorithm 5 lines 1-18 with the subspace size fixed
+//                   (Algorithm 5's QR steps and reduced pencil; eqs. 6-3-13, 7-10)
+//   feast_solve   : Algorithm 5 with the subspace size fixed
 //
 // Device layout.  Every matrix is row-major.  The plan caches, per node j,
 // the LU factors of M_j = z_j B - A (N blocks of n x n, complex128 or
@@ -523,7 +523,7 @@ void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot, int64_t cols) {
   }
 }
 
-// Algorithm 5 lines 2/17 and 5: U -> U_1, A U_1, B U_1, U_2, At, Bt (device m x m).
+// Algorithm 5's QR steps and reduced pencil: U -> U_1, A U_1, B U_1, U_2, At, Bt (device m x m).
 void project_device(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb, z64 *U,
                     int64_t ldu, z64 *AU1, int64_t ldau, z64 *BU1, int64_t ldbu) {
   const int64_t n = p->n, m = p->m;
@@ -756,7 +756,7 @@ int feast_project(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *
 }
 
 // Algorithm 5; from_basis: dV is an orthonormal U_1 that is already filtered
-// (Search's output), so line 1 is skipped.
+// (Search's output), so the Search call is skipped.
 static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
                       int64_t ldb, const feast_z *dV, int64_t ldv, bool from_basis,
                       feast_z *hLambda, feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found,
@@ -820,10 +820,10 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       return st;
     };
     if (from_basis) {
-      // line 1 was Search (feast_search): its basis is U_1
+      // the Search call was feast_search: its basis is U_1
       feast::copy_block_z(s, V, ldv, n, m, U1, m);
     } else {
-      // line 1 (Search with the subspace size fixed): U = Q_N V, QR inside the projection
+      // Search with the subspace size fixed: U = Q_N V, QR inside the projection
       Timer t;
       gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1);
       const int st = run_filter(p->R.as<z64>(), U1, true);
@@ -831,7 +831,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       HIPCHK(hipStreamSynchronize(s));
       inf.t_filter_ms += t.ms();
     }
-    // lines 2 and 5 of the first iteration
+    // QR of B U_1 and the first reduced pencil
     {
       Timer t;
       project_device(p, A, lda, B, ldb, U1, m, AU1, m, BU1, m);
@@ -841,13 +841,13 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     }
     HIPCHK(hipEventRecord(p->ev_cols, s));
     HIPCHK(hipStreamWaitEvent(s2, p->ev_cols, 0));
-    // line 3
+    // e(0) = 0, c(0) = 0
     double e_prev = 0.0, e_prev2 = 0.0;
     int c_prev = 0;
     std::vector<cd> lam_prev;
     std::vector<double> r_prev;
     for (int k = 1; k <= p->o.max_iter; ++k) {
-      // line 16 ahead of time: the next filter needs only B U_1, so it runs on
+      // filter step ahead of time: the next filter needs only B U_1, so it runs on
       // the GPU while the host solves the reduced pencil; it is skipped when
       // this iteration is likely to be the last one: e(k) predicted from the
       // observed reduction factor e(k-1)/e(k-2) (before two values exist, a
@@ -867,7 +867,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
         speculated = true;
       }
       const double launch_ms = tf.ms();
-      // line 6: reduced pencil on the host
+      // reduced eigenproblem on the host
       Timer te;
       if (feast_reduced_eig(m, hAt.data(), m, hBt.data(), m, halpha.data(), hbeta.data(), hY.data(),
                             m) != FEAST_OK)
@@ -890,7 +890,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       feast::ritz_norms(s2, AX, BX, m, n, m, dlam, p->part.as<double>(), dnorm);
       HIPCHK(hipMemcpyAsync(hn.data(), dnorm, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s2));
       HIPCHK(hipStreamSynchronize(s2));
-      // lines 7-12: residuals (eq. 5-1), selection, c(k), e(k)
+      // residuals (eq. 5-1), selection, c(k), e(k)
       std::vector<int32_t> sel;
       std::vector<double> rsel;
       double e_k = 0.0;
@@ -909,7 +909,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       inf.count[k - 1] = c_k;
       inf.err[k - 1] = e_k;
       inf.iters = k;
-      // lines 13-15
+      // stopping rules
       const int act = feast_host::stop_rule(k, c_k, e_k, c_prev, e_prev, p->o.eps, p->o.max_iter);
       if (act == 1 || act == -1) {
         if (c_k > 0) {
@@ -961,7 +961,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       c_prev = c_k;
       HIPCHK(hipEventRecord(p->ev_panel, s2));
       inf.t_ritz_ms += tr.ms();
-      // line 16 (unless it already ran)
+      // filter step (unless it already ran)
       // filter time: its launch plus whatever of it the host work did not hide
       Timer tw;
       if (!speculated || verify_now) {
@@ -974,7 +974,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       }
       HIPCHK(hipStreamSynchronize(s));
       inf.t_filter_ms += launch_ms + tw.ms();
-      // line 17 and line 5 of the next iteration (after the side stream is done with U_1)
+      // QR step and the next reduced pencil (after the side stream is done with U_1)
       {
         Timer t;
         HIPCHK(hipStreamWaitEvent(s, p->ev_panel, 0));
@@ -997,13 +997,13 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
   });
 }
 
-// Block_CIRR (Algorithm 1) on the plan's cached factors.  Step 1's node
+// Block_CIRR (Algorithm 1) on the plan's cached factors.  The moments' node
 // solutions are the filter's solves with right-hand side Y itself (mixed plans
 // apply one FP64 refinement sweep: there is no outer iteration to absorb
-// complex64 solve errors); the moments are weighted node sums; step 2's
+// complex64 solve errors); the moments are weighted node sums; the SVD step's
 // orthonormal basis of the moment block comes from shifted Cholesky QR3 (the
 // Rayleigh-Ritz pencil depends on the span only, so it has the eigenvalues the
-// SVD's left factor gives); steps 3-5 reuse the projection, host eigensolver
+// SVD's left factor gives); the Rayleigh-Ritz steps reuse the projection, host eigensolver
 // and Ritz-residual pieces of Algorithm 5.
 int feast_cirr(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB, int64_t ldb,
                const feast_z *dY, int64_t ldy, int32_t h, int32_t g, feast_z *hLambda,
@@ -1030,7 +1030,7 @@ int feast_cirr(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
     z64 *Ys = p->gblk(feast_plan::G_YS);
     z64 *dlam = p->small.as<z64>();
     int32_t *didx = reinterpret_cast<int32_t *>(p->small.as<z64>() + m);
-    // step 1: Y_j = (z_j B - A)^{-1} Y, then R_i = sum_j w_j mu_j^i Y_j, mu_j = (z_j - gamma)/rho
+    // moments: Y_j = (z_j B - A)^{-1} Y, then R_i = sum_j w_j mu_j^i Y_j, mu_j = (z_j - gamma)/rho
     if (p->mixed())
       solve_nodes_mixed(p, A, lda, B, ldb, Y, ldy, 0.0, 1, h);
     else
@@ -1047,10 +1047,10 @@ int feast_cirr(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
     for (int i = 0; i < g; ++i)
       feast::weighted_sum(s, p->Y.as<z64>(), p->ldY(), m, p->cirr_w.as<z64>() + i * N, N, n, h,
                           U + static_cast<int64_t>(i) * h, m);
-    // step 2: orthonormal basis of the moment block (in place)
+    // orthonormal basis of the moment block (in place)
     feast::fill_i32(s, p->flag.as<int32_t>(), 3, 0);
     orth(p, U, m, 0, t);
-    // step 3: A~ = U^* A U, B~ = U^* B U
+    // Rayleigh-Ritz pencil: A~ = U^* A U, B~ = U^* B U
     gemm_t<z64>(s, 0, n, t, n, zc(1.0), A, lda, 0, U, m, 0, zc(0.0), AU, m, 0, 1);
     gemm_t<z64>(s, 0, n, t, n, zc(1.0), B, ldb, 0, U, m, 0, zc(0.0), BU, m, 0, 1);
     gemm_t<z64>(s, 2, t, t, n, zc(1.0), U, m, 0, AU, m, 0, zc(0.0), Ab, t, 0, 1,
@@ -1066,7 +1066,7 @@ int feast_cirr(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
     HIPCHK(hipStreamSynchronize(s));
     if (hf[0] || hf[1] || hf[2])
       return fail(p, FEAST_ENUMERIC, "feast_cirr: Cholesky QR of the moment block broke down");
-    // step 4
+    // reduced eigenproblem
     if (feast_reduced_eig(t, hA.data(), t, hB.data(), t, hal.data(), hbe.data(), hYv.data(), t) !=
         FEAST_OK)
       return fail(p, FEAST_ENUMERIC, "feast_cirr: reduced eigensolver did not converge");
@@ -1077,7 +1077,7 @@ int feast_cirr(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
       lam[i] = (b != cd(0.0)) ? a / b : cd(INFINITY, 0.0);
       hlam[i] = std::isfinite(lam[i].real()) ? feast_z{lam[i].real(), lam[i].imag()} : feast_z{0, 0};
     }
-    // step 5: x_i = U y_i, residuals (eq. 5-1) from (A U) y_i and (B U) y_i, selection
+    // Ritz pairs: x_i = U y_i, residuals (eq. 5-1) from (A U) y_i and (B U) y_i, selection
     HIPCHK(hipMemcpyAsync(Ys, hYv.data(), sizeof(z64) * tt, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(dlam, hlam.data(), sizeof(z64) * t, hipMemcpyHostToDevice, s));
     gemm_t<z64>(s, 0, n, t, t, zc(1.0), U, m, 0, Ys, t, 0, zc(0.0), X, m, 0, 1);
@@ -1208,11 +1208,11 @@ int feast_search(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
       HIPCHK(hipMemcpyAsync(h.data(), G, sizeof(z64) * k * k, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
     };
-    // line 1
+    // first filtered sample
     int64_t pc = p0, used = p0;
     st = filt(0, pc, U);
     if (st != FEAST_OK) return st;
-    // line 2: s_0 = ceil(Re trace(Y_0^* U) / p)
+    // trace estimate: s_0 = ceil(Re trace(Y_0^* U) / p)
     std::vector<feast_z> hg;
     gram(Y, pc, ldy, U, m, hg);
     double tr = 0.0;
@@ -1222,7 +1222,7 @@ int feast_search(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
     std::vector<int32_t> piv;
     std::vector<double> rd;
     for (;;) {
-      // lines 3-8: widen the block with s_dagger - p newly filtered columns
+      // widen the block with s_dagger - p newly filtered columns
       if (sd > pc) {
         const int64_t c = sd - pc;
         if (used + c > ycols)
@@ -1233,7 +1233,7 @@ int feast_search(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
       } else {
         sd = pc;
       }
-      // line 9: rank-revealing step
+      // rank-revealing step
       gram(U, sd, m, U, m, hg);
       piv.assign(static_cast<size_t>(sd), 0);
       rd.assign(static_cast<size_t>(sd), 0.0);
@@ -1250,7 +1250,7 @@ int feast_search(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
       HIPCHK(hipStreamSynchronize(s));
       if (hf[0] || hf[1] || hf[2])
         return fail(p, FEAST_ENUMERIC, "feast_search: Cholesky QR of the pivot columns broke down");
-      // line 10
+      // rank test
       if (t < sd) {
         feast::copy_block_z(s, Wg, m, n, t, reinterpret_cast<z64 *>(dU1), ldu);
         out.t = t;

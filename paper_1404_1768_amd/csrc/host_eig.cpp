@@ -1,5 +1,5 @@
-// Host solver of the reduced t x t pencil  At y = lambda Bt y  (Algorithm 5
-// line 6; Section 3 names LAPACK's xGGES/xGGEV for this step).  When Bt is
+// Host solver of the reduced t x t pencil  At y = lambda Bt y  (Algorithm 5's
+// reduced eigenproblem; Section 3 names LAPACK's xGGES/xGGEV for this step).  When Bt is
 // upper triangular and well conditioned -- the method's B~ equals R_2 of the
 // QR of B U_1 -- the standard problem Bt^{-1} At is solved (std_eig below).
 // Otherwise it is a from-scratch complex QZ:

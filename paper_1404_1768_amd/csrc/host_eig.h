@@ -1,5 +1,5 @@
-// Host-side pieces of Algorithm 5: the reduced-pencil eigensolver (line 6),
-// quadrature nodes (eq. 8-4) and the stopping rules (lines 13-15).
+// Host-side pieces of Algorithm 5: the reduced-pencil eigensolver,
+// quadrature nodes (eq. 8-4) and the stopping rules.
 #pragma once
 #include <complex>
 #include <cstdint>
@@ -19,7 +19,7 @@ int reduced_eig(int64_t t, const std::complex<double> *At, int64_t lda,
 int contour_nodes(std::complex<double> center, double radius, int N, int rule,
                   std::complex<double> *z, std::complex<double> *w);
 
-// Rank-revealing step of Search (Algorithm 4 line 9) on the Gram matrix
+// Rank-revealing step of Search (Algorithm 4) on the Gram matrix
 // G = U^* U (k x k Hermitian positive semi-definite, row-major, leading
 // dimension ldg): Cholesky with diagonal pivoting, Pi^T G Pi = R^* R, which in
 // exact arithmetic has the pivots and |R_ii| of the column-pivoted QR of U.
@@ -37,7 +37,7 @@ void enclosing_circle(int64_t nv, const std::complex<double> *v, std::complex<do
                       double *radius);
 bool inside_polygon(std::complex<double> z, int64_t nv, const std::complex<double> *v);
 
-// Decision after iteration k: 1 (line 13), 0 (line 14), -1 (line 15), 2 continue.
+// Decision after iteration k: 1 (converged), 0 (no improvement), -1 (iteration cap), 2 continue.
 int stop_rule(int k, int c_k, double e_k, int c_prev, double e_prev, double eps, int max_iter);
 
 }  // namespace feast_host

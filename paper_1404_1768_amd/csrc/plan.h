@@ -148,7 +148,7 @@ int64_t splitws_elems(const feast_plan *p);
 
 // Shifted CholeskyQR3 of the n x m block X in place (flags at flag_slot..+2).
 void orth(feast_plan *p, z64 *X, int64_t ldx, int flag_slot, int64_t cols = -1);
-// Algorithm 5 lines 2/17 and 5 on the device: U -> U_1, A U_1, B U_1, U_2, At, Bt.
+// Algorithm 5's QR steps and reduced pencil on the device: U -> U_1, A U_1, B U_1, U_2, At, Bt.
 void project_device(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb, z64 *U,
                     int64_t ldu, z64 *AU1, int64_t ldau, z64 *BU1, int64_t ldbu);
 // Copy At, Bt to the host and check the Cholesky QR flags (synchronises).

@@ -147,8 +147,8 @@ def test_batch_full_workload_counts_and_spectrum():
 
 
 @pytest.mark.parametrize("prec", [fm.FP64, fm.MIXED])
-def test_batch_single_iteration_stops_every_pencil_at_line_15(prec):
-    """max_iter = 1: every pencil stops at k = 1 by line 15 (flag -1) while the
+def test_batch_single_iteration_stops_every_pencil_at_the_iteration_cap(prec):
+    """max_iter = 1: every pencil stops at k = 1 by the iteration cap (flag -1) while the
     second filter, launched ahead of the host eigensolves, is still in flight;
     the first iteration's Ritz pairs match the oracle's."""
     ps = small_batch()[:4]

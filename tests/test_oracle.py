@@ -262,8 +262,8 @@ def test_convergence_rate_prediction():
 
 
 def test_rebound_returns_previous_iterate():
-    # With eps below the attainable floor the run must end on rule 14 (flag 0)
-    # or on max_iter, never on rule 13; with flag 0 the returned error is the
+    # With eps below the attainable floor the run must end on the no-improvement
+    # rule (flag 0) or on max_iter, never on convergence; with flag 0 the returned error is the
     # previous iteration's.
     p = pg.workload(1)
     res = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, eps=1e-300, max_iter=30)
@@ -275,7 +275,7 @@ def test_rebound_returns_previous_iterate():
 
 
 # ---------------------------------------------------------------------------
-# Stopping rules (Algorithm 5 lines 12-15)
+# Stopping rules (Algorithm 5, Section 4.2)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("seq,eps,max_iter,flag,stop_k", [

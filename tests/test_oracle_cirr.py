@@ -55,7 +55,7 @@ def test_block_cirr_is_basis_invariant():
         lam = o.eigenvalues_from(a, b)
         ev.append(np.sort_complex(lam[o.inside(lam, p.center, p.radius)]))
     # (the three rounding-level directions of this rank-9 block give spurious
-    # Ritz values too, identical in both bases; step 5's residual test drops them)
+    # Ritz values too, identical in both bases; the final residual test drops them)
     assert len(ev[0]) == len(ev[1]) and np.max(np.abs(ev[0] - ev[1])) < 1e-10
 
 

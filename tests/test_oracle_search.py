@@ -56,7 +56,7 @@ def test_trace_of_projector_is_count_and_estimator_mean():
 def test_search_grows_to_the_count_and_the_eigenspace(monkeypatch):
     # outside eigenvalues at |mu| >= 4: the discrete filter 1/(1 + mu^32) leaves
     # them below 1e-19, so the numerical rank of the filtered block is s.  The
-    # trace estimate is forced low so that lines 3-10 have to grow the block
+    # trace estimate is forced low so that the widening step has to grow the block
     # (4 -> 6 -> 9 -> 14 columns) to reach it.
     p = _pencil()
     z, w = o.contour_nodes(p.center, p.radius, p.nodes)
@@ -89,7 +89,7 @@ def test_search_one_round_when_the_start_block_is_wide_enough():
 
 def test_search_rank_is_relative_to_the_block_scale():
     # within a round, |R_ii| >= tau |R_11| does not change when Y is scaled
-    # (one round: p >= s, so line 10 stops at the first rank test)
+    # (one round: p >= s, so the first rank test stops)
     p = _pencil()
     z, w = o.contour_nodes(p.center, p.radius, p.nodes)
     solver = o.ShiftedSolver(p.A, p.B, z)
