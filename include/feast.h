@@ -223,8 +223,8 @@ int feast_region_select(int32_t nv, const feast_z *vertices, int64_t k, const fe
                         int32_t *inside);
 
 /* ---------------------------------------------------------------------------
- * Search (Algorithm 4, Section 4.1): an upper bound t of the number s of
- * eigenvalues inside the contour, without knowing s
+ * Search (Algorithm 4, Section 4.1): bounds the unknown count s of eigenvalues
+ * inside the contour from above by t
  * ------------------------------------------------------------------------- */
 
 typedef struct feast_search_info {
