@@ -201,7 +201,7 @@ def _compare_solve(p, r, ref, lam_tol=1e-10, res_tol=1e-10, vec_tol=1e-10):
         assert abs(np.linalg.norm(X[:, i]) - 1) < 1e-12
 
 
-def test_solve_config1_two_filters_matches_oracle():
+def test_solve_n200_two_filters_matches_oracle():
     p = pg.workload(1)
     A, B, V = to_dev(p.A, p.B, p.V)
     with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, max_iter=2) as plan:
@@ -214,7 +214,7 @@ def test_solve_config1_two_filters_matches_oracle():
 
 
 @pytest.mark.parametrize("prec", [fm.FP64, fm.MIXED])
-def test_solve_config1_converged(prec):
+def test_solve_n200_converged(prec):
     p = pg.workload(1)
     A, B, V = to_dev(p.A, p.B, p.V)
     with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=prec) as plan:

@@ -210,7 +210,7 @@ def test_reduced_eig_matches_definition():
 # The whole algorithm (Algorithm 5)
 # ---------------------------------------------------------------------------
 
-def test_config1_two_filters_then_converged_matches_brute_force():
+def test_n200_two_filters_then_converged_matches_brute_force():
     p = pg.workload(1)
     res2 = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, max_iter=2)
     assert res2.filters == 2 and res2.iters == 2
