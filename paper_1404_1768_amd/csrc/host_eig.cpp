@@ -394,6 +394,43 @@ inline void rot_cols_pair(cd *x, cd *y, int64_t n, double c, cd a, cd b) {
   }
 }
 
+// sum_i conj(u_i) x_i over n entries: two complex numbers a register, two
+// registers deep, so that the sums do not wait on one another.
+inline cd dotc(const cd *u, const cd *x, int64_t n) {
+  const double *pu = reinterpret_cast<const double *>(u);
+  const double *px = reinterpret_cast<const double *>(x);
+  __m256d re0 = _mm256_setzero_pd(), re1 = re0, im0 = re0, im1 = re0;
+  int64_t i = 0;
+  for (; i + 4 <= n; i += 4) {
+    const __m256d u0 = _mm256_loadu_pd(pu + 2 * i), u1 = _mm256_loadu_pd(pu + 2 * i + 4);
+    const __m256d x0 = _mm256_loadu_pd(px + 2 * i), x1 = _mm256_loadu_pd(px + 2 * i + 4);
+    re0 = _mm256_fmadd_pd(u0, x0, re0);  // [ur xr, ui xi] per number
+    re1 = _mm256_fmadd_pd(u1, x1, re1);
+    im0 = _mm256_fmadd_pd(u0, _mm256_permute_pd(x0, 0x5), im0);  // [ur xi, ui xr]
+    im1 = _mm256_fmadd_pd(u1, _mm256_permute_pd(x1, 0x5), im1);
+  }
+  alignas(32) double a[4], b[4];
+  _mm256_store_pd(a, _mm256_add_pd(re0, re1));
+  _mm256_store_pd(b, _mm256_add_pd(im0, im1));
+  cd s((a[0] + a[1]) + (a[2] + a[3]), (b[0] - b[1]) + (b[2] - b[3]));
+  for (; i < n; ++i) s += std::conj(u[i]) * x[i];
+  return s;
+}
+
+// y_i += a x_i over n entries.
+inline void axpy(cd a, const cd *x, cd *y, int64_t n) {
+  const __m256d ar = _mm256_set1_pd(a.real()), ai = _mm256_set1_pd(a.imag());
+  const double *px = reinterpret_cast<const double *>(x);
+  double *py = reinterpret_cast<double *>(y);
+  int64_t i = 0;
+  for (; i + 2 <= n; i += 2) {
+    const __m256d vx = _mm256_loadu_pd(px + 2 * i);
+    const __m256d ax = _mm256_fmaddsub_pd(vx, ar, _mm256_mul_pd(_mm256_permute_pd(vx, 0x5), ai));
+    _mm256_storeu_pd(py + 2 * i, _mm256_add_pd(_mm256_loadu_pd(py + 2 * i), ax));
+  }
+  for (; i < n; ++i) y[i] += a * x[i];
+}
+
 // Pencil with an upper-triangular, well-conditioned Bt (the projected B of the
 // method equals R_2 of the QR of B U_1): the standard problem C = Bt^{-1} At.
 //   1. C by back substitution, reduced to Hessenberg form H0 by Hermitian
@@ -433,12 +470,15 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
   }
   for (const cd &v : H.a)
     if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return -1;
-  // 1. Hessenberg form; reflector k acts on rows/columns k+1..t-1 (one
-  // thread: at these orders a step is too short to share)
+  // 1. Hessenberg form; reflector k acts on rows/columns k+1..t-1.  One pass
+  // over the columns applies it from the left and gathers w = H u for the
+  // right-hand side while each column is in cache; a second pass applies it
+  // from the right.  (One thread: at these orders a reflector step is a few
+  // tens of microseconds, about what the barriers of a split would cost.)
   std::vector<std::vector<cd>> refl(t);
   std::vector<double> rf(t, 0.0);
   {
-    std::vector<cd> w(t);
+    std::vector<cd> u(t), w(t);
     for (int64_t k = 0; k + 2 < t; ++k) {
       const int64_t L = t - k - 1;
       // (the part below the subdiagonal is summed on its own: a tiny tail under
@@ -450,34 +490,22 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
       const cd x0 = H(k + 1, k);
       const double a0 = std::abs(x0);
       const cd ph = (a0 > 0.0) ? x0 / a0 : cd(1.0);
-      std::vector<cd> &u = refl[k];
-      u.resize(L);
       for (int64_t i = 0; i < L; ++i) u[i] = H(k + 1 + i, k);
       u[0] += ph * xn;
       double un2 = 0.0;
       for (int64_t i = 0; i < L; ++i) un2 += std::norm(u[i]);
       const double f = 2.0 / un2;
+      refl[k].assign(u.begin(), u.begin() + L);
       rf[k] = f;
+      std::fill(w.begin(), w.end(), cd(0.0));
       for (int64_t j = k + 1; j < t; ++j) {
-        cd d = 0.0;
-        cd *hc = H.col(j) + k + 1;
-        for (int64_t i = 0; i < L; ++i) d += std::conj(u[i]) * hc[i];
-        d *= f;
-        for (int64_t i = 0; i < L; ++i) hc[i] -= d * u[i];
+        cd *hc = H.col(j);
+        axpy(-f * dotc(u.data(), hc + k + 1, L), u.data(), hc + k + 1, L);
+        axpy(u[j - k - 1], hc, w.data(), t);
       }
       H(k + 1, k) = -ph * xn;
       for (int64_t i = 1; i < L; ++i) H(k + 1 + i, k) = 0.0;
-      std::fill(w.begin(), w.end(), cd(0.0));
-      for (int64_t m = 0; m < L; ++m) {
-        const cd um = u[m];
-        const cd *hc = H.col(k + 1 + m);
-        for (int64_t i = 0; i < t; ++i) w[i] += hc[i] * um;
-      }
-      for (int64_t m = 0; m < L; ++m) {
-        const cd cu = f * std::conj(u[m]);
-        cd *hc = H.col(k + 1 + m);
-        for (int64_t i = 0; i < t; ++i) hc[i] -= w[i] * cu;
-      }
+      for (int64_t j = k + 1; j < t; ++j) axpy(-f * std::conj(u[j - k - 1]), w.data(), H.col(j), t);
     }
   }
   const Mat H0 = H;
