@@ -127,6 +127,10 @@ struct feast_batch {
   std::vector<int64_t> yoff, toff;
   Tables lu_tab, sv_tab, pj_tab;
   DevBuf dinv, flags;  // grouped orthonormalisation: inverted 64 x 64 blocks, breakdown flags
+  // every pencil's At and Bt packed (m_p^2 each, in internal order), on the
+  // device and in page-locked host memory: one copy to the host per projection
+  DevBuf pk;
+  void *pk_host = nullptr;
   int64_t mmax = 0;
   Graph g_factor, g_filter;
   bool factored = false;
@@ -671,6 +675,21 @@ void project_schedule(feast_batch *b, Tables &t, const std::vector<int> &act,
   }
   ggemm<z64>(b, t, 2, false, pa);
   ggemm<z64>(b, t, 2, false, pb);
+  // At, Bt of every pencil in `act` into the packed buffer, in list order
+  std::vector<GrpMat> src, dst;
+  int64_t off = 0, mm_max = 0;
+  for (int p : act) {
+    const int64_t m = b->m[p];
+    feast_plan *q = b->sub[p];
+    for (int which : {feast_plan::G_AT, feast_plan::G_BT}) {
+      src.push_back(GrpMat{q->gblk(which), m, m, m});
+      dst.push_back(GrpMat{b->pk.as<z64>() + off, m, m, m});
+      off += m * m;
+    }
+    mm_max = std::max(mm_max, m * m);
+  }
+  const GrpMat *gsrc = t.put(src), *gdst = t.put(dst);
+  if (!rec) feast::copy_grp(s, gsrc, gdst, 2 * cnt, mm_max);
 }
 
 // The grouped projection of `act` with At, Bt copied to the host (synchronises);
@@ -687,16 +706,19 @@ int project_grouped(feast_batch *b, const std::vector<int> &act, const feast_z *
   hipStream_t s = b->gs;
   const int cnt = static_cast<int>(act.size());
   std::vector<int32_t> hf(8 * cnt);
-  for (int p : act) {
-    const int64_t m = b->m[p];
-    HIPCHK(hipMemcpyAsync(At[p].data(), b->sub[p]->gblk(feast_plan::G_AT), sizeof(z64) * m * m,
-                          hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(Bt[p].data(), b->sub[p]->gblk(feast_plan::G_BT), sizeof(z64) * m * m,
-                          hipMemcpyDeviceToHost, s));
-  }
+  int64_t elems = 0;
+  for (int p : act) elems += 2 * b->m[p] * b->m[p];
+  HIPCHK(hipMemcpyAsync(b->pk_host, b->pk.p, sizeof(z64) * elems, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(hf.data(), b->flags.p, sizeof(int32_t) * 8 * cnt, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
+  const feast_z *hp = static_cast<const feast_z *>(b->pk_host);
+  for (int p : act) {
+    const int64_t mm = b->m[p] * b->m[p];
+    std::copy(hp, hp + mm, At[p].data());
+    std::copy(hp + mm, hp + 2 * mm, Bt[p].data());
+    hp += 2 * mm;
+  }
   for (int i = 0; i < cnt; ++i)
     for (int k = 0; k < 6; ++k)
       if (hf[8 * i + k] != 0) {
@@ -799,6 +821,10 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
     b->mmax = *std::max_element(b->m.begin(), b->m.end());
     b->dinv.alloc(sizeof(z64) * P * b->mblk() * 4096);
     b->flags.alloc(sizeof(int32_t) * 8 * P);
+    int64_t pk_elems = 0;
+    for (int64_t mp : b->m) pk_elems += 2 * mp * mp;
+    b->pk.alloc(sizeof(z64) * pk_elems);
+    HIPCHK(hipHostMalloc(&b->pk_host, sizeof(z64) * pk_elems, hipHostMallocDefault));
     const int64_t nmat = static_cast<int64_t>(P) * N;
     const size_t esz = b->mixed() ? sizeof(c64) : sizeof(z64);
     b->F.alloc(esz * fo);
@@ -861,8 +887,9 @@ int feast_batch_destroy(feast_batch *b) {
   for (feast_plan *p : b->sub) feast_plan_destroy(p);
   for (DevBuf *d : {&b->F, &b->piv, &b->perm, &b->info, &b->Linv, &b->Uinv, &b->grp, &b->Y, &b->Yc,
                     &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev, &b->pj_tab.dev, &b->dinv,
-                    &b->flags})
+                    &b->flags, &b->pk})
     d->release();
+  if (b->pk_host) (void)hipHostFree(b->pk_host);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->ev_proj) (void)hipEventDestroy(b->ev_proj);
