@@ -160,7 +160,7 @@ def test_reduced_eig_against_brute_force(t):
         assert r <= 1e-13 * (abs(be[i]) * np.linalg.norm(A) + abs(al[i]) * np.linalg.norm(B))
 
 
-@pytest.mark.parametrize("t", [1, 2, 3, 17, 64, 160])
+@pytest.mark.parametrize("t", [1, 2, 3, 5, 17, 64, 97, 160, 255, 256])
 def test_reduced_eig_triangular_B_standard_form(t):
     # The method's projected B is upper triangular (R_2 of the QR of B U_1):
     # the solver then works on B^{-1} A; eigenvalues against brute force and
