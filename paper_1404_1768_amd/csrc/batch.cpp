@@ -107,6 +107,8 @@ struct Graph {
 
 }  // namespace
 
+constexpr int64_t kMaxSplits = 4;
+
 struct feast_batch {
   int P = 0, N = 0;
   feast_opts o{};
@@ -131,6 +133,7 @@ struct feast_batch {
   // device and in page-locked host memory: one copy to the host per projection
   DevBuf pk;
   void *pk_host = nullptr;
+  DevBuf sk;  // split-K partials of the m x m products (up to kMaxSplits per pencil)
   int64_t mmax = 0;
   Graph g_factor, g_filter;
   bool factored = false;
@@ -205,6 +208,48 @@ void ggemm(feast_batch *b, Tables &tab, int ta, bool sub, std::vector<GemmArgs<T
   const int64_t tiles = feast::gemm_group_tiles<T>(e.data(), static_cast<int>(e.size()));
   const GemmArgs<T> *d = tab.put(e);
   if (!tab.record) feast::gemm_group<T>(b->gs, ta, sub, d, static_cast<int>(e.size()), tiles);
+}
+
+// C = X^* Y with a small output (m x m: Gram matrices, reduced pencils) and a
+// long K = n, one problem per pencil: a few output tiles per pencil would leave
+// most compute units idle through the K loop, so each problem with K >= 512 is
+// cut into up to kMaxSplits K-chunks written to partials (one grouped launch),
+// then summed in chunk order (C = alpha X^* Y; beta must be 0).
+void ggemm_small_out(feast_batch *b, Tables &tab, std::vector<GemmArgs<z64>> &e) {
+  std::vector<GemmArgs<z64>> parts;
+  std::vector<GrpMat> dst, src;
+  z64 *W = b->sk.as<z64>();
+  int64_t off = 0, per_max = 0;
+  for (const GemmArgs<z64> &g : e) {
+    int64_t S = g.K >= 512 && g.batch == 1 ? std::min<int64_t>(kMaxSplits, g.K / 256) : 1;
+    if (S <= 1 || g.beta.x != 0.0 || g.beta.y != 0.0) {
+      parts.push_back(g);
+      continue;
+    }
+    const int64_t kc = ((g.K + S - 1) / S + 15) / 16 * 16;
+    S = (g.K + kc - 1) / kc;
+    const int64_t per = g.M * g.N;
+    for (int64_t sp = 0; sp < S; ++sp) {
+      GemmArgs<z64> q = g;
+      q.K = std::min(kc, g.K - sp * kc);
+      q.A = g.A + sp * kc * g.lda;  // op(A) = A^*: K runs over the rows of A
+      q.B = g.B + sp * kc * g.ldb;
+      q.C = W + off + sp * per;
+      q.ldc = g.N;
+      parts.push_back(q);
+    }
+    dst.push_back(GrpMat{g.C, g.ldc, g.N, g.M});
+    src.push_back(GrpMat{W + off, g.N, S, g.M});
+    off += S * per;
+    per_max = std::max(per_max, per);
+  }
+  if (off * static_cast<int64_t>(sizeof(z64)) > static_cast<int64_t>(b->sk.bytes))
+    throw HipError{hipErrorInvalidValue, "split-K workspace"};
+  ggemm<z64>(b, tab, 2, false, parts);
+  if (dst.empty()) return;
+  const GrpMat *gdst = tab.put(dst), *gsrc = tab.put(src);
+  if (!tab.record)
+    feast::sum_splits_grp(b->gs, gdst, gsrc, static_cast<int>(dst.size()), per_max);
 }
 
 template <typename T>
@@ -551,7 +596,7 @@ void orth_grouped(feast_batch *b, Tables &t, const std::vector<int> &act, int xb
       e.push_back(gargs<z64>(m, m, n, X, m, 0, X, m, 0, b->sub[p]->gblk(feast_plan::G_GRAM), m, 0,
                              1.0, 0.0, 1));
     }
-    ggemm<z64>(b, t, 2, false, e);
+    ggemm_small_out(b, t, e);
     if (pass == 0 && !rec) feast::add_shift_grp(s, gG, cnt, dshift);
     // blocked Cholesky G = R^* R (upper R over G)
     for (int64_t J0 = 0; J0 < b->mmax; J0 += 64) {
@@ -673,8 +718,8 @@ void project_schedule(feast_batch *b, Tables &t, const std::vector<int> &act,
     pb.push_back(gargs<z64>(m, m, n, U2, m, 0, q->wblk(feast_plan::W_BU1), m, 0,
                             q->gblk(feast_plan::G_BT), m, 0, 1.0, 0.0, 1));
   }
-  ggemm<z64>(b, t, 2, false, pa);
-  ggemm<z64>(b, t, 2, false, pb);
+  ggemm_small_out(b, t, pa);
+  ggemm_small_out(b, t, pb);
   // At, Bt of every pencil in `act` into the packed buffer, in list order
   std::vector<GrpMat> src, dst;
   int64_t off = 0, mm_max = 0;
@@ -824,6 +869,7 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
     int64_t pk_elems = 0;
     for (int64_t mp : b->m) pk_elems += 2 * mp * mp;
     b->pk.alloc(sizeof(z64) * pk_elems);
+    b->sk.alloc(sizeof(z64) * kMaxSplits * pk_elems / 2);
     HIPCHK(hipHostMalloc(&b->pk_host, sizeof(z64) * pk_elems, hipHostMallocDefault));
     const int64_t nmat = static_cast<int64_t>(P) * N;
     const size_t esz = b->mixed() ? sizeof(c64) : sizeof(z64);
@@ -887,7 +933,7 @@ int feast_batch_destroy(feast_batch *b) {
   for (feast_plan *p : b->sub) feast_plan_destroy(p);
   for (DevBuf *d : {&b->F, &b->piv, &b->perm, &b->info, &b->Linv, &b->Uinv, &b->grp, &b->Y, &b->Yc,
                     &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev, &b->pj_tab.dev, &b->dinv,
-                    &b->flags, &b->pk})
+                    &b->flags, &b->pk, &b->sk})
     d->release();
   if (b->pk_host) (void)hipHostFree(b->pk_host);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);

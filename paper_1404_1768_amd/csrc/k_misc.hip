@@ -567,6 +567,25 @@ __global__ __launch_bounds__(256) void k_copy_grp(const GrpMat *__restrict__ src
   static_cast<z64 *>(c.base)[i * c.ld + j] = static_cast<const z64 *>(a.base)[i * a.ld + j];
 }
 
+// Split-K partials summed in a fixed order: for matrix b, dst[b] = {C, ldc,
+// cols, rows} and src[b] = {W, -, S, -} with the S partials (rows x cols each,
+// dense) back to back at W; C = W_0 + ... + W_{S-1}.
+__global__ __launch_bounds__(256) void k_sum_splits_grp(const GrpMat *__restrict__ dst,
+                                                        const GrpMat *__restrict__ src) {
+  const GrpMat c = dst[blockIdx.y], w = src[blockIdx.y];
+  const int64_t rows = c.n, cols = c.stride, per = rows * cols;
+  const int64_t q = blockIdx.x * 256ll + threadIdx.x;
+  if (q >= per) return;
+  const z64 *W = static_cast<const z64 *>(w.base);
+  double sr = 0.0, si = 0.0;
+  for (int64_t s = 0; s < w.stride; ++s) {
+    const z64 v = W[s * per + q];
+    sr += v.x;
+    si += v.y;
+  }
+  static_cast<z64 *>(c.base)[(q / cols) * c.ld + q % cols] = make_double2(sr, si);
+}
+
 // Diagonal blocks of the inverted factor into X_b: block I of Dinv (64 x 64,
 // matrix b at Dinv + b * dstride) to X_b[I*64 : , I*64 : ] (rb = min(64, n_b - I*64)).
 __global__ __launch_bounds__(256) void k_put_diag_grp(const GrpMat *__restrict__ g,
@@ -785,6 +804,13 @@ void copy_grp(hipStream_t s, const GrpMat *src, const GrpMat *dst, int count, in
   if (count <= 0 || max_elems <= 0) return;
   hipLaunchKernelGGL(k_copy_grp, dim3(static_cast<unsigned>((max_elems + 255) / 256), count),
                      dim3(256), 0, s, src, dst);
+}
+
+void sum_splits_grp(hipStream_t s, const GrpMat *dst, const GrpMat *src, int count,
+                    int64_t max_elems) {
+  if (count <= 0 || max_elems <= 0) return;
+  hipLaunchKernelGGL(k_sum_splits_grp, dim3(static_cast<unsigned>((max_elems + 255) / 256), count),
+                     dim3(256), 0, s, dst, src);
 }
 
 void put_diag_grp(hipStream_t s, const GrpMat *g, int count, int64_t nblk_max, const z64 *Dinv,

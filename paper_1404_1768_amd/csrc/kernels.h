@@ -145,6 +145,9 @@ void chol_block_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32
 void zero_lower_grp(hipStream_t s, const GrpMat *g, int count, int64_t tmax, bool all);
 // dst_b = src_b for src_b.n rows and dst_b.stride columns (max_elems = max rows*cols).
 void copy_grp(hipStream_t s, const GrpMat *src, const GrpMat *dst, int count, int64_t max_elems);
+// Sum of split-K partials (k_sum_splits_grp): max_elems >= rows x cols of every dst.
+void sum_splits_grp(hipStream_t s, const GrpMat *dst, const GrpMat *src, int count,
+                    int64_t max_elems);
 // Diagonal blocks I of Dinv + b * dstride (64 x 64 each) into X_b.
 void put_diag_grp(hipStream_t s, const GrpMat *g, int count, int64_t nblk_max, const z64 *Dinv,
                   int64_t dstride);
