@@ -323,6 +323,9 @@ const char *feast_last_error(const feast_plan *plan);
  * All pointer arguments of the batch calls below are HOST arrays of `count`
  * entries (device pointers or host buffers as stated), in the caller's order.
  * Options as for a plan (nb is ignored: the grouped LU uses 64-wide panels).
+ * The batch owns its device memory (factors, node solutions, workspaces) and a
+ * page-locked host buffer of 2 sum_p m[p]^2 complex entries through which the
+ * reduced pencils reach the host; feast_batch_destroy frees all of it.
  * Limits: 1 <= count <= 4096, 1 <= m[p] <= n[p] <= 16384. */
 typedef struct feast_batch feast_batch;
 
