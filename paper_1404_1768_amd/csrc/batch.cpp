@@ -600,11 +600,9 @@ void orth_grouped(feast_batch *b, Tables &t, const std::vector<int> &act, int xb
     if (pass == 0 && !rec) feast::add_shift_grp(s, gG, cnt, dshift);
     // blocked Cholesky G = R^* R (upper R over G)
     for (int64_t J0 = 0; J0 < b->mmax; J0 += 64) {
-      if (!rec) {
-        feast::chol_block_grp(s, gG, cnt, J0, b->flags.as<int32_t>() + slot + pass, 8);
-        feast::diag_block_inverse<z64>(s, nullptr, 0, 0, cnt, b->mmax, 64, J0 / 64, J0 / 64 + 1,
-                                       false, Dinv, dstride, gG, 1);
-      }
+      if (!rec)
+        feast::chol_inv_grp(s, gG, cnt, J0, b->flags.as<int32_t>() + slot + pass, 8, Dinv,
+                            dstride);
       std::vector<GemmArgs<z64>> e1, e2;
       for (int i = 0; i < cnt; ++i) {
         const int p = act[i];

@@ -243,9 +243,9 @@ __global__ __launch_bounds__(256) void k_add_shift(z64 *__restrict__ G, int64_t 
 // flag[0] = 1 + col0 + k for the first non-positive pivot k (a unit pivot is
 // used in its place so the kernel finishes).
 template <int S>
-__global__ __launch_bounds__(S * S) void k_chol_inv(z64 *__restrict__ G, int64_t ld, int jb,
-                                                    int col0, int32_t *__restrict__ flag,
-                                                    z64 *__restrict__ Rinv, int64_t ldi) {
+__device__ __forceinline__ void chol_inv_body(z64 *__restrict__ G, int64_t ld, int jb, int col0,
+                                              int32_t *__restrict__ flag,
+                                              z64 *__restrict__ Rinv, int64_t ldi) {
   constexpr int E = 64 / S, RW = 64 / S;
   __shared__ z64 row[2][E][64];
   __shared__ z64 Rs[64][65];
@@ -374,6 +374,30 @@ __global__ __launch_bounds__(S * S) void k_chol_inv(z64 *__restrict__ G, int64_t
     }
 }
 
+template <int S>
+__global__ __launch_bounds__(S * S) void k_chol_inv(z64 *__restrict__ G, int64_t ld, int jb,
+                                                    int col0, int32_t *__restrict__ flag,
+                                                    z64 *__restrict__ Rinv, int64_t ldi) {
+  chol_inv_body<S>(G, ld, jb, col0, flag, Rinv, ldi);
+}
+
+// The same over a group: matrix b = blockIdx.x of g, its diagonal block at
+// (J0, J0) (skipped when J0 is past its order); the inverse of the factor to
+// Dinv + b * dstride + (J0 / 64) * 4096 (leading dimension 64), a breakdown
+// to flag[b * flag_stride].
+template <int S>
+__global__ __launch_bounds__(S * S) void k_chol_inv_grp(const GrpMat *__restrict__ g, int64_t J0,
+                                                        int32_t *__restrict__ flag,
+                                                        int flag_stride, z64 *__restrict__ Dinv,
+                                                        int64_t dstride) {
+  const GrpMat e = g[blockIdx.x];
+  if (J0 >= e.n) return;
+  const int jb = static_cast<int>(e.n - J0 < 64 ? e.n - J0 : 64);
+  chol_inv_body<S>(static_cast<z64 *>(e.base) + J0 * e.ld + J0, e.ld, jb, static_cast<int>(J0),
+                   flag + blockIdx.x * flag_stride, Dinv + blockIdx.x * dstride + (J0 / 64) * 4096,
+                   64);
+}
+
 // Strict lower triangle of a t x t matrix set to zero; optionally the whole matrix.
 __global__ __launch_bounds__(256) void k_zero_lower(z64 *__restrict__ X, int64_t t, int all) {
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
@@ -490,59 +514,6 @@ __global__ __launch_bounds__(256) void k_add_shift_grp(const GrpMat *__restrict_
   }
   const double sh = shift_rel[blockIdx.x] * red[0];
   for (int64_t i = threadIdx.x; i < t; i += 256) G[i * ld + i].x += sh;
-}
-
-// Cholesky of the diagonal block [J0, J0 + jb) of G_b (jb = min(64, n_b - J0)),
-// as k_chol_block; flags at flag[b * flag_stride].
-__global__ __launch_bounds__(256) void k_chol_block_grp(const GrpMat *__restrict__ g, int64_t J0,
-                                                        int32_t *__restrict__ flag,
-                                                        int flag_stride) {
-  __shared__ z64 S[64][65];
-  __shared__ double s_d;
-  const GrpMat e = g[blockIdx.x];
-  if (J0 >= e.n) return;
-  const int jb = static_cast<int>(e.n - J0 < 64 ? e.n - J0 : 64);
-  const int64_t ld = e.ld;
-  z64 *G = static_cast<z64 *>(e.base) + J0 * ld + J0;
-  int32_t *fl = flag + blockIdx.x * flag_stride;
-  const int tid = threadIdx.x;
-  for (int q = tid; q < jb * jb; q += 256) {
-    const int i = q / jb, j = q % jb;
-    S[i][j] = G[i * ld + j];
-  }
-  __syncthreads();
-  for (int k = 0; k < jb; ++k) {
-    if (tid == 0) {
-      const double d = S[k][k].x;
-      if (!(d > 0.0)) {
-        if (fl[0] == 0) fl[0] = static_cast<int>(J0) + k + 1;
-        s_d = 1.0;
-      } else {
-        s_d = sqrt(d);
-      }
-      S[k][k] = make_double2(s_d, 0.0);
-    }
-    __syncthreads();
-    const double d = s_d;
-    for (int j = k + 1 + tid; j < jb; j += 256) {
-      S[k][j].x /= d;
-      S[k][j].y /= d;
-    }
-    __syncthreads();
-    const int m = jb - k - 1;
-    for (int q = tid; q < m * m; q += 256) {
-      const int i = k + 1 + q / m, j = k + 1 + q % m;
-      if (j < i) continue;
-      const z64 a = S[k][i], bb = S[k][j];
-      S[i][j].x -= a.x * bb.x + a.y * bb.y;
-      S[i][j].y -= a.x * bb.y - a.y * bb.x;
-    }
-    __syncthreads();
-  }
-  for (int q = tid; q < jb * jb; q += 256) {
-    const int i = q / jb, j = q % jb;
-    G[i * ld + j] = (j >= i) ? S[i][j] : make_double2(0.0, 0.0);
-  }
 }
 
 // Zero the strict lower triangle (all = 0) or everything (all = 1) of the
@@ -788,10 +759,11 @@ void add_shift_grp(hipStream_t s, const GrpMat *g, int count, const double *shif
   hipLaunchKernelGGL(k_add_shift_grp, dim3(count), dim3(256), 0, s, g, shift_rel);
 }
 
-void chol_block_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32_t *flag,
-                    int flag_stride) {
+void chol_inv_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32_t *flag,
+                  int flag_stride, z64 *Dinv, int64_t dstride) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_chol_block_grp, dim3(count), dim3(256), 0, s, g, J0, flag, flag_stride);
+  hipLaunchKernelGGL((k_chol_inv_grp<32>), dim3(count), dim3(1024), 0, s, g, J0, flag, flag_stride,
+                     Dinv, dstride);
 }
 
 void zero_lower_grp(hipStream_t s, const GrpMat *g, int count, int64_t tmax, bool all) {

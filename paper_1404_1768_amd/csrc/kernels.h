@@ -137,15 +137,16 @@ void fill_i32(hipStream_t s, int32_t *p, int64_t count, int32_t v);
 
 // G_b += shift_rel[b] * trace(G_b) * I (shift_rel: device array).
 void add_shift_grp(hipStream_t s, const GrpMat *g, int count, const double *shift_rel);
-// Cholesky of the diagonal block [J0, J0 + 64) of every G_b with n_b > J0
-// (upper factor in place; flag[b * flag_stride] = 1 + first failing column).
-void chol_block_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32_t *flag,
-                    int flag_stride);
 // Zero the strict lower triangle (or all) of every n_b x n_b matrix (tmax = max n_b).
 void zero_lower_grp(hipStream_t s, const GrpMat *g, int count, int64_t tmax, bool all);
 // dst_b = src_b for src_b.n rows and dst_b.stride columns (max_elems = max rows*cols).
 void copy_grp(hipStream_t s, const GrpMat *src, const GrpMat *dst, int count, int64_t max_elems);
 // Sum of split-K partials (k_sum_splits_grp): max_elems >= rows x cols of every dst.
+// Cholesky of the diagonal 64 x 64 block at (J0, J0) of every matrix of a group
+// and the inverse of its factor (k_chol_inv per matrix): R into the block, R^{-1}
+// to Dinv + b * dstride + (J0 / 64) * 4096 (leading dimension 64).
+void chol_inv_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32_t *flag,
+                  int flag_stride, z64 *Dinv, int64_t dstride);
 void sum_splits_grp(hipStream_t s, const GrpMat *dst, const GrpMat *src, int count,
                     int64_t max_elems);
 // Diagonal blocks I of Dinv + b * dstride (64 x 64 each) into X_b.
