@@ -363,6 +363,138 @@ def test_left_eigenvectors_match_closed_form(n):
 
 
 # ---------------------------------------------------------------------------
+# Residual of eq. (5-1), worked by hand on Example 3.1
+# ---------------------------------------------------------------------------
+
+def _residual_planted_denominator(A, B, lam, X):
+    """A plausible mistake in eq. (5-1): the denominator ||A x|| + |lambda| ||B x||."""
+    AX, BX = A @ X, B @ X
+    return np.array([np.linalg.norm(AX[:, i] - lam[i] * BX[:, i]) /
+                     (np.linalg.norm(AX[:, i]) + abs(lam[i]) * np.linalg.norm(BX[:, i]))
+                     for i in range(X.shape[1])])
+
+
+# (x, lambda, r) with r worked out by hand for the pencil of Example 3.1:
+#  x = e1 + 0.1 e2, lambda = 0.2:  A x = (0, 0, 0.05, 0.2), B x = (0, 0, 0.1, 1),
+#    A x - lambda B x = (0, 0, 0.03, 0)  ->  r = 0.03 / (sqrt(0.0425) + sqrt(1.01));
+#  x = e1 + i e2, lambda = 0.2 + 0.1i:  A x = (0, 0, 0.5i, 0.2), B x = (0, 0, i, 1),
+#    A x - lambda B x = (0, 0, 0.1 + 0.3i, -0.1i)  ->  r = sqrt(0.11) / (sqrt(0.29) + sqrt(2)).
+_EX31_RESIDUALS = [
+    (np.array([1, 0.1, 0, 0], dtype=np.complex128), 0.2,
+     0.03 / (math.sqrt(0.0425) + math.sqrt(1.01))),
+    (np.array([1, 1j, 0, 0], dtype=np.complex128), 0.2 + 0.1j,
+     math.sqrt(0.11) / (math.sqrt(0.29) + math.sqrt(2.0))),
+]
+
+
+def test_residual_eq_5_1_hand_values_on_example31():
+    # Eq. (5-1): r = ||A x - lambda B x||_2 / (||A x||_2 + ||B x||_2), checked on
+    # values worked out by hand (no re-typed formula), scale invariance in x,
+    # zero at the printed eigenpairs and +inf for an infinite eigenvalue.
+    A, B, eig = load_example31()
+    X = np.stack([x for x, _, _ in _EX31_RESIDUALS], axis=1)
+    lam = np.array([l for _, l, _ in _EX31_RESIDUALS])
+    ref = np.array([r for _, _, r in _EX31_RESIDUALS])
+    r = o.residuals(A, B, lam, X)
+    assert np.max(np.abs(r - ref) / ref) < 1e-14
+    assert np.max(np.abs(o.residuals(A, B, lam, (2.5 - 1.5j) * X) - ref) / ref) < 1e-14
+    for l, x in eig:
+        assert o.residuals(A, B, np.array([l]), x[:, None])[0] == 0.0
+    assert o.residuals(A, B, np.array([np.inf + 0j]), X[:, :1])[0] == np.inf
+
+
+def test_planted_residual_denominator_is_caught():
+    # The hand values above reject the denominator ||A x|| + |lambda| ||B x||.
+    A, B, _ = load_example31()
+    X = np.stack([x for x, _, _ in _EX31_RESIDUALS], axis=1)
+    lam = np.array([l for _, l, _ in _EX31_RESIDUALS])
+    ref = np.array([r for _, _, r in _EX31_RESIDUALS])
+    bad = _residual_planted_denominator(A, B, lam, X)
+    assert np.min(np.abs(bad - ref) / ref) > 0.1
+
+
+# ---------------------------------------------------------------------------
+# Eigenvalue derivatives (first-order perturbation of a simple eigenvalue)
+# ---------------------------------------------------------------------------
+
+def _brute_force_pairs(A, B, center, radius, seed):
+    """Inside eigenvalues with right and left eigenvectors from the dense QZ,
+    each vector rescaled by a random complex factor (so y^* B x != 1)."""
+    ev, Yl, X = sla.eig(A, B, left=True, right=True)
+    sel = np.abs(ev - center) < radius
+    rng = np.random.default_rng(seed)
+    k = int(np.count_nonzero(sel))
+    sx = rng.uniform(0.5, 2.0, k) * np.exp(2j * np.pi * rng.random(k))
+    sy = rng.uniform(0.5, 2.0, k) * np.exp(2j * np.pi * rng.random(k))
+    return ev[sel], X[:, sel] * sx[None, :], Yl[:, sel] * sy[None, :]
+
+
+def _fd_eigenvalue_derivative(A, B, lam, dA, dB, h, center, radius):
+    """Central differences of the brute-force eigenvalues along (dA, dB), each
+    perturbed eigenvalue matched to the nearest unperturbed one."""
+    out = []
+    for sgn in (1.0, -1.0):
+        e = sla.eigvals(A + sgn * h * dA, B + sgn * h * dB)
+        e = e[np.isfinite(e)]
+        out.append(np.array([e[np.argmin(np.abs(e - l))] for l in lam]))
+    return (out[0] - out[1]) / (2.0 * h)
+
+
+def test_eigenvalue_derivatives_match_finite_differences():
+    # d lambda_i = y_i^*(dA - lambda_i dB) x_i / (y_i^* B x_i) against central
+    # differences of brute-force eigenvalues of the perturbed pencils, with the
+    # eigenvectors scaled arbitrarily (the quotient must not depend on it).
+    p = pg.workload(5, n_override=48)
+    lam, X, Yl = _brute_force_pairs(p.A, p.B, p.center, p.radius, seed=12)
+    assert lam.size == p.s
+    rng = np.random.default_rng(13)
+    for _ in range(3):
+        dA = rng.normal(size=(p.n, p.n)) + 1j * rng.normal(size=(p.n, p.n))
+        dB = rng.normal(size=(p.n, p.n)) + 1j * rng.normal(size=(p.n, p.n))
+        an = o.eigenvalue_derivatives(p.B, lam, X, Yl, dA, dB)
+        fd = _fd_eigenvalue_derivative(p.A, p.B, lam, dA, dB, 1e-6, p.center, p.radius)
+        assert np.max(np.abs(an - fd) / np.abs(fd)) < 1e-6
+
+
+def test_eigenvalue_derivatives_closed_form_PDQ():
+    # For A = P D Q, B = P Q: x_i = Q^{-1} e_i, y_i = P^{-*} e_i, so
+    # d lambda_i = e_i^T P^{-1} (dA - d_i dB) Q^{-1} e_i, the i-th diagonal entry
+    # of the transformed perturbation (Theorem 2.1's Weierstrass form).
+    p = pg.workload(5, n_override=64)
+    ins = np.flatnonzero(p.inside_mask)
+    Pi, Qi = np.linalg.inv(p.P), np.linalg.inv(p.Q)
+    rng = np.random.default_rng(14)
+    dA = rng.normal(size=(p.n, p.n)) + 1j * rng.normal(size=(p.n, p.n))
+    dB = rng.normal(size=(p.n, p.n)) + 1j * rng.normal(size=(p.n, p.n))
+    TA, TB = Pi @ dA @ Qi, Pi @ dB @ Qi
+    ref = np.diag(TA)[ins] - p.d[ins] * np.diag(TB)[ins]
+    # oracle from brute-force (arbitrarily scaled) eigenvectors
+    lam, X, Yl = _brute_force_pairs(p.A, p.B, p.center, p.radius, seed=15)
+    order = [int(np.argmin(np.abs(lam - p.d[i]))) for i in ins]
+    an = o.eigenvalue_derivatives(p.B, lam[order], X[:, order], Yl[:, order], dA, dB)
+    assert np.max(np.abs(an - ref) / np.abs(ref)) < 1e-10
+
+
+def test_planted_eigenvalue_derivative_mistakes_are_caught():
+    # Dropping the denominator y^* B x, flipping the sign of the dB term or
+    # conjugating lambda in it all fail the finite-difference pin.
+    p = pg.workload(5, n_override=48)
+    lam, X, Yl = _brute_force_pairs(p.A, p.B, p.center, p.radius, seed=16)
+    rng = np.random.default_rng(17)
+    dA = rng.normal(size=(p.n, p.n)) + 1j * rng.normal(size=(p.n, p.n))
+    dB = rng.normal(size=(p.n, p.n)) + 1j * rng.normal(size=(p.n, p.n))
+    fd = _fd_eigenvalue_derivative(p.A, p.B, lam, dA, dB, 1e-6, p.center, p.radius)
+    planted = [
+        lambda x, y, l: np.vdot(y, (dA - l * dB) @ x),                          # no denominator
+        lambda x, y, l: np.vdot(y, (dA + l * dB) @ x) / np.vdot(y, p.B @ x),    # sign of dB
+        lambda x, y, l: np.vdot(y, (dA - np.conj(l) * dB) @ x) / np.vdot(y, p.B @ x),
+    ]
+    for f in planted:
+        bad = np.array([f(X[:, i], Yl[:, i], lam[i]) for i in range(lam.size)])
+        assert np.max(np.abs(bad - fd) / np.abs(fd)) > 1e-3
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes: the pins above must catch them
 # ---------------------------------------------------------------------------
 
