@@ -100,7 +100,7 @@ def time_form(form, p, A, B, V, steps, warmup):
                 "err": last.err, "count": len(last.lam), "sweeps": last.sweeps,
                 "errs": [float("%.3g" % e) for e in last.errs],
                 "phases_ms": {k: round(v, 3) for k, v in last.times.items()},
-                "lu_gemm": last.lu_gemm}
+                "lu_gemm": last.lu_gemm, "hbm": hbm_report(last.hbm)}
     finally:
         plan.close()
 
@@ -304,45 +304,62 @@ def time_batch(ps, As, Bs, Vs, steps, warmup):
     return out
 
 
-def cpu_baseline(p, gpu_iters, gpu_filters, sample_nodes):
-    """The oracle on a bounded sample: `sample_nodes` of the N shifted LU
-    factorisations and solves, one projection and one reduced eigenproblem,
-    scaled to the full time-to-eigenpairs with the GPU run's iteration count."""
-    import numpy as np
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p):
+    """The oracle (plain NumPy/SciPy FP64 Algorithm 5, not tuned) timed in full
+    on this host: the metric's workload from V to rule 13 with every host core,
+    and the n = 200 workload (two filters) on one thread."""
+    import pencilgen as pg
     from threadpoolctl import threadpool_limits, threadpool_info
     from oracle import gfeast as o
     cores = len(os.sched_getaffinity(0))
     with threadpool_limits(limits=cores):
-        z, w = o.contour_nodes(p.center, p.radius, p.nodes)
-        solver = o.ShiftedSolver(p.A, p.B, z)
-        R = p.B @ p.V
+        blas = sorted({"%s %s (%s threads)" % (d.get("internal_api", "?"),
+                                               d.get("version", "?"), d.get("num_threads"))
+                       for d in threadpool_info()})
         t0 = time.perf_counter()
-        for j in range(sample_nodes):
-            solver.factor(j)
-        t_fac = (time.perf_counter() - t0) / sample_nodes
+        r = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes, eps=1e-10)
+        full_s = time.perf_counter() - t0
+    p1 = pg.workload(1)
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        for j in range(sample_nodes):
-            solver.solve(j, R)
-        t_sol = (time.perf_counter() - t0) / sample_nodes
-        t0 = time.perf_counter()
-        U1, _ = o.orth(R)
-        U2, _ = o.orth(p.B @ U1)
-        At, Bt = o.project(p.A, p.B, U1, U2)
-        t_proj = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        al, be, Y = o.reduced_eig(At, Bt)
-        lam = o.eigenvalues_from(al, be)
-        X = U1 @ Y
-        o.residuals(p.A, p.B, lam, X)
-        t_eig = time.perf_counter() - t0
-    total_s = p.nodes * (t_fac + gpu_filters * t_sol) + gpu_iters * (t_proj + t_eig)
-    blas = ";".join(sorted({d.get("internal_api", "?") + ":" + str(d.get("num_threads"))
-                            for d in threadpool_info()}))
-    return {"value": round(total_s * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
-            "sample": ("%d of %d shifted LU factorisations and solves, 1 projection and 1 reduced "
-                       "eigenproblem at n=%d, m=%d, scaled to %d nodes, %d filters, %d iterations; "
-                       "BLAS %s") % (sample_nodes, p.nodes, p.n, p.m, p.nodes, gpu_filters,
-                                     gpu_iters, blas)}
+        r1 = o.gfeast(p1.A, p1.B, p1.V, p1.center, p1.radius, p1.nodes, max_iter=2)
+        one_s = time.perf_counter() - t0
+    return {"value": round(full_s * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": ("the whole workload, not a sample: Algorithm 5 at n=%d, N=%d, m=%d from V "
+                       "to e(k) < 1e-10 (%d iterations, %d filters, flag %d, %d eigenpairs, "
+                       "Err %.2e)") % (p.n, p.nodes, p.m, r.iters, r.filters, r.flag,
+                                       len(r.lam), r.err),
+            "cpu_model": _cpu_model(), "blas": blas,
+            "one_thread": {"workload": "n=%d N=%d m=%d, 2 filters" % (p1.n, p1.nodes, p1.m),
+                           "ms": round(one_s * 1e3, 1), "count": len(r1.lam)}}
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def hbm_report(hbm):
+    """Achieved GB/s of the bandwidth-bound kernels of one solve (HIP events on
+    the library's stream; algorithmic bytes: operands read once, results written once)."""
+    out = {}
+    for k, v in hbm.items():
+        if v["launches"] <= 0 or v["ms"] <= 0:
+            continue
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        out[k] = {"launches": v["launches"], "avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
+                  "bytes_per_launch": round(v["bytes"] / v["launches"]),
+                  "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def main():
@@ -351,7 +368,6 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="fp64,mixed")
-    ap.add_argument("--cpu-nodes", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cirr", action="store_true",
@@ -365,8 +381,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 1 GiB (3 launches): the reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a PMC run")
-    ap.add_argument("--large", action="store_true",
-                    help="also time the n=8000, m=256 mixed-precision workload (key 'large')")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the n=8000, m=256 mixed-precision workload (key 'large')")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the path shards over quadrature nodes across GPUs "
@@ -430,16 +446,20 @@ def main():
     if not args.no_standin:
         standin = time_standin((6, 7), min(args.steps, 2), 1)
     large = None
-    if args.large:
+    if not args.no_large:
+        t0 = time.perf_counter()
         pl = pg.workload(3)
+        log("[bench] generated workload n=%d m=%d in %.1f s" % (pl.n, pl.m, time.perf_counter() - t0))
         lA, lB, lV = (torch.from_numpy(x).to(dev) for x in (pl.A, pl.B, pl.V))
+        pl.A = pl.B = pl.P = pl.Q = None     # (host copies no longer needed)
         r = time_form("mixed", pl, lA, lB, lV, min(args.steps, 2), 1)
         large = {"workload": "pencil n=8000 N=32 m=256 s=120 (394 eigenvalues in 1.05..1.2)",
                  "mixed": r}
         del lA, lB, lV
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(p, b["iters"], b["filters"], args.cpu_nodes)
+        cpu = cpu_baseline(p)
         log("[bench] cpu baseline: %s" % cpu)
     out = {
         "metric": "time-to-eigenpairs @rel.resid\u22641e-10 (n=4000,N=32), FP64 vs mixed; MFMA util",
@@ -448,7 +468,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[best], "data": "synthetic",
         "config": {"workload": "pencil n=4000 N=32 m=160 s=100 (trapezoid, circle 1+1i r=1)",
                    "form": best, "n": p.n, "nodes": p.nodes, "m": p.m, "eps": 1e-10},
-        "forms": forms, "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "forms": forms, "roofline": roof, "hbm": b["hbm"], "cpu_baseline": cpu,
+        "batched": batched,
         "search": search, "cirr": cirr, "adjoint": adjoint, "standin": standin,
         "large": large,
     }

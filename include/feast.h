@@ -19,8 +19,16 @@
  *    with leading dimension ld (ld >= c) is at index i*ld + j.
  *  - Pointers named dX are device pointers (HIP device memory on the current
  *    device); pointers named hX are host pointers.  The caller owns every
- *    buffer it passes; the library keeps no pointer after a call returns,
- *    except that a plan remembers which (dA, dB) its cached factors belong to.
+ *    buffer it passes; the library keeps no pointer after a call returns.
+ *  - Cached factors: a plan (or batch) keeps the LU factors of its shifted
+ *    matrices and reuses them on a later call only if A and B have the same
+ *    content as when they were factored (Section 4.3 reuses the factors of
+ *    the same shifted matrices).  Each call that may reuse them reads A and B
+ *    once for a 64-bit content fingerprint (a position-keyed hash of every
+ *    entry's bits; any single-entry change is always detected, several
+ *    changes are missed with probability about 2^-64), so a different pencil
+ *    placed at the same address, or A or B changed in place, is refactored.
+ *    The fingerprint costs one read of A and B and a host wait for two words.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    All device work of a plan is enqueued on its stream; entry points that
  *    return host data synchronise that stream before returning.
@@ -105,13 +113,15 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
 /* Release the plan and all memory it owns.  NULL is accepted. */
 int feast_plan_destroy(feast_plan *plan);
 
-/* Drop the cached factors (A or B changed in place). */
+/* Drop the cached factors: the next call factors again whatever the
+ * fingerprints say (a caller that wants to time the factorisation). */
 int feast_plan_invalidate(feast_plan *plan);
 
 /* The filter of eq. (8-4) applied to a block (Algorithm 5, filter step):
  *   U = sum_j w_j (z_j B - A)^{-1} B V,   V, U: n x m.
- * The first call (or the first after feast_plan_invalidate, or with other dA/dB)
- * factors every z_j B - A with partial pivoting and caches the factors.
+ * The first call (or the first after feast_plan_invalidate, or with a pencil
+ * whose content differs from the cached one) factors every z_j B - A with
+ * partial pivoting and caches the factors.
  * FEAST_MIXED factors in complex64 and refines every node solution in FP64
  * (residual B V - (z_j B - A) Y_j, correction with the complex64 factors,
  * FP64 update) until the backward-error target or max_sweeps.
@@ -132,6 +142,24 @@ int feast_project(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_
                   int64_t ldb, feast_z *dU, int64_t ldu, feast_z *dAU1, int64_t ldau,
                   feast_z *dBU1, int64_t ldbu, feast_z *hAt, feast_z *hBt);
 
+/* Bandwidth-bound kernels timed with opts.profile = 1 (feast_info.hbm[class]). */
+enum feast_kclass {
+  FEAST_K_SHIFT = 0,     /* z_j B - A for all nodes: reads A, B, writes N shifted matrices */
+  FEAST_K_WSUM = 1,      /* U = sum_j w_j Y_j: reads N node blocks, writes U */
+  FEAST_K_GATHER = 2,    /* row permutation of the right-hand sides for every node */
+  FEAST_K_Z2C = 3,       /* complex128 -> complex64 right-hand sides (mixed form) */
+  FEAST_K_C2Z = 4,       /* complex64 solutions -> complex128 (set or add; mixed form) */
+  FEAST_K_FINGERPRINT = 5, /* content fingerprints of A and B (factor reuse check) */
+  FEAST_K_CLASSES = 6
+};
+/* launches, summed event time and algorithmic HBM bytes (every operand byte
+   read once and every result byte written once) of one kernel class */
+typedef struct {
+  int32_t launches;
+  double ms;
+  double bytes;
+} feast_kprof;
+
 /* Per-run record of Algorithm 5 (optional output of feast_solve). */
 #define FEAST_MAX_HISTORY 64
 typedef struct {
@@ -147,6 +175,8 @@ typedef struct {
   int32_t lu_gemm_launches;
   double lu_gemm_ms;
   double lu_gemm_flops;
+  /* with opts.profile = 1: the bandwidth-bound kernels of this call, per class */
+  feast_kprof hbm[FEAST_K_CLASSES];
 } feast_info;
 
 /* GFEAST (Algorithm 5) with the subspace size fixed to m and a caller-supplied
@@ -165,7 +195,10 @@ typedef struct {
  * settled count misses eps without at least halving e(k), every later filter
  * refines each node until its normwise backward error reaches refine_tol (at
  * most max_sweeps; a filter already launched is refined further from its
- * node solutions).  Synchronises the stream. */
+ * node solutions).  In the mixed form the no-improvement stop (flag 0) is
+ * taken only once that verified refinement is on: an earlier rise of e(k)
+ * switches it on and the iteration continues (the rise can come from the
+ * complex64 solves rather than from the subspace).  Synchronises the stream. */
 int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
                 int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *hLambda,
                 feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, double *err,
@@ -339,7 +372,7 @@ typedef struct {
 int feast_batch_create(feast_batch **batch, int32_t count, const int64_t *n, const int64_t *m,
                        const feast_contour *c, const feast_opts *o, void *stream);
 int feast_batch_destroy(feast_batch *batch);
-/* Drop the cached factors (A_p or B_p changed in place). */
+/* Drop the cached factors (the next call factors again). */
 int feast_batch_invalidate(feast_batch *batch);
 const char *feast_batch_last_error(const feast_batch *batch);
 
@@ -361,7 +394,9 @@ int feast_batch_filter(feast_batch *batch, const feast_z *const *dA, const int64
  * iters[p] (host arrays of count entries).  Mixed plans refine with one
  * grouped sweep count: none on the first filter, one correction per node
  * afterwards, one more whenever a refined iteration of some pencil misses eps
- * without at least halving e(k) (at most max_sweeps).  The second filter is
+ * without at least halving e(k) (at most max_sweeps); a rise of some pencil's
+ * e(k) while the count is below max_sweeps also adds a sweep instead of
+ * stopping that pencil with flag 0.  The second filter is
  * launched before the first iteration's host eigensolves (a pencil that stops
  * there has had it computed for nothing).
  * info may be NULL. */

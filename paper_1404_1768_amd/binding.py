@@ -60,6 +60,13 @@ class Opts(C.Structure):
                 ("update_tile", C.c_int32)]
 
 
+K_CLASSES = ["shift", "weighted_sum", "gather_rows", "z_to_c", "c_to_z", "fingerprint"]
+
+
+class KProf(C.Structure):
+    _fields_ = [("launches", C.c_int32), ("ms", C.c_double), ("bytes", C.c_double)]
+
+
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("filters", C.c_int32),
                 ("count", C.c_int32 * MAX_HISTORY), ("err", C.c_double * MAX_HISTORY),
@@ -68,7 +75,7 @@ class Info(C.Structure):
                 ("t_project_ms", C.c_double), ("t_host_eig_ms", C.c_double),
                 ("t_ritz_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("lu_gemm_launches", C.c_int32), ("lu_gemm_ms", C.c_double),
-                ("lu_gemm_flops", C.c_double)]
+                ("lu_gemm_flops", C.c_double), ("hbm", KProf * len(K_CLASSES))]
 
 
 class SearchInfo(C.Structure):
@@ -291,6 +298,7 @@ class SolveResult:
     times: dict
     status: int
     lu_gemm: dict
+    hbm: dict = dataclasses.field(default_factory=dict)
 
 
 class Plan:
@@ -415,7 +423,10 @@ class Plan:
                    "project": info.t_project_ms, "host_eig": info.t_host_eig_ms,
                    "ritz": info.t_ritz_ms, "total": info.t_total_ms},
             status=rc, lu_gemm={"launches": info.lu_gemm_launches, "ms": info.lu_gemm_ms,
-                                "flops": info.lu_gemm_flops})
+                                "flops": info.lu_gemm_flops},
+            hbm={name: {"launches": info.hbm[i].launches, "ms": info.hbm[i].ms,
+                        "bytes": info.hbm[i].bytes}
+                 for i, name in enumerate(K_CLASSES) if info.hbm[i].launches > 0})
 
     # -- Search (Algorithm 4) ----------------------------------------------
     def search(self, A, B, Ypool, p: int, alpha: float = 1.5, tau: float = 1e-3):
@@ -513,6 +524,12 @@ def _feast_eig_function():
         @staticmethod
         def forward(ctx, A, B, V, plan, sweeps):
             r = plan.solve(A, B, V)
+            if r.flag != 1:
+                import warnings
+                warnings.warn("feast_eig: Algorithm 5 stopped with flag %d (%s), Err = %.3e; the "
+                              "eigenvalues and their gradients carry that error" %
+                              (r.flag, "no improvement, previous iterate" if r.flag == 0
+                               else "iteration cap", r.err), RuntimeWarning, stacklevel=3)
             ctx.plan, ctx.sweeps = plan, sweeps
             ctx.X = r.X.contiguous().clone()
             ctx.lam = r.lam.copy()

@@ -136,8 +136,11 @@ struct feast_batch {
   DevBuf sk;  // split-K partials of the m x m products (up to kMaxSplits per pencil)
   int64_t mmax = 0;
   Graph g_factor, g_filter;
+  // cached factors belong to the pencils whose content fingerprints are ffp
+  // (A_p, B_p in the caller's order); fptab/fpout: the fingerprint launch
   bool factored = false;
-  std::vector<int64_t> fkey;
+  std::vector<uint64_t> ffp;
+  DevBuf fptab, fpout;
   std::string err;
   int launches = 0;
 
@@ -434,11 +437,37 @@ template <class Body> void run_graph(feast_batch *b, Graph &g, const std::vector
   ++b->launches;
 }
 
+// Content fingerprints of every A_p and B_p (caller's order: A_0, B_0, A_1, ...),
+// one grouped launch; synchronises the batch stream.
+std::vector<uint64_t> fingerprints(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
+                                   const feast_z *const *dB, const int64_t *ldb) {
+  std::vector<GrpMat> tab(2 * static_cast<size_t>(b->P));
+  for (int c = 0; c < b->P; ++c) {
+    const int64_t n = b->n[b->where[c]];
+    tab[2 * c] = {const_cast<feast_z *>(dA[c]), lda[c], 0, n};
+    tab[2 * c + 1] = {const_cast<feast_z *>(dB[c]), ldb[c], 0, n};
+  }
+  b->fptab.alloc(sizeof(GrpMat) * tab.size());
+  b->fpout.alloc(sizeof(uint64_t) * tab.size());
+  HIPCHK(hipMemcpyAsync(b->fptab.p, tab.data(), sizeof(GrpMat) * tab.size(), hipMemcpyHostToDevice,
+                        b->gs));
+  feast::fingerprint(b->gs, b->fptab.as<GrpMat>(), static_cast<int>(tab.size()), GrpMat{},
+                     GrpMat{}, b->nmax, b->fpout.as<uint64_t>());
+  std::vector<uint64_t> out(tab.size());
+  HIPCHK(hipMemcpyAsync(out.data(), b->fpout.p, sizeof(uint64_t) * out.size(),
+                        hipMemcpyDeviceToHost, b->gs));
+  HIPCHK(hipStreamSynchronize(b->gs));
+  return out;
+}
+
 // Factor every shifted matrix of every pencil (graph), then check the pivots.
+// The cached factors are reused only for pencils with unchanged content
+// (Section 4.3); the graph is re-captured when the caller's pointers change.
 int factor_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
                const feast_z *const *dB, const int64_t *ldb) {
+  const std::vector<uint64_t> fps = fingerprints(b, dA, lda, dB, ldb);
+  if (b->factored && fps == b->ffp) return FEAST_OK;
   const std::vector<int64_t> key = make_key(b, dA, lda, dB, ldb, 0);
-  if (b->factored && key == b->fkey) return FEAST_OK;
   b->factored = false;
   run_graph(b, b->g_factor, key, [&]() {
     for (int p = 0; p < b->P; ++p) {
@@ -474,7 +503,7 @@ int factor_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
       }
     }
   b->factored = true;
-  b->fkey = key;
+  b->ffp = fps;
   return FEAST_OK;
 }
 
@@ -497,16 +526,22 @@ void filter_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
     } else {
       z64 *Y = b->Y.as<z64>(), *T1 = b->T1.as<z64>(), *T2 = b->T2.as<z64>();
       c64 *Yc = b->Yc.as<c64>();
+      // ||R_p||_F^2 sets the power-of-two scale of pencil p's complex64 solves
+      auto rn = [&](int p) { return b->sub[p]->rn.as<double>(); };
+      auto rcnt = [&](int p) { return static_cast<double>(b->n[p]) * b->m[p]; };
       for (int p = 0; p < b->P; ++p) {
         const int64_t ldy = b->ldY(p);
+        feast::fro2_batched(s, b->sub[p]->R.as<z64>(), b->m[p], 0, b->n[p], b->m[p], 1, rn(p) + 8,
+                            rn(p));
         feast::gather_rows<z64>(s, b->sub[p]->R.as<z64>(), b->m[p], 0, perm + p * N * nmax,
                                 b->n[p], b->m[p], N, T1 + b->toff[p], ldy, b->m[p], nmax);
-        feast::z_to_c(s, T1 + b->toff[p], ldy, 0, b->n[p], ldy, 1, Yc + b->yoff[p], ldy, 0);
+        feast::z_to_c(s, T1 + b->toff[p], ldy, 0, b->n[p], ldy, 1, Yc + b->yoff[p], ldy, 0, rn(p),
+                      rcnt(p));
       }
       trsolve_grouped<c64>(b, Yc);
       for (int p = 0; p < b->P; ++p)
         feast::c_to_z(s, Yc + b->yoff[p], b->ldY(p), 0, b->n[p], b->ldY(p), 1, Y + b->yoff[p],
-                      b->ldY(p), 0);
+                      b->ldY(p), 0, rn(p), rcnt(p));
       for (int sw = 0; sw < sweeps; ++sw) {
         // FP64 residual r_j = R - (z_j B - A) Y_j of all nodes of a pencil in
         // one launch, then the complex64 correction
@@ -530,12 +565,12 @@ void filter_all(feast_batch *b, const feast_z *const *dA, const int64_t *lda,
           }
           feast::gather_rows<z64>(s, t1, ldy, b->m[p], perm + p * N * nmax, n, b->m[p], N, t2, ldy,
                                   b->m[p], nmax);
-          feast::z_to_c(s, t2, ldy, 0, n, ldy, 1, Yc + b->yoff[p], ldy, 0);
+          feast::z_to_c(s, t2, ldy, 0, n, ldy, 1, Yc + b->yoff[p], ldy, 0, rn(p), rcnt(p));
         }
         trsolve_grouped<c64>(b, Yc);
         for (int p = 0; p < b->P; ++p)
           feast::add_c_to_z(s, Yc + b->yoff[p], b->ldY(p), 0, b->n[p], b->ldY(p), 1,
-                            Y + b->yoff[p], b->ldY(p), 0);
+                            Y + b->yoff[p], b->ldY(p), 0, rn(p), rcnt(p));
       }
     }
     const z64 *Y = b->Y.as<z64>();
@@ -620,13 +655,14 @@ void orth_grouped(feast_batch *b, Tables &t, const std::vector<int> &act, int xb
       ggemm<z64>(b, t, 2, false, e1);
       ggemm<z64>(b, t, 2, false, e2);
     }
-    // Ri = R^{-1}: inverted diagonal blocks, then X12 = -X11 R12 X22 by halving
+    // Ri = R^{-1}: the inverted diagonal blocks chol_inv_grp left in Dinv (upper
+    // triangles; their strict lower parts are not written), then
+    // X12 = -X11 R12 X22 by halving
     if (!rec) {
       feast::zero_lower_grp(s, gG, cnt, b->mmax, false);
       feast::zero_lower_grp(s, gR, cnt, b->mmax, true);
-      feast::diag_block_inverse<z64>(s, nullptr, 0, 0, cnt, b->mmax, 64, 0, b->mblk(), false, Dinv,
-                                     dstride, gG, 1);
       feast::put_diag_grp(s, gR, cnt, b->mblk(), Dinv, dstride);
+      feast::zero_lower_grp(s, gR, cnt, b->mmax, false);
     }
     struct Rec {
       static void run(feast_batch *b, Tables &t, const std::vector<int> &act, int64_t r0,
@@ -931,7 +967,7 @@ int feast_batch_destroy(feast_batch *b) {
   for (feast_plan *p : b->sub) feast_plan_destroy(p);
   for (DevBuf *d : {&b->F, &b->piv, &b->perm, &b->info, &b->Linv, &b->Uinv, &b->grp, &b->Y, &b->Yc,
                     &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev, &b->pj_tab.dev, &b->dinv,
-                    &b->flags, &b->pk, &b->sk})
+                    &b->flags, &b->pk, &b->sk, &b->fptab, &b->fpout})
     d->release();
   if (b->pk_host) (void)hipHostFree(b->pk_host);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
@@ -946,7 +982,7 @@ int feast_batch_destroy(feast_batch *b) {
 int feast_batch_invalidate(feast_batch *b) {
   if (!b) return FEAST_EINVAL;
   b->factored = false;
-  b->fkey.clear();
+  b->ffp.clear();
   return FEAST_OK;
 }
 
@@ -1168,8 +1204,12 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
         }
         const int c_k = static_cast<int>(sel.size());
         if (c_k == 0) e_k = INFINITY;
-        const int a = feast_host::stop_rule(k, c_k, e_k, st[p].c_prev, st[p].e_prev, b->o.eps,
-                                            b->o.max_iter);
+        // mixed form: a rise of e(k) while the grouped sweep count can still
+        // grow is taken as the solves limiting the accuracy (one more sweep,
+        // below), not as the no-improvement stop
+        int a = feast_host::stop_rule(k, c_k, e_k, st[p].c_prev, st[p].e_prev, b->o.eps,
+                                      b->o.max_iter);
+        if (a == 0 && b->mixed() && base_sweeps < b->o.max_sweeps) a = 2;
         int32_t *didx = reinterpret_cast<int32_t *>(q->small.as<z64>() + m);
         if (a == 1 || a == -1) {
           if (c_k > 0) {

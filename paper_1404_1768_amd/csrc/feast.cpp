@@ -217,6 +217,14 @@ void plan_trsolve(feast_plan *p, hipStream_t s, T *Y, int64_t m, int64_t ldy, in
 // Plan helpers
 // ---------------------------------------------------------------------------
 
+// Fingerprints of A and B (n x n) into p->fp[0], p->fp[1] on the plan's stream.
+void launch_fingerprints(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
+  p->fp.alloc(2 * sizeof(uint64_t));
+  const feast::GrpMat a{const_cast<z64 *>(A), lda, 0, p->n}, b{const_cast<z64 *>(B), ldb, 0, p->n};
+  ktimed(p, FEAST_K_FINGERPRINT, 32.0 * p->n * p->n,
+         [&]() { feast::fingerprint(p->s, nullptr, 2, a, b, p->n, p->fp.as<uint64_t>()); });
+}
+
 int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
   const int64_t n = p->n;
   const int N = p->N;
@@ -247,7 +255,9 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
                       p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE,
                       p->pucnt.as<int32_t>()};
   if (p->mixed()) {
-    feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
+    ktimed(p, FEAST_K_SHIFT, (32.0 + 8.0 * N) * n * n, [&]() {
+      feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
+    });
     lu_batched<c64>(lst, p->F.as<c64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<c64>(), p->Uinv.as<c64>(), p->istride(),
                     &prof);
@@ -256,7 +266,9 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
                                 (lower ? p->Linv : p->Uinv).as<c64>(), p->istride(),
                                 (lower ? p->Linv2 : p->Uinv2).as<c64>(), p->istride2(), lower);
   } else {
-    feast::shift_assemble_z(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<z64>(), n, n * n);
+    ktimed(p, FEAST_K_SHIFT, (32.0 + 16.0 * N) * n * n, [&]() {
+      feast::shift_assemble_z(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<z64>(), n, n * n);
+    });
     lu_batched<z64>(lst, p->F.as<z64>(), n, n * n, N, n, p->nb, p->piv.as<int32_t>(),
                     p->info.as<int32_t>(), p->Linv.as<z64>(), p->Uinv.as<z64>(), p->istride(),
                     &prof);
@@ -269,10 +281,13 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
   double *nrm = p->nrm.as<double>();
   feast::fro2_batched(s, A, lda, 0, n, n, 1, p->part.as<double>(), nrm);
   feast::fro2_batched(s, B, ldb, 0, n, n, 1, p->part.as<double>(), nrm + 1);
+  launch_fingerprints(p, A, lda, B, ldb);
   std::vector<int32_t> hinfo(N);
   double h2[2];
+  uint64_t hfp[2];
   HIPCHK(hipMemcpyAsync(hinfo.data(), p->info.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(h2, nrm, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hfp, p->fp.p, sizeof(hfp), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
   p->normA = std::sqrt(h2[0]);
@@ -286,10 +301,8 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     p->prof_ms += ms;
   }
   p->factored = true;
-  p->fA = A;
-  p->fB = B;
-  p->flda = lda;
-  p->fldb = ldb;
+  p->fpA = hfp[0];
+  p->fpB = hfp[1];
   for (int j = 0; j < N; ++j)
     if (hinfo[j] != 0) {
       char buf[200];
@@ -301,8 +314,17 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
   return FEAST_OK;
 }
 
+// Reuse the cached factors only for the pencil they were computed from
+// (Section 4.3: the factors of the same shifted matrices): one read of A and B
+// for their fingerprints and a wait for the two words.
 int ensure_factored(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
-  if (p->factored && p->fA == A && p->fB == B && p->flda == lda && p->fldb == ldb) return FEAST_OK;
+  if (p->factored) {
+    launch_fingerprints(p, A, lda, B, ldb);
+    uint64_t hfp[2];
+    HIPCHK(hipMemcpyAsync(hfp, p->fp.p, sizeof(hfp), hipMemcpyDeviceToHost, p->s));
+    HIPCHK(hipStreamSynchronize(p->s));
+    if (hfp[0] == p->fpA && hfp[1] == p->fpB) return FEAST_OK;
+  }
   return factor(p, A, lda, B, ldb);
 }
 
@@ -312,7 +334,9 @@ int ensure_factored(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int6
 void solve_nodes_z(feast_plan *p, const z64 *R, int64_t ldr, int64_t cols) {
   const int64_t n = p->n, m = p->m, ldY = p->ldY();
   z64 *Y = p->Y.as<z64>();
-  feast::gather_rows<z64>(p->s, R, ldr, 0, p->perm.as<int32_t>(), n, cols, p->N, Y, ldY, m);
+  ktimed(p, FEAST_K_GATHER, 16.0 * n * cols * (1 + p->N), [&]() {
+    feast::gather_rows<z64>(p->s, R, ldr, 0, p->perm.as<int32_t>(), n, cols, p->N, Y, ldY, m);
+  });
   plan_trsolve<z64>(p, p->s, Y, cols, ldY, m, 0);
 }
 
@@ -338,11 +362,18 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
   const c64 *F = p->F.as<c64>();
   const int32_t *perm = p->perm.as<int32_t>();
   double *part = p->part.as<double>(), *nrm = p->nrm.as<double>();
+  // ||R||_F^2 sets the power-of-two scale of every complex64 solve below
+  double *rn = p->rn.as<double>();
+  const double rcnt = static_cast<double>(n) * m;
+  feast::fro2_batched(s, R, ldr, 0, n, m, 1, rn + 8, rn);
   if (!resume) {  // complex64 solve of P_j R
-    feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, sY);
-    feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0);
+    ktimed(p, FEAST_K_GATHER, 16.0 * n * m * (1 + N),
+           [&]() { feast::gather_rows<z64>(s, R, ldr, 0, perm, n, m, N, T1, ldY, sY); });
+    ktimed(p, FEAST_K_Z2C, 24.0 * n * ldY,
+           [&]() { feast::z_to_c(s, T1, ldY, 0, n, ldY, 1, Yc, ldY, 0, rn, rcnt); });
     plan_trsolve<c64>(p, s, Yc, m, ldY, sY, 0);
-    feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
+    ktimed(p, FEAST_K_C2Z, 24.0 * n * ldY,
+           [&]() { feast::c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0, rn, rcnt); });
   }
   p->last_sweeps = 0;
   p->last_be = -1.0;
@@ -385,10 +416,13 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
     }
     // (with cols < m the unused node columns of T1 hold stale values: they are
     // carried along by the conversions but never read by the products)
-    feast::gather_rows<z64>(s, T1, ldY, sY, perm, n, m, N, T2, ldY, sY);
-    feast::z_to_c(s, T2, ldY, 0, n, ldY, 1, Yc, ldY, 0);
+    ktimed(p, FEAST_K_GATHER, 32.0 * n * m * N,
+           [&]() { feast::gather_rows<z64>(s, T1, ldY, sY, perm, n, m, N, T2, ldY, sY); });
+    ktimed(p, FEAST_K_Z2C, 24.0 * n * ldY,
+           [&]() { feast::z_to_c(s, T2, ldY, 0, n, ldY, 1, Yc, ldY, 0, rn, rcnt); });
     plan_trsolve<c64>(p, s, Yc, m, ldY, sY, 0);
-    feast::add_c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0);
+    ktimed(p, FEAST_K_C2Z, 40.0 * n * ldY,
+           [&]() { feast::add_c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0, rn, rcnt); });
     p->last_sweeps = sweep + 1;
   }
 }
@@ -404,8 +438,10 @@ int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t l
     solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps, cols, resume);
   else
     solve_nodes_z(p, R, ldr, cols);
-  feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, cols, U,
-                      ldu);
+  ktimed(p, FEAST_K_WSUM, 16.0 * p->n * cols * (p->N + 1), [&]() {
+    feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, cols, U,
+                        ldu);
+  });
   if (st == FEAST_OK && p->mixed() && p->stagnated) {
     char buf[160];
     std::snprintf(buf, sizeof buf, "refinement stopped at backward error %.3e (target %.3e) after %d sweeps",
@@ -467,6 +503,22 @@ int fail(feast_plan *p, int code, const std::string &msg) {
   return code;
 }
 
+void kprof_reset(feast_plan *p) {
+  p->kev_used = 0;
+  p->krec.clear();
+}
+
+void kprof_collect(feast_plan *p, feast_info *info) {
+  for (const feast_plan::KRec &r : p->krec) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    feast_kprof &k = info->hbm[r.cls];
+    k.launches += 1;
+    k.ms += ms;
+    k.bytes += r.bytes;
+  }
+}
+
 template <>
 void gemm_t<z64>(hipStream_t s, int ta, int64_t M, int64_t N, int64_t K, z64 alpha, const z64 *A,
                  int64_t lda, int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 beta, z64 *C,
@@ -494,6 +546,7 @@ void ensure_workspace(feast_plan *p, bool with_nodes) {
   p->nrm.alloc(sizeof(double) * (3 * m + 4 * N + 16));
   p->flag.alloc(sizeof(int32_t) * 16);
   p->small.alloc(zs * (2 * m + 16));
+  p->rn.alloc(sizeof(double) * (8 + 1024));
   if (p->mixed() && with_nodes) {
     p->T1.alloc(zs * n * m * N);
     p->T2.alloc(zs * n * m * N);
@@ -694,6 +747,7 @@ int feast_plan_destroy(feast_plan *p) {
   if (!p) return FEAST_OK;
   if (p->s) (void)hipStreamSynchronize(p->s);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->kev) (void)hipEventDestroy(e);
   for (hipStream_t st : {p->side, p->aux})
     if (st) {
       (void)hipStreamSynchronize(st);
@@ -705,7 +759,7 @@ int feast_plan_destroy(feast_plan *p) {
     if (e) (void)hipEventDestroy(e);
   for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->pucnt, &p->cirr_w, &p->R,
                     &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->part, &p->nrm,
-                    &p->flag, &p->small})
+                    &p->flag, &p->small, &p->fp, &p->rn})
     b->release();
   delete p;
   return FEAST_OK;
@@ -714,7 +768,6 @@ int feast_plan_destroy(feast_plan *p) {
 int feast_plan_invalidate(feast_plan *p) {
   if (!p) return FEAST_EINVAL;
   p->factored = false;
-  p->fA = p->fB = nullptr;
   return FEAST_OK;
 }
 
@@ -726,6 +779,7 @@ int feast_filter(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
   if (!dA || !dB || !dV || !dU || lda < p->n || ldb < p->n || ldv < p->m || ldu < p->m)
     return fail(p, FEAST_EINVAL, "feast_filter: null pointer or leading dimension too small");
   p->err.clear();
+  kprof_reset(p);
   return guarded(p, [&]() {
     const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
     const z64 *V = reinterpret_cast<const z64 *>(dV);
@@ -777,6 +831,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     feast_info inf{};
     Timer total;
     int status = FEAST_OK;
+    kprof_reset(p);
     {
       Timer t;
       const int st = ensure_factored(p, A, lda, B, ldb);
@@ -909,8 +964,13 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       inf.count[k - 1] = c_k;
       inf.err[k - 1] = e_k;
       inf.iters = k;
-      // stopping rules
-      const int act = feast_host::stop_rule(k, c_k, e_k, c_prev, e_prev, p->o.eps, p->o.max_iter);
+      // stopping rules.  Mixed form: a rise of e(k) before the node solves are
+      // refined to full FP64 backward error may come from the complex64 solves
+      // rather than from the subspace, so it switches verified refinement on
+      // (below) instead of ending the run; the no-improvement rule then judges
+      // iterations whose solves are as accurate as the FP64 form's.
+      int act = feast_host::stop_rule(k, c_k, e_k, c_prev, e_prev, p->o.eps, p->o.max_iter);
+      if (act == 0 && p->mixed() && !verify) act = 2;
       if (act == 1 || act == -1) {
         if (c_k > 0) {
           HIPCHK(hipMemcpyAsync(didx, sel.data(), sizeof(int32_t) * c_k, hipMemcpyHostToDevice, s2));
@@ -992,6 +1052,8 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     inf.lu_gemm_launches = p->prof_launches;
     inf.lu_gemm_ms = p->prof_ms;
     inf.lu_gemm_flops = p->prof_flops;
+    HIPCHK(hipStreamSynchronize(s2));
+    kprof_collect(p, &inf);
     if (info) *info = inf;
     return status;
   });

@@ -58,15 +58,34 @@ __global__ __launch_bounds__(256) void k_shift_residual(const z64 *__restrict__ 
   t1.y = r.y - (zj.x * t2.y + zj.y * t2.x) + t1.y;
 }
 
+// Power-of-two scaling of the complex64 solves in the mixed form: blocks are
+// converted to complex64 as X 2^-e and back as Y 2^e, with e the binary
+// exponent of the root mean square sqrt(nrm2[0] / cnt) of the right-hand side
+// (e = 0 without nrm2, or for a zero or non-finite norm).  Multiplying by a
+// power of two is exact in FP64 and leaves the complex64 rounding unchanged,
+// but keeps right-hand sides and refinement residuals of badly scaled pencils
+// inside complex64's exponent range (residuals shrink to about 1e-16 of the
+// right-hand side, below complex64's smallest normal number for a right-hand
+// side near 1e-25).
+__device__ inline int solve_scale_exp(const double *nrm2, double cnt) {
+  if (!nrm2) return 0;
+  const double rms = sqrt(nrm2[0] / cnt);
+  if (!(rms > 0.0) || !isfinite(rms)) return 0;
+  return ilogb(rms);
+}
+
 __global__ __launch_bounds__(256) void k_c_to_z(const c64 *__restrict__ X, int64_t ldx, int64_t sX,
                                                 int64_t n, int64_t m, z64 *__restrict__ Y,
-                                                int64_t ldy, int64_t sY) {
+                                                int64_t ldy, int64_t sY,
+                                                const double *__restrict__ nrm2, double cnt) {
   const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
   const int b = blockIdx.y;
   if (idx >= n * m) return;
+  const int e = solve_scale_exp(nrm2, cnt);
   const int64_t row = idx / m, col = idx % m;
   const c64 v = X[b * sX + row * ldx + col];
-  Y[b * sY + row * ldy + col] = make_double2(static_cast<double>(v.x), static_cast<double>(v.y));
+  Y[b * sY + row * ldy + col] =
+      make_double2(ldexp(static_cast<double>(v.x), e), ldexp(static_cast<double>(v.y), e));
 }
 
 template <typename T>
@@ -108,26 +127,31 @@ __global__ __launch_bounds__(256) void k_copy_block(const z64 *__restrict__ X, i
 
 __global__ __launch_bounds__(256) void k_z_to_c(const z64 *__restrict__ X, int64_t ldx, int64_t sX,
                                                 int64_t n, int64_t m, c64 *__restrict__ Y,
-                                                int64_t ldy, int64_t sY) {
+                                                int64_t ldy, int64_t sY,
+                                                const double *__restrict__ nrm2, double cnt) {
   const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
   const int b = blockIdx.y;
   if (idx >= n * m) return;
+  const int e = solve_scale_exp(nrm2, cnt);
   const int64_t row = idx / m, col = idx % m;
   const z64 v = X[b * sX + row * ldx + col];
-  Y[b * sY + row * ldy + col] = make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+  Y[b * sY + row * ldy + col] =
+      make_float2(static_cast<float>(ldexp(v.x, -e)), static_cast<float>(ldexp(v.y, -e)));
 }
 
 __global__ __launch_bounds__(256) void k_add_c_to_z(const c64 *__restrict__ X, int64_t ldx,
                                                     int64_t sX, int64_t n, int64_t m,
-                                                    z64 *__restrict__ Y, int64_t ldy, int64_t sY) {
+                                                    z64 *__restrict__ Y, int64_t ldy, int64_t sY,
+                                                    const double *__restrict__ nrm2, double cnt) {
   const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
   const int b = blockIdx.y;
   if (idx >= n * m) return;
+  const int e = solve_scale_exp(nrm2, cnt);
   const int64_t row = idx / m, col = idx % m;
   const c64 v = X[b * sX + row * ldx + col];
   z64 &y = Y[b * sY + row * ldy + col];
-  y.x += static_cast<double>(v.x);
-  y.y += static_cast<double>(v.y);
+  y.x += ldexp(static_cast<double>(v.x), e);
+  y.y += ldexp(static_cast<double>(v.y), e);
 }
 
 // Partial column sums over a chunk of 64 rows: one thread per column.
@@ -209,6 +233,41 @@ __global__ __launch_bounds__(256) void k_fro_part(const z64 *__restrict__ X, int
     __syncthreads();
   }
   if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Content fingerprint of n x n complex128 matrices: the wrapping 64-bit sum,
+// over every entry (i, j), of a bijective mix of the entry's bits keyed by its
+// position i n + j.  A change of any one entry always changes the sum (each
+// term is a bijection of the entry's bits), a change of several entries is
+// missed with probability about 2^-64, and the sum does not depend on the
+// order in which workgroups add their parts.  Matrix b is tab[b] when tab is
+// given, else a0 (b = 0) or a1 (b = 1); out[b] must be zero on entry.
+__device__ inline uint64_t fp_mix(uint64_t x) {
+  x ^= x >> 31;
+  x *= 0x7fb5d329728ea185ull;
+  x ^= x >> 27;
+  x *= 0x81dadef4bc2dd44dull;
+  x ^= x >> 33;
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_fingerprint(const GrpMat *__restrict__ tab, GrpMat a0,
+                                                     GrpMat a1, unsigned long long *__restrict__ out) {
+  const int b = blockIdx.y;
+  const GrpMat e = tab ? tab[b] : (b == 0 ? a0 : a1);
+  const z64 *X = static_cast<const z64 *>(e.base);
+  const int64_t n = e.n, total = n * n;
+  uint64_t h = 0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += 256ll * gridDim.x) {
+    const int64_t row = i / n, col = i - row * n;
+    const z64 v = X[row * e.ld + col];
+    const uint64_t key = static_cast<uint64_t>(i) * 0x9e3779b97f4a7c15ull;
+    h += fp_mix(static_cast<uint64_t>(__double_as_longlong(v.x)) ^ key);
+    h += fp_mix(static_cast<uint64_t>(__double_as_longlong(v.y)) ^ ~key);
+  }
+  // wave reduction, then one atomic per wave (integer sums are order-free)
+  for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out + b, static_cast<unsigned long long>(h));
 }
 
 // A += shift_rel * trace(A) on the diagonal (t x t, one workgroup).
@@ -658,10 +717,10 @@ void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64
 }
 
 void c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
-            int32_t batch, z64 *Y, int64_t ldy, int64_t sY) {
+            int32_t batch, z64 *Y, int64_t ldy, int64_t sY, const double *nrm2, double cnt) {
   const int64_t tot = n * m;
   hipLaunchKernelGGL(k_c_to_z, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256), 0,
-                     s, X, ldx, sX, n, m, Y, ldy, sY);
+                     s, X, ldx, sX, n, m, Y, ldy, sY, nrm2, cnt);
 }
 
 template <typename T>
@@ -689,17 +748,17 @@ void copy_block_z(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t m
 }
 
 void z_to_c(hipStream_t s, const z64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
-            int32_t batch, c64 *Y, int64_t ldy, int64_t sY) {
+            int32_t batch, c64 *Y, int64_t ldy, int64_t sY, const double *nrm2, double cnt) {
   const int64_t tot = n * m;
   hipLaunchKernelGGL(k_z_to_c, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256), 0,
-                     s, X, ldx, sX, n, m, Y, ldy, sY);
+                     s, X, ldx, sX, n, m, Y, ldy, sY, nrm2, cnt);
 }
 
 void add_c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
-                int32_t batch, z64 *Y, int64_t ldy, int64_t sY) {
+                int32_t batch, z64 *Y, int64_t ldy, int64_t sY, const double *nrm2, double cnt) {
   const int64_t tot = n * m;
   hipLaunchKernelGGL(k_add_c_to_z, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256),
-                     0, s, X, ldx, sX, n, m, Y, ldy, sY);
+                     0, s, X, ldx, sX, n, m, Y, ldy, sY, nrm2, cnt);
 }
 
 void ritz_norms(hipStream_t s, const z64 *AX, const z64 *BX, int64_t ld, int64_t n, int64_t t,
@@ -726,6 +785,17 @@ void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n
   hipLaunchKernelGGL(k_fro_part, dim3(blocks, batch), dim3(256), 0, s, X, ld, sX, n, m, part);
   hipLaunchKernelGGL(k_sum_rows, dim3(static_cast<unsigned>((batch + 255) / 256)), dim3(256), 0, s,
                      part, static_cast<int64_t>(blocks), static_cast<int64_t>(batch), out);
+}
+
+void fingerprint(hipStream_t s, const GrpMat *tab, int count, GrpMat a0, GrpMat a1,
+                 int64_t nmax, uint64_t *out) {
+  if (count <= 0) return;
+  fill_i32(s, reinterpret_cast<int32_t *>(out), 2ll * count, 0);
+  if (nmax <= 0) return;
+  const int64_t per = (nmax * nmax + 255) / 256;
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(per, count > 8 ? 64 : 1024));
+  hipLaunchKernelGGL(k_fingerprint, dim3(blocks, count), dim3(256), 0, s, tab, a0, a1,
+                     reinterpret_cast<unsigned long long *>(out));
 }
 
 void add_diag_shift(hipStream_t s, z64 *G, int64_t t, double shift_rel) {

@@ -141,12 +141,12 @@ void add_shift_grp(hipStream_t s, const GrpMat *g, int count, const double *shif
 void zero_lower_grp(hipStream_t s, const GrpMat *g, int count, int64_t tmax, bool all);
 // dst_b = src_b for src_b.n rows and dst_b.stride columns (max_elems = max rows*cols).
 void copy_grp(hipStream_t s, const GrpMat *src, const GrpMat *dst, int count, int64_t max_elems);
-// Sum of split-K partials (k_sum_splits_grp): max_elems >= rows x cols of every dst.
 // Cholesky of the diagonal 64 x 64 block at (J0, J0) of every matrix of a group
 // and the inverse of its factor (k_chol_inv per matrix): R into the block, R^{-1}
-// to Dinv + b * dstride + (J0 / 64) * 4096 (leading dimension 64).
+// (upper triangle only) to Dinv + b * dstride + (J0 / 64) * 4096 (leading dimension 64).
 void chol_inv_grp(hipStream_t s, const GrpMat *g, int count, int64_t J0, int32_t *flag,
                   int flag_stride, z64 *Dinv, int64_t dstride);
+// Sum of split-K partials (k_sum_splits_grp): max_elems >= rows x cols of every dst.
 void sum_splits_grp(hipStream_t s, const GrpMat *dst, const GrpMat *src, int count,
                     int64_t max_elems);
 // Diagonal blocks I of Dinv + b * dstride (64 x 64 each) into X_b.
@@ -180,14 +180,20 @@ void scatter_rows(hipStream_t s, const T *X, int64_t ldx, int64_t sX, const int3
 void weighted_sum(hipStream_t s, const z64 *Y, int64_t ldy, int64_t sY, const z64 *w,
                   int32_t N, int64_t n, int64_t m, z64 *U, int64_t ldu);
 
-// Copy / convert blocks.
+// Copy / convert blocks.  The conversions between complex128 and complex64
+// optionally scale by a power of two: z_to_c writes X 2^-e, c_to_z and
+// add_c_to_z read X 2^e, with e the binary exponent of sqrt(nrm2[0] / cnt)
+// (nrm2 on the device: the squared Frobenius norm of the right-hand side,
+// cnt its number of entries; nrm2 = nullptr: no scaling).
 void copy_block_z(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t m, z64 *Y,
                   int64_t ldy);
 void z_to_c(hipStream_t s, const z64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
-            int32_t batch, c64 *Y, int64_t ldy, int64_t sY);
+            int32_t batch, c64 *Y, int64_t ldy, int64_t sY, const double *nrm2 = nullptr,
+            double cnt = 1.0);
 // Y = X (complex64 -> complex128), per batch.
 void c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
-            int32_t batch, z64 *Y, int64_t ldy, int64_t sY);
+            int32_t batch, z64 *Y, int64_t ldy, int64_t sY, const double *nrm2 = nullptr,
+            double cnt = 1.0);
 // Refinement residual of all nodes in the n x (N m) layout:
 // T1[:, j m + c] <- R[:, c] - z_j T2[:, j m + c] + T1[:, j m + c]   (T1 = A Y, T2 = B Y)
 // for the used columns c < used (default m) of every node block.
@@ -196,7 +202,8 @@ void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64
                     int64_t used = -1);
 // Y += X (complex64 correction into FP64 solution), per batch.
 void add_c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
-                int32_t batch, z64 *Y, int64_t ldy, int64_t sY);
+                int32_t batch, z64 *Y, int64_t ldy, int64_t sY, const double *nrm2 = nullptr,
+                double cnt = 1.0);
 
 // Residual norms of Ritz pairs: for every column i of the n x t blocks AX, BX:
 // out[3i+0] = ||AX_i - lam_i BX_i||^2, out[3i+1] = ||AX_i||^2, out[3i+2] = ||BX_i||^2.
@@ -212,6 +219,13 @@ void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, d
 // part: workspace of max(64 * batch, 1024) doubles.
 void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
                   int32_t batch, double *part, double *out);
+
+// Content fingerprints of `count` n_b x n_b complex128 matrices (entry b of
+// the device table tab, or a0 / a1 by value when tab is null and count <= 2)
+// into out[b] (device, zeroed here first); nmax bounds every n_b.  Reading
+// every entry once, it lets a cache of factors check that a matrix is unchanged.
+void fingerprint(hipStream_t s, const GrpMat *tab, int count, GrpMat a0, GrpMat a1,
+                 int64_t nmax, uint64_t *out);
 
 // Blocked pieces: diagonal += shift_rel * trace; Cholesky of one jb x jb (<= 64)
 // diagonal block inside a matrix of leading dimension ld, R written over it

@@ -82,15 +82,19 @@ struct feast_plan {
   std::vector<cd> hz, hw;
   DevBuf dz, dw, dwc;  // nodes, weights, conjugated weights
   // cached factors
+  // The factors are reused for a pencil whose content fingerprints (A, B)
+  // equal those taken when they were computed: the same shifted matrices,
+  // wherever A and B now live.
   bool factored = false;
-  const void *fA = nullptr, *fB = nullptr;
-  int64_t flda = 0, fldb = 0;
+  uint64_t fpA = 0, fpB = 0;
+  DevBuf fp;  // device fingerprints of the current call's A and B
   DevBuf F, piv, perm, info, Linv, Uinv;
   DevBuf Linv2, Uinv2;
   DevBuf pucnt;  // per-node counters of the one-launch panel updates  // inverted 128 x 128 diagonal blocks (the solves' leaves)
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
   DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
+  DevBuf rn;  // mixed form: ||R||_F^2 at rn[0] (scale of the complex64 solves), partials from rn[8]
   DevBuf adj, adj_piv, adj_info, adj_inv;  // adjoint solves (allocated on first use)
   DevBuf cirr_w;                           // Block_CIRR moment weights (g x N)
   std::string err;
@@ -105,6 +109,15 @@ struct feast_plan {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // A U_1 on the side stream in the projection
   int prof_launches = 0;
   double prof_ms = 0.0, prof_flops = 0.0;
+  // opts.profile: events around the bandwidth-bound launches (class, algorithmic bytes)
+  struct KRec {
+    int cls;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> kev;
+  size_t kev_used = 0;
+  std::vector<KRec> krec;
 
   // n x m work blocks inside W
   enum { W_ORTH = 0, W_U2 = 1, W_X = 2, W_AX = 3, W_BX = 4, W_XPREV = 5, W_U1 = 6, W_AU1 = 7,
@@ -174,5 +187,29 @@ template <typename F> int guarded(feast_plan *p, F &&f) {
   }
 }
 
+
+// With opts.profile, launch() is bracketed by HIP events on the plan's stream
+// and recorded under class cls (enum feast_kclass) with its algorithmic HBM
+// bytes; otherwise it just runs.
+template <class F> void ktimed(feast_plan *p, int cls, double bytes, F &&launch) {
+  if (!p->o.profile || p->krec.size() >= 4096) {
+    launch();
+    return;
+  }
+  while (p->kev.size() < p->kev_used + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    p->kev.push_back(e);
+  }
+  hipEvent_t a = p->kev[p->kev_used], b = p->kev[p->kev_used + 1];
+  p->kev_used += 2;
+  HIPCHK(hipEventRecord(a, p->s));
+  launch();
+  HIPCHK(hipEventRecord(b, p->s));
+  p->krec.push_back({cls, bytes, a, b});
+}
+void kprof_reset(feast_plan *p);
+// Sum the recorded launches per class into info (the stream must be idle).
+void kprof_collect(feast_plan *p, feast_info *info);
 
 }  // namespace feast_drv

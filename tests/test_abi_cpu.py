@@ -250,3 +250,58 @@ def test_reduced_eig_triangular_and_diagonal_inputs():
     T = np.triu(np.ones((t, t))) + np.diag(np.arange(t))
     al, be, Y = fm.feast_reduced_eig(T + 0j, np.eye(t) + 0j)
     assert np.allclose(np.sort((al / be).real), np.sort(np.diag(T)))
+
+
+@pytest.mark.parametrize("sa,sb", [(1e30, 1e30), (1e-30, 1e-30), (1e30, 1e-30), (1e-30, 1e30)])
+@pytest.mark.parametrize("tri", [False, True])
+def test_reduced_eig_badly_scaled_pencils(sa, sb, tri):
+    # The host solver's complex arithmetic does not scale its divisions (it is
+    # built with limited-range complex arithmetic for speed): this pins that
+    # pencils scaled by 1e+-30 -- eigenvalues scaled by up to 1e+-60 -- keep
+    # full relative accuracy, in the standard-form (triangular B) and QZ paths.
+    rng = np.random.default_rng(31)
+    t = 48
+    A = (rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))) / np.sqrt(t)
+    if tri:
+        B = np.triu(0.05 * (rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))))
+        B[np.diag_indices(t)] = 1.0 + 0.2 * rng.normal(size=t)
+    else:
+        B = rng.normal(size=(t, t)) + 1j * rng.normal(size=(t, t))
+    ref = sla.eigvals(A, B)
+    al, be, Y = fm.feast_reduced_eig(sa * A, sb * B)
+    lam = al / be * (sb / sa)
+    assert np.all(np.isfinite(lam))
+    assert _match(lam, ref) < 1e-10 * max(1.0, np.abs(ref).max())
+    for i in range(t):
+        assert abs(np.linalg.norm(Y[:, i]) - 1) < 1e-12
+        # beta sa A y = alpha sb B y  <=>  (beta / sb) A y = (alpha / sa) B y
+        r = np.linalg.norm(be[i] / sb * (A @ Y[:, i]) - al[i] / sa * (B @ Y[:, i]))
+        assert r <= 1e-12 * (abs(be[i] / sb) * np.linalg.norm(A) + abs(al[i] / sa) * np.linalg.norm(B))
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # The ctypes mirrors of the header's structs must have the C layout:
+    # compile a probe against include/feast.h and compare sizes and offsets.
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_1404_1768_amd import binding as b
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "probe.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "feast.h"\n'
+        'int main(void) {\n'
+        '  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(feast_contour), sizeof(feast_opts),\n'
+        '         sizeof(feast_info), sizeof(feast_search_info), sizeof(feast_cirr_info),\n'
+        '         sizeof(feast_batch_info), offsetof(feast_info, hbm));\n'
+        '  return 0;\n}\n')
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [ctypes.sizeof(t) for t in (b.Contour, b.Opts, b.Info, b.SearchInfo, b.CirrInfo,
+                                       b.BatchInfo)] + [b.Info.hbm.offset]
+    assert got == want
