@@ -58,7 +58,9 @@ enum feast_status {
   FEAST_EINVAL = -1,           /* bad size, leading dimension, null pointer, contour or option */
   FEAST_EDEVICE = -2,          /* HIP runtime error */
   FEAST_ENOMEM = -3,           /* device or host allocation failed */
-  FEAST_ENUMERIC = -4          /* host reduced eigensolver or QR broke down */
+  FEAST_ENUMERIC = -4,         /* host reduced eigensolver or QR broke down */
+  FEAST_ESCRATCH = -5          /* the request needs more than feast_zgetrs_batched_noalloc's
+                                  fixed scratch memory */
 };
 
 enum feast_rule { FEAST_TRAPEZOID = 0, FEAST_GAUSS_LEGENDRE = 1 };
@@ -445,6 +447,25 @@ int feast_zgetrf_batched(int64_t n, int32_t batch, feast_z *dM, int64_t ldm, int
 int feast_zgetrs_batched(int64_t n, int64_t nrhs, int32_t batch, const feast_z *dLU,
                          int64_t ldm, int64_t strideM, const int32_t *dPiv, feast_z *dX,
                          int64_t ldx, int64_t strideX, int32_t trans, void *stream);
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the solves
+ * of feast_zgetrs_batched (same arguments, same kernels, same results) with
+ * every temporary (inverted 64 x 64 diagonal blocks of L and U, the row
+ * permutation, a staging block: 2 batch ceil(n/64) 64^2 complex128 +
+ * batch n int32 + batch n nrhs complex128 entries, each piece rounded up to
+ * 256 bytes) in a fixed 64 MiB device array that the library holds on every
+ * GPU it runs on until the process ends.  No device memory is allocated or
+ * freed, and the call does not wait: the work is enqueued on `stream` and the
+ * call returns (synchronise the stream, or capture it).  Requests needing
+ * more than 64 MiB return FEAST_ESCRATCH before any device work.  Every call
+ * on one GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other threads) race; calls ordered on one stream do not.  Nothing
+ * in the array needs clearing between calls (every piece is written before
+ * it is read). */
+int feast_zgetrs_batched_noalloc(int64_t n, int64_t nrhs, int32_t batch, const feast_z *dLU,
+                                 int64_t ldm, int64_t strideM, const int32_t *dPiv, feast_z *dX,
+                                 int64_t ldx, int64_t strideX, int32_t trans, void *stream);
 
 /* C_b = alpha op(A_b) B_b + beta C_b with op(A) = A (transA = 0, A is M x K)
  * or op(A) = A^* (transA = 2, A stored K x M); B is K x N, C is M x N.  The

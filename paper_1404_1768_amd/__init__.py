@@ -6,8 +6,9 @@ projection of Section 3 and Algorithm 5; ``binding`` marshals torch tensors
 into it.  Build it with ``python -m paper_1404_1768_amd.build``.
 """
 from .binding import (FEAST_OK, FEAST_SINGULAR, FEAST_REFINE_STAGNATED, FEAST_EINVAL,  # noqa: F401
-                      FEAST_EDEVICE, FEAST_ENOMEM, FEAST_ENUMERIC, TRAPEZOID, GAUSS_LEGENDRE,
+                      FEAST_EDEVICE, FEAST_ENOMEM, FEAST_ENUMERIC, FEAST_ESCRATCH, TRAPEZOID,
+                      GAUSS_LEGENDRE,
                       FP64, MIXED, FeastError, Plan, SolveResult, feast_filter, feast_project,
                       feast_solve, feast_nodes, feast_reduced_eig, feast_stop_rule, load,
-                      zgemm_batched, zgetrf_batched, zgetrs_batched, LIB_PATH, feast_eig,
+                      zgemm_batched, zgetrf_batched, zgetrs_batched, zgetrs_batched_noalloc, LIB_PATH, feast_eig,
                       Batch, BatchResult, enclosing_circle, region_inside, solve_region)

@@ -25,6 +25,7 @@ FEAST_EINVAL = -1
 FEAST_EDEVICE = -2
 FEAST_ENOMEM = -3
 FEAST_ENUMERIC = -4
+FEAST_ESCRATCH = -5
 
 TRAPEZOID = 0
 GAUSS_LEGENDRE = 1
@@ -40,7 +41,7 @@ EXPORTED = [
     "feast_batch_create", "feast_batch_destroy", "feast_batch_invalidate",
     "feast_batch_last_error", "feast_batch_filter", "feast_batch_solve",
     "feast_search", "feast_plan_set_m", "feast_solve_from", "feast_enclosing_circle",
-    "feast_region_select", "feast_cirr",
+    "feast_region_select", "feast_cirr", "feast_zgetrs_batched_noalloc",
 ]
 
 
@@ -139,6 +140,7 @@ def load(path: str = LIB_PATH):
     lib.feast_stop_rule.argtypes = [i32, i32, dbl, i32, dbl, dbl, i32]
     lib.feast_zgetrf_batched.argtypes = [i64, i32, P, i64, i64, P, P, i32, P]
     lib.feast_zgetrs_batched.argtypes = [i64, i64, i32, P, i64, i64, P, P, i64, i64, i32, P]
+    lib.feast_zgetrs_batched_noalloc.argtypes = list(lib.feast_zgetrs_batched.argtypes)
     lib.feast_zgemm_batched.argtypes = [i32, i64, i64, i64, FeastZ, P, i64, i64, P, i64, i64,
                                         FeastZ, P, i64, i64, i32, P]
     lib.feast_left_eigvecs.argtypes = [P, P, i64, P, i64, P, i64, i64, i32, P, i64]
@@ -611,15 +613,24 @@ def zgetrf_batched(M, nb: int = 0, stream=None):
 
 
 def zgetrs_batched(LU, piv, X, trans: int = 0, stream=None):
+    return _zgetrs("feast_zgetrs_batched", LU, piv, X, trans, stream)
+
+
+def zgetrs_batched_noalloc(LU, piv, X, trans: int = 0, stream=None):
+    """As zgetrs_batched, with the library's fixed device scratch instead of
+    allocations; asynchronous on the stream."""
+    return _zgetrs("feast_zgetrs_batched_noalloc", LU, piv, X, trans, stream)
+
+
+def _zgetrs(name, LU, piv, X, trans, stream):
     lib = load()
     batch, n = LU.shape[0], LU.shape[1]
     nrhs = X.shape[2]
-    rc = lib.feast_zgetrs_batched(n, nrhs, batch, C.c_void_p(LU.data_ptr()), LU.stride(1),
-                                  LU.stride(0), C.c_void_p(piv.data_ptr()),
-                                  C.c_void_p(X.data_ptr()), X.stride(1), X.stride(0), int(trans),
-                                  _stream(stream))
+    rc = getattr(lib, name)(n, nrhs, batch, C.c_void_p(LU.data_ptr()), LU.stride(1),
+                            LU.stride(0), C.c_void_p(piv.data_ptr()), C.c_void_p(X.data_ptr()),
+                            X.stride(1), X.stride(0), int(trans), _stream(stream))
     if rc != FEAST_OK:
-        raise FeastError(rc, "feast_zgetrs_batched")
+        raise FeastError(rc, name)
     return X
 
 

@@ -20,6 +20,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1492,42 +1493,127 @@ int feast_zgetrf_batched(int64_t n, int32_t batch, feast_z *dM, int64_t ldm, int
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of the multi-right-hand-side solves with given factors: inverted
+// 64 x 64 diagonal blocks of L and U, the row permutation and a staging block.
+struct GetrsScratch {
+  z64 *Li, *Ui, *T;
+  int32_t *perm;
+};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Bytes of GetrsScratch for (n, nrhs, batch), each piece 256-byte aligned.
+size_t getrs_scratch_bytes(int64_t n, int64_t nrhs, int32_t batch) {
+  const int64_t ist = ((n + 63) / 64) * 64 * 64;
+  return 2 * align256(sizeof(z64) * batch * ist) + align256(sizeof(int32_t) * batch * n) +
+         align256(sizeof(z64) * batch * n * nrhs);
+}
+
+GetrsScratch carve_getrs(void *base, int64_t n, int64_t nrhs, int32_t batch) {
+  const int64_t ist = ((n + 63) / 64) * 64 * 64;
+  char *q = static_cast<char *>(base);
+  GetrsScratch w;
+  w.Li = reinterpret_cast<z64 *>(q);
+  q += align256(sizeof(z64) * batch * ist);
+  w.Ui = reinterpret_cast<z64 *>(q);
+  q += align256(sizeof(z64) * batch * ist);
+  w.perm = reinterpret_cast<int32_t *>(q);
+  q += align256(sizeof(int32_t) * batch * n);
+  w.T = reinterpret_cast<z64 *>(q);
+  return w;
+}
+
+// The solves of feast_zgetrs_batched, enqueued on s with the scratch w.
+void zgetrs_enqueue(hipStream_t s, int64_t n, int64_t nrhs, int32_t batch, const z64 *F, int64_t ldm,
+                    int64_t strideM, const int32_t *dPiv, z64 *Xz, int64_t ldx, int64_t strideX,
+                    int32_t trans, const GetrsScratch &w) {
+  const int64_t nblk = (n + 63) / 64, ist = nblk * 64 * 64;
+  feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, 64, 0, nblk, true, w.Li, ist);
+  feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, 64, 0, nblk, false, w.Ui, ist);
+  feast::perm_from_ipiv(s, dPiv, w.perm, n, batch);
+  if (trans == 0) {
+    feast::gather_rows<z64>(s, Xz, ldx, strideX, w.perm, n, nrhs, batch, w.T, nrhs, n * nrhs);
+    trsolve<z64>(s, F, ldm, strideM, batch, n, w.Li, w.Ui, ist, w.T, nrhs, nrhs, n * nrhs, 0);
+    for (int32_t i = 0; i < batch; ++i)
+      feast::copy_block_z(s, w.T + i * n * nrhs, nrhs, n, nrhs, Xz + i * strideX, ldx);
+  } else {
+    for (int32_t i = 0; i < batch; ++i)
+      feast::copy_block_z(s, Xz + i * strideX, ldx, n, nrhs, w.T + i * n * nrhs, nrhs);
+    trsolve<z64>(s, F, ldm, strideM, batch, n, w.Li, w.Ui, ist, w.T, nrhs, nrhs, n * nrhs, 2);
+    feast::scatter_rows<z64>(s, w.T, nrhs, n * nrhs, w.perm, n, nrhs, batch, Xz, ldx, strideX);
+  }
+}
+
+bool bad_getrs_args(int64_t n, int64_t nrhs, int32_t batch, const feast_z *dLU, int64_t ldm,
+                    const int32_t *dPiv, const feast_z *dX, int64_t ldx, int32_t trans) {
+  return n < 1 || n > 16384 || nrhs < 0 || batch < 1 || !dLU || !dPiv || !dX || ldm < n ||
+         ldx < nrhs || (trans != 0 && trans != 2);
+}
+
+// The no-allocation variant's scratch: one file-scope device array, present on
+// every GPU the library runs on for the life of the process.  Host code never
+// uses its name as an address (on the host it is only a stand-in): the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken once
+// per device with that device current and kept in scratch_dev.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices] = {};
+
+int scratch_address(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FEAST_EDEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FEAST_EDEVICE;
+    scratch_dev[dev] = ptr;
+  }
+  *out = scratch_dev[dev];
+  return FEAST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int feast_zgetrs_batched(int64_t n, int64_t nrhs, int32_t batch, const feast_z *dLU, int64_t ldm,
                          int64_t strideM, const int32_t *dPiv, feast_z *dX, int64_t ldx,
                          int64_t strideX, int32_t trans, void *stream) {
-  if (n < 1 || n > 16384 || nrhs < 0 || batch < 1 || !dLU || !dPiv || !dX || ldm < n ||
-      ldx < nrhs || (trans != 0 && trans != 2))
-    return FEAST_EINVAL;
+  if (bad_getrs_args(n, nrhs, batch, dLU, ldm, dPiv, dX, ldx, trans)) return FEAST_EINVAL;
   if (nrhs == 0) return FEAST_OK;
   return guarded(nullptr, [&]() {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t nblk = (n + 63) / 64, ist = nblk * 64 * 64;
-    DevBuf Li, Ui, perm, T;
-    Li.alloc(sizeof(z64) * batch * ist);
-    Ui.alloc(sizeof(z64) * batch * ist);
-    perm.alloc(sizeof(int32_t) * batch * n);
-    T.alloc(sizeof(z64) * batch * n * nrhs);
-    const z64 *F = reinterpret_cast<const z64 *>(dLU);
-    z64 *Xz = reinterpret_cast<z64 *>(dX);
-    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, 64, 0, nblk, true, Li.as<z64>(), ist);
-    feast::diag_block_inverse<z64>(s, F, ldm, strideM, batch, n, 64, 0, nblk, false, Ui.as<z64>(), ist);
-    feast::perm_from_ipiv(s, dPiv, perm.as<int32_t>(), n, batch);
-    if (trans == 0) {
-      feast::gather_rows<z64>(s, Xz, ldx, strideX, perm.as<int32_t>(), n, nrhs, batch, T.as<z64>(),
-                              nrhs, n * nrhs);
-      trsolve<z64>(s, F, ldm, strideM, batch, n, Li.as<z64>(), Ui.as<z64>(), ist, T.as<z64>(),
-                   nrhs, nrhs, n * nrhs, 0);
-      for (int32_t i = 0; i < batch; ++i)
-        feast::copy_block_z(s, T.as<z64>() + i * n * nrhs, nrhs, n, nrhs, Xz + i * strideX, ldx);
-    } else {
-      for (int32_t i = 0; i < batch; ++i)
-        feast::copy_block_z(s, Xz + i * strideX, ldx, n, nrhs, T.as<z64>() + i * n * nrhs, nrhs);
-      trsolve<z64>(s, F, ldm, strideM, batch, n, Li.as<z64>(), Ui.as<z64>(), ist, T.as<z64>(),
-                   nrhs, nrhs, n * nrhs, 2);
-      feast::scatter_rows<z64>(s, T.as<z64>(), nrhs, n * nrhs, perm.as<int32_t>(), n, nrhs, batch,
-                               Xz, ldx, strideX);
-    }
+    DevBuf ws;
+    ws.alloc(getrs_scratch_bytes(n, nrhs, batch));
+    zgetrs_enqueue(s, n, nrhs, batch, reinterpret_cast<const z64 *>(dLU), ldm, strideM, dPiv,
+                   reinterpret_cast<z64 *>(dX), ldx, strideX, trans,
+                   carve_getrs(ws.p, n, nrhs, batch));
     HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    return FEAST_OK;
+  });
+}
+
+int feast_zgetrs_batched_noalloc(int64_t n, int64_t nrhs, int32_t batch, const feast_z *dLU,
+                                 int64_t ldm, int64_t strideM, const int32_t *dPiv, feast_z *dX,
+                                 int64_t ldx, int64_t strideX, int32_t trans, void *stream) {
+  if (bad_getrs_args(n, nrhs, batch, dLU, ldm, dPiv, dX, ldx, trans)) return FEAST_EINVAL;
+  if (nrhs == 0) return FEAST_OK;
+  if (getrs_scratch_bytes(n, nrhs, batch) > kNoAllocScratchBytes) return FEAST_ESCRATCH;
+  void *base = nullptr;
+  const int rc = scratch_address(&base);
+  if (rc != FEAST_OK) return rc;
+  return guarded(nullptr, [&]() {
+    zgetrs_enqueue(static_cast<hipStream_t>(stream), n, nrhs, batch,
+                   reinterpret_cast<const z64 *>(dLU), ldm, strideM, dPiv,
+                   reinterpret_cast<z64 *>(dX), ldx, strideX, trans,
+                   carve_getrs(base, n, nrhs, batch));
     HIPCHK(hipGetLastError());
     return FEAST_OK;
   });

@@ -305,3 +305,20 @@ def test_binding_structs_match_the_header(tmp_path):
     want = [ctypes.sizeof(t) for t in (b.Contour, b.Opts, b.Info, b.SearchInfo, b.CirrInfo,
                                        b.BatchInfo)] + [b.Info.hbm.offset]
     assert got == want
+
+
+def test_noalloc_solve_checks_sizes_before_device_work():
+    # Argument and scratch-size checks of feast_zgetrs_batched_noalloc come
+    # before any device call: placeholder pointers are never dereferenced.
+    lib = fm.load()
+    import ctypes
+    fake = ctypes.c_void_p(0x1000)
+    big = lib.feast_zgetrs_batched_noalloc(16384, 1000, 1, fake, 16384, 16384 * 16384, fake, fake,
+                                           1000, 16384 * 1000, 0, None)
+    assert big == fm.FEAST_ESCRATCH
+    assert lib.feast_zgetrs_batched_noalloc(0, 4, 1, fake, 1, 1, fake, fake, 4, 4, 0, None) == \
+        fm.FEAST_EINVAL
+    assert lib.feast_zgetrs_batched_noalloc(8, 4, 1, fake, 8, 64, fake, fake, 4, 32, 1, None) == \
+        fm.FEAST_EINVAL
+    assert lib.feast_zgetrs_batched_noalloc(8, 4, 1, None, 8, 64, fake, fake, 4, 32, 0, None) == \
+        fm.FEAST_EINVAL
