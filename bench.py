@@ -451,7 +451,6 @@ def main():
         pl = pg.workload(3)
         log("[bench] generated workload n=%d m=%d in %.1f s" % (pl.n, pl.m, time.perf_counter() - t0))
         lA, lB, lV = (torch.from_numpy(x).to(dev) for x in (pl.A, pl.B, pl.V))
-        pl.A = pl.B = pl.P = pl.Q = None     # (host copies no longer needed)
         r = time_form("mixed", pl, lA, lB, lV, min(args.steps, 2), 1)
         large = {"workload": "pencil n=8000 N=32 m=256 s=120 (394 eigenvalues in 1.05..1.2)",
                  "mixed": r}
