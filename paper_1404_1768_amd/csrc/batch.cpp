@@ -123,6 +123,7 @@ struct feast_batch {
   int64_t nmax = 0, nblk = 0;
   // grouped factors
   DevBuf F, piv, perm, info, Linv, Uinv, grp;
+  int64_t lu_nb = 128;  // panel width of the grouped LU (64 or 128)
   std::vector<int64_t> foff;  // element offset of pencil p's first matrix in F
   // node solutions (np_p x N m_p each) and the mixed-form buffers
   DevBuf Y, Yc, T1, T2;
@@ -206,11 +207,13 @@ feast_plan *member_plan(int64_t n, int64_t m, const feast_contour &c, const feas
 
 // Grouped product over a list of problems (skipped when empty).
 template <typename T>
-void ggemm(feast_batch *b, Tables &tab, int ta, bool sub, std::vector<GemmArgs<T>> &e) {
+void ggemm(feast_batch *b, Tables &tab, int ta, bool sub, std::vector<GemmArgs<T>> &e,
+           int variant = feast::GROUP_PLAIN) {
   if (e.empty()) return;
   const int64_t tiles = feast::gemm_group_tiles<T>(e.data(), static_cast<int>(e.size()));
   const GemmArgs<T> *d = tab.put(e);
-  if (!tab.record) feast::gemm_group<T>(b->gs, ta, sub, d, static_cast<int>(e.size()), tiles);
+  if (!tab.record)
+    feast::gemm_group<T>(b->gs, ta, sub, d, static_cast<int>(e.size()), tiles, variant);
 }
 
 // C = X^* Y with a small output (m x m: Gram matrices, reduced pencils) and a
@@ -281,8 +284,18 @@ void panel_grp(feast_batch *b, T *F, int nmat, int64_t c0, int w, int64_t pk0, i
   panel_grp<T>(b, F, nmat, c0 + w1, w2, pk0, pkb);
 }
 
-// Blocked right-looking LU of every shifted matrix of every pencil in lockstep
-// (64-wide panels).  record: only collect the GEMM tables.
+// Blocked right-looking LU of every shifted matrix of every pencil in lockstep,
+// with panels of b->lu_nb = 64 or 128 columns (a 128-column step of a pencil
+// padded to an odd multiple of 64 ends with a 64-column panel).  A step:
+//   the panel's first 64 columns (register leaves joined by fused rank updates;
+//   the leaves swap rows over the whole panel) and the inverse of L's diagonal
+//   block; for 128: X = L00^{-1} A(k0:k0+64, k0+64:k0+128) and the update of the
+//   panel's second half by L(k0+64:, k0:k0+64) X, then its own leaves;
+//   the panel's row swaps outside the panel;
+//   U12 = L11^{-1} A12 (for 128: two in-place products with the inverted 64 x 64
+//   blocks and the L10 update between them);
+//   the trailing update A22 -= L21 U12 (K = lu_nb) as one grouped launch.
+// record: only collect the GEMM tables.
 template <typename T>
 void lu_grouped(feast_batch *b, bool record) {
   Tables &tab = b->lu_tab;
@@ -293,30 +306,66 @@ void lu_grouped(feast_batch *b, bool record) {
   const int64_t is = b->istride();
   const GrpMat *g = b->grp.as<GrpMat>();
   int32_t *piv = b->piv.as<int32_t>();
-  if (!record) feast::fill_i32(b->gs, b->info.as<int32_t>(), static_cast<int64_t>(b->P) * N, 0);
-  for (int64_t k0 = 0; k0 < b->nmax; k0 += kPanel) {
-    const int64_t k1 = k0 + kPanel;
+  const int64_t NB = b->lu_nb;
+  if (!record) {
+    feast::fill_i32(b->gs, b->info.as<int32_t>(), static_cast<int64_t>(b->P) * N, 0);
+  }
+  for (int64_t k0 = 0; k0 < b->nmax; k0 += NB) {
+    const int64_t k1 = k0 + NB, j0 = k0 / 64;
     const int act = b->active(k0), nmat = act * N;
     if (!record) {
-      panel_grp<T>(b, F, nmat, k0, static_cast<int>(kPanel), k0, static_cast<int>(kPanel));
-      feast::laswp_outside<T>(b->gs, F, 0, 0, nmat, b->nmax, k0, static_cast<int>(kPanel), k0, k1,
-                              piv, g, N);
-      feast::diag_block_inverse<T>(b->gs, F, 0, 0, nmat, b->nmax, 64, k0 / 64, k0 / 64 + 1, true,
-                                   Linv, is, g, N);
+      panel_grp<T>(b, F, nmat, k0, static_cast<int>(kPanel), k0, static_cast<int>(NB));
+      feast::diag_block_inverse<T>(b->gs, F, 0, 0, nmat, b->nmax, 64, j0, j0 + 1, true, Linv, is,
+                                   g, N);
     }
+    const int acth = NB > kPanel ? b->active(k0 + kPanel) : 0;
+    if (acth > 0) {
+      std::vector<GemmArgs<T>> x, upx;
+      for (int p = 0; p < acth; ++p) {
+        const int64_t ld = b->np[p], st = ld * ld;
+        T *M = F + b->foff[p];
+        T *X = M + k0 * ld + k0 + kPanel;
+        x.push_back(gargs<T>(kPanel, kPanel, kPanel, Linv + p * N * is + j0 * 4096, 64, is, X, ld,
+                             st, X, ld, st, 1.0, 0.0, N));
+        upx.push_back(gargs<T>(ld - k0 - kPanel, kPanel, kPanel, M + (k0 + kPanel) * ld + k0, ld, st,
+                               X, ld, st, M + (k0 + kPanel) * ld + k0 + kPanel, ld, st, -1.0, 1.0,
+                               N));
+      }
+      ggemm<T>(b, tab, 0, false, x);
+      ggemm<T>(b, tab, 0, true, upx);
+      if (!record) {
+        panel_grp<T>(b, F, acth * N, k0 + kPanel, static_cast<int>(kPanel), k0,
+                     static_cast<int>(NB));
+        feast::diag_block_inverse<T>(b->gs, F, 0, 0, acth * N, b->nmax, 64, j0 + 1, j0 + 2, true,
+                                     Linv, is, g, N);
+      }
+    }
+    if (!record)
+      feast::laswp_outside<T>(b->gs, F, 0, 0, nmat, b->nmax, k0, static_cast<int>(NB), k0, k1, piv,
+                              g, N);
     const int act2 = b->active(k1);
-    std::vector<GemmArgs<T>> u12, upd;
+    std::vector<GemmArgs<T>> u0, u10, u1, upd;
     for (int p = 0; p < act2; ++p) {
       const int64_t ld = b->np[p], st = ld * ld, rest = ld - k1;
       T *M = F + b->foff[p];
-      // U12 = L11^{-1} A12 in place (one 64-row tile row), then A22 -= L21 U12
-      u12.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + (k0 / 64) * 4096, 64, is,
-                             M + k0 * ld + k1, ld, st, M + k0 * ld + k1, ld, st, 1.0, 0.0, N));
-      upd.push_back(gargs<T>(rest, rest, kPanel, M + k1 * ld + k0, ld, st, M + k0 * ld + k1, ld, st,
+      T *top = M + k0 * ld + k1;
+      // U12 = L11^{-1} A12 in place (64-row tile rows), then A22 -= L21 U12
+      u0.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + j0 * 4096, 64, is, top, ld, st,
+                            top, ld, st, 1.0, 0.0, N));
+      if (NB > kPanel) {
+        T *bot = M + (k0 + kPanel) * ld + k1;
+        u10.push_back(gargs<T>(kPanel, rest, kPanel, M + (k0 + kPanel) * ld + k0, ld, st, top, ld,
+                               st, bot, ld, st, -1.0, 1.0, N));
+        u1.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + (j0 + 1) * 4096, 64, is, bot,
+                              ld, st, bot, ld, st, 1.0, 0.0, N));
+      }
+      upd.push_back(gargs<T>(rest, rest, NB, M + k1 * ld + k0, ld, st, top, ld, st,
                              M + k1 * ld + k1, ld, st, -1.0, 1.0, N));
     }
-    ggemm<T>(b, tab, 0, false, u12);
-    ggemm<T>(b, tab, 0, true, upd);
+    ggemm<T>(b, tab, 0, false, u0);
+    ggemm<T>(b, tab, 0, true, u10);
+    ggemm<T>(b, tab, 0, false, u1);
+    ggemm<T>(b, tab, 0, true, upd, feast::GROUP_UPDATE_M3);
   }
   if (!record) {
     const int nmat = b->P * N;

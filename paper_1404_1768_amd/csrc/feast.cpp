@@ -42,8 +42,7 @@ namespace {
 // ---------------------------------------------------------------------------
 template <typename T>
 void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-               int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info,
-               int32_t *cnt = nullptr) {
+               int64_t c0, int w, int64_t pk0, int pkb, int32_t *ipiv, int32_t *info) {
   const int ib = feast::leaf_max_width<T>(n - c0);
   if (w <= ib) {
     if (!feast::leaf_lu<T>(s, M, ld, stride, batch, n, c0, w, pk0, pkb, ipiv, info))
@@ -51,10 +50,10 @@ void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, i
     return;
   }
   const int w1 = w / 2, w2 = w - w1;
-  panel_rec<T>(s, M, ld, stride, batch, n, c0, w1, pk0, pkb, ipiv, info, cnt);
+  panel_rec<T>(s, M, ld, stride, batch, n, c0, w1, pk0, pkb, ipiv, info);
   if (w2 <= feast::panel_update_max_width()) {
-    feast::panel_update<T>(s, M, ld, stride, batch, n, c0, w1, w2, nullptr, 1, cnt);
-    panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info, cnt);
+    feast::panel_update<T>(s, M, ld, stride, batch, n, c0, w1, w2);
+    panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info);
     return;
   }
   feast::trsm_small<T>(s, M, ld, stride, batch, c0, w1, w2);
@@ -62,7 +61,7 @@ void panel_rec(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, i
     gemm_t<T>(s, 0, n - c0 - w1, w2, w1, zc(-1.0), M + (c0 + w1) * ld + c0, ld, stride,
               M + c0 * ld + c0 + w1, ld, stride, zc(1.0), M + (c0 + w1) * ld + c0 + w1, ld, stride,
               batch);
-  panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info, cnt);
+  panel_rec<T>(s, M, ld, stride, batch, n, c0 + w1, w2, pk0, pkb, ipiv, info);
 }
 
 struct LuProf {
@@ -132,7 +131,6 @@ struct LuStreams {
   hipStream_t main = nullptr, side = nullptr;
   hipEvent_t cols_ready = nullptr, panel_done = nullptr;
   int update_cfg = feast::GEMM_UPDATE;  // tile of the trailing update
-  int32_t *cnt = nullptr;  // per-matrix counters of the one-launch panel updates (or null)
 };
 
 template <typename T>
@@ -154,9 +152,8 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
     }
   };
   // first panel
-  if (st.cnt) feast::fill_i32(s, st.cnt, batch, 0);
   panel_rec<T>(s, M, ld, stride, batch, n, 0, static_cast<int>(std::min<int64_t>(nb, n)), 0,
-               static_cast<int>(std::min<int64_t>(nb, n)), ipiv, info, st.cnt);
+               static_cast<int>(std::min<int64_t>(nb, n)), ipiv, info);
   for (int64_t k0 = 0; k0 < n; k0 += nb) {
     const int kb = static_cast<int>(std::min<int64_t>(nb, n - k0));
     const int64_t k1 = k0 + kb, rest = n - k1;
@@ -174,7 +171,7 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
       timed_gemm(rest, kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
       HIPCHK(hipEventRecord(st.cols_ready, s));
       HIPCHK(hipStreamWaitEvent(st.side, st.cols_ready, 0));
-      panel_rec<T>(st.side, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info, st.cnt);
+      panel_rec<T>(st.side, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
       HIPCHK(hipEventRecord(st.panel_done, st.side));
       if (rest > kb1)
         timed_gemm(rest, rest - kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1 + kb1,
@@ -182,7 +179,7 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
       HIPCHK(hipStreamWaitEvent(s, st.panel_done, 0));
     } else {
       timed_gemm(rest, rest, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
-      panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info, st.cnt);
+      panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
     }
   }
   const int64_t nblk = (n + kIB - 1) / kIB;
@@ -251,10 +248,8 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     prof.ev = &p->ev;
   }
   hipStream_t sl = s;
-  p->pucnt.alloc(sizeof(int32_t) * N);
   const LuStreams lst{sl, p->o.lookahead ? p->side : nullptr, p->ev_cols, p->ev_panel,
-                      p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE,
-                      p->pucnt.as<int32_t>()};
+                      p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE};
   if (p->mixed()) {
     ktimed(p, FEAST_K_SHIFT, (32.0 + 8.0 * N) * n * n, [&]() {
       feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
@@ -319,14 +314,20 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
 // (Section 4.3: the factors of the same shifted matrices): one read of A and B
 // for their fingerprints and a wait for the two words.
 int ensure_factored(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
+  if (p->factored && p->checked) return FEAST_OK;
   if (p->factored) {
     launch_fingerprints(p, A, lda, B, ldb);
     uint64_t hfp[2];
     HIPCHK(hipMemcpyAsync(hfp, p->fp.p, sizeof(hfp), hipMemcpyDeviceToHost, p->s));
     HIPCHK(hipStreamSynchronize(p->s));
-    if (hfp[0] == p->fpA && hfp[1] == p->fpB) return FEAST_OK;
+    if (hfp[0] == p->fpA && hfp[1] == p->fpB) {
+      p->checked = true;
+      return FEAST_OK;
+    }
   }
-  return factor(p, A, lda, B, ldb);
+  const int st = factor(p, A, lda, B, ldb);
+  p->checked = p->factored;
+  return st;
 }
 
 // FP64 form: Y_j = (z_j B - A)^{-1} R for all nodes (Y: n x N m, node j at columns j m).
@@ -758,7 +759,7 @@ int feast_plan_destroy(feast_plan *p) {
   if (p->ev_panel) (void)hipEventDestroy(p->ev_panel);
   for (hipEvent_t e : {p->ev_fork, p->ev_join})
     if (e) (void)hipEventDestroy(e);
-  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->pucnt, &p->cirr_w, &p->R,
+  for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->cirr_w, &p->R,
                     &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->part, &p->nrm,
                     &p->flag, &p->small, &p->fp, &p->rn})
     b->release();
@@ -780,6 +781,7 @@ int feast_filter(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
   if (!dA || !dB || !dV || !dU || lda < p->n || ldb < p->n || ldv < p->m || ldu < p->m)
     return fail(p, FEAST_EINVAL, "feast_filter: null pointer or leading dimension too small");
   p->err.clear();
+  CheckScope check_scope(p);
   kprof_reset(p);
   return guarded(p, [&]() {
     const z64 *A = reinterpret_cast<const z64 *>(dA), *B = reinterpret_cast<const z64 *>(dB);
@@ -821,6 +823,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       ldb < p->n || ldv < p->m || ldx < p->m)
     return fail(p, FEAST_EINVAL, "feast_solve: null pointer or leading dimension too small");
   p->err.clear();
+  CheckScope check_scope(p);
   return guarded(p, [&]() -> int {
     const int64_t n = p->n, m = p->m;
     hipStream_t s = p->s;       // filters and projections
@@ -1077,6 +1080,7 @@ int feast_cirr(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,
     return fail(p, FEAST_EINVAL,
                 "feast_cirr: null pointer, leading dimension too small, or h g > m");
   p->err.clear();
+  CheckScope check_scope(p);
   return guarded(p, [&]() -> int {
     Timer total;
     const int64_t n = p->n, m = p->m, t = static_cast<int64_t>(h) * g;
@@ -1241,6 +1245,7 @@ int feast_search(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *d
   if (p0 < 1 || p0 > p->m || p0 > ycols || !(alpha > 1.0) || !(tau > 0.0 && tau < 1.0))
     return fail(p, FEAST_EINVAL, "feast_search: need 1 <= p <= min(m, pool columns), alpha > 1, 0 < tau < 1");
   p->err.clear();
+  CheckScope check_scope(p);
   return guarded(p, [&]() -> int {
     Timer total;
     const int64_t n = p->n, m = p->m, cap = std::min(n, m);
@@ -1354,6 +1359,7 @@ int feast_left_eigvecs(feast_plan *p, const feast_z *dA, int64_t lda, const feas
   if (p->mixed())
     return fail(p, FEAST_EINVAL, "feast_left_eigvecs needs an FP64 plan");
   p->err.clear();
+  CheckScope check_scope(p);
   return guarded(p, [&]() -> int {
     const int64_t n = p->n, sc = scnt;
     const int N = p->N;

@@ -464,18 +464,36 @@ void k_gemm_shift(const GemmArgs<T> d, int64_t grid_total) {
 // (the grouped tiles keep the unpipelined four-product loop: the complex64 one
 // then fits four workgroups per compute unit, 128 registers a lane; the
 // complex128 one takes the two-wave budget of the single-problem tile)
-template <typename T, int BM, int BN, int TA, bool SUB, int BK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 16 ? 2 : 1)))
-void k_gemm_grp(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid_total) {
-  const int64_t lin = xcd_remap(blockIdx.x, grid_total);
+template <typename T>
+__device__ inline int find_problem(const GemmArgs<T> *__restrict__ tab, int count, int64_t lin) {
   int lo = 0, hi = count - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (tab[mid].tile0 <= lin) lo = mid;
     else hi = mid - 1;
   }
-  const GemmArgs<T> d = tab[lo];
+  return lo;
+}
+
+template <typename T, int BM, int BN, int TA, bool SUB, int BK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 16 ? 2 : 1)))
+void k_gemm_grp(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid_total) {
+  const int64_t lin = xcd_remap(blockIdx.x, grid_total);
+  const GemmArgs<T> d = tab[find_problem(tab, count, lin)];
   gemm_tile<T, BM, BN, TA, SUB, BK, false, false, false>(d, lin - d.tile0);
+}
+
+// The grouped FP64 LU trailing update C -= A B with the single-problem
+// update's loop: three real products per complex step, next operands read
+// from LDS while the MFMAs issue, BK = 8 and the two-wave register budget.
+// (FP64 rounding of the three-product form stays far below the tolerances;
+// the complex64 grouped update keeps four products, see above.)
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<T, 64>)))
+void k_gemm_grp_upd(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid_total) {
+  const int64_t lin = xcd_remap(blockIdx.x, grid_total);
+  const GemmArgs<T> d = tab[find_problem(tab, count, lin)];
+  gemm_tile<T, 64, 64, 0, true, 8, true, false, true>(d, lin - d.tile0);
 }
 
 // Deterministic reduction of split-K partials: C = sum_s W_s + beta C.
@@ -582,12 +600,14 @@ template int64_t gemm_group_tiles<c64>(GemmArgs<c64> *, int);
 
 template <typename T>
 void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int count,
-                int64_t total_tiles) {
+                int64_t total_tiles, int variant) {
   if (count <= 0 || total_tiles <= 0) return;
   const int64_t padded = (total_tiles + 7) / 8 * 8;
   const dim3 grid(static_cast<unsigned>(padded));
   if (ta == 0) {
-    if (sub)
+    if (sub && variant == GROUP_UPDATE_M3 && sizeof(T) == 16)
+      hipLaunchKernelGGL((k_gemm_grp_upd<T>), grid, dim3(256), 0, s, dtab, count, padded);
+    else if (sub)
       hipLaunchKernelGGL((k_gemm_grp<T, 64, 64, 0, true, 16>), grid, dim3(256), 0, s, dtab, count,
                          padded);
     else
@@ -598,8 +618,8 @@ void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int co
                        padded);
   }
 }
-template void gemm_group<z64>(hipStream_t, int, bool, const GemmArgs<z64> *, int, int64_t);
-template void gemm_group<c64>(hipStream_t, int, bool, const GemmArgs<c64> *, int, int64_t);
+template void gemm_group<z64>(hipStream_t, int, bool, const GemmArgs<z64> *, int, int64_t, int);
+template void gemm_group<c64>(hipStream_t, int, bool, const GemmArgs<c64> *, int, int64_t, int);
 
 void zgemm_shift_residual(hipStream_t s, int64_t M, int64_t N, int64_t K, const z64 *A,
                           const z64 *A2, int64_t lda, const z64 *shift, const z64 *Y, int64_t ldy,

@@ -295,7 +295,9 @@ __global__ __launch_bounds__(NT) void k_leaf(T *__restrict__ Mall, int64_t ld_in
   int pv_[IB];
 #pragma unroll
   for (int c = 0; c < IB; ++c) pv_[c] = c < w ? s_pivs[c] : -1;
-  const int ncol = pkb;  // panel columns; the leaf's own columns are skipped
+  // panel columns (clipped to the matrix: in a grouped launch a wide panel can
+  // extend past a smaller matrix's last column); the leaf's own columns are skipped
+  const int ncol = static_cast<int>(pk0 + pkb <= n ? pkb : n - pk0);
   constexpr int H = 2048 / NT;  // 2 w pkb <= 2048 elements
   T v[H];
   int64_t dst[H], col[H];
@@ -356,13 +358,17 @@ __global__ __launch_bounds__(256) void k_laswp_outside(T *__restrict__ Mall, int
   const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, b);
   T *M = mr.M;
   const int64_t ld = mr.ld, n = mr.n;
-  if (r0 + kb > n) return;
+  // (grouped: a panel wider than what is left of a smaller matrix is clipped
+  // to its last row and column; a matrix already factored has nothing to swap)
+  const int kbe = static_cast<int>(r0 + kb <= n ? kb : n - r0);
+  if (kbe <= 0) return;
+  const int64_t chie = chi < n ? chi : n;
   const int32_t *ipiv = ipiv_all + b * n_in;
   const int64_t t = blockIdx.x * 256ll + threadIdx.x;
-  const int64_t ncols = clo + (n - chi);
+  const int64_t ncols = clo + (n - chie);
   if (t >= ncols) return;
-  const int64_t col = (t < clo) ? t : chi + (t - clo);
-  for (int i = 0; i < kb; ++i) {
+  const int64_t col = (t < clo) ? t : chie + (t - clo);
+  for (int i = 0; i < kbe; ++i) {
     const int64_t r = r0 + i, p = ipiv[r];
     if (p != r) {
       const T x = M[r * ld + col];
@@ -425,26 +431,18 @@ __global__ __launch_bounds__(256) void k_trsm_small(T *__restrict__ Mall, int64_
     }
 }
 
-// One recursion step of the panel factorisation in a single launch, for
-// w1, w2 <= 32:
+// One recursion step of the panel factorisation for w1, w2 <= 32:
 //   X = L11^{-1} X      for X = M[c0:c0+w1, c0+w1:c0+w1+w2], L11 unit lower (w1 x w1),
 //   C -= L21 X          for C = M[c0+w1:n, c0+w1:c0+w1+w2], L21 = M[c0+w1:n, c0:c0+w1].
-// write_x = false: every workgroup solves the small triangular system in LDS
-// (eight lanes per column share each inner product) and updates 64 rows of C
-// from an LDS copy of its L21 rows, 8 outputs per thread; X in the matrix is
-// left as it was, because workgroups that start later still read it.
-// write_x = true (one workgroup per matrix, launched afterwards): solve again
-// and store X.  With per-matrix counters cnt (zero on entry, zero again on
-// exit) the single launch stores X itself: every workgroup counts itself out
-// after its update, and the last one of a matrix (all the others have read X
-// by then) writes its solved copy.  The update is a rank-w1 product with
-// w1 <= 32: it is bound by the traffic of C, so it runs on the VALU.
+// The update is a rank-w1 product with w1 <= 32: it is bound by the traffic of
+// C, so it runs on the VALU.
 constexpr int kPU = 32;
-// The body of k_panel_update for one workgroup: the small triangular solve
-// into sX, then (write_x = false) the update of this workgroup's 64 rows of C.
+// The small triangular solve of one matrix by one workgroup: L11 and X staged
+// in LDS, forward substitution with eight lanes per column sharing each inner
+// product, rows 1.. of the solved X stored back.
 template <typename T>
-__device__ void panel_update_body(T *__restrict__ M, int64_t ld, int64_t n, int64_t c0, int w1,
-                                  int w2, bool write_x, T (*sL)[kPU + 1], T (*sX)[kPU + 1]) {
+__device__ void panel_solve_body(T *__restrict__ M, int64_t ld, int64_t c0, int w1, int w2,
+                                 T (*sL)[kPU + 1], T (*sX)[kPU + 1]) {
   using Tr = cplx_traits<T>;
   const int tid = threadIdx.x;
   for (int e = tid; e < w1 * w1; e += 256) {
@@ -479,22 +477,53 @@ __device__ void panel_update_body(T *__restrict__ M, int64_t ld, int64_t n, int6
     }
   }
   __syncthreads();
-  if (write_x) {
-    for (int e = tid; e < w1 * w2; e += 256) {
-      const int i = e / w2, j = e % w2;
-      if (i > 0) M[(c0 + i) * ld + c0 + w1 + j] = sX[i][j];
-    }
-    return;
+  for (int e = tid; e < w1 * w2; e += 256) {
+    const int i = e / w2, j = e % w2;
+    if (i > 0) M[(c0 + i) * ld + c0 + w1 + j] = sX[i][j];
   }
+}
+
+// The panel update in two launches: the small triangular solve once per
+// matrix (k_panel_solve: X = L11^{-1} X written back), then the rank-w1 update
+// of the rows below by every 64-row chunk (k_panel_rank, reading the solved X).
+// (Fusing both into one launch makes every chunk repeat the solve, a chain of
+// up to 31 dependent LDS steps that then dominates the launch: measured slower.)
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_solve(T *__restrict__ Mall, int64_t ld_in,
+                                                     int64_t stride, int64_t n_in, int64_t c0,
+                                                     int w1, int w2,
+                                                     const GrpMat *__restrict__ grp, int nodes) {
+  __shared__ T sL[64][kPU + 1];
+  __shared__ T sX[kPU][kPU + 1];
+  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, blockIdx.x);
+  if (c0 + w1 + w2 > mr.n) return;
+  panel_solve_body<T>(mr.M, mr.ld, c0, w1, w2, sL, sX);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_rank(T *__restrict__ Mall, int64_t ld_in,
+                                                    int64_t stride, int64_t n_in, int64_t c0,
+                                                    int w1, int w2,
+                                                    const GrpMat *__restrict__ grp, int nodes) {
+  using Tr = cplx_traits<T>;
+  __shared__ T sL[64][kPU + 1];
+  __shared__ T sX[kPU][kPU + 1];
+  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, blockIdx.y);
+  T *M = mr.M;
+  const int64_t ld = mr.ld, n = mr.n;
+  if (c0 + w1 + w2 > n) return;
   const int64_t r0 = c0 + w1 + static_cast<int64_t>(blockIdx.x) * 64;
+  if (r0 >= n) return;  // (a chunk beyond a smaller matrix of a grouped launch)
   const int rows = static_cast<int>((n - r0 < 64) ? n - r0 : 64);
-  if (rows <= 0) return;  // (uniform over the workgroup)
-  // L21 rows of this chunk into LDS (sL is free after the solve)
+  const int tid = threadIdx.x;
+  for (int e = tid; e < w1 * w2; e += 256) {
+    const int i = e / w2, j = e % w2;
+    sX[i][j] = M[(c0 + i) * ld + c0 + w1 + j];
+  }
   for (int e = tid; e < rows * w1; e += 256) {
     const int i = e / w1, k = e % w1;
     sL[i][k] = M[(r0 + i) * ld + c0 + k];
   }
-  __syncthreads();
   const int ti = tid >> 4, tj = tid & 15;
   T acc[4][2];
 #pragma unroll
@@ -504,6 +533,7 @@ __device__ void panel_update_body(T *__restrict__ M, int64_t ld, int64_t n, int6
       const int i = ti + 16 * a, j = tj + 16 * b;
       acc[a][b] = (i < rows && j < w2) ? M[(r0 + i) * ld + c0 + w1 + j] : Tr::make(0.0, 0.0);
     }
+  __syncthreads();
   for (int k = 0; k < w1; ++k) {
     T l[4], x[2];
 #pragma unroll
@@ -523,41 +553,6 @@ __device__ void panel_update_body(T *__restrict__ M, int64_t ld, int64_t n, int6
       if (i < rows && j < w2) M[(r0 + i) * ld + c0 + w1 + j] = acc[a][b];
     }
 }
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_panel_update(T *__restrict__ Mall, int64_t ld_in,
-                                                      int64_t stride, int64_t n_in, int64_t c0,
-                                                      int w1, int w2, bool write_x,
-                                                      const GrpMat *__restrict__ grp, int nodes,
-                                                      int32_t *__restrict__ cnt) {
-  __shared__ T sL[64][kPU + 1];
-  __shared__ T sX[kPU][kPU + 1];
-  __shared__ int s_last;
-  const MatRef<T> mr = mat_of<T>(grp, nodes, Mall, ld_in, stride, n_in, blockIdx.y);
-  T *M = mr.M;
-  const int64_t ld = mr.ld, n = mr.n;
-  // (with counters every workgroup reaches the count below: no early return)
-  if (c0 + w1 + w2 > n && !cnt) return;
-  const bool valid = c0 + w1 + w2 <= n;
-  const int tid = threadIdx.x;
-  if (valid) panel_update_body<T>(M, ld, n, c0, w1, w2, write_x, sL, sX);
-  if (cnt) {
-    // (no fence: this workgroup's loads of X completed before the count, their
-    // values having been used; a device-scope release fence here would write
-    // back the whole L2 of the XCD on every workgroup)
-    if (tid == 0) s_last = atomicAdd(&cnt[blockIdx.y], 1) == static_cast<int>(gridDim.x) - 1;
-    __syncthreads();
-    if (s_last) {
-      if (valid)
-        for (int e = tid; e < w1 * w2; e += 256) {
-          const int i = e / w2, j = e % w2;
-          if (i > 0) M[(c0 + i) * ld + c0 + w1 + j] = sX[i][j];
-        }
-      if (tid == 0) atomicExch(&cnt[blockIdx.y], 0);
-    }
-  }
-}
-
 
 // Register layout shared by the 64 x 64 triangular kernels below: 256 threads,
 // thread (ti, tj) = (tid / 16, tid % 16) holds the 16 entries (ti + 16a,
@@ -853,7 +848,8 @@ template <typename T>
 void laswp_outside(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
                    int64_t r0, int kb, int64_t clo, int64_t chi, const int32_t *ipiv,
                    const GrpMat *grp, int nodes) {
-  const int64_t ncols = clo + (n - chi);
+  // (n: the largest order of a grouped launch; every matrix has at most this many columns)
+  const int64_t ncols = clo + (n > chi ? n - chi : 0);
   if (ncols <= 0 || kb <= 0) return;
   hipLaunchKernelGGL((k_laswp_outside<T>), dim3(static_cast<unsigned>((ncols + 255) / 256), batch),
                      dim3(256), 0, s, M, ld, stride, n, r0, kb, clo, chi, ipiv, grp, nodes);
@@ -874,25 +870,19 @@ template void trsm_small<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int
 
 template <typename T>
 void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w1, int w2, const GrpMat *grp, int nodes, int32_t *cnt) {
-  if (w1 <= 0 || w2 <= 0 || w1 > kPU || w2 > kPU) return;
+                  int64_t c0, int w1, int w2, const GrpMat *grp, int nodes) {
+  if (w1 <= 0 || w2 <= 0 || w1 > kPU || w2 > kPU || batch <= 0) return;
   const int64_t rows = n - c0 - w1;
-  const unsigned chunks = static_cast<unsigned>(rows > 0 ? (rows + 63) / 64 : 1);
-  if (cnt) {  // one launch; the last workgroup of each matrix stores X
-    hipLaunchKernelGGL((k_panel_update<T>), dim3(chunks, batch), dim3(256), 0, s, M, ld, stride, n,
-                       c0, w1, w2, false, grp, nodes, cnt);
-    return;
-  }
+  hipLaunchKernelGGL((k_panel_solve<T>), dim3(batch), dim3(256), 0, s, M, ld, stride, n, c0, w1, w2,
+                     grp, nodes);
   if (rows > 0)
-    hipLaunchKernelGGL((k_panel_update<T>), dim3(chunks, batch), dim3(256), 0, s, M, ld, stride, n,
-                       c0, w1, w2, false, grp, nodes, nullptr);
-  hipLaunchKernelGGL((k_panel_update<T>), dim3(1, batch), dim3(256), 0, s, M, ld, stride, n, c0, w1,
-                     w2, true, grp, nodes, nullptr);
+    hipLaunchKernelGGL((k_panel_rank<T>), dim3(static_cast<unsigned>((rows + 63) / 64), batch),
+                       dim3(256), 0, s, M, ld, stride, n, c0, w1, w2, grp, nodes);
 }
 template void panel_update<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                int, int, const GrpMat *, int, int32_t *);
+                                int, int, const GrpMat *, int);
 template void panel_update<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int64_t,
-                                int, int, const GrpMat *, int, int32_t *);
+                                int, int, const GrpMat *, int);
 int panel_update_max_width() { return kPU; }
 
 template <typename T>

@@ -8,6 +8,28 @@ namespace feast {
 
 namespace {
 
+// Row-wise element kernels: a workgroup of 256 threads is 4 waves, each wave
+// one row; a wave's 64 lanes step through a slice of kRowSlice columns of its
+// row, so consecutive lanes touch consecutive elements (coalesced 16-byte
+// accesses for complex128) and no index is divided.  Grid: x = column slices,
+// y = groups of 4 rows (rows strided by 4 gridDim.y beyond 65535 groups),
+// z = batch.
+constexpr int kRowSlice = 512;
+
+inline dim3 rowwise_grid(int64_t rows, int64_t cols, int32_t batch) {
+  const int64_t gy = std::min<int64_t>((rows + 3) / 4, 65535);
+  return dim3(static_cast<unsigned>(std::max<int64_t>((cols + kRowSlice - 1) / kRowSlice, 1)),
+              static_cast<unsigned>(std::max<int64_t>(gy, 1)),
+              static_cast<unsigned>(std::max<int32_t>(batch, 1)));
+}
+
+#define ROWWISE_FOR(rows, cols, row, col)                                             \
+  for (int64_t row = blockIdx.y * 4ll + (threadIdx.x >> 6); row < (rows);             \
+       row += 4ll * gridDim.y)                                                         \
+    for (int64_t col = blockIdx.x * static_cast<int64_t>(kRowSlice) + (threadIdx.x & 63), \
+                 col##_end = std::min<int64_t>((blockIdx.x + 1ll) * kRowSlice, (cols));  \
+         col < col##_end; col += 64)
+
 // M_j = z_j B - A for all N nodes: A and B are read once, each element is
 // written N times (the write of the N shifted matrices bounds this kernel).
 template <typename T>
@@ -31,13 +53,13 @@ __global__ __launch_bounds__(256) void k_shift(const z64 *__restrict__ A, int64_
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_rows(const T *__restrict__ R, int64_t ldr,
                                                      int64_t sR, const int32_t *__restrict__ perm,
-                                                     int64_t pstride, int64_t m,
+                                                     int64_t pstride, int64_t n, int64_t m,
                                                      T *__restrict__ Y, int64_t ldy, int64_t sY) {
-  const int64_t row = blockIdx.x;
-  const int b = blockIdx.y;
-  const int64_t src = perm[b * pstride + row];
-  for (int64_t c = threadIdx.x; c < m; c += 256)
+  const int b = blockIdx.z;
+  ROWWISE_FOR(n, m, row, c) {
+    const int64_t src = perm[b * pstride + row];
     Y[b * sY + row * ldy + c] = R[b * sR + src * ldr + c];
+  }
 }
 
 // T1 = R - z_j T2 + T1 on the used columns c < used of every node block j
@@ -78,14 +100,13 @@ __global__ __launch_bounds__(256) void k_c_to_z(const c64 *__restrict__ X, int64
                                                 int64_t n, int64_t m, z64 *__restrict__ Y,
                                                 int64_t ldy, int64_t sY,
                                                 const double *__restrict__ nrm2, double cnt) {
-  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
-  const int b = blockIdx.y;
-  if (idx >= n * m) return;
+  const int b = blockIdx.z;
   const int e = solve_scale_exp(nrm2, cnt);
-  const int64_t row = idx / m, col = idx % m;
-  const c64 v = X[b * sX + row * ldx + col];
-  Y[b * sY + row * ldy + col] =
-      make_double2(ldexp(static_cast<double>(v.x), e), ldexp(static_cast<double>(v.y), e));
+  ROWWISE_FOR(n, m, row, col) {
+    const c64 v = X[b * sX + row * ldx + col];
+    Y[b * sY + row * ldy + col] =
+        make_double2(ldexp(static_cast<double>(v.x), e), ldexp(static_cast<double>(v.y), e));
+  }
 }
 
 template <typename T>
@@ -93,65 +114,60 @@ __global__ __launch_bounds__(256) void k_scatter_rows(const T *__restrict__ X, i
                                                       int64_t sX, const int32_t *__restrict__ perm,
                                                       int64_t n, int64_t m, T *__restrict__ Y,
                                                       int64_t ldy, int64_t sY) {
-  const int64_t row = blockIdx.x;
-  const int b = blockIdx.y;
-  const int64_t dst = perm[b * n + row];
-  for (int64_t c = threadIdx.x; c < m; c += 256) Y[b * sY + dst * ldy + c] = X[b * sX + row * ldx + c];
+  const int b = blockIdx.z;
+  ROWWISE_FOR(n, m, row, c) {
+    const int64_t dst = perm[b * n + row];
+    Y[b * sY + dst * ldy + c] = X[b * sX + row * ldx + c];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_weighted_sum(const z64 *__restrict__ Y, int64_t ldy,
                                                       int64_t sY, const z64 *__restrict__ w,
                                                       int32_t N, int64_t n, int64_t m,
                                                       z64 *__restrict__ U, int64_t ldu) {
-  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
-  if (idx >= n * m) return;
-  const int64_t row = idx / m, col = idx % m;
-  double sr = 0.0, si = 0.0;
-  for (int j = 0; j < N; ++j) {
-    const z64 y = Y[j * sY + row * ldy + col];
-    const z64 wj = w[j];
-    sr += wj.x * y.x - wj.y * y.y;
-    si += wj.x * y.y + wj.y * y.x;
+  ROWWISE_FOR(n, m, row, col) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const z64 y = Y[j * sY + row * ldy + col];
+      const z64 wj = w[j];
+      sr += wj.x * y.x - wj.y * y.y;
+      si += wj.x * y.y + wj.y * y.x;
+    }
+    U[row * ldu + col] = make_double2(sr, si);
   }
-  U[row * ldu + col] = make_double2(sr, si);
 }
 
 __global__ __launch_bounds__(256) void k_copy_block(const z64 *__restrict__ X, int64_t ldx,
                                                     int64_t n, int64_t m, z64 *__restrict__ Y,
                                                     int64_t ldy) {
-  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
-  if (idx >= n * m) return;
-  const int64_t row = idx / m, col = idx % m;
-  Y[row * ldy + col] = X[row * ldx + col];
+  ROWWISE_FOR(n, m, row, col) Y[row * ldy + col] = X[row * ldx + col];
 }
 
 __global__ __launch_bounds__(256) void k_z_to_c(const z64 *__restrict__ X, int64_t ldx, int64_t sX,
                                                 int64_t n, int64_t m, c64 *__restrict__ Y,
                                                 int64_t ldy, int64_t sY,
                                                 const double *__restrict__ nrm2, double cnt) {
-  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
-  const int b = blockIdx.y;
-  if (idx >= n * m) return;
+  const int b = blockIdx.z;
   const int e = solve_scale_exp(nrm2, cnt);
-  const int64_t row = idx / m, col = idx % m;
-  const z64 v = X[b * sX + row * ldx + col];
-  Y[b * sY + row * ldy + col] =
-      make_float2(static_cast<float>(ldexp(v.x, -e)), static_cast<float>(ldexp(v.y, -e)));
+  ROWWISE_FOR(n, m, row, col) {
+    const z64 v = X[b * sX + row * ldx + col];
+    Y[b * sY + row * ldy + col] =
+        make_float2(static_cast<float>(ldexp(v.x, -e)), static_cast<float>(ldexp(v.y, -e)));
+  }
 }
 
 __global__ __launch_bounds__(256) void k_add_c_to_z(const c64 *__restrict__ X, int64_t ldx,
                                                     int64_t sX, int64_t n, int64_t m,
                                                     z64 *__restrict__ Y, int64_t ldy, int64_t sY,
                                                     const double *__restrict__ nrm2, double cnt) {
-  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
-  const int b = blockIdx.y;
-  if (idx >= n * m) return;
+  const int b = blockIdx.z;
   const int e = solve_scale_exp(nrm2, cnt);
-  const int64_t row = idx / m, col = idx % m;
-  const c64 v = X[b * sX + row * ldx + col];
-  z64 &y = Y[b * sY + row * ldy + col];
-  y.x += ldexp(static_cast<double>(v.x), e);
-  y.y += ldexp(static_cast<double>(v.y), e);
+  ROWWISE_FOR(n, m, row, col) {
+    const c64 v = X[b * sX + row * ldx + col];
+    z64 &y = Y[b * sY + row * ldy + col];
+    y.x += ldexp(static_cast<double>(v.x), e);
+    y.y += ldexp(static_cast<double>(v.y), e);
+  }
 }
 
 // Partial column sums over a chunk of 64 rows: one thread per column.
@@ -242,32 +258,33 @@ __global__ __launch_bounds__(256) void k_fro_part(const z64 *__restrict__ X, int
 // missed with probability about 2^-64, and the sum does not depend on the
 // order in which workgroups add their parts.  Matrix b is tab[b] when tab is
 // given, else a0 (b = 0) or a1 (b = 1); out[b] must be zero on entry.
+// (each term: xor with the position key, multiply by an odd constant, fold the
+// high half down -- three bijections of the 64-bit word)
 __device__ inline uint64_t fp_mix(uint64_t x) {
-  x ^= x >> 31;
-  x *= 0x7fb5d329728ea185ull;
-  x ^= x >> 27;
   x *= 0x81dadef4bc2dd44dull;
-  x ^= x >> 33;
-  return x;
+  return x ^ (x >> 32);
 }
 
 __global__ __launch_bounds__(256) void k_fingerprint(const GrpMat *__restrict__ tab, GrpMat a0,
                                                      GrpMat a1, unsigned long long *__restrict__ out) {
-  const int b = blockIdx.y;
+  const int b = blockIdx.z;
   const GrpMat e = tab ? tab[b] : (b == 0 ? a0 : a1);
   const z64 *X = static_cast<const z64 *>(e.base);
-  const int64_t n = e.n, total = n * n;
+  const int64_t n = e.n;
   uint64_t h = 0;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += 256ll * gridDim.x) {
-    const int64_t row = i / n, col = i - row * n;
+  ROWWISE_FOR(n, n, row, col) {
     const z64 v = X[row * e.ld + col];
-    const uint64_t key = static_cast<uint64_t>(i) * 0x9e3779b97f4a7c15ull;
+    const uint64_t key = static_cast<uint64_t>(row * n + col) * 0x9e3779b97f4a7c15ull;
     h += fp_mix(static_cast<uint64_t>(__double_as_longlong(v.x)) ^ key);
     h += fp_mix(static_cast<uint64_t>(__double_as_longlong(v.y)) ^ ~key);
   }
-  // wave reduction, then one atomic per wave (integer sums are order-free)
+  // wave sums, then one atomic per workgroup (integer sums are order-free)
+  __shared__ uint64_t part[4];
   for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
-  if ((threadIdx.x & 63) == 0) atomicAdd(out + b, static_cast<unsigned long long>(h));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = h;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicAdd(out + b, static_cast<unsigned long long>(part[0] + part[1] + part[2] + part[3]));
 }
 
 // A += shift_rel * trace(A) on the diagonal (t x t, one workgroup).
@@ -675,9 +692,9 @@ template <typename T>
 void gather_rows(hipStream_t s, const T *R, int64_t ldr, int64_t sR, const int32_t *perm,
                  int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY,
                  int64_t pstride) {
-  if (n <= 0 || batch <= 0) return;
-  hipLaunchKernelGGL((k_gather_rows<T>), dim3(static_cast<unsigned>(n), batch), dim3(256), 0, s, R,
-                     ldr, sR, perm, pstride > 0 ? pstride : n, m, Y, ldy, sY);
+  if (batch <= 0 || n <= 0 || m <= 0) return;
+  hipLaunchKernelGGL((k_gather_rows<T>), rowwise_grid(n, m, batch), dim3(256), 0, s, R,
+                     ldr, sR, perm, pstride > 0 ? pstride : n, n, m, Y, ldy, sY);
 }
 template void gather_rows<z64>(hipStream_t, const z64 *, int64_t, int64_t, const int32_t *,
                                int64_t, int64_t, int32_t, z64 *, int64_t, int64_t, int64_t);
@@ -719,14 +736,16 @@ void shift_residual(hipStream_t s, const z64 *R, int64_t ldr, z64 *T1, const z64
 void c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
             int32_t batch, z64 *Y, int64_t ldy, int64_t sY, const double *nrm2, double cnt) {
   const int64_t tot = n * m;
-  hipLaunchKernelGGL(k_c_to_z, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256), 0,
-                     s, X, ldx, sX, n, m, Y, ldy, sY, nrm2, cnt);
+  if (tot <= 0 || batch <= 0) return;
+  hipLaunchKernelGGL(k_c_to_z, rowwise_grid(n, m, batch), dim3(256), 0, s, X, ldx, sX, n, m, Y,
+                     ldy, sY, nrm2, cnt);
 }
 
 template <typename T>
 void scatter_rows(hipStream_t s, const T *X, int64_t ldx, int64_t sX, const int32_t *perm,
                   int64_t n, int64_t m, int32_t batch, T *Y, int64_t ldy, int64_t sY) {
-  hipLaunchKernelGGL((k_scatter_rows<T>), dim3(static_cast<unsigned>(n), batch), dim3(256), 0, s, X,
+  if (batch <= 0 || n <= 0 || m <= 0) return;
+  hipLaunchKernelGGL((k_scatter_rows<T>), rowwise_grid(n, m, batch), dim3(256), 0, s, X,
                      ldx, sX, perm, n, m, Y, ldy, sY);
 }
 template void scatter_rows<z64>(hipStream_t, const z64 *, int64_t, int64_t, const int32_t *,
@@ -735,7 +754,8 @@ template void scatter_rows<z64>(hipStream_t, const z64 *, int64_t, int64_t, cons
 void weighted_sum(hipStream_t s, const z64 *Y, int64_t ldy, int64_t sY, const z64 *w, int32_t N,
                   int64_t n, int64_t m, z64 *U, int64_t ldu) {
   const int64_t tot = n * m;
-  hipLaunchKernelGGL(k_weighted_sum, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s,
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_weighted_sum, rowwise_grid(n, m, 1), dim3(256), 0, s,
                      Y, ldy, sY, w, N, n, m, U, ldu);
 }
 
@@ -743,22 +763,24 @@ void copy_block_z(hipStream_t s, const z64 *X, int64_t ldx, int64_t n, int64_t m
                   int64_t ldy) {
   const int64_t tot = n * m;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_copy_block, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_copy_block, rowwise_grid(n, m, 1), dim3(256), 0, s,
                      X, ldx, n, m, Y, ldy);
 }
 
 void z_to_c(hipStream_t s, const z64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
             int32_t batch, c64 *Y, int64_t ldy, int64_t sY, const double *nrm2, double cnt) {
   const int64_t tot = n * m;
-  hipLaunchKernelGGL(k_z_to_c, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256), 0,
-                     s, X, ldx, sX, n, m, Y, ldy, sY, nrm2, cnt);
+  if (tot <= 0 || batch <= 0) return;
+  hipLaunchKernelGGL(k_z_to_c, rowwise_grid(n, m, batch), dim3(256), 0, s, X, ldx, sX, n, m, Y,
+                     ldy, sY, nrm2, cnt);
 }
 
 void add_c_to_z(hipStream_t s, const c64 *X, int64_t ldx, int64_t sX, int64_t n, int64_t m,
                 int32_t batch, z64 *Y, int64_t ldy, int64_t sY, const double *nrm2, double cnt) {
   const int64_t tot = n * m;
-  hipLaunchKernelGGL(k_add_c_to_z, dim3(static_cast<unsigned>((tot + 255) / 256), batch), dim3(256),
-                     0, s, X, ldx, sX, n, m, Y, ldy, sY, nrm2, cnt);
+  if (tot <= 0 || batch <= 0) return;
+  hipLaunchKernelGGL(k_add_c_to_z, rowwise_grid(n, m, batch), dim3(256), 0, s, X, ldx, sX, n, m,
+                     Y, ldy, sY, nrm2, cnt);
 }
 
 void ritz_norms(hipStream_t s, const z64 *AX, const z64 *BX, int64_t ld, int64_t n, int64_t t,
@@ -792,9 +814,12 @@ void fingerprint(hipStream_t s, const GrpMat *tab, int count, GrpMat a0, GrpMat 
   if (count <= 0) return;
   fill_i32(s, reinterpret_cast<int32_t *>(out), 2ll * count, 0);
   if (nmax <= 0) return;
-  const int64_t per = (nmax * nmax + 255) / 256;
-  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>(per, count > 8 ? 64 : 1024));
-  hipLaunchKernelGGL(k_fingerprint, dim3(blocks, count), dim3(256), 0, s, tab, a0, a1,
+  // about 2048 workgroups over all matrices (each wave strides over rows), so
+  // the per-workgroup atomics stay few
+  dim3 g = rowwise_grid(nmax, nmax, count);
+  const int64_t want = std::max<int64_t>(1, 2048 / (static_cast<int64_t>(g.x) * count));
+  g.y = static_cast<unsigned>(std::min<int64_t>(g.y, want));
+  hipLaunchKernelGGL(k_fingerprint, g, dim3(256), 0, s, tab, a0, a1,
                      reinterpret_cast<unsigned long long *>(out));
 }
 

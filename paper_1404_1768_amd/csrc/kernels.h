@@ -63,10 +63,14 @@ void cgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha
 // kchunk) of a host table and returns the total tile count; the launch reads
 // the table from device memory.  sub: every problem is C -= A B (alpha = -1,
 // beta = 1); ta: 0 or 2 (2 only with sub = false).
+//   variant: GROUP_PLAIN, or GROUP_UPDATE_M3 for a C -= A B update of
+//   complex128 problems on the three-product, operand-pipelined loop (BK = 8);
+//   complex64 problems always take the plain loop.
+enum { GROUP_PLAIN = 0, GROUP_UPDATE_M3 = 1 };
 template <typename T> int64_t gemm_group_tiles(GemmArgs<T> *tab, int count);
 template <typename T>
 void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int count,
-                int64_t total_tiles);
+                int64_t total_tiles, int variant = GROUP_PLAIN);
 
 // ---- LU building blocks (k_lu.hip); T = z64 or c64 --------------------------
 //
@@ -98,15 +102,12 @@ template <typename T>
 void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t c0,
                 int w1, int w2);
 
-// Both halves of one panel recursion step in one launch (w1, w2 <=
-// panel_update_max_width()): X = L11^{-1} X as in trsm_small, then
-// M[c0+w1:n, c0+w1:c0+w1+w2] -= M[c0+w1:n, c0:c0+w1] X.
-//   cnt: optional per-matrix counters (batch of them, zero on entry and left
-//   zero) that let a single launch store the solved X block.
+// Both halves of one panel recursion step (w1, w2 <= panel_update_max_width()):
+// X = L11^{-1} X as in trsm_small (one workgroup per matrix), then
+// M[c0+w1:n, c0+w1:c0+w1+w2] -= M[c0+w1:n, c0:c0+w1] X (64-row chunks).
 template <typename T>
 void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
-                  int64_t c0, int w1, int w2, const GrpMat *grp = nullptr, int nodes = 1,
-                  int32_t *cnt = nullptr);
+                  int64_t c0, int w1, int w2, const GrpMat *grp = nullptr, int nodes = 1);
 int panel_update_max_width();
 
 // Inverses of the diagonal blocks of the unit-lower L (lower=true) or of the

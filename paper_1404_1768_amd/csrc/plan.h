@@ -88,9 +88,9 @@ struct feast_plan {
   bool factored = false;
   uint64_t fpA = 0, fpB = 0;
   DevBuf fp;  // device fingerprints of the current call's A and B
+  bool checked = false;  // within one entry-point call: the factors were checked (or made)
   DevBuf F, piv, perm, info, Linv, Uinv;
-  DevBuf Linv2, Uinv2;
-  DevBuf pucnt;  // per-node counters of the one-launch panel updates  // inverted 128 x 128 diagonal blocks (the solves' leaves)
+  DevBuf Linv2, Uinv2;  // inverted 128 x 128 diagonal blocks (the solves' leaves)
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
   DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
@@ -187,6 +187,14 @@ template <typename F> int guarded(feast_plan *p, F &&f) {
   }
 }
 
+
+// One entry-point call: A and B cannot change while it runs, so the cached
+// factors are checked against them once per call.
+struct CheckScope {
+  feast_plan *p;
+  explicit CheckScope(feast_plan *q) : p(q) { p->checked = false; }
+  ~CheckScope() { p->checked = false; }
+};
 
 // With opts.profile, launch() is bracketed by HIP events on the plan's stream
 // and recorded under class cls (enum feast_kclass) with its algorithmic HBM
