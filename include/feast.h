@@ -95,6 +95,10 @@ typedef struct {
                           kernels need whole compute units, which the update holds,
                           so the overlap measured slower) */
   int32_t update_tile; /* LU trailing-update tile: 0 = 64 x 64, 1 = 128 x 64 (default 0) */
+  int32_t batch_update; /* batched form's trailing-update loop: 0 = from the tuned table
+                           (with nb = 0 for the panel width too), 1 = four real products per
+                           complex step, 2 = three products, operand-pipelined (complex128;
+                           complex64 takes 1), 3 = four products, operand-pipelined (default 0) */
 } feast_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -357,7 +361,11 @@ const char *feast_last_error(const feast_plan *plan);
  * factorisation and of a filter is captured once in a HIP graph and replayed.
  * All pointer arguments of the batch calls below are HOST arrays of `count`
  * entries (device pointers or host buffers as stated), in the caller's order.
- * Options as for a plan (nb is ignored: the grouped LU uses 64-wide panels).
+ * Options as for a plan.  The grouped LU's panel width (64 or 128) and its
+ * trailing-update loop come from a table written by the project's autotuner
+ * (timings of every candidate per order bucket and precision on an MI355X),
+ * looked up with the order that splits the batch's LU work (sum of n_p^3) in
+ * half; opts.nb = 64 or 128 and opts.batch_update = 1..3 override it.
  * The batch owns its device memory (factors, node solutions, workspaces) and a
  * page-locked host buffer of 2 sum_p m[p]^2 complex entries through which the
  * reduced pencils reach the host; feast_batch_destroy frees all of it.

@@ -58,7 +58,7 @@ class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("eta", C.c_double), ("max_iter", C.c_int32),
                 ("prec", C.c_int32), ("refine_tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("nb", C.c_int32), ("profile", C.c_int32), ("lookahead", C.c_int32),
-                ("update_tile", C.c_int32)]
+                ("update_tile", C.c_int32), ("batch_update", C.c_int32)]
 
 
 K_CLASSES = ["shift", "weighted_sum", "gather_rows", "z_to_c", "c_to_z", "fingerprint"]
@@ -655,7 +655,7 @@ class Batch:
 
     def __init__(self, ns, ms, centers, radii, nodes: int, rule: int = TRAPEZOID,
                  eps: float = 1e-10, eta: float = 1e-3, max_iter: int = 20, prec: int = FP64,
-                 max_sweeps: int = 6, stream=None):
+                 max_sweeps: int = 6, nb: int = 0, batch_update: int = 0, stream=None):
         self.lib = load()
         self.ns = [int(x) for x in ns]
         self.ms = [int(x) for x in ms]
@@ -667,6 +667,7 @@ class Batch:
         self.opts = default_opts()
         self.opts.eps, self.opts.eta, self.opts.max_iter = float(eps), float(eta), int(max_iter)
         self.opts.prec, self.opts.max_sweeps = int(prec), int(max_sweeps)
+        self.opts.nb, self.opts.batch_update = int(nb), int(batch_update)
         self._stream_obj = stream
         self._h = C.c_void_p()
         n_arr = (C.c_int64 * P)(*self.ns)

@@ -34,6 +34,7 @@
 #include <thread>
 #include <vector>
 
+#include "batch_tune.h"
 #include "host_eig.h"
 #include "plan.h"
 
@@ -124,6 +125,7 @@ struct feast_batch {
   // grouped factors
   DevBuf F, piv, perm, info, Linv, Uinv, grp;
   int64_t lu_nb = 128;  // panel width of the grouped LU (64 or 128)
+  int lu_update = feast::GROUP_UPDATE_M3;  // loop of its trailing update (feast::GROUP_*)
   std::vector<int64_t> foff;  // element offset of pencil p's first matrix in F
   // node solutions (np_p x N m_p each) and the mixed-form buffers
   DevBuf Y, Yc, T1, T2;
@@ -179,6 +181,32 @@ template <typename F> int bguarded(feast_batch *b, F &&f) {
     if (b) b->err = "unexpected exception";
     return FEAST_EDEVICE;
   }
+}
+
+// The grouped LU's panel width and trailing-update loop: opts.nb /
+// opts.batch_update when given, else the autotuner's entry for this precision
+// and the order n* at which the padded orders' share of the LU work
+// (sum of np^3, largest first) reaches one half.
+void choose_lu_config(feast_batch *b) {
+  double total = 0.0, acc = 0.0;
+  for (int64_t v : b->np) total += static_cast<double>(v) * v * v;
+  int64_t nstar = b->np.empty() ? 0 : b->np[0];
+  for (int64_t v : b->np) {  // (np in decreasing order)
+    acc += static_cast<double>(v) * v * v;
+    nstar = v;
+    if (acc >= 0.5 * total) break;
+  }
+  int nb = 128, upd = feast::GROUP_UPDATE_M3;
+  for (const feast_tune::Entry &e : feast_tune::kBatch)
+    if (e.prec == b->o.prec && nstar >= e.lo && nstar < e.hi) {
+      nb = e.nb;
+      upd = e.update;
+      break;
+    }
+  if (b->o.nb != 0) nb = b->o.nb;
+  if (b->o.batch_update != 0) upd = b->o.batch_update - 1;
+  b->lu_nb = nb;
+  b->lu_update = upd;
 }
 
 // A member plan: nodes, weights and the n x m / m x m workspaces of one pencil,
@@ -365,7 +393,7 @@ void lu_grouped(feast_batch *b, bool record) {
     ggemm<T>(b, tab, 0, false, u0);
     ggemm<T>(b, tab, 0, true, u10);
     ggemm<T>(b, tab, 0, false, u1);
-    ggemm<T>(b, tab, 0, true, upd, feast::GROUP_UPDATE_M3);
+    ggemm<T>(b, tab, 0, true, upd, b->lu_update);
   }
   if (!record) {
     const int nmat = b->P * N;
@@ -899,7 +927,8 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
   if (o) opts = *o;
   if (!(opts.eta > 0.0) || !(opts.eps >= 0.0) || opts.max_iter < 1 ||
       opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
-      opts.max_sweeps < 0)
+      opts.max_sweeps < 0 || (opts.nb != 0 && opts.nb != 64 && opts.nb != 128) ||
+      opts.batch_update < 0 || opts.batch_update > 3)
     return FEAST_EINVAL;
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > 16384 || m[i] < 1 || m[i] > n[i] || bad_contour(&c[i]) ||
@@ -946,6 +975,7 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
     }
     b->nmax = b->np[0];
     b->nblk = b->nmax / 64;
+    choose_lu_config(b);
     b->mmax = *std::max_element(b->m.begin(), b->m.end());
     b->dinv.alloc(sizeof(z64) * P * b->mblk() * 4096);
     b->flags.alloc(sizeof(int32_t) * 8 * P);

@@ -650,6 +650,7 @@ void feast_opts_default(feast_opts *o) {
   o->profile = 0;
   o->lookahead = 0;
   o->update_tile = 0;
+  o->batch_update = 0;
 }
 
 int feast_nodes(const feast_contour *c, feast_z *hz, feast_z *hw) {
@@ -699,7 +700,8 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
       opts.max_iter > FEAST_MAX_HISTORY || (opts.prec != FEAST_FP64 && opts.prec != FEAST_MIXED) ||
       opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) ||
       (opts.nb != 0 && opts.nb != 64 && opts.nb != 128) || opts.lookahead < 0 ||
-      opts.lookahead > 1 || opts.update_tile < 0 || opts.update_tile > 1)
+      opts.lookahead > 1 || opts.update_tile < 0 || opts.update_tile > 1 ||
+      opts.batch_update < 0 || opts.batch_update > 3)
     return FEAST_EINVAL;
   feast_plan *p = nullptr;
   try {

@@ -496,6 +496,18 @@ void k_gemm_grp_upd(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid
   gemm_tile<T, 64, 64, 0, true, 8, true, false, true>(d, lin - d.tile0);
 }
 
+// The grouped update C -= A B with four real products per complex step and
+// the operand-pipelined loop (BK = 16, the single-problem tiles' register
+// budget): the candidate between the plain grouped loop and the
+// three-product one for either precision.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<T, 64>)))
+void k_gemm_grp_pipe(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid_total) {
+  const int64_t lin = xcd_remap(blockIdx.x, grid_total);
+  const GemmArgs<T> d = tab[find_problem(tab, count, lin)];
+  gemm_tile<T, 64, 64, 0, true, 16, false, false, true>(d, lin - d.tile0);
+}
+
 // Deterministic reduction of split-K partials: C = sum_s W_s + beta C.
 template <typename T>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const GemmArgs<T> d) {
@@ -607,6 +619,8 @@ void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int co
   if (ta == 0) {
     if (sub && variant == GROUP_UPDATE_M3 && sizeof(T) == 16)
       hipLaunchKernelGGL((k_gemm_grp_upd<T>), grid, dim3(256), 0, s, dtab, count, padded);
+    else if (sub && variant == GROUP_UPDATE_PIPE)
+      hipLaunchKernelGGL((k_gemm_grp_pipe<T>), grid, dim3(256), 0, s, dtab, count, padded);
     else if (sub)
       hipLaunchKernelGGL((k_gemm_grp<T, 64, 64, 0, true, 16>), grid, dim3(256), 0, s, dtab, count,
                          padded);

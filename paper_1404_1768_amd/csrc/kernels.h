@@ -63,10 +63,11 @@ void cgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha
 // kchunk) of a host table and returns the total tile count; the launch reads
 // the table from device memory.  sub: every problem is C -= A B (alpha = -1,
 // beta = 1); ta: 0 or 2 (2 only with sub = false).
-//   variant: GROUP_PLAIN, or GROUP_UPDATE_M3 for a C -= A B update of
-//   complex128 problems on the three-product, operand-pipelined loop (BK = 8);
-//   complex64 problems always take the plain loop.
-enum { GROUP_PLAIN = 0, GROUP_UPDATE_M3 = 1 };
+//   variant (sub = true, ta = 0 only): GROUP_PLAIN (four real products per
+//   complex step, unpipelined, BK = 16); GROUP_UPDATE_M3: complex128 problems
+//   on the three-product, operand-pipelined loop (BK = 8), complex64 ones on the
+//   plain loop; GROUP_UPDATE_PIPE: four products on the operand-pipelined loop.
+enum { GROUP_PLAIN = 0, GROUP_UPDATE_M3 = 1, GROUP_UPDATE_PIPE = 2 };
 template <typename T> int64_t gemm_group_tiles(GemmArgs<T> *tab, int count);
 template <typename T>
 void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int count,

@@ -74,6 +74,23 @@ def test_batch_filter_matches_oracle(prec, sweeps):
         assert np.array_equal(U, U2), p.name
 
 
+@pytest.mark.parametrize("prec,nb,upd", [(fm.FP64, 64, 1), (fm.FP64, 64, 2), (fm.FP64, 128, 1),
+                                         (fm.FP64, 128, 3), (fm.MIXED, 64, 3), (fm.MIXED, 128, 1),
+                                         (fm.MIXED, 128, 3)])
+def test_batch_lu_configurations_match_oracle(prec, nb, upd):
+    # every configuration the autotuner may pick (panel width, trailing-update
+    # loop) gives the oracle's filtered blocks; orders 64..300 put odd multiples
+    # of 64 (a last 64-column panel under 128-column steps) in the batch
+    ps = small_batch()
+    As, Bs, Vs = [to_dev(p.A) for p in ps], [to_dev(p.B) for p in ps], [to_dev(p.V) for p in ps]
+    with make_batch(ps, prec, nb=nb, batch_update=upd) as b:
+        Us = [u.cpu().numpy() for u in b.filter(As, Bs, Vs, 3 if prec == fm.MIXED else 0)]
+    for p, U in zip(ps, Us):
+        z, w = o.contour_nodes(p.center, p.radius, p.nodes)
+        ref = o.apply_filter(o.ShiftedSolver(p.A, p.B, z), w, p.V)
+        assert np.max(np.abs(U - ref)) <= 1e-10 * np.abs(ref).max(), (p.name, nb, upd)
+
+
 def test_batch_filter_mixed_without_refinement_is_single_precision_accurate():
     ps = small_batch()[:3]
     As, Bs, Vs = [to_dev(p.A) for p in ps], [to_dev(p.B) for p in ps], [to_dev(p.V) for p in ps]
