@@ -29,6 +29,8 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -56,6 +58,7 @@ struct Tables {
   std::vector<size_t> off, cnt;
   size_t cur = 0;
   DevBuf dev;
+  ~Tables() { dev.release(); }
   void begin() { cur = 0; }
   template <class E> const E *put(const std::vector<E> &v) {
     if (record) {
@@ -75,21 +78,12 @@ struct Tables {
     if (!host.empty()) HIPCHK(hipMemcpy(dev.p, host.data(), host.size(), hipMemcpyHostToDevice));
     record = false;
   }
-  // Per-call tables: back to record mode (the device buffer is kept), and an
-  // upload ordered on `s` (the host copy stays alive until the next reset,
-  // which follows a synchronisation of `s`).
+  // back to record mode (the device buffer is kept)
   void reset() {
     record = true;
     host.clear();
     off.clear();
     cnt.clear();
-    cur = 0;
-  }
-  void upload_async(hipStream_t s) {
-    dev.alloc(std::max<size_t>(host.size(), 256));
-    if (!host.empty())
-      HIPCHK(hipMemcpyAsync(dev.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
-    record = false;
     cur = 0;
   }
 };
@@ -99,6 +93,10 @@ struct Tables {
 struct Graph {
   hipGraphExec_t exec = nullptr;
   std::vector<int64_t> key;
+  Graph() = default;
+  Graph(const Graph &) = delete;
+  Graph &operator=(const Graph &) = delete;
+  ~Graph() { reset(); }
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     exec = nullptr;
@@ -126,11 +124,12 @@ struct feast_batch {
   DevBuf F, piv, perm, info, Linv, Uinv, grp;
   int64_t lu_nb = 128;  // panel width of the grouped LU (64 or 128)
   int lu_update = feast::GROUP_UPDATE_M3;  // loop of its trailing update (feast::GROUP_*)
+  int nbig = 0;  // pencils whose padded order exceeds lu_small_max_order (a prefix)
   std::vector<int64_t> foff;  // element offset of pencil p's first matrix in F
   // node solutions (np_p x N m_p each) and the mixed-form buffers
   DevBuf Y, Yc, T1, T2;
   std::vector<int64_t> yoff, toff;
-  Tables lu_tab, sv_tab, pj_tab;
+  Tables lu_tab, sv_tab;
   DevBuf dinv, flags;  // grouped orthonormalisation: inverted 64 x 64 blocks, breakdown flags
   // every pencil's At and Bt packed (m_p^2 each, in internal order), on the
   // device and in page-locked host memory: one copy to the host per projection
@@ -139,6 +138,13 @@ struct feast_batch {
   DevBuf sk;  // split-K partials of the m x m products (up to kMaxSplits per pencil)
   int64_t mmax = 0;
   Graph g_factor, g_filter;
+  // Projection graphs, one per (caller pointers, list of pencils still
+  // iterating): the scheduling tables of that list and the captured launches.
+  struct ProjGraph {
+    Tables tab;
+    Graph g;
+  };
+  std::map<std::vector<int64_t>, std::unique_ptr<ProjGraph>> proj_graphs;
   // cached factors belong to the pencils whose content fingerprints are ffp
   // (A_p, B_p in the caller's order); fptab/fpout: the fingerprint launch
   bool factored = false;
@@ -335,18 +341,33 @@ void lu_grouped(feast_batch *b, bool record) {
   const GrpMat *g = b->grp.as<GrpMat>();
   int32_t *piv = b->piv.as<int32_t>();
   const int64_t NB = b->lu_nb;
+  // pencils of padded order <= lu_small_max_order (the suffix of the sorted
+  // list) are factored whole, one matrix per workgroup of one persistent
+  // launch, with the inverses of their L diagonal blocks; the lockstep steps
+  // below cover the others
+  const int nbig = b->nbig;
   if (!record) {
     feast::fill_i32(b->gs, b->info.as<int32_t>(), static_cast<int64_t>(b->P) * N, 0);
+    if (nbig < b->P) {
+      const int nsmall = (b->P - nbig) * N;
+      const int64_t off = static_cast<int64_t>(nbig) * N;
+      feast::lu_small<T>(b->gs, g + nbig, N, nsmall, b->nmax, piv + off * b->nmax,
+                         b->info.as<int32_t>() + off);
+      feast::diag_block_inverse<T>(b->gs, nullptr, 0, 0, nsmall, b->nmax, 64, 0,
+                                   b->np[nbig] / 64, true, Linv + off * is, is, g + nbig, N);
+    }
   }
+  auto active = [&](int64_t k) { return std::min(b->active(k), nbig); };
   for (int64_t k0 = 0; k0 < b->nmax; k0 += NB) {
     const int64_t k1 = k0 + NB, j0 = k0 / 64;
-    const int act = b->active(k0), nmat = act * N;
+    const int act = active(k0), nmat = act * N;
+    if (act == 0) break;
     if (!record) {
       panel_grp<T>(b, F, nmat, k0, static_cast<int>(kPanel), k0, static_cast<int>(NB));
       feast::diag_block_inverse<T>(b->gs, F, 0, 0, nmat, b->nmax, 64, j0, j0 + 1, true, Linv, is,
                                    g, N);
     }
-    const int acth = NB > kPanel ? b->active(k0 + kPanel) : 0;
+    const int acth = NB > kPanel ? active(k0 + kPanel) : 0;
     if (acth > 0) {
       std::vector<GemmArgs<T>> x, upx;
       for (int p = 0; p < acth; ++p) {
@@ -371,7 +392,7 @@ void lu_grouped(feast_batch *b, bool record) {
     if (!record)
       feast::laswp_outside<T>(b->gs, F, 0, 0, nmat, b->nmax, k0, static_cast<int>(NB), k0, k1, piv,
                               g, N);
-    const int act2 = b->active(k1);
+    const int act2 = active(k1);
     std::vector<GemmArgs<T>> u0, u10, u1, upd;
     for (int p = 0; p < act2; ++p) {
       const int64_t ld = b->np[p], st = ld * ld, rest = ld - k1;
@@ -854,11 +875,26 @@ int project_grouped(feast_batch *b, const std::vector<int> &act, const feast_z *
                     const int64_t *lda, const feast_z *const *dB, const int64_t *ldb,
                     std::vector<std::vector<feast_z>> &At, std::vector<std::vector<feast_z>> &Bt) {
   if (act.empty()) return FEAST_OK;
-  Tables &t = b->pj_tab;
-  t.reset();
-  project_schedule(b, t, act, dA, lda, dB, ldb);
-  t.upload_async(b->gs);
-  project_schedule(b, t, act, dA, lda, dB, ldb);
+  // the projection of this list of pencils is scheduled once (tables recorded
+  // and uploaded), captured in a graph on its first use and replayed after
+  std::vector<int64_t> key = make_key(b, dA, lda, dB, ldb, -1);
+  key.insert(key.end(), act.begin(), act.end());
+  if (b->proj_graphs.size() >= 16 && !b->proj_graphs.count(key)) {
+    HIPCHK(hipStreamSynchronize(b->gs));  // (no replay in flight when they go)
+    b->proj_graphs.clear();
+  }
+  std::unique_ptr<feast_batch::ProjGraph> &pg = b->proj_graphs[key];
+  if (!pg) {
+    pg = std::make_unique<feast_batch::ProjGraph>();
+    pg->tab.reset();
+    project_schedule(b, pg->tab, act, dA, lda, dB, ldb);
+    pg->tab.upload();
+  }
+  Tables &t = pg->tab;
+  run_graph(b, pg->g, key, [&]() {
+    t.begin();
+    project_schedule(b, t, act, dA, lda, dB, ldb);
+  });
   hipStream_t s = b->gs;
   const int cnt = static_cast<int>(act.size());
   std::vector<int32_t> hf(8 * cnt);
@@ -976,6 +1012,10 @@ int feast_batch_create(feast_batch **out, int32_t count, const int64_t *n, const
     b->nmax = b->np[0];
     b->nblk = b->nmax / 64;
     choose_lu_config(b);
+    const int64_t small = b->mixed() ? feast::lu_small_max_order<c64>()
+                                     : feast::lu_small_max_order<z64>();
+    b->nbig = 0;
+    while (b->nbig < P && b->np[b->nbig] > small) ++b->nbig;
     b->mmax = *std::max_element(b->m.begin(), b->m.end());
     b->dinv.alloc(sizeof(z64) * P * b->mblk() * 4096);
     b->flags.alloc(sizeof(int32_t) * 8 * P);
@@ -1043,9 +1083,11 @@ int feast_batch_destroy(feast_batch *b) {
   if (b->as) (void)hipStreamSynchronize(b->as);
   b->g_factor.reset();
   b->g_filter.reset();
+  for (auto &e : b->proj_graphs) e.second->g.reset();
+  b->proj_graphs.clear();
   for (feast_plan *p : b->sub) feast_plan_destroy(p);
   for (DevBuf *d : {&b->F, &b->piv, &b->perm, &b->info, &b->Linv, &b->Uinv, &b->grp, &b->Y, &b->Yc,
-                    &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev, &b->pj_tab.dev, &b->dinv,
+                    &b->T1, &b->T2, &b->lu_tab.dev, &b->sv_tab.dev, &b->dinv,
                     &b->flags, &b->pk, &b->sk, &b->fptab, &b->fpout})
     d->release();
   if (b->pk_host) (void)hipHostFree(b->pk_host);

@@ -554,6 +554,98 @@ __global__ __launch_bounds__(256) void k_panel_rank(T *__restrict__ Mall, int64_
     }
 }
 
+// LU with partial pivoting (largest |re| + |im|, lowest row on ties, as the
+// leaves) of small matrices held whole in LDS: a persistent grid whose
+// workgroups take matrices b = blockIdx.x, blockIdx.x + gridDim.x, ... of a
+// grouped table (order n_b <= NP), each factored column by column -- pivot
+// search over the column, row exchange, multipliers, rank-1 update of the
+// trailing block -- with the rows and columns spread over the 256 threads.
+// Pivots (LAPACK order) to ipiv_all + b pstride, info_all[b] = 1 + the first
+// column with an exact zero pivot (or 0).
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void k_lu_small(const GrpMat *__restrict__ grp, int nodes,
+                                                  int count, int64_t pstride,
+                                                  int32_t *__restrict__ ipiv_all,
+                                                  int32_t *__restrict__ info_all) {
+  using Tr = cplx_traits<T>;
+  using PK = PivKey<T>;
+  static_assert(NP <= 256, "one row per thread in the pivot search");
+  __shared__ T sM[NP][NP + 1];
+  __shared__ T sl[NP];
+  __shared__ uint64_t s_key[4];
+  __shared__ int s_piv[NP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int b = blockIdx.x; b < count; b += gridDim.x) {
+    const MatRef<T> mr = mat_of<T>(grp, nodes, static_cast<T *>(nullptr), 0, 0, 0, b);
+    T *M = mr.M;
+    const int64_t ld = mr.ld;
+    const int n = static_cast<int>(mr.n);
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e / n, j = e - i * n;
+      sM[i][j] = M[i * ld + j];
+    }
+    __syncthreads();
+    int info = 0;
+    for (int c = 0; c < n; ++c) {
+      // pivot search: thread t looks at row c + t
+      const int r = c + tid;
+      uint64_t k = (r < n) ? PK::key(sM[r][c], r) : 0;
+      uint64_t wk = wave_max_u64(k);
+      if (lane == 0) s_key[wave] = wk;
+      __syncthreads();
+      uint64_t best = s_key[0];
+      for (int w = 1; w < 4; ++w) best = s_key[w] > best ? s_key[w] : best;
+      int p = c;
+      if constexpr (PK::kPacked) {
+        if (best != 0) p = static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(best));
+      } else if (best != 0) {
+        // ties in value: the lowest row among the candidates holding the maximum
+        __syncthreads();
+        const uint64_t ik = (k == best && k != 0) ? 0xFFFFFFFFull - static_cast<uint32_t>(r) : 0;
+        wk = wave_max_u64(ik);
+        if (lane == 0) s_key[wave] = wk;
+        __syncthreads();
+        uint64_t bi = s_key[0];
+        for (int w = 1; w < 4; ++w) bi = s_key[w] > bi ? s_key[w] : bi;
+        p = static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(bi));
+      }
+      if (best == 0 && info == 0) info = c + 1;  // (no comparable entry: keep the diagonal row)
+      if (tid == 0) s_piv[c] = p;
+      // exchange rows c and p
+      if (p != c)
+        for (int j = tid; j < n; j += 256) {
+          const T x = sM[c][j];
+          sM[c][j] = sM[p][j];
+          sM[p][j] = x;
+        }
+      __syncthreads();
+      const T piv = sM[c][c];
+      const bool zero = piv.x == 0 && piv.y == 0;
+      if (zero && info == 0) info = c + 1;
+      const T inv = zero ? czero<T>() : Tr::recip(piv);
+      if (r > c && r < n) {
+        const T l = Tr::mul(sM[r][c], inv);
+        sl[r] = l;
+        sM[r][c] = l;
+      }
+      __syncthreads();
+      // rank-1 update of the trailing block: thread (tr, tc) = (tid / 16, tid % 16)
+      for (int i = c + 1 + (tid >> 4); i < n; i += 16) {
+        const T l = sl[i];
+        for (int j = c + 1 + (tid & 15); j < n; j += 16) sM[i][j] = Tr::fms(sM[i][j], l, sM[c][j]);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e / n, j = e - i * n;
+      M[i * ld + j] = sM[i][j];
+    }
+    for (int i = tid; i < n; i += 256) ipiv_all[b * pstride + i] = s_piv[i];
+    if (tid == 0) info_all[b] = info;
+    __syncthreads();  // (sM, s_piv reused by the next matrix)
+  }
+}
+
 // Register layout shared by the 64 x 64 triangular kernels below: 256 threads,
 // thread (ti, tj) = (tid / 16, tid % 16) holds the 16 entries (ti + 16a,
 // tj + 16c), a, c < 4, and wave wv = tid / 64 holds rows ti in [4 wv, 4 wv + 4)
@@ -867,6 +959,21 @@ void trsm_small(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, 
 }
 template void trsm_small<z64>(hipStream_t, z64 *, int64_t, int64_t, int32_t, int64_t, int, int);
 template void trsm_small<c64>(hipStream_t, c64 *, int64_t, int64_t, int32_t, int64_t, int, int);
+
+template <> int lu_small_max_order<z64>() { return 64; }
+template <> int lu_small_max_order<c64>() { return 128; }
+
+template <typename T>
+void lu_small(hipStream_t s, const GrpMat *grp, int nodes, int count, int64_t pstride,
+              int32_t *ipiv, int32_t *info) {
+  if (count <= 0) return;
+  // persistent: at most four workgroups per compute unit, each looping over matrices
+  const unsigned grid = static_cast<unsigned>(std::min(count, 1024));
+  hipLaunchKernelGGL((k_lu_small<T, (sizeof(T) == 16 ? 64 : 128)>), dim3(grid), dim3(256), 0, s,
+                     grp, nodes, count, pstride, ipiv, info);
+}
+template void lu_small<z64>(hipStream_t, const GrpMat *, int, int, int64_t, int32_t *, int32_t *);
+template void lu_small<c64>(hipStream_t, const GrpMat *, int, int, int64_t, int32_t *, int32_t *);
 
 template <typename T>
 void panel_update(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,

@@ -91,6 +91,15 @@ bool leaf_lu(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int
 // Largest leaf width for `rows` remaining rows.
 template <typename T> int leaf_max_width(int64_t rows);
 
+// Whole LU with partial pivoting of `count` small matrices (grouped table,
+// order n_b <= lu_small_max_order<T>(): 128 for complex64, 64 for complex128),
+// each held in LDS by one workgroup of a persistent grid.  Pivots to
+// ipiv + b pstride, info[b] as leaf_lu.
+template <typename T> int lu_small_max_order();
+template <typename T>
+void lu_small(hipStream_t s, const GrpMat *grp, int nodes, int count, int64_t pstride,
+              int32_t *ipiv, int32_t *info);
+
 // Rows [r0, r0+kb) swapped with ipiv[r0..r0+kb) over columns [0, clo) and [chi, n).
 template <typename T>
 void laswp_outside(hipStream_t s, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,

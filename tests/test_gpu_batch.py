@@ -37,6 +37,9 @@ def small_batch():
                              c=0.05, seed=77, name="tie"))
     ps.append(pg.make_pencil(128, m=12, inside=6, inside_radius=0.9, outside_r=(1.3, 10.0),
                              center=1.0, radius=1.0, nodes=16, c=0.05, seed=78, name="n128"))
+    # padded to 64: factored whole in LDS in either precision (128 and below in complex64)
+    ps.append(pg.make_pencil(40, m=10, inside=4, inside_radius=0.8, outside_r=(1.3, 10.0),
+                             center=0.3j, radius=1.0, nodes=16, c=0.05, seed=79, name="n40"))
     return ps
 
 
