@@ -100,7 +100,8 @@ def time_form(form, p, A, B, V, steps, warmup):
                 "err": last.err, "count": len(last.lam), "sweeps": last.sweeps,
                 "errs": [float("%.3g" % e) for e in last.errs],
                 "phases_ms": {k: round(v, 3) for k, v in last.times.items()},
-                "lu_gemm": last.lu_gemm, "hbm": hbm_report(last.hbm)}
+                "lu_gemm": last.lu_gemm, "hbm": hbm_report(last.hbm),
+                "contraction": [float("%.3g" % c) for c in last.contraction]}
     finally:
         plan.close()
 
@@ -213,7 +214,9 @@ def time_standin(ks, steps, warmup):
             finally:
                 plan.close()
             row[form] = {"ms": ms, "iters": r.iters, "count": len(r.lam), "err": r.err,
-                         "ok": r.flag == 1 and r.err <= 1e-10 and len(r.lam) == g["s"]}
+                         "ok": r.flag == 1 and r.err <= 1e-10 and len(r.lam) == g["s"],
+                         "errs": [float("%.3g" % e) for e in r.errs], "sweeps": r.sweeps,
+                         "contraction": [float("%.3g" % c) for c in r.contraction]}
         log("[bench] stand-in %s: %s" % (name, row))
         out[name] = row
         del dA, dB, dV

@@ -183,6 +183,10 @@ typedef struct {
   double lu_gemm_flops;
   /* with opts.profile = 1: the bandwidth-bound kernels of this call, per class */
   feast_kprof hbm[FEAST_K_CLASSES];
+  /* mixed form: ||d_1||_F / ||Y_0||_F of each filter's first FP64 correction
+     (about the forward error of the complex64 solves, u32 cond(z_j B - A);
+     0 for a filter without corrections) */
+  double contraction[FEAST_MAX_HISTORY];
 } feast_info;
 
 /* GFEAST (Algorithm 5) with the subspace size fixed to m and a caller-supplied

@@ -76,7 +76,8 @@ class Info(C.Structure):
                 ("t_project_ms", C.c_double), ("t_host_eig_ms", C.c_double),
                 ("t_ritz_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("lu_gemm_launches", C.c_int32), ("lu_gemm_ms", C.c_double),
-                ("lu_gemm_flops", C.c_double), ("hbm", KProf * len(K_CLASSES))]
+                ("lu_gemm_flops", C.c_double), ("hbm", KProf * len(K_CLASSES)),
+                ("contraction", C.c_double * MAX_HISTORY)]
 
 
 class SearchInfo(C.Structure):
@@ -301,6 +302,7 @@ class SolveResult:
     status: int
     lu_gemm: dict
     hbm: dict = dataclasses.field(default_factory=dict)
+    contraction: list = dataclasses.field(default_factory=list)
 
 
 class Plan:
@@ -428,7 +430,8 @@ class Plan:
                                 "flops": info.lu_gemm_flops},
             hbm={name: {"launches": info.hbm[i].launches, "ms": info.hbm[i].ms,
                         "bytes": info.hbm[i].bytes}
-                 for i, name in enumerate(K_CLASSES) if info.hbm[i].launches > 0})
+                 for i, name in enumerate(K_CLASSES) if info.hbm[i].launches > 0},
+            contraction=list(info.contraction[:info.filters]))
 
     # -- Search (Algorithm 4) ----------------------------------------------
     def search(self, A, B, Ypool, p: int, alpha: float = 1.5, tau: float = 1e-3):

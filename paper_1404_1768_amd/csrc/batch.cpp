@@ -1265,11 +1265,14 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       parallel_for(static_cast<int>(act.size()), nthreads, [&](int i) {
         const int p = act[i];
         const int64_t m = b->m[p];
+        const feast_contour &cp = b->sub[p]->c;
+        const cd gam(cp.center.re, cp.center.im);
         qz[p] = feast_host::reduced_eig(m, reinterpret_cast<const cd *>(hAt[p].data()), m,
                                         reinterpret_cast<const cd *>(hBt[p].data()), m,
                                         reinterpret_cast<cd *>(st[p].alpha.data()),
                                         reinterpret_cast<cd *>(st[p].beta.data()),
-                                        reinterpret_cast<cd *>(st[p].Yh.data()), m, 1);
+                                        reinterpret_cast<cd *>(st[p].Yh.data()), m, 1, &gam,
+                                        cp.radius);
       });
       inf.t_host_eig_ms += te.ms();
       for (int p : act)

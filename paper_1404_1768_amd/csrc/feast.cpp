@@ -423,6 +423,16 @@ void solve_nodes_mixed(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, i
     ktimed(p, FEAST_K_Z2C, 24.0 * n * ldY,
            [&]() { feast::z_to_c(s, T2, ldY, 0, n, ldY, 1, Yc, ldY, 0, rn, rcnt); });
     plan_trsolve<c64>(p, s, Yc, m, ldY, sY, 0);
+    if (sweep == 0) {
+      // the first correction relative to the solution it corrects: about the
+      // forward error of the complex64 solves, u32 cond(z_j B - A)
+      feast::fro2_c(s, Yc, ldY, n, ldY, rn + 8, rn + 1);
+      feast::fro2_batched(s, Y, ldY, 0, n, ldY, 1, rn + 8, rn + 2);
+      if (p->hrn) {
+        HIPCHK(hipMemcpyAsync(p->hrn, rn, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        p->rho_pending = true;
+      }
+    }
     ktimed(p, FEAST_K_C2Z, 40.0 * n * ldY,
            [&]() { feast::add_c_to_z(s, Yc, ldY, 0, n, ldY, 1, Y, ldY, 0, rn, rcnt); });
     p->last_sweeps = sweep + 1;
@@ -623,6 +633,10 @@ int project_finish(feast_plan *p, feast_z *hAt, feast_z *hBt) {
   return FEAST_OK;
 }
 
+int host_threads() {
+  return static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+}
+
 bool bad_contour(const feast_contour *c) {
   return !c || !(c->radius > 0.0) || !std::isfinite(c->radius) || !std::isfinite(c->center.re) ||
          !std::isfinite(c->center.im) || c->nodes < 1 || c->nodes > 1024 ||
@@ -676,7 +690,7 @@ int feast_reduced_eig(int64_t t, const feast_z *hAt, int64_t lda, const feast_z 
   if (t < 0 || (t > 0 && (!hAt || !hBt || !halpha || !hbeta || !hY)) || lda < t || ldb < t || ldy < t)
     return FEAST_EINVAL;
   try {
-    const int nt = static_cast<int>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    const int nt = host_threads();
     const int rc = feast_host::reduced_eig(t, reinterpret_cast<const cd *>(hAt), lda,
                                            reinterpret_cast<const cd *>(hBt), ldb,
                                            reinterpret_cast<cd *>(halpha),
@@ -731,6 +745,7 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
     HIPCHK(hipMemcpy(p->dw.p, p->hw.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p->dwc.p, wc.data(), sizeof(z64) * p->N, hipMemcpyHostToDevice));
     ensure_workspace(p);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&p->hrn), 4 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming));
@@ -752,6 +767,7 @@ int feast_plan_destroy(feast_plan *p) {
   if (p->s) (void)hipStreamSynchronize(p->s);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->kev) (void)hipEventDestroy(e);
+  if (p->hrn) (void)hipHostFree(p->hrn);
   for (hipStream_t st : {p->side, p->aux})
     if (st) {
       (void)hipStreamSynchronize(st);
@@ -863,12 +879,23 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     // without halving e(k), the solves limit the accuracy (their forward error
     // is the backward error times cond(z_j B - A)): every later filter then
     // refines each node until its backward error reaches refine_tol.
+    // The number of corrections of a refined filter starts at one; once a
+    // filter's first correction has measured the contraction rho = ||d_1|| /
+    // ||Y_0|| (about u32 cond(z_j B - A)), later filters take the s that makes
+    // the predicted error rho^(s+1) at most eps / 10 (at most max_sweeps).
     constexpr double kRefineFrom = 1e-4;
-    const int sweeps = p->mixed() ? 1 : 0;
+    int sweeps = p->mixed() ? 1 : 0;
     auto sweeps_for = [&](double e_last, bool known) {
       if (!p->mixed()) return 0;
       if (known && !(e_last <= kRefineFrom)) return 0;
       return sweeps;
+    };
+    auto predict_sweeps = [&](double rho) {
+      if (!p->mixed() || !(rho > 0.0)) return;
+      const double goal = 0.1 * std::max(p->o.eps, 1e-15);
+      int sw = p->o.max_sweeps;
+      if (rho < 0.5) sw = static_cast<int>(std::ceil(std::log(goal) / std::log(rho))) - 1;
+      sweeps = std::max(1, std::min(sw, std::max(1, p->o.max_sweeps)));
     };
     int sweeps_now = sweeps;
     bool verify = false;
@@ -930,8 +957,13 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       const double launch_ms = tf.ms();
       // reduced eigenproblem on the host
       Timer te;
-      if (feast_reduced_eig(m, hAt.data(), m, hBt.data(), m, halpha.data(), hbeta.data(), hY.data(),
-                            m) != FEAST_OK)
+      // (eigenvectors only for eigenvalues inside the circle: nothing else is selected)
+      if (feast_host::reduced_eig(m, reinterpret_cast<const cd *>(hAt.data()), m,
+                                  reinterpret_cast<const cd *>(hBt.data()), m,
+                                  reinterpret_cast<cd *>(halpha.data()),
+                                  reinterpret_cast<cd *>(hbeta.data()),
+                                  reinterpret_cast<cd *>(hY.data()), m, host_threads(), &gamma,
+                                  rho) != 0)
         return fail(p, FEAST_ENUMERIC, "reduced QZ did not converge");
       inf.t_host_eig_ms += te.ms();
       Timer tr;
@@ -1040,6 +1072,14 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       }
       HIPCHK(hipStreamSynchronize(s));
       inf.t_filter_ms += launch_ms + tw.ms();
+      if (p->rho_pending) {  // the filter's first correction relative to its solution
+        p->rho_pending = false;
+        const double rms = std::sqrt(p->hrn[0] / (static_cast<double>(n) * m));
+        const int e = (rms > 0.0 && std::isfinite(rms)) ? std::ilogb(rms) : 0;
+        const double rho = p->hrn[2] > 0.0 ? std::ldexp(std::sqrt(p->hrn[1] / p->hrn[2]), e) : 0.0;
+        if (inf.filters >= 1 && inf.filters <= FEAST_MAX_HISTORY) inf.contraction[inf.filters - 1] = rho;
+        predict_sweeps(rho);
+      }
       // QR step and the next reduced pencil (after the side stream is done with U_1)
       {
         Timer t;

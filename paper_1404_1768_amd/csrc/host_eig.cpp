@@ -442,7 +442,7 @@ inline void axpy(cd a, const cd *x, cd *y, int64_t n) {
 //      through the reflectors.  Quality is judged downstream anyway: every
 //      Ritz pair's residual (eq. 5-1) is computed with the original A and B.
 int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *alpha, cd *beta,
-            cd *Y, int64_t ldy, int nthreads) {
+            cd *Y, int64_t ldy, int nthreads, const cd *want_center, double want_radius) {
   // threads: about one per 16 columns (at t = 160: up to 10)
   const int nt = std::max(1, std::min<int>(nthreads, static_cast<int>((t + 15) / 16)));
   Mat H(t);
@@ -580,6 +580,10 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
         if (failed.load(std::memory_order_relaxed)) return;
         std::this_thread::sleep_for(std::chrono::microseconds(20));
       }
+      if (want_center && !(std::abs(alpha[j] - *want_center) < want_radius)) {
+        for (int64_t i = 0; i < t; ++i) Y[i * ldy + j] = 0.0;  // (not wanted)
+        continue;
+      }
       eigvec(j, lu, v, sw);
     }
   };
@@ -666,7 +670,8 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
 }  // namespace
 
 int reduced_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd *alpha,
-                cd *beta, cd *Y, int64_t ldy, int nthreads) {
+                cd *beta, cd *Y, int64_t ldy, int nthreads, const cd *want_center,
+                double want_radius) {
   if (t <= 0) return 0;
   // Bt upper triangular to rounding and well conditioned on its diagonal:
   // the standard problem Bt^{-1} At is as accurate as the pencil and cheaper.
@@ -687,7 +692,7 @@ int reduced_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb,
   // products of length n, far below 1e-12 of the whole; the diagonal ratio is
   // a lower bound on the condition number of the triangle)
   if (finite && dmax > 0.0 && dmin >= 1e-4 * dmax && low2 <= 1e-24 * bn2)
-    return std_eig(t, At, lda, Bt, ldb, alpha, beta, Y, ldy, nthreads);
+    return std_eig(t, At, lda, Bt, ldb, alpha, beta, Y, ldy, nthreads, want_center, want_radius);
   return qz_eig(t, At, lda, Bt, ldb, alpha, beta, Y, ldy, nthreads);
 }
 

@@ -9,10 +9,15 @@ namespace feast_host {
 // All eigenpairs of the t x t pencil (At, Bt) (row-major inputs) by complex QZ.
 // alpha/beta: t entries; Y: right eigenvectors as columns (row-major, ldy),
 // unit 2-norm.  Returns 0, -1 (non-finite input) or -2 (no convergence).
+// With want_center set, the standard-form path (triangular Bt) computes only
+// the eigenvectors of eigenvalues strictly inside the circle
+// |lambda - *want_center| < want_radius and leaves the other columns zero
+// (Algorithm 5 selects nothing outside the circle).
 int reduced_eig(int64_t t, const std::complex<double> *At, int64_t lda,
                 const std::complex<double> *Bt, int64_t ldb, std::complex<double> *alpha,
                 std::complex<double> *beta, std::complex<double> *Y, int64_t ldy,
-                int nthreads);
+                int nthreads, const std::complex<double> *want_center = nullptr,
+                double want_radius = 0.0);
 
 // Nodes z_j and weights w_j of the circle quadrature (rule 0: trapezoid with
 // half-offset angles; rule 1: Gauss-Legendre as in eq. 8-4).

@@ -230,7 +230,8 @@ __global__ __launch_bounds__(256) void k_col_part(const z64 *__restrict__ X, int
   }
 }
 
-__global__ __launch_bounds__(256) void k_fro_part(const z64 *__restrict__ X, int64_t ld, int64_t sX,
+template <typename T>
+__global__ __launch_bounds__(256) void k_fro_part(const T *__restrict__ X, int64_t ld, int64_t sX,
                                                   int64_t n, int64_t m, double *__restrict__ part) {
   // part[b * gridDim.x + blockIdx.x]
   __shared__ double red[256];
@@ -239,8 +240,8 @@ __global__ __launch_bounds__(256) void k_fro_part(const z64 *__restrict__ X, int
   const int64_t total = n * m;
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < total; i += 256ll * gridDim.x) {
     const int64_t row = i / m, col = i % m;
-    const z64 x = X[b * sX + row * ld + col];
-    s += x.x * x.x + x.y * x.y;
+    const T x = X[b * sX + row * ld + col];
+    s += static_cast<double>(x.x) * x.x + static_cast<double>(x.y) * x.y;
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -804,9 +805,18 @@ void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, d
 void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
                   int32_t batch, double *part, double *out) {
   const int blocks = (batch == 1 && n * m > (1 << 22)) ? 1024 : 64;
-  hipLaunchKernelGGL(k_fro_part, dim3(blocks, batch), dim3(256), 0, s, X, ld, sX, n, m, part);
+  hipLaunchKernelGGL((k_fro_part<z64>), dim3(blocks, batch), dim3(256), 0, s, X, ld, sX, n, m,
+                     part);
   hipLaunchKernelGGL(k_sum_rows, dim3(static_cast<unsigned>((batch + 255) / 256)), dim3(256), 0, s,
                      part, static_cast<int64_t>(blocks), static_cast<int64_t>(batch), out);
+}
+
+void fro2_c(hipStream_t s, const c64 *X, int64_t ld, int64_t n, int64_t m, double *part,
+            double *out) {
+  const int blocks = n * m > (1 << 22) ? 1024 : 64;
+  hipLaunchKernelGGL((k_fro_part<c64>), dim3(blocks, 1), dim3(256), 0, s, X, ld, 0, n, m, part);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, part, static_cast<int64_t>(blocks),
+                     static_cast<int64_t>(1), out);
 }
 
 void fingerprint(hipStream_t s, const GrpMat *tab, int count, GrpMat a0, GrpMat a1,

@@ -230,6 +230,10 @@ void col_norms2(hipStream_t s, const z64 *X, int64_t ld, int64_t n, int64_t t, d
 // part: workspace of max(64 * batch, 1024) doubles.
 void fro2_batched(hipStream_t s, const z64 *X, int64_t ld, int64_t sX, int64_t n, int64_t m,
                   int32_t batch, double *part, double *out);
+// out[0] = sum |X|^2 of one complex64 n x m block (accumulated in FP64);
+// part: workspace of 1024 doubles.
+void fro2_c(hipStream_t s, const c64 *X, int64_t ld, int64_t n, int64_t m, double *part,
+            double *out);
 
 // Content fingerprints of `count` n_b x n_b complex128 matrices (entry b of
 // the device table tab, or a0 / a1 by value when tab is null and count <= 2)

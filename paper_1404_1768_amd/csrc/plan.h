@@ -94,7 +94,10 @@ struct feast_plan {
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
   DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
-  DevBuf rn;  // mixed form: ||R||_F^2 at rn[0] (scale of the complex64 solves), partials from rn[8]
+  DevBuf rn;  // mixed form: ||R||_F^2 at rn[0] (scale of the complex64 solves), ||d_1||^2 and
+              // ||Y_0||^2 of the first correction at rn[1], rn[2]; partials from rn[8]
+  double *hrn = nullptr;   // page-locked copy of rn[0..3) (read after the stream is idle)
+  bool rho_pending = false;  // hrn holds a filter's first-correction norms not yet read
   DevBuf adj, adj_piv, adj_info, adj_inv;  // adjoint solves (allocated on first use)
   DevBuf cirr_w;                           // Block_CIRR moment weights (g x N)
   std::string err;
@@ -167,6 +170,8 @@ void project_device(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int6
 // Copy At, Bt to the host and check the Cholesky QR flags (synchronises).
 int project_finish(feast_plan *p, feast_z *hAt, feast_z *hBt);
 bool bad_contour(const feast_contour *c);
+// Host threads for the reduced eigensolver (at most 16).
+int host_threads();
 
 // Runs f(), turning HIP and allocation failures into FEAST status codes.
 template <typename F> int guarded(feast_plan *p, F &&f) {
