@@ -252,15 +252,26 @@ TABLE1 = [
 ]
 
 
-def _sparse_real(rng, n: int, nnz: int, kind: str) -> np.ndarray:
+def _pattern(rng, n: int, k: int, band: Optional[int]):
+    """``k`` random positions (i, j): anywhere, or within ``|i - j| <= band``."""
+    i = rng.integers(0, n, k)
+    if band is None:
+        return i, rng.integers(0, n, k)
+    j = np.clip(i + rng.integers(-band, band + 1, k), 0, n - 1)
+    return i, j
+
+
+def _sparse_real(rng, n: int, nnz: int, kind: str, band: Optional[int] = None) -> np.ndarray:
     """A dense array holding a real sparse matrix with about ``nnz`` non-zeros
     of the given structure: unsym, symind (symmetric indefinite), skew,
     spd (symmetric, diagonally dominant, positive diagonal), spsd (as spd with
-    a tenth of the rows and columns zero, hence singular)."""
+    a tenth of the rows and columns zero, hence singular).  ``band``: the
+    off-diagonal non-zeros lie within that distance of the diagonal (else
+    anywhere)."""
     M = np.zeros((n, n))
     if kind == "unsym":
         k = max(nnz - n, 0)
-        i, j = rng.integers(0, n, k), rng.integers(0, n, k)
+        i, j = _pattern(rng, n, k, band)
         M[i, j] = rng.normal(size=k)
         M[np.arange(n), np.arange(n)] += rng.normal(size=n) + 2.0 * rng.choice([-1, 1], n)
         return M
@@ -268,7 +279,7 @@ def _sparse_real(rng, n: int, nnz: int, kind: str) -> np.ndarray:
     if kind == "spsd":  # the zeroed tenth of the rows and columns removes about 19%
         off = int(off / 0.81)
     half = max(off // 2, 0)
-    i, j = rng.integers(0, n, half), rng.integers(0, n, half)
+    i, j = _pattern(rng, n, half, band)
     keep = i != j
     i, j = np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
     U = np.zeros((n, n))
@@ -287,13 +298,16 @@ def _sparse_real(rng, n: int, nnz: int, kind: str) -> np.ndarray:
     return M
 
 
-def sparse_standin(k: int, m: int = 40, seed: int = BASE_SEED + 100):
+def sparse_standin(k: int, m: int = 40, seed: int = BASE_SEED + 100, banded: bool = False):
     """Stand-in for problem k (1..7) of Table 1: real A, B of its order, number
     of non-zeros and structure (random values and pattern), returned dense as
-    complex128, with a complex Gaussian start block V (n x m)."""
+    complex128, with a complex Gaussian start block V (n x m).  ``banded``:
+    the off-diagonal non-zeros of both lie within a band of half-width
+    ``ceil(nnz_A / n)`` around the diagonal instead of anywhere."""
     name, n, nnz_a, nnz_b, ka, kb = TABLE1[k - 1]
     ra, rb, rv = (np.random.default_rng(s) for s in np.random.SeedSequence(seed + k).spawn(3))
-    A = _sparse_real(ra, n, nnz_a, ka).astype(np.complex128)
-    B = _sparse_real(rb, n, nnz_b, kb).astype(np.complex128)
+    band = int(math.ceil(nnz_a / n)) if banded else None
+    A = _sparse_real(ra, n, nnz_a, ka, band).astype(np.complex128)
+    B = _sparse_real(rb, n, nnz_b, kb, band).astype(np.complex128)
     V = _cgauss(rv, (n, m), 1.0)
     return name, A, B, V
