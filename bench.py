@@ -224,6 +224,59 @@ def time_standin(ks, steps, warmup):
             "problems": out}
 
 
+def time_sparse_lu(ks):
+    """Sparse LU against the dense MFMA LU at Table 1's orders.  For each
+    stand-in, with its non-zeros placed at random or within a band of
+    half-width ceil(nnz(A)/n): SuperLU (scipy, COLAMD ordering, one host
+    thread) factors z_1 B - A for the first Gauss-Legendre node and solves
+    for the m = 40 columns of V; its fill (nnz(L) + nnz(U)) / n^2 is
+    reported.  The dense path's factor phase of a complete FP64 solve with 16
+    nodes (all nodes in one pass) is divided by 16 for the per-node figure."""
+    import numpy as np
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    import torch
+    import pencilgen as pg
+    import paper_1404_1768_amd as fm
+    with open(os.path.join(ROOT, "tests", "golden", "standin_contours.json")) as f:
+        golden = json.load(f)
+    out = {}
+    for k in ks:
+        g = golden[str(k)]
+        c = complex(*g["center"])
+        z = complex(fm.feast_nodes(c, g["radius"], 16, fm.GAUSS_LEGENDRE)[0][0])
+        row = {"n": g["n"]}
+        for pattern, banded in (("random", False), ("banded", True)):
+            name, A, B, V = pg.sparse_standin(k, banded=banded)
+            M = sp.csc_matrix(z * B - A)
+            t0 = time.perf_counter()
+            lu = spla.splu(M)
+            t_fac = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            lu.solve(V)
+            t_sol = time.perf_counter() - t0
+            fill = (lu.L.nnz + lu.U.nnz) / float(g["n"]) ** 2
+            dA, dB, dV = (torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0") for x in (A, B, V))
+            plan = fm.Plan(g["n"], 40, c, g["radius"], 16, rule=fm.GAUSS_LEGENDRE, eps=1e-10,
+                           prec=fm.FP64, profile=True)
+            try:
+                plan.solve(dA, dB, dV)          # warm-up
+                plan.invalidate()
+                r = plan.solve(dA, dB, dV)
+            finally:
+                plan.close()
+            row[pattern] = {"superlu_factor_ms": round(t_fac * 1e3, 2),
+                            "superlu_solve40_ms": round(t_sol * 1e3, 2),
+                            "fill": round(fill, 4), "nnz_M": int(M.nnz),
+                            "dense_gpu_factor_ms_per_node": round(r.times["factor"] / 16, 3)}
+            del dA, dB, dV, A, B, M, lu
+            torch.cuda.empty_cache()
+        log("[bench] sparse LU %s: %s" % (name, row))
+        out[name] = row
+    return {"workload": "Table 1 stand-ins, one node z_1 (Gauss-Legendre N=16); SuperLU on one "
+                        "host thread vs the dense GPU LU (FP64, per node)", "problems": out}
+
+
 def time_adjoint(steps, warmup):
     """The adjoint form on its workload: n = 2048, 40 eigenvalues in the unit
     circle, N = 32, m = 64, FP64.  One step = the forward solve (factorisation
@@ -386,6 +439,9 @@ def main():
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a PMC run")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the n=8000, m=256 mixed-precision workload (key 'large')")
+    ap.add_argument("--sparse-lu", action="store_true",
+                    help="add the SuperLU vs dense GPU LU comparison at Table 1's orders "
+                         "(key 'sparse_lu'; about a minute of host time)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the path shards over quadrature nodes across GPUs "
@@ -459,6 +515,9 @@ def main():
                  "mixed": r}
         del lA, lB, lV
         torch.cuda.empty_cache()
+    sparse_lu = None
+    if args.sparse_lu:
+        sparse_lu = time_sparse_lu(range(1, 8))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p)
@@ -473,7 +532,7 @@ def main():
         "forms": forms, "roofline": roof, "hbm": b["hbm"], "cpu_baseline": cpu,
         "batched": batched,
         "search": search, "cirr": cirr, "adjoint": adjoint, "standin": standin,
-        "large": large,
+        "large": large, "sparse_lu": sparse_lu,
     }
     print(json.dumps(out), flush=True)
 

@@ -214,13 +214,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin) {
         cr[a][b][r] = 0;
         ci[a][b][r] = 0;
         if (SUB) {
+          // every lane loads (element (0, 0) stands in outside C) and the
+          // bound selects the value afterwards: a load under a branch would be
+          // waited for inside it, one memory round trip per element
           const int64_t row = m0 + wm * WM + a * 16 + Ops::out_row(lane, r);
           const int64_t col = n0 + wn * WN + b * 16 + (lane & 15);
-          if (row < d.M && col < d.N) {
-            const T o = SHF ? d.C0[bidx * d.sC0 + row * d.ldc0 + col] : C[row * d.ldc + col];
-            cr[a][b][r] = o.x;
-            ci[a][b][r] = o.y;
-          }
+          const bool in = row < d.M && col < d.N;
+          const int64_t rr = in ? row : 0, cc = in ? col : 0;
+          const T o = SHF ? d.C0[bidx * d.sC0 + rr * d.ldc0 + cc] : C[rr * d.ldc + cc];
+          cr[a][b][r] = in ? o.x : real(0);
+          ci[a][b][r] = in ? o.y : real(0);
         }
       }
 
@@ -437,10 +440,11 @@ template <typename T> constexpr bool kM3 = sizeof(T) == 8;
 
 // Waves per SIMD the register allocation must leave room for (512 registers a
 // lane are shared by the waves of a SIMD): the complex64 64 x 64 tile fits
-// three workgroups per compute unit in LDS, and at 168 registers three also
-// fit the register file; the complex128 64 x 64 tiles and the complex64
-// 128 x 64 tiles fit two at 256 (left to themselves they take over 300, one
-// wave per SIMD).  None of them spills; the complex128 128 x 64 tile would.
+// three workgroups per compute unit in LDS at BK = 16 and at 168 registers
+// (at BK = 8, the trailing update, it takes 121 registers and runs four); the
+// complex128 64 x 64 tiles and the complex64 128 x 64 tiles fit two at 256
+// (left to themselves they take over 300, one wave per SIMD).  None of them
+// spills; the complex128 128 x 64 tile would.
 template <typename T, int BM>
 constexpr int kWaves = BM != 64 ? (sizeof(T) == 8 ? 2 : 1) : (sizeof(T) == 8 ? 3 : 2);
 
@@ -544,11 +548,15 @@ void launch_cfg(hipStream_t s, const GemmArgs<T> &d, int ta, bool update = false
   const bool sub = d.splits == 1 && d.alpha.x == -1.0 && d.alpha.y == 0.0 && d.beta.x == 1.0 &&
                    d.beta.y == 0.0;
   if (ta == 0) {
-    if (sub && update)  // (FP64 update: BK = 8 keeps two workgroups per compute unit)
-      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, (sizeof(T) == 16 ? 8 : BK), true>), grid,
-                         dim3(256), 0, s, d, padded);
-    else if (sub)
-      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, BK>), grid, dim3(256), 0, s, d, padded);
+    // (BK = 8: two workgroups per compute unit in FP64, four in complex64; the
+    // 128-row tiles take this instance for every C -= A B, which at BK = 16
+    // would spill in complex64)
+    if (sub && (update || BM > 64))
+      hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, 8, true>), grid, dim3(256), 0, s, d, padded);
+    else if (sub) {
+      if constexpr (BM == 64)
+        hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, true, BK>), grid, dim3(256), 0, s, d, padded);
+    }
     else
       hipLaunchKernelGGL((k_gemm<T, BM, BN, 0, false, BK>), grid, dim3(256), 0, s, d, padded);
   } else {
