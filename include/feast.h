@@ -187,6 +187,8 @@ typedef struct {
      (about the forward error of the complex64 solves, u32 cond(z_j B - A);
      0 for a filter without corrections) */
   double contraction[FEAST_MAX_HISTORY];
+  /* feast_solve_csr: lower and upper bandwidth of the reordered pencil */
+  int32_t band_kl, band_ku;
 } feast_info;
 
 /* GFEAST (Algorithm 5) with the subspace size fixed to m and a caller-supplied
@@ -213,6 +215,55 @@ int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z 
                 int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *hLambda,
                 feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, double *err,
                 int32_t *flag, feast_info *info);
+
+/* ---------------------------------------------------------------------------
+ * Sparse pencils (the problems of Table 1 are sparse): A and B in compressed
+ * sparse row form, factored as band matrices
+ * ------------------------------------------------------------------------- */
+
+/* An n x n sparse matrix in CSR form, every array on the device: row i's
+ * entries are col[rowptr[i] .. rowptr[i+1]) with values val[...] (complex128).
+ * Columns within a row in any order, each at most once; rowptr[0] = 0 and
+ * rowptr[n] = nnz < 2^31. */
+typedef struct feast_csr {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *rowptr;  /* n + 1 entries */
+  const int32_t *col;     /* nnz entries, 0 <= col < n */
+  const feast_z *val;     /* nnz entries */
+} feast_csr;
+
+/* GFEAST (Algorithm 5) as feast_solve, for a pencil given in CSR form.  The
+ * shifted systems of eq. (4-4) are the same; their storage and factorisation
+ * differ: the host orders the rows and columns of the union pattern of A and B
+ * (from its pattern only) by reverse Cuthill-McKee, or keeps the natural order
+ * where that is at least as narrow, and every node's z_j B - A
+ * in that order is factored on the device as a band matrix with partial
+ * pivoting (row interchanges within the kl subdiagonals, U widened to kl + ku
+ * superdiagonals); the filter's node solves are band triangular solves, and
+ * B V, A U_1, B U_1 are sparse x dense products.  Eigenvalues, residuals and
+ * eigenvectors (in the caller's row order) are those of the dense pencil.
+ * Outputs and stopping rules as feast_solve; info->band_kl/band_ku report the
+ * bandwidths and info->t_factor_ms includes the host's symbolic work (pattern
+ * copies, ordering).  The band factors are recomputed on every call.
+ * Errors: FEAST_EINVAL for a mixed plan (band factors are FP64 only), a
+ * malformed pattern (message names the fault), or kl + ku > 63 after
+ * reordering (the band kernels keep their windows in LDS; such a pencil is
+ * factored densely by feast_solve); FEAST_SINGULAR for an exact zero pivot.
+ * Synchronises the stream. */
+int feast_solve_csr(feast_plan *plan, const feast_csr *A, const feast_csr *B,
+                    const feast_z *dV, int64_t ldv, feast_z *hLambda, feast_z *dX,
+                    int64_t ldx, double *hRes, int32_t *s_found, double *err,
+                    int32_t *flag, feast_info *info);
+
+/* Host only: the ordering feast_solve_csr uses, for one pattern (host arrays
+ * rowptr[n + 1], col[rowptr[n]]): reverse Cuthill-McKee of the symmetrised
+ * pattern (diagonal ignored), or the natural order where that is at least as
+ * narrow; hperm[new] = old (n entries, caller-allocated) and the lower and
+ * upper bandwidth of the pattern in that order.  FEAST_EINVAL for a malformed
+ * pattern.  No device work. */
+int feast_csr_order(int64_t n, const int32_t *hrowptr, const int32_t *hcol, int32_t *hperm,
+                    int64_t *kl, int64_t *ku);
 
 /* ---------------------------------------------------------------------------
  * Block_CIRR (Algorithm 1, Section 2): the paper's comparison method, on the

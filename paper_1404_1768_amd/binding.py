@@ -41,7 +41,8 @@ EXPORTED = [
     "feast_batch_create", "feast_batch_destroy", "feast_batch_invalidate",
     "feast_batch_last_error", "feast_batch_filter", "feast_batch_solve",
     "feast_search", "feast_plan_set_m", "feast_solve_from", "feast_enclosing_circle",
-    "feast_region_select", "feast_cirr", "feast_zgetrs_batched_noalloc",
+    "feast_region_select", "feast_cirr", "feast_zgetrs_batched_noalloc", "feast_solve_csr",
+    "feast_csr_order",
 ]
 
 
@@ -77,7 +78,13 @@ class Info(C.Structure):
                 ("t_ritz_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("lu_gemm_launches", C.c_int32), ("lu_gemm_ms", C.c_double),
                 ("lu_gemm_flops", C.c_double), ("hbm", KProf * len(K_CLASSES)),
-                ("contraction", C.c_double * MAX_HISTORY)]
+                ("contraction", C.c_double * MAX_HISTORY),
+                ("band_kl", C.c_int32), ("band_ku", C.c_int32)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
 
 
 class SearchInfo(C.Structure):
@@ -128,6 +135,10 @@ def load(path: str = LIB_PATH):
     lib.feast_solve.argtypes = [P, P, i64, P, i64, P, i64, pz, P, i64, C.POINTER(dbl),
                                 C.POINTER(i32), C.POINTER(dbl), C.POINTER(i32), C.POINTER(Info)]
     lib.feast_solve_from.argtypes = list(lib.feast_solve.argtypes)
+    lib.feast_solve_csr.argtypes = [P, C.POINTER(Csr), C.POINTER(Csr), P, i64, pz, P, i64,
+                                    C.POINTER(dbl), C.POINTER(i32), C.POINTER(dbl), C.POINTER(i32),
+                                    C.POINTER(Info)]
+    lib.feast_csr_order.argtypes = [i64, P, P, P, C.POINTER(i64), C.POINTER(i64)]
     lib.feast_search.argtypes = [P, P, i64, P, i64, P, i64, i64, i32, dbl, dbl, P, i64,
                                  C.POINTER(SearchInfo)]
     lib.feast_plan_set_m.argtypes = [P, i64]
@@ -187,6 +198,38 @@ def _dev(t, rows=None, cols=None, name="tensor"):
     if cols is not None and t.shape[1] != cols:
         raise ValueError("%s has %d columns, expected %d" % (name, t.shape[1], cols))
     return C.c_void_p(t.data_ptr()), max(t.stride(0), t.shape[1])
+
+
+def _csr(M, n, name):
+    """feast_csr of an n x n CSR matrix given as (rowptr, col, val) device
+    tensors: int32 (n + 1), int32 (nnz), complex128 (nnz)."""
+    import torch
+    rp, ci, va = M
+    for t, dt, what in ((rp, torch.int32, "rowptr"), (ci, torch.int32, "col"),
+                        (va, torch.complex128, "val")):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or t.dim() != 1 or not t.is_cuda \
+                or not t.is_contiguous():
+            raise ValueError("%s.%s must be a contiguous 1-D %s CUDA tensor" % (name, what, dt))
+    if rp.numel() != n + 1 or ci.numel() != va.numel():
+        raise ValueError("%s: rowptr needs n + 1 entries and col, val the same count" % name)
+    return Csr(n, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+
+
+def csr_order(rowptr: np.ndarray, col: np.ndarray):
+    """Host: the ordering feast_solve_csr uses for a CSR pattern (reverse
+    Cuthill-McKee of the symmetrised pattern, or the natural order where that
+    is at least as narrow): (perm with perm[new] = old, kl, ku in that order)."""
+    lib = load()
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    n = rp.size - 1
+    perm = np.zeros(n, dtype=np.int32)
+    kl, ku = C.c_int64(), C.c_int64()
+    rc = lib.feast_csr_order(n, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                           perm.ctypes.data_as(C.c_void_p), C.byref(kl), C.byref(ku))
+    if rc != FEAST_OK:
+        raise FeastError(rc, "feast_csr_order: malformed pattern")
+    return perm, int(kl.value), int(ku.value)
 
 
 def _stream(stream):
@@ -303,6 +346,7 @@ class SolveResult:
     lu_gemm: dict
     hbm: dict = dataclasses.field(default_factory=dict)
     contraction: list = dataclasses.field(default_factory=list)
+    band: tuple = None     # feast_solve_csr: (kl, ku) of the reordered pencil
 
 
 class Plan:
@@ -417,6 +461,33 @@ class Plan:
                 res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(s), C.byref(err),
                 C.byref(flag), C.byref(info))
         self._check(rc, what, ok=(FEAST_OK,) + tuple(allow))
+        return self._result(rc, info, lam, res, X, s, err, flag)
+
+    def solve_csr(self, A, B, V, allow=(FEAST_REFINE_STAGNATED,)) -> SolveResult:
+        """Algorithm 5 for a sparse pencil: A and B as (rowptr, col, val) device
+        tensors (int32, int32, complex128) of n x n CSR matrices; FP64 plans
+        only.  The result's `band` is (kl, ku) of the reordered pencil."""
+        import torch
+        n, m = self.n, self.m
+        ca, cb = _csr(A, n, "A"), _csr(B, n, "B")
+        pv, ldv = _dev(V, n, m, "V")
+        X = torch.empty((n, m), dtype=torch.complex128, device=V.device)
+        lam = np.zeros(m, dtype=np.complex128)
+        res = np.zeros(m, dtype=np.float64)
+        s = C.c_int32()
+        err = C.c_double()
+        flag = C.c_int32()
+        info = Info()
+        rc = self.lib.feast_solve_csr(self._h, C.byref(ca), C.byref(cb), pv, ldv, _zptr(lam),
+                                      C.c_void_p(X.data_ptr()), m,
+                                      res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(s),
+                                      C.byref(err), C.byref(flag), C.byref(info))
+        self._check(rc, "feast_solve_csr", ok=(FEAST_OK,) + tuple(allow))
+        out = self._result(rc, info, lam, res, X, s, err, flag)
+        out.band = (int(info.band_kl), int(info.band_ku))
+        return out
+
+    def _result(self, rc, info, lam, res, X, s, err, flag) -> SolveResult:
         k = s.value
         it = info.iters
         return SolveResult(

@@ -20,9 +20,9 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfeast_mi355x.so")
 ARCH = "gfx950"
 
-DEVICE_SOURCES = ["k_gemm.hip", "k_lu.hip", "k_misc.hip"]
+DEVICE_SOURCES = ["k_gemm.hip", "k_lu.hip", "k_misc.hip", "k_band.hip"]
 HOST_HIP_SOURCES = ["feast.cpp", "batch.cpp"]           # host code that calls the HIP runtime
-HOST_SOURCES = ["host_eig.cpp", "host_util.cpp"]   # plain C++
+HOST_SOURCES = ["host_eig.cpp", "host_util.cpp", "host_sparse.cpp"]   # plain C++
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-fcx-limited-range"]
 # Packed-FP32 instructions are disabled for every device compile.

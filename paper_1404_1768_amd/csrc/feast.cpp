@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "host_eig.h"
+#include "host_sparse.h"
 #include "plan.h"
 
 using namespace feast_drv;
@@ -314,6 +315,7 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
 // (Section 4.3: the factors of the same shifted matrices): one read of A and B
 // for their fingerprints and a wait for the two words.
 int ensure_factored(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) {
+  if (p->sp.on) return FEAST_OK;  // (a sparse call's band factors are made on entry)
   if (p->factored && p->checked) return FEAST_OK;
   if (p->factored) {
     launch_fingerprints(p, A, lda, B, ldb);
@@ -446,7 +448,11 @@ int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t l
                bool resume = false) {
   if (cols < 0) cols = p->m;
   int st = ensure_factored(p, A, lda, B, ldb);
-  if (p->mixed())
+  if (p->sp.on)
+    feast::band_solve(p->s, p->sp.Lf.as<z64>(), p->sp.Uf.as<z64>(), p->sp.Dinv.as<z64>(),
+                      p->sp.piv.as<int32_t>(), p->N, p->n, p->sp.kl, p->sp.ku, R, ldr, cols,
+                      p->Y.as<z64>(), p->ldY(), p->m);
+  else if (p->mixed())
     solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps, cols, resume);
   else
     solve_nodes_z(p, R, ldr, cols);
@@ -595,6 +601,18 @@ void project_device(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int6
   hipStream_t s = p->s;
   feast::fill_i32(s, p->flag.as<int32_t>(), 6, 0);
   orth(p, U, ldu, 0);
+  if (p->sp.on) {  // A U_1 and B U_1 in one pass over the shared pattern
+    feast::csr_spmm(s, p->sp.rp.as<int32_t>(), p->sp.ci.as<int32_t>(), p->sp.va.as<z64>(),
+                    p->sp.vb.as<z64>(), n, U, ldu, m, AU1, ldau, BU1, ldbu);
+    z64 *U2 = p->wblk(feast_plan::W_U2);
+    feast::copy_block_z(s, BU1, ldbu, n, m, U2, m);
+    orth(p, U2, m, 3);
+    gemm_t<z64>(s, 2, m, m, n, zc(1.0), U2, m, 0, AU1, ldau, 0, zc(0.0),
+                p->gblk(feast_plan::G_AT), m, 0, 1, p->splitws.as<z64>(), splitws_elems(p));
+    gemm_t<z64>(s, 2, m, m, n, zc(1.0), U2, m, 0, BU1, ldbu, 0, zc(0.0),
+                p->gblk(feast_plan::G_BT), m, 0, 1, p->splitws.as<z64>(), splitws_elems(p));
+    return;
+  }
   // A U_1 runs on the side stream beside B U_1 and the orthonormalisation of
   // B U_1: one n x m product alone fills only (n/64)(m/64) workgroups, and the
   // Cholesky QR chain leaves most compute units idle
@@ -837,8 +855,8 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
                       feast_z *hLambda, feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found,
                       double *err, int32_t *flag, feast_info *info) {
   if (!p) return FEAST_EINVAL;
-  if (!dA || !dB || !dV || !hLambda || !dX || !s_found || !err || !flag || lda < p->n ||
-      ldb < p->n || ldv < p->m || ldx < p->m)
+  if ((!p->sp.on && (!dA || !dB || lda < p->n || ldb < p->n)) || !dV || !hLambda || !dX ||
+      !s_found || !err || !flag || ldv < p->m || ldx < p->m)
     return fail(p, FEAST_EINVAL, "feast_solve: null pointer or leading dimension too small");
   p->err.clear();
   CheckScope check_scope(p);
@@ -913,7 +931,11 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     } else {
       // Search with the subspace size fixed: U = Q_N V, QR inside the projection
       Timer t;
-      gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1);
+      if (p->sp.on)
+        feast::csr_spmm(s, p->sp.rp.as<int32_t>(), p->sp.ci.as<int32_t>(), p->sp.va.as<z64>(),
+                        p->sp.vb.as<z64>(), n, V, ldv, m, nullptr, 0, p->R.as<z64>(), m);
+      else
+        gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1);
       const int st = run_filter(p->R.as<z64>(), U1, true);
       if (st != FEAST_OK && st != FEAST_REFINE_STAGNATED) return st;
       HIPCHK(hipStreamSynchronize(s));
@@ -1251,6 +1273,151 @@ int feast_solve(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB
                 double *hRes, int32_t *s_found, double *err, int32_t *flag, feast_info *info) {
   return solve_impl(p, dA, lda, dB, ldb, dV, ldv, false, hLambda, dX, ldx, hRes, s_found, err,
                     flag, info);
+}
+
+// Sparse pencils: the symbolic steps on the host (pattern copies and checks,
+// union pattern, ordering -- reverse Cuthill-McKee or the natural order,
+// whichever is narrower -- and band widths), then on the
+// device the values gathered onto the reordered pattern and the band LU of
+// every node.
+constexpr int kBandMax = 63;  // kl + ku: LDS windows of the band kernels
+
+int prepare_sparse(feast_plan *p, const feast_csr *A, const feast_csr *B) {
+  const int64_t n = p->n;
+  hipStream_t s = p->s;
+  feast_host::Pattern PA, PB;
+  for (int w = 0; w < 2; ++w) {
+    const feast_csr *M = w ? B : A;
+    feast_host::Pattern &P = w ? PB : PA;
+    P.n = n;
+    P.rp.resize(static_cast<size_t>(n) + 1);
+    P.ci.resize(static_cast<size_t>(M->nnz));
+    HIPCHK(hipMemcpyAsync(P.rp.data(), M->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    if (M->nnz > 0)
+      HIPCHK(hipMemcpyAsync(P.ci.data(), M->col, sizeof(int32_t) * M->nnz, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const std::string bad = feast_host::check_pattern(n, P.rp.data(), P.ci.data(), M->nnz);
+    if (!bad.empty()) return fail(p, FEAST_EINVAL, std::string(w ? "B: " : "A: ") + bad);
+  }
+  std::vector<int32_t> ident(static_cast<size_t>(n));
+  for (int64_t i = 0; i < n; ++i) ident[i] = static_cast<int32_t>(i);
+  const feast_host::UnionPattern U0 = feast_host::union_reordered(PA, PB, ident);
+  int64_t kl = 0, ku = 0;
+  const std::vector<int32_t> perm = feast_host::band_order(U0.P, &kl, &ku);
+  if (kl + ku > kBandMax) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "band too wide after reordering: kl = %lld, ku = %lld (kl + ku <= %d); factor "
+                  "this pencil densely (feast_solve)",
+                  static_cast<long long>(kl), static_cast<long long>(ku), kBandMax);
+    return fail(p, FEAST_EINVAL, buf);
+  }
+  const feast_host::UnionPattern U = feast_host::union_reordered(PA, PB, perm);
+  const int64_t nnz = static_cast<int64_t>(U.P.ci.size());
+  auto &sp = p->sp;
+  sp.kl = static_cast<int>(kl);
+  sp.ku = static_cast<int>(ku);
+  sp.nnz = nnz;
+  sp.rp.alloc(sizeof(int32_t) * (n + 1));
+  sp.ci.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+  sp.map.alloc(sizeof(int32_t) * 2 * std::max<int64_t>(nnz, 1));
+  sp.va.alloc(sizeof(z64) * std::max<int64_t>(nnz, 1));
+  sp.vb.alloc(sizeof(z64) * std::max<int64_t>(nnz, 1));
+  sp.perm.alloc(sizeof(int32_t) * n);
+  HIPCHK(hipMemcpyAsync(sp.rp.p, U.P.rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(sp.perm.p, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  if (nnz > 0) {
+    int32_t *dmap = sp.map.as<int32_t>();
+    HIPCHK(hipMemcpyAsync(sp.ci.p, U.P.ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dmap, U.mapA.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dmap + nnz, U.mapB.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    feast::gather_vals(s, dmap, reinterpret_cast<const z64 *>(A->val), nnz, sp.va.as<z64>());
+    feast::gather_vals(s, dmap + nnz, reinterpret_cast<const z64 *>(B->val), nnz, sp.vb.as<z64>());
+  }
+  const int N = p->N;
+  const int64_t WC = kl + ku + 1;
+  sp.Lf.alloc(sizeof(z64) * N * n * std::max<int64_t>(kl, 1));
+  sp.Uf.alloc(sizeof(z64) * N * n * WC);
+  sp.Dinv.alloc(sizeof(z64) * N * n);
+  sp.piv.alloc(sizeof(int32_t) * N * n);
+  sp.info.alloc(sizeof(int32_t) * N);
+  sp.V.alloc(sizeof(z64) * n * p->m);
+  sp.X.alloc(sizeof(z64) * n * p->m);
+  feast::band_lu(s, sp.rp.as<int32_t>(), sp.ci.as<int32_t>(), sp.va.as<z64>(), sp.vb.as<z64>(),
+                 p->dz.as<z64>(), N, n, sp.kl, sp.ku, sp.Lf.as<z64>(), sp.Uf.as<z64>(),
+                 sp.Dinv.as<z64>(), sp.piv.as<int32_t>(), sp.info.as<int32_t>());
+  std::vector<int32_t> hinfo(N);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), sp.info.p, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  for (int j = 0; j < N; ++j)
+    if (hinfo[j] != 0) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf, "exact zero pivot in the band LU at node %d (z = %.17g%+.17gi), column %d",
+                    j, p->hz[j].real(), p->hz[j].imag(), hinfo[j] - 1);
+      p->err = buf;
+      return FEAST_SINGULAR;
+    }
+  return FEAST_OK;
+}
+
+int feast_solve_csr(feast_plan *p, const feast_csr *A, const feast_csr *B, const feast_z *dV,
+                    int64_t ldv, feast_z *hLambda, feast_z *dX, int64_t ldx, double *hRes,
+                    int32_t *s_found, double *err, int32_t *flag, feast_info *info) {
+  if (!p) return FEAST_EINVAL;
+  if (!A || !B || !dV || !hLambda || !dX || !s_found || !err || !flag || ldv < p->m || ldx < p->m)
+    return fail(p, FEAST_EINVAL, "feast_solve_csr: null pointer or leading dimension too small");
+  if (A->n != p->n || B->n != p->n || A->nnz < 0 || B->nnz < 0 || !A->rowptr || !B->rowptr ||
+      (A->nnz > 0 && (!A->col || !A->val)) || (B->nnz > 0 && (!B->col || !B->val)) ||
+      A->nnz > INT32_MAX || B->nnz > INT32_MAX)
+    return fail(p, FEAST_EINVAL, "feast_solve_csr: matrices must be n x n CSR with device arrays");
+  if (p->mixed())
+    return fail(p, FEAST_EINVAL, "feast_solve_csr: sparse pencils are factored in FP64 only");
+  p->err.clear();
+  return guarded(p, [&]() -> int {
+    const int64_t n = p->n, m = p->m;
+    Timer tf;
+    int st = prepare_sparse(p, A, B);
+    const double t_fac = tf.ms();
+    if (st != FEAST_OK) return st;
+    struct Off {
+      feast_plan *p;
+      ~Off() { p->sp.on = false; }
+    } off{p};
+    p->sp.on = true;
+    const int32_t *perm = p->sp.perm.as<int32_t>();
+    feast::gather_rows<z64>(p->s, reinterpret_cast<const z64 *>(dV), ldv, 0, perm, n, m, 1,
+                            p->sp.V.as<z64>(), m, 0);
+    feast_info inf{};
+    st = solve_impl(p, nullptr, n, nullptr, n, reinterpret_cast<const feast_z *>(p->sp.V.p), m,
+                    false, hLambda, reinterpret_cast<feast_z *>(p->sp.X.p), m, hRes, s_found, err,
+                    flag, &inf);
+    if (st == FEAST_OK || st == FEAST_REFINE_STAGNATED) {
+      if (*s_found > 0)  // eigenvectors back to the caller's row order
+        feast::scatter_rows<z64>(p->s, p->sp.X.as<z64>(), m, 0, perm, n, *s_found, 1,
+                                 reinterpret_cast<z64 *>(dX), ldx, 0);
+      HIPCHK(hipStreamSynchronize(p->s));
+    }
+    inf.t_factor_ms += t_fac;
+    inf.t_total_ms += t_fac;
+    inf.band_kl = p->sp.kl;
+    inf.band_ku = p->sp.ku;
+    if (info) *info = inf;
+    return st;
+  });
+}
+
+int feast_csr_order(int64_t n, const int32_t *hrowptr, const int32_t *hcol, int32_t *hperm,
+                    int64_t *kl, int64_t *ku) {
+  if (n <= 0 || !hrowptr || (hrowptr[n] > 0 && !hcol) || !hperm || !kl || !ku) return FEAST_EINVAL;
+  if (!feast_host::check_pattern(n, hrowptr, hcol, hrowptr[n]).empty()) return FEAST_EINVAL;
+  feast_host::Pattern P;
+  P.n = n;
+  P.rp.assign(hrowptr, hrowptr + n + 1);
+  P.ci.assign(hcol, hcol + hrowptr[n]);
+  const std::vector<int32_t> perm = feast_host::band_order(P, kl, ku);
+  std::copy(perm.begin(), perm.end(), hperm);
+  return FEAST_OK;
 }
 
 int feast_solve_from(feast_plan *p, const feast_z *dA, int64_t lda, const feast_z *dB,

@@ -1,0 +1,440 @@
+// Sparse pencils in band form on gfx950: the shifted matrices z_j B - A of a
+// pencil whose non-zeros (after a bandwidth-reducing reordering) lie within kl
+// subdiagonals and ku superdiagonals.  A and B arrive as values on one shared
+// (union) CSR pattern; the node factorisations are band LU factorisations with
+// partial pivoting, the node solves band triangular solves, and the products
+// A X, B X of the projection CSR x dense products.  (The shifted systems of
+// eq. 4-4 are the same; only their storage and factorisation differ from the
+// dense path.)
+//
+// Band LU (row interchanges as in LAPACK's band factorisation): at column k
+// the pivot is the largest |re| + |im| among rows k .. k + kl (lowest row on
+// ties), the two rows are exchanged on the active columns only, and U gains up
+// to kl superdiagonals from the exchanges, so its rows hold WC = kl + ku + 1
+// entries.  The multipliers of column k are kept in the order of the
+// exchanges, so the forward solve applies exchange k and then column k's
+// multipliers, k = 0, 1, ...
+#include "common.h"
+#include "kernels.h"
+
+namespace feast {
+
+namespace {
+
+// largest of (key, index) over the wavefront, lowest index on equal keys
+__device__ inline void wave_argmax(double &key, int &idx) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ok = __shfl_xor(key, off, 64);
+    const int oi = __shfl_xor(idx, off, 64);
+    if (ok > key || (ok == key && oi < idx)) {
+      key = ok;
+      idx = oi;
+    }
+  }
+}
+
+constexpr int kBandCH = 32;  // rows staged per chunk (LU: CSR rows; solves: factor and block rows)
+
+// One workgroup (256 threads) per node j.  Thread t < WC owns window column
+// slot t for the whole factorisation and keeps that column's rows k .. k + kl
+// in registers (w[i] = row k + i; W >= kl + 1 is the compile-time bound); slot
+// t holds column k + ((t - k) mod WC).  Every kBandCH columns the workgroup
+// stages the next kBandCH incoming rows (row k + kl + 1 enters at column k) as
+// dense band rows of z_j B - A in LDS, every load issued before the first
+// wait.  Per column k, one barrier:
+//   before it, the owner of column k posts that column to LDS and wave 0 finds
+//   the pivot (largest |re| + |im|, lowest row on ties) and the multipliers;
+//   after it, every owner exchanges rows k and k + p of its column, writes its
+//   entry of U's row k, applies the multipliers, moves its rows up by one and
+//   takes the staged row's entry as row k + kl + 1 (the owner of column k
+//   starts column k + WC, zero above the new row).
+// The multipliers are double-buffered by the parity of k, so the next
+// column's cannot overwrite what an owner is still reading.
+template <int W>
+__global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci,
+                                                 const z64 *__restrict__ va,
+                                                 const z64 *__restrict__ vb,
+                                                 const z64 *__restrict__ zn, int64_t n, int kl,
+                                                 int ku, z64 *__restrict__ Lf,
+                                                 z64 *__restrict__ Uf, z64 *__restrict__ Dinv,
+                                                 int32_t *__restrict__ piv,
+                                                 int32_t *__restrict__ info) {
+  const int KR = kl + 1, WC = kl + ku + 1;
+  // rows 0 .. kl of the first window, then the staged rows of each chunk
+  // (row q of the chunk at SR[q WC + c - (row - kl)], c its column)
+  __shared__ z64 SR[64 * 64];
+  __shared__ int32_t srp[kBandCH + 1];
+  __shared__ z64 colbuf[64];
+  __shared__ z64 sl[2][64];  // multipliers of column k (index 1 .. kl)
+  __shared__ int s_p[2];
+  __shared__ int s_info;
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const z64 z = zn[j];
+  z64 *L = Lf + static_cast<int64_t>(j) * n * kl;
+  z64 *U = Uf + static_cast<int64_t>(j) * n * WC;
+  z64 *Di = Dinv + static_cast<int64_t>(j) * n;
+  int32_t *pv = piv + static_cast<int64_t>(j) * n;
+
+  // stage rows r0 .. r0 + cnt - 1 (all < n) into SR (row q at SR[q WC + c - (r0 + q - kl)])
+  auto stage = [&](int64_t r0, int cnt) {
+    for (int e = tid; e < cnt * WC; e += 256) SR[e] = zmake(0.0, 0.0);
+    if (tid <= cnt) srp[tid] = rp[r0 + tid];
+    __syncthreads();
+    const int e0 = srp[0], e1 = srp[cnt];
+    // (at most kBandCH rows of at most 64 entries: 8 per thread, loaded 4 at a time)
+    for (int h = 0; h < 2; ++h) {
+      int32_t c4[4];
+      z64 a4[4], b4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + tid + 256 * (4 * h + q);
+        const int ee = e < e1 ? e : e0;
+        c4[q] = ci[ee];
+        a4[q] = va[ee];
+        b4[q] = vb[ee];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + tid + 256 * (4 * h + q);
+        if (e < e1) {
+          int row = 0;  // the chunk row holding entry e
+          while (row + 1 < cnt && srp[row + 1] <= e) ++row;
+          const z64 b = b4[q], a = a4[q];
+          SR[row * WC + c4[q] - (r0 + row - kl)] =
+              zmake(z.x * b.x - z.y * b.y - a.x, z.x * b.y + z.y * b.x - a.y);
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  if (tid == 0) s_info = 0;
+  stage(0, static_cast<int>(KR < n ? KR : n));
+  const bool owner = tid < WC;
+  z64 w[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    // window row i, column tid: SR index i WC + tid - (i - kl)
+    const int c = tid - i + kl;
+    w[i] = (owner && i < KR && i < n && c >= 0 && c < WC) ? SR[i * WC + c] : zmake(0.0, 0.0);
+  }
+
+  int ck = 0;  // slot of column k
+  for (int64_t k0 = 0; k0 < n; k0 += kBandCH) {
+    const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
+    // incoming rows of this chunk's columns: k0 + KR .. (those below n)
+    const int64_t r0 = k0 + KR;
+    const int cnt = r0 < n ? static_cast<int>(n - r0 < ch ? n - r0 : ch) : 0;
+    __syncthreads();
+    stage(r0 < n ? r0 : 0, cnt);
+    for (int kk = 0; kk < ch; ++kk) {
+      const int64_t k = k0 + kk;
+      const int par = static_cast<int>(k & 1);
+      if (tid < 64) {
+        if (tid == ck) {
+#pragma unroll
+          for (int i = 0; i < W; ++i)
+            if (i < KR) colbuf[i] = w[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const int i = lane;
+        const bool valid = i < KR && k + i < n;
+        const z64 v = valid ? colbuf[i] : zmake(0.0, 0.0);
+        const double a1 = zabs1(v);
+        double key = valid ? (a1 == a1 ? a1 : -1.0) : -2.0;
+        int idx = valid ? i : 1 << 30;
+        wave_argmax(key, idx);
+        const int p = idx < KR ? idx : 0;
+        const double ux = __shfl(v.x, p, 64), uy = __shfl(v.y, p, 64);
+        const double v0x = __shfl(v.x, 0, 64), v0y = __shfl(v.y, 0, 64);
+        const bool zero = !(key > 0.0);
+        const z64 inv = zero ? zmake(0.0, 0.0) : zrecip(zmake(ux, uy));
+        if (i >= 1 && i < KR) {
+          const z64 src = (i == p) ? zmake(v0x, v0y) : v;
+          const z64 l = valid ? zmul(src, inv) : zmake(0.0, 0.0);
+          sl[par][i] = l;
+          L[k * kl + (i - 1)] = l;
+        }
+        if (lane == 0) {
+          s_p[par] = p;
+          pv[k] = static_cast<int32_t>(k + p);
+          Di[k] = inv;
+          if (zero && s_info == 0) s_info = static_cast<int>(k) + 1;
+        }
+      }
+      __syncthreads();
+      if (owner) {
+        const int p = __builtin_amdgcn_readfirstlane(s_p[par]);
+        int jo = tid - ck;  // this column's offset from column k
+        if (jo < 0) jo += WC;
+        const z64 r0v = w[0];
+        z64 rpv = w[0];
+#pragma unroll
+        for (int i = 1; i < W; ++i)
+          if (i == p) rpv = w[i];
+        U[k * WC + jo] = (k + jo < n) ? rpv : zmake(0.0, 0.0);
+        // the incoming row k + KR at this slot's next column (k + jo, or
+        // k + WC for the slot of column k): staged index WC - 1 or jo - 1
+        const z64 nv = (kk < cnt) ? SR[kk * WC + (jo == 0 ? WC - 1 : jo - 1)] : zmake(0.0, 0.0);
+        if (jo == 0) {  // column k leaves: the slot starts column k + WC
+#pragma unroll
+          for (int i = 0; i < W; ++i) w[i] = (i == KR - 1) ? nv : zmake(0.0, 0.0);
+        } else {
+#pragma unroll
+          for (int i = 1; i < W; ++i)
+            if (i < KR && k + i < n) {
+              const z64 cur = (i == p) ? r0v : w[i];
+              w[i] = zfms(cur, sl[par][i], rpv);
+            }
+#pragma unroll
+          for (int i = 0; i < W; ++i) w[i] = (i == KR - 1) ? nv : (i + 1 < W ? w[i + 1] : zmake(0.0, 0.0));
+        }
+      }
+      if (++ck == WC) ck = 0;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) info[j] = s_info;
+}
+
+// The node solves Y_j = M_j^{-1} R with M_j's band factors, one lane per
+// right-hand side (the 64 columns of R from 64 blockIdx.y; node j =
+// blockIdx.x), as two kernels so that each holds one window in registers:
+//   k_band_fwd: exchanges and unit-lower multipliers; a lane keeps rows
+//     k .. k + kl of its column (WF >= kl + 1) and writes row k of the result
+//     to Y_j;
+//   k_band_bwd: U; a lane keeps the solved rows k + 1 .. k + kl + ku
+//     (WB >= kl + ku), sums their products in four independent partial sums
+//     and overwrites row k of Y_j with the solution (times the stored pivot
+//     reciprocal).
+// Factor rows and block rows are staged kBandCH at a time through LDS (loads
+// issued 16 at a time before they are written), so each step reads only LDS
+// and registers.
+struct BandStage {
+  // dst[e] = src[e] for e < cnt (cnt <= kBandCH * 64), 16 loads in flight per lane
+  __device__ static void flat(z64 *dst, const z64 *src, int cnt, int lane) {
+    for (int h = 0; h < 2; ++h) {
+      z64 t[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = lane + 64 * (16 * h + q);
+        t[q] = e < cnt ? src[e] : zmake(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = lane + 64 * (16 * h + q);
+        if (e < cnt) dst[e] = t[q];
+      }
+    }
+  }
+  // rows[q][lane] = M[(r0 + q) ldm + cc] for q < cnt (rows >= lim read as zero)
+  __device__ static void rows(z64 (*dst)[64], const z64 *M, int64_t ldm, int64_t r0, int cnt,
+                              int64_t lim, int64_t cc, int lane) {
+    for (int h = 0; h < 2; ++h) {
+      z64 t[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t r = r0 + 16 * h + q;
+        t[q] = (16 * h + q < cnt && r < lim) ? M[r * ldm + cc] : zmake(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) dst[16 * h + q][lane] = t[q];
+    }
+  }
+};
+
+template <int WF>
+__global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
+                                                 const int32_t *__restrict__ piv, int64_t n,
+                                                 int kl, const z64 *__restrict__ R, int64_t ldr,
+                                                 int64_t m, z64 *__restrict__ Y, int64_t ldy,
+                                                 int64_t sY) {
+  const int KR = kl + 1;
+  __shared__ z64 fac[kBandCH * 64];  // kBandCH rows of multipliers (kl each)
+  __shared__ z64 rows[kBandCH][64];  // the rows of R entering the window
+  __shared__ int32_t s_piv[kBandCH];
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const int64_t col = static_cast<int64_t>(blockIdx.y) * 64 + lane;
+  const bool act = col < m;
+  const int64_t cc = act ? col : 0;  // a valid column for the loads of idle lanes
+  const z64 *L = Lf + static_cast<int64_t>(j) * n * kl;
+  const int32_t *pv = piv + static_cast<int64_t>(j) * n;
+  z64 *Yj = Y + static_cast<int64_t>(j) * sY;
+  z64 w[WF];  // w[i] = row k + i
+#pragma unroll
+  for (int i = 0; i < WF; ++i) w[i] = (i < KR && i < n) ? R[i * ldr + cc] : zmake(0.0, 0.0);
+  for (int64_t k0 = 0; k0 < n; k0 += kBandCH) {
+    const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
+    __syncthreads();
+    BandStage::flat(fac, L + k0 * kl, ch * kl, lane);
+    if (lane < ch) s_piv[lane] = pv[k0 + lane];
+    BandStage::rows(rows, R, ldr, k0 + KR, ch, n, cc, lane);
+    __syncthreads();
+    for (int kk = 0; kk < ch; ++kk) {
+      const int64_t k = k0 + kk;
+      const int p = __builtin_amdgcn_readfirstlane(s_piv[kk] - static_cast<int>(k));
+      z64 y = w[0];
+      if (p != 0) {
+#pragma unroll
+        for (int i = 1; i < WF; ++i)
+          if (i == p) {
+            y = w[i];
+            w[i] = w[0];
+          }
+      }
+      if (act) Yj[k * ldy + col] = y;
+#pragma unroll
+      for (int i = 1; i < WF; ++i)
+        if (i < KR) w[i] = zfms(w[i], fac[kk * kl + i - 1], y);
+      const z64 nv = rows[kk][lane];
+#pragma unroll
+      for (int i = 0; i < WF; ++i)
+        w[i] = (i == KR - 1) ? nv : (i + 1 < WF ? w[i + 1] : zmake(0.0, 0.0));
+    }
+  }
+}
+
+template <int WB>
+__global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
+                                                 const z64 *__restrict__ Dinv, int64_t n, int kl,
+                                                 int ku, int64_t m, z64 *__restrict__ Y,
+                                                 int64_t ldy, int64_t sY) {
+  const int WC = kl + ku + 1, WU = kl + ku;
+  __shared__ z64 fac[kBandCH * 64];  // kBandCH rows of U (WC each)
+  __shared__ z64 rows[kBandCH][64];  // the forward results of those rows
+  __shared__ z64 dinv[kBandCH];
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const int64_t col = static_cast<int64_t>(blockIdx.y) * 64 + lane;
+  const bool act = col < m;
+  const int64_t cc = act ? col : 0;
+  const z64 *U = Uf + static_cast<int64_t>(j) * n * WC;
+  const z64 *Di = Dinv + static_cast<int64_t>(j) * n;
+  z64 *Yj = Y + static_cast<int64_t>(j) * sY;
+  z64 b[WB];  // b[t - 1] = solved row k + t
+#pragma unroll
+  for (int i = 0; i < WB; ++i) b[i] = zmake(0.0, 0.0);
+  for (int64_t k1 = n; k1 > 0; k1 -= kBandCH) {
+    const int ch = static_cast<int>(k1 < kBandCH ? k1 : kBandCH);
+    const int64_t kb = k1 - ch;  // rows kb .. k1 - 1
+    __syncthreads();
+    BandStage::flat(fac, U + kb * WC, ch * WC, lane);
+    if (lane < ch) dinv[lane] = Di[kb + lane];
+    BandStage::rows(rows, Yj, ldy, kb, ch, n, cc, lane);
+    __syncthreads();
+    for (int kk = ch - 1; kk >= 0; --kk) {
+      const int64_t k = kb + kk;
+      // entries past row n - 1 multiply b's zeros
+      const int lim = static_cast<int>(n - 1 - k < WU ? n - 1 - k : WU);
+      z64 s4[4] = {rows[kk][lane], zmake(0.0, 0.0), zmake(0.0, 0.0), zmake(0.0, 0.0)};
+#pragma unroll
+      for (int t = 1; t <= WB; ++t)
+        if (t <= lim) s4[t & 3] = zfms(s4[t & 3], fac[kk * WC + t], b[t - 1]);
+      const z64 s = zadd(zadd(s4[0], s4[1]), zadd(s4[2], s4[3]));
+      const z64 y = zmul(s, dinv[kk]);
+      if (act) Yj[k * ldy + col] = y;
+#pragma unroll
+      for (int t = WB - 1; t > 0; --t) b[t] = b[t - 1];
+      b[0] = y;
+    }
+  }
+}
+
+// YA = A X and YB = B X (either may be null) on the union pattern: one
+// wavefront per row, lanes over the columns.
+__global__ __launch_bounds__(256) void k_csr_spmm(const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci,
+                                                  const z64 *__restrict__ va,
+                                                  const z64 *__restrict__ vb, int64_t n,
+                                                  const z64 *__restrict__ X, int64_t ldx,
+                                                  int64_t m, z64 *__restrict__ YA, int64_t ldya,
+                                                  z64 *__restrict__ YB, int64_t ldyb) {
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const int e0 = rp[row], e1 = rp[row + 1];
+  for (int64_t c0 = 0; c0 < m; c0 += 64) {
+    const int64_t col = c0 + lane;
+    if (col >= m) break;
+    z64 sa = zmake(0.0, 0.0), sb = zmake(0.0, 0.0);
+    for (int e = e0; e < e1; ++e) {
+      const z64 x = X[static_cast<int64_t>(ci[e]) * ldx + col];
+      if (YA) {
+        const z64 a = va[e];
+        sa = zadd(sa, zmul(a, x));
+      }
+      if (YB) {
+        const z64 b = vb[e];
+        sb = zadd(sb, zmul(b, x));
+      }
+    }
+    if (YA) YA[row * ldya + col] = sa;
+    if (YB) YB[row * ldyb + col] = sb;
+  }
+}
+
+// dst[e] = src[map[e]] (or zero where map[e] < 0)
+__global__ __launch_bounds__(256) void k_gather_vals(const int32_t *__restrict__ map,
+                                                     const z64 *__restrict__ src, int64_t cnt,
+                                                     z64 *__restrict__ dst) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= cnt) return;
+  const int32_t s = map[e];
+  dst[e] = s >= 0 ? src[s] : zmake(0.0, 0.0);
+}
+
+}  // namespace
+
+namespace {
+// register window classes of the band kernels
+int band_class(int w) { return w <= 16 ? 16 : w <= 24 ? 24 : w <= 32 ? 32 : w <= 48 ? 48 : 64; }
+
+#define FEAST_BAND_DISPATCH(cls, KERNEL, ...)                                   \
+  switch (cls) {                                                               \
+    case 16: hipLaunchKernelGGL((KERNEL<16>), __VA_ARGS__); break;             \
+    case 24: hipLaunchKernelGGL((KERNEL<24>), __VA_ARGS__); break;             \
+    case 32: hipLaunchKernelGGL((KERNEL<32>), __VA_ARGS__); break;             \
+    case 48: hipLaunchKernelGGL((KERNEL<48>), __VA_ARGS__); break;             \
+    default: hipLaunchKernelGGL((KERNEL<64>), __VA_ARGS__); break;             \
+  }
+}  // namespace
+
+// (kl + ku <= 63: kl + 1 <= 64 rows in the registers of a column owner, and at
+// most 64 owners, all in the first wavefront)
+void band_lu(hipStream_t s, const int32_t *rp, const int32_t *ci, const z64 *va, const z64 *vb,
+             const z64 *z, int32_t N, int64_t n, int kl, int ku, z64 *Lf, z64 *Uf, z64 *Dinv,
+             int32_t *piv, int32_t *info) {
+  if (N <= 0 || n <= 0) return;
+  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_lu, dim3(N), dim3(256), 0, s, rp, ci, va, vb, z,
+                      n, kl, ku, Lf, Uf, Dinv, piv, info)
+}
+
+void band_solve(hipStream_t s, const z64 *Lf, const z64 *Uf, const z64 *Dinv, const int32_t *piv,
+                int32_t N, int64_t n, int kl, int ku, const z64 *R, int64_t ldr, int64_t m,
+                z64 *Y, int64_t ldy, int64_t sY) {
+  if (N <= 0 || n <= 0 || m <= 0) return;
+  const dim3 g(N, static_cast<unsigned>((m + 63) / 64));
+  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, g, dim3(64), 0, s, Lf, piv, n, kl, R, ldr, m,
+                      Y, ldy, sY)
+  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, g, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
+                      Y, ldy, sY)
+}
+
+void csr_spmm(hipStream_t s, const int32_t *rp, const int32_t *ci, const z64 *va, const z64 *vb,
+              int64_t n, const z64 *X, int64_t ldx, int64_t m, z64 *YA, int64_t ldya, z64 *YB,
+              int64_t ldyb) {
+  if (n <= 0 || m <= 0) return;
+  hipLaunchKernelGGL(k_csr_spmm, dim3(static_cast<unsigned>((n + 3) / 4)), dim3(256), 0, s, rp, ci,
+                     va, vb, n, X, ldx, m, YA, ldya, YB, ldyb);
+}
+
+void gather_vals(hipStream_t s, const int32_t *map, const z64 *src, int64_t cnt, z64 *dst) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_gather_vals, dim3(static_cast<unsigned>((cnt + 255) / 256)), dim3(256), 0, s,
+                     map, src, cnt, dst);
+}
+
+}  // namespace feast

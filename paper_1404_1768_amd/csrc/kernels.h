@@ -266,4 +266,27 @@ void conj_transpose(hipStream_t s, const z64 *X, int64_t ldx, int64_t rows, int6
 void scale_cols(hipStream_t s, z64 *X, int64_t ldx, int64_t n, int64_t c, const z64 *d);
 void identity(hipStream_t s, z64 *X, int64_t t);
 
+// Sparse pencils in band form (k_band.hip).  A and B are values va, vb on one
+// CSR pattern (rp, ci) whose entries lie within kl subdiagonals and ku
+// superdiagonals; M_j = z_j B - A.
+// Band LU with partial pivoting of every node (one workgroup each): Lf holds
+// node j's multipliers of column k at (j n + k) kl + i - 1 (rows k + i), Uf
+// its row k of U at (j n + k)(kl + ku + 1) + t (column k + t), Dinv the
+// reciprocal of U's diagonal entry k at j n + k, piv the row exchanged with k,
+// info the first zero-pivot column + 1 (0: none).
+void band_lu(hipStream_t s, const int32_t *rp, const int32_t *ci, const z64 *va, const z64 *vb,
+             const z64 *z, int32_t N, int64_t n, int kl, int ku, z64 *Lf, z64 *Uf, z64 *Dinv,
+             int32_t *piv, int32_t *info);
+// Y_j = M_j^{-1} R (R: n x m, ldr; node j's solution at Y + j sY, leading
+// dimension ldy) with the band factors above.
+void band_solve(hipStream_t s, const z64 *Lf, const z64 *Uf, const z64 *Dinv, const int32_t *piv,
+                int32_t N, int64_t n, int kl, int ku, const z64 *R, int64_t ldr, int64_t m,
+                z64 *Y, int64_t ldy, int64_t sY);
+// YA = A X, YB = B X on the shared pattern (a null output is skipped).
+void csr_spmm(hipStream_t s, const int32_t *rp, const int32_t *ci, const z64 *va, const z64 *vb,
+              int64_t n, const z64 *X, int64_t ldx, int64_t m, z64 *YA, int64_t ldya, z64 *YB,
+              int64_t ldyb);
+// dst[e] = src[map[e]], zero where map[e] < 0.
+void gather_vals(hipStream_t s, const int32_t *map, const z64 *src, int64_t cnt, z64 *dst);
+
 }  // namespace feast

@@ -99,6 +99,17 @@ struct feast_plan {
   double *hrn = nullptr;   // page-locked copy of rn[0..3) (read after the stream is idle)
   bool rho_pending = false;  // hrn holds a filter's first-correction norms not yet read
   DevBuf adj, adj_piv, adj_info, adj_inv;  // adjoint solves (allocated on first use)
+  // sparse pencil of the running feast_solve_csr call: the union pattern of A
+  // and B reordered by reverse Cuthill-McKee (row new holds old row perm[new]),
+  // A's and B's values on it, and the band factors of every node
+  struct Sparse {
+    bool on = false;
+    int kl = 0, ku = 0;
+    int64_t nnz = 0;
+    DevBuf rp, ci, va, vb, map, perm;
+    DevBuf Lf, Uf, Dinv, piv, info;
+    DevBuf V, X;  // start block and eigenvector block in the new order
+  } sp;
   DevBuf cirr_w;                           // Block_CIRR moment weights (g x N)
   std::string err;
   int last_sweeps = 0;       // mixed form: sweeps of the last filter

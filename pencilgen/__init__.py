@@ -252,13 +252,22 @@ TABLE1 = [
 ]
 
 
-def _pattern(rng, n: int, k: int, band: Optional[int]):
-    """``k`` random positions (i, j): anywhere, or within ``|i - j| <= band``."""
-    i = rng.integers(0, n, k)
+def _pattern(rng, n: int, k: int, band: Optional[int], upper: bool = False):
+    """``k`` random positions (i, j) anywhere (repeats possible), or, with
+    ``band``, ``k`` distinct off-diagonal positions with ``|i - j| <= band``
+    (``upper``: ``0 < j - i <= band``)."""
     if band is None:
+        i = rng.integers(0, n, k)
         return i, rng.integers(0, n, k)
-    j = np.clip(i + rng.integers(-band, band + 1, k), 0, n - 1)
-    return i, j
+    offs = np.arange(1, band + 1)
+    if not upper:
+        offs = np.concatenate([-offs[::-1], offs])
+    ci = np.repeat(np.arange(n), offs.size)
+    cj = ci + np.tile(offs, n)
+    ok = (cj >= 0) & (cj < n)
+    ci, cj = ci[ok], cj[ok]
+    sel = rng.choice(ci.size, min(k, ci.size), replace=False)
+    return ci[sel], cj[sel]
 
 
 def _sparse_real(rng, n: int, nnz: int, kind: str, band: Optional[int] = None) -> np.ndarray:
@@ -279,7 +288,7 @@ def _sparse_real(rng, n: int, nnz: int, kind: str, band: Optional[int] = None) -
     if kind == "spsd":  # the zeroed tenth of the rows and columns removes about 19%
         off = int(off / 0.81)
     half = max(off // 2, 0)
-    i, j = _pattern(rng, n, half, band)
+    i, j = _pattern(rng, n, half, band, upper=True)
     keep = i != j
     i, j = np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
     U = np.zeros((n, n))

@@ -1,10 +1,12 @@
 """Writes standin_contours.json: for each sparse-shaped stand-in of Table 1
 (pencilgen.sparse_standin), a circle around about 20 of its eigenvalues, the
 count inside and those reference eigenvalues, chosen from the dense reference
-spectrum.  Calls the oracle only (oracle.dense_eigenvalues,
+spectrum.  With --banded, the same for the banded variants of the stand-ins
+(non-zeros within a band of half-width ceil(nnz(A)/n)), written to
+standin_banded_contours.json.  Calls the oracle only (oracle.dense_eigenvalues,
 oracle.standin_contour).
 
-    python tests/golden/make_standin_contours.py
+    python tests/golden/make_standin_contours.py [--banded]
 """
 import json
 import os
@@ -18,9 +20,10 @@ from oracle import gfeast as o  # noqa: E402
 
 
 def main():
+    banded = "--banded" in sys.argv
     out = {}
     for k in range(1, len(pg.TABLE1) + 1):
-        name, A, B, _ = pg.sparse_standin(k)
+        name, A, B, _ = pg.sparse_standin(k, banded=banded)
         lam = o.dense_eigenvalues(A, B)
         c, r, s, gap = o.standin_contour(lam)
         ins = lam[abs(lam - c) < r]
@@ -28,7 +31,8 @@ def main():
                        "s": s, "gap": gap, "finite_eigenvalues": int(lam.size),
                        "inside": [[z.real, z.imag] for z in ins]}
         print(k, name, "s", s, "gap %.3f" % gap, flush=True)
-    with open(os.path.join(HERE, "standin_contours.json"), "w") as f:
+    fname = "standin_banded_contours.json" if banded else "standin_contours.json"
+    with open(os.path.join(HERE, fname), "w") as f:
         json.dump(out, f, indent=1)
 
 
