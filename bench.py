@@ -224,6 +224,102 @@ def time_standin(ks, steps, warmup):
             "problems": out}
 
 
+def time_stress():
+    """The n = 4000 workload under the literal reading of P, Q = I + c G with
+    unit-variance G (a labelled stress report): P and Q are then far from the
+    identity, cond(z_j B - A) grows by orders of magnitude, and e(k) may floor
+    above eps.  Both forms, one complete solve each (after one warm-up), flags
+    and e(k) history as measured."""
+    import torch
+    import pencilgen as pg
+    import paper_1404_1768_amd as fm
+    p = pg.workload(2, g_var=1.0)
+    A, B, V = (torch.from_numpy(x).to("cuda:0") for x in (p.A, p.B, p.V))
+    out = {"workload": "pencil n=4000 N=32 m=160 s=100 with G ~ CN(0, 1) (unit variance)"}
+    for form, prec in (("fp64", fm.FP64), ("mixed", fm.MIXED)):
+        plan = fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=prec, eps=1e-10)
+        try:
+            plan.solve(A, B, V, allow=(fm.FEAST_REFINE_STAGNATED,))
+            plan.invalidate()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = plan.solve(A, B, V, allow=(fm.FEAST_REFINE_STAGNATED,))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+        except fm.FeastError as e:
+            out[form] = {"error": str(e)}
+            log("[bench] stress %s: %s" % (form, e))
+            continue
+        finally:
+            plan.close()
+        out[form] = {"ms": round(ms, 1), "flag": r.flag, "iters": r.iters, "count": len(r.lam),
+                     "s": p.s, "err": r.err, "errs": [float("%.3g" % e) for e in r.errs],
+                     "sweeps": r.sweeps, "status": r.status}
+        log("[bench] stress %s: %s" % (form, out[form]))
+    del A, B, V
+    return out
+
+
+def time_sparse(ks, steps, warmup):
+    """Sparse pencils (feast_solve_csr) on the banded Table 1 stand-ins: the
+    same Algorithm 5 (Gauss-Legendre, 16 nodes, m = 40) on the pencil given in
+    CSR form -- ordering on the host, band LU and band solves on the GPU --
+    beside the dense path on the same pencil held dense (FP64 and mixed).  One
+    step = one complete solve; the count is checked against the stored
+    reference count."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+    import pencilgen as pg
+    import paper_1404_1768_amd as fm
+    with open(os.path.join(ROOT, "tests", "golden", "standin_banded_contours.json")) as f:
+        golden = json.load(f)
+
+    def csr(M):
+        S = sp.csr_matrix(M)
+        return (torch.from_numpy(S.indptr.astype(np.int32)).to("cuda:0"),
+                torch.from_numpy(S.indices.astype(np.int32)).to("cuda:0"),
+                torch.from_numpy(S.data.astype(np.complex128)).to("cuda:0"))
+
+    out = {}
+    for k in ks:
+        g = golden[str(k)]
+        name, A, B, V = pg.sparse_standin(k, banded=True)
+        c, n = complex(*g["center"]), g["n"]
+        cA, cB = csr(A), csr(B)
+        dA, dB, dV = (torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0") for x in (A, B, V))
+        row = {"n": n, "nnz_A": int(cA[1].numel()), "nnz_B": int(cB[1].numel()), "s_ref": g["s"]}
+        for form, prec, sparse in (("sparse_fp64", fm.FP64, True), ("dense_fp64", fm.FP64, False),
+                                   ("dense_mixed", fm.MIXED, False)):
+            plan = fm.Plan(n, 40, c, g["radius"], 16, rule=fm.GAUSS_LEGENDRE, eps=1e-10, prec=prec)
+            try:
+                run = (lambda: plan.solve_csr(cA, cB, dV)) if sparse else \
+                    (lambda: plan.solve(dA, dB, dV))
+                for _ in range(warmup):
+                    plan.invalidate()
+                    run()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    plan.invalidate()
+                    r = run()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / steps
+            finally:
+                plan.close()
+            row[form] = {"ms": ms, "iters": r.iters, "count": len(r.lam), "err": r.err,
+                         "ok": r.flag == 1 and r.err <= 1e-10 and len(r.lam) == g["s"],
+                         "phases_ms": {q: round(v, 2) for q, v in r.times.items()}}
+            if sparse:
+                row[form]["band"] = list(r.band)
+        log("[bench] sparse %s: %s" % (name, row))
+        out[name] = row
+        del dA, dB, dV
+    return {"workload": "banded Table 1 stand-ins (Table 1's n and nnz, non-zeros within "
+                        "ceil(nnz(A)/n) of the diagonal), Gauss-Legendre N=16, m=40, eps=1e-10",
+            "problems": out}
+
+
 def time_sparse_lu(ks):
     """Sparse LU against the dense MFMA LU at Table 1's orders.  For each
     stand-in, with its non-zeros placed at random or within a band of
@@ -439,6 +535,10 @@ def main():
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a PMC run")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the n=8000, m=256 mixed-precision workload (key 'large')")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the unit-variance G stress report (key 'stress')")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the sparse (CSR, band LU) leg on banded stand-ins (key 'sparse')")
     ap.add_argument("--sparse-lu", action="store_true",
                     help="add the SuperLU vs dense GPU LU comparison at Table 1's orders "
                          "(key 'sparse_lu'; about a minute of host time)")
@@ -515,6 +615,12 @@ def main():
                  "mixed": r}
         del lA, lB, lV
         torch.cuda.empty_cache()
+    stress = None
+    if not args.no_stress:
+        stress = time_stress()
+    sparse = None
+    if not args.no_sparse:
+        sparse = time_sparse((6, 7), min(args.steps, 2), 1)
     sparse_lu = None
     if args.sparse_lu:
         sparse_lu = time_sparse_lu(range(1, 8))
@@ -532,7 +638,7 @@ def main():
         "forms": forms, "roofline": roof, "hbm": b["hbm"], "cpu_baseline": cpu,
         "batched": batched,
         "search": search, "cirr": cirr, "adjoint": adjoint, "standin": standin,
-        "large": large, "sparse_lu": sparse_lu,
+        "large": large, "sparse": sparse, "stress": stress, "sparse_lu": sparse_lu,
     }
     print(json.dumps(out), flush=True)
 
