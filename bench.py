@@ -43,15 +43,15 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # HBM bytes per launch of the LU trailing update, from two rocprofv3 PMC passes
 # (FETCH_SIZE, then WRITE_SIZE) of this script with --forms mixed,fp64 --steps 1
 # --warmup 0 --no-batched --no-cpu-baseline --no-search --no-cirr --no-standin
-# --no-adjoint --no-large --copy-calibration, each scaled by what the counter
-# reads for the 1 GiB copy of --copy-calibration (fetch x2.000, write x1.000);
-# the summary and the commands are in profiles/.  The figures
-# hold for the kernel source they were taken on (its sha256), else `traffic`
-# is reported as null.
+# --no-adjoint --no-large --no-sparse --no-stress --copy-calibration, each
+# scaled by what the counter reads for the 1 GiB copy of --copy-calibration
+# (fetch x2.000, write x1.000); the summary and the commands are in profiles/.
+# The figures hold for the kernel source they were taken on (its sha256), else
+# `traffic` is reported as null.
 TRAFFIC = {"source": "paper_1404_1768_amd/csrc/k_gemm.hip",
-           "sha256": "29aef07bae04dbd0ad89fc79ea14471358221a2c84922589347a625c6ccb0bad",
-           "mixed": {"fetch": 1752231912, "write": 1310958233},
-           "fp64": {"fetch": 4131744068, "write": 2621916467}}
+           "sha256": "c679531747fa4d74b8a0f1ca7e623e4b2b8699eed4d621480bbbae8af989dcad",
+           "mixed": {"fetch": 1743640567, "write": 1310952816},
+           "fp64": {"fetch": 4215014675, "write": 2621905632}}
 
 
 def kernel_traffic(form):
