@@ -254,7 +254,9 @@ def time_stress():
             plan.close()
         out[form] = {"ms": round(ms, 1), "flag": r.flag, "iters": r.iters, "count": len(r.lam),
                      "s": p.s, "err": r.err, "errs": [float("%.3g" % e) for e in r.errs],
-                     "sweeps": r.sweeps, "status": r.status}
+                     "sweeps": r.sweeps, "status": r.status,
+                     "contraction": [float("%.3g" % c) for c in r.contraction],
+                     "fp64_fallback": r.fp64_fallback}
         log("[bench] stress %s: %s" % (form, out[form]))
     del A, B, V
     return out

@@ -189,6 +189,10 @@ typedef struct {
   double contraction[FEAST_MAX_HISTORY];
   /* feast_solve_csr: lower and upper bandwidth of the reordered pencil */
   int32_t band_kl, band_ku;
+  /* mixed form: the filter (1-based count, as in sweeps[]) after which the
+     solve switched to FP64 factors because that filter's contraction would
+     need more than max_sweeps corrections (or was not finite); 0: no switch */
+  int32_t fp64_fallback;
 } feast_info;
 
 /* GFEAST (Algorithm 5) with the subspace size fixed to m and a caller-supplied
@@ -210,7 +214,12 @@ typedef struct {
  * node solutions).  In the mixed form the no-improvement stop (flag 0) is
  * taken only once that verified refinement is on: an earlier rise of e(k)
  * switches it on and the iteration continues (the rise can come from the
- * complex64 solves rather than from the subspace).  Synchronises the stream. */
+ * complex64 solves rather than from the subspace).  When a refined filter's
+ * contraction rho = ||d_1|| / ||Y_0|| is not finite, or so slow that
+ * rho^(s+1) <= eps / 10 needs s > max_sweeps corrections, the solve refactors
+ * every node in FP64, repeats that filter and finishes in FP64
+ * (info->fp64_fallback); the plan is left unfactored in its mixed precision.
+ * Synchronises the stream. */
 int feast_solve(feast_plan *plan, const feast_z *dA, int64_t lda, const feast_z *dB,
                 int64_t ldb, const feast_z *dV, int64_t ldv, feast_z *hLambda,
                 feast_z *dX, int64_t ldx, double *hRes, int32_t *s_found, double *err,

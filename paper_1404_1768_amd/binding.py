@@ -79,7 +79,7 @@ class Info(C.Structure):
                 ("lu_gemm_launches", C.c_int32), ("lu_gemm_ms", C.c_double),
                 ("lu_gemm_flops", C.c_double), ("hbm", KProf * len(K_CLASSES)),
                 ("contraction", C.c_double * MAX_HISTORY),
-                ("band_kl", C.c_int32), ("band_ku", C.c_int32)]
+                ("band_kl", C.c_int32), ("band_ku", C.c_int32), ("fp64_fallback", C.c_int32)]
 
 
 class Csr(C.Structure):
@@ -347,6 +347,7 @@ class SolveResult:
     hbm: dict = dataclasses.field(default_factory=dict)
     contraction: list = dataclasses.field(default_factory=list)
     band: tuple = None     # feast_solve_csr: (kl, ku) of the reordered pencil
+    fp64_fallback: int = 0  # mixed form: filter after which the solve switched to FP64 (0: none)
 
 
 class Plan:
@@ -502,7 +503,7 @@ class Plan:
             hbm={name: {"launches": info.hbm[i].launches, "ms": info.hbm[i].ms,
                         "bytes": info.hbm[i].bytes}
                  for i, name in enumerate(K_CLASSES) if info.hbm[i].launches > 0},
-            contraction=list(info.contraction[:info.filters]))
+            contraction=list(info.contraction[:info.filters]), fp64_fallback=int(info.fp64_fallback))
 
     # -- Search (Algorithm 4) ----------------------------------------------
     def search(self, A, B, Ypool, p: int, alpha: float = 1.5, tau: float = 1e-3):

@@ -448,14 +448,17 @@ int filter_rhs(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t l
                bool resume = false) {
   if (cols < 0) cols = p->m;
   int st = ensure_factored(p, A, lda, B, ldb);
-  if (p->sp.on)
-    feast::band_solve(p->s, p->sp.Lf.as<z64>(), p->sp.Uf.as<z64>(), p->sp.Dinv.as<z64>(),
-                      p->sp.piv.as<int32_t>(), p->N, p->n, p->sp.kl, p->sp.ku, R, ldr, cols,
-                      p->Y.as<z64>(), p->ldY(), p->m);
-  else if (p->mixed())
+  if (p->mixed()) {
     solve_nodes_mixed(p, A, lda, B, ldb, R, ldr, target, sweeps, cols, resume);
-  else
-    solve_nodes_z(p, R, ldr, cols);
+  } else {
+    p->last_sweeps = 0;
+    if (p->sp.on)
+      feast::band_solve(p->s, p->sp.Lf.as<z64>(), p->sp.Uf.as<z64>(), p->sp.Dinv.as<z64>(),
+                        p->sp.piv.as<int32_t>(), p->N, p->n, p->sp.kl, p->sp.ku, R, ldr, cols,
+                        p->Y.as<z64>(), p->ldY(), p->m);
+    else
+      solve_nodes_z(p, R, ldr, cols);
+  }
   ktimed(p, FEAST_K_WSUM, 16.0 * p->n * cols * (p->N + 1), [&]() {
     feast::weighted_sum(p->s, p->Y.as<z64>(), p->ldY(), p->m, p->dw.as<z64>(), p->N, p->n, cols, U,
                         ldu);
@@ -917,6 +920,30 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     };
     int sweeps_now = sweeps;
     bool verify = false;
+    // FP64 fallback: a contraction that is not finite, or so slow that the
+    // corrections would need more than max_sweeps to bring the complex64
+    // solves to eps / 10, means refinement cannot make this pencil's filter as
+    // accurate as the FP64 form's (or only at more cost); the solve then
+    // refactors in FP64, repeats that filter and continues in FP64.  The plan
+    // returns to complex64 (unfactored) at the end.
+    auto needs_fp64 = [&](double rho) {
+      if (!(rho >= 0.0) || !std::isfinite(rho)) return true;
+      if (rho == 0.0) return false;
+      if (rho >= 1.0) return true;
+      const double goal = 0.1 * std::max(p->o.eps, 1e-15);
+      return std::ceil(std::log(goal) / std::log(rho)) - 1.0 > p->o.max_sweeps;
+    };
+    struct PrecRestore {
+      feast_plan *p;
+      bool on = false;
+      ~PrecRestore() {
+        if (on) {
+          p->o.prec = FEAST_MIXED;
+          p->factored = false;
+          p->checked = false;
+        }
+      }
+    } prec_restore{p};
     auto run_filter = [&](const z64 *R, z64 *Uout, bool first, bool resume = false) -> int {
       const double target = (!first && verify) ? p->o.refine_tol : 0.0;
       const int st = filter_rhs(p, A, lda, B, ldb, R, m, Uout, m, target, first ? 0 : sweeps_now,
@@ -1101,6 +1128,23 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
         const double rho = p->hrn[2] > 0.0 ? std::ldexp(std::sqrt(p->hrn[1] / p->hrn[2]), e) : 0.0;
         if (inf.filters >= 1 && inf.filters <= FEAST_MAX_HISTORY) inf.contraction[inf.filters - 1] = rho;
         predict_sweeps(rho);
+        if (p->mixed() && needs_fp64(rho)) {
+          HIPCHK(hipStreamSynchronize(s2));
+          HIPCHK(hipStreamSynchronize(p->side));
+          prec_restore.on = true;
+          p->o.prec = FEAST_FP64;
+          p->factored = false;
+          inf.fp64_fallback = inf.filters;
+          Timer tfac;
+          const int stf = ensure_factored(p, A, lda, B, ldb);
+          inf.t_factor_ms += tfac.ms();
+          if (stf == FEAST_SINGULAR) return stf;
+          Timer tw2;
+          const int st = run_filter(BU1, UF, false);
+          if (st != FEAST_OK) return st;
+          HIPCHK(hipStreamSynchronize(s));
+          inf.t_filter_ms += tw2.ms();
+        }
       }
       // QR step and the next reduced pencil (after the side stream is done with U_1)
       {
