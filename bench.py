@@ -46,25 +46,32 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # --no-adjoint --no-large --no-sparse --no-stress --copy-calibration, each
 # scaled by what the counter reads for the 1 GiB copy of --copy-calibration
 # (fetch x2.000, write x1.000); the summary and the commands are in profiles/.
-# The figures hold for the kernel source they were taken on (its sha256), else
-# `traffic` is reported as null.
-TRAFFIC = {"source": "paper_1404_1768_amd/csrc/k_gemm.hip",
-           "sha256": "c679531747fa4d74b8a0f1ca7e623e4b2b8699eed4d621480bbbae8af989dcad",
-           "mixed": {"fetch": 1743640567, "write": 1310952816},
-           "fp64": {"fetch": 4215014675, "write": 2621905632}}
+# The figures hold for the kernel and LU-driver sources they were taken on
+# (their sha256: the driver sets the launch shapes), else `traffic` is null.
+TRAFFIC = {"sources": {
+               "paper_1404_1768_amd/csrc/k_gemm.hip":
+                   "c679531747fa4d74b8a0f1ca7e623e4b2b8699eed4d621480bbbae8af989dcad",
+               "paper_1404_1768_amd/csrc/feast.cpp":
+                   "bd3e7cc49fa4ea8f95266304a9bfd834ea74e9d9d28b37e759d52719a67f5a2d"},
+           "mixed": {"fetch": 806053859, "write": 463280533},
+           "fp64": {"fetch": 2363068384, "write": 926561066}}
 
 
 def kernel_traffic(form):
+    """HBM bytes per launch of the trailing update (FETCH_SIZE + WRITE_SIZE, scaled),
+    or None unless every source the figures were taken on is unchanged."""
     import hashlib
-    path = os.path.join(ROOT, TRAFFIC["source"])
-    try:
-        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
-    except OSError:
-        return None
+    for path, want in TRAFFIC["sources"].items():
+        try:
+            sha = hashlib.sha256(open(os.path.join(ROOT, path), "rb").read()).hexdigest()
+        except OSError:
+            return None
+        if want is None or sha != want:
+            return None
     t = TRAFFIC.get(form)
-    if t is None or sha != TRAFFIC["sha256"]:
-        return None
-    return t["fetch"] + t["write"]
+    return None if t is None else t["fetch"] + t["write"]
+
+
 DTYPE = {"fp64": "complex128", "mixed": "complex64+complex128"}
 
 

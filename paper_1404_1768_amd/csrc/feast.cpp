@@ -178,6 +178,28 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
         timed_gemm(rest, rest - kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1 + kb1,
                    M + k1 * ld + k1 + kb1);
       HIPCHK(hipStreamWaitEvent(s, st.panel_done, 0));
+    } else if (k1 + kb1 < n) {
+      // two panels per trailing update (K = kb + kb1): the next panel's
+      // columns get this panel's update first, that panel is factored and its
+      // exchanges applied outside it (including to this panel's L21 and to the
+      // columns still waiting for this panel's update: exchanging rows of both
+      // commutes with the update), its rows get this panel's update, then its
+      // U12, and one update with both panels covers the rest.  Same flops as
+      // two single-panel steps; the trailing block is read and written once
+      // instead of twice.
+      const int64_t k2 = k1 + kb1, rest2 = n - k2;
+      timed_gemm(rest, kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
+      panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
+      feast::laswp_outside<T>(s, M, ld, stride, batch, n, k1, kb1, k1, k2, ipiv);
+      feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, kIB, k1 / kIB,
+                                   (k2 + kIB - 1) / kIB, true, Linv, istride);
+      timed_gemm(kb1, rest2, kb, M + k1 * ld + k0, M + k0 * ld + k2, M + k1 * ld + k2);
+      trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, k1, k2, M + k2, ld, stride, rest2,
+                        0);
+      timed_gemm(rest2, rest2, kb + kb1, M + k2 * ld + k0, M + k0 * ld + k2, M + k2 * ld + k2);
+      const int kb2 = static_cast<int>(std::min<int64_t>(nb, rest2));
+      panel_rec<T>(s, M, ld, stride, batch, n, k2, kb2, k2, kb2, ipiv, info);
+      k0 = k1;  // (the loop's step moves on to the panel at k2)
     } else {
       timed_gemm(rest, rest, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
       panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
