@@ -71,6 +71,12 @@ struct LuProf {
   double flops = 0.0;
 };
 
+// Tile of the solves' off-diagonal products X -= L X: complex128 takes the
+// trailing update's instance (three real products per complex step, BK = 8;
+// 2.6 ms less per FP64 solve at n = 4000), complex64's own tile already uses
+// three products and measured no faster on the update instance.
+template <typename T> constexpr int kSolveCfg = sizeof(T) == 16 ? feast::GEMM_UPDATE : feast::GEMM_SQUARE;
+
 // Diagonal blocks of the triangular factors are inverted in blocks of kIB rows;
 // this is also the leaf size of the recursive triangular solves.
 constexpr int kIB = 64;
@@ -96,7 +102,8 @@ void trsm_lower_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32
   trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, r0, mid, X, ldx, sX, ncols, ta, lb);
   if (ta == 0)  // X[mid:r1] -= L[mid:r1, r0:mid] X[r0:mid]
     gemm_t<T>(s, 0, r1 - mid, ncols, mid - r0, zc(-1.0), M + mid * ld + r0, ld, stride,
-              X + r0 * ldx, ldx, sX, zc(1.0), X + mid * ldx, ldx, sX, batch);
+              X + r0 * ldx, ldx, sX, zc(1.0), X + mid * ldx, ldx, sX, batch, nullptr, 0,
+              kSolveCfg<T>);
   else  // lower factor given as (U^*): rows [mid, r1) of U^* are columns of U rows [r0, mid)
     gemm_t<T>(s, 2, r1 - mid, ncols, mid - r0, zc(-1.0), M + r0 * ld + mid, ld, stride,
               X + r0 * ldx, ldx, sX, zc(1.0), X + mid * ldx, ldx, sX, batch);
@@ -120,7 +127,8 @@ void trsm_upper_rec(hipStream_t s, const T *M, int64_t ld, int64_t stride, int32
   trsm_upper_rec<T>(s, M, ld, stride, batch, Inv, istride, mid, r1, X, ldx, sX, ncols, ta, lb);
   if (ta == 0)  // X[r0:mid] -= U[r0:mid, mid:r1] X[mid:r1]
     gemm_t<T>(s, 0, mid - r0, ncols, r1 - mid, zc(-1.0), M + r0 * ld + mid, ld, stride,
-              X + mid * ldx, ldx, sX, zc(1.0), X + r0 * ldx, ldx, sX, batch);
+              X + mid * ldx, ldx, sX, zc(1.0), X + r0 * ldx, ldx, sX, batch, nullptr, 0,
+              kSolveCfg<T>);
   else  // rows [r0, mid) of L^* are columns of L rows [mid, r1)
     gemm_t<T>(s, 2, mid - r0, ncols, r1 - mid, zc(-1.0), M + mid * ld + r0, ld, stride,
               X + mid * ldx, ldx, sX, zc(1.0), X + r0 * ldx, ldx, sX, batch);
