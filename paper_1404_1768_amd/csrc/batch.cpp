@@ -239,11 +239,17 @@ feast_plan *member_plan(int64_t n, int64_t m, const feast_contour &c, const feas
   return p;
 }
 
-// Grouped product over a list of problems (skipped when empty).
+// Grouped product over a list of problems (skipped when empty).  Without an
+// explicit variant, complex128 products C -= A B (triangular solves, panel
+// joins) take the three-product loop (fewer MFMAs; its FP64 rounding stays far
+// below the tolerances), everything else the plain loop; the trailing update
+// passes the autotuned variant.
 template <typename T>
 void ggemm(feast_batch *b, Tables &tab, int ta, bool sub, std::vector<GemmArgs<T>> &e,
-           int variant = feast::GROUP_PLAIN) {
+           int variant = -1) {
   if (e.empty()) return;
+  if (variant < 0)
+    variant = (sub && ta == 0 && sizeof(T) == 16) ? feast::GROUP_UPDATE_M3 : feast::GROUP_PLAIN;
   const int64_t tiles = feast::gemm_group_tiles<T>(e.data(), static_cast<int>(e.size()));
   const GemmArgs<T> *d = tab.put(e);
   if (!tab.record)
