@@ -50,11 +50,11 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # (their sha256: the driver sets the launch shapes), else `traffic` is null.
 TRAFFIC = {"sources": {
                "paper_1404_1768_amd/csrc/k_gemm.hip":
-                   "c679531747fa4d74b8a0f1ca7e623e4b2b8699eed4d621480bbbae8af989dcad",
+                   "ee3b5f78e5afef841903fe384cb5c978d59de53d713345af8819be176324e8de",
                "paper_1404_1768_amd/csrc/feast.cpp":
-                   "bd3e7cc49fa4ea8f95266304a9bfd834ea74e9d9d28b37e759d52719a67f5a2d"},
-           "mixed": {"fetch": 806053859, "write": 463280533},
-           "fp64": {"fetch": 2363068384, "write": 926561066}}
+                   "1af9352a5d40f5e850b778cb0f01f56c30c236e15bf839eecb91de107688352c"},
+           "mixed": {"fetch": 806422430, "write": 463278968},
+           "fp64": {"fetch": 2059700691, "write": 583602683}}
 
 
 def kernel_traffic(form):

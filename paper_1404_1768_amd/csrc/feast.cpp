@@ -72,14 +72,20 @@ struct LuProf {
 };
 
 // Tile of the solves' off-diagonal products X -= L X: complex128 takes the
-// trailing update's instance (three real products per complex step, BK = 8;
-// 2.6 ms less per FP64 solve at n = 4000), complex64's own tile already uses
-// three products and measured no faster on the update instance.
-template <typename T> constexpr int kSolveCfg = sizeof(T) == 16 ? feast::GEMM_UPDATE : feast::GEMM_SQUARE;
+// trailing update's tile (three real products per complex step, BK = 8; 2.6 ms
+// less per FP64 solve at n = 4000), complex64's own tile already uses three
+// products and measured no faster on the update's.
+template <typename T> constexpr int kSolveCfg = sizeof(T) == 16 ? feast::GEMM_SOLVE : feast::GEMM_SQUARE;
 
 // Diagonal blocks of the triangular factors are inverted in blocks of kIB rows;
 // this is also the leaf size of the recursive triangular solves.
 constexpr int kIB = 64;
+
+// Panels per trailing update of the LU (the update's K is their total width):
+// at n = 4000, three for complex128 (factor 128.3 -> 126.8 ms against two)
+// and two for complex64 (three: 72.7 -> 73.1 ms, the narrow updates of the
+// third panel cost more than the wider update saves).
+template <typename T> constexpr int kGroup = sizeof(T) == 16 ? 3 : 2;
 
 // X <- L^{-1} X for the unit-lower L = M[r0:r1, r0:r1] (r0 a multiple of kIB)
 // and X = rows [r0, r1) of the block with columns starting at Xc (leading
@@ -187,27 +193,32 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
                    M + k1 * ld + k1 + kb1);
       HIPCHK(hipStreamWaitEvent(s, st.panel_done, 0));
     } else if (k1 + kb1 < n) {
-      // two panels per trailing update (K = kb + kb1): the next panel's
-      // columns get this panel's update first, that panel is factored and its
-      // exchanges applied outside it (including to this panel's L21 and to the
-      // columns still waiting for this panel's update: exchanging rows of both
-      // commutes with the update), its rows get this panel's update, then its
-      // U12, and one update with both panels covers the rest.  Same flops as
-      // two single-panel steps; the trailing block is read and written once
-      // instead of twice.
-      const int64_t k2 = k1 + kb1, rest2 = n - k2;
-      timed_gemm(rest, kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
-      panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
-      feast::laswp_outside<T>(s, M, ld, stride, batch, n, k1, kb1, k1, k2, ipiv);
-      feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, kIB, k1 / kIB,
-                                   (k2 + kIB - 1) / kIB, true, Linv, istride);
-      timed_gemm(kb1, rest2, kb, M + k1 * ld + k0, M + k0 * ld + k2, M + k1 * ld + k2);
-      trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, k1, k2, M + k2, ld, stride, rest2,
-                        0);
-      timed_gemm(rest2, rest2, kb + kb1, M + k2 * ld + k0, M + k0 * ld + k2, M + k2 * ld + k2);
-      const int kb2 = static_cast<int>(std::min<int64_t>(nb, rest2));
-      panel_rec<T>(s, M, ld, stride, batch, n, k2, kb2, k2, kb2, ipiv, info);
-      k0 = k1;  // (the loop's step moves on to the panel at k2)
+      // up to kGroup<T> panels per trailing update (K = their total width): each
+      // further panel's columns get the group's earlier panels' update, that
+      // panel is factored and its exchanges applied outside it (including to
+      // the group's L21 columns and to the columns still waiting for the
+      // group's update: exchanging rows of both commutes with the update), its
+      // rows get the same update, then its U12; one update with all the
+      // group's panels covers the rest.  Same flops as one step per panel; the
+      // trailing block is read and written once per group.
+      int64_t kg = k1;  // end of the group's factored panels
+      for (int g = 1; g < kGroup<T> && kg + nb < n; ++g) {
+        const int64_t ks = kg, ke = kg + nb;
+        timed_gemm(n - ks, static_cast<int>(nb), ks - k0, M + ks * ld + k0, M + k0 * ld + ks,
+                   M + ks * ld + ks);
+        panel_rec<T>(s, M, ld, stride, batch, n, ks, nb, ks, nb, ipiv, info);
+        feast::laswp_outside<T>(s, M, ld, stride, batch, n, ks, nb, ks, ke, ipiv);
+        feast::diag_block_inverse<T>(s, M, ld, stride, batch, n, kIB, ks / kIB,
+                                     (ke + kIB - 1) / kIB, true, Linv, istride);
+        timed_gemm(nb, n - ke, ks - k0, M + ks * ld + k0, M + k0 * ld + ke, M + ks * ld + ke);
+        trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, ks, ke, M + ke, ld, stride,
+                          n - ke, 0);
+        kg = ke;
+      }
+      timed_gemm(n - kg, n - kg, kg - k0, M + kg * ld + k0, M + k0 * ld + kg, M + kg * ld + kg);
+      const int kbn = static_cast<int>(std::min<int64_t>(nb, n - kg));
+      panel_rec<T>(s, M, ld, stride, batch, n, kg, kbn, kg, kbn, ipiv, info);
+      k0 = kg - nb;  // (the loop's step moves on to the panel at kg)
     } else {
       timed_gemm(rest, rest, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
       panel_rec<T>(s, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);

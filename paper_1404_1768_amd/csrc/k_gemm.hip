@@ -454,6 +454,15 @@ void k_gemm(const GemmArgs<T> d, int64_t grid_total) {
   gemm_tile<T, BM, BN, TA, SUB, BK, kM3<T> || UPD>(d, xcd_remap(blockIdx.x, grid_total));
 }
 
+// C -= A B of the triangular solves (GEMM_SOLVE): the trailing update's tile
+// (three real products per complex step, BK = 8) under a name of its own, so
+// kernel traces and counters time the update alone.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<T, 64>)))
+void k_gemm_solve(const GemmArgs<T> d, int64_t grid_total) {
+  gemm_tile<T, 64, 64, 0, true, 8, true>(d, xcd_remap(blockIdx.x, grid_total));
+}
+
 // C_b = C0_b - (shift[b] A2 - A) B_b (FP64: three-product form at BK = 8, as the
 // trailing update).
 template <typename T, int BK>
@@ -591,10 +600,18 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
       d.splits = static_cast<int32_t>((d.K + d.kchunk - 1) / d.kchunk);
     }
   }
-  if (cfg == GEMM_TALL || cfg == GEMM_UPDATE_TALL)
+  const bool sub = d.splits == 1 && d.alpha.x == -1.0 && d.alpha.y == 0.0 && d.beta.x == 1.0 &&
+                   d.beta.y == 0.0;
+  if (cfg == GEMM_SOLVE && ta == 0 && sub) {
+    const int64_t tiles2 = ((d.M + 63) / 64) * ((d.N + 63) / 64) * d.batch;
+    const int64_t padded = (tiles2 + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_gemm_solve<T>), dim3(static_cast<unsigned>(padded)), dim3(256), 0, s, d,
+                       padded);
+  } else if (cfg == GEMM_TALL || cfg == GEMM_UPDATE_TALL) {
     launch_cfg<T, 128, 64>(s, d, ta, cfg == GEMM_UPDATE_TALL);
-  else
+  } else {
     launch_cfg<T, 64, 64>(s, d, ta, cfg == GEMM_UPDATE);
+  }
   if (d.splits > 1) {
     const int64_t n = d.M * d.N * d.batch;
     hipLaunchKernelGGL((k_splitk_reduce<T>), dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256),

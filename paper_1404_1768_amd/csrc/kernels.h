@@ -43,8 +43,10 @@ void zgemm_shift_residual(hipStream_t s, int64_t M, int64_t N, int64_t K, const 
                           int64_t sC, int32_t batch);
 
 // GEMM_UPDATE / GEMM_UPDATE_TALL: the 64 x 64 / 128 x 64 configurations under
-// kernel names of their own (the LU trailing update).
-enum { GEMM_SQUARE = 0, GEMM_TALL = 1, GEMM_UPDATE = 3, GEMM_UPDATE_TALL = 4 };
+// kernel names of their own (the LU trailing update); GEMM_SOLVE: C -= A B
+// (no transpose) on the update's 64 x 64 tile under a third name (the
+// triangular solves), other products as GEMM_SQUARE.
+enum { GEMM_SQUARE = 0, GEMM_TALL = 1, GEMM_UPDATE = 3, GEMM_UPDATE_TALL = 4, GEMM_SOLVE = 5 };
 
 // C_b = alpha op(A_b) B_b + beta C_b; transA 0: A is M x K; 2: A stored K x M, op = ^*.
 // `work` (optional, work_elems entries) enables split-K for small outputs.
