@@ -90,15 +90,20 @@ typedef struct {
   int32_t nb;          /* LU panel width: 64 or 128, 0 = automatic (128) */
   int32_t profile;     /* 1: time the LU trailing-update GEMM launches with HIP events on
                           the plan's stream (reported in feast_info); default 0 */
-  int32_t lookahead;   /* 1: factor the next panel on a second stream while the trailing
-                          matrix is updated; 0: panels and updates in sequence (default 0: the panel
-                          kernels need whole compute units, which the update holds,
-                          so the overlap measured slower) */
+  int32_t lookahead;   /* 1: factor the next panel on a second stream while the rest of the
+                          trailing matrix is updated by persistent workgroups that leave
+                          ahead_cus compute units free for it; 0: panels and updates in
+                          sequence (default 0: at n = 4000 the overlap gains 1-2 % of the
+                          factorisation, the persistent update being slower per flop) */
   int32_t update_tile; /* LU trailing-update tile: 0 = 64 x 64, 1 = 128 x 64 (default 0) */
   int32_t batch_update; /* batched form's trailing-update loop: 0 = from the tuned table
                            (with nb = 0 for the panel width too), 1 = four real products per
                            complex step, 2 = three products, operand-pipelined (complex128;
                            complex64 takes 1), 3 = four products, operand-pipelined (default 0) */
+  int32_t ahead_cus;   /* look-ahead: compute units left to the panel factorisation, 8 to 128
+                          (0 = 32) */
+  int32_t ahead_rows;  /* look-ahead: only steps whose trailing block has at most this many
+                          rows look ahead, the others run in sequence (0 = 2048) */
 } feast_opts;
 
 /* Fill *o with the defaults listed above. */

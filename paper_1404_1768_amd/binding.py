@@ -59,7 +59,8 @@ class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("eta", C.c_double), ("max_iter", C.c_int32),
                 ("prec", C.c_int32), ("refine_tol", C.c_double), ("max_sweeps", C.c_int32),
                 ("nb", C.c_int32), ("profile", C.c_int32), ("lookahead", C.c_int32),
-                ("update_tile", C.c_int32), ("batch_update", C.c_int32)]
+                ("update_tile", C.c_int32), ("batch_update", C.c_int32),
+                ("ahead_cus", C.c_int32), ("ahead_rows", C.c_int32)]
 
 
 K_CLASSES = ["shift", "weighted_sum", "gather_rows", "z_to_c", "c_to_z", "fingerprint"]
@@ -358,6 +359,7 @@ class Plan:
                  max_iter: int = 20, prec: int = FP64, refine_tol: Optional[float] = None,
                  max_sweeps: int = 6, nb: int = 0, profile: bool = False,
                  lookahead: Optional[bool] = None, update_tile: Optional[int] = None,
+                 ahead_cus: Optional[int] = None, ahead_rows: Optional[int] = None,
                  stream=None):
         self.lib = load()
         self.n, self.m = int(n), int(m)
@@ -370,6 +372,10 @@ class Plan:
             self.opts.lookahead = 1 if lookahead else 0
         if update_tile is not None:
             self.opts.update_tile = int(update_tile)
+        if ahead_cus is not None:
+            self.opts.ahead_cus = int(ahead_cus)
+        if ahead_rows is not None:
+            self.opts.ahead_rows = int(ahead_rows)
         if refine_tol is not None:
             self.opts.refine_tol = float(refine_tol)
         self._stream_obj = stream

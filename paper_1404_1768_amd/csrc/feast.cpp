@@ -146,7 +146,25 @@ struct LuStreams {
   hipStream_t main = nullptr, side = nullptr;
   hipEvent_t cols_ready = nullptr, panel_done = nullptr;
   int update_cfg = feast::GEMM_UPDATE;  // tile of the trailing update
+  int upd_wgs = 0;                      // look-ahead: persistent workgroups of the rest's update
+  int64_t ahead_rows = 0;               // look-ahead: most trailing rows of a look-ahead step
 };
+
+template <typename T>
+void update_persistent_t(hipStream_t s, int64_t M, int64_t N, int64_t K, const T *A, const T *B,
+                         T *C, int64_t ld, int64_t stride, int32_t batch, int wgs);
+template <>
+void update_persistent_t<z64>(hipStream_t s, int64_t M, int64_t N, int64_t K, const z64 *A,
+                              const z64 *B, z64 *C, int64_t ld, int64_t stride, int32_t batch,
+                              int wgs) {
+  feast::zupdate_persistent(s, M, N, K, A, ld, stride, B, ld, stride, C, ld, stride, batch, wgs);
+}
+template <>
+void update_persistent_t<c64>(hipStream_t s, int64_t M, int64_t N, int64_t K, const c64 *A,
+                              const c64 *B, c64 *C, int64_t ld, int64_t stride, int32_t batch,
+                              int wgs) {
+  feast::cupdate_persistent(s, M, N, K, A, ld, stride, B, ld, stride, C, ld, stride, batch, wgs);
+}
 
 template <typename T>
 void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t batch, int64_t n,
@@ -155,11 +173,16 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
   hipStream_t s = st.main;
   const bool ahead = st.side != nullptr;
   feast::fill_i32(s, info, batch, 0);
-  auto timed_gemm = [&](int64_t rows, int64_t cols, int64_t kb, const T *Ap, const T *Bp, T *Cp) {
+  // wgs > 0: the update on that many persistent workgroups (the look-ahead's)
+  auto timed_gemm = [&](int64_t rows, int64_t cols, int64_t kb, const T *Ap, const T *Bp, T *Cp,
+                        int wgs = 0) {
     const bool timed = prof && prof->ev && prof->used + 2 <= static_cast<int>(prof->ev->size());
     if (timed) HIPCHK(hipEventRecord((*prof->ev)[prof->used], s));
-    gemm_t<T>(s, 0, rows, cols, kb, zc(-1.0), Ap, ld, stride, Bp, ld, stride, zc(1.0), Cp, ld,
-              stride, batch, nullptr, 0, st.update_cfg);
+    if (wgs > 0)
+      update_persistent_t<T>(s, rows, cols, kb, Ap, Bp, Cp, ld, stride, batch, wgs);
+    else
+      gemm_t<T>(s, 0, rows, cols, kb, zc(-1.0), Ap, ld, stride, Bp, ld, stride, zc(1.0), Cp, ld,
+                stride, batch, nullptr, 0, st.update_cfg);
     if (timed) {
       HIPCHK(hipEventRecord((*prof->ev)[prof->used + 1], s));
       prof->used += 2;
@@ -180,17 +203,19 @@ void lu_batched(const LuStreams &st, T *M, int64_t ld, int64_t stride, int32_t b
     // U12 = L11^{-1} A12
     trsm_lower_rec<T>(s, M, ld, stride, batch, Linv, istride, k0, k1, M + k1, ld, stride, rest, 0);
     const int kb1 = static_cast<int>(std::min<int64_t>(nb, rest));
-    if (ahead) {
-      // look-ahead: update the next panel's columns, factor that panel on the
-      // side stream while the rest of the trailing matrix is updated here
+    if (ahead && rest > kb1 && rest <= st.ahead_rows) {
+      // look-ahead: update the next panel's columns (whole chip), then factor
+      // that panel on the side stream while the rest of the trailing matrix is
+      // updated here by persistent workgroups that leave compute units to it
+      // (only once the trailing block is short enough that the panel's
+      // latency-bound kernels take a good part of a step)
       timed_gemm(rest, kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1, M + k1 * ld + k1);
       HIPCHK(hipEventRecord(st.cols_ready, s));
       HIPCHK(hipStreamWaitEvent(st.side, st.cols_ready, 0));
       panel_rec<T>(st.side, M, ld, stride, batch, n, k1, kb1, k1, kb1, ipiv, info);
       HIPCHK(hipEventRecord(st.panel_done, st.side));
-      if (rest > kb1)
-        timed_gemm(rest, rest - kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1 + kb1,
-                   M + k1 * ld + k1 + kb1);
+      timed_gemm(rest, rest - kb1, kb, M + k1 * ld + k0, M + k0 * ld + k1 + kb1,
+                 M + k1 * ld + k1 + kb1, st.upd_wgs);
       HIPCHK(hipStreamWaitEvent(s, st.panel_done, 0));
     } else if (k1 + kb1 < n) {
       // up to kGroup<T> panels per trailing update (K = their total width): each
@@ -290,8 +315,11 @@ int factor(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int64_t ldb) 
     prof.ev = &p->ev;
   }
   hipStream_t sl = s;
+  const int ahead_cus = p->o.ahead_cus ? p->o.ahead_cus : 32;
   const LuStreams lst{sl, p->o.lookahead ? p->side : nullptr, p->ev_cols, p->ev_panel,
-                      p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE};
+                      p->o.update_tile ? feast::GEMM_UPDATE_TALL : feast::GEMM_UPDATE,
+                      std::max(8, p->cus - ahead_cus),
+                      p->o.ahead_rows ? p->o.ahead_rows : 2048};
   if (p->mixed()) {
     ktimed(p, FEAST_K_SHIFT, (32.0 + 8.0 * N) * n * n, [&]() {
       feast::shift_assemble_c(sl, A, lda, B, ldb, p->dz.as<z64>(), N, n, p->F.as<c64>(), n, n * n);
@@ -726,6 +754,8 @@ void feast_opts_default(feast_opts *o) {
   o->profile = 0;
   o->lookahead = 0;
   o->update_tile = 0;
+  o->ahead_cus = 0;
+  o->ahead_rows = 0;
   o->batch_update = 0;
 }
 
@@ -777,7 +807,9 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
       opts.max_sweeps < 0 || !(opts.refine_tol >= 0.0) ||
       (opts.nb != 0 && opts.nb != 64 && opts.nb != 128) || opts.lookahead < 0 ||
       opts.lookahead > 1 || opts.update_tile < 0 || opts.update_tile > 1 ||
-      opts.batch_update < 0 || opts.batch_update > 3)
+      opts.batch_update < 0 || opts.batch_update > 3 ||
+      (opts.ahead_cus != 0 && (opts.ahead_cus < 8 || opts.ahead_cus > 128)) ||
+      opts.ahead_rows < 0)
     return FEAST_EINVAL;
   feast_plan *p = nullptr;
   try {
@@ -810,6 +842,9 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
     HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&p->hrn), 4 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(hipEventCreateWithFlags(&p->ev_cols, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&p->ev_panel, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));

@@ -60,6 +60,17 @@ void cgemm(hipStream_t s, int transA, int64_t M, int64_t N, int64_t K, z64 alpha
            int64_t ldc, int64_t sC, int32_t batch, c64 *work = nullptr, int64_t work_elems = 0,
            int cfg = GEMM_SQUARE);
 
+// The LU trailing update C_b -= A_b B_b (row-major, batch strided, the tile of
+// GEMM_UPDATE) on `wgs` persistent workgroups (rounded down to a multiple of
+// 8, at least 8, at most what the tiles need), each of which takes a whole
+// compute unit: the units beyond `wgs` stay free for work on other streams.
+void zupdate_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, const z64 *A, int64_t lda,
+                        int64_t sA, const z64 *B, int64_t ldb, int64_t sB, z64 *C, int64_t ldc,
+                        int64_t sC, int32_t batch, int wgs);
+void cupdate_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, const c64 *A, int64_t lda,
+                        int64_t sA, const c64 *B, int64_t ldb, int64_t sB, c64 *C, int64_t ldc,
+                        int64_t sC, int32_t batch, int wgs);
+
 // Grouped product: `count` independent problems (each a uniform batch, 64 x 64
 // tiles, no split-K) in one launch.  gemm_group_tiles fills tile0 (and splits,
 // kchunk) of a host table and returns the total tile count; the launch reads

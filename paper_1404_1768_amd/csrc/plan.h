@@ -118,6 +118,7 @@ struct feast_plan {
   // opts.profile: events around the LU trailing-update GEMMs
   std::vector<hipEvent_t> ev;
   hipStream_t side = nullptr;                 // look-ahead panel stream
+  int cus = 256;                              // compute units of the plan's device
   hipStream_t aux = nullptr;                  // Ritz vectors/residuals overlapping a filter
   hipEvent_t ev_cols = nullptr, ev_panel = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // A U_1 on the side stream in the projection

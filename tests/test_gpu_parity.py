@@ -239,14 +239,16 @@ def test_solve_scaled_workloads(k, n, prec):
 
 
 @pytest.mark.parametrize("prec", [fm.FP64, fm.MIXED])
-@pytest.mark.parametrize("update_tile", [0, 1])
-def test_solve_lookahead_and_tall_update(prec, update_tile):
-    # the look-ahead factorisation (next panel on a second stream) and the
-    # 128-row trailing-update tile against the oracle
+@pytest.mark.parametrize("update_tile,ahead_cus", [(0, 32), (1, 8), (0, 128)])
+def test_solve_lookahead_and_tall_update(prec, update_tile, ahead_cus):
+    # the look-ahead factorisation (next panel on a second stream while
+    # persistent workgroups update the rest; every step looks ahead, so the
+    # persistent update meets ragged blocks down to one 64-row tile row) and
+    # the 128-row trailing-update tile against the oracle
     p = pg.workload(2, n_override=1000)
     A, B, V = to_dev(p.A, p.B, p.V)
     with fm.Plan(p.n, p.m, p.center, p.radius, p.nodes, prec=prec, lookahead=True,
-                 update_tile=update_tile) as plan:
+                 update_tile=update_tile, ahead_cus=ahead_cus, ahead_rows=1 << 20) as plan:
         r = plan.solve(A, B, V)
     ref = o.gfeast(p.A, p.B, p.V, p.center, p.radius, p.nodes)
     assert r.flag == 1 and ref.flag == 1
