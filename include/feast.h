@@ -98,8 +98,8 @@ typedef struct {
   int32_t update_tile; /* LU trailing-update tile: 0 = 64 x 64, 1 = 128 x 64 (default 0) */
   int32_t batch_update; /* batched form's trailing-update loop: 0 = from the tuned table
                            (with nb = 0 for the panel width too), 1 = four real products per
-                           complex step, 2 = three products, operand-pipelined (complex128;
-                           complex64 takes 1), 3 = four products, operand-pipelined (default 0) */
+                           complex step, 2 = three products, operand-pipelined, 3 = four
+                           products, operand-pipelined (default 0) */
   int32_t ahead_cus;   /* look-ahead: compute units left to the panel factorisation, 8 to 128
                           (0 = 32) */
   int32_t ahead_rows;  /* look-ahead: only steps whose trailing block has at most this many

@@ -3,7 +3,7 @@
 For every order bucket and precision it factors a synthetic batch under each
 candidate configuration -- panel width 64 or 128, and the loop of the grouped
 trailing update (four real products per complex step; three products with
-operand pipelining, complex128 only; four products with operand pipelining) --
+operand pipelining; four products with operand pipelining) --
 and writes the fastest per bucket to ``csrc/batch_tune.h``, which
 ``feast_batch_create`` consults (rebuild the library afterwards).
 
@@ -30,9 +30,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 BUCKETS = [(64, 384, 48), (384, 768, 32), (768, 1536, 24), (1536, 3072, 12), (3072, 16385, 4)]
 FP64, MIXED = 0, 1
 # candidates: (panel width, opts.batch_update): 1 = four products, 2 = three
-# products pipelined (complex128), 3 = four products pipelined
+# products pipelined, 3 = four products pipelined
 CANDIDATES = {FP64: [(64, 1), (64, 2), (64, 3), (128, 1), (128, 2), (128, 3)],
-              MIXED: [(64, 1), (64, 3), (128, 1), (128, 3)]}
+              MIXED: [(64, 1), (64, 2), (64, 3), (128, 1), (128, 2), (128, 3)]}
 # batch_update value -> the library's feast::GROUP_* code
 GROUP_CODE = {1: 0, 2: 1, 3: 2}
 

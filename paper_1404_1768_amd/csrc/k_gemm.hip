@@ -466,10 +466,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin, boo
 // Complex products take three real MFMAs per step (M3) in the single-problem
 // complex64 kernels and in the FP64 trailing update (where the extra LDS plane
 // and accumulators still allow two workgroups per compute unit at BK = 8).
-// Other FP64 products, and the grouped kernels of every type, keep four: the
-// grouped complex64 LU of the batched form loses enough backward accuracy with
-// three that a pencil near the tolerance needs one more refinement iteration,
-// which costs far more than the multiplications saved.
+// Other FP64 products and the plain grouped kernels keep four (the grouped
+// trailing update has a three-product form of its own, k_gemm_grp_upd).
 template <typename T> constexpr bool kM3 = sizeof(T) == 8;
 
 // Waves per SIMD the register allocation must leave room for (512 registers a
@@ -563,11 +561,11 @@ void k_gemm_grp(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid_tot
   gemm_tile<T, BM, BN, TA, SUB, BK, false, false, false>(d, lin - d.tile0);
 }
 
-// The grouped FP64 LU trailing update C -= A B with the single-problem
-// update's loop: three real products per complex step, next operands read
-// from LDS while the MFMAs issue, BK = 8 and the two-wave register budget.
-// (FP64 rounding of the three-product form stays far below the tolerances;
-// the complex64 grouped update keeps four products, see above.)
+// The grouped LU trailing update C -= A B with the single-problem update's
+// loop: three real products per complex step, next operands read from LDS
+// while the MFMAs issue, BK = 8 (complex128 in the two-wave register budget,
+// complex64 at four workgroups per compute unit).  The batched form picks it
+// (or a four-product loop) per precision and order from its tuned table.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves<T, 64>)))
 void k_gemm_grp_upd(const GemmArgs<T> *__restrict__ tab, int count, int64_t grid_total) {
@@ -709,7 +707,7 @@ void gemm_group(hipStream_t s, int ta, bool sub, const GemmArgs<T> *dtab, int co
   const int64_t padded = (total_tiles + 7) / 8 * 8;
   const dim3 grid(static_cast<unsigned>(padded));
   if (ta == 0) {
-    if (sub && variant == GROUP_UPDATE_M3 && sizeof(T) == 16)
+    if (sub && variant == GROUP_UPDATE_M3)
       hipLaunchKernelGGL((k_gemm_grp_upd<T>), grid, dim3(256), 0, s, dtab, count, padded);
     else if (sub && variant == GROUP_UPDATE_PIPE)
       hipLaunchKernelGGL((k_gemm_grp_pipe<T>), grid, dim3(256), 0, s, dtab, count, padded);

@@ -77,9 +77,9 @@ void cupdate_persistent(hipStream_t s, int64_t M, int64_t N, int64_t K, const c6
 // the table from device memory.  sub: every problem is C -= A B (alpha = -1,
 // beta = 1); ta: 0 or 2 (2 only with sub = false).
 //   variant (sub = true, ta = 0 only): GROUP_PLAIN (four real products per
-//   complex step, unpipelined, BK = 16); GROUP_UPDATE_M3: complex128 problems
-//   on the three-product, operand-pipelined loop (BK = 8), complex64 ones on the
-//   plain loop; GROUP_UPDATE_PIPE: four products on the operand-pipelined loop.
+//   complex step, unpipelined, BK = 16); GROUP_UPDATE_M3: the three-product,
+//   operand-pipelined loop (BK = 8); GROUP_UPDATE_PIPE: four products on the
+//   operand-pipelined loop.
 enum { GROUP_PLAIN = 0, GROUP_UPDATE_M3 = 1, GROUP_UPDATE_PIPE = 2 };
 template <typename T> int64_t gemm_group_tiles(GemmArgs<T> *tab, int count);
 template <typename T>
