@@ -50,11 +50,11 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # (their sha256: the driver sets the launch shapes), else `traffic` is null.
 TRAFFIC = {"sources": {
                "paper_1404_1768_amd/csrc/k_gemm.hip":
-                   "ee3b5f78e5afef841903fe384cb5c978d59de53d713345af8819be176324e8de",
+                   "bf8f9ce9641e0480b9b97476b4e73c4d5de0b73c1c81de7c371ebaee4df62521",
                "paper_1404_1768_amd/csrc/feast.cpp":
-                   "1af9352a5d40f5e850b778cb0f01f56c30c236e15bf839eecb91de107688352c"},
-           "mixed": {"fetch": 806422430, "write": 463278968},
-           "fp64": {"fetch": 2059700691, "write": 583602683}}
+                   "6681cc0d408d2ac89c4b4388198c8727ee0b9e8f224638e2cad41eb543ce1f9b"},
+           "mixed": {"fetch": 805239011, "write": 463278085},
+           "fp64": {"fetch": 2019915060, "write": 583601570}}
 
 
 def kernel_traffic(form):
