@@ -1056,6 +1056,7 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
     HIPCHK(hipStreamWaitEvent(s2, p->ev_cols, 0));
     // e(0) = 0, c(0) = 0
     double e_prev = 0.0, e_prev2 = 0.0;
+    double last_filter_ms = 0.0, last_host_ms = 0.0;  // the speculation margin's inputs
     int c_prev = 0;
     std::vector<cd> lam_prev;
     std::vector<double> r_prev;
@@ -1064,12 +1065,21 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
       // the GPU while the host solves the reduced pencil; it is skipped when
       // this iteration is likely to be the last one: e(k) predicted from the
       // observed reduction factor e(k-1)/e(k-2) (before two values exist, a
-      // fast one), below eps.  A wrong guess only costs the overlap.
+      // fast one) below eps times a margin.  A filter launched for nothing
+      // costs a whole filter, a missed overlap at most the host solve, so the
+      // margin is the ratio of the last filter's time to the last host solve's
+      // (at least 1): with a short reduced problem and an expensive filter (a
+      // mixed filter with several corrections), only a clear miss of eps
+      // launches ahead.
       const double q = (k >= 3 && e_prev2 > 0.0 && std::isfinite(e_prev2) && std::isfinite(e_prev))
                            ? std::min(1.0, e_prev / e_prev2)
                            : 1e-8;
-      const bool likely_last =
-          (k == p->o.max_iter) || (c_prev > 0 && std::isfinite(e_prev) && e_prev * q < p->o.eps);
+      const double margin =
+          (last_filter_ms > 0.0 && last_host_ms > 0.0)
+              ? std::min(1e3, std::max(1.0, last_filter_ms / last_host_ms))
+              : 1.0;
+      const bool likely_last = (k == p->o.max_iter) ||
+                               (c_prev > 0 && std::isfinite(e_prev) && e_prev * q < p->o.eps * margin);
       bool speculated = false;
       Timer tf;
       if (!likely_last) {
@@ -1090,7 +1100,8 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
                                   reinterpret_cast<cd *>(hY.data()), m, host_threads(), &gamma,
                                   rho) != 0)
         return fail(p, FEAST_ENUMERIC, "reduced QZ did not converge");
-      inf.t_host_eig_ms += te.ms();
+      last_host_ms = te.ms();
+      inf.t_host_eig_ms += last_host_ms;
       Timer tr;
       std::vector<cd> lam(m);
       std::vector<feast_z> hlam(m);
@@ -1196,7 +1207,8 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
         else if (st != FEAST_OK) return st;
       }
       HIPCHK(hipStreamSynchronize(s));
-      inf.t_filter_ms += launch_ms + tw.ms();
+      last_filter_ms = launch_ms + tw.ms();
+      inf.t_filter_ms += last_filter_ms;
       if (p->rho_pending) {  // the filter's first correction relative to its solution
         p->rho_pending = false;
         const double rms = std::sqrt(p->hrn[0] / (static_cast<double>(n) * m));
