@@ -67,6 +67,8 @@ template <typename T> __device__ inline T ld_cplx(const T *p) { return *p; }
 // not run in lockstep: while one waits for its operands another computes.
 // A group with no tile of its own passes own = false with any valid lin: it
 // stages operands but issues no MFMAs or stores.
+constexpr int kFoldK = 128;  // three-product form: K steps between folds of T1 (power of 2)
+
 template <typename T, int BM, int BN, int TA, bool SUB, int BK, bool M3, bool SHF = false,
           bool PIPE = true, int NG = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin, bool own = true,
@@ -320,6 +322,22 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &d, int64_t lin, boo
               __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
             }
           }
+        }
+        // T1 folded into both parts every kFoldK steps of K: the shared term
+        // then never sums more than kFoldK products before it meets P and Q,
+        // whatever the launch's K (long K ranges otherwise let T1 and P grow
+        // far beyond their difference, and the complex64 factors lose digits)
+        if (((kt + 1) & (kFoldK / BK - 1)) == 0 && kt + 1 < nk) {  // (the last fold is the epilogue's)
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                cr[a][b][r] += t1[a][b][r];
+                ci[a][b][r] += t1[a][b][r];
+                t1[a][b][r] = 0;
+              }
         }
       }
     } else if (live && !PIPE) {
