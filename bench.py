@@ -50,11 +50,11 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # (their sha256: the driver sets the launch shapes), else `traffic` is null.
 TRAFFIC = {"sources": {
                "paper_1404_1768_amd/csrc/k_gemm.hip":
-                   "bf8f9ce9641e0480b9b97476b4e73c4d5de0b73c1c81de7c371ebaee4df62521",
+                   "40b77fb010356d9c2d6453fa2d12a35b1f9ecd8e2b591435bfd57e605696a0de",
                "paper_1404_1768_amd/csrc/feast.cpp":
-                   "6681cc0d408d2ac89c4b4388198c8727ee0b9e8f224638e2cad41eb543ce1f9b"},
-           "mixed": {"fetch": 805239011, "write": 463278085},
-           "fp64": {"fetch": 2019915060, "write": 583601570}}
+                   "2758059589454f589ac7891c0249471ca85309ffde6ccfad4adf8c455c8ea371"},
+           "mixed": {"fetch": 806430837, "write": 463280349},
+           "fp64": {"fetch": 2049751079, "write": 583604423}}
 
 
 def kernel_traffic(form):
