@@ -631,7 +631,12 @@ void ensure_workspace(feast_plan *p, bool with_nodes) {
   if (with_nodes) p->Y.alloc(zs * n * m * N);
   p->W.alloc(zs * n * m * feast_plan::W_COUNT);
   p->G.alloc(zs * m * m * feast_plan::G_COUNT);
-  p->splitws.alloc(zs * std::max<int64_t>(m * m * 96, 1 << 16));
+  // split-K partials: the m x m Gram and projection products (K = n), and with
+  // the node solutions (a solving plan) the n x m products with K = n of the
+  // projection, one buffer per stream they run on
+  p->splitws.alloc(zs * std::max<int64_t>(std::max<int64_t>(m * m * 96, with_nodes ? 4 * n * m : 0),
+                                          1 << 16));
+  if (with_nodes) p->splitws2.alloc(zs * std::max<int64_t>(4 * n * m, 1 << 16));
   p->part.alloc(sizeof(double) * std::max<int64_t>(((n + 63) / 64) * 3 * m, 64 * N + 64));
   p->nrm.alloc(sizeof(double) * (3 * m + 4 * N + 16));
   p->flag.alloc(sizeof(int32_t) * 16);
@@ -690,9 +695,12 @@ void project_device(feast_plan *p, const z64 *A, int64_t lda, const z64 *B, int6
   // Cholesky QR chain leaves most compute units idle
   HIPCHK(hipEventRecord(p->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-  gemm_t<z64>(p->side, 0, n, m, n, zc(1.0), A, lda, 0, U, ldu, 0, zc(0.0), AU1, ldau, 0, 1);
+  // (K = n over (n/64)(m/64) output tiles: split-K, each stream with partials of its own)
+  gemm_t<z64>(p->side, 0, n, m, n, zc(1.0), A, lda, 0, U, ldu, 0, zc(0.0), AU1, ldau, 0, 1,
+              p->splitws2.as<z64>(), static_cast<int64_t>(p->splitws2.bytes / sizeof(z64)));
   HIPCHK(hipEventRecord(p->ev_join, p->side));
-  gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, U, ldu, 0, zc(0.0), BU1, ldbu, 0, 1);
+  gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, U, ldu, 0, zc(0.0), BU1, ldbu, 0, 1,
+              p->splitws.as<z64>(), splitws_elems(p));
   z64 *U2 = p->wblk(feast_plan::W_U2);
   feast::copy_block_z(s, BU1, ldbu, n, m, U2, m);
   orth(p, U2, m, 3);
@@ -875,7 +883,7 @@ int feast_plan_destroy(feast_plan *p) {
   for (hipEvent_t e : {p->ev_fork, p->ev_join})
     if (e) (void)hipEventDestroy(e);
   for (DevBuf *b : {&p->dz, &p->dw, &p->dwc, &p->adj, &p->adj_piv, &p->adj_info, &p->adj_inv, &p->F, &p->piv, &p->perm, &p->info, &p->Linv, &p->Uinv, &p->Linv2, &p->Uinv2, &p->cirr_w, &p->R,
-                    &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->part, &p->nrm,
+                    &p->Y, &p->T1, &p->T2, &p->Yc, &p->W, &p->G, &p->splitws, &p->splitws2, &p->part, &p->nrm,
                     &p->flag, &p->small, &p->fp, &p->rn})
     b->release();
   delete p;
@@ -1038,7 +1046,8 @@ static int solve_impl(feast_plan *p, const feast_z *dA, int64_t lda, const feast
         feast::csr_spmm(s, p->sp.rp.as<int32_t>(), p->sp.ci.as<int32_t>(), p->sp.va.as<z64>(),
                         p->sp.vb.as<z64>(), n, V, ldv, m, nullptr, 0, p->R.as<z64>(), m);
       else
-        gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1);
+        gemm_t<z64>(s, 0, n, m, n, zc(1.0), B, ldb, 0, V, ldv, 0, zc(0.0), p->R.as<z64>(), m, 0, 1,
+                    p->splitws.as<z64>(), splitws_elems(p));
       const int st = run_filter(p->R.as<z64>(), U1, true);
       if (st != FEAST_OK && st != FEAST_REFINE_STAGNATED) return st;
       HIPCHK(hipStreamSynchronize(s));

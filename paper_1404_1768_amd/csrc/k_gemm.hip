@@ -672,9 +672,10 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
   // and the FP64 one needs more than the 512 registers of a lane: not used)
   const int BM = (cfg == GEMM_TALL || cfg == GEMM_UPDATE_TALL) ? 128 : 64;
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + 63) / 64);
-  // Split K when the output is too small to fill the chip.
-  if (d.work && d.K >= 512 && tiles * d.batch < 192) {
-    int64_t sp = (256 + tiles * d.batch - 1) / (tiles * d.batch);
+  // Split K when the output is too small to fill the chip (aiming at about
+  // three workgroups per compute unit, each K chunk at least 256 long).
+  if (d.work && d.K >= 512 && tiles * d.batch < 512) {
+    int64_t sp = (768 + tiles * d.batch - 1) / (tiles * d.batch);
     sp = std::min<int64_t>(sp, d.K / 256);
     while (sp > 1 && sp * d.batch * d.M * d.N > work_elems) --sp;
     if (sp > 1) {

@@ -93,7 +93,7 @@ struct feast_plan {
   DevBuf Linv2, Uinv2;  // inverted 128 x 128 diagonal blocks (the solves' leaves)
   double normA = 0.0, normB = 0.0;  // Frobenius norms of A and B (refinement test)
   // workspaces
-  DevBuf R, Y, T1, T2, Yc, W, G, splitws, part, nrm, flag, small;
+  DevBuf R, Y, T1, T2, Yc, W, G, splitws, splitws2, part, nrm, flag, small;
   DevBuf rn;  // mixed form: ||R||_F^2 at rn[0] (scale of the complex64 solves), ||d_1||^2 and
               // ||Y_0||^2 of the first correction at rn[1], rn[2]; partials from rn[8]
   double *hrn = nullptr;   // page-locked copy of rn[0..3) (read after the stream is idle)
