@@ -50,11 +50,11 @@ PEAK = {"fp64": 78.6, "mixed": 157.3}        # dense MFMA TFLOP/s: FP64, FP32 (c
 # (their sha256: the driver sets the launch shapes), else `traffic` is null.
 TRAFFIC = {"sources": {
                "paper_1404_1768_amd/csrc/k_gemm.hip":
-                   "40b77fb010356d9c2d6453fa2d12a35b1f9ecd8e2b591435bfd57e605696a0de",
-               "paper_1404_1768_amd/csrc/feast.cpp":
-                   "2758059589454f589ac7891c0249471ca85309ffde6ccfad4adf8c455c8ea371"},
-           "mixed": {"fetch": 806430837, "write": 463280349},
-           "fp64": {"fetch": 2049751079, "write": 583604423}}
+                   "74543d04f59b57831d60fe18ab3f29479f4bc23f35027dec044a4107d1eb57c7",
+               "paper_1404_1768_amd/csrc/feast.cpp#lu":
+                   "042aa502efa17b1a65a21e6fb3fb076dccdb9b7f1c2064bb55e4ce7f56b4cbfb"},
+           "mixed": {"fetch": 805345023, "write": 463276262},
+           "fp64": {"fetch": 2049106973, "write": 583599274}}
 
 
 # A source key "path#region" hashes only the text of that file from the region's
