@@ -417,6 +417,28 @@ inline cd dotc(const cd *u, const cd *x, int64_t n) {
   return s;
 }
 
+// sum_i u_i x_i over n entries (no conjugate), laid out as dotc.
+inline cd dotu(const cd *u, const cd *x, int64_t n) {
+  const double *pu = reinterpret_cast<const double *>(u);
+  const double *px = reinterpret_cast<const double *>(x);
+  __m256d re0 = _mm256_setzero_pd(), re1 = re0, im0 = re0, im1 = re0;
+  int64_t i = 0;
+  for (; i + 4 <= n; i += 4) {
+    const __m256d u0 = _mm256_loadu_pd(pu + 2 * i), u1 = _mm256_loadu_pd(pu + 2 * i + 4);
+    const __m256d x0 = _mm256_loadu_pd(px + 2 * i), x1 = _mm256_loadu_pd(px + 2 * i + 4);
+    re0 = _mm256_fmadd_pd(u0, x0, re0);  // [ur xr, ui xi] per number
+    re1 = _mm256_fmadd_pd(u1, x1, re1);
+    im0 = _mm256_fmadd_pd(u0, _mm256_permute_pd(x0, 0x5), im0);  // [ur xi, ui xr]
+    im1 = _mm256_fmadd_pd(u1, _mm256_permute_pd(x1, 0x5), im1);
+  }
+  alignas(32) double a[4], b[4];
+  _mm256_store_pd(a, _mm256_add_pd(re0, re1));
+  _mm256_store_pd(b, _mm256_add_pd(im0, im1));
+  cd s((a[0] - a[1]) + (a[2] - a[3]), (b[0] + b[1]) + (b[2] + b[3]));
+  for (; i < n; ++i) s += u[i] * x[i];
+  return s;
+}
+
 // y_i += a x_i over n entries.
 inline void axpy(cd a, const cd *x, cd *y, int64_t n) {
   const __m256d ar = _mm256_set1_pd(a.real()), ai = _mm256_set1_pd(a.imag());
@@ -510,6 +532,11 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
   }
   const Mat H0 = H;
   const double hnorm = fro(H0);
+  // row-major copy of H0 for the inverse iterations: their LU eliminates
+  // along rows and their back substitution reads rows, both contiguous here
+  std::vector<cd> H0r(static_cast<size_t>(t * t));
+  for (int64_t i = 0; i < t; ++i)
+    for (int64_t j = 0; j < t; ++j) H0r[i * t + j] = H0(i, j);
   const double atol = std::max(kSafmin, kUlp * hnorm);
   // 3. eigenvectors by inverse iteration on H0, then x = P_0 ... P_{t-3} v;
   // the other threads take eigenvalues as the QR iteration deflates them
@@ -518,22 +545,23 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
   std::atomic<bool> failed{false};
   auto eigvec = [&](int64_t j, std::vector<cd> &lu, std::vector<cd> &v, std::vector<int8_t> &sw) {
     const cd lam = alpha[j];
-    // LU of H0 - lam I (upper Hessenberg, column-major copy in lu): eliminate
+    // LU of H0 - lam I (upper Hessenberg, row-major copy in lu): eliminate
     // the subdiagonal with row interchanges between k and k+1
-    for (int64_t j = 0; j < t; ++j) std::copy(H0.col(j), H0.col(j) + t, lu.data() + j * t);
+    for (int64_t i = 0; i < t; ++i) {  // (the Hessenberg part only: nothing below it is read)
+      const int64_t c0 = i > 0 ? i - 1 : 0;
+      std::copy(H0r.begin() + i * t + c0, H0r.begin() + (i + 1) * t, lu.begin() + i * t + c0);
+    }
     for (int64_t k = 0; k < t; ++k) lu[k * t + k] -= lam;
     const double tiny = std::max(kSafmin, kUlp * hnorm);
     for (int64_t k = 0; k + 1 < t; ++k) {
-      cd &dk = lu[k * t + k];
-      cd &sk = lu[k * t + k + 1];
-      sw[k] = std::abs(sk) > std::abs(dk) ? 1 : 0;
-      if (sw[k])
-        for (int64_t jj = k; jj < t; ++jj) std::swap(lu[jj * t + k], lu[jj * t + k + 1]);
-      cd piv = lu[k * t + k];
-      if (std::abs(piv) < tiny) piv = lu[k * t + k] = tiny;
-      const cd mlt = lu[k * t + k + 1] / piv;
-      lu[k * t + k + 1] = mlt;
-      for (int64_t jj = k + 1; jj < t; ++jj) lu[jj * t + k + 1] -= mlt * lu[jj * t + k];
+      cd *rk = lu.data() + k * t, *rk1 = rk + t;
+      sw[k] = std::abs(rk1[k]) > std::abs(rk[k]) ? 1 : 0;
+      if (sw[k]) std::swap_ranges(rk + k, rk + t, rk1 + k);
+      cd piv = rk[k];
+      if (std::abs(piv) < tiny) piv = rk[k] = tiny;
+      const cd mlt = rk1[k] / piv;
+      rk1[k] = mlt;
+      axpy(-mlt, rk + k + 1, rk1 + k + 1, t - k - 1);
     }
     if (std::abs(lu[(t - 1) * t + t - 1]) < tiny) lu[(t - 1) * t + t - 1] = tiny;
     std::fill(v.begin(), v.end(), cd(1.0));
@@ -541,12 +569,12 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
       // forward (unit lower, with the interchanges), then backward (upper)
       for (int64_t k = 0; k + 1 < t; ++k) {
         if (sw[k]) std::swap(v[k], v[k + 1]);
-        v[k + 1] -= lu[k * t + k + 1] * v[k];
+        v[k + 1] -= lu[(k + 1) * t + k] * v[k];
       }
       for (int64_t k = t - 1; k >= 0; --k) {
-        cd acc = v[k];
-        for (int64_t jj = k + 1; jj < t; ++jj) acc -= lu[jj * t + k] * v[jj];
-        v[k] = acc / lu[k * t + k];
+        const cd *rk = lu.data() + k * t;
+        const cd acc = v[k] - dotu(rk + k + 1, v.data() + k + 1, t - k - 1);
+        v[k] = acc / rk[k];
       }
       double nr = 0.0;
       for (const cd &e : v) nr = std::max(nr, std::abs(e));
@@ -557,10 +585,8 @@ int std_eig(int64_t t, const cd *At, int64_t lda, const cd *Bt, int64_t ldb, cd 
       if (refl[k].empty()) continue;
       const std::vector<cd> &u = refl[k];
       const int64_t L = t - k - 1;
-      cd d = 0.0;
-      for (int64_t i = 0; i < L; ++i) d += std::conj(u[i]) * v[k + 1 + i];
-      d *= rf[k];
-      for (int64_t i = 0; i < L; ++i) v[k + 1 + i] -= d * u[i];
+      const cd d = rf[k] * dotc(u.data(), v.data() + k + 1, L);
+      axpy(-d, u.data(), v.data() + k + 1, L);
     }
     double nr = 0.0;
     for (const cd &e : v) nr += std::norm(e);
