@@ -130,6 +130,7 @@ struct feast_batch {
   DevBuf Y, Yc, T1, T2;
   std::vector<int64_t> yoff, toff;
   Tables lu_tab, sv_tab;
+  Tables bv_tab;  // the right-hand sides B V of a call (the caller's pointers: filled per call)
   DevBuf dinv, flags;  // grouped orthonormalisation: inverted 64 x 64 blocks, breakdown flags
   // every pencil's At and Bt packed (m_p^2 each, in internal order), on the
   // device and in page-locked host memory: one copy to the host per projection
@@ -939,6 +940,33 @@ void leave(feast_batch *b) {
   HIPCHK(hipStreamWaitEvent(b->s, b->ev_out, 0));
 }
 
+// R_p = B_p V_p of every pencil (K = n_p over few output tiles each) as one
+// grouped launch on the batch stream; the table holds the caller's pointers,
+// so it is written and uploaded at each call.
+void rhs_all(feast_batch *b, const feast_z *const *dB, const int64_t *ldb,
+             const feast_z *const *dV, const int64_t *ldv) {
+  std::vector<GemmArgs<z64>> e;
+  for (int p = 0; p < b->P; ++p) {
+    const int c = b->order[p];
+    e.push_back(GemmArgs<z64>{b->n[p], b->m[p], b->n[p], reinterpret_cast<const z64 *>(dB[c]),
+                              ldb[c], 0, reinterpret_cast<const z64 *>(dV[c]), ldv[c], 0,
+                              b->sub[p]->R.as<z64>(), b->m[p], 0, make_double2(1.0, 0.0),
+                              make_double2(0.0, 0.0), 1, 1, b->n[p], nullptr, 0});
+  }
+  Tables &t = b->bv_tab;
+  t.host.clear();
+  t.off.clear();
+  t.cnt.clear();
+  t.record = true;
+  t.begin();
+  ggemm<z64>(b, t, 0, false, e);
+  // (the previous call's launch may still read the old table: upload behind it)
+  HIPCHK(hipStreamSynchronize(b->gs));
+  t.upload();
+  t.begin();
+  ggemm<z64>(b, t, 0, false, e);
+}
+
 // Runs f(i) for i in [0, count) on up to `threads` host threads.
 template <class F> void parallel_for(int count, int threads, F &&f) {
   threads = std::max(1, std::min(threads, count));
@@ -1133,13 +1161,7 @@ int feast_batch_filter(feast_batch *b, const feast_z *const *dA, const int64_t *
     enter(b);
     const int st = factor_all(b, dA, lda, dB, ldb);
     if (st != FEAST_OK) return st;
-    for (int p = 0; p < b->P; ++p) {
-      const int c = b->order[p];
-      gemm_t<z64>(b->gs, 0, b->n[p], b->m[p], b->n[p], make_double2(1.0, 0.0),
-                  reinterpret_cast<const z64 *>(dB[c]), ldb[c], 0,
-                  reinterpret_cast<const z64 *>(dV[c]), ldv[c], 0, make_double2(0.0, 0.0),
-                  b->sub[p]->R.as<z64>(), b->m[p], 0, 1);
-    }
+    rhs_all(b, dB, ldb, dV, ldv);
     filter_all(b, dA, lda, dB, ldb, sweeps);
     for (int p = 0; p < b->P; ++p) {
       const int c = b->order[p];
@@ -1180,8 +1202,6 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       inf.t_factor_ms = t.ms();
       if (st != FEAST_OK) return st;
     }
-    auto Ap = [&](int p) { return reinterpret_cast<const z64 *>(dA[b->order[p]]); };
-    auto Bp = [&](int p) { return reinterpret_cast<const z64 *>(dB[b->order[p]]); };
     // per-pencil state of Algorithm 5
     struct St {
       bool done = false;
@@ -1225,12 +1245,7 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       return r;
     };
     // Search with the subspace size fixed: U = Q_N V
-    for (int p = 0; p < P; ++p) {
-      const int c = b->order[p];
-      gemm_t<z64>(s, 0, b->n[p], b->m[p], b->n[p], make_double2(1.0, 0.0), Bp(p), ldb[c], 0,
-                  reinterpret_cast<const z64 *>(dV[c]), ldv[c], 0, make_double2(0.0, 0.0),
-                  b->sub[p]->R.as<z64>(), b->m[p], 0, 1);
-    }
+    rhs_all(b, dB, ldb, dV, ldv);
     grouped_filter();
     {
       const int r = project_active();
