@@ -131,6 +131,7 @@ struct feast_batch {
   std::vector<int64_t> yoff, toff;
   Tables lu_tab, sv_tab;
   Tables bv_tab;  // the right-hand sides B V of a call (the caller's pointers: filled per call)
+  Tables ritz_tab;  // the Ritz products of an iteration (the pencils still iterating: per call)
   DevBuf dinv, flags;  // grouped orthonormalisation: inverted 64 x 64 blocks, breakdown flags
   // every pencil's At and Bt packed (m_p^2 each, in internal order), on the
   // device and in page-locked host memory: one copy to the host per projection
@@ -940,6 +941,25 @@ void leave(feast_batch *b) {
   HIPCHK(hipStreamWaitEvent(b->s, b->ev_out, 0));
 }
 
+// One grouped launch of the products e (C = alpha A B + beta C, ta = 0) on
+// stream st, its table written and uploaded now (after st's earlier work,
+// which may still read the table's previous contents).
+void grouped_on(Tables &t, hipStream_t st, std::vector<GemmArgs<z64>> &e) {
+  if (e.empty()) return;
+  const int64_t tiles = feast::gemm_group_tiles<z64>(e.data(), static_cast<int>(e.size()));
+  t.host.clear();
+  t.off.clear();
+  t.cnt.clear();
+  t.record = true;
+  t.begin();
+  t.put(e);
+  HIPCHK(hipStreamSynchronize(st));
+  t.upload();
+  t.begin();
+  feast::gemm_group<z64>(st, 0, false, t.put(e), static_cast<int>(e.size()), tiles,
+                         feast::GROUP_PLAIN);
+}
+
 // R_p = B_p V_p of every pencil (K = n_p over few output tiles each) as one
 // grouped launch on the batch stream; the table holds the caller's pointers,
 // so it is written and uploaded at each call.
@@ -953,18 +973,7 @@ void rhs_all(feast_batch *b, const feast_z *const *dB, const int64_t *ldb,
                               b->sub[p]->R.as<z64>(), b->m[p], 0, make_double2(1.0, 0.0),
                               make_double2(0.0, 0.0), 1, 1, b->n[p], nullptr, 0});
   }
-  Tables &t = b->bv_tab;
-  t.host.clear();
-  t.off.clear();
-  t.cnt.clear();
-  t.record = true;
-  t.begin();
-  ggemm<z64>(b, t, 0, false, e);
-  // (the previous call's launch may still read the old table: upload behind it)
-  HIPCHK(hipStreamSynchronize(b->gs));
-  t.upload();
-  t.begin();
-  ggemm<z64>(b, t, 0, false, e);
+  grouped_on(b->bv_tab, b->gs, e);
 }
 
 // Runs f(i) for i in [0, count) on up to `threads` host threads.
@@ -1299,8 +1308,11 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
       for (int p : act)
         if (qz[p] != 0) return bfail(b, FEAST_ENUMERIC, "reduced QZ did not converge in pencil " +
                                                           std::to_string(b->order[p]));
-      // Ritz vectors and the norms of eq. 5-1 on the device
+      // Ritz vectors and the norms of eq. 5-1 on the device: the products
+      // X = U_1 Y, A X = (A U_1) Y, B X = (B U_1) Y of every pencil in one
+      // grouped launch once the Y blocks are on the device
       std::vector<std::vector<cd>> lam(P);
+      std::vector<GemmArgs<z64>> ritz;
       for (int p : act) {
         feast_plan *q = b->sub[p];
         const int64_t n = b->n[p], m = b->m[p];
@@ -1315,14 +1327,19 @@ int feast_batch_solve(feast_batch *b, const feast_z *const *dA, const int64_t *l
         HIPCHK(hipMemcpyAsync(Ys, st[p].Yh.data(), sizeof(z64) * m * m, hipMemcpyHostToDevice, rs));
         HIPCHK(hipMemcpyAsync(dlam, st[p].lam.data(), sizeof(z64) * m, hipMemcpyHostToDevice, rs));
         const z64 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0);
-        gemm_t<z64>(rs, 0, n, m, m, one, q->wblk(feast_plan::W_U1), m, 0, Ys, m, 0, zero,
-                    q->wblk(feast_plan::W_X), m, 0, 1);
-        gemm_t<z64>(rs, 0, n, m, m, one, q->wblk(feast_plan::W_AU1), m, 0, Ys, m, 0, zero,
-                    q->wblk(feast_plan::W_AX), m, 0, 1);
-        gemm_t<z64>(rs, 0, n, m, m, one, q->wblk(feast_plan::W_BU1), m, 0, Ys, m, 0, zero,
-                    q->wblk(feast_plan::W_BX), m, 0, 1);
-        feast::ritz_norms(rs, q->wblk(feast_plan::W_AX), q->wblk(feast_plan::W_BX), m, n, m, dlam,
-                          q->part.as<double>(), q->nrm.as<double>());
+        for (const int w : {int(feast_plan::W_U1), int(feast_plan::W_AU1), int(feast_plan::W_BU1)}) {
+          const int out = w == feast_plan::W_U1 ? feast_plan::W_X
+                                                : (w == feast_plan::W_AU1 ? feast_plan::W_AX : feast_plan::W_BX);
+          ritz.push_back(GemmArgs<z64>{n, m, m, q->wblk(w), m, 0, Ys, m, 0, q->wblk(out), m, 0, one,
+                                       zero, 1, 1, m, nullptr, 0});
+        }
+      }
+      grouped_on(b->ritz_tab, rs, ritz);
+      for (int p : act) {
+        feast_plan *q = b->sub[p];
+        const int64_t n = b->n[p], m = b->m[p];
+        feast::ritz_norms(rs, q->wblk(feast_plan::W_AX), q->wblk(feast_plan::W_BX), m, n, m,
+                          q->small.as<z64>(), q->part.as<double>(), q->nrm.as<double>());
         HIPCHK(hipMemcpyAsync(st[p].hn.data(), q->nrm.p, sizeof(double) * 3 * m,
                               hipMemcpyDeviceToHost, rs));
       }
