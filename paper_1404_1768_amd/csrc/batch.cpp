@@ -308,6 +308,12 @@ GemmArgs<T> gargs(int64_t M, int64_t Nc, int64_t K, const T *A, int64_t lda, int
                      make_double2(beta, 0.0), batch, 1, K, nullptr, 0};
 }
 
+// Panels per trailing update of the grouped LU: four for complex128, two for
+// complex64 (64-pencil batch, orders 283-1999: complex128 factorisation 180 ms
+// with one panel per update, 173.9 / 172.1 / 171.2 ms with two / three / four;
+// complex64 102.5 ms with one, 100.1 / 100.3 / 101.2 with two / three / four).
+template <typename T> constexpr int kBatchGroup = sizeof(T) == 16 ? 4 : 2;
+
 // Panel [c0, c0 + w) of the active matrices: halves down to register leaves,
 // each split joined by the fused triangular solve + rank update.
 template <typename T>
@@ -336,7 +342,8 @@ void panel_grp(feast_batch *b, T *F, int nmat, int64_t c0, int w, int64_t pk0, i
 //   the panel's row swaps outside the panel;
 //   U12 = L11^{-1} A12 (for 128: two in-place products with the inverted 64 x 64
 //   blocks and the L10 update between them);
-//   the trailing update A22 -= L21 U12 (K = lu_nb) as one grouped launch.
+//   the trailing update A22 -= L21 U12 as one grouped launch, once per group of
+//   kBatchGroup panels (K = the group's width; see the loop below).
 // record: only collect the GEMM tables.
 template <typename T>
 void lu_grouped(feast_batch *b, bool record) {
@@ -366,63 +373,106 @@ void lu_grouped(feast_batch *b, bool record) {
     }
   }
   auto active = [&](int64_t k) { return std::min(b->active(k), nbig); };
-  for (int64_t k0 = 0; k0 < b->nmax; k0 += NB) {
-    const int64_t k1 = k0 + NB, j0 = k0 / 64;
-    const int act = active(k0), nmat = act * N;
-    if (act == 0) break;
+  // panel [kp, kp + NB) of the pencils with np > kp: leaves, the inverses of
+  // L's diagonal blocks, and its row exchanges outside it
+  auto factor_panel = [&](int64_t kp) {
+    const int64_t kq = kp + NB, jp = kp / 64;
+    const int actp = active(kp), nmat = actp * N;
     if (!record) {
-      panel_grp<T>(b, F, nmat, k0, static_cast<int>(kPanel), k0, static_cast<int>(NB));
-      feast::diag_block_inverse<T>(b->gs, F, 0, 0, nmat, b->nmax, 64, j0, j0 + 1, true, Linv, is,
+      panel_grp<T>(b, F, nmat, kp, static_cast<int>(kPanel), kp, static_cast<int>(NB));
+      feast::diag_block_inverse<T>(b->gs, F, 0, 0, nmat, b->nmax, 64, jp, jp + 1, true, Linv, is,
                                    g, N);
     }
-    const int acth = NB > kPanel ? active(k0 + kPanel) : 0;
+    const int acth = NB > kPanel ? active(kp + kPanel) : 0;
     if (acth > 0) {
       std::vector<GemmArgs<T>> x, upx;
       for (int p = 0; p < acth; ++p) {
         const int64_t ld = b->np[p], st = ld * ld;
         T *M = F + b->foff[p];
-        T *X = M + k0 * ld + k0 + kPanel;
-        x.push_back(gargs<T>(kPanel, kPanel, kPanel, Linv + p * N * is + j0 * 4096, 64, is, X, ld,
+        T *X = M + kp * ld + kp + kPanel;
+        x.push_back(gargs<T>(kPanel, kPanel, kPanel, Linv + p * N * is + jp * 4096, 64, is, X, ld,
                              st, X, ld, st, 1.0, 0.0, N));
-        upx.push_back(gargs<T>(ld - k0 - kPanel, kPanel, kPanel, M + (k0 + kPanel) * ld + k0, ld, st,
-                               X, ld, st, M + (k0 + kPanel) * ld + k0 + kPanel, ld, st, -1.0, 1.0,
+        upx.push_back(gargs<T>(ld - kp - kPanel, kPanel, kPanel, M + (kp + kPanel) * ld + kp, ld, st,
+                               X, ld, st, M + (kp + kPanel) * ld + kp + kPanel, ld, st, -1.0, 1.0,
                                N));
       }
       ggemm<T>(b, tab, 0, false, x);
       ggemm<T>(b, tab, 0, true, upx);
       if (!record) {
-        panel_grp<T>(b, F, acth * N, k0 + kPanel, static_cast<int>(kPanel), k0,
+        panel_grp<T>(b, F, acth * N, kp + kPanel, static_cast<int>(kPanel), kp,
                      static_cast<int>(NB));
-        feast::diag_block_inverse<T>(b->gs, F, 0, 0, acth * N, b->nmax, 64, j0 + 1, j0 + 2, true,
+        feast::diag_block_inverse<T>(b->gs, F, 0, 0, acth * N, b->nmax, 64, jp + 1, jp + 2, true,
                                      Linv, is, g, N);
       }
     }
     if (!record)
-      feast::laswp_outside<T>(b->gs, F, 0, 0, nmat, b->nmax, k0, static_cast<int>(NB), k0, k1, piv,
+      feast::laswp_outside<T>(b->gs, F, 0, 0, nmat, b->nmax, kp, static_cast<int>(NB), kp, kq, piv,
                               g, N);
-    const int act2 = active(k1);
-    std::vector<GemmArgs<T>> u0, u10, u1, upd;
-    for (int p = 0; p < act2; ++p) {
-      const int64_t ld = b->np[p], st = ld * ld, rest = ld - k1;
+  };
+  // U12 = L11^{-1} A12 of panel kp over the columns past it (in place, 64-row
+  // tile rows; for 128 the L10 update between the two halves)
+  auto u12 = [&](int64_t kp) {
+    const int64_t kq = kp + NB, jp = kp / 64;
+    std::vector<GemmArgs<T>> u0, u10, u1;
+    for (int p = 0; p < active(kq); ++p) {
+      const int64_t ld = b->np[p], st = ld * ld, rest = ld - kq;
       T *M = F + b->foff[p];
-      T *top = M + k0 * ld + k1;
-      // U12 = L11^{-1} A12 in place (64-row tile rows), then A22 -= L21 U12
-      u0.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + j0 * 4096, 64, is, top, ld, st,
+      T *top = M + kp * ld + kq;
+      u0.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + jp * 4096, 64, is, top, ld, st,
                             top, ld, st, 1.0, 0.0, N));
       if (NB > kPanel) {
-        T *bot = M + (k0 + kPanel) * ld + k1;
-        u10.push_back(gargs<T>(kPanel, rest, kPanel, M + (k0 + kPanel) * ld + k0, ld, st, top, ld,
+        T *bot = M + (kp + kPanel) * ld + kq;
+        u10.push_back(gargs<T>(kPanel, rest, kPanel, M + (kp + kPanel) * ld + kp, ld, st, top, ld,
                                st, bot, ld, st, -1.0, 1.0, N));
-        u1.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + (j0 + 1) * 4096, 64, is, bot,
+        u1.push_back(gargs<T>(kPanel, rest, kPanel, Linv + p * N * is + (jp + 1) * 4096, 64, is, bot,
                               ld, st, bot, ld, st, 1.0, 0.0, N));
       }
-      upd.push_back(gargs<T>(rest, rest, NB, M + k1 * ld + k0, ld, st, top, ld, st,
-                             M + k1 * ld + k1, ld, st, -1.0, 1.0, N));
     }
     ggemm<T>(b, tab, 0, false, u0);
     ggemm<T>(b, tab, 0, true, u10);
     ggemm<T>(b, tab, 0, false, u1);
-    ggemm<T>(b, tab, 0, true, upd, b->lu_update);
+  };
+  // C[r0:r1, c0:c1] -= L[r0:r1, ka:kb] U[ka:kb, c0:c1] of every pencil with
+  // np > max(r0, c0), rows and columns clipped to its order (r1, c1 < 0: to
+  // its order)
+  auto update = [&](int64_t r0, int64_t r1, int64_t c0, int64_t c1, int64_t ka, int64_t kb,
+                    int variant) {
+    std::vector<GemmArgs<T>> e;
+    for (int p = 0; p < active(std::max(r0, c0)); ++p) {
+      const int64_t ld = b->np[p], st = ld * ld;
+      const int64_t re = r1 < 0 ? ld : std::min(r1, ld), ce = c1 < 0 ? ld : std::min(c1, ld);
+      if (re <= r0 || ce <= c0) continue;
+      if (!(0 <= ka && ka < kb && kb <= r0 && kb <= c0))
+        throw HipError{hipErrorInvalidValue, "grouped update range"};
+      T *M = F + b->foff[p];
+      e.push_back(gargs<T>(re - r0, ce - c0, kb - ka, M + r0 * ld + ka, ld, st, M + ka * ld + c0, ld,
+                           st, M + r0 * ld + c0, ld, st, -1.0, 1.0, N));
+    }
+    ggemm<T>(b, tab, 0, true, e, variant);
+  };
+  // Steps of up to kGroup panels: each further panel's columns get the
+  // group's earlier panels' update, it is factored (its exchanges reach the
+  // group's L21 columns and the columns still waiting for the update, which
+  // commutes with them), its rows get the same update and then its U12; one
+  // update with K = the group's width covers the rest (the trailing block is
+  // read and written once per group).
+  for (int64_t k0 = 0; k0 < b->nmax;) {
+    if (active(k0) == 0) break;
+    factor_panel(k0);
+    int64_t kg = k0 + NB;
+    if (active(kg) == 0) break;
+    u12(k0);
+    for (int gi = 1; gi < kBatchGroup<T> && active(kg) > 0; ++gi) {
+      const int64_t ks = kg, ke = kg + NB;
+      update(ks, -1, ks, ke, k0, ks, -1);
+      factor_panel(ks);
+      kg = ke;
+      if (active(ke) == 0) break;
+      update(ks, ke, ke, -1, k0, ks, -1);
+      u12(ks);
+    }
+    if (active(kg) > 0) update(kg, -1, kg, -1, k0, kg, b->lu_update);
+    k0 = kg;
   }
   if (!record) {
     const int nmat = b->P * N;

@@ -16,16 +16,16 @@ struct Entry {
 };
 
 inline constexpr Entry kBatch[] = {
-    {64, 384, 0, 128, 0},  // ms: nb128_u1 5.75, nb128_u2 5.75, nb128_u3 5.78, nb64_u1 5.97, nb64_u2 5.91, nb64_u3 6.00
-    {64, 384, 1, 64, 2},  // ms: nb128_u1 4.60, nb128_u2 4.31, nb128_u3 4.39, nb64_u1 4.41, nb64_u2 4.27, nb64_u3 4.15
-    {384, 768, 0, 128, 1},  // ms: nb128_u1 18.87, nb128_u2 18.13, nb128_u3 18.74, nb64_u1 19.47, nb64_u2 19.00, nb64_u3 19.54
-    {384, 768, 1, 128, 1},  // ms: nb128_u1 12.11, nb128_u2 11.35, nb128_u3 11.70, nb64_u1 13.03, nb64_u2 11.46, nb64_u3 11.87
-    {768, 1536, 0, 128, 1},  // ms: nb128_u1 62.68, nb128_u2 59.81, nb128_u3 62.68, nb64_u1 66.92, nb64_u2 64.19, nb64_u3 67.45
-    {768, 1536, 1, 128, 1},  // ms: nb128_u1 39.24, nb128_u2 35.44, nb128_u3 37.06, nb64_u1 43.73, nb64_u2 36.99, nb64_u3 38.76
-    {1536, 3072, 0, 128, 1},  // ms: nb128_u1 232.16, nb128_u2 216.17, nb128_u3 233.19, nb64_u1 262.93, nb64_u2 245.96, nb64_u3 263.01
-    {1536, 3072, 1, 128, 1},  // ms: nb128_u1 138.45, nb128_u2 118.66, nb128_u3 126.50, nb64_u1 164.87, nb64_u2 131.86, nb64_u3 139.30
-    {3072, 16385, 0, 128, 1},  // ms: nb128_u1 195.93, nb128_u2 182.06, nb128_u3 196.16, nb64_u1 218.06, nb64_u2 203.52, nb64_u3 218.87
-    {3072, 16385, 1, 128, 1},  // ms: nb128_u1 117.46, nb128_u2 101.18, nb128_u3 107.90, nb64_u1 138.45, nb64_u2 108.26, nb64_u3 117.97
+    {64, 384, 0, 128, 1},  // ms: nb128_u1 5.72, nb128_u2 5.69, nb128_u3 5.71, nb64_u1 5.87, nb64_u2 5.87, nb64_u3 5.89
+    {64, 384, 1, 64, 1},  // ms: nb128_u1 4.47, nb128_u2 4.44, nb128_u3 4.39, nb64_u1 4.38, nb64_u2 4.32, nb64_u3 4.33
+    {384, 768, 0, 64, 1},  // ms: nb128_u1 17.95, nb128_u2 17.85, nb128_u3 17.90, nb64_u1 17.95, nb64_u2 17.60, nb64_u3 17.95
+    {384, 768, 1, 64, 1},  // ms: nb128_u1 11.72, nb128_u2 11.39, nb128_u3 11.51, nb64_u1 11.86, nb64_u2 10.96, nb64_u3 11.37
+    {768, 1536, 0, 64, 1},  // ms: nb128_u1 58.24, nb128_u2 56.98, nb128_u3 58.23, nb64_u1 58.90, nb64_u2 56.61, nb64_u3 59.30
+    {768, 1536, 1, 64, 1},  // ms: nb128_u1 37.34, nb128_u2 34.96, nb128_u3 36.11, nb64_u1 38.72, nb64_u2 34.67, nb64_u3 36.35
+    {1536, 3072, 0, 128, 1},  // ms: nb128_u1 213.56, nb128_u2 201.03, nb128_u3 212.29, nb64_u1 217.93, nb64_u2 203.08, nb64_u3 218.75
+    {1536, 3072, 1, 128, 1},  // ms: nb128_u1 128.49, nb128_u2 112.28, nb128_u3 119.86, nb64_u1 138.14, nb64_u2 116.58, nb64_u3 125.00
+    {3072, 16385, 0, 128, 1},  // ms: nb128_u1 177.00, nb128_u2 166.62, nb128_u3 177.14, nb64_u1 180.63, nb64_u2 168.00, nb64_u3 180.79
+    {3072, 16385, 1, 128, 1},  // ms: nb128_u1 108.68, nb128_u2 96.90, nb128_u3 102.66, nb64_u1 116.54, nb64_u2 99.41, nb64_u3 106.41
 };
 
 }  // namespace feast_tune
