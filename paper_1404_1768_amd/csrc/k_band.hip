@@ -205,8 +205,8 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
 // right-hand side (the 64 columns of R from 64 blockIdx.y; node j =
 // blockIdx.x), as two kernels so that each holds one window in registers:
 //   k_band_fwd: exchanges and unit-lower multipliers; a lane keeps rows
-//     k .. k + kl of its column (WF >= kl + 1) and writes row k of the result
-//     to Y_j;
+//     k .. k + WF - 1 of its column (WF >= kl + 1; rows past k + kl wait
+//     unchanged) and writes row k of the result to Y_j;
 //   k_band_bwd: U; a lane keeps the solved rows k + 1 .. k + kl + ku
 //     (WB >= kl + ku), sums their products in four independent partial sums
 //     and overwrites row k of Y_j with the solution (times the stored pivot
@@ -215,19 +215,24 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
 // issued 16 at a time before they are written), so each step reads only LDS
 // and registers.
 struct BandStage {
-  // dst[e] = src[e] for e < cnt (cnt <= kBandCH * 64), 16 loads in flight per lane
-  __device__ static void flat(z64 *dst, const z64 *src, int cnt, int lane) {
+  // dst[q P + c] = src[q S + off + c] for c < lim, zero for lim <= c < P (rows
+  // q < cnt; cnt P <= kBandCH * 64), 16 loads in flight per lane.  The zero
+  // tail pads every factor row to the register window, so a step needs no
+  // per-entry bound.
+  template <int P>
+  __device__ static void padded(z64 *dst, const z64 *src, int S, int off, int lim, int cnt,
+                                int lane) {
     for (int h = 0; h < 2; ++h) {
       z64 t[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const int e = lane + 64 * (16 * h + q);
-        t[q] = e < cnt ? src[e] : zmake(0.0, 0.0);
+        const int e = lane + 64 * (16 * h + q), row = e / P, c = e - row * P;
+        t[q] = (row < cnt && c < lim) ? src[row * S + off + c] : zmake(0.0, 0.0);
       }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int e = lane + 64 * (16 * h + q);
-        if (e < cnt) dst[e] = t[q];
+        if (e < cnt * P) dst[e] = t[q];
       }
     }
   }
@@ -247,55 +252,123 @@ struct BandStage {
   }
 };
 
+// a - b c as four fused multiply-adds (the shared zfms rounds b c first and
+// costs six instructions; these kernels issue from one wavefront per node and
+// run at its instruction rate)
+__device__ inline z64 band_fms(z64 a, z64 b, z64 c) {
+  return zmake(fma(b.y, c.y, fma(-b.x, c.x, a.x)), fma(-b.y, c.x, fma(-b.x, c.y, a.y)));
+}
+
+// Windows shift once per block of kBandU rows rather than at every row: within
+// a block, step r addresses the window kBandU entries further along (forward)
+// or back (backward), so the entries stay put and one block move of the
+// window follows the block.
+constexpr int kBandU = 4;
+static_assert(kBandCH % kBandU == 0, "chunks hold whole blocks");
+
+// One row of the forward solve at block step r (w[r + i] = row k + i): the
+// exchange of rows k and k + p (p wave-uniform) takes one uniform branch per
+// slot; the empty asm keeps each arm a branch rather than W - 1 selects of
+// four registers on every row.  Slot r is dead after the step, so only row
+// k + p is written back.  The multipliers are loaded in groups of G, all in
+// flight before the group's first product (every one of them for windows up
+// to 24 rows; wider windows leave no registers for that many).
+template <int WF, int r, int N>
+__device__ inline z64 band_fwd_row(z64 (&w)[N], const z64 *f, int p, z64 nv) {
+  static_assert(r + WF < N, "window inside the buffer");
+  z64 y = w[r];
+  if (p != 0) {
+#pragma unroll
+    for (int i = 1; i < WF; ++i)
+      if (i == p) {
+        asm volatile("" ::: "memory");
+        y = w[r + i];
+        w[r + i] = w[r];
+      }
+  }
+  constexpr int G = WF <= 24 ? WF - 1 : WF <= 32 ? 12 : 8;
+#pragma unroll
+  for (int g = 1; g < WF; g += G) {
+    z64 fr[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+      if (g + t < WF) fr[t] = f[g + t - 1];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+      if (g + t < WF) w[r + g + t] = band_fms(w[r + g + t], fr[t], y);
+  }
+  w[r + WF] = nv;
+  return y;
+}
+
 template <int WF>
 __global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
                                                  const int32_t *__restrict__ piv, int64_t n,
                                                  int kl, const z64 *__restrict__ R, int64_t ldr,
                                                  int64_t m, z64 *__restrict__ Y, int64_t ldy,
                                                  int64_t sY) {
-  const int KR = kl + 1;
-  __shared__ z64 fac[kBandCH * 64];  // kBandCH rows of multipliers (kl each)
+  // (the widest window has no registers for extra rows: it moves every row)
+  constexpr int UF = WF > 48 ? 1 : kBandU, PF = WF - 1;
+  __shared__ z64 fac[kBandCH * PF];  // kBandCH rows of multipliers (kl each, zero-padded)
   __shared__ z64 rows[kBandCH][64];  // the rows of R entering the window
   __shared__ int32_t s_piv[kBandCH];
   const int j = blockIdx.x, lane = threadIdx.x;
   const int64_t col = static_cast<int64_t>(blockIdx.y) * 64 + lane;
   const bool act = col < m;
-  const int64_t cc = act ? col : 0;  // a valid column for the loads of idle lanes
+  // idle lanes (col >= m, in the last block only) duplicate column m - 1 of
+  // their own wavefront, so they may store: same values, same instruction
+  const int64_t cc = act ? col : m - 1;
   const z64 *L = Lf + static_cast<int64_t>(j) * n * kl;
   const int32_t *pv = piv + static_cast<int64_t>(j) * n;
   z64 *Yj = Y + static_cast<int64_t>(j) * sY;
-  z64 w[WF];  // w[i] = row k + i
+  // step r of a block: w[r + i] = row k + i, i < WF (multipliers past kl are
+  // zero, so the window spans WF rows and row k + WF enters at w[r + WF])
+  z64 w[WF + UF];
 #pragma unroll
-  for (int i = 0; i < WF; ++i) w[i] = (i < KR && i < n) ? R[i * ldr + cc] : zmake(0.0, 0.0);
+  for (int i = 0; i < WF + UF; ++i) w[i] = (i < WF && i < n) ? R[i * ldr + cc] : zmake(0.0, 0.0);
   for (int64_t k0 = 0; k0 < n; k0 += kBandCH) {
     const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
     __syncthreads();
-    BandStage::flat(fac, L + k0 * kl, ch * kl, lane);
-    if (lane < ch) s_piv[lane] = pv[k0 + lane];
-    BandStage::rows(rows, R, ldr, k0 + KR, ch, n, cc, lane);
+    BandStage::padded<PF>(fac, L + k0 * kl, kl, 0, kl, ch, lane);
+    if (lane < ch) s_piv[lane] = pv[k0 + lane] - static_cast<int32_t>(k0 + lane);
+    BandStage::rows(rows, R, ldr, k0 + WF, ch, n, cc, lane);
     __syncthreads();
-    for (int kk = 0; kk < ch; ++kk) {
-      const int64_t k = k0 + kk;
-      const int p = __builtin_amdgcn_readfirstlane(s_piv[kk] - static_cast<int>(k));
-      z64 y = w[0];
-      if (p != 0) {
+    for (int kb = 0; kb < ch; kb += UF) {
+      const z64 *f = fac + kb * PF;
+      // unconditional stores (no divergent branch in the row)
+      z64 *yk = Yj + (k0 + kb) * ldy + cc;
+      // the last chunk may end inside a block (ch - kb < UF)
+      const int nb = __builtin_amdgcn_readfirstlane(ch - kb);
+      // the block's exchanges, read together (kb + UF <= kBandCH: in bounds)
+      int pb[UF];
 #pragma unroll
-        for (int i = 1; i < WF; ++i)
-          if (i == p) {
-            y = w[i];
-            w[i] = w[0];
-          }
-      }
-      if (act) Yj[k * ldy + col] = y;
+      for (int r = 0; r < UF; ++r) pb[r] = s_piv[kb + r];
+#define FEAST_FWD_STEP(r)                                                               \
+  if (r < nb) {                                                                         \
+    const int p = __builtin_amdgcn_readfirstlane(pb[r]);                                \
+    const z64 y = band_fwd_row<WF, r>(w, f + r * PF, p, rows[kb + r][lane]);            \
+    yk[r * ldy] = y;                                                                    \
+  }
+      FEAST_FWD_STEP(0)
+      if constexpr (UF > 1) { FEAST_FWD_STEP(1) }
+      if constexpr (UF == 4) { FEAST_FWD_STEP(2) FEAST_FWD_STEP(3) }
+#undef FEAST_FWD_STEP
 #pragma unroll
-      for (int i = 1; i < WF; ++i)
-        if (i < KR) w[i] = zfms(w[i], fac[kk * kl + i - 1], y);
-      const z64 nv = rows[kk][lane];
-#pragma unroll
-      for (int i = 0; i < WF; ++i)
-        w[i] = (i == KR - 1) ? nv : (i + 1 < WF ? w[i + 1] : zmake(0.0, 0.0));
+      for (int i = 0; i < WF; ++i) w[i] = w[i + UF];
     }
   }
+}
+
+// (v of lane l mod 32, v of lane 32 + l mod 32) in every lane l, one
+// v_permlane32_swap per dword (both halves see the pair in the same order)
+__device__ inline void band_halves(double v, double &lo, double &hi) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const unsigned u0 = static_cast<unsigned>(u), u1 = static_cast<unsigned>(u >> 32);
+  const auto a = __builtin_amdgcn_permlane32_swap(u0, u0, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(u1, u1, false, false);
+  lo = __builtin_bit_cast(double, static_cast<uint64_t>(a[0]) | (static_cast<uint64_t>(b[0]) << 32));
+  hi = __builtin_bit_cast(double, static_cast<uint64_t>(a[1]) | (static_cast<uint64_t>(b[1]) << 32));
 }
 
 template <int WB>
@@ -303,42 +376,79 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
                                                  const z64 *__restrict__ Dinv, int64_t n, int kl,
                                                  int ku, int64_t m, z64 *__restrict__ Y,
                                                  int64_t ldy, int64_t sY) {
+  constexpr int UB = kBandU, H = WB / 2, G = H > 24 ? H / 2 : H;
+  static_assert(H >= UB, "the far half's block rows come from the near half's window");
+  static_assert(H % G == 0, "whole factor groups");
   const int WC = kl + ku + 1, WU = kl + ku;
-  __shared__ z64 fac[kBandCH * 64];  // kBandCH rows of U (WC each)
-  __shared__ z64 rows[kBandCH][64];  // the forward results of those rows
+  __shared__ z64 fac[kBandCH * WB];  // kBandCH rows of U past the diagonal (WU each, zero-padded)
+  __shared__ z64 rows[kBandCH][64];  // the forward results of those rows (both halves load them)
   __shared__ z64 dinv[kBandCH];
-  const int j = blockIdx.x, lane = threadIdx.x;
-  const int64_t col = static_cast<int64_t>(blockIdx.y) * 64 + lane;
+  const int j = blockIdx.x, lane = threadIdx.x, half = lane >> 5;
+  const int64_t col = static_cast<int64_t>(blockIdx.y) * 32 + (lane & 31);
   const bool act = col < m;
-  const int64_t cc = act ? col : 0;
+  const int64_t cc = act ? col : m - 1;
   const z64 *U = Uf + static_cast<int64_t>(j) * n * WC;
   const z64 *Di = Dinv + static_cast<int64_t>(j) * n;
   z64 *Yj = Y + static_cast<int64_t>(j) * sY;
-  z64 b[WB];  // b[t - 1] = solved row k + t
+  // Lanes l and l + 32 share column l: the near half sums the terms t = 1 .. H
+  // of row k, the far half t = H + 1 .. 2H.  Step r of a block (rows
+  // descending): b[UB - 1 - r + t] = solved row k + t (near) or k + H + t
+  // (far); rows past n - 1 stay zero (and U's entries there are stored zero).
+  z64 b[H + UB];
 #pragma unroll
-  for (int i = 0; i < WB; ++i) b[i] = zmake(0.0, 0.0);
+  for (int i = 0; i < H + UB; ++i) b[i] = zmake(0.0, 0.0);
   for (int64_t k1 = n; k1 > 0; k1 -= kBandCH) {
     const int ch = static_cast<int>(k1 < kBandCH ? k1 : kBandCH);
-    const int64_t kb = k1 - ch;  // rows kb .. k1 - 1
+    const int64_t kb0 = k1 - ch;  // rows kb0 .. k1 - 1
     __syncthreads();
-    BandStage::flat(fac, U + kb * WC, ch * WC, lane);
-    if (lane < ch) dinv[lane] = Di[kb + lane];
-    BandStage::rows(rows, Yj, ldy, kb, ch, n, cc, lane);
+    BandStage::padded<WB>(fac, U + kb0 * WC, WC, 1, WU, ch, lane);
+    if (lane < ch) dinv[lane] = Di[kb0 + lane];
+    BandStage::rows(rows, Yj, ldy, kb0, ch, n, cc, lane);
     __syncthreads();
-    for (int kk = ch - 1; kk >= 0; --kk) {
-      const int64_t k = kb + kk;
-      // entries past row n - 1 multiply b's zeros
-      const int lim = static_cast<int>(n - 1 - k < WU ? n - 1 - k : WU);
-      z64 s4[4] = {rows[kk][lane], zmake(0.0, 0.0), zmake(0.0, 0.0), zmake(0.0, 0.0)};
+    for (int q = 0; q < ch; q += UB) {
+      // the far half's first UB slots are the near half's last UB (the near
+      // half's own are rewritten by this block's rows before it reads them)
 #pragma unroll
-      for (int t = 1; t <= WB; ++t)
-        if (t <= lim) s4[t & 3] = zfms(s4[t & 3], fac[kk * WC + t], b[t - 1]);
-      const z64 s = zadd(zadd(s4[0], s4[1]), zadd(s4[2], s4[3]));
-      const z64 y = zmul(s, dinv[kk]);
-      if (act) Yj[k * ldy + col] = y;
+      for (int i = 0; i < UB; ++i) {
+        double lo, hi;
+        band_halves(b[H + i].x, lo, hi);
+        b[i].x = lo;
+        band_halves(b[H + i].y, lo, hi);
+        b[i].y = lo;
+      }
+      const int nb = __builtin_amdgcn_readfirstlane(ch - q);  // the last chunk may end inside a block
 #pragma unroll
-      for (int t = WB - 1; t > 0; --t) b[t] = b[t - 1];
-      b[0] = y;
+      for (int r = 0; r < UB; ++r) {
+        if (r < nb) {
+          const int kk = ch - 1 - (q + r);
+          const z64 *f = fac + kk * WB + half * H;
+          z64 s2[2] = {half == 0 ? rows[kk][lane] : zmake(0.0, 0.0), zmake(0.0, 0.0)};
+          // the factor loads of a group (the whole row up to H = 24) all in
+          // flight before its first product
+#pragma unroll
+          for (int g = 0; g < H; g += G) {
+            z64 fr[G];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < G; ++t) fr[t] = f[g + t];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = g + 1; t <= g + G; ++t)
+              s2[t & 1] = band_fms(s2[t & 1], fr[t - 1 - g], b[UB - 1 - r + t]);
+          }
+          const z64 sh = zadd(s2[0], s2[1]);
+          double xl, xh, yl, yh;
+          band_halves(sh.x, xl, xh);
+          band_halves(sh.y, yl, yh);
+          const z64 y = zmul(zmake(xl + xh, yl + yh), dinv[kk]);
+          if (half == 0) {
+            if (act) Yj[(kb0 + kk) * ldy + col] = y;
+            b[UB - 1 - r] = y;
+          }
+        }
+      }
+#pragma unroll
+      for (int i = H - 1; i >= 0; --i) b[i + UB] = b[i];
     }
   }
 }
@@ -416,10 +526,10 @@ void band_solve(hipStream_t s, const z64 *Lf, const z64 *Uf, const z64 *Dinv, co
                 int32_t N, int64_t n, int kl, int ku, const z64 *R, int64_t ldr, int64_t m,
                 z64 *Y, int64_t ldy, int64_t sY) {
   if (N <= 0 || n <= 0 || m <= 0) return;
-  const dim3 g(N, static_cast<unsigned>((m + 63) / 64));
-  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, g, dim3(64), 0, s, Lf, piv, n, kl, R, ldr, m,
-                      Y, ldy, sY)
-  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, g, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
+  const dim3 gf(N, static_cast<unsigned>((m + 63) / 64)), gb(N, static_cast<unsigned>((m + 31) / 32));
+  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, gf, dim3(64), 0, s, Lf, piv, n, kl, R, ldr,
+                      m, Y, ldy, sY)
+  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, gb, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
                       Y, ldy, sY)
 }
 
