@@ -21,20 +21,82 @@ namespace feast {
 
 namespace {
 
-// largest of (key, index) over the wavefront, lowest index on equal keys
+// Partners for a wave-wide all-reduce without the LDS crossbar: DPP within
+// rows of 16 lanes (exchange within pairs, within quads, mirrored within
+// eight and within sixteen; each step pairs lanes whose groups already agree),
+// then v_permlane16_swap / v_permlane32_swap across rows and halves, which
+// hand every lane both members of its pair in the same order.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(u), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, static_cast<uint64_t>(static_cast<uint32_t>(lo)) |
+                                        (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32));
+}
+template <bool ROWS16>
+__device__ inline void swap_pair(double v, double &a, double &b) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const unsigned u0 = static_cast<unsigned>(u), u1 = static_cast<unsigned>(u >> 32);
+  const auto x = ROWS16 ? __builtin_amdgcn_permlane16_swap(u0, u0, false, false)
+                        : __builtin_amdgcn_permlane32_swap(u0, u0, false, false);
+  const auto y = ROWS16 ? __builtin_amdgcn_permlane16_swap(u1, u1, false, false)
+                        : __builtin_amdgcn_permlane32_swap(u1, u1, false, false);
+  a = __builtin_bit_cast(double, static_cast<uint64_t>(x[0]) | (static_cast<uint64_t>(y[0]) << 32));
+  b = __builtin_bit_cast(double, static_cast<uint64_t>(x[1]) | (static_cast<uint64_t>(y[1]) << 32));
+}
+template <bool ROWS16>
+__device__ inline void swap_pair(int v, int &a, int &b) {
+  const unsigned u = static_cast<unsigned>(v);
+  const auto x = ROWS16 ? __builtin_amdgcn_permlane16_swap(u, u, false, false)
+                        : __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  a = static_cast<int>(x[0]);
+  b = static_cast<int>(x[1]);
+}
+
+// v of lane l (l wave-uniform) in every lane, through scalar registers
+__device__ inline double lane_at(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(u), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), l);
+  return __builtin_bit_cast(double, static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32));
+}
+
+// (key, idx) of the lane with the largest key, the lowest index on ties, in
+// every lane of the wavefront (all 64 lanes active)
 __device__ inline void wave_argmax(double &key, int &idx) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ok = __shfl_xor(key, off, 64);
-    const int oi = __shfl_xor(idx, off, 64);
+  auto take = [&](double ok, int oi) {
     if (ok > key || (ok == key && oi < idx)) {
       key = ok;
       idx = oi;
     }
-  }
+  };
+  take(dpp_f64<0xB1>(key), __builtin_amdgcn_mov_dpp(idx, 0xB1, 0xF, 0xF, false));     // lane ^ 1
+  take(dpp_f64<0x4E>(key), __builtin_amdgcn_mov_dpp(idx, 0x4E, 0xF, 0xF, false));     // lane ^ 2
+  take(dpp_f64<0x141>(key), __builtin_amdgcn_mov_dpp(idx, 0x141, 0xF, 0xF, false));   // 7 - lane mod 8
+  take(dpp_f64<0x140>(key), __builtin_amdgcn_mov_dpp(idx, 0x140, 0xF, 0xF, false));   // 15 - lane mod 16
+  double k0, k1;
+  int i0, i1;
+  swap_pair<true>(key, k0, k1);  // rows 2r and 2r + 1
+  swap_pair<true>(idx, i0, i1);
+  key = k0;
+  idx = i0;
+  take(k1, i1);
+  swap_pair<false>(key, k0, k1);  // the two halves
+  swap_pair<false>(idx, i0, i1);
+  key = k0;
+  idx = i0;
+  take(k1, i1);
 }
 
 constexpr int kBandCH = 32;  // rows staged per chunk (LU: CSR rows; solves: factor and block rows)
+
+// a - b c as four fused multiply-adds (the shared zfms rounds b c first and
+// costs six instructions; the band kernels' steps run at one wavefront's
+// instruction rate)
+__device__ inline z64 band_fms(z64 a, z64 b, z64 c) {
+  return zmake(fma(b.y, c.y, fma(-b.x, c.x, a.x)), fma(-b.y, c.x, fma(-b.x, c.y, a.y)));
+}
 
 // One workgroup (256 threads) per node j.  Thread t < WC owns window column
 // slot t for the whole factorisation and keeps that column's rows k .. k + kl
@@ -62,9 +124,10 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
                                                  int32_t *__restrict__ piv,
                                                  int32_t *__restrict__ info) {
   const int KR = kl + 1, WC = kl + ku + 1;
-  // rows 0 .. kl of the first window, then the staged rows of each chunk
-  // (row q of the chunk at SR[q WC + c - (row - kl)], c its column)
-  __shared__ z64 SR[64 * 64];
+  // the staged rows of a chunk (row q of the chunk at SR[q WC + c - (row -
+  // kl)], c its column); the first window's rows 0 .. kl pass through it
+  // kBandCH at a time
+  __shared__ z64 SR[kBandCH * 64];
   __shared__ int32_t srp[kBandCH + 1];
   __shared__ z64 colbuf[64];
   __shared__ z64 sl[2][64];  // multipliers of column k (index 1 .. kl)
@@ -112,14 +175,21 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
   };
 
   if (tid == 0) s_info = 0;
-  stage(0, static_cast<int>(KR < n ? KR : n));
   const bool owner = tid < WC;
   z64 w[W];
 #pragma unroll
-  for (int i = 0; i < W; ++i) {
-    // window row i, column tid: SR index i WC + tid - (i - kl)
-    const int c = tid - i + kl;
-    w[i] = (owner && i < KR && i < n && c >= 0 && c < WC) ? SR[i * WC + c] : zmake(0.0, 0.0);
+  for (int i = 0; i < W; ++i) w[i] = zmake(0.0, 0.0);
+  const int r1 = static_cast<int>(KR < n ? KR : n);  // the first window's rows
+  for (int h = 0; h < r1; h += kBandCH) {
+    const int cnt = r1 - h < kBandCH ? r1 - h : kBandCH;
+    __syncthreads();  // the previous rows are read
+    stage(h, cnt);
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      // window row i, column tid: SR index (i - h) WC + tid - (i - kl)
+      const int c = tid - i + kl;
+      if (owner && i >= h && i < h + cnt && c >= 0 && c < WC) w[i] = SR[(i - h) * WC + c];
+    }
   }
 
   int ck = 0;  // slot of column k
@@ -136,8 +206,7 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
       if (tid < 64) {
         if (tid == ck) {
 #pragma unroll
-          for (int i = 0; i < W; ++i)
-            if (i < KR) colbuf[i] = w[i];
+          for (int i = 0; i < W; ++i) colbuf[i] = w[i];  // (rows past k + kl are not read)
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -148,16 +217,17 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
         double key = valid ? (a1 == a1 ? a1 : -1.0) : -2.0;
         int idx = valid ? i : 1 << 30;
         wave_argmax(key, idx);
-        const int p = idx < KR ? idx : 0;
-        const double ux = __shfl(v.x, p, 64), uy = __shfl(v.y, p, 64);
-        const double v0x = __shfl(v.x, 0, 64), v0y = __shfl(v.y, 0, 64);
+        key = lane_at(key, 0);  // (every lane holds it: a scalar from here on)
+        const int p = __builtin_amdgcn_readfirstlane(idx < KR ? idx : 0);
+        const double ux = lane_at(v.x, p), uy = lane_at(v.y, p);
+        const double v0x = lane_at(v.x, 0), v0y = lane_at(v.y, 0);
         const bool zero = !(key > 0.0);
         const z64 inv = zero ? zmake(0.0, 0.0) : zrecip(zmake(ux, uy));
-        if (i >= 1 && i < KR) {
+        if (i >= 1 && i < W) {  // zero past row k + kl and past row n - 1
           const z64 src = (i == p) ? zmake(v0x, v0y) : v;
           const z64 l = valid ? zmul(src, inv) : zmake(0.0, 0.0);
           sl[par][i] = l;
-          L[k * kl + (i - 1)] = l;
+          if (i < KR) L[k * kl + (i - 1)] = l;
         }
         if (lane == 0) {
           s_p[par] = p;
@@ -171,28 +241,52 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
         const int p = __builtin_amdgcn_readfirstlane(s_p[par]);
         int jo = tid - ck;  // this column's offset from column k
         if (jo < 0) jo += WC;
-        const z64 r0v = w[0];
+        // exchange rows k and k + p (row k's slot is dead after the step):
+        // one uniform branch per slot, the empty asm keeping each arm a
+        // branch rather than a select of four registers per slot
         z64 rpv = w[0];
+        if (p != 0) {
 #pragma unroll
-        for (int i = 1; i < W; ++i)
-          if (i == p) rpv = w[i];
+          for (int i = 1; i < W; ++i)
+            if (i == p) {
+              asm volatile("" ::: "memory");
+              rpv = w[i];
+              w[i] = w[0];
+            }
+        }
         U[k * WC + jo] = (k + jo < n) ? rpv : zmake(0.0, 0.0);
         // the incoming row k + KR at this slot's next column (k + jo, or
         // k + WC for the slot of column k): staged index WC - 1 or jo - 1
         const z64 nv = (kk < cnt) ? SR[kk * WC + (jo == 0 ? WC - 1 : jo - 1)] : zmake(0.0, 0.0);
-        if (jo == 0) {  // column k leaves: the slot starts column k + WC
+        // the multipliers (zero past row k + kl: no bound per row) in groups
+        // of G, all in flight before the group's first product
+        const z64 *lk = sl[par];
+        constexpr int G = W <= 24 ? W - 1 : 8;
 #pragma unroll
-          for (int i = 0; i < W; ++i) w[i] = (i == KR - 1) ? nv : zmake(0.0, 0.0);
-        } else {
+        for (int g = 1; g < W; g += G) {
+          z64 lr[G];
 #pragma unroll
-          for (int i = 1; i < W; ++i)
-            if (i < KR && k + i < n) {
-              const z64 cur = (i == p) ? r0v : w[i];
-              w[i] = zfms(cur, sl[par][i], rpv);
-            }
+          for (int t = 0; t < G; ++t)
+            if (g + t < W) lr[t] = lk[g + t];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int i = 0; i < W; ++i) w[i] = (i == KR - 1) ? nv : (i + 1 < W ? w[i + 1] : zmake(0.0, 0.0));
+          for (int t = 0; t < G; ++t)
+            if (g + t < W) w[g + t] = band_fms(w[g + t], lr[t], rpv);
         }
+        if (jo == 0) {  // column k leaves: the slot starts column k + WC
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int i = 0; i < W; ++i) w[i] = zmake(0.0, 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i + 1 < W; ++i) w[i] = w[i + 1];
+        w[W - 1] = zmake(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+          if (i == KR - 1) {
+            asm volatile("" ::: "memory");
+            w[i] = nv;
+          }
       }
       if (++ck == WC) ck = 0;
     }
@@ -251,13 +345,6 @@ struct BandStage {
     }
   }
 };
-
-// a - b c as four fused multiply-adds (the shared zfms rounds b c first and
-// costs six instructions; these kernels issue from one wavefront per node and
-// run at its instruction rate)
-__device__ inline z64 band_fms(z64 a, z64 b, z64 c) {
-  return zmake(fma(b.y, c.y, fma(-b.x, c.x, a.x)), fma(-b.y, c.x, fma(-b.x, c.y, a.y)));
-}
 
 // Windows shift once per block of kBandU rows rather than at every row: within
 // a block, step r addresses the window kBandU entries further along (forward)
