@@ -259,11 +259,15 @@ typedef struct feast_csr {
  * eigenvectors (in the caller's row order) are those of the dense pencil.
  * Outputs and stopping rules as feast_solve; info->band_kl/band_ku report the
  * bandwidths and info->t_factor_ms includes the host's symbolic work (pattern
- * copies, ordering).  The band factors are recomputed on every call.
+ * copies, ordering).  The ordering is kept in the plan: a later call whose A
+ * and B have the same patterns (rowptr and col equal entry by entry) reuses
+ * it and skips that work; the values are gathered and the band factors
+ * recomputed on every call.
  * Errors: FEAST_EINVAL for a mixed plan (band factors are FP64 only), a
  * malformed pattern (message names the fault), or kl + ku > 63 after
- * reordering (the band kernels keep their windows in LDS; such a pencil is
- * factored densely by feast_solve); FEAST_SINGULAR for an exact zero pivot.
+ * reordering (the band kernels keep a column's or a right-hand side's window
+ * in registers; such a pencil is factored densely by feast_solve);
+ * FEAST_SINGULAR for an exact zero pivot.
  * Synchronises the stream. */
 int feast_solve_csr(feast_plan *plan, const feast_csr *A, const feast_csr *B,
                     const feast_z *dV, int64_t ldv, feast_z *hLambda, feast_z *dX,

@@ -1440,38 +1440,55 @@ int prepare_sparse(feast_plan *p, const feast_csr *A, const feast_csr *B) {
     const std::string bad = feast_host::check_pattern(n, P.rp.data(), P.ci.data(), M->nnz);
     if (!bad.empty()) return fail(p, FEAST_EINVAL, std::string(w ? "B: " : "A: ") + bad);
   }
-  std::vector<int32_t> ident(static_cast<size_t>(n));
-  for (int64_t i = 0; i < n; ++i) ident[i] = static_cast<int32_t>(i);
-  const feast_host::UnionPattern U0 = feast_host::union_reordered(PA, PB, ident);
-  int64_t kl = 0, ku = 0;
-  const std::vector<int32_t> perm = feast_host::band_order(U0.P, &kl, &ku);
-  if (kl + ku > kBandMax) {
-    char buf[200];
-    std::snprintf(buf, sizeof buf,
-                  "band too wide after reordering: kl = %lld, ku = %lld (kl + ku <= %d); factor "
-                  "this pencil densely (feast_solve)",
-                  static_cast<long long>(kl), static_cast<long long>(ku), kBandMax);
-    return fail(p, FEAST_EINVAL, buf);
-  }
-  const feast_host::UnionPattern U = feast_host::union_reordered(PA, PB, perm);
-  const int64_t nnz = static_cast<int64_t>(U.P.ci.size());
   auto &sp = p->sp;
-  sp.kl = static_cast<int>(kl);
-  sp.ku = static_cast<int>(ku);
-  sp.nnz = nnz;
-  sp.rp.alloc(sizeof(int32_t) * (n + 1));
-  sp.ci.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
-  sp.map.alloc(sizeof(int32_t) * 2 * std::max<int64_t>(nnz, 1));
+  // the symbolic work (ordering, union pattern, its upload) depends on the
+  // patterns only: reused while A's and B's are those of the last ordering
+  const bool same = sp.ordered && PA.rp == sp.keyA_rp && PA.ci == sp.keyA_ci &&
+                    PB.rp == sp.keyB_rp && PB.ci == sp.keyB_ci;
+  if (!same) {
+    sp.ordered = false;
+    std::vector<int32_t> ident(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) ident[i] = static_cast<int32_t>(i);
+    const feast_host::UnionPattern U0 = feast_host::union_reordered(PA, PB, ident);
+    int64_t kl = 0, ku = 0;
+    const std::vector<int32_t> perm = feast_host::band_order(U0.P, &kl, &ku);
+    if (kl + ku > kBandMax) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "band too wide after reordering: kl = %lld, ku = %lld (kl + ku <= %d); factor "
+                    "this pencil densely (feast_solve)",
+                    static_cast<long long>(kl), static_cast<long long>(ku), kBandMax);
+      return fail(p, FEAST_EINVAL, buf);
+    }
+    const feast_host::UnionPattern U = feast_host::union_reordered(PA, PB, perm);
+    const int64_t nnz = static_cast<int64_t>(U.P.ci.size());
+    sp.kl = static_cast<int>(kl);
+    sp.ku = static_cast<int>(ku);
+    sp.nnz = nnz;
+    sp.rp.alloc(sizeof(int32_t) * (n + 1));
+    sp.ci.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    sp.map.alloc(sizeof(int32_t) * 2 * std::max<int64_t>(nnz, 1));
+    sp.perm.alloc(sizeof(int32_t) * n);
+    HIPCHK(hipMemcpyAsync(sp.rp.p, U.P.rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(sp.perm.p, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    if (nnz > 0) {
+      int32_t *dmap = sp.map.as<int32_t>();
+      HIPCHK(hipMemcpyAsync(sp.ci.p, U.P.ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(dmap, U.mapA.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(dmap + nnz, U.mapB.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));  // the host arrays above are freed on return
+    sp.keyA_rp = std::move(PA.rp);
+    sp.keyA_ci = std::move(PA.ci);
+    sp.keyB_rp = std::move(PB.rp);
+    sp.keyB_ci = std::move(PB.ci);
+    sp.ordered = true;
+  }
+  const int64_t nnz = sp.nnz, kl = sp.kl, ku = sp.ku;
   sp.va.alloc(sizeof(z64) * std::max<int64_t>(nnz, 1));
   sp.vb.alloc(sizeof(z64) * std::max<int64_t>(nnz, 1));
-  sp.perm.alloc(sizeof(int32_t) * n);
-  HIPCHK(hipMemcpyAsync(sp.rp.p, U.P.rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(sp.perm.p, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
   if (nnz > 0) {
-    int32_t *dmap = sp.map.as<int32_t>();
-    HIPCHK(hipMemcpyAsync(sp.ci.p, U.P.ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dmap, U.mapA.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dmap + nnz, U.mapB.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+    const int32_t *dmap = sp.map.as<int32_t>();
     feast::gather_vals(s, dmap, reinterpret_cast<const z64 *>(A->val), nnz, sp.va.as<z64>());
     feast::gather_vals(s, dmap + nnz, reinterpret_cast<const z64 *>(B->val), nnz, sp.vb.as<z64>());
   }

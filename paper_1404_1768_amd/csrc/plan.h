@@ -109,6 +109,10 @@ struct feast_plan {
     DevBuf rp, ci, va, vb, map, perm;
     DevBuf Lf, Uf, Dinv, piv, info;
     DevBuf V, X;  // start block and eigenvector block in the new order
+    // the patterns the device ordering (rp, ci, map, perm, kl, ku) was made
+    // for: a later call with the same patterns reuses it
+    bool ordered = false;
+    std::vector<int32_t> keyA_rp, keyA_ci, keyB_rp, keyB_ci;
   } sp;
   DevBuf cirr_w;                           // Block_CIRR moment weights (g x N)
   std::string err;

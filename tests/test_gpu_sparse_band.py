@@ -120,6 +120,29 @@ def test_scrambled_pencil_same_eigenpairs():
         assert np.abs(X1[:, b] - X0[q, a]).max() <= 1e-8
 
 
+def test_one_plan_reuses_the_ordering_not_the_values():
+    """One plan, four calls: the pencil, the same pattern with A scaled by
+    1.001 (the ordering is reused; the values and factors are not: the
+    eigenvalues scale with A), a symmetric permutation (a new pattern, ordered
+    afresh) and the first pencil again (ordered again, same result)."""
+    A, B, V, c, r, ref = _case(3)
+    n, m = A.shape[0], V.shape[1]
+    q = np.random.default_rng(5).permutation(n)
+    calls = [(A, B, V), (A * 1.001, B, V), (A[np.ix_(q, q)], B[np.ix_(q, q)], V[q]), (A, B, V)]
+    out = []
+    with fm.Plan(n, m, c, r, 16, rule=fm.GAUSS_LEGENDRE, eps=1e-10, prec=fm.FP64) as plan:
+        for Ak, Bk, Vk in calls:
+            dV = torch.from_numpy(np.ascontiguousarray(Vk)).to("cuda")
+            out.append(plan.solve_csr(_csr(Ak), _csr(Bk), dV))
+    r0, r1, r2, r3 = out
+    scale = max(1.0, abs(c) + r)
+    assert r0.flag == 1 and len(r0.lam) == len(ref)
+    assert len(r1.lam) == len(r0.lam) and _match(r1.lam, 1.001 * r0.lam) <= 1e-8 * scale
+    assert _match(r1.lam, r0.lam) > 1e-6 * scale  # not the first call's values
+    assert len(r2.lam) == len(r0.lam) and _match(r2.lam, r0.lam) <= 1e-9 * scale
+    assert r3.band == r0.band and _match(r3.lam, r0.lam) <= 1e-12 * scale
+
+
 def test_diagonal_pencil_closed_form():
     """kl = ku = 0: A = diag(d), B = I has eigenvalues d exactly."""
     n = 600
