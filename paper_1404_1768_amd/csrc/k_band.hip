@@ -295,16 +295,17 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
   if (tid == 0) info[j] = s_info;
 }
 
-// The node solves Y_j = M_j^{-1} R with M_j's band factors, one lane per
-// right-hand side (the 64 columns of R from 64 blockIdx.y; node j =
+// The node solves Y_j = M_j^{-1} R with M_j's band factors (node j =
 // blockIdx.x), as two kernels so that each holds one window in registers:
-//   k_band_fwd: exchanges and unit-lower multipliers; a lane keeps rows
+//   k_band_fwd: exchanges and unit-lower multipliers, one lane per right-hand
+//     side (64 columns of R per blockIdx.y); a lane keeps rows
 //     k .. k + WF - 1 of its column (WF >= kl + 1; rows past k + kl wait
 //     unchanged) and writes row k of the result to Y_j;
-//   k_band_bwd: U; a lane keeps the solved rows k + 1 .. k + kl + ku
-//     (WB >= kl + ku), sums their products in four independent partial sums
-//     and overwrites row k of Y_j with the solution (times the stored pivot
-//     reciprocal).
+//   k_band_bwd: U, two lanes per right-hand side (32 columns per
+//     blockIdx.y): lane l keeps the solved rows k + 1 .. k + WB / 2 of
+//     column l, lane l + 32 the rows after them (WB >= kl + ku); each sums
+//     its half of row k's products, the halves add, and lane l overwrites row
+//     k of Y_j with the solution (times the stored pivot reciprocal).
 // Factor rows and block rows are staged kBandCH at a time through LDS (loads
 // issued 16 at a time before they are written), so each step reads only LDS
 // and registers.
