@@ -310,19 +310,19 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
 // issued 16 at a time before they are written), so each step reads only LDS
 // and registers.
 struct BandStage {
-  // dst[q P + c] = src[q S + off + c] for c < lim, zero for lim <= c < P (rows
-  // q < cnt; cnt P <= kBandCH * 64), 16 loads in flight per lane.  The zero
-  // tail pads every factor row to the register window, so a step needs no
+  // dst[q P + c] = src[q S + off + c] for lo <= c < lim, zero for the other
+  // c < P (rows q < cnt; cnt P <= kBandCH * 64), 16 loads in flight per lane.
+  // The zeros pad every factor row to the register window, so a step needs no
   // per-entry bound.
   template <int P>
-  __device__ static void padded(z64 *dst, const z64 *src, int S, int off, int lim, int cnt,
-                                int lane) {
+  __device__ __forceinline__ static void padded(z64 *dst, const z64 *src, int S, int off,
+                                                int lo, int lim, int cnt, int lane) {
     for (int h = 0; h < 2; ++h) {
       z64 t[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int e = lane + 64 * (16 * h + q), row = e / P, c = e - row * P;
-        t[q] = (row < cnt && c < lim) ? src[row * S + off + c] : zmake(0.0, 0.0);
+        t[q] = (row < cnt && c >= lo && c < lim) ? src[row * S + off + c] : zmake(0.0, 0.0);
       }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
@@ -332,8 +332,9 @@ struct BandStage {
     }
   }
   // rows[q][lane] = M[(r0 + q) ldm + cc] for q < cnt (rows >= lim read as zero)
-  __device__ static void rows(z64 (*dst)[64], const z64 *M, int64_t ldm, int64_t r0, int cnt,
-                              int64_t lim, int64_t cc, int lane) {
+  __device__ __forceinline__ static void rows(z64 (*dst)[64], const z64 *M, int64_t ldm,
+                                              int64_t r0, int cnt, int64_t lim, int64_t cc,
+                                              int lane) {
     for (int h = 0; h < 2; ++h) {
       z64 t[16];
 #pragma unroll
@@ -354,39 +355,69 @@ struct BandStage {
 constexpr int kBandU = 4;
 static_assert(kBandCH % kBandU == 0, "chunks hold whole blocks");
 
-// One row of the forward solve at block step r (w[r + i] = row k + i): the
-// exchange of rows k and k + p (p wave-uniform) takes one uniform branch per
-// slot; the empty asm keeps each arm a branch rather than W - 1 selects of
-// four registers on every row.  Slot r is dead after the step, so only row
-// k + p is written back.  The multipliers are loaded in groups of G, all in
-// flight before the group's first product (every one of them for windows up
-// to 24 rows; wider windows leave no registers for that many).
-template <int WF, int r, int N>
-__device__ inline z64 band_fwd_row(z64 (&w)[N], const z64 *f, int p, z64 nv) {
-  static_assert(r + WF < N, "window inside the buffer");
-  z64 y = w[r];
+// One row of the forward solve at block step r.  Lanes l and l + 32 share a
+// column: slot r + s holds row k + s in the near half (lanes below 32) and row
+// k + H + s in the far half, s < H.  Rows k and k + p (p wave-uniform) are
+// exchanged inside the near half, or across the halves through
+// v_permlane32_swap when p >= H: one uniform branch per slot, the empty asm
+// keeping each arm a branch rather than a select of four registers per slot.
+// Row k (near slot r, multiplier 0) is y; every slot s takes
+// f[s] y off (f: the half's H multipliers, loaded before the first product,
+// at most G in flight); then the far half's first row moves to the near
+// half's slot r + H and row k + 2H enters the far half there.
+template <int H, int r, int N>
+__device__ inline z64 band_fwd_row(z64 (&w)[N], const z64 *f, int p, z64 nv, int half) {
+  static_assert(r + H < N, "window inside the buffer");
   if (p != 0) {
+    if (p < H) {
 #pragma unroll
-    for (int i = 1; i < WF; ++i)
-      if (i == p) {
-        asm volatile("" ::: "memory");
-        y = w[r + i];
-        w[r + i] = w[r];
-      }
+      for (int i = 1; i < H; ++i)
+        if (i == p) {
+          asm volatile("" ::: "memory");
+          if (half == 0) {
+            const z64 t = w[r + i];
+            w[r + i] = w[r];
+            w[r] = t;
+          }
+        }
+    } else {
+      const int q = p - H;  // row k + p is far slot r + q
+      z64 x = w[r];         // the near half sends row k, the far half row k + p
+#pragma unroll
+      for (int i = 0; i < H; ++i)
+        if (i == q) {
+          asm volatile("" ::: "memory");
+          if (half) x = w[r + i];
+        }
+      z64 xn, xf;
+      swap_pair<false>(x.x, xn.x, xf.x);
+      swap_pair<false>(x.y, xn.y, xf.y);
+      if (half == 0) w[r] = xf;
+#pragma unroll
+      for (int i = 0; i < H; ++i)
+        if (i == q) {
+          asm volatile("" ::: "memory");
+          if (half) w[r + i] = xn;
+        }
+    }
   }
-  constexpr int G = WF <= 24 ? WF - 1 : WF <= 32 ? 12 : 8;
+  z64 y, yf;
+  swap_pair<false>(w[r].x, y.x, yf.x);
+  swap_pair<false>(w[r].y, y.y, yf.y);
+  constexpr int G = H <= 24 ? H : H / 2;
 #pragma unroll
-  for (int g = 1; g < WF; g += G) {
+  for (int g = 0; g < H; g += G) {
     z64 fr[G];
 #pragma unroll
-    for (int t = 0; t < G; ++t)
-      if (g + t < WF) fr[t] = f[g + t - 1];
+    for (int t = 0; t < G; ++t) fr[t] = f[g + t];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int t = 0; t < G; ++t)
-      if (g + t < WF) w[r + g + t] = band_fms(w[r + g + t], fr[t], y);
+    for (int t = 0; t < G; ++t) w[r + g + t] = band_fms(w[r + g + t], fr[t], y);
   }
-  w[r + WF] = nv;
+  z64 un, uf;  // the halves' slot r after the update: far's is row k + H
+  swap_pair<false>(w[r].x, un.x, uf.x);
+  swap_pair<false>(w[r].y, un.y, uf.y);
+  w[r + H] = half ? nv : uf;
   return y;
 }
 
@@ -396,13 +427,13 @@ __global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
                                                  int kl, const z64 *__restrict__ R, int64_t ldr,
                                                  int64_t m, z64 *__restrict__ Y, int64_t ldy,
                                                  int64_t sY) {
-  // (the widest window has no registers for extra rows: it moves every row)
-  constexpr int UF = WF > 48 ? 1 : kBandU, PF = WF - 1;
-  __shared__ z64 fac[kBandCH * PF];  // kBandCH rows of multipliers (kl each, zero-padded)
-  __shared__ z64 rows[kBandCH][64];  // the rows of R entering the window
+  constexpr int UF = kBandU, H = WF / 2;
+  static_assert(WF % 2 == 0, "two halves of the window");
+  __shared__ z64 fac[kBandCH * WF];  // per row: 0, then the kl multipliers, zero-padded
+  __shared__ z64 rows[kBandCH][64];  // the rows of R entering the window (both halves load them)
   __shared__ int32_t s_piv[kBandCH];
-  const int j = blockIdx.x, lane = threadIdx.x;
-  const int64_t col = static_cast<int64_t>(blockIdx.y) * 64 + lane;
+  const int j = blockIdx.x, lane = threadIdx.x, half = lane >> 5;
+  const int64_t col = static_cast<int64_t>(blockIdx.y) * 32 + (lane & 31);
   const bool act = col < m;
   // idle lanes (col >= m, in the last block only) duplicate column m - 1 of
   // their own wavefront, so they may store: same values, same instruction
@@ -410,21 +441,23 @@ __global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
   const z64 *L = Lf + static_cast<int64_t>(j) * n * kl;
   const int32_t *pv = piv + static_cast<int64_t>(j) * n;
   z64 *Yj = Y + static_cast<int64_t>(j) * sY;
-  // step r of a block: w[r + i] = row k + i, i < WF (multipliers past kl are
-  // zero, so the window spans WF rows and row k + WF enters at w[r + WF])
-  z64 w[WF + UF];
+  z64 w[H + UF];
 #pragma unroll
-  for (int i = 0; i < WF + UF; ++i) w[i] = (i < WF && i < n) ? R[i * ldr + cc] : zmake(0.0, 0.0);
+  for (int i = 0; i < H + UF; ++i) {
+    const int64_t row = static_cast<int64_t>(half) * H + i;
+    w[i] = (i < H && row < n) ? R[row * ldr + cc] : zmake(0.0, 0.0);
+  }
   for (int64_t k0 = 0; k0 < n; k0 += kBandCH) {
     const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
     __syncthreads();
-    BandStage::padded<PF>(fac, L + k0 * kl, kl, 0, kl, ch, lane);
+    BandStage::padded<WF>(fac, L + k0 * kl, kl, -1, 1, kl + 1, ch, lane);
     if (lane < ch) s_piv[lane] = pv[k0 + lane] - static_cast<int32_t>(k0 + lane);
     BandStage::rows(rows, R, ldr, k0 + WF, ch, n, cc, lane);
     __syncthreads();
     for (int kb = 0; kb < ch; kb += UF) {
-      const z64 *f = fac + kb * PF;
-      // unconditional stores (no divergent branch in the row)
+      const z64 *f = fac + kb * WF + half * H;
+      // unconditional stores (no divergent branch in the row; both halves
+      // store the same y)
       z64 *yk = Yj + (k0 + kb) * ldy + cc;
       // the last chunk may end inside a block (ch - kb < UF)
       const int nb = __builtin_amdgcn_readfirstlane(ch - kb);
@@ -432,18 +465,16 @@ __global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
       int pb[UF];
 #pragma unroll
       for (int r = 0; r < UF; ++r) pb[r] = s_piv[kb + r];
-#define FEAST_FWD_STEP(r)                                                               \
-  if (r < nb) {                                                                         \
-    const int p = __builtin_amdgcn_readfirstlane(pb[r]);                                \
-    const z64 y = band_fwd_row<WF, r>(w, f + r * PF, p, rows[kb + r][lane]);            \
-    yk[r * ldy] = y;                                                                    \
+#define FEAST_FWD_STEP(r)                                                                   \
+  if (r < nb) {                                                                             \
+    const int p = __builtin_amdgcn_readfirstlane(pb[r]);                                    \
+    const z64 y = band_fwd_row<H, r>(w, f + r * WF, p, rows[kb + r][lane], half);           \
+    yk[r * ldy] = y;                                                                        \
   }
-      FEAST_FWD_STEP(0)
-      if constexpr (UF > 1) { FEAST_FWD_STEP(1) }
-      if constexpr (UF == 4) { FEAST_FWD_STEP(2) FEAST_FWD_STEP(3) }
+      FEAST_FWD_STEP(0) FEAST_FWD_STEP(1) FEAST_FWD_STEP(2) FEAST_FWD_STEP(3)
 #undef FEAST_FWD_STEP
 #pragma unroll
-      for (int i = 0; i < WF; ++i) w[i] = w[i + UF];
+      for (int i = 0; i < H; ++i) w[i] = w[i + UF];
     }
   }
 }
@@ -489,7 +520,7 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
     const int ch = static_cast<int>(k1 < kBandCH ? k1 : kBandCH);
     const int64_t kb0 = k1 - ch;  // rows kb0 .. k1 - 1
     __syncthreads();
-    BandStage::padded<WB>(fac, U + kb0 * WC, WC, 1, WU, ch, lane);
+    BandStage::padded<WB>(fac, U + kb0 * WC, WC, 1, 0, WU, ch, lane);
     if (lane < ch) dinv[lane] = Di[kb0 + lane];
     BandStage::rows(rows, Yj, ldy, kb0, ch, n, cc, lane);
     __syncthreads();
@@ -614,10 +645,11 @@ void band_solve(hipStream_t s, const z64 *Lf, const z64 *Uf, const z64 *Dinv, co
                 int32_t N, int64_t n, int kl, int ku, const z64 *R, int64_t ldr, int64_t m,
                 z64 *Y, int64_t ldy, int64_t sY) {
   if (N <= 0 || n <= 0 || m <= 0) return;
-  const dim3 gf(N, static_cast<unsigned>((m + 63) / 64)), gb(N, static_cast<unsigned>((m + 31) / 32));
-  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, gf, dim3(64), 0, s, Lf, piv, n, kl, R, ldr,
+  // both kernels: 32 columns per wavefront, two lanes per column
+  const dim3 g(N, static_cast<unsigned>((m + 31) / 32));
+  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, g, dim3(64), 0, s, Lf, piv, n, kl, R, ldr,
                       m, Y, ldy, sY)
-  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, gb, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
+  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, g, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
                       Y, ldy, sY)
 }
 
