@@ -143,6 +143,53 @@ def test_one_plan_reuses_the_ordering_not_the_values():
     assert r3.band == r0.band and _match(r3.lam, r0.lam) <= 1e-12 * scale
 
 
+def _wide_band_pencil(n, kl, ku, seed):
+    """A full random band (kl below, ku above the diagonal) on a spread
+    diagonal: eigenvalue condition numbers stay below about 12, and z B - A
+    on the contour pivots on about a fifth of its columns, anywhere in the
+    kl rows below the diagonal."""
+    rng = np.random.default_rng(seed)
+    i, j = np.indices((n, n))
+    band = (j - i <= ku) & (i - j <= kl)
+    N1 = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    N2 = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    d = np.linspace(-4, 4, n) + 0.05j * rng.normal(size=n)
+    A = np.where(band, 0.02 * N1, 0) + np.diag(d)
+    B = np.where(band, 0.002 * N2, 0) + np.eye(n)
+    return A.astype(np.complex128), B.astype(np.complex128)
+
+
+@pytest.mark.parametrize("kl,ku", [(62, 1), (1, 62), (47, 16), (16, 47), (31, 31), (23, 8),
+                                   (8, 15)])
+def test_wide_bands_every_window_class(kl, ku):
+    """Bands up to kl + ku = 63 in the natural order, so that every register
+    window class of the band LU and the forward solve (kl + 1 up to 16, 24,
+    32, 48, 64 rows) and of the backward solve (kl + ku up to 24, 32, 64) runs:
+    the eigenvalues inside the circle are those of the dense spectrum and of
+    the dense path."""
+    import scipy.linalg as sl
+    n = 480
+    A, B = _wide_band_pencil(n, kl, ku, 1000 + 64 * kl + ku)
+    lam = sl.eigvals(A, B)
+    c = lam[np.argmin(np.abs(lam - 0.3))]
+    dist = np.sort(np.abs(lam - c))
+    r = 0.5 * (dist[9] + dist[10])
+    inside = lam[np.abs(lam - c) < r]
+    V = np.random.default_rng(3).normal(size=(n, 2 * len(inside) + 4)).astype(np.complex128)
+    res = _solve_csr(A, B, V, c, r)
+    assert res.band == (kl, ku)
+    assert res.flag == 1 and len(res.lam) == len(inside)
+    scale = max(1.0, abs(c) + r)
+    assert _match(res.lam, inside) <= 1e-8 * scale
+    dA, dB, dV = (torch.from_numpy(np.ascontiguousarray(x)).to("cuda") for x in (A, B, V))
+    with fm.Plan(n, V.shape[1], c, r, 16, rule=fm.GAUSS_LEGENDRE, eps=1e-10,
+                 prec=fm.FP64) as plan:
+        rd = plan.solve(dA, dB, dV)
+    assert len(rd.lam) == len(res.lam) and _match(res.lam, rd.lam) <= 1e-9 * scale
+    X = res.X.cpu().numpy()
+    assert np.all(_residuals(A, B, X, res.lam) <= 1e-9)
+
+
 def test_diagonal_pencil_closed_form():
     """kl = ku = 0: A = diag(d), B = I has eigenvalues d exactly."""
     n = 600
