@@ -98,21 +98,34 @@ __device__ inline z64 band_fms(z64 a, z64 b, z64 c) {
   return zmake(fma(b.y, c.y, fma(-b.x, c.x, a.x)), fma(-b.y, c.x, fma(-b.x, c.y, a.y)));
 }
 
+// 1 / (x + i y) with one division: scaled first by the power of two 2^-e that
+// puts the larger of |x|, |y| in [1/2, 1) (exact), so the squared modulus lies
+// in [1/4, 2] and neither overflows nor underflows; then conj / |.|^2, scaled
+// back.  (The shared zrecip, Smith's method, takes two divisions; here the
+// reciprocal is on the pivot's critical path.)  x + i y != 0.
+__device__ inline z64 band_recip(double x, double y) {
+  int e;
+  (void)frexp(fmax(fabs(x), fabs(y)), &e);
+  const double a = ldexp(x, -e), b = ldexp(y, -e);
+  const double d = 1.0 / fma(a, a, b * b);
+  return zmake(ldexp(a * d, -e), ldexp(-b * d, -e));
+}
+
 // One workgroup (256 threads) per node j.  Thread t < WC owns window column
 // slot t for the whole factorisation and keeps that column's rows k .. k + kl
 // in registers (w[i] = row k + i; W >= kl + 1 is the compile-time bound); slot
 // t holds column k + ((t - k) mod WC).  Every kBandCH columns the workgroup
 // stages the next kBandCH incoming rows (row k + kl + 1 enters at column k) as
 // dense band rows of z_j B - A in LDS, every load issued before the first
-// wait.  Per column k, one barrier:
+// wait.  The owners (WC <= 64) are lanes of wave 0, which does every column's
+// work; the other waves only stage.  Per column k, one wavefront barrier:
 //   before it, the owner of column k posts that column to LDS and wave 0 finds
 //   the pivot (largest |re| + |im|, lowest row on ties) and the multipliers;
 //   after it, every owner exchanges rows k and k + p of its column, writes its
 //   entry of U's row k, applies the multipliers, moves its rows up by one and
 //   takes the staged row's entry as row k + kl + 1 (the owner of column k
 //   starts column k + WC, zero above the new row).
-// The multipliers are double-buffered by the parity of k, so the next
-// column's cannot overwrite what an owner is still reading.
+// The multipliers are double-buffered by the parity of k.
 template <int W>
 __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
@@ -131,7 +144,6 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
   __shared__ int32_t srp[kBandCH + 1];
   __shared__ z64 colbuf[64];
   __shared__ z64 sl[2][64];  // multipliers of column k (index 1 .. kl)
-  __shared__ int s_p[2];
   __shared__ int s_info;
   const int j = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -222,7 +234,7 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
         const double ux = lane_at(v.x, p), uy = lane_at(v.y, p);
         const double v0x = lane_at(v.x, 0), v0y = lane_at(v.y, 0);
         const bool zero = !(key > 0.0);
-        const z64 inv = zero ? zmake(0.0, 0.0) : zrecip(zmake(ux, uy));
+        const z64 inv = zero ? zmake(0.0, 0.0) : band_recip(ux, uy);
         if (i >= 1 && i < W) {  // zero past row k + kl and past row n - 1
           const z64 src = (i == p) ? zmake(v0x, v0y) : v;
           const z64 l = valid ? zmul(src, inv) : zmake(0.0, 0.0);
@@ -230,63 +242,74 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
           if (i < KR) L[k * kl + (i - 1)] = l;
         }
         if (lane == 0) {
-          s_p[par] = p;
           pv[k] = static_cast<int32_t>(k + p);
           Di[k] = inv;
           if (zero && s_info == 0) s_info = static_cast<int>(k) + 1;
         }
-      }
-      __syncthreads();
-      if (owner) {
-        const int p = __builtin_amdgcn_readfirstlane(s_p[par]);
-        int jo = tid - ck;  // this column's offset from column k
-        if (jo < 0) jo += WC;
-        // exchange rows k and k + p (row k's slot is dead after the step):
-        // one uniform branch per slot, the empty asm keeping each arm a
-        // branch rather than a select of four registers per slot
-        z64 rpv = w[0];
-        if (p != 0) {
+        // every owner is a lane of this wavefront: a wavefront barrier makes
+        // the multipliers visible
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (owner) {
+          int jo = tid - ck;  // this column's offset from column k
+          if (jo < 0) jo += WC;
+          // exchange rows k and k + p (row k's slot is dead after the step):
+          // one uniform branch per slot, the empty asm keeping each arm a
+          // branch rather than a select of four registers per slot
+          z64 rpv = w[0];
+          if (p != 0) {
 #pragma unroll
-          for (int i = 1; i < W; ++i)
-            if (i == p) {
+            for (int i = 1; i < W; ++i)
+              if (i == p) {
+                asm volatile("" ::: "memory");
+                rpv = w[i];
+                w[i] = w[0];
+              }
+          }
+          U[k * WC + jo] = (k + jo < n) ? rpv : zmake(0.0, 0.0);
+          // the incoming row k + KR at this slot's next column (k + jo, or
+          // k + WC for the slot of column k): staged index WC - 1 or jo - 1
+          const z64 nv = (kk < cnt) ? SR[kk * WC + (jo == 0 ? WC - 1 : jo - 1)] : zmake(0.0, 0.0);
+          // the multipliers (zero past row k + kl: no bound per row) in groups
+          // of G, all in flight before the group's first product
+          const z64 *lk = sl[par];
+          constexpr int G = W <= 24 ? W - 1 : 8;
+#pragma unroll
+          for (int g = 1; g < W; g += G) {
+            z64 lr[G];
+#pragma unroll
+            for (int t = 0; t < G; ++t)
+              if (g + t < W) lr[t] = lk[g + t];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < G; ++t)
+              if (g + t < W) w[g + t] = band_fms(w[g + t], lr[t], rpv);
+          }
+          // rows move up one slot; the slot of column k (leaving) starts column
+          // k + WC with zeros above the incoming row: one multiply by 1 or 0
+          // per entry does both (the window's entries are finite).  The widest
+          // window has no registers for the products: it zeroes, then moves.
+          if constexpr (W <= 48) {
+            const double keep = jo == 0 ? 0.0 : 1.0;
+#pragma unroll
+            for (int i = 0; i + 1 < W; ++i) w[i] = zmake(w[i + 1].x * keep, w[i + 1].y * keep);
+          } else {
+            if (jo == 0) {
               asm volatile("" ::: "memory");
-              rpv = w[i];
-              w[i] = w[0];
+#pragma unroll
+              for (int i = 0; i < W; ++i) w[i] = zmake(0.0, 0.0);
+            }
+#pragma unroll
+            for (int i = 0; i + 1 < W; ++i) w[i] = w[i + 1];
+          }
+          w[W - 1] = zmake(0.0, 0.0);
+#pragma unroll
+          for (int i = 0; i < W; ++i)
+            if (i == KR - 1) {
+              asm volatile("" ::: "memory");
+              w[i] = nv;
             }
         }
-        U[k * WC + jo] = (k + jo < n) ? rpv : zmake(0.0, 0.0);
-        // the incoming row k + KR at this slot's next column (k + jo, or
-        // k + WC for the slot of column k): staged index WC - 1 or jo - 1
-        const z64 nv = (kk < cnt) ? SR[kk * WC + (jo == 0 ? WC - 1 : jo - 1)] : zmake(0.0, 0.0);
-        // the multipliers (zero past row k + kl: no bound per row) in groups
-        // of G, all in flight before the group's first product
-        const z64 *lk = sl[par];
-        constexpr int G = W <= 24 ? W - 1 : 8;
-#pragma unroll
-        for (int g = 1; g < W; g += G) {
-          z64 lr[G];
-#pragma unroll
-          for (int t = 0; t < G; ++t)
-            if (g + t < W) lr[t] = lk[g + t];
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int t = 0; t < G; ++t)
-            if (g + t < W) w[g + t] = band_fms(w[g + t], lr[t], rpv);
-        }
-        if (jo == 0) {  // column k leaves: the slot starts column k + WC
-          asm volatile("" ::: "memory");
-#pragma unroll
-          for (int i = 0; i < W; ++i) w[i] = zmake(0.0, 0.0);
-        }
-#pragma unroll
-        for (int i = 0; i + 1 < W; ++i) w[i] = w[i + 1];
-        w[W - 1] = zmake(0.0, 0.0);
-#pragma unroll
-        for (int i = 0; i < W; ++i)
-          if (i == KR - 1) {
-            asm volatile("" ::: "memory");
-            w[i] = nv;
-          }
       }
       if (++ck == WC) ck = 0;
     }
@@ -297,10 +320,11 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
 
 // The node solves Y_j = M_j^{-1} R with M_j's band factors (node j =
 // blockIdx.x), as two kernels so that each holds one window in registers:
-//   k_band_fwd: exchanges and unit-lower multipliers, one lane per right-hand
-//     side (64 columns of R per blockIdx.y); a lane keeps rows
-//     k .. k + WF - 1 of its column (WF >= kl + 1; rows past k + kl wait
-//     unchanged) and writes row k of the result to Y_j;
+//   k_band_fwd: exchanges and unit-lower multipliers, two lanes per
+//     right-hand side (32 columns of R per blockIdx.y): lanes l and l + 32
+//     keep rows k .. k + WF / 2 - 1 and the WF / 2 rows after them of column
+//     l (WF >= kl + 1; rows past k + kl wait unchanged) and write row k of
+//     the result to Y_j;
 //   k_band_bwd: U, two lanes per right-hand side (32 columns per
 //     blockIdx.y): lane l keeps the solved rows k + 1 .. k + WB / 2 of
 //     column l, lane l + 32 the rows after them (WB >= kl + ku); each sums
