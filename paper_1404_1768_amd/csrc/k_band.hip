@@ -325,11 +325,12 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
 //     keep rows k .. k + WF / 2 - 1 and the WF / 2 rows after them of column
 //     l (WF >= kl + 1; rows past k + kl wait unchanged) and write row k of
 //     the result to Y_j;
-//   k_band_bwd: U, two lanes per right-hand side (32 columns per
-//     blockIdx.y): lane l keeps the solved rows k + 1 .. k + WB / 2 of
-//     column l, lane l + 32 the rows after them (WB >= kl + ku); each sums
-//     its half of row k's products, the halves add, and lane l overwrites row
-//     k of Y_j with the solution (times the stored pivot reciprocal).
+//   k_band_bwd: U, four lanes per right-hand side (16 columns per
+//     blockIdx.y): lanes l, l + 16, l + 32, l + 48 keep the solved rows
+//     k + 1 .. k + WB / 4 of column l and the three runs of WB / 4 rows after
+//     them (WB >= kl + ku); each sums its quarter of row k's products, the
+//     quarters add, and lane l overwrites row k of Y_j with the solution
+//     (times the stored pivot reciprocal).
 // Factor rows and block rows are staged kBandCH at a time through LDS (loads
 // issued 16 at a time before they are written), so each step reads only LDS
 // and registers.
@@ -503,15 +504,20 @@ __global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
   }
 }
 
-// (v of lane l mod 32, v of lane 32 + l mod 32) in every lane l, one
-// v_permlane32_swap per dword (both halves see the pair in the same order)
-__device__ inline void band_halves(double v, double &lo, double &hi) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const unsigned u0 = static_cast<unsigned>(u), u1 = static_cast<unsigned>(u >> 32);
-  const auto a = __builtin_amdgcn_permlane32_swap(u0, u0, false, false);
-  const auto b = __builtin_amdgcn_permlane32_swap(u1, u1, false, false);
-  lo = __builtin_bit_cast(double, static_cast<uint64_t>(a[0]) | (static_cast<uint64_t>(b[0]) << 32));
-  hi = __builtin_bit_cast(double, static_cast<uint64_t>(a[1]) | (static_cast<uint64_t>(b[1]) << 32));
+// Across the four quarters of a wavefront (lanes l, l + 16, l + 32, l + 48 for
+// l < 16): the sum of v over the four, added in the same order in every lane,
+// and the value of the previous quarter (quarter 0 gets its own back).
+__device__ inline double quarter_sum(double v) {
+  double a, b, c, d;
+  swap_pair<false>(v, a, b);  // quarters 0 + 2 and 1 + 3
+  swap_pair<true>(a + b, c, d);
+  return c + d;
+}
+__device__ inline double quarter_prev(double v, int qt) {
+  double e, o, lo, hi;
+  swap_pair<true>(v, e, o);                   // even and odd quarter's of each pair
+  swap_pair<false>(qt == 0 ? o : v, lo, hi);  // quarter 2 gets quarter 0's: quarter 1's value
+  return (qt & 1) ? e : (qt == 2 ? lo : v);
 }
 
 template <int WB>
@@ -519,27 +525,26 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
                                                  const z64 *__restrict__ Dinv, int64_t n, int kl,
                                                  int ku, int64_t m, z64 *__restrict__ Y,
                                                  int64_t ldy, int64_t sY) {
-  constexpr int UB = kBandU, H = WB / 2, G = H > 24 ? H / 2 : H;
-  static_assert(H >= UB, "the far half's block rows come from the near half's window");
-  static_assert(H % G == 0, "whole factor groups");
+  constexpr int UB = kBandU, Q = WB / 4;
+  static_assert(WB % 4 == 0 && Q >= UB, "a quarter's block rows come from the quarter before");
   const int WC = kl + ku + 1, WU = kl + ku;
   __shared__ z64 fac[kBandCH * WB];  // kBandCH rows of U past the diagonal (WU each, zero-padded)
-  __shared__ z64 rows[kBandCH][64];  // the forward results of those rows (both halves load them)
+  __shared__ z64 rows[kBandCH][64];  // the forward results of those rows (all quarters load them)
   __shared__ z64 dinv[kBandCH];
-  const int j = blockIdx.x, lane = threadIdx.x, half = lane >> 5;
-  const int64_t col = static_cast<int64_t>(blockIdx.y) * 32 + (lane & 31);
+  const int j = blockIdx.x, lane = threadIdx.x, qt = lane >> 4;
+  const int64_t col = static_cast<int64_t>(blockIdx.y) * 16 + (lane & 15);
   const bool act = col < m;
   const int64_t cc = act ? col : m - 1;
   const z64 *U = Uf + static_cast<int64_t>(j) * n * WC;
   const z64 *Di = Dinv + static_cast<int64_t>(j) * n;
   z64 *Yj = Y + static_cast<int64_t>(j) * sY;
-  // Lanes l and l + 32 share column l: the near half sums the terms t = 1 .. H
-  // of row k, the far half t = H + 1 .. 2H.  Step r of a block (rows
-  // descending): b[UB - 1 - r + t] = solved row k + t (near) or k + H + t
-  // (far); rows past n - 1 stay zero (and U's entries there are stored zero).
-  z64 b[H + UB];
+  // Lanes l, l + 16, l + 32, l + 48 share column l: quarter q sums the terms
+  // t = qQ + 1 .. (q + 1)Q of row k.  Step r of a block (rows descending):
+  // b[UB - 1 - r + t] = solved row k + qQ + t, t = 1 .. Q; rows past n - 1
+  // stay zero (and U's entries there are stored zero).
+  z64 b[Q + UB];
 #pragma unroll
-  for (int i = 0; i < H + UB; ++i) b[i] = zmake(0.0, 0.0);
+  for (int i = 0; i < Q + UB; ++i) b[i] = zmake(0.0, 0.0);
   for (int64_t k1 = n; k1 > 0; k1 -= kBandCH) {
     const int ch = static_cast<int>(k1 < kBandCH ? k1 : kBandCH);
     const int64_t kb0 = k1 - ch;  // rows kb0 .. k1 - 1
@@ -549,49 +554,38 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
     BandStage::rows(rows, Yj, ldy, kb0, ch, n, cc, lane);
     __syncthreads();
     for (int q = 0; q < ch; q += UB) {
-      // the far half's first UB slots are the near half's last UB (the near
-      // half's own are rewritten by this block's rows before it reads them)
+      // a quarter's first UB slots are the previous quarter's last UB
+      // (quarter 0's own are rewritten by this block's rows before it reads
+      // them)
 #pragma unroll
-      for (int i = 0; i < UB; ++i) {
-        double lo, hi;
-        band_halves(b[H + i].x, lo, hi);
-        b[i].x = lo;
-        band_halves(b[H + i].y, lo, hi);
-        b[i].y = lo;
-      }
+      for (int i = 0; i < UB; ++i)
+        b[i] = zmake(quarter_prev(b[Q + i].x, qt), quarter_prev(b[Q + i].y, qt));
       const int nb = __builtin_amdgcn_readfirstlane(ch - q);  // the last chunk may end inside a block
 #pragma unroll
       for (int r = 0; r < UB; ++r) {
         if (r < nb) {
           const int kk = ch - 1 - (q + r);
-          const z64 *f = fac + kk * WB + half * H;
-          z64 s2[2] = {half == 0 ? rows[kk][lane] : zmake(0.0, 0.0), zmake(0.0, 0.0)};
-          // the factor loads of a group (the whole row up to H = 24) all in
-          // flight before its first product
+          const z64 *f = fac + kk * WB + qt * Q;
+          z64 s2[2] = {qt == 0 ? rows[kk][lane] : zmake(0.0, 0.0), zmake(0.0, 0.0)};
+          // the quarter's factor loads all in flight before its first product
+          z64 fr[Q];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int g = 0; g < H; g += G) {
-            z64 fr[G];
-            __builtin_amdgcn_sched_barrier(0);
+          for (int t = 0; t < Q; ++t) fr[t] = f[t];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int t = 0; t < G; ++t) fr[t] = f[g + t];
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int t = g + 1; t <= g + G; ++t)
-              s2[t & 1] = band_fms(s2[t & 1], fr[t - 1 - g], b[UB - 1 - r + t]);
-          }
-          const z64 sh = zadd(s2[0], s2[1]);
-          double xl, xh, yl, yh;
-          band_halves(sh.x, xl, xh);
-          band_halves(sh.y, yl, yh);
-          const z64 y = zmul(zmake(xl + xh, yl + yh), dinv[kk]);
-          if (half == 0) {
+          for (int t = 1; t <= Q; ++t)
+            s2[t & 1] = band_fms(s2[t & 1], fr[t - 1], b[UB - 1 - r + t]);
+          const z64 sq = zadd(s2[0], s2[1]);
+          const z64 y = zmul(zmake(quarter_sum(sq.x), quarter_sum(sq.y)), dinv[kk]);
+          if (qt == 0) {
             if (act) Yj[(kb0 + kk) * ldy + col] = y;
             b[UB - 1 - r] = y;
           }
         }
       }
 #pragma unroll
-      for (int i = H - 1; i >= 0; --i) b[i + UB] = b[i];
+      for (int i = Q - 1; i >= 0; --i) b[i + UB] = b[i];
     }
   }
 }
@@ -669,11 +663,12 @@ void band_solve(hipStream_t s, const z64 *Lf, const z64 *Uf, const z64 *Dinv, co
                 int32_t N, int64_t n, int kl, int ku, const z64 *R, int64_t ldr, int64_t m,
                 z64 *Y, int64_t ldy, int64_t sY) {
   if (N <= 0 || n <= 0 || m <= 0) return;
-  // both kernels: 32 columns per wavefront, two lanes per column
-  const dim3 g(N, static_cast<unsigned>((m + 31) / 32));
-  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, g, dim3(64), 0, s, Lf, piv, n, kl, R, ldr,
+  // forward: 32 columns per wavefront (two lanes each); backward: 16 (four)
+  const dim3 gf(N, static_cast<unsigned>((m + 31) / 32));
+  const dim3 gb(N, static_cast<unsigned>((m + 15) / 16));
+  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, gf, dim3(64), 0, s, Lf, piv, n, kl, R, ldr,
                       m, Y, ldy, sY)
-  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, g, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
+  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, gb, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
                       Y, ldy, sY)
 }
 
