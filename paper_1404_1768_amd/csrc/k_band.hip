@@ -71,10 +71,11 @@ __device__ inline void wave_argmax(double &key, int &idx) {
       idx = oi;
     }
   };
-  take(dpp_f64<0xB1>(key), __builtin_amdgcn_mov_dpp(idx, 0xB1, 0xF, 0xF, false));     // lane ^ 1
-  take(dpp_f64<0x4E>(key), __builtin_amdgcn_mov_dpp(idx, 0x4E, 0xF, 0xF, false));     // lane ^ 2
-  take(dpp_f64<0x141>(key), __builtin_amdgcn_mov_dpp(idx, 0x141, 0xF, 0xF, false));   // 7 - lane mod 8
-  take(dpp_f64<0x140>(key), __builtin_amdgcn_mov_dpp(idx, 0x140, 0xF, 0xF, false));   // 15 - lane mod 16
+  // partners: lane ^ 1, lane ^ 2, 7 - lane mod 8, 15 - lane mod 16
+  take(dpp_f64<0xB1>(key), __builtin_amdgcn_mov_dpp(idx, 0xB1, 0xF, 0xF, false));
+  take(dpp_f64<0x4E>(key), __builtin_amdgcn_mov_dpp(idx, 0x4E, 0xF, 0xF, false));
+  take(dpp_f64<0x141>(key), __builtin_amdgcn_mov_dpp(idx, 0x141, 0xF, 0xF, false));
+  take(dpp_f64<0x140>(key), __builtin_amdgcn_mov_dpp(idx, 0x140, 0xF, 0xF, false));
   double k0, k1;
   int i0, i1;
   swap_pair<true>(key, k0, k1);  // rows 2r and 2r + 1
@@ -560,7 +561,8 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
 #pragma unroll
       for (int i = 0; i < UB; ++i)
         b[i] = zmake(quarter_prev(b[Q + i].x, qt), quarter_prev(b[Q + i].y, qt));
-      const int nb = __builtin_amdgcn_readfirstlane(ch - q);  // the last chunk may end inside a block
+      // the last chunk may end inside a block
+      const int nb = __builtin_amdgcn_readfirstlane(ch - q);
 #pragma unroll
       for (int r = 0; r < UB; ++r) {
         if (r < nb) {
