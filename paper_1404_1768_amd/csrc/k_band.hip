@@ -138,14 +138,24 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
                                                  int32_t *__restrict__ piv,
                                                  int32_t *__restrict__ info) {
   const int KR = kl + 1, WC = kl + ku + 1;
-  // the staged rows of a chunk (row q of the chunk at SR[q WC + c - (row -
-  // kl)], c its column); the first window's rows 0 .. kl pass through it
-  // kBandCH at a time
-  __shared__ z64 SR[kBandCH * 64];
-  __shared__ int32_t srp[kBandCH + 1];
-  __shared__ z64 colbuf[64];
-  __shared__ z64 sl[2][64];  // multipliers of column k (index 1 .. kl)
-  __shared__ int s_info;
+  // one block, so that the per-column arrays sit at the low LDS addresses
+  // (immediate offsets) whatever the allocator's order
+  struct Lds {
+    z64 sl[2][64];  // multipliers of column k (index 1 .. kl), by the parity of k
+    z64 colbuf[64];
+    int32_t srp[kBandCH + 1];
+    int info;
+    // the staged rows of two chunks (row q of a chunk at SR[b][q WC + c -
+    // (row - kl)], c its column); the first window's rows 0 .. kl pass
+    // through SR[0] kBandCH at a time
+    z64 SR[2][kBandCH * 64];
+  };
+  __shared__ Lds sm;
+  auto &sl = sm.sl;
+  auto &colbuf = sm.colbuf;
+  auto &srp = sm.srp;
+  auto &s_info = sm.info;
+  z64 *SR = sm.SR[0];
   const int j = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
   const z64 z = zn[j];
@@ -187,6 +197,33 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
     __syncthreads();
   };
 
+  // waves 1-3 (192 threads, 6 per row): rows r0 .. r0 + cnt - 1 (< n) into
+  // SR[b] while wave 0 factors; each thread owns the slots c = sub mod 6 of
+  // its row, zeroes them and writes the row's entries that fall there, so no
+  // barrier orders the staging threads among themselves
+  static_assert(192 / 6 >= kBandCH, "a staging row per 6 threads");
+  auto stage_bg = [&](int b, int64_t r0, int cnt) {
+    const int t = tid - 64, row = t / 6, sub = t - 6 * row;
+    if (row >= cnt) return;
+    z64 *dst = sm.SR[b] + row * WC;
+    for (int c = sub; c < WC; c += 6) dst[c] = zmake(0.0, 0.0);
+    const int64_t r = r0 + row;
+    const int64_t base = r - kl;  // the column of slot 0
+    for (int e = rp[r], e1 = rp[r + 1]; e < e1; ++e) {
+      const int c = static_cast<int>(ci[e] - base);
+      if (c % 6 == sub) {
+        const z64 bv = vb[e], av = va[e];
+        dst[c] = zmake(z.x * bv.x - z.y * bv.y - av.x, z.x * bv.y + z.y * bv.x - av.y);
+      }
+    }
+  };
+  // the rows entering during the chunk of columns k0 .. k0 + kBandCH - 1
+  auto chunk_rows = [&](int64_t k0, int64_t *r0) {
+    const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
+    *r0 = k0 + KR;
+    return *r0 < n ? static_cast<int>(n - *r0 < ch ? n - *r0 : ch) : 0;
+  };
+
   if (tid == 0) s_info = 0;
   const bool owner = tid < WC;
   z64 w[W];
@@ -205,18 +242,31 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
     }
   }
 
+  __syncthreads();  // the first window is read: SR[0] takes chunk 0's rows
+  if (tid >= 64) {
+    int64_t r0;
+    const int cnt = chunk_rows(0, &r0);
+    stage_bg(0, r0, cnt);
+  }
   int ck = 0;  // slot of column k
-  for (int64_t k0 = 0; k0 < n; k0 += kBandCH) {
+  for (int64_t k0 = 0, c = 0; k0 < n; k0 += kBandCH, ++c) {
     const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
-    // incoming rows of this chunk's columns: k0 + KR .. (those below n)
-    const int64_t r0 = k0 + KR;
-    const int cnt = r0 < n ? static_cast<int>(n - r0 < ch ? n - r0 : ch) : 0;
-    __syncthreads();
-    stage(r0 < n ? r0 : 0, cnt);
+    int64_t r0;
+    const int cnt = chunk_rows(k0, &r0);  // incoming rows of this chunk's columns
+    const z64 *SRc = sm.SR[c & 1];
+    __syncthreads();  // this chunk's rows are staged; the other buffer is free
+    if (tid >= 64) {  // the next chunk's rows, while wave 0 factors this one's
+      if (k0 + kBandCH < n) {
+        int64_t r0n;
+        const int cntn = chunk_rows(k0 + kBandCH, &r0n);
+        stage_bg(static_cast<int>((c + 1) & 1), r0n, cntn);
+      }
+      continue;
+    }
     for (int kk = 0; kk < ch; ++kk) {
       const int64_t k = k0 + kk;
       const int par = static_cast<int>(k & 1);
-      if (tid < 64) {
+      {
         if (tid == ck) {
 #pragma unroll
           for (int i = 0; i < W; ++i) colbuf[i] = w[i];  // (rows past k + kl are not read)
@@ -270,7 +320,7 @@ __global__ __launch_bounds__(256) void k_band_lu(const int32_t *__restrict__ rp,
           U[k * WC + jo] = (k + jo < n) ? rpv : zmake(0.0, 0.0);
           // the incoming row k + KR at this slot's next column (k + jo, or
           // k + WC for the slot of column k): staged index WC - 1 or jo - 1
-          const z64 nv = (kk < cnt) ? SR[kk * WC + (jo == 0 ? WC - 1 : jo - 1)] : zmake(0.0, 0.0);
+          const z64 nv = (kk < cnt) ? SRc[kk * WC + (jo == 0 ? WC - 1 : jo - 1)] : zmake(0.0, 0.0);
           // the multipliers (zero past row k + kl: no bound per row) in groups
           // of G, all in flight before the group's first product
           const z64 *lk = sl[par];
