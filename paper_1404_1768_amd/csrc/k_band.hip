@@ -498,17 +498,18 @@ __device__ inline z64 band_fwd_row(z64 (&w)[N], const z64 *f, int p, z64 nv, int
 }
 
 template <int WF>
-__global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
-                                                 const int32_t *__restrict__ piv, int64_t n,
-                                                 int kl, const z64 *__restrict__ R, int64_t ldr,
-                                                 int64_t m, z64 *__restrict__ Y, int64_t ldy,
-                                                 int64_t sY) {
+__global__ __launch_bounds__(128) void k_band_fwd(const z64 *__restrict__ Lf,
+                                                  const int32_t *__restrict__ piv, int64_t n,
+                                                  int kl, const z64 *__restrict__ R, int64_t ldr,
+                                                  int64_t m, z64 *__restrict__ Y, int64_t ldy,
+                                                  int64_t sY) {
   constexpr int UF = kBandU, H = WF / 2;
   static_assert(WF % 2 == 0, "two halves of the window");
-  __shared__ z64 fac[kBandCH * WF];  // per row: 0, then the kl multipliers, zero-padded
-  __shared__ z64 rows[kBandCH][64];  // the rows of R entering the window (both halves load them)
-  __shared__ int32_t s_piv[kBandCH];
-  const int j = blockIdx.x, lane = threadIdx.x, half = lane >> 5;
+  // two chunks' staging (wave 1 fills one while wave 0 solves from the other)
+  __shared__ z64 fac[2][kBandCH * WF];  // per row: 0, then the kl multipliers, zero-padded
+  __shared__ z64 rows[2][kBandCH][64];  // the rows of R entering the window (both halves load them)
+  __shared__ int32_t s_piv[2][kBandCH];
+  const int j = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5;
   const int64_t col = static_cast<int64_t>(blockIdx.y) * 32 + (lane & 31);
   const bool act = col < m;
   // idle lanes (col >= m, in the last block only) duplicate column m - 1 of
@@ -517,21 +518,30 @@ __global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
   const z64 *L = Lf + static_cast<int64_t>(j) * n * kl;
   const int32_t *pv = piv + static_cast<int64_t>(j) * n;
   z64 *Yj = Y + static_cast<int64_t>(j) * sY;
+  // wave 1: the chunk of rows k0 .. k0 + kBandCH - 1 into buffer b
+  auto stage = [&](int b, int64_t k0) {
+    const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
+    BandStage::padded<WF>(fac[b], L + k0 * kl, kl, -1, 1, kl + 1, ch, lane);
+    if (lane < ch) s_piv[b][lane] = pv[k0 + lane] - static_cast<int32_t>(k0 + lane);
+    BandStage::rows(rows[b], R, ldr, k0 + WF, ch, n, cc, lane);
+  };
   z64 w[H + UF];
 #pragma unroll
   for (int i = 0; i < H + UF; ++i) {
     const int64_t row = static_cast<int64_t>(half) * H + i;
     w[i] = (i < H && row < n) ? R[row * ldr + cc] : zmake(0.0, 0.0);
   }
-  for (int64_t k0 = 0; k0 < n; k0 += kBandCH) {
+  if (wv == 1) stage(0, 0);
+  for (int64_t k0 = 0, c = 0; k0 < n; k0 += kBandCH, ++c) {
     const int ch = static_cast<int>(n - k0 < kBandCH ? n - k0 : kBandCH);
-    __syncthreads();
-    BandStage::padded<WF>(fac, L + k0 * kl, kl, -1, 1, kl + 1, ch, lane);
-    if (lane < ch) s_piv[lane] = pv[k0 + lane] - static_cast<int32_t>(k0 + lane);
-    BandStage::rows(rows, R, ldr, k0 + WF, ch, n, cc, lane);
-    __syncthreads();
+    const int b = static_cast<int>(c & 1);
+    __syncthreads();  // this chunk is staged; the other buffer is free
+    if (wv == 1) {
+      if (k0 + kBandCH < n) stage(b ^ 1, k0 + kBandCH);
+      continue;
+    }
     for (int kb = 0; kb < ch; kb += UF) {
-      const z64 *f = fac + kb * WF + half * H;
+      const z64 *f = fac[b] + kb * WF + half * H;
       // unconditional stores (no divergent branch in the row; both halves
       // store the same y)
       z64 *yk = Yj + (k0 + kb) * ldy + cc;
@@ -540,11 +550,11 @@ __global__ __launch_bounds__(64) void k_band_fwd(const z64 *__restrict__ Lf,
       // the block's exchanges, read together (kb + UF <= kBandCH: in bounds)
       int pb[UF];
 #pragma unroll
-      for (int r = 0; r < UF; ++r) pb[r] = s_piv[kb + r];
+      for (int r = 0; r < UF; ++r) pb[r] = s_piv[b][kb + r];
 #define FEAST_FWD_STEP(r)                                                                   \
   if (r < nb) {                                                                             \
     const int p = __builtin_amdgcn_readfirstlane(pb[r]);                                    \
-    const z64 y = band_fwd_row<H, r>(w, f + r * WF, p, rows[kb + r][lane], half);           \
+    const z64 y = band_fwd_row<H, r>(w, f + r * WF, p, rows[b][kb + r][lane], half);        \
     yk[r * ldy] = y;                                                                        \
   }
       FEAST_FWD_STEP(0) FEAST_FWD_STEP(1) FEAST_FWD_STEP(2) FEAST_FWD_STEP(3)
@@ -572,17 +582,18 @@ __device__ inline double quarter_prev(double v, int qt) {
 }
 
 template <int WB>
-__global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
-                                                 const z64 *__restrict__ Dinv, int64_t n, int kl,
-                                                 int ku, int64_t m, z64 *__restrict__ Y,
-                                                 int64_t ldy, int64_t sY) {
+__global__ __launch_bounds__(128) void k_band_bwd(const z64 *__restrict__ Uf,
+                                                  const z64 *__restrict__ Dinv, int64_t n, int kl,
+                                                  int ku, int64_t m, z64 *__restrict__ Y,
+                                                  int64_t ldy, int64_t sY) {
   constexpr int UB = kBandU, Q = WB / 4;
   static_assert(WB % 4 == 0 && Q >= UB, "a quarter's block rows come from the quarter before");
   const int WC = kl + ku + 1, WU = kl + ku;
-  __shared__ z64 fac[kBandCH * WB];  // kBandCH rows of U past the diagonal (WU each, zero-padded)
-  __shared__ z64 rows[kBandCH][64];  // the forward results of those rows (all quarters load them)
-  __shared__ z64 dinv[kBandCH];
-  const int j = blockIdx.x, lane = threadIdx.x, qt = lane >> 4;
+  // two chunks' staging (wave 1 fills one while wave 0 solves from the other)
+  __shared__ z64 fac[2][kBandCH * WB];  // rows of U past the diagonal (WU each, zero-padded)
+  __shared__ z64 rows[2][kBandCH][64];  // the forward results of those rows (all quarters)
+  __shared__ z64 dinv[2][kBandCH];
+  const int j = blockIdx.x, wv = threadIdx.x >> 6, lane = threadIdx.x & 63, qt = lane >> 4;
   const int64_t col = static_cast<int64_t>(blockIdx.y) * 16 + (lane & 15);
   const bool act = col < m;
   const int64_t cc = act ? col : m - 1;
@@ -593,17 +604,28 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
   // t = qQ + 1 .. (q + 1)Q of row k.  Step r of a block (rows descending):
   // b[UB - 1 - r + t] = solved row k + qQ + t, t = 1 .. Q; rows past n - 1
   // stay zero (and U's entries there are stored zero).
+  // wave 1: the chunk of rows k1 - kBandCH .. k1 - 1 (from 0) into buffer bf;
+  // its rows of Y hold forward results until wave 0 reaches them
+  auto stage = [&](int bf, int64_t k1) {
+    const int ch = static_cast<int>(k1 < kBandCH ? k1 : kBandCH);
+    const int64_t kb0 = k1 - ch;
+    BandStage::padded<WB>(fac[bf], U + kb0 * WC, WC, 1, 0, WU, ch, lane);
+    if (lane < ch) dinv[bf][lane] = Di[kb0 + lane];
+    BandStage::rows(rows[bf], Yj, ldy, kb0, ch, n, cc, lane);
+  };
   z64 b[Q + UB];
 #pragma unroll
   for (int i = 0; i < Q + UB; ++i) b[i] = zmake(0.0, 0.0);
-  for (int64_t k1 = n; k1 > 0; k1 -= kBandCH) {
+  if (wv == 1) stage(0, n);
+  for (int64_t k1 = n, c = 0; k1 > 0; k1 -= kBandCH, ++c) {
     const int ch = static_cast<int>(k1 < kBandCH ? k1 : kBandCH);
     const int64_t kb0 = k1 - ch;  // rows kb0 .. k1 - 1
-    __syncthreads();
-    BandStage::padded<WB>(fac, U + kb0 * WC, WC, 1, 0, WU, ch, lane);
-    if (lane < ch) dinv[lane] = Di[kb0 + lane];
-    BandStage::rows(rows, Yj, ldy, kb0, ch, n, cc, lane);
-    __syncthreads();
+    const int bf = static_cast<int>(c & 1);
+    __syncthreads();  // this chunk is staged; the other buffer is free
+    if (wv == 1) {
+      if (kb0 > 0) stage(bf ^ 1, kb0);
+      continue;
+    }
     for (int q = 0; q < ch; q += UB) {
       // a quarter's first UB slots are the previous quarter's last UB
       // (quarter 0's own are rewritten by this block's rows before it reads
@@ -617,8 +639,8 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
       for (int r = 0; r < UB; ++r) {
         if (r < nb) {
           const int kk = ch - 1 - (q + r);
-          const z64 *f = fac + kk * WB + qt * Q;
-          z64 s2[2] = {qt == 0 ? rows[kk][lane] : zmake(0.0, 0.0), zmake(0.0, 0.0)};
+          const z64 *f = fac[bf] + kk * WB + qt * Q;
+          z64 s2[2] = {qt == 0 ? rows[bf][kk][lane] : zmake(0.0, 0.0), zmake(0.0, 0.0)};
           // the quarter's factor loads all in flight before its first product
           z64 fr[Q];
           __builtin_amdgcn_sched_barrier(0);
@@ -629,7 +651,7 @@ __global__ __launch_bounds__(64) void k_band_bwd(const z64 *__restrict__ Uf,
           for (int t = 1; t <= Q; ++t)
             s2[t & 1] = band_fms(s2[t & 1], fr[t - 1], b[UB - 1 - r + t]);
           const z64 sq = zadd(s2[0], s2[1]);
-          const z64 y = zmul(zmake(quarter_sum(sq.x), quarter_sum(sq.y)), dinv[kk]);
+          const z64 y = zmul(zmake(quarter_sum(sq.x), quarter_sum(sq.y)), dinv[bf][kk]);
           if (qt == 0) {
             if (act) Yj[(kb0 + kk) * ldy + col] = y;
             b[UB - 1 - r] = y;
@@ -718,10 +740,11 @@ void band_solve(hipStream_t s, const z64 *Lf, const z64 *Uf, const z64 *Dinv, co
   // forward: 32 columns per wavefront (two lanes each); backward: 16 (four)
   const dim3 gf(N, static_cast<unsigned>((m + 31) / 32));
   const dim3 gb(N, static_cast<unsigned>((m + 15) / 16));
-  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, gf, dim3(64), 0, s, Lf, piv, n, kl, R, ldr,
+  // (a second wavefront per block stages the next chunk)
+  FEAST_BAND_DISPATCH(band_class(kl + 1), k_band_fwd, gf, dim3(128), 0, s, Lf, piv, n, kl, R,
+                      ldr, m, Y, ldy, sY)
+  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, gb, dim3(128), 0, s, Uf, Dinv, n, kl, ku,
                       m, Y, ldy, sY)
-  FEAST_BAND_DISPATCH(band_class(kl + ku), k_band_bwd, gb, dim3(64), 0, s, Uf, Dinv, n, kl, ku, m,
-                      Y, ldy, sY)
 }
 
 void csr_spmm(hipStream_t s, const int32_t *rp, const int32_t *ci, const z64 *va, const z64 *vb,
