@@ -673,10 +673,12 @@ void gemm_impl(hipStream_t s, GemmArgs<T> d, int ta, int cfg, int64_t work_elems
   const int BM = (cfg == GEMM_TALL || cfg == GEMM_UPDATE_TALL) ? 128 : 64;
   const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + 63) / 64);
   // Split K when the output is too small to fill the chip (aiming at about
-  // three workgroups per compute unit, each K chunk at least 256 long).
+  // three workgroups per compute unit, each K chunk at least 64 long: the
+  // Gram products of an n x m block, m <= 160, are otherwise a few long
+  // workgroups).
   if (d.work && d.K >= 512 && tiles * d.batch < 512) {
     int64_t sp = (768 + tiles * d.batch - 1) / (tiles * d.batch);
-    sp = std::min<int64_t>(sp, d.K / 256);
+    sp = std::min<int64_t>(sp, d.K / 64);
     while (sp > 1 && sp * d.batch * d.M * d.N > work_elems) --sp;
     if (sp > 1) {
       d.splits = static_cast<int32_t>(sp);
