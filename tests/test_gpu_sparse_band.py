@@ -190,6 +190,27 @@ def test_wide_bands_every_window_class(kl, ku):
     assert np.all(_residuals(A, B, X, res.lam) <= 1e-9)
 
 
+@pytest.mark.parametrize("n,kl,ku", [(24, 5, 9), (7, 6, 0), (31, 2, 3)])
+def test_pencils_smaller_than_one_chunk(n, kl, ku):
+    """Orders below one staging chunk (32 rows) and, for n = 7, a window that
+    covers the whole matrix; m below the 16 columns of a solve block."""
+    import scipy.linalg as sl
+    A, B = _wide_band_pencil(n, kl, ku, 77)
+    lam = sl.eigvals(A, B)
+    c = lam[np.argmin(np.abs(lam - 0.3))]
+    dist = np.sort(np.abs(lam - c))
+    r = 0.5 * (dist[2] + dist[3])
+    inside = lam[np.abs(lam - c) < r]
+    V = np.random.default_rng(3).normal(size=(n, min(n, 2 * len(inside) + 2))).astype(
+        np.complex128)
+    res = _solve_csr(A, B, V, c, r)
+    assert res.band == (kl, ku)
+    assert res.flag == 1 and len(res.lam) == len(inside) == 3
+    scale = max(1.0, abs(c) + r)
+    assert _match(res.lam, inside) <= 1e-10 * scale
+    assert np.all(_residuals(A, B, res.X.cpu().numpy(), res.lam) <= 1e-10)
+
+
 def test_diagonal_pencil_closed_form():
     """kl = ku = 0: A = diag(d), B = I has eigenvalues d exactly."""
     n = 600
