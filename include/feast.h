@@ -125,7 +125,9 @@ int feast_plan_create(feast_plan **plan, int64_t n, int64_t m, const feast_conto
 int feast_plan_destroy(feast_plan *plan);
 
 /* Drop the cached factors: the next call factors again whatever the
- * fingerprints say (a caller that wants to time the factorisation). */
+ * fingerprints say (a caller that wants to time the factorisation).  The
+ * host ordering feast_solve_csr keeps for a sparsity pattern is not a factor
+ * and stays (it is made again only for other patterns). */
 int feast_plan_invalidate(feast_plan *plan);
 
 /* The filter of eq. (8-4) applied to a block (Algorithm 5, filter step):
