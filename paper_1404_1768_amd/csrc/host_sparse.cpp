@@ -40,26 +40,62 @@ std::string check_pattern(int64_t n, const int32_t *rp, const int32_t *ci, int64
 
 namespace {
 
-// adjacency of the symmetrised pattern without the diagonal (sorted, unique)
-std::vector<std::vector<int32_t>> adjacency(const Pattern &P) {
-  std::vector<std::vector<int32_t>> adj(static_cast<size_t>(P.n));
-  for (int64_t i = 0; i < P.n; ++i)
-    for (int32_t e = P.rp[i]; e < P.rp[i + 1]; ++e) {
-      const int32_t c = P.ci[e];
-      if (c == i) continue;
-      adj[i].push_back(c);
-      adj[c].push_back(static_cast<int32_t>(i));
+// adjacency of the symmetrised pattern without the diagonal (sorted, unique),
+// in one CSR array: adj[v] is the range of v's neighbours
+struct Adjacency {
+  std::vector<int64_t> off;
+  std::vector<int32_t> nb;
+  struct Range {
+    const int32_t *b, *e;
+    const int32_t *begin() const { return b; }
+    const int32_t *end() const { return e; }
+    size_t size() const { return static_cast<size_t>(e - b); }
+  };
+  Range operator[](int64_t v) const { return {nb.data() + off[v], nb.data() + off[v + 1]}; }
+};
+
+// transpose of an n x n pattern by counting sort: the rows of the result come
+// out sorted (rows of the input are scanned in increasing order)
+void transpose(int64_t n, const int32_t *rp, const int32_t *ci, std::vector<int64_t> &trp,
+               std::vector<int32_t> &tci) {
+  trp.assign(static_cast<size_t>(n) + 1, 0);
+  for (int64_t e = 0; e < rp[n]; ++e) ++trp[ci[e] + 1];
+  for (int64_t i = 0; i < n; ++i) trp[i + 1] += trp[i];
+  tci.resize(static_cast<size_t>(rp[n]));
+  std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) tci[fill[ci[e]]++] = static_cast<int32_t>(i);
+}
+
+Adjacency adjacency(const Pattern &P) {
+  const int64_t n = P.n;
+  // T = P^T and S = T^T = P, both with sorted rows; row v of the symmetrised
+  // pattern is the merge of S's row v and T's row v
+  std::vector<int64_t> trp, srp;
+  std::vector<int32_t> tci, sci;
+  transpose(n, P.rp.data(), P.ci.data(), trp, tci);
+  std::vector<int32_t> trp32(trp.begin(), trp.end());
+  transpose(n, trp32.data(), tci.data(), srp, sci);
+  Adjacency A;
+  A.off.assign(static_cast<size_t>(n) + 1, 0);
+  A.nb.reserve(2 * sci.size());
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t x = srp[v], y = trp[v];
+    const int64_t xe = srp[v + 1], ye = trp[v + 1];
+    int32_t last = -1;
+    while (x < xe || y < ye) {
+      const int32_t c = (y >= ye || (x < xe && sci[x] <= tci[y])) ? sci[x++] : tci[y++];
+      if (c != v && c != last) A.nb.push_back(c);
+      last = c;
     }
-  for (auto &a : adj) {
-    std::sort(a.begin(), a.end());
-    a.erase(std::unique(a.begin(), a.end()), a.end());
+    A.off[v + 1] = static_cast<int64_t>(A.nb.size());
   }
-  return adj;
+  return A;
 }
 
 // breadth-first levels from `root` inside its component; returns the vertices
 // of the last level and the number of levels
-int bfs_levels(const std::vector<std::vector<int32_t>> &adj, int32_t root,
+int bfs_levels(const Adjacency &adj, int32_t root,
                std::vector<int32_t> &level, std::vector<int32_t> &last) {
   std::vector<int32_t> cur{root}, next;
   level[root] = 0;
